@@ -1,0 +1,196 @@
+"""Seeded synthetic workloads.  Every random number is drawn here with NumPy PCG64 from
+a fixed seed, so the GPU path and the oracle see identical inputs.
+
+Workloads (sizes are parameters so tests can shrink them with the same structure):
+  matern2d      2D Matern prior (Sec. 2.2), P1 on an s x s grid, uniform point data
+                on a seeded smooth target.                        (default 32x32)
+  advdiff_st    space-time advection-diffusion prior (Sec. 2.3-2.4, App. A) on an
+                ns x ns grid x nt implicit-Euler slices, white noise in space,
+                Galerkin PDE rows on slices 2..nt plus 1% point data.  (128x128x64)
+  matern_batch  many independent 2D Matern GMRFs of uneven size stacked block-
+                diagonally.                                      (256 problems)
+  matern3d      3D Matern prior on a Kuhn-split cube grid with point data. (64^3)
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+from . import fem, obs, priors
+
+
+@dataclass
+class Problem:
+    """Prior N(mu, Q^-1) and likelihood y | u ~ N(A u + b, Q_eps^-1) with diagonal Q_eps.
+
+    CSR arrays: int64 row pointers, int32 column indices, float64 values; Q stores both
+    triangles with a symmetric pattern."""
+    n: int
+    Q: sp.csr_matrix
+    A: sp.csr_matrix
+    q_eps: np.ndarray
+    y: np.ndarray
+    b: np.ndarray
+    coords: np.ndarray
+    block_ptr: np.ndarray | None = None
+    mu: np.ndarray | None = None
+    meta: dict = field(default_factory=dict)
+
+    def csr(self, which: str):
+        M = self.Q if which == "Q" else self.A
+        return (np.ascontiguousarray(M.indptr, dtype=np.int64),
+                np.ascontiguousarray(M.indices, dtype=np.int32),
+                np.ascontiguousarray(M.data, dtype=np.float64))
+
+
+def rng_for(seed: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+def smooth_target(rng: np.random.Generator, dim: int, terms: int = 8):
+    """u*(x) = sum_k a_k cos(2 pi w_k . x + phi_k), a_k ~ N(0,1)/k, w_k in {1..4}^d,
+    phi_k ~ U[0, 2 pi)."""
+    a = rng.standard_normal(terms) / np.arange(1, terms + 1)
+    w = rng.integers(1, 5, size=(terms, dim))
+    phi = rng.uniform(0.0, 2.0 * math.pi, size=terms)
+
+    def f(x):
+        x = np.atleast_2d(x)
+        return (a[None, :] * np.cos(2.0 * math.pi * (x @ w.T) + phi[None, :])).sum(axis=1)
+    return f
+
+
+def _sym_clean(Q: sp.csr_matrix) -> sp.csr_matrix:
+    """Exact symmetrisation of values (the products above are symmetric only up to
+    rounding); pattern must already be symmetric."""
+    Qt = Q.T.tocsr(); Qt.sort_indices()
+    if not (np.array_equal(Q.indptr, Qt.indptr) and np.array_equal(Q.indices, Qt.indices)):
+        raise ValueError("pattern is not symmetric")
+    return sp.csr_matrix((0.5 * (Q.data + Qt.data), Q.indices.copy(), Q.indptr.copy()),
+                         shape=Q.shape)
+
+
+def matern2d(side: int = 32, kappa: float = 5.0, tau: float = 1.0, n_obs: int = 100,
+             sigma: float = 0.01, seed: int = 1) -> Problem:
+    rng = rng_for(seed)
+    mesh = fem.structured_mesh((side, side))
+    Q, K, m = priors.matern_precision(mesh, kappa, tau)
+    Q = _sym_clean(Q)
+    target = smooth_target(rng, 2)
+    pts = rng.uniform(0.0, 1.0, size=(n_obs, 2))
+    A = obs.point_rows(mesh, pts, mesh.n)
+    y = target(pts) + sigma * rng.standard_normal(n_obs)
+    return Problem(mesh.n, Q, A, np.full(n_obs, 1.0 / sigma**2), y, np.zeros(n_obs),
+                   mesh.coords.copy(),
+                   meta=dict(workload="matern2d", side=side, kappa=kappa, tau=tau,
+                             n_obs=n_obs, sigma=sigma, seed=seed, K=K, m=m, mesh=mesh))
+
+
+def advdiff_spacetime(ns: int = 128, nt: int = 64, c: float = 0.5, nu: float = 0.01,
+                      tau: float = 1.0, kappa1: float = 10.0, sigma_pde: float = 1e-3,
+                      sigma: float = 1e-3, obs_frac: float = 0.01, seed: int = 2,
+                      pde_rows: bool = True) -> Problem:
+    """du/dt + c du/dx - nu Laplace u = tau W on [0,1]^2 x [0,1]: Nt slices, dt=1/(Nt-1).
+    Q1 = 2D Matern (alpha=2) with kappa1 and unit marginal variance
+    tau1 = 1/(sqrt(4 pi) kappa1).  Observations: Galerkin implicit-Euler residual rows
+    (G u^k - M~ u^(k-1))/dt = 0 on slices 2..Nt with noise sigma_pde, plus
+    ceil(obs_frac N) points at uniform locations and uniform slice indices with noise
+    sigma; the data come from the noiseless implicit-Euler FEM solution started from
+    the seeded smooth target."""
+    rng = rng_for(seed)
+    mesh = fem.structured_mesh((ns, ns))
+    dt = 1.0 / (nt - 1)
+    S = fem.stiffness(mesh)
+    C = fem.convection(mesh, axis=0)
+    m = fem.lumped_mass(mesh)
+    tau1 = 1.0 / (math.sqrt(4.0 * math.pi) * kappa1)
+    Q1, _, _ = priors.matern_precision(mesh, kappa1, tau1, S=S, m=m)
+    Ls = nu * S + c * C
+    Q, G = priors.spacetime_precision(mesh, nt, dt, Ls, tau, Q1, m)
+    Q = _sym_clean(Q)
+    N = ns * ns * nt
+    # deterministic implicit-Euler trajectory from the smooth initial condition
+    target = smooth_target(rng, 2)
+    u = np.empty((nt, mesh.n))
+    u[0] = target(mesh.coords)
+    lu = spla.splu(G.tocsc())
+    for k in range(1, nt):
+        u[k] = lu.solve(m * u[k - 1])
+    n_pts = int(math.ceil(obs_frac * N))
+    pts = rng.uniform(0.0, 1.0, size=(n_pts, 2))
+    kk = rng.integers(0, nt, size=n_pts)
+    A_pt = obs.point_rows(mesh, pts, N, offset=kk * mesh.n)
+    y_pt = A_pt @ u.ravel() + sigma * rng.standard_normal(n_pts)
+    blocks, ys, qs = [], [], []
+    if pde_rows:
+        A_pde = obs.galerkin_euler_rows(G, m, nt, dt, first_slice=1)
+        blocks.append(A_pde); ys.append(np.zeros(A_pde.shape[0]))
+        qs.append(np.full(A_pde.shape[0], 1.0 / sigma_pde**2))
+    blocks.append(A_pt); ys.append(y_pt); qs.append(np.full(n_pts, 1.0 / sigma**2))
+    A = sp.vstack(blocks, format="csr")
+    A.sort_indices()
+    y = np.concatenate(ys)
+    coords = np.concatenate([np.tile(mesh.coords, (nt, 1)),
+                             np.repeat(np.arange(nt) * dt, mesh.n)[:, None]], axis=1)
+    return Problem(N, Q, A, np.concatenate(qs), y, np.zeros(y.size), coords,
+                   meta=dict(workload="advdiff_spacetime", ns=ns, nt=nt, dt=dt, c=c, nu=nu,
+                             tau=tau, kappa1=kappa1, tau1=tau1, sigma_pde=sigma_pde,
+                             sigma=sigma, n_pts=n_pts, seed=seed, G=G, m=m, Q1=Q1,
+                             mesh=mesh, u_true=u))
+
+
+def matern_batch(n_prob: int = 256, side_lo: int = 64, side_hi: int = 256,
+                 kappa_lo: float = 1.0, kappa_hi: float = 20.0, tau: float = 1.0,
+                 sigma: float = 0.01, seed: int = 4) -> Problem:
+    """Block-diagonal stack of independent 2D Matern problems with sides ~ U{lo..hi},
+    kappa ~ U[kappa_lo, kappa_hi], ceil(0.01 N_i) points each."""
+    rng = rng_for(seed)
+    sides = rng.integers(side_lo, side_hi + 1, size=n_prob)
+    kappas = rng.uniform(kappa_lo, kappa_hi, size=n_prob)
+    Qs, As, ys, qs, cs = [], [], [], [], []
+    ptr = [0]
+    for s, kap in zip(sides, kappas):
+        mesh = fem.structured_mesh((int(s), int(s)))
+        Q, _, _ = priors.matern_precision(mesh, float(kap), tau)
+        target = smooth_target(rng, 2)
+        npts = int(math.ceil(0.01 * mesh.n))
+        pts = rng.uniform(0.0, 1.0, size=(npts, 2))
+        As.append(obs.point_rows(mesh, pts, mesh.n))
+        ys.append(target(pts) + sigma * rng.standard_normal(npts))
+        qs.append(np.full(npts, 1.0 / sigma**2))
+        Qs.append(_sym_clean(Q))
+        cs.append(mesh.coords + 2.0 * len(cs))   # disjoint boxes per problem
+        ptr.append(ptr[-1] + mesh.n)
+    Q = sp.block_diag(Qs, format="csr"); Q.sort_indices()
+    A = sp.block_diag(As, format="csr"); A.sort_indices()
+    y = np.concatenate(ys)
+    return Problem(ptr[-1], Q, A, np.concatenate(qs), y, np.zeros(y.size),
+                   np.concatenate(cs), block_ptr=np.asarray(ptr, dtype=np.int64),
+                   meta=dict(workload="matern_batch", n_prob=n_prob, sides=sides,
+                             kappas=kappas, tau=tau, sigma=sigma, seed=seed))
+
+
+def matern3d(side: int = 64, kappa: float = 10.0, tau: float = 1.0, n_obs: int = 5000,
+             sigma: float = 0.05, seed: int = 5) -> Problem:
+    rng = rng_for(seed)
+    mesh = fem.structured_mesh((side, side, side))
+    Q, K, m = priors.matern_precision(mesh, kappa, tau)
+    Q = _sym_clean(Q)
+    target = smooth_target(rng, 3)
+    pts = rng.uniform(0.0, 1.0, size=(n_obs, 3))
+    A = obs.point_rows(mesh, pts, mesh.n)
+    y = target(pts) + sigma * rng.standard_normal(n_obs)
+    return Problem(mesh.n, Q, A, np.full(n_obs, 1.0 / sigma**2), y, np.zeros(n_obs),
+                   mesh.coords.copy(),
+                   meta=dict(workload="matern3d", side=side, kappa=kappa, tau=tau,
+                             n_obs=n_obs, sigma=sigma, seed=seed, K=K, m=m, mesh=mesh))
+
+
+def standard_normal_f32(n: int, k: int, seed: int) -> np.ndarray:
+    """z ~ N(0, I) as float32, shape (n, k) column-major (Fortran order)."""
+    rng = rng_for(seed)
+    return np.asfortranarray(rng.standard_normal((n, k)).astype(np.float32))

@@ -1,0 +1,16 @@
+"""ORACLE -- test infrastructure only.
+
+A plain, slow, FP64 CPU reference of the GMRF posterior path (Sec. 3.1-3.2 of the
+paper): conditioning, sparse Cholesky, triangular solves, sampling, the Takahashi
+recursion for marginal variances, log-determinant, and the log marginal likelihood
+with its hyper-parameter gradient.  Only the test suite, the smoke check and the
+bench's CPU-baseline leg may import it; the GPU library never does, and the two share
+no code.
+"""
+from .core import (Factor, NotSPDError, assemble, block_logdets, build, cholesky,
+                   dense_posterior, logdet, marginal_variances, nd_order, posterior,
+                   rcm_order, sample, selinv, sigma_on_pattern, solve)
+
+__all__ = ["Factor", "NotSPDError", "assemble", "block_logdets", "build", "cholesky",
+           "dense_posterior", "logdet", "marginal_variances", "nd_order", "posterior",
+           "rcm_order", "sample", "selinv", "sigma_on_pattern", "solve"]
