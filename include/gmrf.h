@@ -1,0 +1,194 @@
+/*
+ * gmrf.h -- C ABI of the MI355X GMRF posterior library (libgmrf.so).
+ *
+ * Computes, for a Gaussian Markov random field prior u ~ N(mu, Q^-1) and a linear
+ * Gaussian likelihood y | u ~ N(A u + b, Q_eps^-1) with diagonal Q_eps:
+ *   posterior precision  Q_post = Q + A^T Q_eps A                 (Sec. 3.1, conditioning)
+ *   posterior mean       mu_post = mu + Q_post^-1 A^T Q_eps (y - A mu - b)
+ *                                                                   (Sec. 3.1, eq. posterior-mean)
+ *   sparse Cholesky      P Q_post P^T = L L^T with a fill-reducing nested-dissection
+ *                        order P computed once per pattern          (Sec. 3.2 and 3.3)
+ *   mean                 one forward and one backward triangular solve (Sec. 3.2)
+ *   samples              x = mu_post + P^T L^-T z, z ~ N(0, I)        (Sec. 3.2, sampling)
+ *   marginal variances   diag(Q_post^-1) by the Takahashi recursion   (Sec. 3.2)
+ *   log-determinant      log det Q_post = 2 sum_j log L_jj (follows from the factorisation)
+ * plus refactorisation with an unchanged pattern for Gauss-Newton (Sec. 3.3).
+ *
+ * Conventions shared by every call
+ *   - Matrices are CSR, 0-based: int64 row pointers, int32 column indices sorted
+ *     ascending within each row, float64 values.  Q stores both triangles; its pattern
+ *     must be symmetric and contain the diagonal, and A^T Q_eps A must fall inside it
+ *     (data rows touching one element; Galerkin PDE rows of the same FEM stencil).
+ *   - Array arguments are DEVICE pointers on the context's device unless marked "host".
+ *     The caller owns every buffer; the library never keeps a caller pointer past the
+ *     call.  The library copies the patterns (to the host, at the first gmrf_assemble)
+ *     and the values it needs.  It owns the factor, the selected inverse and all
+ *     workspaces until gmrf_destroy.
+ *   - Vectors indexed by unknowns are in the caller's (original) numbering, except the
+ *     standard-normal input of gmrf_sample, which is consumed in pivot order (z[k]
+ *     drives pivot k); gmrf_stats exposes the pivot order.
+ *   - Work is enqueued on the stream given to gmrf_create.  Calls that return host
+ *     results (gmrf_analyze, gmrf_logdet, gmrf_solve, gmrf_sample, gmrf_selinv,
+ *     gmrf_stats) synchronise that stream before returning.
+ *   - Call order: assemble -> analyze -> factor -> {logdet, solve, sample, selinv}.
+ *     update_values may follow any call after analyze and must be followed by factor.
+ *     A violation returns GMRF_ERR_STATE.
+ *   - Errors: every call returns a gmrf_status; on failure gmrf_last_error gives a
+ *     message.  A non-positive or NaN pivot is detected on the device during
+ *     gmrf_factor and reported by the next synchronising call as GMRF_ERR_NOT_SPD, with
+ *     the failing unknown (original numbering) in gmrf_stats_t.failed_index.
+ */
+#ifndef GMRF_H
+#define GMRF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gmrf_ctx* gmrf_t;
+typedef int32_t gmrf_status;
+
+enum {
+  GMRF_OK = 0,
+  GMRF_ERR_ARG = -1,           /* invalid argument, size or pattern */
+  GMRF_ERR_STATE = -2,         /* call out of order */
+  GMRF_ERR_NOT_SPD = -3,       /* factorisation met a non-positive or NaN pivot */
+  GMRF_ERR_PATTERN = -4,       /* values given for a pattern other than the analysed one */
+  GMRF_ERR_HIP = -5,           /* HIP runtime error */
+  GMRF_ERR_OOM = -6,           /* device allocation failed */
+  GMRF_ERR_NOT_CONVERGED = -7  /* refinement stopped above tolerance (result still written) */
+};
+
+typedef enum {
+  GMRF_FP64 = 0,          /* every factor, solve and selected-inverse operation in FP64 */
+  GMRF_FP32_REFINE = 1    /* FP32 fronts and updates on MFMA with FP32 accumulation; FP64
+                             diagonal-block pivots, log-det sum, residuals and iterative
+                             refinement of the mean */
+} gmrf_precision;
+
+/* Options of gmrf_analyze (NULL = defaults). */
+typedef struct {
+  int32_t leaf_size;   /* nested-dissection leaf size (default 64) */
+  int32_t relax_small; /* relaxed supernodes: always merge up to this many columns (8) */
+  int32_t relax_mid;   /* ... up to this many columns with <= 50% explicit zeros (32) */
+  int32_t relax_big;   /* ... up to this many columns with <= 15% explicit zeros (128) */
+} gmrf_options;
+
+typedef struct {
+  int64_t n;              /* unknowns */
+  int64_t nnz_q;          /* stored entries of Q (both triangles) */
+  int64_t m;              /* observations */
+  int64_t nnz_a;
+  int64_t nnz_l;          /* exact nonzeros of L (diagonal included) */
+  int64_t stored_l;       /* supernodal storage of L (relaxation zeros included) */
+  int64_t n_super;        /* supernodes */
+  int64_t tree_depth;     /* depth of the supernodal elimination tree */
+  int64_t max_front;      /* largest front size */
+  double flops_factor;    /* sum_j c_j^2 over exact column counts c_j */
+  double flops_selinv;    /* 2 sum_j c_j^2 */
+  double flops_solve;     /* 4 nnz(L) - 2n, per right-hand side */
+  double bytes_front_ws;  /* device bytes of the two front workspaces */
+  double bytes_factor;    /* device bytes of L */
+  int64_t failed_index;   /* original index of the first failing pivot, -1 if none */
+  int32_t precision;      /* precision of the last factorisation */
+  int32_t refine_iters;   /* refinement iterations of the last gmrf_solve */
+  double refine_resid;    /* ||h - Q_post mu|| / ||h|| after the last gmrf_solve */
+} gmrf_stats_t;
+
+/* Create a context on HIP device `device`, enqueuing on `hip_stream` (a hipStream_t;
+   NULL = the device's null stream).  *h receives the handle. */
+gmrf_status gmrf_create(gmrf_t* h, int device, void* hip_stream);
+
+/* Release every device and host resource of the context.  NULL is accepted. */
+gmrf_status gmrf_destroy(gmrf_t h);
+
+/* Conditioning, Sec. 3.1: Q_post = Q + A^T diag(q_eps) A on Q's pattern and
+   h = A^T diag(q_eps) (y - A mu_prior - b).
+   n, m        unknowns, observations (m may be 0; then A arrays may be NULL).
+   q_*         CSR of Q (device).   a_*   CSR of A, m x n (device).
+   q_eps, y    m entries (device).  b, mu_prior  m / n entries or NULL (= 0).
+   n_blocks, block_ptr  optional block-diagonal structure (host, n_blocks+1 entries,
+               block_ptr[0] = 0, block_ptr[n_blocks] = n); gmrf_logdet then returns one
+               value per block.  n_blocks = 0 or block_ptr = NULL means one block.
+   The first call copies and validates both patterns (sorted, in range, symmetric Q
+   with diagonal, A^T A inside Q's pattern) and builds the assembly maps; later calls
+   must pass the same pattern (same n, m, nnz; else GMRF_ERR_PATTERN). */
+gmrf_status gmrf_assemble(gmrf_t h, int64_t n, const int64_t* q_rowptr, const int32_t* q_col,
+                          const double* q_val, int64_t m, const int64_t* a_rowptr,
+                          const int32_t* a_col, const double* a_val, const double* q_eps,
+                          const double* y, const double* b, const double* mu_prior,
+                          int64_t n_blocks, const int64_t* block_ptr);
+
+/* New values on the already assembled patterns (Gauss-Newton, Sec. 3.3): any of the
+   pointers may be NULL to keep the previous values.  Re-runs the assembly on device
+   without host synchronisation.  Must be followed by gmrf_factor. */
+gmrf_status gmrf_update_values(gmrf_t h, const double* q_val, const double* a_val,
+                               const double* q_eps, const double* y, const double* b);
+
+/* Symbolic analysis on the host (Sec. 3.2: fill-reducing reordering, once per pattern,
+   Sec. 3.3): nested dissection (steered by coords when given: host, n x dim row-major,
+   dim 1..3; NULL = purely graph-based), elimination tree, exact column counts, relaxed
+   supernodes and the device execution plan. */
+gmrf_status gmrf_analyze(gmrf_t h, const double* coords, int dim, const gmrf_options* opts);
+
+/* Numeric factorisation P Q_post P^T = L L^T (Sec. 3.2) in the given precision,
+   asynchronous.  Repeatable after gmrf_update_values. */
+gmrf_status gmrf_factor(gmrf_t h, gmrf_precision p);
+
+/* log det Q_post (host output, one value per block of gmrf_assemble). */
+gmrf_status gmrf_logdet(gmrf_t h, double* out);
+
+/* Posterior mean (Sec. 3.1 eq. posterior-mean; Sec. 3.2: one forward and one backward
+   solve).  mu_out: n entries (device).  In GMRF_FP32_REFINE (and in GMRF_FP64 when
+   max_refine > 0) iterative refinement with FP64 residuals r = h - Q_post x runs until
+   ||r||/||h|| <= tol or max_refine corrections; iters_out and resid_out (host, nullable)
+   receive the count and the final relative residual.  Returns GMRF_ERR_NOT_CONVERGED if
+   the tolerance was not met (mu_out is still written). */
+gmrf_status gmrf_solve(gmrf_t h, double* mu_out, int max_refine, double tol, int* iters_out,
+                       double* resid_out);
+
+/* k posterior samples x = mu_post + P^T L^-T z (Sec. 3.2, sampling) from the mean of the
+   last gmrf_solve.  z: n x k float32, column-major, pivot order (device).
+   x_out: n x k float64, column-major, original order (device).  1 <= k <= 16. */
+gmrf_status gmrf_sample(gmrf_t h, int64_t k, const float* z, double* x_out);
+
+/* Selected inverse by the Takahashi recursion (Sec. 3.2, marginal variances).
+   var_out: diag(Q_post^-1), n entries (device).  sigma_q_out (nullable, device): the
+   entries of Q_post^-1 at every stored entry of Q, in Q's CSR order.  The factor is kept. */
+gmrf_status gmrf_selinv(gmrf_t h, double* var_out, double* sigma_q_out);
+
+/* Deterministic sum_e a[e] * b[e] over len entries (device inputs, host output); used
+   for traces tr(Q_post^-1 dQ) = sum over Q's pattern of Sigma_e dQ_e. */
+gmrf_status gmrf_dot(gmrf_t h, int64_t len, const double* a, const double* b, double* out);
+
+/* Counters of the analysed pattern and of the last calls (host output); also reports a
+   pending device status (GMRF_ERR_NOT_SPD). */
+gmrf_status gmrf_stats(gmrf_t h, gmrf_stats_t* out);
+
+/* Pivot order (host output, n entries): perm[k] = original index of pivot k. */
+gmrf_status gmrf_pivot_order(gmrf_t h, int32_t* perm_out);
+
+/* Elapsed device milliseconds of the phases of the last gmrf_factor, gmrf_solve and
+   gmrf_selinv calls, measured with events on the context's stream (host output, 3
+   entries: factor, solve, selinv). */
+gmrf_status gmrf_phase_ms(gmrf_t h, double* out3);
+
+/* Message of the last failing call on this context (never NULL). */
+const char* gmrf_last_error(gmrf_t h);
+
+/* Host-only symbolic analysis with no device (for tests and planning): pattern of Q
+   (host CSR as in gmrf_assemble), optional coords.  perm_out (n entries) and
+   colcount_out (n entries, exact column counts of L in pivot order) may be NULL;
+   stats_out receives the pattern counters (device fields zero). */
+gmrf_status gmrf_symbolic_host(int64_t n, const int64_t* rowptr, const int32_t* col,
+                               const double* coords, int dim, const gmrf_options* opts,
+                               int32_t* perm_out, int64_t* colcount_out,
+                               gmrf_stats_t* stats_out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GMRF_H */

@@ -1,0 +1,973 @@
+// C ABI of libgmrf.so: pattern intake and validation, assembly maps, the device
+// execution plan derived from the symbolic analysis, and the drivers of the numeric
+// phases (factor, solves with iterative refinement, sampling, selected inversion).
+#include "gmrf.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <climits>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "kernels.h"
+#include "symbolic.h"
+
+using namespace gmrf;
+
+namespace {
+
+template <typename T>
+struct DevArr {
+  T* p = nullptr;
+  size_t n = 0;
+  DevArr() = default;
+  DevArr(const DevArr&) = delete;
+  DevArr& operator=(const DevArr&) = delete;
+  ~DevArr() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+  hipError_t alloc(size_t cnt) {
+    if (cnt <= n && p) return hipSuccess;
+    release();
+    size_t bytes = std::max<size_t>(cnt, 1) * sizeof(T);
+    hipError_t e = hipMalloc((void**)&p, bytes);
+    if (e != hipSuccess) { p = nullptr; return e; }
+    n = cnt;
+    return hipSuccess;
+  }
+};
+
+enum : int { ST_ASSEMBLED = 1, ST_ANALYZED = 2, ST_FACTORED = 4, ST_SOLVED = 8 };
+
+struct HostList {  // a launch list before upload
+  int64_t f_off = 0, p_off = 0;
+  int32_t count = 0;
+  int64_t total = 0;
+};
+
+struct Level {
+  std::vector<int32_t> fronts;     // sorted by column count p descending
+  int nsteps = 0;
+  int64_t map_begin = 0, map_end = 0;
+  int64_t wsize = 0;               // elements of the square fronts at this depth
+  HostList all;                    // every front, one work-group each
+  std::vector<HostList> ext;       // extend-add per child slot (tiles = child u)
+  std::vector<HostList> fvec_ext;  // vector extend-add per child slot (1 per parent)
+  std::vector<HostList> potrf, trsm, upd;   // per step
+  HostList syrk, copyL;
+  std::vector<HostList> fdiag, fupd;        // forward solve per step
+  HostList binit;
+  std::vector<HostList> bdiag, bupd;        // backward solve per step (from the right)
+  HostList sgather;
+  std::vector<HostList> sY, sgemm, spart, sfin;  // selinv per step (from the right)
+};
+
+}  // namespace
+
+struct gmrf_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+  int state = 0;
+  int64_t n = 0, m = 0, nnzq = 0, nnza = 0;
+  std::vector<int64_t> qrp, arp;
+  std::vector<int32_t> qci, aci;
+  int64_t nblocks = 1;
+  std::vector<int64_t> block_ptr;
+  bool has_b = false, has_mu = false;
+
+  DevArr<int64_t> d_qrp, d_qdiag, d_arp, d_atp, d_cptr;
+  DevArr<int32_t> d_qci, d_qrow, d_aci, d_arow, d_ati, d_cpair;
+  DevArr<double> d_qval, d_aval, d_qeps, d_y, d_b, d_mu, d_qpost, d_h, d_rvec, d_qhat, d_scale;
+  DevArr<int32_t> d_sexp;
+
+  Symbolic sym;
+  AnalyzeOptions opt;
+  DevArr<int32_t> d_perm, d_sfirst, d_rows, d_relpos, d_child_ptr, d_child_idx, d_sparent;
+  DevArr<int64_t> d_rowptr, d_Loff, d_Woff, d_Doff, d_Voff;
+  DevArr<int64_t> d_map_e, d_map_off;
+  DevArr<int32_t> d_lfronts;
+  DevArr<int64_t> d_lprefix;
+  DevArr<int64_t> d_bptr;
+  DevArr<int32_t> d_bpiv;
+  std::vector<Level> levels;
+  int64_t max_front = 0;
+  int64_t part_max = 0;   // largest split-K partial launch (work-groups)
+
+  int prec = -1;
+  DevArr<char> d_L, d_D, d_W0, d_W1, d_Y, d_part;
+  DevArr<double> d_piv, d_V0, d_V1, d_xp, d_w, d_r, d_red, d_norm, d_ld, d_mu_post;
+  DevArr<int32_t> d_status;
+  int refine_iters = 0;
+  double refine_resid = 0.0;
+  int64_t failed_index = -1;
+  hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  double phase_ms[3] = {0, 0, 0};
+  bool ev_factor = false, ev_solve = false, ev_sel = false;
+};
+
+namespace {
+
+gmrf_status fail(gmrf_t h, gmrf_status code, const std::string& msg) {
+  if (h) h->err = msg;
+  return code;
+}
+
+#define HIPCHK(h, expr)                                                                   \
+  do {                                                                                    \
+    hipError_t _e = (expr);                                                               \
+    if (_e != hipSuccess)                                                                 \
+      return fail(h, _e == hipErrorOutOfMemory ? GMRF_ERR_OOM : GMRF_ERR_HIP,             \
+                  std::string(#expr) + ": " + hipGetErrorString(_e));                     \
+  } while (0)
+
+template <typename T>
+hipError_t upload(DevArr<T>& d, const std::vector<T>& h, hipStream_t st) {
+  hipError_t e = d.alloc(h.size());
+  if (e != hipSuccess) return e;
+  if (h.empty()) return hipSuccess;
+  e = hipMemcpyAsync(d.p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, st);
+  if (e != hipSuccess) return e;
+  return hipStreamSynchronize(st);
+}
+
+template <typename T>
+hipError_t download(std::vector<T>& h, const T* d, size_t cnt, hipStream_t st) {
+  h.resize(cnt);
+  if (cnt == 0) return hipSuccess;
+  hipError_t e = hipMemcpyAsync(h.data(), d, cnt * sizeof(T), hipMemcpyDeviceToHost, st);
+  if (e != hipSuccess) return e;
+  return hipStreamSynchronize(st);
+}
+
+hipError_t copy_d2d(void* dst, const void* src, size_t bytes, hipStream_t st) {
+  if (bytes == 0) return hipSuccess;
+  return hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, st);
+}
+
+std::string check_csr(int64_t nr, int64_t nc, const std::vector<int64_t>& rp,
+                      const std::vector<int32_t>& ci, const char* name) {
+  if (rp.empty() || rp[0] != 0) return std::string(name) + ": row pointer must start at 0";
+  for (int64_t r = 0; r < nr; ++r) {
+    if (rp[r + 1] < rp[r]) return std::string(name) + ": row pointers decrease";
+    for (int64_t e = rp[r]; e < rp[r + 1]; ++e) {
+      if (ci[e] < 0 || ci[e] >= nc) return std::string(name) + ": column index out of range";
+      if (e > rp[r] && ci[e] <= ci[e - 1]) return std::string(name) + ": columns not strictly increasing";
+    }
+  }
+  return std::string();
+}
+
+int64_t find_entry(const std::vector<int64_t>& rp, const std::vector<int32_t>& ci, int64_t r, int32_t c) {
+  const int32_t* b = ci.data() + rp[r];
+  const int32_t* e = ci.data() + rp[r + 1];
+  const int32_t* it = std::lower_bound(b, e, c);
+  if (it == e || *it != c) return -1;
+  return rp[r] + (it - b);
+}
+
+// ------------------------------------------------------------------ plan construction
+struct ListBuilder {
+  std::vector<int32_t> fronts;
+  std::vector<int64_t> prefix;
+  template <typename F>
+  HostList add(const std::vector<int32_t>& cand, F tiles) {
+    HostList L;
+    L.f_off = (int64_t)fronts.size();
+    L.p_off = (int64_t)prefix.size();
+    int64_t tot = 0;
+    for (int32_t s : cand) {
+      int64_t t = tiles(s);
+      if (t <= 0) continue;
+      fronts.push_back(s);
+      prefix.push_back(tot);
+      tot += t;
+      L.count++;
+    }
+    prefix.push_back(tot);
+    L.total = tot;
+    return L;
+  }
+};
+
+LaunchList dev_list(const gmrf_ctx* h, const HostList& L) {
+  LaunchList d;
+  d.fronts = h->d_lfronts.p + L.f_off;
+  d.prefix = h->d_lprefix.p + L.p_off;
+  d.count = L.count;
+  d.total = L.total;
+  return d;
+}
+
+DevSym dev_sym(const gmrf_ctx* h) {
+  DevSym S;
+  S.n = h->n;
+  S.perm = h->d_perm.p;
+  S.sfirst = h->d_sfirst.p;
+  S.rowptr = h->d_rowptr.p;
+  S.rows = h->d_rows.p;
+  S.relpos = h->d_relpos.p;
+  S.child_ptr = h->d_child_ptr.p;
+  S.child_idx = h->d_child_idx.p;
+  S.Loff = h->d_Loff.p;
+  S.Woff = h->d_Woff.p;
+  S.Doff = h->d_Doff.p;
+  S.Voff = h->d_Voff.p;
+  return S;
+}
+
+gmrf_status build_plan(gmrf_t h) {
+  const Symbolic& Y = h->sym;
+  const int nb = kNB;
+  h->levels.assign(Y.max_depth + 1, Level());
+  h->max_front = 0;
+  for (int32_t s = 0; s < Y.ns; ++s) {
+    h->levels[Y.depth[s]].fronts.push_back(s);
+    h->max_front = std::max<int64_t>(h->max_front, Y.nf(s));
+  }
+  // scatter / gather map: every stored entry of Q, grouped by depth of the owning front
+  std::vector<int32_t> colsup(h->n);
+  for (int32_t s = 0; s < Y.ns; ++s)
+    for (int32_t j = Y.sfirst[s]; j < Y.sfirst[s + 1]; ++j) colsup[j] = s;
+  std::vector<int64_t> cnt(Y.max_depth + 2, 0);
+  std::vector<int32_t> edep(h->nnzq);
+  std::vector<int64_t> eoff(h->nnzq);
+  for (int64_t r = 0; r < h->n; ++r) {
+    for (int64_t e = h->qrp[r]; e < h->qrp[r + 1]; ++e) {
+      const int32_t i = Y.iperm[r], j = Y.iperm[h->qci[e]];
+      const int32_t lo = std::min(i, j), hi = std::max(i, j);
+      const int32_t s = colsup[lo];
+      const int32_t* rb = Y.rows.data() + Y.rowptr[s];
+      const int32_t* re = Y.rows.data() + Y.rowptr[s + 1];
+      const int32_t* it = std::lower_bound(rb, re, hi);
+      if (it == re || *it != hi) return fail(h, GMRF_ERR_ARG, "internal: entry of Q outside the symbolic factor");
+      const int64_t nf = Y.nf(s);
+      eoff[e] = Y.Woff[s] + (int64_t)(it - rb) + (int64_t)(lo - Y.sfirst[s]) * nf;
+      edep[e] = Y.depth[s];
+      cnt[Y.depth[s] + 1]++;
+    }
+  }
+  for (int d = 0; d <= Y.max_depth; ++d) cnt[d + 1] += cnt[d];
+  std::vector<int64_t> map_e(h->nnzq), map_off(h->nnzq);
+  {
+    std::vector<int64_t> fill(cnt.begin(), cnt.end() - 1);
+    for (int64_t r = 0; r < h->n; ++r) {
+      for (int64_t e = h->qrp[r]; e < h->qrp[r + 1]; ++e) {
+        const int32_t i = Y.iperm[r], j = Y.iperm[h->qci[e]];
+        const int64_t q = fill[edep[e]]++;
+        map_e[q] = i >= j ? e : -(e + 1);
+        map_off[q] = eoff[e];
+      }
+    }
+  }
+  edep.clear(); edep.shrink_to_fit(); eoff.clear(); eoff.shrink_to_fit();
+
+  ListBuilder B;
+  h->part_max = 0;
+  for (int d = 0; d <= Y.max_depth; ++d) {
+    Level& lv = h->levels[d];
+    lv.map_begin = cnt[d];
+    lv.map_end = cnt[d + 1];
+    std::stable_sort(lv.fronts.begin(), lv.fronts.end(),
+                     [&](int32_t a, int32_t b) { return Y.p(a) > Y.p(b); });
+    lv.nsteps = 0;
+    lv.wsize = 0;
+    int maxch = 0;
+    for (int32_t s : lv.fronts) {
+      lv.nsteps = std::max(lv.nsteps, (Y.p(s) + nb - 1) / nb);
+      lv.wsize = std::max<int64_t>(lv.wsize, Y.Woff[s] + (int64_t)Y.nf(s) * Y.nf(s));
+      maxch = std::max(maxch, Y.child_ptr[s + 1] - Y.child_ptr[s]);
+    }
+    auto nF = [&](int32_t s) { return (int64_t)Y.nf(s); };
+    auto pF = [&](int32_t s) { return (int64_t)Y.p(s); };
+    lv.all = B.add(lv.fronts, [](int32_t) { return (int64_t)1; });
+    for (int c = 0; c < maxch; ++c) {
+      lv.ext.push_back(B.add(lv.fronts, [&](int32_t s) -> int64_t {
+        if (Y.child_ptr[s + 1] - Y.child_ptr[s] <= c) return 0;
+        const int32_t ch = Y.child_idx[Y.child_ptr[s] + c];
+        return nF(ch) - pF(ch);
+      }));
+      lv.fvec_ext.push_back(B.add(lv.fronts, [&](int32_t s) -> int64_t {
+        return Y.child_ptr[s + 1] - Y.child_ptr[s] > c ? 1 : 0;
+      }));
+    }
+    for (int k = 0; k < lv.nsteps; ++k) {
+      const int64_t k0 = (int64_t)k * nb;
+      auto active = [&](int32_t s) { return pF(s) > k0; };
+      auto kb = [&](int32_t s) { return std::min<int64_t>(nb, pF(s) - k0); };
+      lv.potrf.push_back(B.add(lv.fronts, [&](int32_t s) -> int64_t { return active(s) ? 1 : 0; }));
+      lv.trsm.push_back(B.add(lv.fronts, [&](int32_t s) -> int64_t {
+        if (!active(s)) return 0;
+        const int64_t rows = nF(s) - k0 - kb(s);
+        return (rows + kTile - 1) / kTile;
+      }));
+      lv.upd.push_back(B.add(lv.fronts, [&](int32_t s) -> int64_t {
+        if (!active(s)) return 0;
+        const int64_t clo = k0 + kb(s), chi = pF(s);
+        int64_t t = 0;
+        for (int64_t c0 = clo; c0 < chi; c0 += kTile) t += (nF(s) - c0 + kTile - 1) / kTile;
+        return t;
+      }));
+      lv.fdiag.push_back(B.add(lv.fronts, [&](int32_t s) -> int64_t { return active(s) ? 1 : 0; }));
+      lv.fupd.push_back(B.add(lv.fronts, [&](int32_t s) -> int64_t {
+        if (!active(s)) return 0;
+        return (nF(s) - k0 - kb(s) + kTile - 1) / kTile;
+      }));
+      // steps counted from the right: block index nblk-1-k
+      auto rblk = [&](int32_t s) { return (pF(s) + nb - 1) / nb - 1 - k; };
+      auto ractive = [&](int32_t s) { return rblk(s) >= 0; };
+      auto rtail = [&](int32_t s) {  // rows after the block
+        const int64_t kk = rblk(s), kk0 = kk * nb, kkb = std::min<int64_t>(nb, pF(s) - kk0);
+        return nF(s) - kk0 - kkb;
+      };
+      lv.bdiag.push_back(B.add(lv.fronts, [&](int32_t s) -> int64_t { return ractive(s) ? 1 : 0; }));
+      lv.bupd.push_back(B.add(lv.fronts, [&](int32_t s) -> int64_t { return ractive(s) ? rblk(s) : 0; }));
+      lv.sY.push_back(B.add(lv.fronts, [&](int32_t s) -> int64_t {
+        return ractive(s) ? (rtail(s) + kTile - 1) / kTile : 0;
+      }));
+      lv.sgemm.push_back(B.add(lv.fronts, [&](int32_t s) -> int64_t {
+        return ractive(s) ? (rtail(s) + kTile - 1) / kTile : 0;
+      }));
+      lv.spart.push_back(B.add(lv.fronts, [&](int32_t s) -> int64_t {
+        return ractive(s) ? std::max<int64_t>(1, (rtail(s) + 511) / 512) : 0;
+      }));
+      h->part_max = std::max(h->part_max, lv.spart.back().total);
+      lv.sfin.push_back(B.add(lv.fronts, [&](int32_t s) -> int64_t { return ractive(s) ? 1 : 0; }));
+    }
+    lv.syrk = B.add(lv.fronts, [&](int32_t s) -> int64_t {
+      const int64_t u = nF(s) - pF(s);
+      const int64_t T = (u + kTile - 1) / kTile;
+      return T * (T + 1) / 2;
+    });
+    lv.copyL = B.add(lv.fronts, [&](int32_t s) -> int64_t { return pF(s); });
+    lv.binit = B.add(lv.fronts, [&](int32_t s) -> int64_t { return (pF(s) + nb - 1) / nb; });
+    lv.sgather = B.add(lv.fronts, [&](int32_t s) -> int64_t {
+      return Y.sparent[s] >= 0 ? nF(s) - pF(s) : 0;
+    });
+  }
+  hipStream_t st = h->stream;
+  HIPCHK(h, upload(h->d_lfronts, B.fronts, st));
+  HIPCHK(h, upload(h->d_lprefix, B.prefix, st));
+  HIPCHK(h, upload(h->d_map_e, map_e, st));
+  HIPCHK(h, upload(h->d_map_off, map_off, st));
+  HIPCHK(h, upload(h->d_perm, Y.perm, st));
+  HIPCHK(h, upload(h->d_sfirst, Y.sfirst, st));
+  HIPCHK(h, upload(h->d_rowptr, Y.rowptr, st));
+  HIPCHK(h, upload(h->d_rows, Y.rows, st));
+  HIPCHK(h, upload(h->d_relpos, Y.relpos, st));
+  HIPCHK(h, upload(h->d_child_ptr, Y.child_ptr, st));
+  HIPCHK(h, upload(h->d_child_idx, Y.child_idx, st));
+  HIPCHK(h, upload(h->d_sparent, Y.sparent, st));
+  HIPCHK(h, upload(h->d_Loff, Y.Loff, st));
+  HIPCHK(h, upload(h->d_Woff, Y.Woff, st));
+  HIPCHK(h, upload(h->d_Doff, Y.Doff, st));
+  HIPCHK(h, upload(h->d_Voff, Y.Voff, st));
+  // per-block pivot lists for the log-determinant
+  {
+    std::vector<int64_t> bp(h->nblocks + 1, 0);
+    std::vector<int32_t> owner(h->n);
+    for (int64_t b = 0; b < h->nblocks; ++b)
+      for (int64_t o = h->block_ptr[b]; o < h->block_ptr[b + 1]; ++o) owner[o] = (int32_t)b;
+    for (int64_t j = 0; j < h->n; ++j) bp[owner[Y.perm[j]] + 1]++;
+    for (int64_t b = 0; b < h->nblocks; ++b) bp[b + 1] += bp[b];
+    std::vector<int32_t> bpiv(h->n);
+    std::vector<int64_t> fill(bp.begin(), bp.end() - 1);
+    for (int64_t j = 0; j < h->n; ++j) bpiv[fill[owner[Y.perm[j]]]++] = (int32_t)j;
+    HIPCHK(h, upload(h->d_bptr, bp, st));
+    HIPCHK(h, upload(h->d_bpiv, bpiv, st));
+  }
+  return GMRF_OK;
+}
+
+// ------------------------------------------------------------------ numeric drivers
+template <typename T>
+gmrf_status alloc_numeric(gmrf_t h) {
+  const Symbolic& Y = h->sym;
+  HIPCHK(h, h->d_L.alloc((size_t)Y.Lsize * sizeof(T)));
+  HIPCHK(h, h->d_D.alloc((size_t)Y.Dsize * sizeof(T)));
+  HIPCHK(h, h->d_W0.alloc((size_t)std::max<int64_t>(Y.Wsize[0], 1) * sizeof(T)));
+  HIPCHK(h, h->d_W1.alloc((size_t)std::max<int64_t>(Y.Wsize[1], 1) * sizeof(T)));
+  HIPCHK(h, h->d_piv.alloc(h->n));
+  HIPCHK(h, h->d_status.alloc(1));
+  HIPCHK(h, h->d_scale.alloc(h->n));
+  HIPCHK(h, h->d_sexp.alloc(h->n));
+  HIPCHK(h, h->d_qhat.alloc(h->nnzq));
+  return GMRF_OK;
+}
+
+template <typename T>
+gmrf_status run_factor(gmrf_t h) {
+  const Symbolic& Y = h->sym;
+  hipStream_t st = h->stream;
+  gmrf_status rc = alloc_numeric<T>(h);
+  if (rc != GMRF_OK) return rc;
+  const DevSym S = dev_sym(h);
+  launch_equilibrate(st, h->n, h->nnzq, h->d_qdiag.p, h->d_qrow.p, h->d_qci.p, h->d_qpost.p, h->d_sexp.p,
+                     h->d_scale.p, h->d_qhat.p);
+  launch_fill_i32(st, h->d_status.p, 1, INT_MAX);
+  T* W[2] = {(T*)h->d_W0.p, (T*)h->d_W1.p};
+  for (int d = Y.max_depth; d >= 0; --d) {
+    const Level& lv = h->levels[d];
+    NumBufs<T> B;
+    B.L = (T*)h->d_L.p;
+    B.D = (T*)h->d_D.p;
+    B.piv = h->d_piv.p;
+    B.Wcur = W[d & 1];
+    B.Wchild = W[(d + 1) & 1];
+    B.status = h->d_status.p;
+    launch_zero<T>(st, B.Wcur, lv.wsize);
+    launch_scatter<T>(st, lv.map_end - lv.map_begin, h->d_map_e.p + lv.map_begin,
+                      h->d_map_off.p + lv.map_begin, h->d_qhat.p, B.Wcur);
+    for (size_t c = 0; c < lv.ext.size(); ++c)
+      launch_extend_add<T>(st, S, dev_list(h, lv.ext[c]), (int)c, B.Wchild, B.Wcur);
+    for (int k = 0; k < lv.nsteps; ++k) {
+      launch_potrf<T>(st, S, dev_list(h, lv.potrf[k]), k, B);
+      launch_trsm<T>(st, S, dev_list(h, lv.trsm[k]), k, B);
+      launch_update<T>(st, S, dev_list(h, lv.upd[k]), k, 0, B);
+    }
+    launch_update<T>(st, S, dev_list(h, lv.syrk), 0, 1, B);
+    launch_copy_L<T>(st, S, dev_list(h, lv.copyL), B);
+  }
+  HIPCHK(h, hipGetLastError());
+  return GMRF_OK;
+}
+
+gmrf_status check_status(gmrf_t h) {
+  if (!(h->state & ST_FACTORED)) return GMRF_OK;
+  int32_t s = INT_MAX;
+  HIPCHK(h, hipMemcpyAsync(&s, h->d_status.p, sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  if (s != INT_MAX) {
+    h->failed_index = (s >= 0 && s < h->n) ? h->sym.perm[s] : -1;
+    return fail(h, GMRF_ERR_NOT_SPD, "matrix is not positive definite: non-positive pivot at original index " +
+                                         std::to_string(h->failed_index));
+  }
+  h->failed_index = -1;
+  return GMRF_OK;
+}
+
+// forward + backward (or backward only) solve of the FP64 pivot-order block xp (n x nrhs)
+template <typename T>
+void run_solve(gmrf_t h, int nrhs, bool forward) {
+  const Symbolic& Y = h->sym;
+  hipStream_t st = h->stream;
+  const DevSym S = dev_sym(h);
+  double* V[2] = {h->d_V0.p, h->d_V1.p};
+  const T* Lp = (const T*)h->d_L.p;
+  const T* D = (const T*)h->d_D.p;
+  if (forward) {
+    for (int d = Y.max_depth; d >= 0; --d) {
+      const Level& lv = h->levels[d];
+      SolveBufs B{h->d_xp.p, V[d & 1], V[(d + 1) & 1], nrhs};
+      launch_fvec_init<T>(st, S, dev_list(h, lv.all), B);
+      for (size_t c = 0; c < lv.fvec_ext.size(); ++c)
+        launch_fvec_extend<T>(st, S, dev_list(h, lv.fvec_ext[c]), (int)c, B);
+      for (int k = 0; k < lv.nsteps; ++k) {
+        launch_fwd_diag<T>(st, S, dev_list(h, lv.fdiag[k]), k, D, B);
+        launch_fwd_update<T>(st, S, dev_list(h, lv.fupd[k]), k, Lp, B);
+      }
+    }
+  }
+  for (int d = 0; d <= Y.max_depth; ++d) {
+    const Level& lv = h->levels[d];
+    SolveBufs B{h->d_xp.p, V[d & 1], V[(d + 1) & 1], nrhs};
+    launch_bwd_init<T>(st, S, dev_list(h, lv.binit), Lp, B);
+    for (int k = 0; k < lv.nsteps; ++k) {
+      launch_bwd_diag<T>(st, S, dev_list(h, lv.bdiag[k]), k, D, B);
+      launch_bwd_update<T>(st, S, dev_list(h, lv.bupd[k]), k, Lp, B);
+    }
+  }
+}
+
+gmrf_status alloc_solve(gmrf_t h, int nrhs) {
+  const Symbolic& Y = h->sym;
+  HIPCHK(h, h->d_V0.alloc((size_t)std::max<int64_t>(Y.Vsize[0], 1) * nrhs));
+  HIPCHK(h, h->d_V1.alloc((size_t)std::max<int64_t>(Y.Vsize[1], 1) * nrhs));
+  HIPCHK(h, h->d_xp.alloc((size_t)h->n * nrhs));
+  HIPCHK(h, h->d_w.alloc(h->n));
+  HIPCHK(h, h->d_r.alloc(h->n));
+  HIPCHK(h, h->d_red.alloc(1024));
+  HIPCHK(h, h->d_norm.alloc(4));
+  HIPCHK(h, h->d_mu_post.alloc(h->n));
+  return GMRF_OK;
+}
+
+template <typename T>
+gmrf_status run_selinv(gmrf_t h, double* var, double* sigq) {
+  const Symbolic& Y = h->sym;
+  hipStream_t st = h->stream;
+  const DevSym S = dev_sym(h);
+  int64_t ysz = std::max<int64_t>(std::max(Y.Vsize[0], Y.Vsize[1]), 1) * kNB;
+  HIPCHK(h, h->d_Y.alloc((size_t)ysz * sizeof(T)));
+  HIPCHK(h, h->d_part.alloc((size_t)std::max<int64_t>(h->part_max, 1) * kNB * kNB * sizeof(T)));
+  T* W[2] = {(T*)h->d_W0.p, (T*)h->d_W1.p};
+  for (int d = 0; d <= Y.max_depth; ++d) {
+    const Level& lv = h->levels[d];
+    SelBufs<T> B;
+    B.L = (const T*)h->d_L.p;
+    B.D = (const T*)h->d_D.p;
+    B.Scur = W[d & 1];
+    B.Spar = W[(d + 1) & 1];   // parent depth d-1 has the other parity
+    B.Y = (T*)h->d_Y.p;
+    B.part = (T*)h->d_part.p;
+    launch_sel_gather<T>(st, S, dev_list(h, lv.sgather), h->d_sparent.p, B);
+    for (int k = 0; k < lv.nsteps; ++k) {
+      launch_sel_Y<T>(st, S, dev_list(h, lv.sY[k]), k, B);
+      launch_sel_gemm<T>(st, S, dev_list(h, lv.sgemm[k]), k, B);
+      launch_sel_diag_partial<T>(st, S, dev_list(h, lv.spart[k]), k, B);
+      launch_sel_diag_finish<T>(st, S, dev_list(h, lv.sfin[k]), dev_list(h, lv.spart[k]), k, B);
+    }
+    launch_sel_extract<T>(st, S, dev_list(h, lv.all), B, h->d_scale.p, var);
+    if (sigq)
+      launch_sel_pattern<T>(st, lv.map_end - lv.map_begin, h->d_map_e.p + lv.map_begin,
+                            h->d_map_off.p + lv.map_begin, h->d_qrow.p, h->d_qci.p, h->d_scale.p, B.Scur,
+                            sigq);
+  }
+  HIPCHK(h, hipGetLastError());
+  return GMRF_OK;
+}
+
+gmrf_status assemble_device(gmrf_t h) {
+  hipStream_t st = h->stream;
+  launch_assemble_qpost(st, h->nnzq, h->d_qval.p, h->d_cptr.p, h->d_cpair.p, h->d_arow.p, h->d_aval.p,
+                        h->d_qeps.p, h->d_qpost.p);
+  if (h->m > 0) {
+    launch_obs_residual(st, h->m, h->d_arp.p, h->d_aci.p, h->d_aval.p, h->d_qeps.p, h->d_y.p,
+                        h->has_b ? h->d_b.p : nullptr, h->has_mu ? h->d_mu.p : nullptr, h->d_rvec.p);
+    launch_at_times(st, h->n, h->d_atp.p, h->d_ati.p, h->d_arow.p, h->d_aval.p, h->d_rvec.p, h->d_h.p);
+  } else {
+    launch_fill_f64(st, h->d_h.p, h->n, 0.0);
+  }
+  HIPCHK(h, hipGetLastError());
+  return GMRF_OK;
+}
+
+float elapsed(hipEvent_t a, hipEvent_t b) {
+  float ms = 0.f;
+  if (hipEventElapsedTime(&ms, a, b) != hipSuccess) return 0.f;
+  return ms;
+}
+
+}  // namespace
+
+// ====================================================================== C ABI
+extern "C" {
+
+gmrf_status gmrf_create(gmrf_t* out, int device, void* hip_stream) {
+  if (!out) return GMRF_ERR_ARG;
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return GMRF_ERR_ARG;
+  if (hipSetDevice(device) != hipSuccess) return GMRF_ERR_HIP;
+  gmrf_t h = new gmrf_ctx();
+  h->device = device;
+  h->stream = (hipStream_t)hip_stream;
+  for (auto& e : h->ev) {
+    if (hipEventCreate(&e) != hipSuccess) { delete h; return GMRF_ERR_HIP; }
+  }
+  *out = h;
+  return GMRF_OK;
+}
+
+gmrf_status gmrf_destroy(gmrf_t h) {
+  if (!h) return GMRF_OK;
+  (void)hipSetDevice(h->device);
+  if (h->stream) (void)hipStreamSynchronize(h->stream);
+  else (void)hipDeviceSynchronize();
+  for (auto& e : h->ev)
+    if (e) (void)hipEventDestroy(e);
+  delete h;
+  return GMRF_OK;
+}
+
+const char* gmrf_last_error(gmrf_t h) {
+  if (!h) return "null handle";
+  return h->err.c_str();
+}
+
+gmrf_status gmrf_assemble(gmrf_t h, int64_t n, const int64_t* q_rowptr, const int32_t* q_col,
+                          const double* q_val, int64_t m, const int64_t* a_rowptr, const int32_t* a_col,
+                          const double* a_val, const double* q_eps, const double* y, const double* b,
+                          const double* mu_prior, int64_t n_blocks, const int64_t* block_ptr) {
+  if (!h) return GMRF_ERR_ARG;
+  if (hipSetDevice(h->device) != hipSuccess) return fail(h, GMRF_ERR_HIP, "hipSetDevice failed");
+  hipStream_t st = h->stream;
+  if (n <= 0 || m < 0 || !q_rowptr || !q_col || !q_val) return fail(h, GMRF_ERR_ARG, "bad sizes or null Q");
+  if (m > 0 && (!a_rowptr || !a_col || !a_val || !q_eps || !y)) return fail(h, GMRF_ERR_ARG, "null A arrays");
+  int64_t nnzq = 0, nnza = 0;
+  HIPCHK(h, hipMemcpy(&nnzq, q_rowptr + n, sizeof(int64_t), hipMemcpyDeviceToHost));
+  if (m > 0) HIPCHK(h, hipMemcpy(&nnza, a_rowptr + m, sizeof(int64_t), hipMemcpyDeviceToHost));
+  const bool first = !(h->state & ST_ASSEMBLED);
+  if (!first && (n != h->n || m != h->m || nnzq != h->nnzq || nnza != h->nnza))
+    return fail(h, GMRF_ERR_PATTERN, "pattern differs from the first gmrf_assemble of this context");
+  if (first) {
+    if (nnzq <= 0 || nnzq >= ((int64_t)1 << 40)) return fail(h, GMRF_ERR_ARG, "bad nnz(Q)");
+    if (nnza >= ((int64_t)1 << 31)) return fail(h, GMRF_ERR_ARG, "nnz(A) must be below 2^31");
+    h->n = n; h->m = m; h->nnzq = nnzq; h->nnza = nnza;
+    HIPCHK(h, download(h->qrp, q_rowptr, (size_t)n + 1, st));
+    HIPCHK(h, download(h->qci, q_col, (size_t)nnzq, st));
+    if (m > 0) {
+      HIPCHK(h, download(h->arp, a_rowptr, (size_t)m + 1, st));
+      HIPCHK(h, download(h->aci, a_col, (size_t)nnza, st));
+    } else {
+      h->arp.assign(1, 0);
+      h->aci.clear();
+    }
+    std::string e = check_csr(n, n, h->qrp, h->qci, "Q");
+    if (e.empty() && m > 0) e = check_csr(m, n, h->arp, h->aci, "A");
+    if (!e.empty()) { h->state = 0; return fail(h, GMRF_ERR_ARG, e); }
+    // diagonal, symmetry
+    std::vector<int64_t> qdiag(n);
+    std::vector<int32_t> qrow(nnzq);
+    for (int64_t r = 0; r < n; ++r) {
+      int64_t dpos = find_entry(h->qrp, h->qci, r, (int32_t)r);
+      if (dpos < 0) { h->state = 0; return fail(h, GMRF_ERR_ARG, "Q lacks diagonal entry " + std::to_string(r)); }
+      qdiag[r] = dpos;
+      for (int64_t q = h->qrp[r]; q < h->qrp[r + 1]; ++q) {
+        qrow[q] = (int32_t)r;
+        if (find_entry(h->qrp, h->qci, h->qci[q], (int32_t)r) < 0) {
+          h->state = 0;
+          return fail(h, GMRF_ERR_ARG, "pattern of Q is not symmetric");
+        }
+      }
+    }
+    // A row index, A^T (CSC) and the contribution list of A^T Q_eps A on Q's pattern
+    std::vector<int32_t> arow(nnza);
+    for (int64_t r = 0; r < m; ++r)
+      for (int64_t q = h->arp[r]; q < h->arp[r + 1]; ++q) arow[q] = (int32_t)r;
+    std::vector<int64_t> atp(n + 1, 0);
+    for (int64_t q = 0; q < nnza; ++q) atp[h->aci[q] + 1]++;
+    for (int64_t i = 0; i < n; ++i) atp[i + 1] += atp[i];
+    std::vector<int32_t> ati(nnza);
+    {
+      std::vector<int64_t> fill(atp.begin(), atp.end() - 1);
+      for (int64_t q = 0; q < nnza; ++q) ati[fill[h->aci[q]]++] = (int32_t)q;
+    }
+    std::vector<int64_t> cptr(nnzq + 1, 0);
+    for (int64_t r = 0; r < m; ++r) {
+      for (int64_t a1 = h->arp[r]; a1 < h->arp[r + 1]; ++a1) {
+        for (int64_t a2 = h->arp[r]; a2 < h->arp[r + 1]; ++a2) {
+          int64_t e2 = find_entry(h->qrp, h->qci, h->aci[a1], h->aci[a2]);
+          if (e2 < 0) {
+            h->state = 0;
+            return fail(h, GMRF_ERR_ARG, "A^T Q_eps A has an entry outside the pattern of Q");
+          }
+          cptr[e2 + 1]++;
+        }
+      }
+    }
+    for (int64_t e2 = 0; e2 < nnzq; ++e2) cptr[e2 + 1] += cptr[e2];
+    std::vector<int32_t> cpair(2 * (size_t)cptr[nnzq]);
+    {
+      std::vector<int64_t> fill(cptr.begin(), cptr.end() - 1);
+      for (int64_t r = 0; r < m; ++r)
+        for (int64_t a1 = h->arp[r]; a1 < h->arp[r + 1]; ++a1)
+          for (int64_t a2 = h->arp[r]; a2 < h->arp[r + 1]; ++a2) {
+            int64_t e2 = find_entry(h->qrp, h->qci, h->aci[a1], h->aci[a2]);
+            int64_t q = fill[e2]++;
+            cpair[2 * q] = (int32_t)a1;
+            cpair[2 * q + 1] = (int32_t)a2;
+          }
+    }
+    HIPCHK(h, upload(h->d_qrp, h->qrp, st));
+    HIPCHK(h, upload(h->d_qci, h->qci, st));
+    HIPCHK(h, upload(h->d_qrow, qrow, st));
+    HIPCHK(h, upload(h->d_qdiag, qdiag, st));
+    HIPCHK(h, upload(h->d_arp, h->arp, st));
+    HIPCHK(h, upload(h->d_aci, h->aci, st));
+    HIPCHK(h, upload(h->d_arow, arow, st));
+    HIPCHK(h, upload(h->d_atp, atp, st));
+    HIPCHK(h, upload(h->d_ati, ati, st));
+    HIPCHK(h, upload(h->d_cptr, cptr, st));
+    HIPCHK(h, upload(h->d_cpair, cpair, st));
+    HIPCHK(h, h->d_qval.alloc(nnzq));
+    HIPCHK(h, h->d_aval.alloc(std::max<int64_t>(nnza, 1)));
+    HIPCHK(h, h->d_qeps.alloc(std::max<int64_t>(m, 1)));
+    HIPCHK(h, h->d_y.alloc(std::max<int64_t>(m, 1)));
+    HIPCHK(h, h->d_b.alloc(std::max<int64_t>(m, 1)));
+    HIPCHK(h, h->d_mu.alloc(n));
+    HIPCHK(h, h->d_qpost.alloc(nnzq));
+    HIPCHK(h, h->d_h.alloc(n));
+    HIPCHK(h, h->d_rvec.alloc(std::max<int64_t>(m, 1)));
+    // blocks
+    h->nblocks = 1;
+    h->block_ptr.assign({0, n});
+    if (n_blocks > 0 && block_ptr) {
+      if (block_ptr[0] != 0 || block_ptr[n_blocks] != n) return fail(h, GMRF_ERR_ARG, "block_ptr must span 0..n");
+      for (int64_t q = 0; q < n_blocks; ++q)
+        if (block_ptr[q + 1] < block_ptr[q]) return fail(h, GMRF_ERR_ARG, "block_ptr decreases");
+      h->nblocks = n_blocks;
+      h->block_ptr.assign(block_ptr, block_ptr + n_blocks + 1);
+    }
+  }
+  HIPCHK(h, copy_d2d(h->d_qval.p, q_val, nnzq * sizeof(double), st));
+  if (m > 0) {
+    HIPCHK(h, copy_d2d(h->d_aval.p, a_val, nnza * sizeof(double), st));
+    HIPCHK(h, copy_d2d(h->d_qeps.p, q_eps, m * sizeof(double), st));
+    HIPCHK(h, copy_d2d(h->d_y.p, y, m * sizeof(double), st));
+  }
+  h->has_b = b != nullptr;
+  h->has_mu = mu_prior != nullptr;
+  if (b && m > 0) HIPCHK(h, copy_d2d(h->d_b.p, b, m * sizeof(double), st));
+  if (mu_prior) HIPCHK(h, copy_d2d(h->d_mu.p, mu_prior, n * sizeof(double), st));
+  gmrf_status rc = assemble_device(h);
+  if (rc != GMRF_OK) return rc;
+  h->state |= ST_ASSEMBLED;
+  h->state &= ~(ST_FACTORED | ST_SOLVED);
+  return GMRF_OK;
+}
+
+gmrf_status gmrf_update_values(gmrf_t h, const double* q_val, const double* a_val, const double* q_eps,
+                               const double* y, const double* b) {
+  if (!h) return GMRF_ERR_ARG;
+  if (!(h->state & ST_ASSEMBLED)) return fail(h, GMRF_ERR_STATE, "gmrf_update_values before gmrf_assemble");
+  hipStream_t st = h->stream;
+  if (q_val) HIPCHK(h, copy_d2d(h->d_qval.p, q_val, h->nnzq * sizeof(double), st));
+  if (h->m > 0) {
+    if (a_val) HIPCHK(h, copy_d2d(h->d_aval.p, a_val, h->nnza * sizeof(double), st));
+    if (q_eps) HIPCHK(h, copy_d2d(h->d_qeps.p, q_eps, h->m * sizeof(double), st));
+    if (y) HIPCHK(h, copy_d2d(h->d_y.p, y, h->m * sizeof(double), st));
+    if (b) { HIPCHK(h, copy_d2d(h->d_b.p, b, h->m * sizeof(double), st)); h->has_b = true; }
+  }
+  gmrf_status rc = assemble_device(h);
+  if (rc != GMRF_OK) return rc;
+  h->state &= ~(ST_FACTORED | ST_SOLVED);
+  return GMRF_OK;
+}
+
+static void fill_opts(const gmrf_options* o, AnalyzeOptions& opt) {
+  opt = AnalyzeOptions();
+  if (!o) return;
+  if (o->leaf_size > 0) opt.leaf_size = o->leaf_size;
+  if (o->relax_small > 0) opt.relax_small = o->relax_small;
+  if (o->relax_mid > 0) opt.relax_mid = o->relax_mid;
+  if (o->relax_big > 0) opt.relax_big = o->relax_big;
+}
+
+gmrf_status gmrf_analyze(gmrf_t h, const double* coords, int dim, const gmrf_options* opts) {
+  if (!h) return GMRF_ERR_ARG;
+  if (!(h->state & ST_ASSEMBLED)) return fail(h, GMRF_ERR_STATE, "gmrf_analyze before gmrf_assemble");
+  if (coords && (dim < 1 || dim > 3)) return fail(h, GMRF_ERR_ARG, "dim must be 1..3");
+  if (hipSetDevice(h->device) != hipSuccess) return fail(h, GMRF_ERR_HIP, "hipSetDevice failed");
+  fill_opts(opts, h->opt);
+  h->opt.nb = kNB;
+  std::string e = analyze(h->n, h->qrp.data(), h->qci.data(), coords, coords ? dim : 0, h->opt, h->sym);
+  if (!e.empty()) return fail(h, GMRF_ERR_ARG, e);
+  gmrf_status rc = build_plan(h);
+  if (rc != GMRF_OK) return rc;
+  h->state = (h->state & ST_ASSEMBLED) | ST_ANALYZED;
+  h->prec = -1;
+  return GMRF_OK;
+}
+
+gmrf_status gmrf_factor(gmrf_t h, gmrf_precision p) {
+  if (!h) return GMRF_ERR_ARG;
+  if (!(h->state & ST_ANALYZED)) return fail(h, GMRF_ERR_STATE, "gmrf_factor before gmrf_analyze");
+  if (p != GMRF_FP64 && p != GMRF_FP32_REFINE) return fail(h, GMRF_ERR_ARG, "unknown precision");
+  if (hipSetDevice(h->device) != hipSuccess) return fail(h, GMRF_ERR_HIP, "hipSetDevice failed");
+  HIPCHK(h, hipEventRecord(h->ev[0], h->stream));
+  gmrf_status rc = p == GMRF_FP64 ? run_factor<double>(h) : run_factor<float>(h);
+  if (rc != GMRF_OK) return rc;
+  HIPCHK(h, hipEventRecord(h->ev[1], h->stream));
+  h->ev_factor = true;
+  h->prec = (int)p;
+  h->state |= ST_FACTORED;
+  h->state &= ~ST_SOLVED;
+  return GMRF_OK;
+}
+
+gmrf_status gmrf_logdet(gmrf_t h, double* out) {
+  if (!h || !out) return fail(h, GMRF_ERR_ARG, "null argument");
+  if (!(h->state & ST_FACTORED)) return fail(h, GMRF_ERR_STATE, "gmrf_logdet before gmrf_factor");
+  gmrf_status rc = check_status(h);
+  if (rc != GMRF_OK) return rc;
+  HIPCHK(h, h->d_ld.alloc(h->nblocks));
+  launch_logdet(h->stream, h->nblocks, h->d_bptr.p, h->d_bpiv.p, h->d_perm.p, h->d_piv.p, h->d_sexp.p, h->d_ld.p);
+  HIPCHK(h, hipGetLastError());
+  HIPCHK(h, hipMemcpyAsync(out, h->d_ld.p, h->nblocks * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  return GMRF_OK;
+}
+
+gmrf_status gmrf_solve(gmrf_t h, double* mu_out, int max_refine, double tol, int* iters_out, double* resid_out) {
+  if (!h || !mu_out) return fail(h, GMRF_ERR_ARG, "null argument");
+  if (!(h->state & ST_FACTORED)) return fail(h, GMRF_ERR_STATE, "gmrf_solve before gmrf_factor");
+  gmrf_status rc = check_status(h);
+  if (rc != GMRF_OK) return rc;
+  rc = alloc_solve(h, 1);
+  if (rc != GMRF_OK) return rc;
+  hipStream_t st = h->stream;
+  const int64_t n = h->n;
+  const bool f32 = h->prec == GMRF_FP32_REFINE;
+  HIPCHK(h, hipEventRecord(h->ev[2], st));
+  // w = Q_post^-1 h:  w = S P^T solve(P S h)
+  launch_permute_in(st, n, 1, h->d_perm.p, h->d_scale.p, h->d_h.p, n, h->d_xp.p);
+  if (f32) run_solve<float>(h, 1, true); else run_solve<double>(h, 1, true);
+  launch_permute_out(st, n, 1, h->d_perm.p, h->d_scale.p, h->d_xp.p, nullptr, 0, h->d_w.p, n, 0);
+  // FP64 residual and refinement
+  launch_norm2(st, n, h->d_h.p, h->d_red.p, h->d_norm.p);
+  double hn = 0.0;
+  HIPCHK(h, hipMemcpyAsync(&hn, h->d_norm.p, sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(h, hipStreamSynchronize(st));
+  if (hn == 0.0) hn = 1.0;
+  int it = 0;
+  double rel = 0.0;
+  const int maxit = std::max(0, max_refine);
+  while (true) {
+    launch_resid(st, n, h->d_qrp.p, h->d_qci.p, h->d_qpost.p, h->d_h.p, h->d_w.p, h->d_r.p);
+    launch_norm2(st, n, h->d_r.p, h->d_red.p, h->d_norm.p);
+    double rn = 0.0;
+    HIPCHK(h, hipMemcpyAsync(&rn, h->d_norm.p, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(h, hipStreamSynchronize(st));
+    rel = rn / hn;
+    if (rel <= tol || it >= maxit || !std::isfinite(rel)) break;
+    launch_permute_in(st, n, 1, h->d_perm.p, h->d_scale.p, h->d_r.p, n, h->d_xp.p);
+    if (f32) run_solve<float>(h, 1, true); else run_solve<double>(h, 1, true);
+    launch_permute_out(st, n, 1, h->d_perm.p, h->d_scale.p, h->d_xp.p, nullptr, 0, h->d_w.p, n, 1);
+    ++it;
+  }
+  // mu_post = mu + w
+  launch_add(st, n, h->d_w.p, h->has_mu ? h->d_mu.p : nullptr, h->d_mu_post.p);
+  HIPCHK(h, hipEventRecord(h->ev[3], st));
+  h->ev_solve = true;
+  HIPCHK(h, copy_d2d(mu_out, h->d_mu_post.p, n * sizeof(double), st));
+  HIPCHK(h, hipStreamSynchronize(st));
+  h->refine_iters = it;
+  h->refine_resid = rel;
+  if (iters_out) *iters_out = it;
+  if (resid_out) *resid_out = rel;
+  h->state |= ST_SOLVED;
+  if (!(rel <= tol) && (f32 || maxit > 0))
+    return fail(h, GMRF_ERR_NOT_CONVERGED, "refinement stopped at relative residual " + std::to_string(rel));
+  return GMRF_OK;
+}
+
+gmrf_status gmrf_sample(gmrf_t h, int64_t k, const float* z, double* x_out) {
+  if (!h || !z || !x_out) return fail(h, GMRF_ERR_ARG, "null argument");
+  if (k < 1 || k > 16) return fail(h, GMRF_ERR_ARG, "k must be 1..16");
+  if (!(h->state & ST_SOLVED)) return fail(h, GMRF_ERR_STATE, "gmrf_sample needs a posterior mean (gmrf_solve)");
+  gmrf_status rc = check_status(h);
+  if (rc != GMRF_OK) return rc;
+  rc = alloc_solve(h, (int)k);
+  if (rc != GMRF_OK) return rc;
+  hipStream_t st = h->stream;
+  launch_permute_in_f32(st, h->n, (int)k, z, h->d_xp.p);
+  if (h->prec == GMRF_FP32_REFINE) run_solve<float>(h, (int)k, false);
+  else run_solve<double>(h, (int)k, false);
+  launch_permute_out(st, h->n, (int)k, h->d_perm.p, h->d_scale.p, h->d_xp.p, h->d_mu_post.p, 0, x_out, h->n, 0);
+  HIPCHK(h, hipGetLastError());
+  HIPCHK(h, hipStreamSynchronize(st));
+  return GMRF_OK;
+}
+
+gmrf_status gmrf_selinv(gmrf_t h, double* var_out, double* sigma_q_out) {
+  if (!h || !var_out) return fail(h, GMRF_ERR_ARG, "null argument");
+  if (!(h->state & ST_FACTORED)) return fail(h, GMRF_ERR_STATE, "gmrf_selinv before gmrf_factor");
+  gmrf_status rc = check_status(h);
+  if (rc != GMRF_OK) return rc;
+  HIPCHK(h, hipEventRecord(h->ev[4], h->stream));
+  rc = h->prec == GMRF_FP32_REFINE ? run_selinv<float>(h, var_out, sigma_q_out)
+                                   : run_selinv<double>(h, var_out, sigma_q_out);
+  if (rc != GMRF_OK) return rc;
+  HIPCHK(h, hipEventRecord(h->ev[5], h->stream));
+  h->ev_sel = true;
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  return GMRF_OK;
+}
+
+gmrf_status gmrf_dot(gmrf_t h, int64_t len, const double* a, const double* b, double* out) {
+  if (!h || !a || !b || !out || len < 0) return fail(h, GMRF_ERR_ARG, "bad argument");
+  HIPCHK(h, h->d_red.alloc(1024));
+  HIPCHK(h, h->d_norm.alloc(4));
+  launch_dot(h->stream, len, a, b, h->d_red.p, h->d_norm.p);
+  HIPCHK(h, hipGetLastError());
+  HIPCHK(h, hipMemcpyAsync(out, h->d_norm.p, sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  return GMRF_OK;
+}
+
+static void fill_sym_stats(const Symbolic& Y, gmrf_stats_t* o) {
+  o->n = Y.n;
+  o->nnz_l = Y.nnzL;
+  o->stored_l = Y.stored_L;
+  o->n_super = Y.ns;
+  o->tree_depth = Y.max_depth + 1;
+  int64_t mf = 0;
+  for (int32_t s = 0; s < Y.ns; ++s) mf = std::max<int64_t>(mf, Y.nf(s));
+  o->max_front = mf;
+  o->flops_factor = Y.flops_factor;
+  o->flops_selinv = Y.flops_selinv;
+  o->flops_solve = Y.flops_solve;
+}
+
+gmrf_status gmrf_stats(gmrf_t h, gmrf_stats_t* out) {
+  if (!h || !out) return fail(h, GMRF_ERR_ARG, "null argument");
+  std::memset(out, 0, sizeof(*out));
+  out->failed_index = -1;
+  gmrf_status rc = GMRF_OK;
+  if (h->state & ST_FACTORED) rc = check_status(h);
+  if (h->state & ST_ANALYZED) fill_sym_stats(h->sym, out);
+  out->n = h->n;
+  out->nnz_q = h->nnzq;
+  out->m = h->m;
+  out->nnz_a = h->nnza;
+  const double w = h->prec == GMRF_FP32_REFINE ? 4.0 : 8.0;
+  out->bytes_front_ws = (double)(h->sym.Wsize[0] + h->sym.Wsize[1]) * w;
+  out->bytes_factor = (double)h->sym.Lsize * w;
+  out->failed_index = h->failed_index;
+  out->precision = h->prec;
+  out->refine_iters = h->refine_iters;
+  out->refine_resid = h->refine_resid;
+  return rc;
+}
+
+gmrf_status gmrf_pivot_order(gmrf_t h, int32_t* perm_out) {
+  if (!h || !perm_out) return fail(h, GMRF_ERR_ARG, "null argument");
+  if (!(h->state & ST_ANALYZED)) return fail(h, GMRF_ERR_STATE, "gmrf_pivot_order before gmrf_analyze");
+  std::memcpy(perm_out, h->sym.perm.data(), sizeof(int32_t) * h->n);
+  return GMRF_OK;
+}
+
+gmrf_status gmrf_phase_ms(gmrf_t h, double* out3) {
+  if (!h || !out3) return fail(h, GMRF_ERR_ARG, "null argument");
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  out3[0] = h->ev_factor ? elapsed(h->ev[0], h->ev[1]) : 0.0;
+  out3[1] = h->ev_solve ? elapsed(h->ev[2], h->ev[3]) : 0.0;
+  out3[2] = h->ev_sel ? elapsed(h->ev[4], h->ev[5]) : 0.0;
+  return GMRF_OK;
+}
+
+gmrf_status gmrf_symbolic_host(int64_t n, const int64_t* rowptr, const int32_t* col, const double* coords, int dim,
+                               const gmrf_options* opts, int32_t* perm_out, int64_t* colcount_out,
+                               gmrf_stats_t* stats_out) {
+  if (n <= 0 || !rowptr || !col) return GMRF_ERR_ARG;
+  std::vector<int64_t> rp(rowptr, rowptr + n + 1);
+  std::vector<int32_t> ci(col, col + rp[n]);
+  if (!check_csr(n, n, rp, ci, "Q").empty()) return GMRF_ERR_ARG;
+  AnalyzeOptions opt;
+  fill_opts(opts, opt);
+  opt.nb = kNB;
+  Symbolic Y;
+  std::string e = analyze(n, rp.data(), ci.data(), coords, coords ? dim : 0, opt, Y);
+  if (!e.empty()) return GMRF_ERR_ARG;
+  if (perm_out) std::memcpy(perm_out, Y.perm.data(), sizeof(int32_t) * n);
+  if (colcount_out) std::memcpy(colcount_out, Y.colcount.data(), sizeof(int64_t) * n);
+  if (stats_out) {
+    std::memset(stats_out, 0, sizeof(*stats_out));
+    fill_sym_stats(Y, stats_out);
+    stats_out->nnz_q = rp[n];
+    stats_out->failed_index = -1;
+    stats_out->bytes_front_ws = 8.0 * (double)(Y.Wsize[0] + Y.Wsize[1]);
+    stats_out->bytes_factor = 8.0 * (double)Y.Lsize;
+  }
+  return GMRF_OK;
+}
+
+}  // extern "C"

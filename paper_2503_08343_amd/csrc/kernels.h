@@ -1,0 +1,125 @@
+// Device-side data of the numeric phase and the launch wrappers of the HIP kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace gmrf {
+
+constexpr int kTile = 64;     // dense tile edge (rows/cols) of the front kernels
+constexpr int kNB = 64;       // diagonal block width; equals the analysis option nb
+
+// Read-only symbolic arrays on the device (pivot numbering).
+struct DevSym {
+  int64_t n;
+  const int32_t* perm;      // pivot -> original
+  const int32_t* sfirst;    // ns+1
+  const int64_t* rowptr;    // ns+1
+  const int32_t* rows;      // front index lists
+  const int32_t* relpos;    // child R -> parent front position
+  const int32_t* child_ptr; // ns+1
+  const int32_t* child_idx;
+  const int64_t* Loff;
+  const int64_t* Woff;
+  const int64_t* Doff;
+  const int64_t* Voff;
+};
+
+// One batched launch over a list of fronts; prefix[i] = first work-group of front i.
+struct LaunchList {
+  const int32_t* fronts;
+  const int64_t* prefix;
+  int32_t count;
+  int64_t total;            // number of work-groups
+};
+
+template <typename T>
+struct NumBufs {
+  T* L;            // supernodal panels
+  T* D;            // inverse diagonal blocks (nb x nb each)
+  double* piv;     // FP64 pivots L_jj (pivot order)
+  T* Wcur;         // front buffer of the current depth
+  T* Wchild;       // front buffer of the child depth
+  int32_t* status; // first failing pivot (INT32_MAX if none)
+};
+
+// ---- assembly (original numbering) ----
+void launch_assemble_qpost(hipStream_t st, int64_t nnzq, const double* qval,
+                           const int64_t* cptr, const int32_t* cpair, const int32_t* arow,
+                           const double* aval, const double* qeps, double* qpost);
+void launch_obs_residual(hipStream_t st, int64_t m, const int64_t* arp, const int32_t* aci,
+                         const double* aval, const double* qeps, const double* y,
+                         const double* b, const double* mu, double* rvec);
+void launch_at_times(hipStream_t st, int64_t n, const int64_t* atp, const int32_t* ati,
+                     const int32_t* arow, const double* aval, const double* rvec, double* h);
+void launch_equilibrate(hipStream_t st, int64_t n, int64_t nnzq, const int64_t* qdiag,
+                        const int32_t* qrow, const int32_t* qcol, const double* qpost,
+                        int32_t* sexp, double* scale, double* qhat);
+void launch_fill_i32(hipStream_t st, int32_t* p, int64_t n, int32_t v);
+void launch_fill_f64(hipStream_t st, double* p, int64_t n, double v);
+
+// ---- factorisation ----
+template <typename T> void launch_zero(hipStream_t st, T* p, int64_t n);
+template <typename T> void launch_scatter(hipStream_t st, int64_t cnt, const int64_t* map_e,
+                                          const int64_t* map_off, const double* qhat, T* W);
+template <typename T> void launch_extend_add(hipStream_t st, const DevSym& S, const LaunchList& L,
+                                             int slot, const T* Wchild, T* Wcur);
+template <typename T> void launch_potrf(hipStream_t st, const DevSym& S, const LaunchList& L,
+                                        int step, NumBufs<T> B);
+template <typename T> void launch_trsm(hipStream_t st, const DevSym& S, const LaunchList& L,
+                                       int step, NumBufs<T> B);
+template <typename T> void launch_update(hipStream_t st, const DevSym& S, const LaunchList& L,
+                                         int step, int syrk, NumBufs<T> B);
+template <typename T> void launch_copy_L(hipStream_t st, const DevSym& S, const LaunchList& L,
+                                         NumBufs<T> B);
+void launch_logdet(hipStream_t st, int64_t nblocks, const int64_t* bptr, const int32_t* bpiv,
+                   const int32_t* perm, const double* piv, const int32_t* sexp, double* out);
+
+// ---- triangular solves (front vectors in FP64, L in T) ----
+struct SolveBufs {
+  double* xp;      // n x nrhs, pivot order, ld n
+  double* Vcur;    // front vectors of the current depth
+  double* Vchild;  // front vectors of the adjacent depth
+  int nrhs;
+};
+template <typename T> void launch_fvec_init(hipStream_t st, const DevSym& S, const LaunchList& L, SolveBufs V);
+template <typename T> void launch_fvec_extend(hipStream_t st, const DevSym& S, const LaunchList& L, int slot, SolveBufs V);
+template <typename T> void launch_fwd_diag(hipStream_t st, const DevSym& S, const LaunchList& L, int step, const T* D, SolveBufs V);
+template <typename T> void launch_fwd_update(hipStream_t st, const DevSym& S, const LaunchList& L, int step, const T* Lp, SolveBufs V);
+template <typename T> void launch_bwd_init(hipStream_t st, const DevSym& S, const LaunchList& L, const T* Lp, SolveBufs V);
+template <typename T> void launch_bwd_diag(hipStream_t st, const DevSym& S, const LaunchList& L, int step, const T* D, SolveBufs V);
+template <typename T> void launch_bwd_update(hipStream_t st, const DevSym& S, const LaunchList& L, int step, const T* Lp, SolveBufs V);
+void launch_permute_in(hipStream_t st, int64_t n, int nrhs, const int32_t* perm, const double* scale,
+                       const double* src, int64_t lds, double* xp);
+void launch_permute_in_f32(hipStream_t st, int64_t n, int nrhs, const float* z, double* xp);
+void launch_permute_out(hipStream_t st, int64_t n, int nrhs, const int32_t* perm, const double* scale,
+                        const double* xp, const double* add, int64_t ldadd, double* out, int64_t ldo,
+                        int accumulate);
+void launch_resid(hipStream_t st, int64_t n, const int64_t* rp, const int32_t* ci, const double* val,
+                  const double* h, const double* x, double* r);
+void launch_add(hipStream_t st, int64_t n, const double* a, const double* b, double* out);
+void launch_norm2(hipStream_t st, int64_t n, const double* v, double* partial, double* out);
+
+// ---- selected inversion ----
+template <typename T>
+struct SelBufs {
+  const T* L;
+  const T* D;
+  T* Scur;         // square Sigma fronts of the current depth
+  T* Spar;         // square Sigma fronts of the parent depth
+  T* Y;            // n_s x nb scratch per front (offset Voff * nb)
+  T* part;         // split-K partials
+};
+template <typename T> void launch_sel_gather(hipStream_t st, const DevSym& S, const LaunchList& L, const int32_t* sparent, SelBufs<T> B);
+template <typename T> void launch_sel_Y(hipStream_t st, const DevSym& S, const LaunchList& L, int step, SelBufs<T> B);
+template <typename T> void launch_sel_gemm(hipStream_t st, const DevSym& S, const LaunchList& L, int step, SelBufs<T> B);
+template <typename T> void launch_sel_diag_partial(hipStream_t st, const DevSym& S, const LaunchList& L, int step, SelBufs<T> B);
+template <typename T> void launch_sel_diag_finish(hipStream_t st, const DevSym& S, const LaunchList& L, const LaunchList& Lpart, int step, SelBufs<T> B);
+template <typename T> void launch_sel_extract(hipStream_t st, const DevSym& S, const LaunchList& L, SelBufs<T> B,
+                                              const double* scale, double* var);
+template <typename T> void launch_sel_pattern(hipStream_t st, int64_t cnt, const int64_t* map_e,
+                                              const int64_t* map_off, const int32_t* qrow,
+                                              const int32_t* qcol, const double* scale,
+                                              const T* Scur, double* sigq);
+void launch_dot(hipStream_t st, int64_t n, const double* a, const double* b, double* partial, double* out);
+
+}  // namespace gmrf

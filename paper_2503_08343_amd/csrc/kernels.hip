@@ -1,0 +1,1070 @@
+// HIP kernels of the GMRF posterior path for gfx950 (MI355X).
+//
+// Numeric phase = multifrontal supernodal Cholesky of P Q^ P^T (Sec. 3.2), scheduled by
+// depth of the supernodal elimination tree: every front of one depth is processed by
+// the same batched launch.  Dense front work is blocked in 64-wide column blocks:
+//   * diagonal 64x64 blocks are factored in FP64 in LDS (also in the FP32 mode) and
+//     inverted (the inverse drives the panel TRSM and the solves),
+//   * panel TRSM, panel update and the trailing SYRK are 64x64 MFMA tiles
+//     (v_mfma_f64_16x16x4f64 / v_mfma_f32_16x16x4f32), operands staged in LDS,
+//   * children's update matrices are pulled into the parent front one child slot at
+//     a time (deterministic, no floating-point atomics).
+// Solves pass update vectors up the tree (forward) and read ancestors' solution
+// entries (backward).  Selected inversion runs the blocked Takahashi recursion on a
+// square Sigma front per supernode, top-down (Sec. 3.2, marginal variances).
+#include "kernels.h"
+
+#include <climits>
+
+namespace gmrf {
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kP = 80;        // LDS row pitch of the MFMA operand tiles (bank spread)
+constexpr int kTK = 16;       // K chunk of the MFMA tile loop
+constexpr int kChunk = 512;   // rows per split-K partial in the Sigma diagonal blocks
+
+template <typename T> struct V4;
+template <> struct V4<double> { typedef double type __attribute__((ext_vector_type(4))); };
+template <> struct V4<float> { typedef float type __attribute__((ext_vector_type(4))); };
+
+__device__ __forceinline__ V4<double>::type mfma(double a, double b, V4<double>::type c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ V4<float>::type mfma(float a, float b, V4<float>::type c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ int fn(const DevSym& S, int s) { return (int)(S.rowptr[s + 1] - S.rowptr[s]); }
+__device__ __forceinline__ int fp(const DevSym& S, int s) { return S.sfirst[s + 1] - S.sfirst[s]; }
+
+// work-group -> (list index, local work-group index) by binary search on the prefix
+__device__ __forceinline__ void find_front(const LaunchList& L, int64_t wg, int& fi, int64_t& loc) {
+  int lo = 0, hi = L.count - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (L.prefix[mid] <= wg) lo = mid; else hi = mid - 1;
+  }
+  fi = lo;
+  loc = wg - L.prefix[lo];
+}
+
+__device__ __forceinline__ int64_t wg_id() { return (int64_t)blockIdx.x; }
+
+// C(64x64 tile) = sum_k Aop[m][k] Bop[k][n], k < K, rows m < M, cols n < N valid.
+//  A_KC=false: Aop[m][k] = A[m + k*lda];  A_KC=true: Aop[m][k] = A[k + m*lda]
+//  B_KC=true:  Bop[k][n] = B[k + n*ldb];  B_KC=false: Bop[k][n] = B[n + k*ldb]
+// Wave w owns the 32x32 sub-tile at rows 32*(w&1), cols 32*(w>>1): 2x2 MFMA 16x16 blocks.
+// acc[i][j][r] holds C[32*(w&1) + 16 i + acc_row<T>(lane, r)][32*(w>>1) + 16 j + (lane&15)].
+template <typename T, bool A_KC, bool B_KC>
+__device__ __forceinline__ void gemm_tile(const T* __restrict__ A, int64_t lda,
+                                          const T* __restrict__ B, int64_t ldb, int M, int N,
+                                          int K, typename V4<T>::type (&acc)[2][2], T* sA, T* sB) {
+  const int t = threadIdx.x;
+  const int lane = t & 63;
+  const int w = t >> 6;
+  const int wm = (w & 1) * 32, wn = (w >> 1) * 32;
+  for (int k0 = 0; k0 < K; k0 += kTK) {
+    if (!A_KC) {
+      const int m = t & 63;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int k = (t >> 6) + 4 * i;
+        T v = T(0);
+        if (m < M && k0 + k < K) v = A[m + (int64_t)(k0 + k) * lda];
+        sA[k * kP + m] = v;
+      }
+    } else {
+      const int k = t & 15;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int m = (t >> 4) + 16 * i;
+        T v = T(0);
+        if (m < M && k0 + k < K) v = A[(k0 + k) + (int64_t)m * lda];
+        sA[k * kP + m] = v;
+      }
+    }
+    if (!B_KC) {
+      const int nn = t & 63;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int k = (t >> 6) + 4 * i;
+        T v = T(0);
+        if (nn < N && k0 + k < K) v = B[nn + (int64_t)(k0 + k) * ldb];
+        sB[k * kP + nn] = v;
+      }
+    } else {
+      const int k = t & 15;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int nn = (t >> 4) + 16 * i;
+        T v = T(0);
+        if (nn < N && k0 + k < K) v = B[(k0 + k) + (int64_t)nn * ldb];
+        sB[k * kP + nn] = v;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < kTK; kk += 4) {
+      T a[2], b[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) a[i] = sA[(kk + (lane >> 4)) * kP + wm + 16 * i + (lane & 15)];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) b[j] = sB[(kk + (lane >> 4)) * kP + wn + 16 * j + (lane & 15)];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = mfma(a[i], b[j], acc[i][j]);
+    }
+    __syncthreads();
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void zero_acc(typename V4<T>::type (&acc)[2][2]) {
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = typename V4<T>::type{T(0), T(0), T(0), T(0)};
+}
+
+// Row of accumulator register r held by `lane` in a 16x16 MFMA output block: the FP32
+// 16x16x4 instruction gives each lane 4 consecutive rows, the FP64 one gives rows
+// interleaved by 4 (one 64-bit register pair per row group).
+template <typename T> __device__ __forceinline__ int acc_row(int lane, int r);
+template <> __device__ __forceinline__ int acc_row<float>(int lane, int r) { return 4 * (lane >> 4) + r; }
+template <> __device__ __forceinline__ int acc_row<double>(int lane, int r) { return (lane >> 4) + 4 * r; }
+
+// visit every accumulator element with its tile-local (row, col)
+template <typename T, typename F>
+__device__ __forceinline__ void for_acc(typename V4<T>::type (&acc)[2][2], F f) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wm = (w & 1) * 32, wn = (w >> 1) * 32;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        f(wm + 16 * i + acc_row<T>(lane, r), wn + 16 * j + (lane & 15), acc[i][j][r]);
+}
+
+// ------------------------------------------------------------------ assembly kernels
+__global__ void k_assemble_qpost(int64_t nnzq, const double* __restrict__ qval,
+                                 const int64_t* __restrict__ cptr, const int32_t* __restrict__ cpair,
+                                 const int32_t* __restrict__ arow, const double* __restrict__ aval,
+                                 const double* __restrict__ qeps, double* __restrict__ qpost) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nnzq;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    double v = qval[e];
+    for (int64_t c = cptr[e]; c < cptr[e + 1]; ++c) {
+      const int32_t a1 = cpair[2 * c], a2 = cpair[2 * c + 1];
+      v += qeps[arow[a1]] * aval[a1] * aval[a2];
+    }
+    qpost[e] = v;
+  }
+}
+
+__global__ void k_obs_residual(int64_t m, const int64_t* __restrict__ arp, const int32_t* __restrict__ aci,
+                               const double* __restrict__ aval, const double* __restrict__ qeps,
+                               const double* __restrict__ y, const double* __restrict__ b,
+                               const double* __restrict__ mu, double* __restrict__ rvec) {
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < m;
+       r += (int64_t)gridDim.x * blockDim.x) {
+    double s = y[r];
+    if (b) s -= b[r];
+    if (mu) {
+      double am = 0.0;
+      for (int64_t e = arp[r]; e < arp[r + 1]; ++e) am += aval[e] * mu[aci[e]];
+      s -= am;
+    }
+    rvec[r] = qeps[r] * s;
+  }
+}
+
+__global__ void k_at_times(int64_t n, const int64_t* __restrict__ atp, const int32_t* __restrict__ ati,
+                           const int32_t* __restrict__ arow, const double* __restrict__ aval,
+                           const double* __restrict__ rvec, double* __restrict__ h) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (int64_t t = atp[i]; t < atp[i + 1]; ++t) {
+      const int32_t a = ati[t];
+      s += aval[a] * rvec[arow[a]];
+    }
+    h[i] = s;
+  }
+}
+
+// power-of-two equilibration: s_i = 2^-floor(ilogb(Q_ii)/2), exact in floating point
+__device__ __forceinline__ int eq_exp(double d) {
+  if (!(d > 0.0) || !isfinite(d)) return 0;
+  const int k = ilogb(d);
+  return -(k >> 1);
+}
+
+__global__ void k_equil_rows(int64_t n, const int64_t* __restrict__ qdiag, const double* __restrict__ qpost,
+                             int32_t* __restrict__ sexp, double* __restrict__ scale) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int e = eq_exp(qpost[qdiag[i]]);
+    sexp[i] = e;
+    scale[i] = ldexp(1.0, e);
+  }
+}
+
+__global__ void k_equil_vals(int64_t nnzq, const int64_t* __restrict__ qdiag, const int32_t* __restrict__ qrow,
+                             const int32_t* __restrict__ qcol, const double* __restrict__ qpost,
+                             double* __restrict__ qhat) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nnzq;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int er = eq_exp(qpost[qdiag[qrow[e]]]);
+    const int ec = eq_exp(qpost[qdiag[qcol[e]]]);
+    qhat[e] = ldexp(qpost[e], er + ec);
+  }
+}
+
+template <typename V>
+__global__ void k_fill(V* p, int64_t n, V v) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+template <typename T>
+__global__ void k_scatter(int64_t cnt, const int64_t* __restrict__ map_e, const int64_t* __restrict__ map_off,
+                          const double* __restrict__ qhat, T* __restrict__ W) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cnt;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t e = map_e[i];
+    if (e >= 0) W[map_off[i]] = (T)qhat[e];
+  }
+}
+
+// ------------------------------------------------------------------ factorisation kernels
+// child slot `slot` of every listed parent: add the child's update matrix (lower
+// triangle, column `loc` per work-group) into the parent front.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_extend_add(DevSym S, LaunchList L, int slot,
+                                                         const T* __restrict__ Wc, T* __restrict__ Wp) {
+  int fi; int64_t loc;
+  find_front(L, wg_id(), fi, loc);
+  const int s = L.fronts[fi];
+  const int c = S.child_idx[S.child_ptr[s] + slot];
+  const int nc = fn(S, c), pc = fp(S, c), uc = nc - pc;
+  const int b = (int)loc;
+  const int32_t* rel = S.relpos + S.rowptr[c] + pc;
+  const int ns = fn(S, s);
+  const T* src = Wc + S.Woff[c] + (int64_t)(pc + b) * nc + pc;
+  T* dst = Wp + S.Woff[s] + (int64_t)rel[b] * ns;
+  for (int a = b + threadIdx.x; a < uc; a += blockDim.x) dst[rel[a]] += src[a];
+}
+
+// FP64 Cholesky of the step-th 64x64 diagonal block of each listed front, in LDS, and
+// the inverse of the resulting lower-triangular block.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_potrf(DevSym S, LaunchList L, int step, NumBufs<T> B) {
+  __shared__ double A[kNB][kNB + 1];
+  __shared__ double X[kNB][kNB + 1];
+  __shared__ int fail;
+  const int s = L.fronts[blockIdx.x];
+  const int n = fn(S, s), p = fp(S, s);
+  const int k0 = step * kNB;
+  const int kb = min(kNB, p - k0);
+  T* F = B.Wcur + S.Woff[s];
+  const int t = threadIdx.x;
+  for (int idx = t; idx < kNB * kNB; idx += kThreads) {
+    const int i = idx & (kNB - 1), j = idx >> 6;
+    double v = 0.0;
+    if (i < kb && j < kb && i >= j) v = (double)F[(k0 + i) + (int64_t)(k0 + j) * n];
+    A[i][j] = v;
+  }
+  if (t == 0) fail = -1;
+  __syncthreads();
+  for (int j = 0; j < kb; ++j) {
+    const double d = A[j][j];
+    const bool bad = !(d > 0.0);
+    const double ljj = bad ? 1.0 : sqrt(d);
+    __syncthreads();
+    if (t == 0) {
+      A[j][j] = ljj;
+      if (bad && fail < 0) fail = j;
+    }
+    for (int i = j + 1 + t; i < kb; i += kThreads) A[i][j] = A[i][j] / ljj;
+    __syncthreads();
+    const int m = kb - j - 1;
+    for (int idx = t; idx < m * m; idx += kThreads) {
+      const int ii = idx % m, ll = idx / m;
+      if (ii >= ll) {
+        const int i = j + 1 + ii, l = j + 1 + ll;
+        A[i][l] -= A[i][j] * A[l][j];
+      }
+    }
+    __syncthreads();
+  }
+  if (t < kNB) {
+    const int c = t;
+    for (int i = 0; i < kNB; ++i) X[i][c] = 0.0;
+    if (c < kb) {
+      X[c][c] = 1.0 / A[c][c];
+      for (int i = c + 1; i < kb; ++i) {
+        double acc = 0.0;
+        for (int l = c; l < i; ++l) acc += A[i][l] * X[l][c];
+        X[i][c] = -acc / A[i][i];
+      }
+    }
+  }
+  __syncthreads();
+  for (int idx = t; idx < kNB * kNB; idx += kThreads) {
+    const int i = idx & (kNB - 1), j = idx >> 6;
+    if (i < kb && j < kb && i >= j) F[(k0 + i) + (int64_t)(k0 + j) * n] = (T)A[i][j];
+  }
+  T* Dblk = B.D + S.Doff[s] + (int64_t)step * kNB * kNB;
+  for (int idx = t; idx < kNB * kNB; idx += kThreads) {
+    const int i = idx & (kNB - 1), j = idx >> 6;
+    Dblk[i + j * kNB] = (T)X[i][j];
+  }
+  if (t < kb) B.piv[S.sfirst[s] + k0 + t] = A[t][t];
+  if (t == 0 && fail >= 0) atomicMin(B.status, S.sfirst[s] + k0 + fail);
+}
+
+// panel rows below the step-th diagonal block: F[r, blk] = F[r, blk] * Linv^T
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_trsm(DevSym S, LaunchList L, int step, NumBufs<T> B) {
+  __shared__ T sA[kTK * kP];
+  __shared__ T sB[kTK * kP];
+  int fi; int64_t loc;
+  find_front(L, wg_id(), fi, loc);
+  const int s = L.fronts[fi];
+  const int n = fn(S, s), p = fp(S, s);
+  const int k0 = step * kNB, kb = min(kNB, p - k0);
+  const int row0 = k0 + kb + kTile * (int)loc;
+  const int M = min(kTile, n - row0);
+  T* F = B.Wcur + S.Woff[s];
+  const T* Dblk = B.D + S.Doff[s] + (int64_t)step * kNB * kNB;
+  typename V4<T>::type acc[2][2];
+  zero_acc<T>(acc);
+  gemm_tile<T, false, false>(F + row0 + (int64_t)k0 * n, n, Dblk, kNB, M, kb, kb, acc, sA, sB);
+  for_acc<T>(acc, [&](int r, int c, T v) {
+    if (r < M && c < kb) F[(row0 + r) + (int64_t)(k0 + c) * n] = v;
+  });
+}
+
+// lower-trapezoid tile update C -= A B^T inside each front.
+// syrk=0: step-th panel update: columns [k0+kb, p), rows >= column, K range [k0, k0+kb)
+// syrk=1: trailing update matrix: columns [p, n), rows >= column, K range [0, p)
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_update(DevSym S, LaunchList L, int step, int syrk,
+                                                     NumBufs<T> B) {
+  __shared__ T sA[kTK * kP];
+  __shared__ T sB[kTK * kP];
+  int fi; int64_t loc;
+  find_front(L, wg_id(), fi, loc);
+  const int s = L.fronts[fi];
+  const int n = fn(S, s), p = fp(S, s);
+  int clo, chi, klo, khi;
+  if (syrk) { clo = p; chi = n; klo = 0; khi = p; }
+  else {
+    const int k0 = step * kNB, kb = min(kNB, p - k0);
+    clo = k0 + kb; chi = p; klo = k0; khi = k0 + kb;
+  }
+  // decode (column tile, row tile) of the lower trapezoid, column-major over tiles
+  int ct = 0;
+  int64_t r = loc;
+  while (true) {
+    const int c0 = clo + kTile * ct;
+    if (c0 >= chi) return;   // unreachable for a consistent launch list
+    const int64_t nr = (n - c0 + kTile - 1) / kTile;
+    if (r < nr) break;
+    r -= nr;
+    ++ct;
+  }
+  const int col0 = clo + kTile * ct;
+  const int row0 = col0 + kTile * (int)r;
+  const int M = min(kTile, n - row0), N = min(kTile, chi - col0);
+  T* F = B.Wcur + S.Woff[s];
+  typename V4<T>::type acc[2][2];
+  zero_acc<T>(acc);
+  gemm_tile<T, false, false>(F + row0 + (int64_t)klo * n, n, F + col0 + (int64_t)klo * n, n, M, N,
+                             khi - klo, acc, sA, sB);
+  for_acc<T>(acc, [&](int rr, int cc, T v) {
+    const int gi = row0 + rr, gj = col0 + cc;
+    if (rr < M && cc < N && gi >= gj) F[gi + (int64_t)gj * n] -= v;
+  });
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_copy_L(DevSym S, LaunchList L, NumBufs<T> B) {
+  int fi; int64_t loc;
+  find_front(L, wg_id(), fi, loc);
+  const int s = L.fronts[fi];
+  const int n = fn(S, s);
+  const int j = (int)loc;
+  const T* src = B.Wcur + S.Woff[s] + (int64_t)j * n;
+  T* dst = B.L + S.Loff[s] + (int64_t)j * n;
+  for (int i = j + threadIdx.x; i < n; i += blockDim.x) dst[i] = src[i];
+}
+
+// per-block log det = 2 sum log L^_jj - 2 ln2 sum e_i (equilibration exponents), summed
+// in a fixed order (per-thread strided partial sums, then a binary tree)
+__global__ __launch_bounds__(kThreads) void k_logdet(const int64_t* __restrict__ bptr,
+                                                     const int32_t* __restrict__ bpiv,
+                                                     const int32_t* __restrict__ perm,
+                                                     const double* __restrict__ piv,
+                                                     const int32_t* __restrict__ sexp,
+                                                     double* __restrict__ out) {
+  __shared__ double red[kThreads];
+  const int b = blockIdx.x;
+  double acc = 0.0;
+  for (int64_t q = bptr[b] + threadIdx.x; q < bptr[b + 1]; q += kThreads) {
+    const int32_t j = bpiv[q];
+    acc += 2.0 * log(piv[j]) - 2.0 * 0.69314718055994530942 * (double)sexp[perm[j]];
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = kThreads / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[b] = red[0];
+}
+
+// ------------------------------------------------------------------ solve kernels
+// front vector of supernode s: V + Voff[s]*nrhs, entry (i, r) at i + r*n_s
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_fvec_init(DevSym S, LaunchList L, SolveBufs V) {
+  const int s = L.fronts[blockIdx.x];
+  const int n = fn(S, s), p = fp(S, s);
+  double* v = V.Vcur + S.Voff[s] * V.nrhs;
+  const int64_t f0 = S.sfirst[s];
+  for (int idx = threadIdx.x; idx < n * V.nrhs; idx += blockDim.x) {
+    const int i = idx % n, r = idx / n;
+    v[idx] = i < p ? V.xp[f0 + i + (int64_t)r * S.n] : 0.0;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_fvec_extend(DevSym S, LaunchList L, int slot, SolveBufs V) {
+  const int s = L.fronts[blockIdx.x];
+  const int c = S.child_idx[S.child_ptr[s] + slot];
+  const int nc = fn(S, c), pc = fp(S, c), uc = nc - pc;
+  const int ns = fn(S, s);
+  const int32_t* rel = S.relpos + S.rowptr[c] + pc;
+  double* vp = V.Vcur + S.Voff[s] * V.nrhs;
+  const double* vc = V.Vchild + S.Voff[c] * V.nrhs;
+  for (int idx = threadIdx.x; idx < uc * V.nrhs; idx += blockDim.x) {
+    const int a = idx % uc, r = idx / uc;
+    vp[rel[a] + r * ns] += vc[pc + a + r * nc];
+  }
+}
+
+// x_blk = Linv * v_blk
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_fwd_diag(DevSym S, LaunchList L, int step, const T* __restrict__ D,
+                                                       SolveBufs V) {
+  __shared__ double xv[kNB * 16];
+  const int s = L.fronts[blockIdx.x];
+  const int n = fn(S, s), p = fp(S, s);
+  const int k0 = step * kNB, kb = min(kNB, p - k0);
+  double* v = V.Vcur + S.Voff[s] * V.nrhs;
+  const T* Li = D + S.Doff[s] + (int64_t)step * kNB * kNB;
+  for (int idx = threadIdx.x; idx < kb * V.nrhs; idx += blockDim.x) {
+    const int i = idx % kb, r = idx / kb;
+    xv[i + r * kNB] = v[k0 + i + r * n];
+  }
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < kb * V.nrhs; idx += blockDim.x) {
+    const int i = idx % kb, r = idx / kb;
+    double acc = 0.0;
+    for (int l = 0; l <= i; ++l) acc += (double)Li[i + l * kNB] * xv[l + r * kNB];
+    v[k0 + i + r * n] = acc;
+    V.xp[S.sfirst[s] + k0 + i + (int64_t)r * S.n] = acc;
+  }
+}
+
+// v[rows below block] -= L[rows, blk] * x_blk
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_fwd_update(DevSym S, LaunchList L, int step, const T* __restrict__ Lp,
+                                                         SolveBufs V) {
+  __shared__ double xv[kNB * 16];
+  int fi; int64_t loc;
+  find_front(L, wg_id(), fi, loc);
+  const int s = L.fronts[fi];
+  const int n = fn(S, s), p = fp(S, s);
+  const int k0 = step * kNB, kb = min(kNB, p - k0);
+  const int row0 = k0 + kb + kTile * (int)loc;
+  double* v = V.Vcur + S.Voff[s] * V.nrhs;
+  for (int idx = threadIdx.x; idx < kb * V.nrhs; idx += blockDim.x) {
+    const int i = idx % kb, r = idx / kb;
+    xv[i + r * kNB] = v[k0 + i + r * n];
+  }
+  __syncthreads();
+  const int i = threadIdx.x & 63, rg = threadIdx.x >> 6;
+  const int row = row0 + i;
+  if (row < n) {
+    const T* Lc = Lp + S.Loff[s] + row + (int64_t)k0 * n;
+    for (int r = rg; r < V.nrhs; r += 4) {
+      double acc = 0.0;
+      for (int c = 0; c < kb; ++c) acc += (double)Lc[(int64_t)c * n] * xv[c + r * kNB];
+      v[row + r * n] -= acc;
+    }
+  }
+}
+
+// r_S = y_S - L_RS^T x_R for a 64-column block of S; x_R gathered from the pivot vector
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_bwd_init(DevSym S, LaunchList L, const T* __restrict__ Lp,
+                                                       SolveBufs V) {
+  __shared__ double Ls[kTile][kTile + 1];
+  __shared__ double Xs[kTile][17];
+  int fi; int64_t loc;
+  find_front(L, wg_id(), fi, loc);
+  const int s = L.fronts[fi];
+  const int n = fn(S, s), p = fp(S, s);
+  const int j0 = kNB * (int)loc, jb = min(kNB, p - j0);
+  const int64_t f0 = S.sfirst[s];
+  const int32_t* rows = S.rows + S.rowptr[s];
+  const T* Lf = Lp + S.Loff[s];
+  const int t = threadIdx.x;
+  const int c = t & 63, rg = t >> 6;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int i0 = p; i0 < n; i0 += kTile) {
+    const int mi = min(kTile, n - i0);
+    for (int idx = t; idx < kTile * kTile; idx += kThreads) {
+      const int ii = idx & 63, jj = idx >> 6;
+      Ls[ii][jj] = (ii < mi && jj < jb) ? (double)Lf[(i0 + ii) + (int64_t)(j0 + jj) * n] : 0.0;
+    }
+    for (int idx = t; idx < kTile * V.nrhs; idx += kThreads) {
+      const int ii = idx & 63, r = idx >> 6;
+      Xs[ii][r] = ii < mi ? V.xp[rows[i0 + ii] + (int64_t)r * S.n] : 0.0;
+    }
+    __syncthreads();
+    for (int q = 0; q < 4; ++q) {
+      const int r = rg + 4 * q;
+      if (r < V.nrhs) {
+        double a = 0.0;
+        for (int ii = 0; ii < mi; ++ii) a += Ls[ii][c] * Xs[ii][r];
+        acc[q] += a;
+      }
+    }
+    __syncthreads();
+  }
+  double* v = V.Vcur + S.Voff[s] * V.nrhs;
+  if (c < jb) {
+    for (int q = 0; q < 4; ++q) {
+      const int r = rg + 4 * q;
+      if (r < V.nrhs) v[j0 + c + r * n] = V.xp[f0 + j0 + c + (int64_t)r * S.n] - acc[q];
+    }
+  }
+}
+
+// x_blk = Linv^T r_blk (block index counted from the right by `step`)
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_bwd_diag(DevSym S, LaunchList L, int step, const T* __restrict__ D,
+                                                       SolveBufs V) {
+  __shared__ double rv[kNB * 16];
+  const int s = L.fronts[blockIdx.x];
+  const int n = fn(S, s), p = fp(S, s);
+  const int nblk = (p + kNB - 1) / kNB;
+  const int k = nblk - 1 - step;
+  const int k0 = k * kNB, kb = min(kNB, p - k0);
+  double* v = V.Vcur + S.Voff[s] * V.nrhs;
+  const T* Li = D + S.Doff[s] + (int64_t)k * kNB * kNB;
+  for (int idx = threadIdx.x; idx < kb * V.nrhs; idx += blockDim.x) {
+    const int i = idx % kb, r = idx / kb;
+    rv[i + r * kNB] = v[k0 + i + r * n];
+  }
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < kb * V.nrhs; idx += blockDim.x) {
+    const int i = idx % kb, r = idx / kb;
+    double acc = 0.0;
+    for (int l = i; l < kb; ++l) acc += (double)Li[l + i * kNB] * rv[l + r * kNB];
+    v[k0 + i + r * n] = acc;
+    V.xp[S.sfirst[s] + k0 + i + (int64_t)r * S.n] = acc;
+  }
+}
+
+// r_j -= L[blk rows, j cols]^T x_blk for every column block j left of the current block
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_bwd_update(DevSym S, LaunchList L, int step, const T* __restrict__ Lp,
+                                                         SolveBufs V) {
+  __shared__ double Ls[kTile][kTile + 1];
+  __shared__ double xv[kNB * 16];
+  int fi; int64_t loc;
+  find_front(L, wg_id(), fi, loc);
+  const int s = L.fronts[fi];
+  const int n = fn(S, s), p = fp(S, s);
+  const int nblk = (p + kNB - 1) / kNB;
+  const int k = nblk - 1 - step;
+  const int k0 = k * kNB, kb = min(kNB, p - k0);
+  const int j0 = kNB * (int)loc;
+  double* v = V.Vcur + S.Voff[s] * V.nrhs;
+  const T* Lf = Lp + S.Loff[s];
+  const int t = threadIdx.x;
+  for (int idx = t; idx < kTile * kTile; idx += kThreads) {
+    const int ii = idx & 63, jj = idx >> 6;
+    Ls[ii][jj] = ii < kb ? (double)Lf[(k0 + ii) + (int64_t)(j0 + jj) * n] : 0.0;
+  }
+  for (int idx = t; idx < kb * V.nrhs; idx += kThreads) {
+    const int i = idx % kb, r = idx / kb;
+    xv[i + r * kNB] = v[k0 + i + r * n];
+  }
+  __syncthreads();
+  const int c = t & 63, rg = t >> 6;
+  for (int r = rg; r < V.nrhs; r += 4) {
+    double a = 0.0;
+    for (int ii = 0; ii < kb; ++ii) a += Ls[ii][c] * xv[ii + r * kNB];
+    v[j0 + c + r * n] -= a;
+  }
+}
+
+__global__ void k_permute_in(int64_t n, int nrhs, const int32_t* __restrict__ perm, const double* __restrict__ scale,
+                             const double* __restrict__ src, int64_t lds, double* __restrict__ xp) {
+  const int64_t tot = n * nrhs;
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < tot;
+       q += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t j = q % n, r = q / n;
+    const int32_t o = perm[j];
+    xp[q] = scale[o] * src[o + r * lds];
+  }
+}
+
+__global__ void k_permute_in_f32(int64_t tot, const float* __restrict__ z, double* __restrict__ xp) {
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < tot;
+       q += (int64_t)gridDim.x * blockDim.x)
+    xp[q] = (double)z[q];
+}
+
+__global__ void k_permute_out(int64_t n, int nrhs, const int32_t* __restrict__ perm, const double* __restrict__ scale,
+                              const double* __restrict__ xp, const double* __restrict__ add, int64_t ldadd,
+                              double* __restrict__ out, int64_t ldo, int accumulate) {
+  const int64_t tot = n * nrhs;
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < tot;
+       q += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t j = q % n, r = q / n;
+    const int32_t o = perm[j];
+    double v = scale[o] * xp[q];
+    if (accumulate) v += out[o + r * ldo];
+    else if (add) v += add[o + r * ldadd];
+    out[o + r * ldo] = v;
+  }
+}
+
+__global__ void k_resid(int64_t n, const int64_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                        const double* __restrict__ val, const double* __restrict__ h,
+                        const double* __restrict__ x, double* __restrict__ r) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (int64_t e = rp[i]; e < rp[i + 1]; ++e) s += val[e] * x[ci[e]];
+    r[i] = h[i] - s;
+  }
+}
+
+__global__ void k_add(int64_t n, const double* __restrict__ a, const double* __restrict__ b,
+                      double* __restrict__ out) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = b ? a[i] + b[i] : a[i];
+}
+
+constexpr int kRedBlocks = 512;
+
+// deterministic two-pass sum of a[i]*b[i] (b == nullptr: a[i]^2)
+__global__ __launch_bounds__(kThreads) void k_dot_partial(int64_t n, const double* __restrict__ a,
+                                                          const double* __restrict__ b,
+                                                          double* __restrict__ partial) {
+  __shared__ double red[kThreads];
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)kRedBlocks * kThreads)
+    acc += a[i] * (b ? b[i] : a[i]);
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = kThreads / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(kThreads) void k_dot_final(const double* __restrict__ partial, int sq,
+                                                        double* __restrict__ out) {
+  __shared__ double red[kThreads];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < kRedBlocks; i += kThreads) acc += partial[i];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = kThreads / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = sq ? sqrt(red[0]) : red[0];
+}
+
+// ------------------------------------------------------------------ selected inversion
+// Sigma front of s: square n_s x n_s (both triangles) at Scur + Woff[s].
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_sel_gather(DevSym S, LaunchList L, const int32_t* __restrict__ sparent,
+                                                          SelBufs<T> B) {
+  int fi; int64_t loc;
+  find_front(L, wg_id(), fi, loc);
+  const int s = L.fronts[fi];
+  const int n = fn(S, s), p = fp(S, s), u = n - p;
+  const int par = sparent[s];
+  const int np = fn(S, par);
+  const int b = (int)loc;
+  const int32_t* rel = S.relpos + S.rowptr[s] + p;
+  T* dst = B.Scur + S.Woff[s] + (int64_t)(p + b) * n + p;
+  const T* src = B.Spar + S.Woff[par] + (int64_t)rel[b] * np;
+  for (int a = threadIdx.x; a < u; a += blockDim.x) dst[a] = src[rel[a]];
+}
+
+// Y = L[R', blk] * Linv  (R' = rows after the block), stored with ld n_s from row 0
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_sel_Y(DevSym S, LaunchList L, int step, SelBufs<T> B) {
+  __shared__ T sA[kTK * kP];
+  __shared__ T sB[kTK * kP];
+  int fi; int64_t loc;
+  find_front(L, wg_id(), fi, loc);
+  const int s = L.fronts[fi];
+  const int n = fn(S, s), p = fp(S, s);
+  const int nblk = (p + kNB - 1) / kNB;
+  const int k = nblk - 1 - step;
+  const int k0 = k * kNB, kb = min(kNB, p - k0);
+  const int rs = k0 + kb;
+  const int row0 = rs + kTile * (int)loc;
+  const int M = min(kTile, n - row0);
+  const T* Lf = B.L + S.Loff[s];
+  const T* Dblk = B.D + S.Doff[s] + (int64_t)k * kNB * kNB;
+  typename V4<T>::type acc[2][2];
+  zero_acc<T>(acc);
+  gemm_tile<T, false, true>(Lf + row0 + (int64_t)k0 * n, n, Dblk, kNB, M, kb, kb, acc, sA, sB);
+  T* Y = B.Y + S.Voff[s] * kNB;
+  for_acc<T>(acc, [&](int r, int c, T v) {
+    if (r < M && c < kb) Y[(row0 - rs + r) + (int64_t)c * n] = v;
+  });
+}
+
+// Sigma[R', blk] = -Sigma[R', R'] Y, mirrored into Sigma[blk, R']
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_sel_gemm(DevSym S, LaunchList L, int step, SelBufs<T> B) {
+  __shared__ T sA[kTK * kP];
+  __shared__ T sB[kTK * kP];
+  int fi; int64_t loc;
+  find_front(L, wg_id(), fi, loc);
+  const int s = L.fronts[fi];
+  const int n = fn(S, s), p = fp(S, s);
+  const int nblk = (p + kNB - 1) / kNB;
+  const int k = nblk - 1 - step;
+  const int k0 = k * kNB, kb = min(kNB, p - k0);
+  const int rs = k0 + kb;
+  const int row0 = rs + kTile * (int)loc;
+  const int M = min(kTile, n - row0);
+  T* Sf = B.Scur + S.Woff[s];
+  const T* Y = B.Y + S.Voff[s] * kNB;
+  typename V4<T>::type acc[2][2];
+  zero_acc<T>(acc);
+  gemm_tile<T, false, true>(Sf + row0 + (int64_t)rs * n, n, Y, n, M, kb, n - rs, acc, sA, sB);
+  for_acc<T>(acc, [&](int r, int c, T v) {
+    if (r < M && c < kb) {
+      Sf[(row0 + r) + (int64_t)(k0 + c) * n] = -v;
+      Sf[(k0 + c) + (int64_t)(row0 + r) * n] = -v;
+    }
+  });
+}
+
+// partial[wg] = Y[chunk]^T Sigma[chunk, blk]  (kChunk rows of R' per work-group)
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_sel_diag_partial(DevSym S, LaunchList L, int step, SelBufs<T> B) {
+  __shared__ T sA[kTK * kP];
+  __shared__ T sB[kTK * kP];
+  int fi; int64_t loc;
+  find_front(L, wg_id(), fi, loc);
+  const int s = L.fronts[fi];
+  const int n = fn(S, s), p = fp(S, s);
+  const int nblk = (p + kNB - 1) / kNB;
+  const int k = nblk - 1 - step;
+  const int k0 = k * kNB, kb = min(kNB, p - k0);
+  const int rs = k0 + kb;
+  const int r0 = kChunk * (int)loc;               // offset inside R'
+  const int kr = max(0, min(kChunk, n - rs - r0));
+  const T* Sf = B.Scur + S.Woff[s];
+  const T* Y = B.Y + S.Voff[s] * kNB;
+  typename V4<T>::type acc[2][2];
+  zero_acc<T>(acc);
+  if (kr > 0)
+    gemm_tile<T, true, true>(Y + r0, n, Sf + (rs + r0) + (int64_t)k0 * n, n, kb, kb, kr, acc, sA, sB);
+  T* out = B.part + wg_id() * (kNB * kNB);
+  for_acc<T>(acc, [&](int r, int c, T v) { out[r + c * kNB] = v; });
+}
+
+// Sigma[blk, blk] = Linv^T Linv - sum of the partials (fixed order)
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_sel_diag_finish(DevSym S, LaunchList L, LaunchList Lpart, int step,
+                                                              SelBufs<T> B) {
+  __shared__ double Li[kNB][kNB + 1];
+  const int fi = blockIdx.x;
+  const int s = L.fronts[fi];
+  const int n = fn(S, s), p = fp(S, s);
+  const int nblk = (p + kNB - 1) / kNB;
+  const int k = nblk - 1 - step;
+  const int k0 = k * kNB, kb = min(kNB, p - k0);
+  const T* Dblk = B.D + S.Doff[s] + (int64_t)k * kNB * kNB;
+  for (int idx = threadIdx.x; idx < kNB * kNB; idx += kThreads) {
+    const int i = idx & 63, j = idx >> 6;
+    Li[i][j] = (double)Dblk[i + j * kNB];
+  }
+  __syncthreads();
+  T* Sf = B.Scur + S.Woff[s];
+  const int64_t q0 = Lpart.prefix[fi], q1 = Lpart.prefix[fi + 1];
+  for (int idx = threadIdx.x; idx < kb * kb; idx += kThreads) {
+    const int i = idx % kb, j = idx / kb;
+    if (i < j) continue;
+    double a = 0.0;
+    for (int l = i; l < kb; ++l) a += Li[l][i] * Li[l][j];
+    double sp = 0.0;
+    for (int64_t q = q0; q < q1; ++q) sp += (double)B.part[q * (kNB * kNB) + i + j * kNB];
+    const T v = (T)(a - sp);
+    Sf[(k0 + i) + (int64_t)(k0 + j) * n] = v;
+    Sf[(k0 + j) + (int64_t)(k0 + i) * n] = v;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_sel_extract(DevSym S, LaunchList L, SelBufs<T> B,
+                                                          const double* __restrict__ scale, double* __restrict__ var) {
+  const int s = L.fronts[blockIdx.x];
+  const int n = fn(S, s), p = fp(S, s);
+  const T* Sf = B.Scur + S.Woff[s];
+  for (int j = threadIdx.x; j < p; j += blockDim.x) {
+    const int32_t o = S.perm[S.sfirst[s] + j];
+    const double sc = scale[o];
+    var[o] = sc * sc * (double)Sf[j + (int64_t)j * n];
+  }
+}
+
+template <typename T>
+__global__ void k_sel_pattern(int64_t cnt, const int64_t* __restrict__ map_e, const int64_t* __restrict__ map_off,
+                              const int32_t* __restrict__ qrow, const int32_t* __restrict__ qcol,
+                              const double* __restrict__ scale, const T* __restrict__ Sc,
+                              double* __restrict__ sigq) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cnt;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    int64_t e = map_e[i];
+    if (e < 0) e = -e - 1;
+    sigq[e] = scale[qrow[e]] * scale[qcol[e]] * (double)Sc[map_off[i]];
+  }
+}
+
+inline unsigned grid_for(int64_t n, int64_t cap = 65536) {
+  int64_t g = (n + kThreads - 1) / kThreads;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (unsigned)g;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ launch wrappers
+void launch_assemble_qpost(hipStream_t st, int64_t nnzq, const double* qval, const int64_t* cptr,
+                           const int32_t* cpair, const int32_t* arow, const double* aval,
+                           const double* qeps, double* qpost) {
+  hipLaunchKernelGGL(k_assemble_qpost, dim3(grid_for(nnzq)), dim3(kThreads), 0, st, nnzq, qval, cptr,
+                     cpair, arow, aval, qeps, qpost);
+}
+void launch_obs_residual(hipStream_t st, int64_t m, const int64_t* arp, const int32_t* aci,
+                         const double* aval, const double* qeps, const double* y, const double* b,
+                         const double* mu, double* rvec) {
+  if (m <= 0) return;
+  hipLaunchKernelGGL(k_obs_residual, dim3(grid_for(m)), dim3(kThreads), 0, st, m, arp, aci, aval, qeps,
+                     y, b, mu, rvec);
+}
+void launch_at_times(hipStream_t st, int64_t n, const int64_t* atp, const int32_t* ati,
+                     const int32_t* arow, const double* aval, const double* rvec, double* h) {
+  hipLaunchKernelGGL(k_at_times, dim3(grid_for(n)), dim3(kThreads), 0, st, n, atp, ati, arow, aval, rvec, h);
+}
+void launch_equilibrate(hipStream_t st, int64_t n, int64_t nnzq, const int64_t* qdiag,
+                        const int32_t* qrow, const int32_t* qcol, const double* qpost, int32_t* sexp,
+                        double* scale, double* qhat) {
+  hipLaunchKernelGGL(k_equil_rows, dim3(grid_for(n)), dim3(kThreads), 0, st, n, qdiag, qpost, sexp, scale);
+  hipLaunchKernelGGL(k_equil_vals, dim3(grid_for(nnzq)), dim3(kThreads), 0, st, nnzq, qdiag, qrow, qcol,
+                     qpost, qhat);
+}
+void launch_fill_i32(hipStream_t st, int32_t* p, int64_t n, int32_t v) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_fill<int32_t>, dim3(grid_for(n)), dim3(kThreads), 0, st, p, n, v);
+}
+void launch_fill_f64(hipStream_t st, double* p, int64_t n, double v) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_fill<double>, dim3(grid_for(n)), dim3(kThreads), 0, st, p, n, v);
+}
+
+template <typename T> void launch_zero(hipStream_t st, T* p, int64_t n) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_fill<T>, dim3(grid_for(n, 1 << 20)), dim3(kThreads), 0, st, p, n, T(0));
+}
+template <typename T> void launch_scatter(hipStream_t st, int64_t cnt, const int64_t* map_e,
+                                          const int64_t* map_off, const double* qhat, T* W) {
+  if (cnt <= 0) return;
+  hipLaunchKernelGGL(k_scatter<T>, dim3(grid_for(cnt)), dim3(kThreads), 0, st, cnt, map_e, map_off, qhat, W);
+}
+template <typename T> void launch_extend_add(hipStream_t st, const DevSym& S, const LaunchList& L, int slot,
+                                             const T* Wchild, T* Wcur) {
+  if (L.total <= 0) return;
+  hipLaunchKernelGGL(k_extend_add<T>, dim3((unsigned)L.total), dim3(kThreads), 0, st, S, L, slot, Wchild, Wcur);
+}
+template <typename T> void launch_potrf(hipStream_t st, const DevSym& S, const LaunchList& L, int step,
+                                        NumBufs<T> B) {
+  if (L.count <= 0) return;
+  hipLaunchKernelGGL(k_potrf<T>, dim3((unsigned)L.count), dim3(kThreads), 0, st, S, L, step, B);
+}
+template <typename T> void launch_trsm(hipStream_t st, const DevSym& S, const LaunchList& L, int step,
+                                       NumBufs<T> B) {
+  if (L.total <= 0) return;
+  hipLaunchKernelGGL(k_trsm<T>, dim3((unsigned)L.total), dim3(kThreads), 0, st, S, L, step, B);
+}
+template <typename T> void launch_update(hipStream_t st, const DevSym& S, const LaunchList& L, int step,
+                                         int syrk, NumBufs<T> B) {
+  if (L.total <= 0) return;
+  hipLaunchKernelGGL(k_update<T>, dim3((unsigned)L.total), dim3(kThreads), 0, st, S, L, step, syrk, B);
+}
+template <typename T> void launch_copy_L(hipStream_t st, const DevSym& S, const LaunchList& L, NumBufs<T> B) {
+  if (L.total <= 0) return;
+  hipLaunchKernelGGL(k_copy_L<T>, dim3((unsigned)L.total), dim3(kThreads), 0, st, S, L, B);
+}
+void launch_logdet(hipStream_t st, int64_t nblocks, const int64_t* bptr, const int32_t* bpiv,
+                   const int32_t* perm, const double* piv, const int32_t* sexp, double* out) {
+  hipLaunchKernelGGL(k_logdet, dim3((unsigned)nblocks), dim3(kThreads), 0, st, bptr, bpiv, perm, piv, sexp, out);
+}
+
+template <typename T> void launch_fvec_init(hipStream_t st, const DevSym& S, const LaunchList& L, SolveBufs V) {
+  if (L.count <= 0) return;
+  hipLaunchKernelGGL(k_fvec_init<T>, dim3((unsigned)L.count), dim3(kThreads), 0, st, S, L, V);
+}
+template <typename T> void launch_fvec_extend(hipStream_t st, const DevSym& S, const LaunchList& L, int slot,
+                                              SolveBufs V) {
+  if (L.count <= 0) return;
+  hipLaunchKernelGGL(k_fvec_extend<T>, dim3((unsigned)L.count), dim3(kThreads), 0, st, S, L, slot, V);
+}
+template <typename T> void launch_fwd_diag(hipStream_t st, const DevSym& S, const LaunchList& L, int step,
+                                           const T* D, SolveBufs V) {
+  if (L.count <= 0) return;
+  hipLaunchKernelGGL(k_fwd_diag<T>, dim3((unsigned)L.count), dim3(kThreads), 0, st, S, L, step, D, V);
+}
+template <typename T> void launch_fwd_update(hipStream_t st, const DevSym& S, const LaunchList& L, int step,
+                                             const T* Lp, SolveBufs V) {
+  if (L.total <= 0) return;
+  hipLaunchKernelGGL(k_fwd_update<T>, dim3((unsigned)L.total), dim3(kThreads), 0, st, S, L, step, Lp, V);
+}
+template <typename T> void launch_bwd_init(hipStream_t st, const DevSym& S, const LaunchList& L, const T* Lp,
+                                           SolveBufs V) {
+  if (L.total <= 0) return;
+  hipLaunchKernelGGL(k_bwd_init<T>, dim3((unsigned)L.total), dim3(kThreads), 0, st, S, L, Lp, V);
+}
+template <typename T> void launch_bwd_diag(hipStream_t st, const DevSym& S, const LaunchList& L, int step,
+                                           const T* D, SolveBufs V) {
+  if (L.count <= 0) return;
+  hipLaunchKernelGGL(k_bwd_diag<T>, dim3((unsigned)L.count), dim3(kThreads), 0, st, S, L, step, D, V);
+}
+template <typename T> void launch_bwd_update(hipStream_t st, const DevSym& S, const LaunchList& L, int step,
+                                             const T* Lp, SolveBufs V) {
+  if (L.total <= 0) return;
+  hipLaunchKernelGGL(k_bwd_update<T>, dim3((unsigned)L.total), dim3(kThreads), 0, st, S, L, step, Lp, V);
+}
+void launch_permute_in(hipStream_t st, int64_t n, int nrhs, const int32_t* perm, const double* scale,
+                       const double* src, int64_t lds, double* xp) {
+  hipLaunchKernelGGL(k_permute_in, dim3(grid_for(n * nrhs)), dim3(kThreads), 0, st, n, nrhs, perm, scale, src,
+                     lds, xp);
+}
+void launch_permute_in_f32(hipStream_t st, int64_t n, int nrhs, const float* z, double* xp) {
+  hipLaunchKernelGGL(k_permute_in_f32, dim3(grid_for(n * nrhs)), dim3(kThreads), 0, st, n * nrhs, z, xp);
+}
+void launch_permute_out(hipStream_t st, int64_t n, int nrhs, const int32_t* perm, const double* scale,
+                        const double* xp, const double* add, int64_t ldadd, double* out, int64_t ldo,
+                        int accumulate) {
+  hipLaunchKernelGGL(k_permute_out, dim3(grid_for(n * nrhs)), dim3(kThreads), 0, st, n, nrhs, perm, scale, xp,
+                     add, ldadd, out, ldo, accumulate);
+}
+void launch_resid(hipStream_t st, int64_t n, const int64_t* rp, const int32_t* ci, const double* val,
+                  const double* h, const double* x, double* r) {
+  hipLaunchKernelGGL(k_resid, dim3(grid_for(n)), dim3(kThreads), 0, st, n, rp, ci, val, h, x, r);
+}
+void launch_add(hipStream_t st, int64_t n, const double* a, const double* b, double* out) {
+  hipLaunchKernelGGL(k_add, dim3(grid_for(n)), dim3(kThreads), 0, st, n, a, b, out);
+}
+void launch_norm2(hipStream_t st, int64_t n, const double* v, double* partial, double* out) {
+  hipLaunchKernelGGL(k_dot_partial, dim3(kRedBlocks), dim3(kThreads), 0, st, n, v, (const double*)nullptr, partial);
+  hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(kThreads), 0, st, partial, 1, out);
+}
+void launch_dot(hipStream_t st, int64_t n, const double* a, const double* b, double* partial, double* out) {
+  hipLaunchKernelGGL(k_dot_partial, dim3(kRedBlocks), dim3(kThreads), 0, st, n, a, b, partial);
+  hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(kThreads), 0, st, partial, 0, out);
+}
+
+template <typename T> void launch_sel_gather(hipStream_t st, const DevSym& S, const LaunchList& L,
+                                             const int32_t* sparent, SelBufs<T> B) {
+  if (L.total <= 0) return;
+  hipLaunchKernelGGL(k_sel_gather<T>, dim3((unsigned)L.total), dim3(kThreads), 0, st, S, L, sparent, B);
+}
+template <typename T> void launch_sel_diag_finish(hipStream_t st, const DevSym& S, const LaunchList& L,
+                                                  const LaunchList& Lpart, int step, SelBufs<T> B) {
+  if (L.count <= 0) return;
+  hipLaunchKernelGGL(k_sel_diag_finish<T>, dim3((unsigned)L.count), dim3(kThreads), 0, st, S, L, Lpart, step, B);
+}
+template <typename T> void launch_sel_Y(hipStream_t st, const DevSym& S, const LaunchList& L, int step,
+                                        SelBufs<T> B) {
+  if (L.total <= 0) return;
+  hipLaunchKernelGGL(k_sel_Y<T>, dim3((unsigned)L.total), dim3(kThreads), 0, st, S, L, step, B);
+}
+template <typename T> void launch_sel_gemm(hipStream_t st, const DevSym& S, const LaunchList& L, int step,
+                                           SelBufs<T> B) {
+  if (L.total <= 0) return;
+  hipLaunchKernelGGL(k_sel_gemm<T>, dim3((unsigned)L.total), dim3(kThreads), 0, st, S, L, step, B);
+}
+template <typename T> void launch_sel_diag_partial(hipStream_t st, const DevSym& S, const LaunchList& L, int step,
+                                                   SelBufs<T> B) {
+  if (L.total <= 0) return;
+  hipLaunchKernelGGL(k_sel_diag_partial<T>, dim3((unsigned)L.total), dim3(kThreads), 0, st, S, L, step, B);
+}
+template <typename T> void launch_sel_extract(hipStream_t st, const DevSym& S, const LaunchList& L, SelBufs<T> B,
+                                              const double* scale, double* var) {
+  if (L.count <= 0) return;
+  hipLaunchKernelGGL(k_sel_extract<T>, dim3((unsigned)L.count), dim3(kThreads), 0, st, S, L, B, scale, var);
+}
+template <typename T> void launch_sel_pattern(hipStream_t st, int64_t cnt, const int64_t* map_e,
+                                              const int64_t* map_off, const int32_t* qrow, const int32_t* qcol,
+                                              const double* scale, const T* Scur, double* sigq) {
+  if (cnt <= 0) return;
+  hipLaunchKernelGGL(k_sel_pattern<T>, dim3(grid_for(cnt)), dim3(kThreads), 0, st, cnt, map_e, map_off, qrow, qcol,
+                     scale, Scur, sigq);
+}
+
+
+#define GMRF_INST(T)                                                                                  \
+  template void launch_zero<T>(hipStream_t, T*, int64_t);                                            \
+  template void launch_scatter<T>(hipStream_t, int64_t, const int64_t*, const int64_t*, const double*, T*); \
+  template void launch_extend_add<T>(hipStream_t, const DevSym&, const LaunchList&, int, const T*, T*); \
+  template void launch_potrf<T>(hipStream_t, const DevSym&, const LaunchList&, int, NumBufs<T>);     \
+  template void launch_trsm<T>(hipStream_t, const DevSym&, const LaunchList&, int, NumBufs<T>);      \
+  template void launch_update<T>(hipStream_t, const DevSym&, const LaunchList&, int, int, NumBufs<T>); \
+  template void launch_copy_L<T>(hipStream_t, const DevSym&, const LaunchList&, NumBufs<T>);         \
+  template void launch_fvec_init<T>(hipStream_t, const DevSym&, const LaunchList&, SolveBufs);       \
+  template void launch_fvec_extend<T>(hipStream_t, const DevSym&, const LaunchList&, int, SolveBufs); \
+  template void launch_fwd_diag<T>(hipStream_t, const DevSym&, const LaunchList&, int, const T*, SolveBufs); \
+  template void launch_fwd_update<T>(hipStream_t, const DevSym&, const LaunchList&, int, const T*, SolveBufs); \
+  template void launch_bwd_init<T>(hipStream_t, const DevSym&, const LaunchList&, const T*, SolveBufs); \
+  template void launch_bwd_diag<T>(hipStream_t, const DevSym&, const LaunchList&, int, const T*, SolveBufs); \
+  template void launch_bwd_update<T>(hipStream_t, const DevSym&, const LaunchList&, int, const T*, SolveBufs); \
+  template void launch_sel_gather<T>(hipStream_t, const DevSym&, const LaunchList&, const int32_t*, SelBufs<T>); \
+  template void launch_sel_Y<T>(hipStream_t, const DevSym&, const LaunchList&, int, SelBufs<T>);     \
+  template void launch_sel_gemm<T>(hipStream_t, const DevSym&, const LaunchList&, int, SelBufs<T>);  \
+  template void launch_sel_diag_partial<T>(hipStream_t, const DevSym&, const LaunchList&, int, SelBufs<T>); \
+  template void launch_sel_diag_finish<T>(hipStream_t, const DevSym&, const LaunchList&, const LaunchList&, int, SelBufs<T>); \
+  template void launch_sel_extract<T>(hipStream_t, const DevSym&, const LaunchList&, SelBufs<T>, const double*, double*); \
+  template void launch_sel_pattern<T>(hipStream_t, int64_t, const int64_t*, const int64_t*, const int32_t*, const int32_t*, const double*, const T*, double*);
+GMRF_INST(double)
+GMRF_INST(float)
+#undef GMRF_INST
+
+}  // namespace gmrf
