@@ -175,6 +175,24 @@ gmrf_status gmrf_pivot_order(gmrf_t h, int32_t* perm_out);
    entries: factor, solve, selinv). */
 gmrf_status gmrf_phase_ms(gmrf_t h, double* out3);
 
+/* Per-kernel-class profile: device time between events recorded around every launch
+   of the class while profiling is on, with the algorithmic flops and bytes of those
+   launches as counted from the supernodal structure (lower triangles only). */
+typedef struct {
+  char name[32];
+  int64_t launches;
+  double ms;
+  double flops;
+  double bytes;
+} gmrf_kernel_stat_t;
+
+/* Reset the per-class counters and switch per-launch events on (enable != 0) or off. */
+gmrf_status gmrf_profile(gmrf_t h, int enable);
+
+/* Copy up to `capacity` class records (host) and the number of classes to *count;
+   synchronises the stream. */
+gmrf_status gmrf_kernel_stats(gmrf_t h, gmrf_kernel_stat_t* out, int capacity, int* count);
+
 /* Message of the last failing call on this context (never NULL). */
 const char* gmrf_last_error(gmrf_t h);
 

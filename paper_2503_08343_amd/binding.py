@@ -28,7 +28,7 @@ GMRF_FP32_REFINE = 1
 EXPORTS = ["gmrf_create", "gmrf_destroy", "gmrf_assemble", "gmrf_update_values", "gmrf_analyze",
            "gmrf_factor", "gmrf_logdet", "gmrf_solve", "gmrf_sample", "gmrf_selinv", "gmrf_dot",
            "gmrf_stats", "gmrf_pivot_order", "gmrf_phase_ms", "gmrf_last_error",
-           "gmrf_symbolic_host"]
+           "gmrf_symbolic_host", "gmrf_profile", "gmrf_kernel_stats"]
 
 
 class gmrf_options(ctypes.Structure):
@@ -48,6 +48,11 @@ class gmrf_stats_t(ctypes.Structure):
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class gmrf_kernel_stat_t(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_int64), ("ms", ctypes.c_double),
+                ("flops", ctypes.c_double), ("bytes", ctypes.c_double)]
 
 
 class GmrfError(RuntimeError):
@@ -95,6 +100,8 @@ def load():
         "gmrf_phase_ms": ([P, P], i32),
         "gmrf_last_error": ([P], ctypes.c_char_p),
         "gmrf_symbolic_host": ([i64, P, P, P, ctypes.c_int, P, P, P, P], i32),
+        "gmrf_profile": ([P, ctypes.c_int], i32),
+        "gmrf_kernel_stats": ([P, P, ctypes.c_int, P], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -277,6 +284,17 @@ class Context:
         p = np.empty(self.n, dtype=np.int32)
         self._check(self.lib.gmrf_pivot_order(self.h, _np_ptr(p)))
         return p
+
+    def profile(self, enable=True):
+        self._check(self.lib.gmrf_profile(self.h, 1 if enable else 0))
+
+    def kernel_stats(self):
+        cnt = ctypes.c_int(0)
+        self._check(self.lib.gmrf_kernel_stats(self.h, None, 0, ctypes.byref(cnt)))
+        arr = (gmrf_kernel_stat_t * cnt.value)()
+        self._check(self.lib.gmrf_kernel_stats(self.h, arr, cnt.value, ctypes.byref(cnt)))
+        return {a.name.decode(): dict(launches=a.launches, ms=a.ms, flops=a.flops, bytes=a.bytes)
+                for a in arr}
 
     def phase_ms(self):
         out = np.zeros(3)

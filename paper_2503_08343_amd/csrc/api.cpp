@@ -50,7 +50,20 @@ struct HostList {  // a launch list before upload
   int64_t f_off = 0, p_off = 0;
   int32_t count = 0;
   int64_t total = 0;
+  double flops = 0.0;   // algorithmic flops of the launch
+  double elems = 0.0;   // algorithmic element traffic of the launch (x sizeof(T) = bytes)
 };
+
+// kernel classes of the per-launch profiler
+enum KClass : int {
+  KC_ASSEMBLE = 0, KC_EQUIL, KC_ZERO, KC_SCATTER, KC_EXTEND, KC_POTRF, KC_TRSM, KC_UPDATE,
+  KC_SYRK, KC_COPYL, KC_LOGDET, KC_FWD, KC_BWD, KC_RESID, KC_PERMUTE, KC_SEL_GATHER, KC_SEL_Y,
+  KC_SEL_GEMM, KC_SEL_DIAG, KC_SEL_OUT, KC_COUNT
+};
+const char* const kClassNames[KC_COUNT] = {
+  "assemble", "equilibrate", "front_zero", "front_scatter", "extend_add", "potrf_diag", "trsm_panel",
+  "update_panel", "syrk_update", "copy_L", "logdet", "solve_fwd", "solve_bwd", "residual",
+  "permute", "sel_gather", "sel_Y", "sel_gemm", "sel_diag", "sel_extract"};
 
 struct Level {
   std::vector<int32_t> fronts;     // sorted by column count p descending
@@ -67,6 +80,7 @@ struct Level {
   std::vector<HostList> bdiag, bupd;        // backward solve per step (from the right)
   HostList sgather;
   std::vector<HostList> sY, sgemm, spart, sfin;  // selinv per step (from the right)
+  double wsize_elems_scatter = 0.0;
 };
 
 }  // namespace
@@ -111,6 +125,17 @@ struct gmrf_ctx {
   hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
   double phase_ms[3] = {0, 0, 0};
   bool ev_factor = false, ev_solve = false, ev_sel = false;
+  // per-launch profiler (events around every launch of a class while enabled)
+  bool prof = false;
+  std::vector<hipEvent_t> evpool;
+  size_t evused = 0;
+  struct Mark { int cls; size_t e0, e1; double flops, bytes; };
+  std::vector<Mark> marks;
+  double cls_ms[KC_COUNT] = {0};
+  double cls_flops[KC_COUNT] = {0};
+  double cls_bytes[KC_COUNT] = {0};
+  int64_t cls_n[KC_COUNT] = {0};
+  int tsize = 8;   // bytes per working-precision element of the current numeric phase
 };
 
 namespace {
@@ -127,6 +152,44 @@ gmrf_status fail(gmrf_t h, gmrf_status code, const std::string& msg) {
       return fail(h, _e == hipErrorOutOfMemory ? GMRF_ERR_OOM : GMRF_ERR_HIP,             \
                   std::string(#expr) + ": " + hipGetErrorString(_e));                     \
   } while (0)
+
+
+hipEvent_t prof_event(gmrf_t h) {
+  if (h->evused == h->evpool.size()) {
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    h->evpool.push_back(e);
+  }
+  return h->evpool[h->evused++];
+}
+
+// run `launch` with events around it when profiling is on
+template <typename F>
+void prof_launch(gmrf_t h, int cls, double flops, double elems, F launch) {
+  if (!h->prof) { launch(); return; }
+  const size_t i0 = h->evused;
+  hipEvent_t a = prof_event(h);
+  if (a) (void)hipEventRecord(a, h->stream);
+  launch();
+  const size_t i1 = h->evused;
+  hipEvent_t b = prof_event(h);
+  if (b) (void)hipEventRecord(b, h->stream);
+  if (a && b) h->marks.push_back({cls, i0, i1, flops, elems * (double)h->tsize});
+}
+
+void prof_fold(gmrf_t h) {
+  if (h->marks.empty()) return;
+  (void)hipStreamSynchronize(h->stream);
+  for (const auto& m : h->marks) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, h->evpool[m.e0], h->evpool[m.e1]) == hipSuccess) h->cls_ms[m.cls] += ms;
+    h->cls_flops[m.cls] += m.flops;
+    h->cls_bytes[m.cls] += m.bytes;
+    h->cls_n[m.cls] += 1;
+  }
+  h->marks.clear();
+  h->evused = 0;
+}
 
 template <typename T>
 hipError_t upload(DevArr<T>& d, const std::vector<T>& h, hipStream_t st) {
@@ -174,11 +237,17 @@ int64_t find_entry(const std::vector<int64_t>& rp, const std::vector<int32_t>& c
 }
 
 // ------------------------------------------------------------------ plan construction
+struct Cost { double flops, elems; };
+
 struct ListBuilder {
   std::vector<int32_t> fronts;
   std::vector<int64_t> prefix;
   template <typename F>
   HostList add(const std::vector<int32_t>& cand, F tiles) {
+    return add(cand, tiles, [](int32_t) { return Cost{0.0, 0.0}; });
+  }
+  template <typename F, typename C>
+  HostList add(const std::vector<int32_t>& cand, F tiles, C cost) {
     HostList L;
     L.f_off = (int64_t)fronts.size();
     L.p_off = (int64_t)prefix.size();
@@ -190,6 +259,9 @@ struct ListBuilder {
       prefix.push_back(tot);
       tot += t;
       L.count++;
+      const Cost c = cost(s);
+      L.flops += c.flops;
+      L.elems += c.elems;
     }
     prefix.push_back(tot);
     L.total = tot;
@@ -287,26 +359,36 @@ gmrf_status build_plan(gmrf_t h) {
     }
     auto nF = [&](int32_t s) { return (int64_t)Y.nf(s); };
     auto pF = [&](int32_t s) { return (int64_t)Y.p(s); };
-    lv.all = B.add(lv.fronts, [](int32_t) { return (int64_t)1; });
+    lv.all = B.add(lv.fronts, [](int32_t) { return (int64_t)1; },
+                   [&](int32_t s) { return Cost{0.0, (double)pF(s) + (double)nF(s)}; });
     for (int c = 0; c < maxch; ++c) {
+      auto child = [&](int32_t s) { return Y.child_idx[Y.child_ptr[s] + c]; };
+      auto has = [&](int32_t s) { return Y.child_ptr[s + 1] - Y.child_ptr[s] > c; };
       lv.ext.push_back(B.add(lv.fronts, [&](int32_t s) -> int64_t {
-        if (Y.child_ptr[s + 1] - Y.child_ptr[s] <= c) return 0;
-        const int32_t ch = Y.child_idx[Y.child_ptr[s] + c];
-        return nF(ch) - pF(ch);
+        return has(s) ? nF(child(s)) - pF(child(s)) : 0;
+      }, [&](int32_t s) {
+        const double u = (double)(nF(child(s)) - pF(child(s)));
+        return Cost{0.5 * u * (u + 1), 1.5 * u * (u + 1)};
       }));
-      lv.fvec_ext.push_back(B.add(lv.fronts, [&](int32_t s) -> int64_t {
-        return Y.child_ptr[s + 1] - Y.child_ptr[s] > c ? 1 : 0;
-      }));
+      lv.fvec_ext.push_back(B.add(lv.fronts, [&](int32_t s) -> int64_t { return has(s) ? 1 : 0; }));
     }
     for (int k = 0; k < lv.nsteps; ++k) {
       const int64_t k0 = (int64_t)k * nb;
       auto active = [&](int32_t s) { return pF(s) > k0; };
       auto kb = [&](int32_t s) { return std::min<int64_t>(nb, pF(s) - k0); };
-      lv.potrf.push_back(B.add(lv.fronts, [&](int32_t s) -> int64_t { return active(s) ? 1 : 0; }));
+      auto below = [&](int32_t s) { return (double)(nF(s) - k0 - kb(s)); };
+      lv.potrf.push_back(B.add(lv.fronts, [&](int32_t s) -> int64_t { return active(s) ? 1 : 0; },
+                               [&](int32_t s) {
+                                 const double b3 = (double)kb(s);
+                                 return Cost{2.0 * b3 * b3 * b3 / 3.0, 3.0 * b3 * b3};
+                               }));
       lv.trsm.push_back(B.add(lv.fronts, [&](int32_t s) -> int64_t {
         if (!active(s)) return 0;
         const int64_t rows = nF(s) - k0 - kb(s);
         return (rows + kTile - 1) / kTile;
+      }, [&](int32_t s) {
+        const double r = below(s), b = (double)kb(s);
+        return Cost{r * b * b, 2.0 * r * b + b * b};
       }));
       lv.upd.push_back(B.add(lv.fronts, [&](int32_t s) -> int64_t {
         if (!active(s)) return 0;
@@ -314,43 +396,75 @@ gmrf_status build_plan(gmrf_t h) {
         int64_t t = 0;
         for (int64_t c0 = clo; c0 < chi; c0 += kTile) t += (nF(s) - c0 + kTile - 1) / kTile;
         return t;
+      }, [&](int32_t s) {
+        const int64_t clo = k0 + kb(s), chi = pF(s);
+        double E = 0.0;
+        for (int64_t c = clo; c < chi; ++c) E += (double)(nF(s) - c);
+        return Cost{2.0 * (double)kb(s) * E, 2.0 * E + (double)(nF(s) - k0) * (double)kb(s)};
       }));
-      lv.fdiag.push_back(B.add(lv.fronts, [&](int32_t s) -> int64_t { return active(s) ? 1 : 0; }));
+      lv.fdiag.push_back(B.add(lv.fronts, [&](int32_t s) -> int64_t { return active(s) ? 1 : 0; },
+                               [&](int32_t s) { const double b = (double)kb(s); return Cost{b * b, 0.5 * b * b}; }));
       lv.fupd.push_back(B.add(lv.fronts, [&](int32_t s) -> int64_t {
         if (!active(s)) return 0;
         return (nF(s) - k0 - kb(s) + kTile - 1) / kTile;
-      }));
+      }, [&](int32_t s) { return Cost{2.0 * below(s) * (double)kb(s), below(s) * (double)kb(s)}; }));
       // steps counted from the right: block index nblk-1-k
       auto rblk = [&](int32_t s) { return (pF(s) + nb - 1) / nb - 1 - k; };
       auto ractive = [&](int32_t s) { return rblk(s) >= 0; };
+      auto rkb = [&](int32_t s) { return std::min<int64_t>(nb, pF(s) - rblk(s) * nb); };
       auto rtail = [&](int32_t s) {  // rows after the block
-        const int64_t kk = rblk(s), kk0 = kk * nb, kkb = std::min<int64_t>(nb, pF(s) - kk0);
-        return nF(s) - kk0 - kkb;
+        const int64_t kk0 = rblk(s) * nb;
+        return nF(s) - kk0 - rkb(s);
       };
-      lv.bdiag.push_back(B.add(lv.fronts, [&](int32_t s) -> int64_t { return ractive(s) ? 1 : 0; }));
-      lv.bupd.push_back(B.add(lv.fronts, [&](int32_t s) -> int64_t { return ractive(s) ? rblk(s) : 0; }));
+      lv.bdiag.push_back(B.add(lv.fronts, [&](int32_t s) -> int64_t { return ractive(s) ? 1 : 0; },
+                               [&](int32_t s) { const double b = (double)rkb(s); return Cost{b * b, 0.5 * b * b}; }));
+      lv.bupd.push_back(B.add(lv.fronts, [&](int32_t s) -> int64_t { return ractive(s) ? rblk(s) : 0; },
+                              [&](int32_t s) {
+                                const double w = (double)rblk(s) * nb, b = (double)rkb(s);
+                                return Cost{2.0 * w * b, w * b};
+                              }));
       lv.sY.push_back(B.add(lv.fronts, [&](int32_t s) -> int64_t {
         return ractive(s) ? (rtail(s) + kTile - 1) / kTile : 0;
+      }, [&](int32_t s) {
+        const double r = (double)rtail(s), b = (double)rkb(s);
+        return Cost{r * b * b, 2.0 * r * b};
       }));
       lv.sgemm.push_back(B.add(lv.fronts, [&](int32_t s) -> int64_t {
         return ractive(s) ? (rtail(s) + kTile - 1) / kTile : 0;
+      }, [&](int32_t s) {
+        const double r = (double)rtail(s), b = (double)rkb(s);
+        return Cost{2.0 * r * r * b, r * r + 3.0 * r * b};
       }));
       lv.spart.push_back(B.add(lv.fronts, [&](int32_t s) -> int64_t {
         return ractive(s) ? std::max<int64_t>(1, (rtail(s) + 511) / 512) : 0;
+      }, [&](int32_t s) {
+        const double r = (double)rtail(s), b = (double)rkb(s);
+        return Cost{r * b * (b + 1.0), 2.0 * r * b};
       }));
       h->part_max = std::max(h->part_max, lv.spart.back().total);
-      lv.sfin.push_back(B.add(lv.fronts, [&](int32_t s) -> int64_t { return ractive(s) ? 1 : 0; }));
+      lv.sfin.push_back(B.add(lv.fronts, [&](int32_t s) -> int64_t { return ractive(s) ? 1 : 0; },
+                              [&](int32_t s) { const double b = (double)rkb(s); return Cost{b * b * b / 3.0, 2.0 * b * b}; }));
     }
     lv.syrk = B.add(lv.fronts, [&](int32_t s) -> int64_t {
       const int64_t u = nF(s) - pF(s);
       const int64_t T = (u + kTile - 1) / kTile;
       return T * (T + 1) / 2;
+    }, [&](int32_t s) {
+      const double u = (double)(nF(s) - pF(s)), p = (double)pF(s);
+      return Cost{p * u * (u + 1.0), u * (u + 1.0) + u * p};
     });
-    lv.copyL = B.add(lv.fronts, [&](int32_t s) -> int64_t { return pF(s); });
-    lv.binit = B.add(lv.fronts, [&](int32_t s) -> int64_t { return (pF(s) + nb - 1) / nb; });
+    lv.copyL = B.add(lv.fronts, [&](int32_t s) -> int64_t { return pF(s); }, [&](int32_t s) {
+      const double p = (double)pF(s), n = (double)nF(s);
+      return Cost{0.0, 2.0 * (p * n - 0.5 * p * (p - 1.0))};
+    });
+    lv.binit = B.add(lv.fronts, [&](int32_t s) -> int64_t { return (pF(s) + nb - 1) / nb; }, [&](int32_t s) {
+      const double u = (double)(nF(s) - pF(s)), p = (double)pF(s);
+      return Cost{2.0 * u * p, u * p};
+    });
     lv.sgather = B.add(lv.fronts, [&](int32_t s) -> int64_t {
       return Y.sparent[s] >= 0 ? nF(s) - pF(s) : 0;
-    });
+    }, [&](int32_t s) { const double u = (double)(nF(s) - pF(s)); return Cost{0.0, 2.0 * u * u}; });
+    lv.wsize_elems_scatter = (double)(lv.map_end - lv.map_begin);
   }
   hipStream_t st = h->stream;
   HIPCHK(h, upload(h->d_lfronts, B.fronts, st));
@@ -409,8 +523,11 @@ gmrf_status run_factor(gmrf_t h) {
   gmrf_status rc = alloc_numeric<T>(h);
   if (rc != GMRF_OK) return rc;
   const DevSym S = dev_sym(h);
-  launch_equilibrate(st, h->n, h->nnzq, h->d_qdiag.p, h->d_qrow.p, h->d_qci.p, h->d_qpost.p, h->d_sexp.p,
-                     h->d_scale.p, h->d_qhat.p);
+  h->tsize = (int)sizeof(T);
+  prof_launch(h, KC_EQUIL, 0.0, 3.0 * h->nnzq, [&] {
+    launch_equilibrate(st, h->n, h->nnzq, h->d_qdiag.p, h->d_qrow.p, h->d_qci.p, h->d_qpost.p, h->d_sexp.p,
+                       h->d_scale.p, h->d_qhat.p);
+  });
   launch_fill_i32(st, h->d_status.p, 1, INT_MAX);
   T* W[2] = {(T*)h->d_W0.p, (T*)h->d_W1.p};
   for (int d = Y.max_depth; d >= 0; --d) {
@@ -422,18 +539,28 @@ gmrf_status run_factor(gmrf_t h) {
     B.Wcur = W[d & 1];
     B.Wchild = W[(d + 1) & 1];
     B.status = h->d_status.p;
-    launch_zero<T>(st, B.Wcur, lv.wsize);
-    launch_scatter<T>(st, lv.map_end - lv.map_begin, h->d_map_e.p + lv.map_begin,
-                      h->d_map_off.p + lv.map_begin, h->d_qhat.p, B.Wcur);
+    prof_launch(h, KC_ZERO, 0.0, (double)lv.wsize, [&] { launch_zero<T>(st, B.Wcur, lv.wsize); });
+    prof_launch(h, KC_SCATTER, 0.0, 2.0 * lv.wsize_elems_scatter, [&] {
+      launch_scatter<T>(st, lv.map_end - lv.map_begin, h->d_map_e.p + lv.map_begin,
+                        h->d_map_off.p + lv.map_begin, h->d_qhat.p, B.Wcur);
+    });
     for (size_t c = 0; c < lv.ext.size(); ++c)
-      launch_extend_add<T>(st, S, dev_list(h, lv.ext[c]), (int)c, B.Wchild, B.Wcur);
+      prof_launch(h, KC_EXTEND, lv.ext[c].flops, lv.ext[c].elems, [&] {
+        launch_extend_add<T>(st, S, dev_list(h, lv.ext[c]), (int)c, B.Wchild, B.Wcur);
+      });
     for (int k = 0; k < lv.nsteps; ++k) {
-      launch_potrf<T>(st, S, dev_list(h, lv.potrf[k]), k, B);
-      launch_trsm<T>(st, S, dev_list(h, lv.trsm[k]), k, B);
-      launch_update<T>(st, S, dev_list(h, lv.upd[k]), k, 0, B);
+      prof_launch(h, KC_POTRF, lv.potrf[k].flops, lv.potrf[k].elems,
+                  [&] { launch_potrf<T>(st, S, dev_list(h, lv.potrf[k]), k, B); });
+      prof_launch(h, KC_TRSM, lv.trsm[k].flops, lv.trsm[k].elems,
+                  [&] { launch_trsm<T>(st, S, dev_list(h, lv.trsm[k]), k, B); });
+      if (lv.upd[k].total > 0)
+        prof_launch(h, KC_UPDATE, lv.upd[k].flops, lv.upd[k].elems,
+                    [&] { launch_update<T>(st, S, dev_list(h, lv.upd[k]), k, 0, B); });
     }
-    launch_update<T>(st, S, dev_list(h, lv.syrk), 0, 1, B);
-    launch_copy_L<T>(st, S, dev_list(h, lv.copyL), B);
+    if (lv.syrk.total > 0)
+      prof_launch(h, KC_SYRK, lv.syrk.flops, lv.syrk.elems,
+                  [&] { launch_update<T>(st, S, dev_list(h, lv.syrk), 0, 1, B); });
+    prof_launch(h, KC_COPYL, 0.0, lv.copyL.elems, [&] { launch_copy_L<T>(st, S, dev_list(h, lv.copyL), B); });
   }
   HIPCHK(h, hipGetLastError());
   return GMRF_OK;
@@ -457,6 +584,7 @@ gmrf_status check_status(gmrf_t h) {
 template <typename T>
 void run_solve(gmrf_t h, int nrhs, bool forward) {
   const Symbolic& Y = h->sym;
+  h->tsize = (int)sizeof(T);
   hipStream_t st = h->stream;
   const DevSym S = dev_sym(h);
   double* V[2] = {h->d_V0.p, h->d_V1.p};
@@ -466,22 +594,31 @@ void run_solve(gmrf_t h, int nrhs, bool forward) {
     for (int d = Y.max_depth; d >= 0; --d) {
       const Level& lv = h->levels[d];
       SolveBufs B{h->d_xp.p, V[d & 1], V[(d + 1) & 1], nrhs};
-      launch_fvec_init<T>(st, S, dev_list(h, lv.all), B);
-      for (size_t c = 0; c < lv.fvec_ext.size(); ++c)
-        launch_fvec_extend<T>(st, S, dev_list(h, lv.fvec_ext[c]), (int)c, B);
+      prof_launch(h, KC_FWD, 0.0, 0.0, [&] {
+        launch_fvec_init<T>(st, S, dev_list(h, lv.all), B);
+        for (size_t c = 0; c < lv.fvec_ext.size(); ++c)
+          launch_fvec_extend<T>(st, S, dev_list(h, lv.fvec_ext[c]), (int)c, B);
+      });
       for (int k = 0; k < lv.nsteps; ++k) {
-        launch_fwd_diag<T>(st, S, dev_list(h, lv.fdiag[k]), k, D, B);
-        launch_fwd_update<T>(st, S, dev_list(h, lv.fupd[k]), k, Lp, B);
+        prof_launch(h, KC_FWD, nrhs * (lv.fdiag[k].flops + lv.fupd[k].flops),
+                    lv.fdiag[k].elems + lv.fupd[k].elems, [&] {
+          launch_fwd_diag<T>(st, S, dev_list(h, lv.fdiag[k]), k, D, B);
+          launch_fwd_update<T>(st, S, dev_list(h, lv.fupd[k]), k, Lp, B);
+        });
       }
     }
   }
   for (int d = 0; d <= Y.max_depth; ++d) {
     const Level& lv = h->levels[d];
     SolveBufs B{h->d_xp.p, V[d & 1], V[(d + 1) & 1], nrhs};
-    launch_bwd_init<T>(st, S, dev_list(h, lv.binit), Lp, B);
+    prof_launch(h, KC_BWD, nrhs * lv.binit.flops, lv.binit.elems,
+                [&] { launch_bwd_init<T>(st, S, dev_list(h, lv.binit), Lp, B); });
     for (int k = 0; k < lv.nsteps; ++k) {
-      launch_bwd_diag<T>(st, S, dev_list(h, lv.bdiag[k]), k, D, B);
-      launch_bwd_update<T>(st, S, dev_list(h, lv.bupd[k]), k, Lp, B);
+      prof_launch(h, KC_BWD, nrhs * (lv.bdiag[k].flops + lv.bupd[k].flops),
+                  lv.bdiag[k].elems + lv.bupd[k].elems, [&] {
+        launch_bwd_diag<T>(st, S, dev_list(h, lv.bdiag[k]), k, D, B);
+        launch_bwd_update<T>(st, S, dev_list(h, lv.bupd[k]), k, Lp, B);
+      });
     }
   }
 }
@@ -504,6 +641,7 @@ gmrf_status run_selinv(gmrf_t h, double* var, double* sigq) {
   const Symbolic& Y = h->sym;
   hipStream_t st = h->stream;
   const DevSym S = dev_sym(h);
+  h->tsize = (int)sizeof(T);
   int64_t ysz = std::max<int64_t>(std::max(Y.Vsize[0], Y.Vsize[1]), 1) * kNB;
   HIPCHK(h, h->d_Y.alloc((size_t)ysz * sizeof(T)));
   HIPCHK(h, h->d_part.alloc((size_t)std::max<int64_t>(h->part_max, 1) * kNB * kNB * sizeof(T)));
@@ -517,18 +655,26 @@ gmrf_status run_selinv(gmrf_t h, double* var, double* sigq) {
     B.Spar = W[(d + 1) & 1];   // parent depth d-1 has the other parity
     B.Y = (T*)h->d_Y.p;
     B.part = (T*)h->d_part.p;
-    launch_sel_gather<T>(st, S, dev_list(h, lv.sgather), h->d_sparent.p, B);
+    prof_launch(h, KC_SEL_GATHER, 0.0, lv.sgather.elems,
+                [&] { launch_sel_gather<T>(st, S, dev_list(h, lv.sgather), h->d_sparent.p, B); });
     for (int k = 0; k < lv.nsteps; ++k) {
-      launch_sel_Y<T>(st, S, dev_list(h, lv.sY[k]), k, B);
-      launch_sel_gemm<T>(st, S, dev_list(h, lv.sgemm[k]), k, B);
-      launch_sel_diag_partial<T>(st, S, dev_list(h, lv.spart[k]), k, B);
-      launch_sel_diag_finish<T>(st, S, dev_list(h, lv.sfin[k]), dev_list(h, lv.spart[k]), k, B);
+      prof_launch(h, KC_SEL_Y, lv.sY[k].flops, lv.sY[k].elems,
+                  [&] { launch_sel_Y<T>(st, S, dev_list(h, lv.sY[k]), k, B); });
+      if (lv.sgemm[k].total > 0)
+        prof_launch(h, KC_SEL_GEMM, lv.sgemm[k].flops, lv.sgemm[k].elems,
+                    [&] { launch_sel_gemm<T>(st, S, dev_list(h, lv.sgemm[k]), k, B); });
+      prof_launch(h, KC_SEL_DIAG, lv.spart[k].flops + lv.sfin[k].flops, lv.spart[k].elems + lv.sfin[k].elems, [&] {
+        launch_sel_diag_partial<T>(st, S, dev_list(h, lv.spart[k]), k, B);
+        launch_sel_diag_finish<T>(st, S, dev_list(h, lv.sfin[k]), dev_list(h, lv.spart[k]), k, B);
+      });
     }
-    launch_sel_extract<T>(st, S, dev_list(h, lv.all), B, h->d_scale.p, var);
-    if (sigq)
-      launch_sel_pattern<T>(st, lv.map_end - lv.map_begin, h->d_map_e.p + lv.map_begin,
-                            h->d_map_off.p + lv.map_begin, h->d_qrow.p, h->d_qci.p, h->d_scale.p, B.Scur,
-                            sigq);
+    prof_launch(h, KC_SEL_OUT, 0.0, 0.0, [&] {
+      launch_sel_extract<T>(st, S, dev_list(h, lv.all), B, h->d_scale.p, var);
+      if (sigq)
+        launch_sel_pattern<T>(st, lv.map_end - lv.map_begin, h->d_map_e.p + lv.map_begin,
+                              h->d_map_off.p + lv.map_begin, h->d_qrow.p, h->d_qci.p, h->d_scale.p, B.Scur,
+                              sigq);
+    });
   }
   HIPCHK(h, hipGetLastError());
   return GMRF_OK;
@@ -582,6 +728,8 @@ gmrf_status gmrf_destroy(gmrf_t h) {
   if (h->stream) (void)hipStreamSynchronize(h->stream);
   else (void)hipDeviceSynchronize();
   for (auto& e : h->ev)
+    if (e) (void)hipEventDestroy(e);
+  for (auto& e : h->evpool)
     if (e) (void)hipEventDestroy(e);
   delete h;
   return GMRF_OK;
@@ -821,8 +969,10 @@ gmrf_status gmrf_solve(gmrf_t h, double* mu_out, int max_refine, double tol, int
   double rel = 0.0;
   const int maxit = std::max(0, max_refine);
   while (true) {
-    launch_resid(st, n, h->d_qrp.p, h->d_qci.p, h->d_qpost.p, h->d_h.p, h->d_w.p, h->d_r.p);
-    launch_norm2(st, n, h->d_r.p, h->d_red.p, h->d_norm.p);
+    prof_launch(h, KC_RESID, 2.0 * h->nnzq, 0.0, [&] {
+      launch_resid(st, n, h->d_qrp.p, h->d_qci.p, h->d_qpost.p, h->d_h.p, h->d_w.p, h->d_r.p);
+      launch_norm2(st, n, h->d_r.p, h->d_red.p, h->d_norm.p);
+    });
     double rn = 0.0;
     HIPCHK(h, hipMemcpyAsync(&rn, h->d_norm.p, sizeof(double), hipMemcpyDeviceToHost, st));
     HIPCHK(h, hipStreamSynchronize(st));
@@ -932,6 +1082,30 @@ gmrf_status gmrf_pivot_order(gmrf_t h, int32_t* perm_out) {
   if (!h || !perm_out) return fail(h, GMRF_ERR_ARG, "null argument");
   if (!(h->state & ST_ANALYZED)) return fail(h, GMRF_ERR_STATE, "gmrf_pivot_order before gmrf_analyze");
   std::memcpy(perm_out, h->sym.perm.data(), sizeof(int32_t) * h->n);
+  return GMRF_OK;
+}
+
+gmrf_status gmrf_profile(gmrf_t h, int enable) {
+  if (!h) return GMRF_ERR_ARG;
+  prof_fold(h);
+  for (int c = 0; c < KC_COUNT; ++c) { h->cls_ms[c] = 0; h->cls_flops[c] = 0; h->cls_bytes[c] = 0; h->cls_n[c] = 0; }
+  h->prof = enable != 0;
+  return GMRF_OK;
+}
+
+gmrf_status gmrf_kernel_stats(gmrf_t h, gmrf_kernel_stat_t* out, int capacity, int* count) {
+  if (!h) return GMRF_ERR_ARG;
+  prof_fold(h);
+  if (count) *count = KC_COUNT;
+  if (!out) return GMRF_OK;
+  for (int c = 0; c < KC_COUNT && c < capacity; ++c) {
+    std::memset(out[c].name, 0, sizeof(out[c].name));
+    std::strncpy(out[c].name, kClassNames[c], sizeof(out[c].name) - 1);
+    out[c].launches = h->cls_n[c];
+    out[c].ms = h->cls_ms[c];
+    out[c].flops = h->cls_flops[c];
+    out[c].bytes = h->cls_bytes[c];
+  }
   return GMRF_OK;
 }
 
