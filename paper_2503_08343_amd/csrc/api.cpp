@@ -73,13 +73,15 @@ struct Level {
   HostList all;                    // every front, one work-group each
   std::vector<HostList> ext;       // extend-add per child slot (tiles = child u)
   std::vector<HostList> fvec_ext;  // vector extend-add per child slot (1 per parent)
-  std::vector<HostList> potrf, trsm, upd;   // per step
+  std::vector<HostList> potrf, trsm, upd, upd_out;   // per 64-block step
   HostList syrk, copyL;
   std::vector<HostList> fdiag, fupd;        // forward solve per step
   HostList binit;
   std::vector<HostList> bdiag, bupd;        // backward solve per step (from the right)
   HostList sgather;
   std::vector<HostList> sY, sgemm, spart, sfin;  // selinv per step (from the right)
+  int nsteps2 = 0;                                // 256-wide outer blocks of the widest front
+  std::vector<HostList> sinv2, sY2, sgemm2, spart2, sfin2;
   double wsize_elems_scatter = 0.0;
 };
 
@@ -109,14 +111,15 @@ struct gmrf_ctx {
   DevArr<int64_t> d_map_e, d_map_off;
   DevArr<int32_t> d_lfronts;
   DevArr<int64_t> d_lprefix;
-  DevArr<int64_t> d_bptr;
+  DevArr<int64_t> d_bptr, d_D2off;
+  int64_t D2size = 0;
   DevArr<int32_t> d_bpiv;
   std::vector<Level> levels;
   int64_t max_front = 0;
   int64_t part_max = 0;   // largest split-K partial launch (work-groups)
 
   int prec = -1;
-  DevArr<char> d_L, d_D, d_W0, d_W1, d_Y, d_part;
+  DevArr<char> d_L, d_D, d_D2, d_W0, d_W1, d_Y, d_part;
   DevArr<double> d_piv, d_V0, d_V1, d_xp, d_w, d_r, d_red, d_norm, d_ld, d_mu_post;
   DevArr<int32_t> d_status;
   int refine_iters = 0;
@@ -295,6 +298,39 @@ DevSym dev_sym(const gmrf_ctx* h) {
   return S;
 }
 
+// update region of the two-level blocked panel / SYRK updates (mirrors the device side)
+void upd_region(int mode, int64_t step, int64_t n, int64_t p, int64_t& clo, int64_t& chi, int64_t& klo,
+                int64_t& khi) {
+  const int64_t sub = kNB2 / kNB;
+  if (mode == 2) { clo = p; chi = n; klo = 0; khi = p; return; }
+  if (mode == 1) {
+    const int64_t k2 = (step / sub) * kNB2;
+    clo = k2 + kNB2; chi = p; klo = k2; khi = k2 + kNB2;
+    return;
+  }
+  const int64_t k0 = step * kNB, kb = std::min<int64_t>(kNB, p - k0);
+  const int64_t oe = std::min<int64_t>((step / sub + 1) * kNB2, p);
+  clo = k0 + kb; chi = oe; klo = k0; khi = k0 + kb;
+}
+
+int64_t upd_tiles(int64_t n, int64_t p, int mode, int64_t step, int64_t ts) {
+  int64_t clo, chi, klo, khi;
+  upd_region(mode, step, n, p, clo, chi, klo, khi);
+  int64_t t = 0;
+  for (int64_t c0 = clo; c0 < chi; c0 += ts) t += (n - c0 + ts - 1) / ts;
+  return t;
+}
+
+Cost upd_cost(int64_t n, int64_t p, int mode, int64_t step) {
+  int64_t clo, chi, klo, khi;
+  upd_region(mode, step, n, p, clo, chi, klo, khi);
+  // lower-trapezoid entries: sum over columns c of (n - c)
+  const double cols = (double)std::max<int64_t>(chi - clo, 0);
+  const double E = cols * (double)(n - clo) - 0.5 * cols * (cols - 1.0);
+  const double K = (double)(khi - klo);
+  return Cost{2.0 * K * E, 2.0 * E + (double)(n - clo) * K};
+}
+
 gmrf_status build_plan(gmrf_t h) {
   const Symbolic& Y = h->sym;
   const int nb = kNB;
@@ -392,16 +428,13 @@ gmrf_status build_plan(gmrf_t h) {
       }));
       lv.upd.push_back(B.add(lv.fronts, [&](int32_t s) -> int64_t {
         if (!active(s)) return 0;
-        const int64_t clo = k0 + kb(s), chi = pF(s);
-        int64_t t = 0;
-        for (int64_t c0 = clo; c0 < chi; c0 += kTile) t += (nF(s) - c0 + kTile - 1) / kTile;
-        return t;
-      }, [&](int32_t s) {
-        const int64_t clo = k0 + kb(s), chi = pF(s);
-        double E = 0.0;
-        for (int64_t c = clo; c < chi; ++c) E += (double)(nF(s) - c);
-        return Cost{2.0 * (double)kb(s) * E, 2.0 * E + (double)(nF(s) - k0) * (double)kb(s)};
-      }));
+        return upd_tiles(nF(s), pF(s), 0, k, kTile);
+      }, [&](int32_t s) { return upd_cost(nF(s), pF(s), 0, k); }));
+      const bool outer_here = (k + 1) % (kNB2 / nb) == 0;
+      lv.upd_out.push_back(B.add(lv.fronts, [&](int32_t s) -> int64_t {
+        if (!outer_here || pF(s) <= (int64_t)(k + 1) * nb) return 0;
+        return upd_tiles(nF(s), pF(s), 1, k, kBigTile);
+      }, [&](int32_t s) { return upd_cost(nF(s), pF(s), 1, k); }));
       lv.fdiag.push_back(B.add(lv.fronts, [&](int32_t s) -> int64_t { return active(s) ? 1 : 0; },
                                [&](int32_t s) { const double b = (double)kb(s); return Cost{b * b, 0.5 * b * b}; }));
       lv.fupd.push_back(B.add(lv.fronts, [&](int32_t s) -> int64_t {
@@ -445,14 +478,43 @@ gmrf_status build_plan(gmrf_t h) {
       lv.sfin.push_back(B.add(lv.fronts, [&](int32_t s) -> int64_t { return ractive(s) ? 1 : 0; },
                               [&](int32_t s) { const double b = (double)rkb(s); return Cost{b * b * b / 3.0, 2.0 * b * b}; }));
     }
+    // two-level selected inversion: outer blocks of 256 columns, counted from the right
+    lv.nsteps2 = 0;
+    for (int32_t s : lv.fronts) lv.nsteps2 = std::max<int>(lv.nsteps2, (int)((pF(s) + kNB2 - 1) / kNB2));
+    for (int t = 0; t < lv.nsteps2; ++t) {
+      auto oK = [&](int32_t s) { return (pF(s) + kNB2 - 1) / kNB2 - 1 - t; };
+      auto oact = [&](int32_t s) { return oK(s) >= 0; };
+      auto okb2 = [&](int32_t s) { return std::min<int64_t>(kNB2, pF(s) - oK(s) * kNB2); };
+      auto otail = [&](int32_t s) { return nF(s) - oK(s) * kNB2 - okb2(s); };
+      auto onsub = [&](int32_t s) { return (okb2(s) + nb - 1) / nb; };
+      auto onct = [&](int32_t s) { return (okb2(s) + kBigTile - 1) / kBigTile; };
+      lv.sinv2.push_back(B.add(lv.fronts, [&](int32_t s) -> int64_t { return oact(s) ? onsub(s) : 0; },
+                               [&](int32_t s) { const double b = (double)okb2(s); return Cost{b * b * b / 3.0, b * b}; }));
+      lv.sY2.push_back(B.add(lv.fronts, [&](int32_t s) -> int64_t {
+        return oact(s) ? ((otail(s) + kBigTile - 1) / kBigTile) * onct(s) : 0;
+      }, [&](int32_t s) {
+        const double r = (double)otail(s), b = (double)okb2(s);
+        return Cost{r * b * b, 2.0 * r * b + b * b};
+      }));
+      lv.sgemm2.push_back(B.add(lv.fronts, [&](int32_t s) -> int64_t {
+        return oact(s) ? ((otail(s) + kBigTile - 1) / kBigTile) * onct(s) : 0;
+      }, [&](int32_t s) {
+        const double r = (double)otail(s), b = (double)okb2(s);
+        return Cost{2.0 * r * r * b, r * r + 3.0 * r * b};
+      }));
+      lv.spart2.push_back(B.add(lv.fronts, [&](int32_t s) -> int64_t {
+        return oact(s) ? std::max<int64_t>(1, (otail(s) + 511) / 512) * onsub(s) * onsub(s) : 0;
+      }, [&](int32_t s) {
+        const double r = (double)otail(s), b = (double)okb2(s);
+        return Cost{2.0 * r * b * b, 2.0 * r * b};
+      }));
+      h->part_max = std::max(h->part_max, lv.spart2.back().total);
+      lv.sfin2.push_back(B.add(lv.fronts, [&](int32_t s) -> int64_t { return oact(s) ? onsub(s) * onsub(s) : 0; },
+                               [&](int32_t s) { const double b = (double)okb2(s); return Cost{b * b * b / 3.0, 2.0 * b * b}; }));
+    }
     lv.syrk = B.add(lv.fronts, [&](int32_t s) -> int64_t {
-      const int64_t u = nF(s) - pF(s);
-      const int64_t T = (u + kTile - 1) / kTile;
-      return T * (T + 1) / 2;
-    }, [&](int32_t s) {
-      const double u = (double)(nF(s) - pF(s)), p = (double)pF(s);
-      return Cost{p * u * (u + 1.0), u * (u + 1.0) + u * p};
-    });
+      return nF(s) > pF(s) ? upd_tiles(nF(s), pF(s), 2, 0, kBigTile) : 0;
+    }, [&](int32_t s) { return upd_cost(nF(s), pF(s), 2, 0); });
     lv.copyL = B.add(lv.fronts, [&](int32_t s) -> int64_t { return pF(s); }, [&](int32_t s) {
       const double p = (double)pF(s), n = (double)nF(s);
       return Cost{0.0, 2.0 * (p * n - 0.5 * p * (p - 1.0))};
@@ -483,6 +545,18 @@ gmrf_status build_plan(gmrf_t h) {
   HIPCHK(h, upload(h->d_Woff, Y.Woff, st));
   HIPCHK(h, upload(h->d_Doff, Y.Doff, st));
   HIPCHK(h, upload(h->d_Voff, Y.Voff, st));
+  // storage of the 256-wide inverse diagonal blocks (selected inversion)
+  {
+    std::vector<int64_t> d2(Y.ns, 0);
+    int64_t off = 0;
+    for (int32_t s = 0; s < Y.ns; ++s) {
+      const int64_t p = Y.p(s), nK = (p + kNB2 - 1) / kNB2, last = p - (nK - 1) * kNB2;
+      d2[s] = off;
+      off += (nK - 1) * (int64_t)kNB2 * kNB2 + last * last;
+    }
+    h->D2size = off;
+    HIPCHK(h, upload(h->d_D2off, d2, st));
+  }
   // per-block pivot lists for the log-determinant
   {
     std::vector<int64_t> bp(h->nblocks + 1, 0);
@@ -556,10 +630,13 @@ gmrf_status run_factor(gmrf_t h) {
       if (lv.upd[k].total > 0)
         prof_launch(h, KC_UPDATE, lv.upd[k].flops, lv.upd[k].elems,
                     [&] { launch_update<T>(st, S, dev_list(h, lv.upd[k]), k, 0, B); });
+      if (lv.upd_out[k].total > 0)
+        prof_launch(h, KC_UPDATE, lv.upd_out[k].flops, lv.upd_out[k].elems,
+                    [&] { launch_update<T>(st, S, dev_list(h, lv.upd_out[k]), k, 1, B); });
     }
     if (lv.syrk.total > 0)
       prof_launch(h, KC_SYRK, lv.syrk.flops, lv.syrk.elems,
-                  [&] { launch_update<T>(st, S, dev_list(h, lv.syrk), 0, 1, B); });
+                  [&] { launch_update<T>(st, S, dev_list(h, lv.syrk), 0, 2, B); });
     prof_launch(h, KC_COPYL, 0.0, lv.copyL.elems, [&] { launch_copy_L<T>(st, S, dev_list(h, lv.copyL), B); });
   }
   HIPCHK(h, hipGetLastError());
@@ -642,10 +719,12 @@ gmrf_status run_selinv(gmrf_t h, double* var, double* sigq) {
   hipStream_t st = h->stream;
   const DevSym S = dev_sym(h);
   h->tsize = (int)sizeof(T);
-  int64_t ysz = std::max<int64_t>(std::max(Y.Vsize[0], Y.Vsize[1]), 1) * kNB;
+  int64_t ysz = std::max<int64_t>(std::max(Y.Vsize[0], Y.Vsize[1]), 1) * kNB2;
   HIPCHK(h, h->d_Y.alloc((size_t)ysz * sizeof(T)));
   HIPCHK(h, h->d_part.alloc((size_t)std::max<int64_t>(h->part_max, 1) * kNB * kNB * sizeof(T)));
   T* W[2] = {(T*)h->d_W0.p, (T*)h->d_W1.p};
+  HIPCHK(h, h->d_D2.alloc((size_t)std::max<int64_t>(h->D2size, 1) * sizeof(T)));
+  T* D2 = (T*)h->d_D2.p;
   for (int d = 0; d <= Y.max_depth; ++d) {
     const Level& lv = h->levels[d];
     SelBufs<T> B;
@@ -657,15 +736,17 @@ gmrf_status run_selinv(gmrf_t h, double* var, double* sigq) {
     B.part = (T*)h->d_part.p;
     prof_launch(h, KC_SEL_GATHER, 0.0, lv.sgather.elems,
                 [&] { launch_sel_gather<T>(st, S, dev_list(h, lv.sgather), h->d_sparent.p, B); });
-    for (int k = 0; k < lv.nsteps; ++k) {
-      prof_launch(h, KC_SEL_Y, lv.sY[k].flops, lv.sY[k].elems,
-                  [&] { launch_sel_Y<T>(st, S, dev_list(h, lv.sY[k]), k, B); });
-      if (lv.sgemm[k].total > 0)
-        prof_launch(h, KC_SEL_GEMM, lv.sgemm[k].flops, lv.sgemm[k].elems,
-                    [&] { launch_sel_gemm<T>(st, S, dev_list(h, lv.sgemm[k]), k, B); });
-      prof_launch(h, KC_SEL_DIAG, lv.spart[k].flops + lv.sfin[k].flops, lv.spart[k].elems + lv.sfin[k].elems, [&] {
-        launch_sel_diag_partial<T>(st, S, dev_list(h, lv.spart[k]), k, B);
-        launch_sel_diag_finish<T>(st, S, dev_list(h, lv.sfin[k]), dev_list(h, lv.spart[k]), k, B);
+    for (int t = 0; t < lv.nsteps2; ++t) {
+      prof_launch(h, KC_SEL_Y, lv.sinv2[t].flops + lv.sY2[t].flops, lv.sinv2[t].elems + lv.sY2[t].elems, [&] {
+        launch_sel_inv256<T>(st, S, dev_list(h, lv.sinv2[t]), t, B, h->d_D2off.p, D2);
+        launch_sel_Y2<T>(st, S, dev_list(h, lv.sY2[t]), t, B, h->d_D2off.p, D2);
+      });
+      if (lv.sgemm2[t].total > 0)
+        prof_launch(h, KC_SEL_GEMM, lv.sgemm2[t].flops, lv.sgemm2[t].elems,
+                    [&] { launch_sel_gemm2<T>(st, S, dev_list(h, lv.sgemm2[t]), t, B); });
+      prof_launch(h, KC_SEL_DIAG, lv.spart2[t].flops + lv.sfin2[t].flops, lv.spart2[t].elems + lv.sfin2[t].elems, [&] {
+        launch_sel_part2<T>(st, S, dev_list(h, lv.spart2[t]), t, B);
+        launch_sel_fin2<T>(st, S, dev_list(h, lv.sfin2[t]), dev_list(h, lv.spart2[t]), t, B, h->d_D2off.p, D2);
       });
     }
     prof_launch(h, KC_SEL_OUT, 0.0, 0.0, [&] {

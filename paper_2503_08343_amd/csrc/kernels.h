@@ -7,6 +7,8 @@ namespace gmrf {
 
 constexpr int kTile = 64;     // dense tile edge (rows/cols) of the front kernels
 constexpr int kNB = 64;       // diagonal block width; equals the analysis option nb
+constexpr int kNB2 = 256;     // outer block width of the two-level blocking
+constexpr int kBigTile = 128; // tile edge of the long-K MFMA kernels
 
 // Read-only symbolic arrays on the device (pivot numbering).
 struct DevSym {
@@ -67,8 +69,10 @@ template <typename T> void launch_potrf(hipStream_t st, const DevSym& S, const L
                                         int step, NumBufs<T> B);
 template <typename T> void launch_trsm(hipStream_t st, const DevSym& S, const LaunchList& L,
                                        int step, NumBufs<T> B);
+// mode 0: inner panel update after 64-block `step`; 1: outer update after the last
+// 64-block of a 256-wide outer block; 2: trailing SYRK of the update matrix
 template <typename T> void launch_update(hipStream_t st, const DevSym& S, const LaunchList& L,
-                                         int step, int syrk, NumBufs<T> B);
+                                         int step, int mode, NumBufs<T> B);
 template <typename T> void launch_copy_L(hipStream_t st, const DevSym& S, const LaunchList& L,
                                          NumBufs<T> B);
 void launch_logdet(hipStream_t st, int64_t nblocks, const int64_t* bptr, const int32_t* bpiv,
@@ -106,7 +110,7 @@ struct SelBufs {
   const T* D;
   T* Scur;         // square Sigma fronts of the current depth
   T* Spar;         // square Sigma fronts of the parent depth
-  T* Y;            // n_s x nb scratch per front (offset Voff * nb)
+  T* Y;            // n_s x 256 scratch per front (offset Voff * 256)
   T* part;         // split-K partials
 };
 template <typename T> void launch_sel_gather(hipStream_t st, const DevSym& S, const LaunchList& L, const int32_t* sparent, SelBufs<T> B);
@@ -114,6 +118,15 @@ template <typename T> void launch_sel_Y(hipStream_t st, const DevSym& S, const L
 template <typename T> void launch_sel_gemm(hipStream_t st, const DevSym& S, const LaunchList& L, int step, SelBufs<T> B);
 template <typename T> void launch_sel_diag_partial(hipStream_t st, const DevSym& S, const LaunchList& L, int step, SelBufs<T> B);
 template <typename T> void launch_sel_diag_finish(hipStream_t st, const DevSym& S, const LaunchList& L, const LaunchList& Lpart, int step, SelBufs<T> B);
+// two-level selected inversion (256-wide outer blocks counted from the right by `step`)
+template <typename T> void launch_sel_inv256(hipStream_t st, const DevSym& S, const LaunchList& L, int step,
+                                             SelBufs<T> B, const int64_t* D2off, T* D2);
+template <typename T> void launch_sel_Y2(hipStream_t st, const DevSym& S, const LaunchList& L, int step,
+                                         SelBufs<T> B, const int64_t* D2off, const T* D2);
+template <typename T> void launch_sel_gemm2(hipStream_t st, const DevSym& S, const LaunchList& L, int step, SelBufs<T> B);
+template <typename T> void launch_sel_part2(hipStream_t st, const DevSym& S, const LaunchList& L, int step, SelBufs<T> B);
+template <typename T> void launch_sel_fin2(hipStream_t st, const DevSym& S, const LaunchList& L, const LaunchList& Lpart,
+                                           int step, SelBufs<T> B, const int64_t* D2off, const T* D2);
 template <typename T> void launch_sel_extract(hipStream_t st, const DevSym& S, const LaunchList& L, SelBufs<T> B,
                                               const double* scale, double* var);
 template <typename T> void launch_sel_pattern(hipStream_t st, int64_t cnt, const int64_t* map_e,

@@ -24,6 +24,7 @@ constexpr int kThreads = 256;
 constexpr int kP = 80;        // LDS row pitch of the MFMA operand tiles (bank spread)
 constexpr int kTK = 16;       // K chunk of the MFMA tile loop
 constexpr int kChunk = 512;   // rows per split-K partial in the Sigma diagonal blocks
+constexpr int kSub = kNB2 / kNB;
 
 template <typename T> struct V4;
 template <> struct V4<double> { typedef double type __attribute__((ext_vector_type(4))); };
@@ -148,6 +149,131 @@ __device__ __forceinline__ void for_acc(typename V4<T>::type (&acc)[2][2], F f) 
 #pragma unroll
       for (int r = 0; r < 4; ++r)
         f(wm + 16 * i + acc_row<T>(lane, r), wn + 16 * j + (lane & 15), acc[i][j][r]);
+}
+
+template <typename T, typename F>
+__device__ __forceinline__ void for_acc128(typename V4<T>::type (&acc)[4][4], F f) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wm = (w & 1) * 64, wn = (w >> 1) * 64;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        f(wm + 16 * i + acc_row<T>(lane, r), wn + 16 * j + (lane & 15), acc[i][j][r]);
+}
+
+
+// C(128x128 tile) = sum_k Aop[m][k] Bop[k][n] with the operand conventions of gemm_tile.
+// Each wave owns a 64x64 sub-tile (4x4 MFMA 16x16 blocks).  The K loop is software
+// pipelined: the next 16-wide K chunk is loaded into registers while the current one,
+// double-buffered in LDS, feeds the MFMAs.
+constexpr int kBT = 128;
+constexpr int kBP = 144;   // LDS pitch: rows of a K slice start 32 banks apart (FP64) / 16 (FP32)
+
+template <typename T, bool A_KC, bool B_KC>
+__device__ __forceinline__ void big_load(const T* __restrict__ A, int64_t lda, const T* __restrict__ B,
+                                         int64_t ldb, int M, int N, int K, int k0, T (&ra)[8], T (&rb)[8]) {
+  const int t = threadIdx.x;
+  if (!A_KC) {
+    const int m = t & 127;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int k = (t >> 7) + 2 * i;
+      ra[i] = (m < M && k0 + k < K) ? A[m + (int64_t)(k0 + k) * lda] : T(0);
+    }
+  } else {
+    const int k = t & 15;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int m = (t >> 4) + 16 * i;
+      ra[i] = (m < M && k0 + k < K) ? A[(k0 + k) + (int64_t)m * lda] : T(0);
+    }
+  }
+  if (!B_KC) {
+    const int nn = t & 127;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int k = (t >> 7) + 2 * i;
+      rb[i] = (nn < N && k0 + k < K) ? B[nn + (int64_t)(k0 + k) * ldb] : T(0);
+    }
+  } else {
+    const int k = t & 15;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int nn = (t >> 4) + 16 * i;
+      rb[i] = (nn < N && k0 + k < K) ? B[(k0 + k) + (int64_t)nn * ldb] : T(0);
+    }
+  }
+}
+
+template <typename T, bool A_KC, bool B_KC>
+__device__ __forceinline__ void big_store(T* sA, T* sB, const T (&ra)[8], const T (&rb)[8]) {
+  const int t = threadIdx.x;
+  if (!A_KC) {
+    const int m = t & 127;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) sA[((t >> 7) + 2 * i) * kBP + m] = ra[i];
+  } else {
+    const int k = t & 15;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) sA[k * kBP + (t >> 4) + 16 * i] = ra[i];
+  }
+  if (!B_KC) {
+    const int nn = t & 127;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) sB[((t >> 7) + 2 * i) * kBP + nn] = rb[i];
+  } else {
+    const int k = t & 15;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) sB[k * kBP + (t >> 4) + 16 * i] = rb[i];
+  }
+}
+
+// sA, sB: 2 buffers each of kTK * kBP elements
+template <typename T, bool A_KC, bool B_KC>
+__device__ __forceinline__ void gemm_tile128(const T* __restrict__ A, int64_t lda,
+                                             const T* __restrict__ B, int64_t ldb, int M, int N, int K,
+                                             typename V4<T>::type (&acc)[4][4], T* sA, T* sB) {
+  const int lane = threadIdx.x & 63;
+  const int w = threadIdx.x >> 6;
+  const int wm = (w & 1) * 64, wn = (w >> 1) * 64;
+  T ra[8], rb[8];
+  if (K <= 0) return;
+  big_load<T, A_KC, B_KC>(A, lda, B, ldb, M, N, K, 0, ra, rb);
+  big_store<T, A_KC, B_KC>(sA, sB, ra, rb);
+  __syncthreads();
+  int buf = 0;
+  for (int k0 = 0; k0 < K; k0 += kTK) {
+    const bool more = k0 + kTK < K;
+    if (more) big_load<T, A_KC, B_KC>(A, lda, B, ldb, M, N, K, k0 + kTK, ra, rb);
+    const T* cA = sA + buf * (kTK * kBP);
+    const T* cB = sB + buf * (kTK * kBP);
+#pragma unroll
+    for (int kk = 0; kk < kTK; kk += 4) {
+      T a[4], b[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a[i] = cA[(kk + (lane >> 4)) * kBP + wm + 16 * i + (lane & 15)];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) b[j] = cB[(kk + (lane >> 4)) * kBP + wn + 16 * j + (lane & 15)];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = mfma(a[i], b[j], acc[i][j]);
+    }
+    if (more) big_store<T, A_KC, B_KC>(sA + (buf ^ 1) * (kTK * kBP), sB + (buf ^ 1) * (kTK * kBP), ra, rb);
+    __syncthreads();
+    buf ^= 1;
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void zero_acc128(typename V4<T>::type (&acc)[4][4]) {
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = typename V4<T>::type{T(0), T(0), T(0), T(0)};
 }
 
 // ------------------------------------------------------------------ assembly kernels
@@ -351,47 +477,72 @@ __global__ __launch_bounds__(kThreads) void k_trsm(DevSym S, LaunchList L, int s
   });
 }
 
-// lower-trapezoid tile update C -= A B^T inside each front.
-// syrk=0: step-th panel update: columns [k0+kb, p), rows >= column, K range [k0, k0+kb)
-// syrk=1: trailing update matrix: columns [p, n), rows >= column, K range [0, p)
-template <typename T>
-__global__ __launch_bounds__(kThreads) void k_update(DevSym S, LaunchList L, int step, int syrk,
+// Lower-trapezoid tile update C -= A B^T inside each front: columns [clo, chi), rows
+// from the column to n, reduction over front columns [klo, khi).  Two-level blocking:
+//   mode 0 (inner, after 64-block `step`): columns up to the end of its 256-wide outer
+//          block, K = the 64-block;
+//   mode 1 (outer, after the last 64-block of an outer block): every panel column right
+//          of the outer block, K = the 256-wide outer block;
+//   mode 2 (SYRK): the update matrix, columns [p, n), K = all p pivot columns.
+__device__ __forceinline__ void upd_region(int mode, int step, int n, int p, int& clo, int& chi,
+                                           int& klo, int& khi) {
+  if (mode == 2) { clo = p; chi = n; klo = 0; khi = p; return; }
+  if (mode == 1) {
+    const int k2 = (step / kSub) * kNB2;
+    clo = k2 + kNB2; chi = p; klo = k2; khi = k2 + kNB2;
+    return;
+  }
+  const int k0 = step * kNB, kb = min(kNB, p - k0);
+  const int oe = min((step / kSub + 1) * kNB2, p);
+  clo = k0 + kb; chi = oe; klo = k0; khi = k0 + kb;
+}
+
+template <typename T, int TS>
+__global__ __launch_bounds__(kThreads) void k_update(DevSym S, LaunchList L, int step, int mode,
                                                      NumBufs<T> B) {
-  __shared__ T sA[kTK * kP];
-  __shared__ T sB[kTK * kP];
   int fi; int64_t loc;
   find_front(L, wg_id(), fi, loc);
   const int s = L.fronts[fi];
   const int n = fn(S, s), p = fp(S, s);
   int clo, chi, klo, khi;
-  if (syrk) { clo = p; chi = n; klo = 0; khi = p; }
-  else {
-    const int k0 = step * kNB, kb = min(kNB, p - k0);
-    clo = k0 + kb; chi = p; klo = k0; khi = k0 + kb;
-  }
-  // decode (column tile, row tile) of the lower trapezoid, column-major over tiles
+  upd_region(mode, step, n, p, clo, chi, klo, khi);
   int ct = 0;
   int64_t r = loc;
   while (true) {
-    const int c0 = clo + kTile * ct;
+    const int c0 = clo + TS * ct;
     if (c0 >= chi) return;   // unreachable for a consistent launch list
-    const int64_t nr = (n - c0 + kTile - 1) / kTile;
+    const int64_t nr = (n - c0 + TS - 1) / TS;
     if (r < nr) break;
     r -= nr;
     ++ct;
   }
-  const int col0 = clo + kTile * ct;
-  const int row0 = col0 + kTile * (int)r;
-  const int M = min(kTile, n - row0), N = min(kTile, chi - col0);
+  const int col0 = clo + TS * ct;
+  const int row0 = col0 + TS * (int)r;
+  const int M = min(TS, n - row0), N = min(TS, chi - col0);
   T* F = B.Wcur + S.Woff[s];
-  typename V4<T>::type acc[2][2];
-  zero_acc<T>(acc);
-  gemm_tile<T, false, false>(F + row0 + (int64_t)klo * n, n, F + col0 + (int64_t)klo * n, n, M, N,
-                             khi - klo, acc, sA, sB);
-  for_acc<T>(acc, [&](int rr, int cc, T v) {
-    const int gi = row0 + rr, gj = col0 + cc;
-    if (rr < M && cc < N && gi >= gj) F[gi + (int64_t)gj * n] -= v;
-  });
+  if constexpr (TS == 64) {
+    __shared__ T sA[kTK * kP];
+    __shared__ T sB[kTK * kP];
+    typename V4<T>::type acc[2][2];
+    zero_acc<T>(acc);
+    gemm_tile<T, false, false>(F + row0 + (int64_t)klo * n, n, F + col0 + (int64_t)klo * n, n, M, N,
+                               khi - klo, acc, sA, sB);
+    for_acc<T>(acc, [&](int rr, int cc, T v) {
+      const int gi = row0 + rr, gj = col0 + cc;
+      if (rr < M && cc < N && gi >= gj) F[gi + (int64_t)gj * n] -= v;
+    });
+  } else {
+    __shared__ T sA[2 * kTK * kBP];
+    __shared__ T sB[2 * kTK * kBP];
+    typename V4<T>::type acc[4][4];
+    zero_acc128<T>(acc);
+    gemm_tile128<T, false, false>(F + row0 + (int64_t)klo * n, n, F + col0 + (int64_t)klo * n, n, M, N,
+                                  khi - klo, acc, sA, sB);
+    for_acc128<T>(acc, [&](int rr, int cc, T v) {
+      const int gi = row0 + rr, gj = col0 + cc;
+      if (rr < M && cc < N && gi >= gj) F[gi + (int64_t)gj * n] -= v;
+    });
+  }
 }
 
 template <typename T>
@@ -831,6 +982,202 @@ __global__ __launch_bounds__(kThreads) void k_sel_diag_finish(DevSym S, LaunchLi
   }
 }
 
+// ---- two-level selected inversion: 256-wide outer blocks K (counted from the right) ----
+// For the outer block K of front s with rows after it R' (n' = n - k2 - kb2 rows):
+//   X = L[R', K] Linv_KK,  Sigma[R', K] = -Sigma[R', R'] X,
+//   Sigma[K, K] = Linv_KK^T Linv_KK - X^T Sigma[R', K]
+// (the supernodal Takahashi relations with K as the supernode and R' its row set).
+struct OuterBlk { int K, k2, kb2, rs, nsub; };
+__device__ __forceinline__ OuterBlk outer_blk(int p, int n, int step) {
+  OuterBlk o;
+  const int nK = (p + kNB2 - 1) / kNB2;
+  o.K = nK - 1 - step;
+  o.k2 = o.K * kNB2;
+  o.kb2 = min(kNB2, p - o.k2);
+  o.rs = o.k2 + o.kb2;
+  o.nsub = (o.kb2 + kNB - 1) / kNB;
+  (void)n;
+  return o;
+}
+
+// Linv_KK from the 64-block inverses: column block j of X = L_KK^-1 satisfies
+// X_jj = Linv_jj and X_ij = -Linv_ii sum_{j<=l<i} L_il X_lj for i > j.  One work-group
+// per (front, column block j); X is stored column-major with ld kb2 at D2 + D2off[s] +
+// K * 256^2 (zeros above the diagonal).
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_sel_inv256(DevSym S, LaunchList L, int step, SelBufs<T> B,
+                                                         const int64_t* __restrict__ D2off, T* __restrict__ D2) {
+  __shared__ T sA[kTK * kP];
+  __shared__ T sB[kTK * kP];
+  int fi; int64_t loc;
+  find_front(L, wg_id(), fi, loc);
+  const int s = L.fronts[fi];
+  const int n = fn(S, s), p = fp(S, s);
+  const OuterBlk o = outer_blk(p, n, step);
+  const int j = (int)loc;
+  const int kb2 = o.kb2;
+  const int sbj = min(kNB, kb2 - kNB * j);
+  T* X = D2 + D2off[s] + (int64_t)o.K * kNB2 * kNB2;
+  const T* Lf = B.L + S.Loff[s];
+  const int blk0 = o.k2 / kNB;
+  // column block j: zero, then the diagonal block
+  for (int idx = threadIdx.x; idx < kb2 * kNB; idx += kThreads) {
+    const int r = idx % kb2, c = idx / kb2;
+    if (c < sbj) {
+      T v = T(0);
+      if (r >= kNB * j && r < kNB * j + sbj)
+        v = B.D[S.Doff[s] + (int64_t)(blk0 + j) * kNB * kNB + (r - kNB * j) + c * kNB];
+      X[r + (int64_t)(kNB * j + c) * kb2] = v;
+    }
+  }
+  __threadfence();
+  __syncthreads();
+  for (int i = j + 1; i < o.nsub; ++i) {
+    const int sbi = min(kNB, kb2 - kNB * i);
+    typename V4<T>::type acc[2][2];
+    zero_acc<T>(acc);
+    // T_ij = sum_{l=j}^{i-1} L_il X_lj  (K = 64 (i - j))
+    gemm_tile<T, false, true>(Lf + (o.k2 + kNB * i) + (int64_t)(o.k2 + kNB * j) * n, n,
+                              X + kNB * j + (int64_t)(kNB * j) * kb2, kb2, sbi, sbj, kNB * (i - j), acc, sA, sB);
+    T* Xij = X + kNB * i + (int64_t)(kNB * j) * kb2;
+    for_acc<T>(acc, [&](int r, int c, T v) {
+      if (r < sbi && c < sbj) Xij[r + (int64_t)c * kb2] = v;
+    });
+    __threadfence();
+    __syncthreads();
+    zero_acc<T>(acc);
+    gemm_tile<T, false, true>(B.D + S.Doff[s] + (int64_t)(blk0 + i) * kNB * kNB, kNB, Xij, kb2, sbi, sbj, sbi,
+                              acc, sA, sB);
+    __syncthreads();
+    for_acc<T>(acc, [&](int r, int c, T v) {
+      if (r < sbi && c < sbj) Xij[r + (int64_t)c * kb2] = -v;
+    });
+    __threadfence();
+    __syncthreads();
+  }
+}
+
+// X = L[R', K] Linv_KK into Y (ld n_s, row 0 = first row of R'); 128x128 tiles
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_sel_Y2(DevSym S, LaunchList L, int step, SelBufs<T> B,
+                                                     const int64_t* __restrict__ D2off, const T* __restrict__ D2) {
+  __shared__ T sA[2 * kTK * kBP];
+  __shared__ T sB[2 * kTK * kBP];
+  int fi; int64_t loc;
+  find_front(L, wg_id(), fi, loc);
+  const int s = L.fronts[fi];
+  const int n = fn(S, s), p = fp(S, s);
+  const OuterBlk o = outer_blk(p, n, step);
+  const int nct = (o.kb2 + kBT - 1) / kBT;
+  const int rt = (int)(loc / nct), ctile = (int)(loc % nct);
+  const int row0 = o.rs + kBT * rt, col0 = kBT * ctile;
+  const int M = min(kBT, n - row0), N = min(kBT, o.kb2 - col0);
+  const T* X = D2 + D2off[s] + (int64_t)o.K * kNB2 * kNB2;
+  typename V4<T>::type acc[4][4];
+  zero_acc128<T>(acc);
+  gemm_tile128<T, false, true>(B.L + S.Loff[s] + row0 + (int64_t)o.k2 * n, n, X + (int64_t)col0 * o.kb2, o.kb2,
+                               M, N, o.kb2, acc, sA, sB);
+  T* Y = B.Y + S.Voff[s] * kNB2;
+  for_acc128<T>(acc, [&](int r, int c, T v) {
+    if (r < M && c < N) Y[(row0 - o.rs + r) + (int64_t)(col0 + c) * n] = v;
+  });
+}
+
+// Sigma[R', K] = -Sigma[R', R'] Y, mirrored into Sigma[K, R']; 128x128 tiles
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_sel_gemm2(DevSym S, LaunchList L, int step, SelBufs<T> B) {
+  __shared__ T sA[2 * kTK * kBP];
+  __shared__ T sB[2 * kTK * kBP];
+  int fi; int64_t loc;
+  find_front(L, wg_id(), fi, loc);
+  const int s = L.fronts[fi];
+  const int n = fn(S, s), p = fp(S, s);
+  const OuterBlk o = outer_blk(p, n, step);
+  const int nct = (o.kb2 + kBT - 1) / kBT;
+  const int rt = (int)(loc / nct), ctile = (int)(loc % nct);
+  const int row0 = o.rs + kBT * rt, col0 = kBT * ctile;
+  const int M = min(kBT, n - row0), N = min(kBT, o.kb2 - col0);
+  T* Sf = B.Scur + S.Woff[s];
+  const T* Y = B.Y + S.Voff[s] * kNB2;
+  typename V4<T>::type acc[4][4];
+  zero_acc128<T>(acc);
+  gemm_tile128<T, false, true>(Sf + row0 + (int64_t)o.rs * n, n, Y + (int64_t)col0 * n, n, M, N, n - o.rs,
+                               acc, sA, sB);
+  for_acc128<T>(acc, [&](int r, int c, T v) {
+    if (r < M && c < N) {
+      Sf[(row0 + r) + (int64_t)(o.k2 + col0 + c) * n] = -v;
+      Sf[(o.k2 + col0 + c) + (int64_t)(row0 + r) * n] = -v;
+    }
+  });
+}
+
+// split-K partials of X^T Sigma[R', K]: work-group (front, chunk, ti, tj) computes the
+// 64x64 tile (ti, tj) over kChunk rows of R' into part + wg * 64^2
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_sel_part2(DevSym S, LaunchList L, int step, SelBufs<T> B) {
+  __shared__ T sA[kTK * kP];
+  __shared__ T sB[kTK * kP];
+  int fi; int64_t loc;
+  find_front(L, wg_id(), fi, loc);
+  const int s = L.fronts[fi];
+  const int n = fn(S, s), p = fp(S, s);
+  const OuterBlk o = outer_blk(p, n, step);
+  const int nt = o.nsub * o.nsub;
+  const int chunk = (int)(loc / nt), rem = (int)(loc % nt);
+  const int ti = rem / o.nsub, tj = rem % o.nsub;
+  const int r0 = kChunk * chunk;
+  const int kr = max(0, min(kChunk, n - o.rs - r0));
+  const int M = min(kNB, o.kb2 - kNB * ti), N = min(kNB, o.kb2 - kNB * tj);
+  const T* Sf = B.Scur + S.Woff[s];
+  const T* Y = B.Y + S.Voff[s] * kNB2;
+  typename V4<T>::type acc[2][2];
+  zero_acc<T>(acc);
+  if (kr > 0)
+    gemm_tile<T, true, true>(Y + r0 + (int64_t)(kNB * ti) * n, n,
+                             Sf + (o.rs + r0) + (int64_t)(o.k2 + kNB * tj) * n, n, M, N, kr, acc, sA, sB);
+  T* out = B.part + wg_id() * (kNB * kNB);
+  for_acc<T>(acc, [&](int r, int c, T v) { out[r + c * kNB] = v; });
+}
+
+// Sigma[K, K] tile (ti >= tj) = (Linv^T Linv)[ti, tj] - sum over chunks of the partials,
+// written to both triangles
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_sel_fin2(DevSym S, LaunchList L, LaunchList Lpart, int step,
+                                                       SelBufs<T> B, const int64_t* __restrict__ D2off,
+                                                       const T* __restrict__ D2) {
+  __shared__ T sA[kTK * kP];
+  __shared__ T sB[kTK * kP];
+  int fi; int64_t loc;
+  find_front(L, wg_id(), fi, loc);
+  const int s = L.fronts[fi];
+  const int n = fn(S, s), p = fp(S, s);
+  const OuterBlk o = outer_blk(p, n, step);
+  const int ti = (int)(loc / o.nsub), tj = (int)(loc % o.nsub);
+  if (ti < tj) return;
+  const int M = min(kNB, o.kb2 - kNB * ti), N = min(kNB, o.kb2 - kNB * tj);
+  const T* X = D2 + D2off[s] + (int64_t)o.K * kNB2 * kNB2;
+  typename V4<T>::type acc[2][2];
+  zero_acc<T>(acc);
+  gemm_tile<T, true, true>(X + (int64_t)(kNB * ti) * o.kb2, o.kb2, X + (int64_t)(kNB * tj) * o.kb2, o.kb2, M, N,
+                           o.kb2, acc, sA, sB);
+  const int nt = o.nsub * o.nsub;
+  const int64_t q0 = Lpart.prefix[fi];
+  const int nchunks = (int)((Lpart.prefix[fi + 1] - q0) / nt);
+  T* Sf = B.Scur + S.Woff[s];
+  for_acc<T>(acc, [&](int r, int c, T v) {
+    if (r < M && c < N) {
+      T sp = T(0);
+      for (int ch = 0; ch < nchunks; ++ch)
+        sp += B.part[(q0 + (int64_t)ch * nt + ti * o.nsub + tj) * (kNB * kNB) + r + c * kNB];
+      const T val = v - sp;
+      if (ti == tj && r < c) return;   // the diagonal tile writes its lower half only
+      const int gi = o.k2 + kNB * ti + r, gj = o.k2 + kNB * tj + c;
+      Sf[gi + (int64_t)gj * n] = val;
+      Sf[gj + (int64_t)gi * n] = val;
+    }
+  });
+}
+
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_sel_extract(DevSym S, LaunchList L, SelBufs<T> B,
                                                           const double* __restrict__ scale, double* __restrict__ var) {
@@ -925,9 +1272,12 @@ template <typename T> void launch_trsm(hipStream_t st, const DevSym& S, const La
   hipLaunchKernelGGL(k_trsm<T>, dim3((unsigned)L.total), dim3(kThreads), 0, st, S, L, step, B);
 }
 template <typename T> void launch_update(hipStream_t st, const DevSym& S, const LaunchList& L, int step,
-                                         int syrk, NumBufs<T> B) {
+                                         int mode, NumBufs<T> B) {
   if (L.total <= 0) return;
-  hipLaunchKernelGGL(k_update<T>, dim3((unsigned)L.total), dim3(kThreads), 0, st, S, L, step, syrk, B);
+  if (mode == 0)
+    hipLaunchKernelGGL((k_update<T, 64>), dim3((unsigned)L.total), dim3(kThreads), 0, st, S, L, step, mode, B);
+  else
+    hipLaunchKernelGGL((k_update<T, 128>), dim3((unsigned)L.total), dim3(kThreads), 0, st, S, L, step, mode, B);
 }
 template <typename T> void launch_copy_L(hipStream_t st, const DevSym& S, const LaunchList& L, NumBufs<T> B) {
   if (L.total <= 0) return;
@@ -1027,6 +1377,32 @@ template <typename T> void launch_sel_diag_partial(hipStream_t st, const DevSym&
   if (L.total <= 0) return;
   hipLaunchKernelGGL(k_sel_diag_partial<T>, dim3((unsigned)L.total), dim3(kThreads), 0, st, S, L, step, B);
 }
+template <typename T> void launch_sel_inv256(hipStream_t st, const DevSym& S, const LaunchList& L, int step,
+                                             SelBufs<T> B, const int64_t* D2off, T* D2) {
+  if (L.total <= 0) return;
+  hipLaunchKernelGGL(k_sel_inv256<T>, dim3((unsigned)L.total), dim3(kThreads), 0, st, S, L, step, B, D2off, D2);
+}
+template <typename T> void launch_sel_Y2(hipStream_t st, const DevSym& S, const LaunchList& L, int step,
+                                         SelBufs<T> B, const int64_t* D2off, const T* D2) {
+  if (L.total <= 0) return;
+  hipLaunchKernelGGL(k_sel_Y2<T>, dim3((unsigned)L.total), dim3(kThreads), 0, st, S, L, step, B, D2off, D2);
+}
+template <typename T> void launch_sel_gemm2(hipStream_t st, const DevSym& S, const LaunchList& L, int step,
+                                            SelBufs<T> B) {
+  if (L.total <= 0) return;
+  hipLaunchKernelGGL(k_sel_gemm2<T>, dim3((unsigned)L.total), dim3(kThreads), 0, st, S, L, step, B);
+}
+template <typename T> void launch_sel_part2(hipStream_t st, const DevSym& S, const LaunchList& L, int step,
+                                            SelBufs<T> B) {
+  if (L.total <= 0) return;
+  hipLaunchKernelGGL(k_sel_part2<T>, dim3((unsigned)L.total), dim3(kThreads), 0, st, S, L, step, B);
+}
+template <typename T> void launch_sel_fin2(hipStream_t st, const DevSym& S, const LaunchList& L,
+                                           const LaunchList& Lpart, int step, SelBufs<T> B,
+                                           const int64_t* D2off, const T* D2) {
+  if (L.total <= 0) return;
+  hipLaunchKernelGGL(k_sel_fin2<T>, dim3((unsigned)L.total), dim3(kThreads), 0, st, S, L, Lpart, step, B, D2off, D2);
+}
 template <typename T> void launch_sel_extract(hipStream_t st, const DevSym& S, const LaunchList& L, SelBufs<T> B,
                                               const double* scale, double* var) {
   if (L.count <= 0) return;
@@ -1061,6 +1437,11 @@ template <typename T> void launch_sel_pattern(hipStream_t st, int64_t cnt, const
   template void launch_sel_gemm<T>(hipStream_t, const DevSym&, const LaunchList&, int, SelBufs<T>);  \
   template void launch_sel_diag_partial<T>(hipStream_t, const DevSym&, const LaunchList&, int, SelBufs<T>); \
   template void launch_sel_diag_finish<T>(hipStream_t, const DevSym&, const LaunchList&, const LaunchList&, int, SelBufs<T>); \
+  template void launch_sel_inv256<T>(hipStream_t, const DevSym&, const LaunchList&, int, SelBufs<T>, const int64_t*, T*); \
+  template void launch_sel_Y2<T>(hipStream_t, const DevSym&, const LaunchList&, int, SelBufs<T>, const int64_t*, const T*); \
+  template void launch_sel_gemm2<T>(hipStream_t, const DevSym&, const LaunchList&, int, SelBufs<T>); \
+  template void launch_sel_part2<T>(hipStream_t, const DevSym&, const LaunchList&, int, SelBufs<T>); \
+  template void launch_sel_fin2<T>(hipStream_t, const DevSym&, const LaunchList&, const LaunchList&, int, SelBufs<T>, const int64_t*, const T*); \
   template void launch_sel_extract<T>(hipStream_t, const DevSym&, const LaunchList&, SelBufs<T>, const double*, double*); \
   template void launch_sel_pattern<T>(hipStream_t, int64_t, const int64_t*, const int64_t*, const int32_t*, const int32_t*, const double*, const T*, double*);
 GMRF_INST(double)

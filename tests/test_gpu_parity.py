@@ -32,6 +32,7 @@ CASES_FP64 = {
     "spacetime_16x16x8": lambda: gi.advdiff_spacetime(ns=16, nt=8, seed=42),
     "spacetime_20x20x12": lambda: gi.advdiff_spacetime(ns=20, nt=12, seed=43),
     "matern3d_12": lambda: gi.matern3d(side=12, n_obs=200, seed=44),
+    "spacetime_24x24x16_multiblock": lambda: gi.advdiff_spacetime(ns=24, nt=16, seed=53),
 }
 
 
