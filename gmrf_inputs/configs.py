@@ -147,15 +147,31 @@ def matern_batch(n_prob: int = 256, side_lo: int = 64, side_hi: int = 256,
                  kappa_lo: float = 1.0, kappa_hi: float = 20.0, tau: float = 1.0,
                  sigma: float = 0.01, seed: int = 4) -> Problem:
     """Block-diagonal stack of independent 2D Matern problems with sides ~ U{lo..hi},
-    kappa ~ U[kappa_lo, kappa_hi], ceil(0.01 N_i) points each."""
+    kappa ~ U[kappa_lo, kappa_hi], ceil(0.01 N_i) points each.
+
+    Per side the FEM pieces are built once and Q is combined on the 2-ring pattern as
+    Q = tau^-2 (kappa^4 M~ + 2 kappa^2 S + S M~^-1 S), i.e. K M~^-1 K with K = kappa^2 M~ + S."""
     rng = rng_for(seed)
     sides = rng.integers(side_lo, side_hi + 1, size=n_prob)
     kappas = rng.uniform(kappa_lo, kappa_hi, size=n_prob)
+    cache = {}
     Qs, As, ys, qs, cs = [], [], [], [], []
     ptr = [0]
-    for s, kap in zip(sides, kappas):
-        mesh = fem.structured_mesh((int(s), int(s)))
-        Q, _, _ = priors.matern_precision(mesh, float(kap), tau)
+    for s_, kap in zip(sides, kappas):
+        s_ = int(s_)
+        if s_ not in cache:
+            mesh = fem.structured_mesh((s_, s_))
+            S = fem.stiffness(mesh)
+            m = fem.lumped_mass(mesh)
+            P2 = fem.ring_pattern(mesh, 2)
+            cache[s_] = (mesh, m, P2,
+                         fem.on_pattern(sp.diags(m), P2).data,
+                         fem.on_pattern(S, P2).data,
+                         fem.on_pattern(S @ sp.diags(1.0 / m) @ S, P2).data)
+        mesh, m, P2, Md, Sd, SMSd = cache[s_]
+        k2 = float(kap) ** 2
+        data = (k2 * k2 * Md + 2.0 * k2 * Sd + SMSd) / (tau * tau)
+        Q = sp.csr_matrix((data, P2.indices.copy(), P2.indptr.copy()), shape=P2.shape)
         target = smooth_target(rng, 2)
         npts = int(math.ceil(0.01 * mesh.n))
         pts = rng.uniform(0.0, 1.0, size=(npts, 2))
@@ -172,6 +188,17 @@ def matern_batch(n_prob: int = 256, side_lo: int = 64, side_hi: int = 256,
                    np.concatenate(cs), block_ptr=np.asarray(ptr, dtype=np.int64),
                    meta=dict(workload="matern_batch", n_prob=n_prob, sides=sides,
                              kappas=kappas, tau=tau, sigma=sigma, seed=seed))
+
+
+def batch_block(problem: Problem, b: int) -> Problem:
+    """The b-th independent problem of a block-diagonal batch as a Problem of its own."""
+    lo, hi = int(problem.block_ptr[b]), int(problem.block_ptr[b + 1])
+    Qb = problem.Q[lo:hi, lo:hi].tocsr()
+    Ab_all = problem.A[:, lo:hi].tocsr()
+    rows = np.flatnonzero(np.diff(Ab_all.indptr))
+    Ab = Ab_all[rows].tocsr()
+    return Problem(hi - lo, Qb, Ab, problem.q_eps[rows], problem.y[rows], problem.b[rows],
+                   problem.coords[lo:hi], meta=dict(workload="matern_batch_block", block=b))
 
 
 def matern3d(side: int = 64, kappa: float = 10.0, tau: float = 1.0, n_obs: int = 5000,

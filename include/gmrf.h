@@ -186,7 +186,10 @@ typedef struct {
   double bytes;
 } gmrf_kernel_stat_t;
 
-/* Reset the per-class counters and switch per-launch events on (enable != 0) or off. */
+/* Reset the per-class counters and switch per-launch events off (enable == 0), on for
+   every class (enable == 1), or on for the classes whose bits are set in any other
+   value of enable (bit i = i-th record of gmrf_kernel_stats), so that a timed run can
+   carry events around one kernel class only. */
 gmrf_status gmrf_profile(gmrf_t h, int enable);
 
 /* Copy up to `capacity` class records (host) and the number of classes to *count;

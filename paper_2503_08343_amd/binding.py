@@ -50,6 +50,12 @@ class gmrf_stats_t(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+KERNEL_CLASSES = ["assemble", "equilibrate", "front_zero", "front_scatter", "extend_add",
+                  "potrf_diag", "trsm_panel", "update_panel", "syrk_update", "copy_L", "logdet",
+                  "solve_fwd", "solve_bwd", "residual", "permute", "sel_gather", "sel_Y",
+                  "sel_gemm", "sel_diag", "sel_extract"]
+
+
 class gmrf_kernel_stat_t(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_int64), ("ms", ctypes.c_double),
                 ("flops", ctypes.c_double), ("bytes", ctypes.c_double)]
@@ -285,8 +291,18 @@ class Context:
         self._check(self.lib.gmrf_pivot_order(self.h, _np_ptr(p)))
         return p
 
-    def profile(self, enable=True):
-        self._check(self.lib.gmrf_profile(self.h, 1 if enable else 0))
+    def profile(self, enable=True, classes=None):
+        """enable: switch per-launch events on/off; classes: optional list of kernel-class
+        names (as reported by kernel_stats) restricting the events to those classes."""
+        val = 1 if enable else 0
+        if enable and classes:
+            names = KERNEL_CLASSES
+            val = 0
+            for c in classes:
+                val |= 1 << names.index(c)
+            if val == 1:   # class 0 alone would read as "all"; widen by an unused bit
+                val |= 1 << 31
+        self._check(self.lib.gmrf_profile(self.h, val))
 
     def kernel_stats(self):
         cnt = ctypes.c_int(0)

@@ -74,14 +74,11 @@ struct Level {
   std::vector<HostList> ext;       // extend-add per child slot (tiles = child u)
   std::vector<HostList> fvec_ext;  // vector extend-add per child slot (1 per parent)
   std::vector<HostList> potrf, trsm, upd, upd_out;   // per 64-block step
-  HostList syrk, copyL;
-  std::vector<HostList> fdiag, fupd;        // forward solve per step
-  HostList binit;
-  std::vector<HostList> bdiag, bupd;        // backward solve per step (from the right)
+  HostList syrk, copyL, inv256;
   HostList sgather;
-  std::vector<HostList> sY, sgemm, spart, sfin;  // selinv per step (from the right)
   int nsteps2 = 0;                                // 256-wide outer blocks of the widest front
-  std::vector<HostList> sinv2, sY2, sgemm2, spart2, sfin2;
+  std::vector<HostList> fblk, fout, bpart, bblk;  // solves per outer block
+  std::vector<HostList> sY2, sgemm2, spart2, sfin2;
   double wsize_elems_scatter = 0.0;
 };
 
@@ -117,10 +114,11 @@ struct gmrf_ctx {
   std::vector<Level> levels;
   int64_t max_front = 0;
   int64_t part_max = 0;   // largest split-K partial launch (work-groups)
+  int64_t bpart_max = 0;  // largest backward-solve partial launch (work-groups)
 
   int prec = -1;
   DevArr<char> d_L, d_D, d_D2, d_W0, d_W1, d_Y, d_part;
-  DevArr<double> d_piv, d_V0, d_V1, d_xp, d_w, d_r, d_red, d_norm, d_ld, d_mu_post;
+  DevArr<double> d_piv, d_V0, d_V1, d_xp, d_w, d_r, d_red, d_norm, d_ld, d_mu_post, d_bpart;
   DevArr<int32_t> d_status;
   int refine_iters = 0;
   double refine_resid = 0.0;
@@ -130,6 +128,7 @@ struct gmrf_ctx {
   bool ev_factor = false, ev_solve = false, ev_sel = false;
   // per-launch profiler (events around every launch of a class while enabled)
   bool prof = false;
+  uint32_t prof_mask = 0xffffffffu;   // kernel classes that get events while profiling
   std::vector<hipEvent_t> evpool;
   size_t evused = 0;
   struct Mark { int cls; size_t e0, e1; double flops, bytes; };
@@ -169,7 +168,7 @@ hipEvent_t prof_event(gmrf_t h) {
 // run `launch` with events around it when profiling is on
 template <typename F>
 void prof_launch(gmrf_t h, int cls, double flops, double elems, F launch) {
-  if (!h->prof) { launch(); return; }
+  if (!h->prof || !((h->prof_mask >> cls) & 1u)) { launch(); return; }
   const size_t i0 = h->evused;
   hipEvent_t a = prof_event(h);
   if (a) (void)hipEventRecord(a, h->stream);
@@ -379,6 +378,7 @@ gmrf_status build_plan(gmrf_t h) {
 
   ListBuilder B;
   h->part_max = 0;
+  h->bpart_max = 0;
   for (int d = 0; d <= Y.max_depth; ++d) {
     Level& lv = h->levels[d];
     lv.map_begin = cnt[d];
@@ -435,48 +435,6 @@ gmrf_status build_plan(gmrf_t h) {
         if (!outer_here || pF(s) <= (int64_t)(k + 1) * nb) return 0;
         return upd_tiles(nF(s), pF(s), 1, k, kBigTile);
       }, [&](int32_t s) { return upd_cost(nF(s), pF(s), 1, k); }));
-      lv.fdiag.push_back(B.add(lv.fronts, [&](int32_t s) -> int64_t { return active(s) ? 1 : 0; },
-                               [&](int32_t s) { const double b = (double)kb(s); return Cost{b * b, 0.5 * b * b}; }));
-      lv.fupd.push_back(B.add(lv.fronts, [&](int32_t s) -> int64_t {
-        if (!active(s)) return 0;
-        return (nF(s) - k0 - kb(s) + kTile - 1) / kTile;
-      }, [&](int32_t s) { return Cost{2.0 * below(s) * (double)kb(s), below(s) * (double)kb(s)}; }));
-      // steps counted from the right: block index nblk-1-k
-      auto rblk = [&](int32_t s) { return (pF(s) + nb - 1) / nb - 1 - k; };
-      auto ractive = [&](int32_t s) { return rblk(s) >= 0; };
-      auto rkb = [&](int32_t s) { return std::min<int64_t>(nb, pF(s) - rblk(s) * nb); };
-      auto rtail = [&](int32_t s) {  // rows after the block
-        const int64_t kk0 = rblk(s) * nb;
-        return nF(s) - kk0 - rkb(s);
-      };
-      lv.bdiag.push_back(B.add(lv.fronts, [&](int32_t s) -> int64_t { return ractive(s) ? 1 : 0; },
-                               [&](int32_t s) { const double b = (double)rkb(s); return Cost{b * b, 0.5 * b * b}; }));
-      lv.bupd.push_back(B.add(lv.fronts, [&](int32_t s) -> int64_t { return ractive(s) ? rblk(s) : 0; },
-                              [&](int32_t s) {
-                                const double w = (double)rblk(s) * nb, b = (double)rkb(s);
-                                return Cost{2.0 * w * b, w * b};
-                              }));
-      lv.sY.push_back(B.add(lv.fronts, [&](int32_t s) -> int64_t {
-        return ractive(s) ? (rtail(s) + kTile - 1) / kTile : 0;
-      }, [&](int32_t s) {
-        const double r = (double)rtail(s), b = (double)rkb(s);
-        return Cost{r * b * b, 2.0 * r * b};
-      }));
-      lv.sgemm.push_back(B.add(lv.fronts, [&](int32_t s) -> int64_t {
-        return ractive(s) ? (rtail(s) + kTile - 1) / kTile : 0;
-      }, [&](int32_t s) {
-        const double r = (double)rtail(s), b = (double)rkb(s);
-        return Cost{2.0 * r * r * b, r * r + 3.0 * r * b};
-      }));
-      lv.spart.push_back(B.add(lv.fronts, [&](int32_t s) -> int64_t {
-        return ractive(s) ? std::max<int64_t>(1, (rtail(s) + 511) / 512) : 0;
-      }, [&](int32_t s) {
-        const double r = (double)rtail(s), b = (double)rkb(s);
-        return Cost{r * b * (b + 1.0), 2.0 * r * b};
-      }));
-      h->part_max = std::max(h->part_max, lv.spart.back().total);
-      lv.sfin.push_back(B.add(lv.fronts, [&](int32_t s) -> int64_t { return ractive(s) ? 1 : 0; },
-                              [&](int32_t s) { const double b = (double)rkb(s); return Cost{b * b * b / 3.0, 2.0 * b * b}; }));
     }
     // two-level selected inversion: outer blocks of 256 columns, counted from the right
     lv.nsteps2 = 0;
@@ -488,8 +446,6 @@ gmrf_status build_plan(gmrf_t h) {
       auto otail = [&](int32_t s) { return nF(s) - oK(s) * kNB2 - okb2(s); };
       auto onsub = [&](int32_t s) { return (okb2(s) + nb - 1) / nb; };
       auto onct = [&](int32_t s) { return (okb2(s) + kBigTile - 1) / kBigTile; };
-      lv.sinv2.push_back(B.add(lv.fronts, [&](int32_t s) -> int64_t { return oact(s) ? onsub(s) : 0; },
-                               [&](int32_t s) { const double b = (double)okb2(s); return Cost{b * b * b / 3.0, b * b}; }));
       lv.sY2.push_back(B.add(lv.fronts, [&](int32_t s) -> int64_t {
         return oact(s) ? ((otail(s) + kBigTile - 1) / kBigTile) * onct(s) : 0;
       }, [&](int32_t s) {
@@ -509,19 +465,40 @@ gmrf_status build_plan(gmrf_t h) {
         return Cost{2.0 * r * b * b, 2.0 * r * b};
       }));
       h->part_max = std::max(h->part_max, lv.spart2.back().total);
+      // solves: forward outer block t (left to right), backward outer block from the right
+      auto fact = [&](int32_t s) { return pF(s) > (int64_t)t * kNB2; };
+      auto fkb2 = [&](int32_t s) { return std::min<int64_t>(kNB2, pF(s) - (int64_t)t * kNB2); };
+      auto fbelow = [&](int32_t s) { return nF(s) - (int64_t)t * kNB2 - fkb2(s); };
+      lv.fblk.push_back(B.add(lv.fronts, [&](int32_t s) -> int64_t { return fact(s) ? 1 : 0; },
+                              [&](int32_t s) { const double b = (double)fkb2(s); return Cost{b * b, 0.5 * b * b}; }));
+      lv.fout.push_back(B.add(lv.fronts, [&](int32_t s) -> int64_t {
+        return fact(s) ? (fbelow(s) + 63) / 64 : 0;
+      }, [&](int32_t s) {
+        const double r = (double)fbelow(s), b = (double)fkb2(s);
+        return Cost{2.0 * r * b, r * b};
+      }));
+      lv.bpart.push_back(B.add(lv.fronts, [&](int32_t s) -> int64_t {
+        return oact(s) ? std::max<int64_t>(1, (otail(s) + 255) / 256) : 0;
+      }, [&](int32_t s) {
+        const double r = (double)otail(s), b = (double)okb2(s);
+        return Cost{2.0 * r * b, r * b};
+      }));
+      h->bpart_max = std::max(h->bpart_max, lv.bpart.back().total);
+      lv.bblk.push_back(B.add(lv.fronts, [&](int32_t s) -> int64_t { return oact(s) ? 1 : 0; },
+                              [&](int32_t s) { const double b = (double)okb2(s); return Cost{b * b, 0.5 * b * b}; }));
       lv.sfin2.push_back(B.add(lv.fronts, [&](int32_t s) -> int64_t { return oact(s) ? onsub(s) * onsub(s) : 0; },
                                [&](int32_t s) { const double b = (double)okb2(s); return Cost{b * b * b / 3.0, 2.0 * b * b}; }));
     }
     lv.syrk = B.add(lv.fronts, [&](int32_t s) -> int64_t {
       return nF(s) > pF(s) ? upd_tiles(nF(s), pF(s), 2, 0, kBigTile) : 0;
     }, [&](int32_t s) { return upd_cost(nF(s), pF(s), 2, 0); });
+    lv.inv256 = B.add(lv.fronts, [&](int32_t s) -> int64_t { return (pF(s) + nb - 1) / nb; }, [&](int32_t s) {
+      const double p = (double)pF(s);
+      return Cost{p * (double)kNB2 * (double)kNB2 / 3.0, p * (double)kNB2};
+    });
     lv.copyL = B.add(lv.fronts, [&](int32_t s) -> int64_t { return pF(s); }, [&](int32_t s) {
       const double p = (double)pF(s), n = (double)nF(s);
       return Cost{0.0, 2.0 * (p * n - 0.5 * p * (p - 1.0))};
-    });
-    lv.binit = B.add(lv.fronts, [&](int32_t s) -> int64_t { return (pF(s) + nb - 1) / nb; }, [&](int32_t s) {
-      const double u = (double)(nF(s) - pF(s)), p = (double)pF(s);
-      return Cost{2.0 * u * p, u * p};
     });
     lv.sgather = B.add(lv.fronts, [&](int32_t s) -> int64_t {
       return Y.sparent[s] >= 0 ? nF(s) - pF(s) : 0;
@@ -580,6 +557,7 @@ gmrf_status alloc_numeric(gmrf_t h) {
   const Symbolic& Y = h->sym;
   HIPCHK(h, h->d_L.alloc((size_t)Y.Lsize * sizeof(T)));
   HIPCHK(h, h->d_D.alloc((size_t)Y.Dsize * sizeof(T)));
+  HIPCHK(h, h->d_D2.alloc((size_t)std::max<int64_t>(h->D2size, 1) * sizeof(T)));
   HIPCHK(h, h->d_W0.alloc((size_t)std::max<int64_t>(Y.Wsize[0], 1) * sizeof(T)));
   HIPCHK(h, h->d_W1.alloc((size_t)std::max<int64_t>(Y.Wsize[1], 1) * sizeof(T)));
   HIPCHK(h, h->d_piv.alloc(h->n));
@@ -637,6 +615,9 @@ gmrf_status run_factor(gmrf_t h) {
     if (lv.syrk.total > 0)
       prof_launch(h, KC_SYRK, lv.syrk.flops, lv.syrk.elems,
                   [&] { launch_update<T>(st, S, dev_list(h, lv.syrk), 0, 2, B); });
+    prof_launch(h, KC_POTRF, lv.inv256.flops, lv.inv256.elems, [&] {
+      launch_inv256<T>(st, S, dev_list(h, lv.inv256), B.Wcur, 1, B.D, h->d_D2off.p, (T*)h->d_D2.p);
+    });
     prof_launch(h, KC_COPYL, 0.0, lv.copyL.elems, [&] { launch_copy_L<T>(st, S, dev_list(h, lv.copyL), B); });
   }
   HIPCHK(h, hipGetLastError());
@@ -676,11 +657,10 @@ void run_solve(gmrf_t h, int nrhs, bool forward) {
         for (size_t c = 0; c < lv.fvec_ext.size(); ++c)
           launch_fvec_extend<T>(st, S, dev_list(h, lv.fvec_ext[c]), (int)c, B);
       });
-      for (int k = 0; k < lv.nsteps; ++k) {
-        prof_launch(h, KC_FWD, nrhs * (lv.fdiag[k].flops + lv.fupd[k].flops),
-                    lv.fdiag[k].elems + lv.fupd[k].elems, [&] {
-          launch_fwd_diag<T>(st, S, dev_list(h, lv.fdiag[k]), k, D, B);
-          launch_fwd_update<T>(st, S, dev_list(h, lv.fupd[k]), k, Lp, B);
+      for (int t = 0; t < lv.nsteps2; ++t) {
+        prof_launch(h, KC_FWD, nrhs * (lv.fblk[t].flops + lv.fout[t].flops), lv.fblk[t].elems + lv.fout[t].elems, [&] {
+          launch_fwd_block<T>(st, S, dev_list(h, lv.fblk[t]), t, (const T*)h->d_D2.p, h->d_D2off.p, B);
+          launch_fwd_outer<T>(st, S, dev_list(h, lv.fout[t]), t, Lp, B);
         });
       }
     }
@@ -688,13 +668,11 @@ void run_solve(gmrf_t h, int nrhs, bool forward) {
   for (int d = 0; d <= Y.max_depth; ++d) {
     const Level& lv = h->levels[d];
     SolveBufs B{h->d_xp.p, V[d & 1], V[(d + 1) & 1], nrhs};
-    prof_launch(h, KC_BWD, nrhs * lv.binit.flops, lv.binit.elems,
-                [&] { launch_bwd_init<T>(st, S, dev_list(h, lv.binit), Lp, B); });
-    for (int k = 0; k < lv.nsteps; ++k) {
-      prof_launch(h, KC_BWD, nrhs * (lv.bdiag[k].flops + lv.bupd[k].flops),
-                  lv.bdiag[k].elems + lv.bupd[k].elems, [&] {
-        launch_bwd_diag<T>(st, S, dev_list(h, lv.bdiag[k]), k, D, B);
-        launch_bwd_update<T>(st, S, dev_list(h, lv.bupd[k]), k, Lp, B);
+    for (int t = 0; t < lv.nsteps2; ++t) {
+      prof_launch(h, KC_BWD, nrhs * (lv.bpart[t].flops + lv.bblk[t].flops), lv.bpart[t].elems + lv.bblk[t].elems, [&] {
+        launch_bwd_part<T>(st, S, dev_list(h, lv.bpart[t]), t, Lp, B, h->d_bpart.p);
+        launch_bwd_block<T>(st, S, dev_list(h, lv.bblk[t]), dev_list(h, lv.bpart[t]), t, (const T*)h->d_D2.p,
+                            h->d_D2off.p, B, h->d_bpart.p);
       });
     }
   }
@@ -710,6 +688,7 @@ gmrf_status alloc_solve(gmrf_t h, int nrhs) {
   HIPCHK(h, h->d_red.alloc(1024));
   HIPCHK(h, h->d_norm.alloc(4));
   HIPCHK(h, h->d_mu_post.alloc(h->n));
+  HIPCHK(h, h->d_bpart.alloc((size_t)std::max<int64_t>(h->bpart_max, 1) * kNB2 * 16));
   return GMRF_OK;
 }
 
@@ -723,7 +702,6 @@ gmrf_status run_selinv(gmrf_t h, double* var, double* sigq) {
   HIPCHK(h, h->d_Y.alloc((size_t)ysz * sizeof(T)));
   HIPCHK(h, h->d_part.alloc((size_t)std::max<int64_t>(h->part_max, 1) * kNB * kNB * sizeof(T)));
   T* W[2] = {(T*)h->d_W0.p, (T*)h->d_W1.p};
-  HIPCHK(h, h->d_D2.alloc((size_t)std::max<int64_t>(h->D2size, 1) * sizeof(T)));
   T* D2 = (T*)h->d_D2.p;
   for (int d = 0; d <= Y.max_depth; ++d) {
     const Level& lv = h->levels[d];
@@ -737,10 +715,8 @@ gmrf_status run_selinv(gmrf_t h, double* var, double* sigq) {
     prof_launch(h, KC_SEL_GATHER, 0.0, lv.sgather.elems,
                 [&] { launch_sel_gather<T>(st, S, dev_list(h, lv.sgather), h->d_sparent.p, B); });
     for (int t = 0; t < lv.nsteps2; ++t) {
-      prof_launch(h, KC_SEL_Y, lv.sinv2[t].flops + lv.sY2[t].flops, lv.sinv2[t].elems + lv.sY2[t].elems, [&] {
-        launch_sel_inv256<T>(st, S, dev_list(h, lv.sinv2[t]), t, B, h->d_D2off.p, D2);
-        launch_sel_Y2<T>(st, S, dev_list(h, lv.sY2[t]), t, B, h->d_D2off.p, D2);
-      });
+      prof_launch(h, KC_SEL_Y, lv.sY2[t].flops, lv.sY2[t].elems,
+                  [&] { launch_sel_Y2<T>(st, S, dev_list(h, lv.sY2[t]), t, B, h->d_D2off.p, D2); });
       if (lv.sgemm2[t].total > 0)
         prof_launch(h, KC_SEL_GEMM, lv.sgemm2[t].flops, lv.sgemm2[t].elems,
                     [&] { launch_sel_gemm2<T>(st, S, dev_list(h, lv.sgemm2[t]), t, B); });
@@ -1017,8 +993,11 @@ gmrf_status gmrf_logdet(gmrf_t h, double* out) {
   if (!(h->state & ST_FACTORED)) return fail(h, GMRF_ERR_STATE, "gmrf_logdet before gmrf_factor");
   gmrf_status rc = check_status(h);
   if (rc != GMRF_OK) return rc;
-  HIPCHK(h, h->d_ld.alloc(h->nblocks));
-  launch_logdet(h->stream, h->nblocks, h->d_bptr.p, h->d_bpiv.p, h->d_perm.p, h->d_piv.p, h->d_sexp.p, h->d_ld.p);
+  HIPCHK(h, h->d_ld.alloc(h->nblocks * 65));
+  prof_launch(h, KC_LOGDET, 0.0, 0.0, [&] {
+    launch_logdet(h->stream, h->nblocks, h->d_bptr.p, h->d_bpiv.p, h->d_perm.p, h->d_piv.p, h->d_sexp.p,
+                  h->d_ld.p + h->nblocks, h->d_ld.p);
+  });
   HIPCHK(h, hipGetLastError());
   HIPCHK(h, hipMemcpyAsync(out, h->d_ld.p, h->nblocks * sizeof(double), hipMemcpyDeviceToHost, h->stream));
   HIPCHK(h, hipStreamSynchronize(h->stream));
@@ -1171,6 +1150,7 @@ gmrf_status gmrf_profile(gmrf_t h, int enable) {
   prof_fold(h);
   for (int c = 0; c < KC_COUNT; ++c) { h->cls_ms[c] = 0; h->cls_flops[c] = 0; h->cls_bytes[c] = 0; h->cls_n[c] = 0; }
   h->prof = enable != 0;
+  h->prof_mask = enable == 1 ? 0xffffffffu : (uint32_t)enable;
   return GMRF_OK;
 }
 

@@ -75,8 +75,9 @@ template <typename T> void launch_update(hipStream_t st, const DevSym& S, const 
                                          int step, int mode, NumBufs<T> B);
 template <typename T> void launch_copy_L(hipStream_t st, const DevSym& S, const LaunchList& L,
                                          NumBufs<T> B);
+// part: nblocks * 64 doubles of scratch
 void launch_logdet(hipStream_t st, int64_t nblocks, const int64_t* bptr, const int32_t* bpiv,
-                   const int32_t* perm, const double* piv, const int32_t* sexp, double* out);
+                   const int32_t* perm, const double* piv, const int32_t* sexp, double* part, double* out);
 
 // ---- triangular solves (front vectors in FP64, L in T) ----
 struct SolveBufs {
@@ -87,11 +88,19 @@ struct SolveBufs {
 };
 template <typename T> void launch_fvec_init(hipStream_t st, const DevSym& S, const LaunchList& L, SolveBufs V);
 template <typename T> void launch_fvec_extend(hipStream_t st, const DevSym& S, const LaunchList& L, int slot, SolveBufs V);
-template <typename T> void launch_fwd_diag(hipStream_t st, const DevSym& S, const LaunchList& L, int step, const T* D, SolveBufs V);
-template <typename T> void launch_fwd_update(hipStream_t st, const DevSym& S, const LaunchList& L, int step, const T* Lp, SolveBufs V);
-template <typename T> void launch_bwd_init(hipStream_t st, const DevSym& S, const LaunchList& L, const T* Lp, SolveBufs V);
-template <typename T> void launch_bwd_diag(hipStream_t st, const DevSym& S, const LaunchList& L, int step, const T* D, SolveBufs V);
-template <typename T> void launch_bwd_update(hipStream_t st, const DevSym& S, const LaunchList& L, int step, const T* Lp, SolveBufs V);
+// solves blocked by 256-wide outer blocks (forward left to right, backward from the right)
+template <typename T> void launch_fwd_block(hipStream_t st, const DevSym& S, const LaunchList& L, int t,
+                                            const T* D2, const int64_t* D2off, SolveBufs V);
+// inverses of the 256-wide diagonal blocks (Lbase: front buffer if from_front, else L storage)
+template <typename T> void launch_inv256(hipStream_t st, const DevSym& S, const LaunchList& L, const T* Lbase,
+                                         int from_front, const T* Dinv, const int64_t* D2off, T* D2);
+template <typename T> void launch_fwd_outer(hipStream_t st, const DevSym& S, const LaunchList& L, int t,
+                                            const T* Lp, SolveBufs V);
+template <typename T> void launch_bwd_part(hipStream_t st, const DevSym& S, const LaunchList& L, int t,
+                                           const T* Lp, SolveBufs V, double* part);
+template <typename T> void launch_bwd_block(hipStream_t st, const DevSym& S, const LaunchList& L,
+                                            const LaunchList& Lpart, int t, const T* D2, const int64_t* D2off,
+                                            SolveBufs V, const double* part);
 void launch_permute_in(hipStream_t st, int64_t n, int nrhs, const int32_t* perm, const double* scale,
                        const double* src, int64_t lds, double* xp);
 void launch_permute_in_f32(hipStream_t st, int64_t n, int nrhs, const float* z, double* xp);
@@ -114,13 +123,7 @@ struct SelBufs {
   T* part;         // split-K partials
 };
 template <typename T> void launch_sel_gather(hipStream_t st, const DevSym& S, const LaunchList& L, const int32_t* sparent, SelBufs<T> B);
-template <typename T> void launch_sel_Y(hipStream_t st, const DevSym& S, const LaunchList& L, int step, SelBufs<T> B);
-template <typename T> void launch_sel_gemm(hipStream_t st, const DevSym& S, const LaunchList& L, int step, SelBufs<T> B);
-template <typename T> void launch_sel_diag_partial(hipStream_t st, const DevSym& S, const LaunchList& L, int step, SelBufs<T> B);
-template <typename T> void launch_sel_diag_finish(hipStream_t st, const DevSym& S, const LaunchList& L, const LaunchList& Lpart, int step, SelBufs<T> B);
 // two-level selected inversion (256-wide outer blocks counted from the right by `step`)
-template <typename T> void launch_sel_inv256(hipStream_t st, const DevSym& S, const LaunchList& L, int step,
-                                             SelBufs<T> B, const int64_t* D2off, T* D2);
 template <typename T> void launch_sel_Y2(hipStream_t st, const DevSym& S, const LaunchList& L, int step,
                                          SelBufs<T> B, const int64_t* D2off, const T* D2);
 template <typename T> void launch_sel_gemm2(hipStream_t st, const DevSym& S, const LaunchList& L, int step, SelBufs<T> B);

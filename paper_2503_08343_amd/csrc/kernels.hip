@@ -172,86 +172,98 @@ __device__ __forceinline__ void for_acc128(typename V4<T>::type (&acc)[4][4], F 
 constexpr int kBT = 128;
 constexpr int kBP = 144;   // LDS pitch: rows of a K slice start 32 banks apart (FP64) / 16 (FP32)
 
+// K chunk of the 128x128 tile (16: the LDS footprint leaves room for several work-groups
+// per CU; 32 halved the occupancy and ran slower)
+template <typename T> struct BigTK { static constexpr int v = 16; };
+
 template <typename T, bool A_KC, bool B_KC>
 __device__ __forceinline__ void big_load(const T* __restrict__ A, int64_t lda, const T* __restrict__ B,
-                                         int64_t ldb, int M, int N, int K, int k0, T (&ra)[8], T (&rb)[8]) {
+                                         int64_t ldb, int M, int N, int K, int k0,
+                                         T (&ra)[BigTK<T>::v / 2], T (&rb)[BigTK<T>::v / 2]) {
+  constexpr int TK = BigTK<T>::v, NL = TK / 2;
   const int t = threadIdx.x;
   if (!A_KC) {
     const int m = t & 127;
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
+    for (int i = 0; i < NL; ++i) {
       const int k = (t >> 7) + 2 * i;
       ra[i] = (m < M && k0 + k < K) ? A[m + (int64_t)(k0 + k) * lda] : T(0);
     }
   } else {
-    const int k = t & 15;
+    const int k = t & (TK - 1);
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const int m = (t >> 4) + 16 * i;
+    for (int i = 0; i < NL; ++i) {
+      const int m = t / TK + (kThreads / TK) * i;
       ra[i] = (m < M && k0 + k < K) ? A[(k0 + k) + (int64_t)m * lda] : T(0);
     }
   }
   if (!B_KC) {
     const int nn = t & 127;
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
+    for (int i = 0; i < NL; ++i) {
       const int k = (t >> 7) + 2 * i;
       rb[i] = (nn < N && k0 + k < K) ? B[nn + (int64_t)(k0 + k) * ldb] : T(0);
     }
   } else {
-    const int k = t & 15;
+    const int k = t & (TK - 1);
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const int nn = (t >> 4) + 16 * i;
+    for (int i = 0; i < NL; ++i) {
+      const int nn = t / TK + (kThreads / TK) * i;
       rb[i] = (nn < N && k0 + k < K) ? B[(k0 + k) + (int64_t)nn * ldb] : T(0);
     }
   }
 }
 
 template <typename T, bool A_KC, bool B_KC>
-__device__ __forceinline__ void big_store(T* sA, T* sB, const T (&ra)[8], const T (&rb)[8]) {
+__device__ __forceinline__ void big_store(T* sA, T* sB, const T (&ra)[BigTK<T>::v / 2],
+                                          const T (&rb)[BigTK<T>::v / 2]) {
+  constexpr int TK = BigTK<T>::v, NL = TK / 2;
   const int t = threadIdx.x;
   if (!A_KC) {
     const int m = t & 127;
 #pragma unroll
-    for (int i = 0; i < 8; ++i) sA[((t >> 7) + 2 * i) * kBP + m] = ra[i];
+    for (int i = 0; i < NL; ++i) sA[((t >> 7) + 2 * i) * kBP + m] = ra[i];
   } else {
-    const int k = t & 15;
+    const int k = t & (TK - 1);
 #pragma unroll
-    for (int i = 0; i < 8; ++i) sA[k * kBP + (t >> 4) + 16 * i] = ra[i];
+    for (int i = 0; i < NL; ++i) sA[k * kBP + t / TK + (kThreads / TK) * i] = ra[i];
   }
   if (!B_KC) {
     const int nn = t & 127;
 #pragma unroll
-    for (int i = 0; i < 8; ++i) sB[((t >> 7) + 2 * i) * kBP + nn] = rb[i];
+    for (int i = 0; i < NL; ++i) sB[((t >> 7) + 2 * i) * kBP + nn] = rb[i];
   } else {
-    const int k = t & 15;
+    const int k = t & (TK - 1);
 #pragma unroll
-    for (int i = 0; i < 8; ++i) sB[k * kBP + (t >> 4) + 16 * i] = rb[i];
+    for (int i = 0; i < NL; ++i) sB[k * kBP + t / TK + (kThreads / TK) * i] = rb[i];
   }
 }
 
-// sA, sB: 2 buffers each of kTK * kBP elements
+// LDS elements per operand (two K-chunk buffers)
+template <typename T> struct BigLds { static constexpr int v = 2 * BigTK<T>::v * kBP; };
+
+// sA, sB: BigLds<T>::v elements each
 template <typename T, bool A_KC, bool B_KC>
 __device__ __forceinline__ void gemm_tile128(const T* __restrict__ A, int64_t lda,
                                              const T* __restrict__ B, int64_t ldb, int M, int N, int K,
                                              typename V4<T>::type (&acc)[4][4], T* sA, T* sB) {
+  constexpr int TK = BigTK<T>::v;
   const int lane = threadIdx.x & 63;
   const int w = threadIdx.x >> 6;
   const int wm = (w & 1) * 64, wn = (w >> 1) * 64;
-  T ra[8], rb[8];
+  T ra[TK / 2], rb[TK / 2];
   if (K <= 0) return;
   big_load<T, A_KC, B_KC>(A, lda, B, ldb, M, N, K, 0, ra, rb);
   big_store<T, A_KC, B_KC>(sA, sB, ra, rb);
   __syncthreads();
   int buf = 0;
-  for (int k0 = 0; k0 < K; k0 += kTK) {
-    const bool more = k0 + kTK < K;
-    if (more) big_load<T, A_KC, B_KC>(A, lda, B, ldb, M, N, K, k0 + kTK, ra, rb);
-    const T* cA = sA + buf * (kTK * kBP);
-    const T* cB = sB + buf * (kTK * kBP);
+  for (int k0 = 0; k0 < K; k0 += TK) {
+    const bool more = k0 + TK < K;
+    if (more) big_load<T, A_KC, B_KC>(A, lda, B, ldb, M, N, K, k0 + TK, ra, rb);
+    const T* cA = sA + buf * (TK * kBP);
+    const T* cB = sB + buf * (TK * kBP);
 #pragma unroll
-    for (int kk = 0; kk < kTK; kk += 4) {
+    for (int kk = 0; kk < TK; kk += 4) {
       T a[4], b[4];
 #pragma unroll
       for (int i = 0; i < 4; ++i) a[i] = cA[(kk + (lane >> 4)) * kBP + wm + 16 * i + (lane & 15)];
@@ -262,7 +274,7 @@ __device__ __forceinline__ void gemm_tile128(const T* __restrict__ A, int64_t ld
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = mfma(a[i], b[j], acc[i][j]);
     }
-    if (more) big_store<T, A_KC, B_KC>(sA + (buf ^ 1) * (kTK * kBP), sB + (buf ^ 1) * (kTK * kBP), ra, rb);
+    if (more) big_store<T, A_KC, B_KC>(sA + (buf ^ 1) * (TK * kBP), sB + (buf ^ 1) * (TK * kBP), ra, rb);
     __syncthreads();
     buf ^= 1;
   }
@@ -532,8 +544,8 @@ __global__ __launch_bounds__(kThreads) void k_update(DevSym S, LaunchList L, int
       if (rr < M && cc < N && gi >= gj) F[gi + (int64_t)gj * n] -= v;
     });
   } else {
-    __shared__ T sA[2 * kTK * kBP];
-    __shared__ T sB[2 * kTK * kBP];
+    __shared__ T sA[BigLds<T>::v];
+    __shared__ T sB[BigLds<T>::v];
     typename V4<T>::type acc[4][4];
     zero_acc128<T>(acc);
     gemm_tile128<T, false, false>(F + row0 + (int64_t)klo * n, n, F + col0 + (int64_t)klo * n, n, M, N,
@@ -558,17 +570,22 @@ __global__ __launch_bounds__(kThreads) void k_copy_L(DevSym S, LaunchList L, Num
 }
 
 // per-block log det = 2 sum log L^_jj - 2 ln2 sum e_i (equilibration exponents), summed
-// in a fixed order (per-thread strided partial sums, then a binary tree)
+// in a fixed order: work-group (block, g) reduces its share of the block's pivots
+// (strided per-thread sums, then a binary tree); a second pass adds the kLdParts partials
+constexpr int kLdParts = 64;
 __global__ __launch_bounds__(kThreads) void k_logdet(const int64_t* __restrict__ bptr,
                                                      const int32_t* __restrict__ bpiv,
                                                      const int32_t* __restrict__ perm,
                                                      const double* __restrict__ piv,
                                                      const int32_t* __restrict__ sexp,
-                                                     double* __restrict__ out) {
+                                                     double* __restrict__ part) {
   __shared__ double red[kThreads];
-  const int b = blockIdx.x;
+  const int b = blockIdx.x / kLdParts, g = blockIdx.x % kLdParts;
+  const int64_t q0 = bptr[b], len = bptr[b + 1] - q0;
+  const int64_t per = (len + kLdParts - 1) / kLdParts;
+  const int64_t lo = q0 + per * g, hi = min(bptr[b + 1], lo + per);
   double acc = 0.0;
-  for (int64_t q = bptr[b] + threadIdx.x; q < bptr[b + 1]; q += kThreads) {
+  for (int64_t q = lo + threadIdx.x; q < hi; q += kThreads) {
     const int32_t j = bpiv[q];
     acc += 2.0 * log(piv[j]) - 2.0 * 0.69314718055994530942 * (double)sexp[perm[j]];
   }
@@ -578,7 +595,15 @@ __global__ __launch_bounds__(kThreads) void k_logdet(const int64_t* __restrict__
     if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
     __syncthreads();
   }
-  if (threadIdx.x == 0) out[b] = red[0];
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ void k_logdet_final(int64_t nblocks, const double* __restrict__ part, double* __restrict__ out) {
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nblocks) return;
+  double acc = 0.0;
+  for (int g = 0; g < kLdParts; ++g) acc += part[b * kLdParts + g];
+  out[b] = acc;
 }
 
 // ------------------------------------------------------------------ solve kernels
@@ -610,163 +635,169 @@ __global__ __launch_bounds__(kThreads) void k_fvec_extend(DevSym S, LaunchList L
   }
 }
 
-// x_blk = Linv * v_blk
+// ---- solves blocked by 256-wide outer blocks ----
+// Forward, one work-group per front and outer block t (left to right):
+// x_K = Linv_KK v_K with the stored inverse of the 256-wide diagonal block; x is written
+// to the front vector and to the pivot-order vector.
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_fwd_diag(DevSym S, LaunchList L, int step, const T* __restrict__ D,
-                                                       SolveBufs V) {
-  __shared__ double xv[kNB * 16];
+__global__ __launch_bounds__(kThreads) void k_fwd_block(DevSym S, LaunchList L, int t, const T* __restrict__ D2,
+                                                        const int64_t* __restrict__ D2off, SolveBufs V) {
+  __shared__ double xv[kNB2 * 16];
   const int s = L.fronts[blockIdx.x];
   const int n = fn(S, s), p = fp(S, s);
-  const int k0 = step * kNB, kb = min(kNB, p - k0);
-  double* v = V.Vcur + S.Voff[s] * V.nrhs;
-  const T* Li = D + S.Doff[s] + (int64_t)step * kNB * kNB;
-  for (int idx = threadIdx.x; idx < kb * V.nrhs; idx += blockDim.x) {
-    const int i = idx % kb, r = idx / kb;
-    xv[i + r * kNB] = v[k0 + i + r * n];
+  const int nr = V.nrhs;
+  const int k2 = t * kNB2, kb2 = min(kNB2, p - k2);
+  double* v = V.Vcur + S.Voff[s] * nr;
+  const T* X = D2 + D2off[s] + (int64_t)t * kNB2 * kNB2;
+  for (int idx = threadIdx.x; idx < kb2 * nr; idx += kThreads) {
+    const int i = idx % kb2, r = idx / kb2;
+    xv[i + r * kNB2] = v[k2 + i + r * n];
   }
   __syncthreads();
-  for (int idx = threadIdx.x; idx < kb * V.nrhs; idx += blockDim.x) {
-    const int i = idx % kb, r = idx / kb;
+  for (int idx = threadIdx.x; idx < kb2 * nr; idx += kThreads) {
+    const int i = idx % kb2, r = idx / kb2;
     double acc = 0.0;
-    for (int l = 0; l <= i; ++l) acc += (double)Li[i + l * kNB] * xv[l + r * kNB];
-    v[k0 + i + r * n] = acc;
-    V.xp[S.sfirst[s] + k0 + i + (int64_t)r * S.n] = acc;
+    for (int l = 0; l <= i; ++l) acc += (double)X[i + (int64_t)l * kb2] * xv[l + r * kNB2];
+    v[k2 + i + r * n] = acc;
+    V.xp[S.sfirst[s] + k2 + i + (int64_t)r * S.n] = acc;
   }
 }
 
-// v[rows below block] -= L[rows, blk] * x_blk
+// Forward, rows below outer block t: v[rows] -= L[rows, K] x_K; 64 rows per work-group,
+// the 256 columns split over the 4 waves and reduced through LDS.
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_fwd_update(DevSym S, LaunchList L, int step, const T* __restrict__ Lp,
-                                                         SolveBufs V) {
-  __shared__ double xv[kNB * 16];
+__global__ __launch_bounds__(kThreads) void k_fwd_outer(DevSym S, LaunchList L, int t, const T* __restrict__ Lp,
+                                                        SolveBufs V) {
+  __shared__ double xs[kNB2 * 16];
+  __shared__ double red[4][64][17];
   int fi; int64_t loc;
   find_front(L, wg_id(), fi, loc);
   const int s = L.fronts[fi];
   const int n = fn(S, s), p = fp(S, s);
-  const int k0 = step * kNB, kb = min(kNB, p - k0);
-  const int row0 = k0 + kb + kTile * (int)loc;
-  double* v = V.Vcur + S.Voff[s] * V.nrhs;
-  for (int idx = threadIdx.x; idx < kb * V.nrhs; idx += blockDim.x) {
-    const int i = idx % kb, r = idx / kb;
-    xv[i + r * kNB] = v[k0 + i + r * n];
+  const int nr = V.nrhs;
+  const int k2 = t * kNB2, kb2 = min(kNB2, p - k2);
+  double* v = V.Vcur + S.Voff[s] * nr;
+  for (int idx = threadIdx.x; idx < kb2 * nr; idx += kThreads) {
+    const int i = idx % kb2, r = idx / kb2;
+    xs[i + r * kNB2] = v[k2 + i + r * n];
   }
   __syncthreads();
-  const int i = threadIdx.x & 63, rg = threadIdx.x >> 6;
-  const int row = row0 + i;
+  const int i = threadIdx.x & 63, cg = threadIdx.x >> 6;
+  const int row = k2 + kb2 + 64 * (int)loc + i;
+  double acc[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) acc[r] = 0.0;
   if (row < n) {
-    const T* Lc = Lp + S.Loff[s] + row + (int64_t)k0 * n;
-    for (int r = rg; r < V.nrhs; r += 4) {
-      double acc = 0.0;
-      for (int c = 0; c < kb; ++c) acc += (double)Lc[(int64_t)c * n] * xv[c + r * kNB];
-      v[row + r * n] -= acc;
+    const T* Lr = Lp + S.Loff[s] + row + (int64_t)k2 * n;
+    for (int c = cg * 64; c < min(kb2, cg * 64 + 64); ++c) {
+      const double l = (double)Lr[(int64_t)c * n];
+#pragma unroll
+      for (int r = 0; r < 16; ++r)
+        if (r < nr) acc[r] += l * xs[c + r * kNB2];
     }
   }
+#pragma unroll
+  for (int r = 0; r < 16; ++r)
+    if (r < nr) red[cg][i][r] = acc[r];
+  __syncthreads();
+  if (cg == 0 && row < n) {
+    for (int r = 0; r < nr; ++r)
+      v[row + r * n] -= (red[0][i][r] + red[1][i][r]) + (red[2][i][r] + red[3][i][r]);
+  }
 }
 
-// r_S = y_S - L_RS^T x_R for a 64-column block of S; x_R gathered from the pivot vector
+// Backward split-K partials for outer block t (from the right): work-group (front,
+// chunk of 256 rows below the block) computes part = L[chunk, K]^T x[chunk] (256 x nrhs)
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_bwd_init(DevSym S, LaunchList L, const T* __restrict__ Lp,
-                                                       SolveBufs V) {
-  __shared__ double Ls[kTile][kTile + 1];
-  __shared__ double Xs[kTile][17];
+__global__ __launch_bounds__(kThreads) void k_bwd_part(DevSym S, LaunchList L, int t, const T* __restrict__ Lp,
+                                                       SolveBufs V, double* __restrict__ part) {
+  __shared__ T Ls[32][kNB2 + 1];
+  __shared__ double Xs[32][17];
   int fi; int64_t loc;
   find_front(L, wg_id(), fi, loc);
   const int s = L.fronts[fi];
   const int n = fn(S, s), p = fp(S, s);
-  const int j0 = kNB * (int)loc, jb = min(kNB, p - j0);
-  const int64_t f0 = S.sfirst[s];
+  const int nr = V.nrhs;
+  const int nK = (p + kNB2 - 1) / kNB2, K = nK - 1 - t;
+  const int k2 = K * kNB2, kb2 = min(kNB2, p - k2);
+  const int rs = k2 + kb2;
+  const int r0 = rs + 256 * (int)loc, r1 = min(n, r0 + 256);
   const int32_t* rows = S.rows + S.rowptr[s];
   const T* Lf = Lp + S.Loff[s];
-  const int t = threadIdx.x;
-  const int c = t & 63, rg = t >> 6;
-  double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int i0 = p; i0 < n; i0 += kTile) {
-    const int mi = min(kTile, n - i0);
-    for (int idx = t; idx < kTile * kTile; idx += kThreads) {
-      const int ii = idx & 63, jj = idx >> 6;
-      Ls[ii][jj] = (ii < mi && jj < jb) ? (double)Lf[(i0 + ii) + (int64_t)(j0 + jj) * n] : 0.0;
+  const int c = threadIdx.x;
+  double acc[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) acc[r] = 0.0;
+  for (int i0 = r0; i0 < r1; i0 += 32) {
+    const int mi = min(32, r1 - i0);
+    for (int idx = threadIdx.x; idx < 32 * kNB2; idx += kThreads) {
+      const int ii = idx & 31, cc = idx >> 5;
+      Ls[ii][cc] = (ii < mi && cc < kb2) ? Lf[(i0 + ii) + (int64_t)(k2 + cc) * n] : T(0);
     }
-    for (int idx = t; idx < kTile * V.nrhs; idx += kThreads) {
-      const int ii = idx & 63, r = idx >> 6;
+    for (int idx = threadIdx.x; idx < 32 * nr; idx += kThreads) {
+      const int ii = idx & 31, r = idx >> 5;
       Xs[ii][r] = ii < mi ? V.xp[rows[i0 + ii] + (int64_t)r * S.n] : 0.0;
     }
     __syncthreads();
-    for (int q = 0; q < 4; ++q) {
-      const int r = rg + 4 * q;
-      if (r < V.nrhs) {
-        double a = 0.0;
-        for (int ii = 0; ii < mi; ++ii) a += Ls[ii][c] * Xs[ii][r];
-        acc[q] += a;
-      }
+    for (int ii = 0; ii < mi; ++ii) {
+      const double l = (double)Ls[ii][c];
+#pragma unroll
+      for (int r = 0; r < 16; ++r)
+        if (r < nr) acc[r] += l * Xs[ii][r];
     }
     __syncthreads();
   }
-  double* v = V.Vcur + S.Voff[s] * V.nrhs;
-  if (c < jb) {
-    for (int q = 0; q < 4; ++q) {
-      const int r = rg + 4 * q;
-      if (r < V.nrhs) v[j0 + c + r * n] = V.xp[f0 + j0 + c + (int64_t)r * S.n] - acc[q];
-    }
-  }
+  double* out = part + wg_id() * (int64_t)(kNB2 * 16);
+#pragma unroll
+  for (int r = 0; r < 16; ++r)
+    if (r < nr) out[c + r * kNB2] = acc[r];
 }
 
-// x_blk = Linv^T r_blk (block index counted from the right by `step`)
+// Backward, one work-group per front and outer block t (from the right):
+// r_K = y_K - sum of the partials, x_K = Linv_KK^T r_K, written to the pivot vector.
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_bwd_diag(DevSym S, LaunchList L, int step, const T* __restrict__ D,
-                                                       SolveBufs V) {
-  __shared__ double rv[kNB * 16];
-  const int s = L.fronts[blockIdx.x];
-  const int n = fn(S, s), p = fp(S, s);
-  const int nblk = (p + kNB - 1) / kNB;
-  const int k = nblk - 1 - step;
-  const int k0 = k * kNB, kb = min(kNB, p - k0);
-  double* v = V.Vcur + S.Voff[s] * V.nrhs;
-  const T* Li = D + S.Doff[s] + (int64_t)k * kNB * kNB;
-  for (int idx = threadIdx.x; idx < kb * V.nrhs; idx += blockDim.x) {
-    const int i = idx % kb, r = idx / kb;
-    rv[i + r * kNB] = v[k0 + i + r * n];
-  }
-  __syncthreads();
-  for (int idx = threadIdx.x; idx < kb * V.nrhs; idx += blockDim.x) {
-    const int i = idx % kb, r = idx / kb;
-    double acc = 0.0;
-    for (int l = i; l < kb; ++l) acc += (double)Li[l + i * kNB] * rv[l + r * kNB];
-    v[k0 + i + r * n] = acc;
-    V.xp[S.sfirst[s] + k0 + i + (int64_t)r * S.n] = acc;
-  }
-}
-
-// r_j -= L[blk rows, j cols]^T x_blk for every column block j left of the current block
-template <typename T>
-__global__ __launch_bounds__(kThreads) void k_bwd_update(DevSym S, LaunchList L, int step, const T* __restrict__ Lp,
-                                                         SolveBufs V) {
-  __shared__ double Ls[kTile][kTile + 1];
-  __shared__ double xv[kNB * 16];
-  int fi; int64_t loc;
-  find_front(L, wg_id(), fi, loc);
+__global__ __launch_bounds__(kThreads) void k_bwd_block(DevSym S, LaunchList L, LaunchList Lpart, int t,
+                                                        const T* __restrict__ D2, const int64_t* __restrict__ D2off,
+                                                        SolveBufs V, const double* __restrict__ part) {
+  __shared__ double rv[kNB2 * 16];
+  const int fi = blockIdx.x;
   const int s = L.fronts[fi];
-  const int n = fn(S, s), p = fp(S, s);
-  const int nblk = (p + kNB - 1) / kNB;
-  const int k = nblk - 1 - step;
-  const int k0 = k * kNB, kb = min(kNB, p - k0);
-  const int j0 = kNB * (int)loc;
-  double* v = V.Vcur + S.Voff[s] * V.nrhs;
-  const T* Lf = Lp + S.Loff[s];
-  const int t = threadIdx.x;
-  for (int idx = t; idx < kTile * kTile; idx += kThreads) {
-    const int ii = idx & 63, jj = idx >> 6;
-    Ls[ii][jj] = ii < kb ? (double)Lf[(k0 + ii) + (int64_t)(j0 + jj) * n] : 0.0;
-  }
-  for (int idx = t; idx < kb * V.nrhs; idx += kThreads) {
-    const int i = idx % kb, r = idx / kb;
-    xv[i + r * kNB] = v[k0 + i + r * n];
+  const int p = fp(S, s);
+  const int nr = V.nrhs;
+  const int nK = (p + kNB2 - 1) / kNB2, K = nK - 1 - t;
+  const int k2 = K * kNB2, kb2 = min(kNB2, p - k2);
+  const int64_t f0 = S.sfirst[s];
+  const int64_t q0 = Lpart.prefix[fi], q1 = Lpart.prefix[fi + 1];
+  const T* X = D2 + D2off[s] + (int64_t)K * kNB2 * kNB2;
+  for (int idx = threadIdx.x; idx < kb2 * nr; idx += kThreads) {
+    const int i = idx % kb2, r = idx / kb2;
+    double sp = 0.0;
+    for (int64_t q = q0; q < q1; ++q) sp += part[q * (kNB2 * 16) + i + r * kNB2];
+    rv[i + r * kNB2] = V.xp[f0 + k2 + i + (int64_t)r * S.n] - sp;
   }
   __syncthreads();
-  const int c = t & 63, rg = t >> 6;
-  for (int r = rg; r < V.nrhs; r += 4) {
-    double a = 0.0;
-    for (int ii = 0; ii < kb; ++ii) a += Ls[ii][c] * xv[ii + r * kNB];
-    v[j0 + c + r * n] -= a;
+  // x_i = sum_{l >= i} X[l][i] r_l: column i of X is contiguous, so one wave sweeps it with
+  // coalesced loads and reduces across its lanes
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int i = wv; i < kb2; i += kThreads / 64) {
+    const T* Xc = X + (int64_t)i * kb2;
+    double acc[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[r] = 0.0;
+    for (int l = i + lane; l < kb2; l += 64) {
+      const double xv = (double)Xc[l];
+#pragma unroll
+      for (int r = 0; r < 16; ++r)
+        if (r < nr) acc[r] += xv * rv[l + r * kNB2];
+    }
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      if (r < nr) {
+        double a = acc[r];
+        for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off, 64);
+        if (lane == 0) V.xp[f0 + k2 + i + (int64_t)r * S.n] = a;
+      }
+    }
   }
 }
 
@@ -871,117 +902,6 @@ __global__ __launch_bounds__(kThreads) void k_sel_gather(DevSym S, LaunchList L,
   for (int a = threadIdx.x; a < u; a += blockDim.x) dst[a] = src[rel[a]];
 }
 
-// Y = L[R', blk] * Linv  (R' = rows after the block), stored with ld n_s from row 0
-template <typename T>
-__global__ __launch_bounds__(kThreads) void k_sel_Y(DevSym S, LaunchList L, int step, SelBufs<T> B) {
-  __shared__ T sA[kTK * kP];
-  __shared__ T sB[kTK * kP];
-  int fi; int64_t loc;
-  find_front(L, wg_id(), fi, loc);
-  const int s = L.fronts[fi];
-  const int n = fn(S, s), p = fp(S, s);
-  const int nblk = (p + kNB - 1) / kNB;
-  const int k = nblk - 1 - step;
-  const int k0 = k * kNB, kb = min(kNB, p - k0);
-  const int rs = k0 + kb;
-  const int row0 = rs + kTile * (int)loc;
-  const int M = min(kTile, n - row0);
-  const T* Lf = B.L + S.Loff[s];
-  const T* Dblk = B.D + S.Doff[s] + (int64_t)k * kNB * kNB;
-  typename V4<T>::type acc[2][2];
-  zero_acc<T>(acc);
-  gemm_tile<T, false, true>(Lf + row0 + (int64_t)k0 * n, n, Dblk, kNB, M, kb, kb, acc, sA, sB);
-  T* Y = B.Y + S.Voff[s] * kNB;
-  for_acc<T>(acc, [&](int r, int c, T v) {
-    if (r < M && c < kb) Y[(row0 - rs + r) + (int64_t)c * n] = v;
-  });
-}
-
-// Sigma[R', blk] = -Sigma[R', R'] Y, mirrored into Sigma[blk, R']
-template <typename T>
-__global__ __launch_bounds__(kThreads) void k_sel_gemm(DevSym S, LaunchList L, int step, SelBufs<T> B) {
-  __shared__ T sA[kTK * kP];
-  __shared__ T sB[kTK * kP];
-  int fi; int64_t loc;
-  find_front(L, wg_id(), fi, loc);
-  const int s = L.fronts[fi];
-  const int n = fn(S, s), p = fp(S, s);
-  const int nblk = (p + kNB - 1) / kNB;
-  const int k = nblk - 1 - step;
-  const int k0 = k * kNB, kb = min(kNB, p - k0);
-  const int rs = k0 + kb;
-  const int row0 = rs + kTile * (int)loc;
-  const int M = min(kTile, n - row0);
-  T* Sf = B.Scur + S.Woff[s];
-  const T* Y = B.Y + S.Voff[s] * kNB;
-  typename V4<T>::type acc[2][2];
-  zero_acc<T>(acc);
-  gemm_tile<T, false, true>(Sf + row0 + (int64_t)rs * n, n, Y, n, M, kb, n - rs, acc, sA, sB);
-  for_acc<T>(acc, [&](int r, int c, T v) {
-    if (r < M && c < kb) {
-      Sf[(row0 + r) + (int64_t)(k0 + c) * n] = -v;
-      Sf[(k0 + c) + (int64_t)(row0 + r) * n] = -v;
-    }
-  });
-}
-
-// partial[wg] = Y[chunk]^T Sigma[chunk, blk]  (kChunk rows of R' per work-group)
-template <typename T>
-__global__ __launch_bounds__(kThreads) void k_sel_diag_partial(DevSym S, LaunchList L, int step, SelBufs<T> B) {
-  __shared__ T sA[kTK * kP];
-  __shared__ T sB[kTK * kP];
-  int fi; int64_t loc;
-  find_front(L, wg_id(), fi, loc);
-  const int s = L.fronts[fi];
-  const int n = fn(S, s), p = fp(S, s);
-  const int nblk = (p + kNB - 1) / kNB;
-  const int k = nblk - 1 - step;
-  const int k0 = k * kNB, kb = min(kNB, p - k0);
-  const int rs = k0 + kb;
-  const int r0 = kChunk * (int)loc;               // offset inside R'
-  const int kr = max(0, min(kChunk, n - rs - r0));
-  const T* Sf = B.Scur + S.Woff[s];
-  const T* Y = B.Y + S.Voff[s] * kNB;
-  typename V4<T>::type acc[2][2];
-  zero_acc<T>(acc);
-  if (kr > 0)
-    gemm_tile<T, true, true>(Y + r0, n, Sf + (rs + r0) + (int64_t)k0 * n, n, kb, kb, kr, acc, sA, sB);
-  T* out = B.part + wg_id() * (kNB * kNB);
-  for_acc<T>(acc, [&](int r, int c, T v) { out[r + c * kNB] = v; });
-}
-
-// Sigma[blk, blk] = Linv^T Linv - sum of the partials (fixed order)
-template <typename T>
-__global__ __launch_bounds__(kThreads) void k_sel_diag_finish(DevSym S, LaunchList L, LaunchList Lpart, int step,
-                                                              SelBufs<T> B) {
-  __shared__ double Li[kNB][kNB + 1];
-  const int fi = blockIdx.x;
-  const int s = L.fronts[fi];
-  const int n = fn(S, s), p = fp(S, s);
-  const int nblk = (p + kNB - 1) / kNB;
-  const int k = nblk - 1 - step;
-  const int k0 = k * kNB, kb = min(kNB, p - k0);
-  const T* Dblk = B.D + S.Doff[s] + (int64_t)k * kNB * kNB;
-  for (int idx = threadIdx.x; idx < kNB * kNB; idx += kThreads) {
-    const int i = idx & 63, j = idx >> 6;
-    Li[i][j] = (double)Dblk[i + j * kNB];
-  }
-  __syncthreads();
-  T* Sf = B.Scur + S.Woff[s];
-  const int64_t q0 = Lpart.prefix[fi], q1 = Lpart.prefix[fi + 1];
-  for (int idx = threadIdx.x; idx < kb * kb; idx += kThreads) {
-    const int i = idx % kb, j = idx / kb;
-    if (i < j) continue;
-    double a = 0.0;
-    for (int l = i; l < kb; ++l) a += Li[l][i] * Li[l][j];
-    double sp = 0.0;
-    for (int64_t q = q0; q < q1; ++q) sp += (double)B.part[q * (kNB * kNB) + i + j * kNB];
-    const T v = (T)(a - sp);
-    Sf[(k0 + i) + (int64_t)(k0 + j) * n] = v;
-    Sf[(k0 + j) + (int64_t)(k0 + i) * n] = v;
-  }
-}
-
 // ---- two-level selected inversion: 256-wide outer blocks K (counted from the right) ----
 // For the outer block K of front s with rows after it R' (n' = n - k2 - kb2 rows):
 //   X = L[R', K] Linv_KK,  Sigma[R', K] = -Sigma[R', R'] X,
@@ -1000,44 +920,45 @@ __device__ __forceinline__ OuterBlk outer_blk(int p, int n, int step) {
   return o;
 }
 
-// Linv_KK from the 64-block inverses: column block j of X = L_KK^-1 satisfies
-// X_jj = Linv_jj and X_ij = -Linv_ii sum_{j<=l<i} L_il X_lj for i > j.  One work-group
-// per (front, column block j); X is stored column-major with ld kb2 at D2 + D2off[s] +
-// K * 256^2 (zeros above the diagonal).
+// Inverse of every 256-wide outer diagonal block, Linv_KK = L_KK^-1, from the 64-block
+// inverses: column block j of X = L_KK^-1 has X_jj = Linv_jj and
+// X_ij = -Linv_ii sum_{j<=l<i} L_il X_lj for i > j.  One work-group per (front, 64-block
+// b), b = 4 K + j; X is column-major with ld kb2 at D2 + D2off[s] + K * 256^2 (zeros
+// above the diagonal).  `base` selects where L lives: the square front (during the
+// factorisation) or the L panel storage; both have leading dimension n_s.
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_sel_inv256(DevSym S, LaunchList L, int step, SelBufs<T> B,
-                                                         const int64_t* __restrict__ D2off, T* __restrict__ D2) {
+__global__ __launch_bounds__(kThreads) void k_inv256(DevSym S, LaunchList L, const T* __restrict__ Lbase,
+                                                     int from_front, const T* __restrict__ Dinv,
+                                                     const int64_t* __restrict__ D2off, T* __restrict__ D2) {
   __shared__ T sA[kTK * kP];
   __shared__ T sB[kTK * kP];
   int fi; int64_t loc;
   find_front(L, wg_id(), fi, loc);
   const int s = L.fronts[fi];
   const int n = fn(S, s), p = fp(S, s);
-  const OuterBlk o = outer_blk(p, n, step);
-  const int j = (int)loc;
-  const int kb2 = o.kb2;
+  const int K = (int)(loc / kSub), j = (int)(loc % kSub);
+  const int k2 = K * kNB2, kb2 = min(kNB2, p - k2);
+  const int nsub = (kb2 + kNB - 1) / kNB;
   const int sbj = min(kNB, kb2 - kNB * j);
-  T* X = D2 + D2off[s] + (int64_t)o.K * kNB2 * kNB2;
-  const T* Lf = B.L + S.Loff[s];
-  const int blk0 = o.k2 / kNB;
-  // column block j: zero, then the diagonal block
+  T* X = D2 + D2off[s] + (int64_t)K * kNB2 * kNB2;
+  const T* Lf = Lbase + (from_front ? S.Woff[s] : S.Loff[s]);
+  const int blk0 = k2 / kNB;
   for (int idx = threadIdx.x; idx < kb2 * kNB; idx += kThreads) {
     const int r = idx % kb2, c = idx / kb2;
     if (c < sbj) {
       T v = T(0);
       if (r >= kNB * j && r < kNB * j + sbj)
-        v = B.D[S.Doff[s] + (int64_t)(blk0 + j) * kNB * kNB + (r - kNB * j) + c * kNB];
+        v = Dinv[S.Doff[s] + (int64_t)(blk0 + j) * kNB * kNB + (r - kNB * j) + c * kNB];
       X[r + (int64_t)(kNB * j + c) * kb2] = v;
     }
   }
   __threadfence();
   __syncthreads();
-  for (int i = j + 1; i < o.nsub; ++i) {
+  for (int i = j + 1; i < nsub; ++i) {
     const int sbi = min(kNB, kb2 - kNB * i);
     typename V4<T>::type acc[2][2];
     zero_acc<T>(acc);
-    // T_ij = sum_{l=j}^{i-1} L_il X_lj  (K = 64 (i - j))
-    gemm_tile<T, false, true>(Lf + (o.k2 + kNB * i) + (int64_t)(o.k2 + kNB * j) * n, n,
+    gemm_tile<T, false, true>(Lf + (k2 + kNB * i) + (int64_t)(k2 + kNB * j) * n, n,
                               X + kNB * j + (int64_t)(kNB * j) * kb2, kb2, sbi, sbj, kNB * (i - j), acc, sA, sB);
     T* Xij = X + kNB * i + (int64_t)(kNB * j) * kb2;
     for_acc<T>(acc, [&](int r, int c, T v) {
@@ -1046,7 +967,7 @@ __global__ __launch_bounds__(kThreads) void k_sel_inv256(DevSym S, LaunchList L,
     __threadfence();
     __syncthreads();
     zero_acc<T>(acc);
-    gemm_tile<T, false, true>(B.D + S.Doff[s] + (int64_t)(blk0 + i) * kNB * kNB, kNB, Xij, kb2, sbi, sbj, sbi,
+    gemm_tile<T, false, true>(Dinv + S.Doff[s] + (int64_t)(blk0 + i) * kNB * kNB, kNB, Xij, kb2, sbi, sbj, sbi,
                               acc, sA, sB);
     __syncthreads();
     for_acc<T>(acc, [&](int r, int c, T v) {
@@ -1061,8 +982,8 @@ __global__ __launch_bounds__(kThreads) void k_sel_inv256(DevSym S, LaunchList L,
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_sel_Y2(DevSym S, LaunchList L, int step, SelBufs<T> B,
                                                      const int64_t* __restrict__ D2off, const T* __restrict__ D2) {
-  __shared__ T sA[2 * kTK * kBP];
-  __shared__ T sB[2 * kTK * kBP];
+  __shared__ T sA[BigLds<T>::v];
+  __shared__ T sB[BigLds<T>::v];
   int fi; int64_t loc;
   find_front(L, wg_id(), fi, loc);
   const int s = L.fronts[fi];
@@ -1086,8 +1007,8 @@ __global__ __launch_bounds__(kThreads) void k_sel_Y2(DevSym S, LaunchList L, int
 // Sigma[R', K] = -Sigma[R', R'] Y, mirrored into Sigma[K, R']; 128x128 tiles
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_sel_gemm2(DevSym S, LaunchList L, int step, SelBufs<T> B) {
-  __shared__ T sA[2 * kTK * kBP];
-  __shared__ T sB[2 * kTK * kBP];
+  __shared__ T sA[BigLds<T>::v];
+  __shared__ T sB[BigLds<T>::v];
   int fi; int64_t loc;
   find_front(L, wg_id(), fi, loc);
   const int s = L.fronts[fi];
@@ -1284,8 +1205,11 @@ template <typename T> void launch_copy_L(hipStream_t st, const DevSym& S, const 
   hipLaunchKernelGGL(k_copy_L<T>, dim3((unsigned)L.total), dim3(kThreads), 0, st, S, L, B);
 }
 void launch_logdet(hipStream_t st, int64_t nblocks, const int64_t* bptr, const int32_t* bpiv,
-                   const int32_t* perm, const double* piv, const int32_t* sexp, double* out) {
-  hipLaunchKernelGGL(k_logdet, dim3((unsigned)nblocks), dim3(kThreads), 0, st, bptr, bpiv, perm, piv, sexp, out);
+                   const int32_t* perm, const double* piv, const int32_t* sexp, double* part, double* out) {
+  hipLaunchKernelGGL(k_logdet, dim3((unsigned)(nblocks * kLdParts)), dim3(kThreads), 0, st, bptr, bpiv, perm, piv,
+                     sexp, part);
+  hipLaunchKernelGGL(k_logdet_final, dim3((unsigned)((nblocks + kThreads - 1) / kThreads)), dim3(kThreads), 0, st,
+                     nblocks, (const double*)part, out);
 }
 
 template <typename T> void launch_fvec_init(hipStream_t st, const DevSym& S, const LaunchList& L, SolveBufs V) {
@@ -1297,30 +1221,33 @@ template <typename T> void launch_fvec_extend(hipStream_t st, const DevSym& S, c
   if (L.count <= 0) return;
   hipLaunchKernelGGL(k_fvec_extend<T>, dim3((unsigned)L.count), dim3(kThreads), 0, st, S, L, slot, V);
 }
-template <typename T> void launch_fwd_diag(hipStream_t st, const DevSym& S, const LaunchList& L, int step,
-                                           const T* D, SolveBufs V) {
+template <typename T> void launch_fwd_block(hipStream_t st, const DevSym& S, const LaunchList& L, int t,
+                                            const T* D2, const int64_t* D2off, SolveBufs V) {
   if (L.count <= 0) return;
-  hipLaunchKernelGGL(k_fwd_diag<T>, dim3((unsigned)L.count), dim3(kThreads), 0, st, S, L, step, D, V);
+  hipLaunchKernelGGL(k_fwd_block<T>, dim3((unsigned)L.count), dim3(kThreads), 0, st, S, L, t, D2, D2off, V);
 }
-template <typename T> void launch_fwd_update(hipStream_t st, const DevSym& S, const LaunchList& L, int step,
-                                             const T* Lp, SolveBufs V) {
+template <typename T> void launch_inv256(hipStream_t st, const DevSym& S, const LaunchList& L, const T* Lbase,
+                                         int from_front, const T* Dinv, const int64_t* D2off, T* D2) {
   if (L.total <= 0) return;
-  hipLaunchKernelGGL(k_fwd_update<T>, dim3((unsigned)L.total), dim3(kThreads), 0, st, S, L, step, Lp, V);
+  hipLaunchKernelGGL(k_inv256<T>, dim3((unsigned)L.total), dim3(kThreads), 0, st, S, L, Lbase, from_front, Dinv,
+                     D2off, D2);
 }
-template <typename T> void launch_bwd_init(hipStream_t st, const DevSym& S, const LaunchList& L, const T* Lp,
-                                           SolveBufs V) {
+template <typename T> void launch_fwd_outer(hipStream_t st, const DevSym& S, const LaunchList& L, int t,
+                                            const T* Lp, SolveBufs V) {
   if (L.total <= 0) return;
-  hipLaunchKernelGGL(k_bwd_init<T>, dim3((unsigned)L.total), dim3(kThreads), 0, st, S, L, Lp, V);
+  hipLaunchKernelGGL(k_fwd_outer<T>, dim3((unsigned)L.total), dim3(kThreads), 0, st, S, L, t, Lp, V);
 }
-template <typename T> void launch_bwd_diag(hipStream_t st, const DevSym& S, const LaunchList& L, int step,
-                                           const T* D, SolveBufs V) {
+template <typename T> void launch_bwd_part(hipStream_t st, const DevSym& S, const LaunchList& L, int t,
+                                           const T* Lp, SolveBufs V, double* part) {
+  if (L.total <= 0) return;
+  hipLaunchKernelGGL(k_bwd_part<T>, dim3((unsigned)L.total), dim3(kThreads), 0, st, S, L, t, Lp, V, part);
+}
+template <typename T> void launch_bwd_block(hipStream_t st, const DevSym& S, const LaunchList& L,
+                                            const LaunchList& Lpart, int t, const T* D2, const int64_t* D2off,
+                                            SolveBufs V, const double* part) {
   if (L.count <= 0) return;
-  hipLaunchKernelGGL(k_bwd_diag<T>, dim3((unsigned)L.count), dim3(kThreads), 0, st, S, L, step, D, V);
-}
-template <typename T> void launch_bwd_update(hipStream_t st, const DevSym& S, const LaunchList& L, int step,
-                                             const T* Lp, SolveBufs V) {
-  if (L.total <= 0) return;
-  hipLaunchKernelGGL(k_bwd_update<T>, dim3((unsigned)L.total), dim3(kThreads), 0, st, S, L, step, Lp, V);
+  hipLaunchKernelGGL(k_bwd_block<T>, dim3((unsigned)L.count), dim3(kThreads), 0, st, S, L, Lpart, t, D2, D2off, V,
+                     part);
 }
 void launch_permute_in(hipStream_t st, int64_t n, int nrhs, const int32_t* perm, const double* scale,
                        const double* src, int64_t lds, double* xp) {
@@ -1356,31 +1283,6 @@ template <typename T> void launch_sel_gather(hipStream_t st, const DevSym& S, co
                                              const int32_t* sparent, SelBufs<T> B) {
   if (L.total <= 0) return;
   hipLaunchKernelGGL(k_sel_gather<T>, dim3((unsigned)L.total), dim3(kThreads), 0, st, S, L, sparent, B);
-}
-template <typename T> void launch_sel_diag_finish(hipStream_t st, const DevSym& S, const LaunchList& L,
-                                                  const LaunchList& Lpart, int step, SelBufs<T> B) {
-  if (L.count <= 0) return;
-  hipLaunchKernelGGL(k_sel_diag_finish<T>, dim3((unsigned)L.count), dim3(kThreads), 0, st, S, L, Lpart, step, B);
-}
-template <typename T> void launch_sel_Y(hipStream_t st, const DevSym& S, const LaunchList& L, int step,
-                                        SelBufs<T> B) {
-  if (L.total <= 0) return;
-  hipLaunchKernelGGL(k_sel_Y<T>, dim3((unsigned)L.total), dim3(kThreads), 0, st, S, L, step, B);
-}
-template <typename T> void launch_sel_gemm(hipStream_t st, const DevSym& S, const LaunchList& L, int step,
-                                           SelBufs<T> B) {
-  if (L.total <= 0) return;
-  hipLaunchKernelGGL(k_sel_gemm<T>, dim3((unsigned)L.total), dim3(kThreads), 0, st, S, L, step, B);
-}
-template <typename T> void launch_sel_diag_partial(hipStream_t st, const DevSym& S, const LaunchList& L, int step,
-                                                   SelBufs<T> B) {
-  if (L.total <= 0) return;
-  hipLaunchKernelGGL(k_sel_diag_partial<T>, dim3((unsigned)L.total), dim3(kThreads), 0, st, S, L, step, B);
-}
-template <typename T> void launch_sel_inv256(hipStream_t st, const DevSym& S, const LaunchList& L, int step,
-                                             SelBufs<T> B, const int64_t* D2off, T* D2) {
-  if (L.total <= 0) return;
-  hipLaunchKernelGGL(k_sel_inv256<T>, dim3((unsigned)L.total), dim3(kThreads), 0, st, S, L, step, B, D2off, D2);
 }
 template <typename T> void launch_sel_Y2(hipStream_t st, const DevSym& S, const LaunchList& L, int step,
                                          SelBufs<T> B, const int64_t* D2off, const T* D2) {
@@ -1427,17 +1329,12 @@ template <typename T> void launch_sel_pattern(hipStream_t st, int64_t cnt, const
   template void launch_copy_L<T>(hipStream_t, const DevSym&, const LaunchList&, NumBufs<T>);         \
   template void launch_fvec_init<T>(hipStream_t, const DevSym&, const LaunchList&, SolveBufs);       \
   template void launch_fvec_extend<T>(hipStream_t, const DevSym&, const LaunchList&, int, SolveBufs); \
-  template void launch_fwd_diag<T>(hipStream_t, const DevSym&, const LaunchList&, int, const T*, SolveBufs); \
-  template void launch_fwd_update<T>(hipStream_t, const DevSym&, const LaunchList&, int, const T*, SolveBufs); \
-  template void launch_bwd_init<T>(hipStream_t, const DevSym&, const LaunchList&, const T*, SolveBufs); \
-  template void launch_bwd_diag<T>(hipStream_t, const DevSym&, const LaunchList&, int, const T*, SolveBufs); \
-  template void launch_bwd_update<T>(hipStream_t, const DevSym&, const LaunchList&, int, const T*, SolveBufs); \
+  template void launch_fwd_block<T>(hipStream_t, const DevSym&, const LaunchList&, int, const T*, const int64_t*, SolveBufs); \
+  template void launch_fwd_outer<T>(hipStream_t, const DevSym&, const LaunchList&, int, const T*, SolveBufs); \
+  template void launch_bwd_part<T>(hipStream_t, const DevSym&, const LaunchList&, int, const T*, SolveBufs, double*); \
+  template void launch_bwd_block<T>(hipStream_t, const DevSym&, const LaunchList&, const LaunchList&, int, const T*, const int64_t*, SolveBufs, const double*); \
   template void launch_sel_gather<T>(hipStream_t, const DevSym&, const LaunchList&, const int32_t*, SelBufs<T>); \
-  template void launch_sel_Y<T>(hipStream_t, const DevSym&, const LaunchList&, int, SelBufs<T>);     \
-  template void launch_sel_gemm<T>(hipStream_t, const DevSym&, const LaunchList&, int, SelBufs<T>);  \
-  template void launch_sel_diag_partial<T>(hipStream_t, const DevSym&, const LaunchList&, int, SelBufs<T>); \
-  template void launch_sel_diag_finish<T>(hipStream_t, const DevSym&, const LaunchList&, const LaunchList&, int, SelBufs<T>); \
-  template void launch_sel_inv256<T>(hipStream_t, const DevSym&, const LaunchList&, int, SelBufs<T>, const int64_t*, T*); \
+  template void launch_inv256<T>(hipStream_t, const DevSym&, const LaunchList&, const T*, int, const T*, const int64_t*, T*); \
   template void launch_sel_Y2<T>(hipStream_t, const DevSym&, const LaunchList&, int, SelBufs<T>, const int64_t*, const T*); \
   template void launch_sel_gemm2<T>(hipStream_t, const DevSym&, const LaunchList&, int, SelBufs<T>); \
   template void launch_sel_part2<T>(hipStream_t, const DevSym&, const LaunchList&, int, SelBufs<T>); \
