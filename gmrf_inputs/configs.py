@@ -221,3 +221,29 @@ def standard_normal_f32(n: int, k: int, seed: int) -> np.ndarray:
     """z ~ N(0, I) as float32, shape (n, k) column-major (Fortran order)."""
     rng = rng_for(seed)
     return np.asfortranarray(rng.standard_normal((n, k)).astype(np.float32))
+
+
+def matern_pieces(problem: Problem):
+    """Lumped mass, stiffness and S M~^-1 S placed on the stored pattern of a Matern
+    problem's Q (arrays aligned with Q.data), from which the Matern precision of any
+    (kappa, tau) is tau^-2 (kappa^4 M~ + 2 kappa^2 S + S M~^-1 S)."""
+    meta = problem.meta
+    K, m = meta["K"], meta["m"]
+    S = (K - sp.diags(meta["kappa"] ** 2 * m)).tocsr()
+    P = sp.csr_matrix((np.ones(problem.Q.nnz), problem.Q.indices, problem.Q.indptr),
+                      shape=problem.Q.shape)
+    Mq = fem.on_pattern(sp.diags(m), P).data
+    Sq = fem.on_pattern(S, P).data
+    SMSq = fem.on_pattern(S @ sp.diags(1.0 / m) @ S, P).data
+    return Mq, Sq, SMSq
+
+
+def matern_from_pieces(problem: Problem, pieces, kappa: float, tau: float):
+    """(Q, dQ/dlog kappa) as CSR matrices on Q's pattern for the given hyper-parameters."""
+    Mq, Sq, SMSq = pieces
+    k2 = kappa * kappa
+    q = (k2 * k2 * Mq + 2.0 * k2 * Sq + SMSq) / (tau * tau)
+    dq = 4.0 * k2 * (k2 * Mq + Sq) / (tau * tau)
+    mk = lambda v: sp.csr_matrix((v, problem.Q.indices.copy(), problem.Q.indptr.copy()),  # noqa: E731
+                                 shape=problem.Q.shape)
+    return mk(q), mk(dq)

@@ -149,6 +149,10 @@ gmrf_status gmrf_logdet(gmrf_t h, double* out);
 gmrf_status gmrf_solve(gmrf_t h, double* mu_out, int max_refine, double tol, int* iters_out,
                        double* resid_out);
 
+/* x = Q_post^-1 rhs (one forward and one backward solve with the current factor; no
+   refinement; rhs and x_out device, n entries, original order).  Used for adjoints. */
+gmrf_status gmrf_solve_rhs(gmrf_t h, const double* rhs, double* x_out);
+
 /* k posterior samples x = mu_post + P^T L^-T z (Sec. 3.2, sampling) from the mean of the
    last gmrf_solve.  z: n x k float32, column-major, pivot order (device).
    x_out: n x k float64, column-major, original order (device).  1 <= k <= 16. */
@@ -162,6 +166,24 @@ gmrf_status gmrf_selinv(gmrf_t h, double* var_out, double* sigma_q_out);
 /* Deterministic sum_e a[e] * b[e] over len entries (device inputs, host output); used
    for traces tr(Q_post^-1 dQ) = sum over Q's pattern of Sigma_e dQ_e. */
 gmrf_status gmrf_dot(gmrf_t h, int64_t len, const double* a, const double* b, double* out);
+
+/* Whittle-Matern precision values (Sec. 2.2, eq. sparse-prec-matrix, alpha = 2) on the
+   stored pattern of Q: given the lumped mass M~, the stiffness S and S M~^-1 S placed on
+   that pattern (device, nnz entries each, zeros where absent), writes
+     q_out  = tau^-2 (kappa^4 M~ + 2 kappa^2 S + S M~^-1 S)   (= tau^-2 K M~^-1 K,
+                                                                K = kappa^2 M~ + S)
+     dq_out = dQ/dlog(kappa) = 4 kappa^2 tau^-2 K             (nullable)
+   Enqueued on the context's stream; needs no prior call. */
+gmrf_status gmrf_matern_values(gmrf_t h, int64_t nnz, const double* m_on_q, const double* s_on_q,
+                               const double* sms_on_q, double kappa, double tau, double* q_out,
+                               double* dq_out);
+
+/* y = V x for V given by its values on the stored pattern of Q (device, nnz_q values; x,
+   y device, n entries).  After gmrf_assemble.  Asynchronous. */
+gmrf_status gmrf_spmv(gmrf_t h, const double* v_val, const double* x, double* y);
+
+/* Data misfit sum_r q_eps[r] (y - b - A x)_r^2 for x (device, n entries); host output. */
+gmrf_status gmrf_misfit(gmrf_t h, const double* x, double* out);
 
 /* Counters of the analysed pattern and of the last calls (host output); also reports a
    pending device status (GMRF_ERR_NOT_SPD). */

@@ -11,6 +11,8 @@ from .core import (Factor, NotSPDError, assemble, block_logdets, build, cholesky
                    dense_posterior, logdet, marginal_variances, nd_order, posterior,
                    rcm_order, sample, selinv, sigma_on_pattern, solve)
 
-__all__ = ["Factor", "NotSPDError", "assemble", "block_logdets", "build", "cholesky",
+from .lml import lml_dense, lml_sparse
+
+__all__ = ["lml_dense", "lml_sparse", "Factor", "NotSPDError", "assemble", "block_logdets", "build", "cholesky",
            "dense_posterior", "logdet", "marginal_variances", "nd_order", "posterior",
            "rcm_order", "sample", "selinv", "sigma_on_pattern", "solve"]

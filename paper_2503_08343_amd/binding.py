@@ -28,7 +28,8 @@ GMRF_FP32_REFINE = 1
 EXPORTS = ["gmrf_create", "gmrf_destroy", "gmrf_assemble", "gmrf_update_values", "gmrf_analyze",
            "gmrf_factor", "gmrf_logdet", "gmrf_solve", "gmrf_sample", "gmrf_selinv", "gmrf_dot",
            "gmrf_stats", "gmrf_pivot_order", "gmrf_phase_ms", "gmrf_last_error",
-           "gmrf_symbolic_host", "gmrf_profile", "gmrf_kernel_stats"]
+           "gmrf_symbolic_host", "gmrf_profile", "gmrf_kernel_stats", "gmrf_matern_values",
+           "gmrf_spmv", "gmrf_misfit", "gmrf_solve_rhs"]
 
 
 class gmrf_options(ctypes.Structure):
@@ -107,6 +108,10 @@ def load():
         "gmrf_last_error": ([P], ctypes.c_char_p),
         "gmrf_symbolic_host": ([i64, P, P, P, ctypes.c_int, P, P, P, P], i32),
         "gmrf_profile": ([P, ctypes.c_int], i32),
+        "gmrf_matern_values": ([P, i64, P, P, P, d, d, P, P], i32),
+        "gmrf_spmv": ([P, P, P, P], i32),
+        "gmrf_misfit": ([P, P, P], i32),
+        "gmrf_solve_rhs": ([P, P, P], i32),
         "gmrf_kernel_stats": ([P, P, ctypes.c_int, P], i32),
     }
     for name, (args, res) in sig.items():
@@ -278,6 +283,26 @@ class Context:
     def dot(self, a, b):
         out = np.zeros(1)
         self._check(self.lib.gmrf_dot(self.h, a.numel(), _t_ptr(a), _t_ptr(b), _np_ptr(out)))
+        return float(out[0])
+
+    def matern_values(self, m_on_q, s_on_q, sms_on_q, kappa, tau, q_out, dq_out=None):
+        self._check(self.lib.gmrf_matern_values(self.h, m_on_q.numel(), _t_ptr(m_on_q), _t_ptr(s_on_q),
+                                                _t_ptr(sms_on_q), float(kappa), float(tau), _t_ptr(q_out),
+                                                _t_ptr(dq_out)))
+
+    def spmv(self, v_val, x, y):
+        self._check(self.lib.gmrf_spmv(self.h, _t_ptr(v_val), _t_ptr(x), _t_ptr(y)))
+        return y
+
+    def solve_rhs(self, rhs, out=None):
+        T = self.torch
+        x = out if out is not None else T.empty_like(rhs)
+        self._check(self.lib.gmrf_solve_rhs(self.h, _t_ptr(rhs), _t_ptr(x)))
+        return x
+
+    def misfit(self, x):
+        out = np.zeros(1)
+        self._check(self.lib.gmrf_misfit(self.h, _t_ptr(x), _np_ptr(out)))
         return float(out[0])
 
     def stats(self):

@@ -1059,6 +1059,23 @@ gmrf_status gmrf_solve(gmrf_t h, double* mu_out, int max_refine, double tol, int
   return GMRF_OK;
 }
 
+gmrf_status gmrf_solve_rhs(gmrf_t h, const double* rhs, double* x_out) {
+  if (!h || !rhs || !x_out) return fail(h, GMRF_ERR_ARG, "null argument");
+  if (!(h->state & ST_FACTORED)) return fail(h, GMRF_ERR_STATE, "gmrf_solve_rhs before gmrf_factor");
+  gmrf_status rc = check_status(h);
+  if (rc != GMRF_OK) return rc;
+  rc = alloc_solve(h, 1);
+  if (rc != GMRF_OK) return rc;
+  hipStream_t st = h->stream;
+  launch_permute_in(st, h->n, 1, h->d_perm.p, h->d_scale.p, rhs, h->n, h->d_xp.p);
+  if (h->prec == GMRF_FP32_REFINE) run_solve<float>(h, 1, true);
+  else run_solve<double>(h, 1, true);
+  launch_permute_out(st, h->n, 1, h->d_perm.p, h->d_scale.p, h->d_xp.p, nullptr, 0, x_out, h->n, 0);
+  HIPCHK(h, hipGetLastError());
+  HIPCHK(h, hipStreamSynchronize(st));
+  return GMRF_OK;
+}
+
 gmrf_status gmrf_sample(gmrf_t h, int64_t k, const float* z, double* x_out) {
   if (!h || !z || !x_out) return fail(h, GMRF_ERR_ARG, "null argument");
   if (k < 1 || k > 16) return fail(h, GMRF_ERR_ARG, "k must be 1..16");
@@ -1097,6 +1114,39 @@ gmrf_status gmrf_dot(gmrf_t h, int64_t len, const double* a, const double* b, do
   HIPCHK(h, h->d_red.alloc(1024));
   HIPCHK(h, h->d_norm.alloc(4));
   launch_dot(h->stream, len, a, b, h->d_red.p, h->d_norm.p);
+  HIPCHK(h, hipGetLastError());
+  HIPCHK(h, hipMemcpyAsync(out, h->d_norm.p, sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  return GMRF_OK;
+}
+
+gmrf_status gmrf_matern_values(gmrf_t h, int64_t nnz, const double* m_on_q, const double* s_on_q,
+                               const double* sms_on_q, double kappa, double tau, double* q_out, double* dq_out) {
+  if (!h || nnz < 0 || !m_on_q || !s_on_q || !sms_on_q || !q_out) return fail(h, GMRF_ERR_ARG, "bad argument");
+  if (!(kappa > 0.0) || !(tau > 0.0)) return fail(h, GMRF_ERR_ARG, "kappa and tau must be positive");
+  launch_matern_values(h->stream, nnz, m_on_q, s_on_q, sms_on_q, kappa, tau, q_out, dq_out);
+  HIPCHK(h, hipGetLastError());
+  return GMRF_OK;
+}
+
+gmrf_status gmrf_spmv(gmrf_t h, const double* v_val, const double* x, double* y) {
+  if (!h || !v_val || !x || !y) return fail(h, GMRF_ERR_ARG, "null argument");
+  if (!(h->state & ST_ASSEMBLED)) return fail(h, GMRF_ERR_STATE, "gmrf_spmv before gmrf_assemble");
+  launch_spmv(h->stream, h->n, h->d_qrp.p, h->d_qci.p, v_val, x, y);
+  HIPCHK(h, hipGetLastError());
+  return GMRF_OK;
+}
+
+gmrf_status gmrf_misfit(gmrf_t h, const double* x, double* out) {
+  if (!h || !x || !out) return fail(h, GMRF_ERR_ARG, "null argument");
+  if (!(h->state & ST_ASSEMBLED)) return fail(h, GMRF_ERR_STATE, "gmrf_misfit before gmrf_assemble");
+  *out = 0.0;
+  if (h->m == 0) return GMRF_OK;
+  HIPCHK(h, h->d_red.alloc(1024));
+  HIPCHK(h, h->d_norm.alloc(4));
+  launch_weighted_resid(h->stream, h->m, h->d_arp.p, h->d_aci.p, h->d_aval.p, h->d_qeps.p, h->d_y.p,
+                        h->has_b ? h->d_b.p : nullptr, x, h->d_rvec.p);
+  launch_dot(h->stream, h->m, h->d_rvec.p, h->d_rvec.p, h->d_red.p, h->d_norm.p);
   HIPCHK(h, hipGetLastError());
   HIPCHK(h, hipMemcpyAsync(out, h->d_norm.p, sizeof(double), hipMemcpyDeviceToHost, h->stream));
   HIPCHK(h, hipStreamSynchronize(h->stream));

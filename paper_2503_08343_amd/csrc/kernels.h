@@ -109,6 +109,12 @@ void launch_permute_out(hipStream_t st, int64_t n, int nrhs, const int32_t* perm
                         int accumulate);
 void launch_resid(hipStream_t st, int64_t n, const int64_t* rp, const int32_t* ci, const double* val,
                   const double* h, const double* x, double* r);
+void launch_matern_values(hipStream_t st, int64_t nnz, const double* mv, const double* sv, const double* smsv,
+                          double kappa, double tau, double* q, double* dq);
+void launch_spmv(hipStream_t st, int64_t n, const int64_t* rp, const int32_t* ci, const double* val,
+                 const double* x, double* y);
+void launch_weighted_resid(hipStream_t st, int64_t m, const int64_t* arp, const int32_t* aci, const double* aval,
+                           const double* qeps, const double* y, const double* b, const double* x, double* w);
 void launch_add(hipStream_t st, int64_t n, const double* a, const double* b, double* out);
 void launch_norm2(hipStream_t st, int64_t n, const double* v, double* partial, double* out);
 

@@ -851,6 +851,44 @@ __global__ void k_add(int64_t n, const double* __restrict__ a, const double* __r
     out[i] = b ? a[i] + b[i] : a[i];
 }
 
+// Whittle-Matern precision values on Q's pattern (alpha = 2):
+// Q = tau^-2 (kappa^4 M~ + 2 kappa^2 S + S M~^-1 S) = tau^-2 K M~^-1 K with K = kappa^2 M~ + S,
+// dQ/dlog(kappa) = 4 kappa^2 tau^-2 K
+__global__ void k_matern_values(int64_t nnz, const double* __restrict__ mv, const double* __restrict__ sv,
+                                const double* __restrict__ smsv, double kappa, double tau,
+                                double* __restrict__ q, double* __restrict__ dq) {
+  const double k2 = kappa * kappa, it2 = 1.0 / (tau * tau);
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nnz;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    q[e] = it2 * (k2 * k2 * mv[e] + 2.0 * k2 * sv[e] + smsv[e]);
+    if (dq) dq[e] = 4.0 * k2 * it2 * (k2 * mv[e] + sv[e]);
+  }
+}
+
+__global__ void k_spmv(int64_t n, const int64_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                       const double* __restrict__ val, const double* __restrict__ x, double* __restrict__ y) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (int64_t e = rp[i]; e < rp[i + 1]; ++e) s += val[e] * x[ci[e]];
+    y[i] = s;
+  }
+}
+
+// w_r = sqrt(q_eps_r) (y_r - b_r - (A x)_r)
+__global__ void k_weighted_resid(int64_t m, const int64_t* __restrict__ arp, const int32_t* __restrict__ aci,
+                                 const double* __restrict__ aval, const double* __restrict__ qeps,
+                                 const double* __restrict__ y, const double* __restrict__ b,
+                                 const double* __restrict__ x, double* __restrict__ w) {
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < m;
+       r += (int64_t)gridDim.x * blockDim.x) {
+    double s = y[r];
+    if (b) s -= b[r];
+    for (int64_t e = arp[r]; e < arp[r + 1]; ++e) s -= aval[e] * x[aci[e]];
+    w[r] = sqrt(qeps[r]) * s;
+  }
+}
+
 constexpr int kRedBlocks = 512;
 
 // deterministic two-pass sum of a[i]*b[i] (b == nullptr: a[i]^2)
@@ -1266,6 +1304,20 @@ void launch_permute_out(hipStream_t st, int64_t n, int nrhs, const int32_t* perm
 void launch_resid(hipStream_t st, int64_t n, const int64_t* rp, const int32_t* ci, const double* val,
                   const double* h, const double* x, double* r) {
   hipLaunchKernelGGL(k_resid, dim3(grid_for(n)), dim3(kThreads), 0, st, n, rp, ci, val, h, x, r);
+}
+void launch_matern_values(hipStream_t st, int64_t nnz, const double* mv, const double* sv, const double* smsv,
+                          double kappa, double tau, double* q, double* dq) {
+  hipLaunchKernelGGL(k_matern_values, dim3(grid_for(nnz)), dim3(kThreads), 0, st, nnz, mv, sv, smsv, kappa, tau,
+                     q, dq);
+}
+void launch_spmv(hipStream_t st, int64_t n, const int64_t* rp, const int32_t* ci, const double* val,
+                 const double* x, double* y) {
+  hipLaunchKernelGGL(k_spmv, dim3(grid_for(n)), dim3(kThreads), 0, st, n, rp, ci, val, x, y);
+}
+void launch_weighted_resid(hipStream_t st, int64_t m, const int64_t* arp, const int32_t* aci, const double* aval,
+                           const double* qeps, const double* y, const double* b, const double* x, double* w) {
+  if (m <= 0) return;
+  hipLaunchKernelGGL(k_weighted_resid, dim3(grid_for(m)), dim3(kThreads), 0, st, m, arp, aci, aval, qeps, y, b, x, w);
 }
 void launch_add(hipStream_t st, int64_t n, const double* a, const double* b, double* out) {
   hipLaunchKernelGGL(k_add, dim3(grid_for(n)), dim3(kThreads), 0, st, n, a, b, out);

@@ -1,0 +1,118 @@
+"""GPU log marginal likelihood and hand-written adjoint gradient w.r.t. (log kappa,
+log tau, log sigma): against the oracle on moderate grids (element by element for the
+scalars), against central finite differences (h = 1e-5) of the GPU's own LML at the full
+64^3 size, against the exact tau/sigma scaling identity, through torch.autograd, and the
+posterior-mean adjoint against finite differences."""
+import math
+
+import numpy as np
+import pytest
+
+import gmrf_inputs as gi
+import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+
+def _engine(gpu_lib, p, precision=0):
+    from paper_2503_08343_amd import adjoint
+    pieces = gi.matern_pieces(p)
+    eng = adjoint.MaternLML(p.Q.indptr, p.Q.indices, *pieces, p.A, p.y, p.b, p.coords,
+                            precision=precision)
+    return eng, pieces
+
+
+@pytest.mark.parametrize("maker,theta", [
+    (lambda: gi.matern2d(side=40, n_obs=150, seed=81), (math.log(4.0), math.log(0.7), math.log(0.05))),
+    (lambda: gi.matern3d(side=12, n_obs=200, seed=82), (math.log(9.0), math.log(1.2), math.log(0.1))),
+])
+def test_lml_and_gradient_match_oracle(gpu_lib, maker, theta):
+    p = maker()
+    eng, pieces = _engine(gpu_lib, p)
+    lml, g = eng.evaluate(*theta)
+    k, t, s = np.exp(theta)
+    Q, dQk = gi.matern_from_pieces(p, pieces, k, t)
+    q_eps = np.full(p.A.shape[0], 1.0 / s**2)
+    ref, gref, _ = O.lml_sparse(Q, p.A, q_eps, p.y, p.b, p.coords,
+                                [(dQk, None), (-2.0 * Q, None), (0.0 * Q, -2.0 * q_eps)])
+    print(f"[lml] n={p.n} gpu {lml:.12e} oracle {ref:.12e} g {g} gref {gref}", flush=True)
+    assert abs(lml - ref) <= 1e-10 * max(1.0, abs(ref))
+    for i in range(3):
+        assert abs(g[i] - gref[i]) <= 1e-8 * max(1.0, abs(gref[i])), (i, g[i], gref[i])
+    eng.close()
+
+
+def test_full_size_gradient_vs_finite_differences_and_autograd(gpu_lib):
+    import torch
+    from paper_2503_08343_amd import adjoint
+    p = gi.matern3d()      # 64^3 P1 (262,144 unknowns), 5000 points, sigma = 0.05
+    print(f"[lml] full size n={p.n} m={p.A.shape[0]}", flush=True)
+    eng, _ = _engine(gpu_lib, p)
+    th = np.array([math.log(10.0), 0.0, math.log(0.05)])
+    lml, g = eng.evaluate(*th)
+    h = 1e-5
+    for i in range(3):
+        e = np.zeros(3)
+        e[i] = h
+        fp = eng.evaluate(*(th + e), gradient=False)[0]
+        fm = eng.evaluate(*(th - e), gradient=False)[0]
+        fd = (fp - fm) / (2 * h)
+        print(f"[lml] param {i}: adjoint {g[i]:.10e} fd {fd:.10e}", flush=True)
+        assert abs(g[i] - fd) <= 1e-5 * max(1.0, abs(g[i]))
+    # scaling identity g_tau + g_sigma = -M + mu^T Q mu + r^T Q_eps r
+    eng.evaluate(*th)
+    mu = eng.mu
+    eng.post.spmv(eng.q, mu, eng.tmp)
+    quad = eng.post.dot(mu, eng.tmp)
+    misfit = eng.post.misfit(mu)
+    M = p.A.shape[0]
+    assert abs(g[1] + g[2] - (-M + quad + misfit)) <= 1e-8 * max(1.0, abs(g[1]))
+    # torch.autograd through the hand-written adjoint
+    theta = torch.tensor(th, dtype=torch.float64, requires_grad=True)
+    out = adjoint.log_ml(theta, eng)
+    out.backward()
+    assert np.allclose(theta.grad.numpy(), g, rtol=1e-12, atol=0)
+    assert abs(float(out) - lml) <= 1e-12 * abs(lml)
+    eng.close()
+
+
+def test_posterior_mean_adjoint_vs_finite_differences(gpu_lib):
+    import torch
+    from paper_2503_08343_amd import adjoint
+    p = gi.matern2d(side=30, n_obs=80, seed=83)
+    eng, _ = _engine(gpu_lib, p)
+    w = torch.from_numpy(gi.rng_for(84).standard_normal(p.n)).cuda()
+    th = torch.tensor([math.log(6.0), math.log(0.9), math.log(0.05)], dtype=torch.float64, requires_grad=True)
+    mu = adjoint.posterior_mean(th, eng)
+    loss = (w * mu).sum()
+    loss.backward()
+    g = th.grad.numpy()
+    h = 1e-5
+    base = th.detach().numpy()
+    for i in range(3):
+        e = np.zeros(3)
+        e[i] = h
+        eng.evaluate(*(base + e), gradient=False)
+        lp = float((w * eng.mu).sum())
+        eng.evaluate(*(base - e), gradient=False)
+        lm = float((w * eng.mu).sum())
+        fd = (lp - lm) / (2 * h)
+        assert abs(g[i] - fd) <= 1e-6 * max(1.0, abs(fd)), (i, g[i], fd)
+    # mu depends on tau and sigma only through their ratio
+    assert abs(g[1] + g[2]) <= 1e-10 * max(1.0, abs(g[1]))
+    eng.close()
+
+
+def test_fp32_lml_close_to_fp64(gpu_lib):
+    p = gi.matern3d(side=24, n_obs=500, seed=85)
+    th = (math.log(10.0), 0.0, math.log(0.05))
+    e64, _ = _engine(gpu_lib, p, precision=0)
+    e32, _ = _engine(gpu_lib, p, precision=1)
+    l64, g64 = e64.evaluate(*th)
+    l32, g32 = e32.evaluate(*th)
+    print(f"[lml] fp32 vs fp64: lml rel {abs(l32 - l64) / abs(l64):.2e} grad rel "
+          f"{np.max(np.abs(g32 - g64) / np.maximum(1.0, np.abs(g64))):.2e}", flush=True)
+    assert abs(l32 - l64) <= 1e-6 * abs(l64)
+    assert np.all(np.abs(g32 - g64) <= 1e-2 * np.maximum(1.0, np.abs(g64)))
+    e64.close()
+    e32.close()
