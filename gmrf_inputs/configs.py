@@ -247,3 +247,70 @@ def matern_from_pieces(problem: Problem, pieces, kappa: float, tau: float):
     mk = lambda v: sp.csr_matrix((v, problem.Q.indices.copy(), problem.Q.indptr.copy()),  # noqa: E731
                                  shape=problem.Q.shape)
     return mk(q), mk(dq)
+
+
+def burgers_spacetime(nx: int = 1024, nt: int = 1024, nu: float = 0.01 / math.pi,
+                      sigma_pde: float = 1e-3, sigma_ic: float = 1e-3, range_s: float = 0.02,
+                      tau: float = 1.0, seed: int = 3) -> Problem:
+    """Viscous Burgers u_t + u u_x = nu u_xx on [-1, 1] x [0, 1] (Sec. 2.3, 3.3).
+
+    Prior: the linear stochastic proxy u_t - nu u_xx = tau W (the advection speed c is the
+    mean of the initial condition, here 0), implicit Euler in time, P1 in space on nx
+    interior nodes (homogeneous Dirichlet nodes at +-1 eliminated), spatial noise a 1D
+    Matern field (alpha = 2, nu_s = 3/2) with range range_s, scaled to unit mean marginal
+    variance of the discrete field, which is also the initial-slice precision.  Observations: nx initial-condition rows
+    u^0_i = u0(x_i) (noise sigma_ic) and the Galerkin implicit-Euler Burgers residual rows
+    on slices 2..nt (noise sigma_pde, data 0).  A holds the linearisation at u = 0; the
+    library rewrites A and b at every Gauss-Newton iterate.  Initial condition
+    u0 = -sin(pi x) + 0.1 sum_{k=2}^{4} a_k sin(k pi x), a_k ~ N(0, 1)."""
+    rng = rng_for(seed)
+    full = fem.structured_mesh((nx + 2,), lo=(-1.0,), hi=(1.0,))
+    inner = np.arange(1, nx + 1)
+    S = fem.stiffness(full)[inner][:, inner].tocsr()
+    m = fem.lumped_mass(full)[inner]
+    mesh = fem.structured_mesh((nx,), lo=(float(full.coords[1, 0]),), hi=(float(full.coords[nx, 0]),))
+    dt = 1.0 / (nt - 1)
+    kappa_s = priors.matern_range_to_kappa(range_s, 1.5)
+    Ks = (S + sp.diags(kappa_s * kappa_s * m)).tocsr()
+    Q0 = (Ks.T @ sp.diags(1.0 / m) @ Ks).tocsr()
+    # tau_s gives the discrete noise field unit mean marginal variance
+    tau_s = math.sqrt(1.0 / float(np.mean(np.diag(np.linalg.inv(Q0.toarray())))))
+    Qs = fem.on_pattern(Q0 / (tau_s * tau_s), fem.ring_pattern(mesh, 2))
+    Qs = _sym_clean(Qs)
+    Q, G = priors.spacetime_precision(mesh, nt, dt, nu * S, tau, Qs, m, sigma_inv=Qs)
+    Q = _sym_clean(Q)
+    a = rng.standard_normal(3)
+    x = full.coords[inner, 0]
+    u0 = -np.sin(np.pi * x) + 0.1 * sum(a[k - 2] * np.sin(k * np.pi * x) for k in (2, 3, 4))
+    # S rows as (left, diagonal, right) triplets
+    s3 = np.zeros((nx, 3))
+    Sd = S.toarray() if nx <= 4096 else None
+    for i in range(nx):
+        row = S.getrow(i)
+        for j, v in zip(row.indices, row.data):
+            s3[i, 1 + (j - i)] = v
+    del Sd
+    # A pattern and its linearisation at u = 0 (B vanishes there)
+    rows, cols, vals = [], [], []
+    rows.append(np.arange(nx)); cols.append(np.arange(nx)); vals.append(np.ones(nx))
+    r = nx
+    k = np.repeat(np.arange(1, nt), nx)
+    i = np.tile(np.arange(nx), nt - 1)
+    rr = nx + (k - 1) * nx + i
+    rows.append(rr); cols.append((k - 1) * nx + i); vals.append(-m[i] / dt)
+    sel = i > 0
+    rows.append(rr[sel]); cols.append(k[sel] * nx + i[sel] - 1); vals.append(nu * s3[i[sel], 0])
+    rows.append(rr); cols.append(k * nx + i); vals.append(m[i] / dt + nu * s3[i, 1])
+    sel = i < nx - 1
+    rows.append(rr[sel]); cols.append(k[sel] * nx + i[sel] + 1); vals.append(nu * s3[i[sel], 2])
+    N = nx * nt
+    A = sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                      shape=(N, N)).tocsr()
+    A.sum_duplicates(); A.sort_indices()
+    y = np.concatenate([u0, np.zeros((nt - 1) * nx)])
+    q_eps = np.concatenate([np.full(nx, 1.0 / sigma_ic**2), np.full((nt - 1) * nx, 1.0 / sigma_pde**2)])
+    coords = np.stack([np.tile(x, nt), np.repeat(np.arange(nt) * dt, nx)], axis=1)
+    return Problem(N, Q, A, q_eps, y, np.zeros(N), coords,
+                   meta=dict(workload="burgers_spacetime", nx=nx, nt=nt, dt=dt, nu=nu, mass=m, s3=s3,
+                             u0=u0, x=x, sigma_pde=sigma_pde, sigma_ic=sigma_ic, kappa_s=kappa_s,
+                             tau_s=tau_s, seed=seed))

@@ -153,6 +153,30 @@ gmrf_status gmrf_solve(gmrf_t h, double* mu_out, int max_refine, double tol, int
    refinement; rhs and x_out device, n entries, original order).  Used for adjoints. */
 gmrf_status gmrf_solve_rhs(gmrf_t h, const double* rhs, double* x_out);
 
+/* Gauss-Newton for the nonlinear Burgers space-time problem (Sec. 3.3).  Unknowns
+   u^k_i, slice k = 0..nt-1, interior node i = 0..nx-1 (homogeneous Dirichlet outside),
+   index k*nx + i.  The context must hold Q (prior, analysed) and A with m = nx*nt rows in
+   this layout: row i (< nx) observes u^0_i (one entry); row nx + (k-1)*nx + i holds the
+   Galerkin implicit-Euler residual
+     f = mass_i (u^k_i - u^(k-1)_i)/dt + nu (S u^k)_i + (u_{i+1}^2 + u_i u_{i+1} - u_{i-1} u_i
+         - u_{i-1}^2)/6
+   with entries at columns (k-1)*nx+i, k*nx+i-1, k*nx+i, k*nx+i+1 (those in range); y and
+   q_eps as assembled.  mass (nx) and stiff3 (3*nx: S_{i,i-1}, S_{i,i}, S_{i,i+1}) are
+   device arrays.  Each iteration linearises f at u (J values and offset b written into the
+   assembled A and b), assembles H = Q + J^T Q_eps J on the analysed pattern (the ordering
+   is reused), factors in `precision`, solves for the linearised posterior mean with
+   `refine` FP64 residual corrections, and takes a backtracking Armijo step (c = 1e-4,
+   alpha = 1, 1/2, ..., 1/128, the first that passes, else 1/128) chosen on the device.
+   With use_graph != 0 the iterations after the first replay one captured hipGraph.
+   u (device, n): start on entry, final iterate on exit.  rec_out (host, 4*iters,
+   nullable): per iteration objective at the start, step length, Newton decrement
+   lambda^2 = -grad^T d, and grad^T d.  On return the context holds the factor of the
+   Gauss-Newton Laplace approximation at the final iterate and mu_post = u, so
+   gmrf_logdet, gmrf_sample and gmrf_selinv describe N(u*, (Q + J*^T Q_eps J*)^-1). */
+gmrf_status gmrf_gn_burgers(gmrf_t h, int64_t nx, int64_t nt, double dt, double nu,
+                            const double* mass, const double* stiff3, int iters, int precision,
+                            int refine, int use_graph, double* u, double* rec_out);
+
 /* k posterior samples x = mu_post + P^T L^-T z (Sec. 3.2, sampling) from the mean of the
    last gmrf_solve.  z: n x k float32, column-major, pivot order (device).
    x_out: n x k float64, column-major, original order (device).  1 <= k <= 16. */

@@ -12,7 +12,8 @@ from .core import (Factor, NotSPDError, assemble, block_logdets, build, cholesky
                    rcm_order, sample, selinv, sigma_on_pattern, solve)
 
 from .lml import lml_dense, lml_sparse
+from .gn import burgers_residual_and_jacobian, gn_step
 
-__all__ = ["lml_dense", "lml_sparse", "Factor", "NotSPDError", "assemble", "block_logdets", "build", "cholesky",
+__all__ = ["lml_dense", "lml_sparse", "burgers_residual_and_jacobian", "gn_step", "Factor", "NotSPDError", "assemble", "block_logdets", "build", "cholesky",
            "dense_posterior", "logdet", "marginal_variances", "nd_order", "posterior",
            "rcm_order", "sample", "selinv", "sigma_on_pattern", "solve"]

@@ -29,7 +29,7 @@ EXPORTS = ["gmrf_create", "gmrf_destroy", "gmrf_assemble", "gmrf_update_values",
            "gmrf_factor", "gmrf_logdet", "gmrf_solve", "gmrf_sample", "gmrf_selinv", "gmrf_dot",
            "gmrf_stats", "gmrf_pivot_order", "gmrf_phase_ms", "gmrf_last_error",
            "gmrf_symbolic_host", "gmrf_profile", "gmrf_kernel_stats", "gmrf_matern_values",
-           "gmrf_spmv", "gmrf_misfit", "gmrf_solve_rhs"]
+           "gmrf_spmv", "gmrf_misfit", "gmrf_solve_rhs", "gmrf_gn_burgers"]
 
 
 class gmrf_options(ctypes.Structure):
@@ -112,6 +112,8 @@ def load():
         "gmrf_spmv": ([P, P, P, P], i32),
         "gmrf_misfit": ([P, P, P], i32),
         "gmrf_solve_rhs": ([P, P, P], i32),
+        "gmrf_gn_burgers": ([P, i64, i64, d, d, P, P, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                             ctypes.c_int, P, P], i32),
         "gmrf_kernel_stats": ([P, P, ctypes.c_int, P], i32),
     }
     for name, (args, res) in sig.items():
@@ -299,6 +301,16 @@ class Context:
         x = out if out is not None else T.empty_like(rhs)
         self._check(self.lib.gmrf_solve_rhs(self.h, _t_ptr(rhs), _t_ptr(x)))
         return x
+
+    def gn_burgers(self, nx, nt, dt, nu, mass, stiff3, u, iters=10, precision=GMRF_FP64, refine=2,
+                   use_graph=True):
+        """Gauss-Newton iterations on the assembled Burgers problem; u (device) is updated in
+        place.  Returns the per-iteration records (objective, step, decrement, slope)."""
+        rec = np.zeros(4 * iters)
+        self._check(self.lib.gmrf_gn_burgers(self.h, int(nx), int(nt), float(dt), float(nu), _t_ptr(mass),
+                                             _t_ptr(stiff3), int(iters), int(precision), int(refine),
+                                             1 if use_graph else 0, _t_ptr(u), _np_ptr(rec)))
+        return rec.reshape(iters, 4)
 
     def misfit(self, x):
         out = np.zeros(1)

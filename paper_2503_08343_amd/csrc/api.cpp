@@ -138,6 +138,11 @@ struct gmrf_ctx {
   double cls_bytes[KC_COUNT] = {0};
   int64_t cls_n[KC_COUNT] = {0};
   int tsize = 8;   // bytes per working-precision element of the current numeric phase
+  // Gauss-Newton scratch
+  DevArr<double> d_gn_x, d_gn_d, d_gn_tmp, d_gn_part, d_gn_quad, d_gn_sel, d_gn_rec;
+  hipStream_t gn_stream = nullptr;
+  hipGraphExec_t gn_exec = nullptr;
+  int gn_exec_prec = -1;
 };
 
 namespace {
@@ -752,6 +757,61 @@ gmrf_status assemble_device(gmrf_t h) {
   return GMRF_OK;
 }
 
+// ------------------------------------------------------------------ Gauss-Newton driver
+struct GNArgs {
+  int64_t nx, nt;
+  double dt, nu;
+  const double* mass;
+  const double* s3;
+  double* u;
+  int refine;
+};
+
+// solve Q_post x = h on device only (no host synchronisation): one solve plus `refine`
+// corrections with FP64 residuals
+template <typename T>
+void device_solve(gmrf_t h, double* x, int refine) {
+  hipStream_t st = h->stream;
+  const int64_t n = h->n;
+  launch_permute_in(st, n, 1, h->d_perm.p, h->d_scale.p, h->d_h.p, n, h->d_xp.p);
+  run_solve<T>(h, 1, true);
+  launch_permute_out(st, n, 1, h->d_perm.p, h->d_scale.p, h->d_xp.p, nullptr, 0, x, n, 0);
+  for (int it = 0; it < refine; ++it) {
+    launch_resid(st, n, h->d_qrp.p, h->d_qci.p, h->d_qpost.p, h->d_h.p, x, h->d_r.p);
+    launch_permute_in(st, n, 1, h->d_perm.p, h->d_scale.p, h->d_r.p, n, h->d_xp.p);
+    run_solve<T>(h, 1, true);
+    launch_permute_out(st, n, 1, h->d_perm.p, h->d_scale.p, h->d_xp.p, nullptr, 0, x, n, 1);
+  }
+}
+
+// one Gauss-Newton iteration, fully asynchronous (capturable): linearise at u, assemble
+// H = Q + J^T Q_eps J and the right-hand side, factor (same pattern, reused analysis),
+// solve for the linearised posterior mean x, direction d = x - u, batched backtracking
+// line search on the device, u += alpha d.  The iteration record lands in d_gn_rec[0..3].
+template <typename T>
+gmrf_status gn_body(gmrf_t h, const GNArgs& a) {
+  hipStream_t st = h->stream;
+  const int64_t n = h->n;
+  launch_burgers_linearize(st, a.nx, a.nt, a.dt, a.nu, a.mass, a.s3, a.u, h->d_arp.p, h->d_aval.p, h->d_b.p);
+  gmrf_status rc = assemble_device(h);
+  if (rc != GMRF_OK) return rc;
+  rc = run_factor<T>(h);
+  if (rc != GMRF_OK) return rc;
+  device_solve<T>(h, h->d_gn_x.p, a.refine);
+  launch_gn_direction(st, n, h->d_gn_x.p, a.u, h->d_gn_d.p);
+  launch_spmv(st, n, h->d_qrp.p, h->d_qci.p, h->d_qval.p, a.u, h->d_gn_tmp.p);
+  launch_dot(st, n, a.u, h->d_gn_tmp.p, h->d_red.p, h->d_gn_quad.p + 0);
+  launch_dot(st, n, h->d_gn_d.p, h->d_gn_tmp.p, h->d_red.p, h->d_gn_quad.p + 1);
+  launch_spmv(st, n, h->d_qrp.p, h->d_qci.p, h->d_qval.p, h->d_gn_d.p, h->d_gn_tmp.p);
+  launch_dot(st, n, h->d_gn_d.p, h->d_gn_tmp.p, h->d_red.p, h->d_gn_quad.p + 2);
+  launch_gn_linesearch(st, a.nx, a.nt, a.dt, a.nu, a.mass, a.s3, a.u, h->d_gn_d.p, h->d_y.p, h->d_qeps.p,
+                       h->d_arp.p, h->d_aci.p, h->d_aval.p, h->d_gn_part.p, h->d_gn_quad.p, h->d_gn_sel.p,
+                       h->d_gn_rec.p);
+  launch_gn_update(st, n, h->d_gn_sel.p, h->d_gn_d.p, a.u);
+  HIPCHK(h, hipGetLastError());
+  return GMRF_OK;
+}
+
 float elapsed(hipEvent_t a, hipEvent_t b) {
   float ms = 0.f;
   if (hipEventElapsedTime(&ms, a, b) != hipSuccess) return 0.f;
@@ -788,6 +848,8 @@ gmrf_status gmrf_destroy(gmrf_t h) {
     if (e) (void)hipEventDestroy(e);
   for (auto& e : h->evpool)
     if (e) (void)hipEventDestroy(e);
+  if (h->gn_exec) (void)hipGraphExecDestroy(h->gn_exec);
+  if (h->gn_stream) (void)hipStreamDestroy(h->gn_stream);
   delete h;
   return GMRF_OK;
 }
@@ -1074,6 +1136,99 @@ gmrf_status gmrf_solve_rhs(gmrf_t h, const double* rhs, double* x_out) {
   HIPCHK(h, hipGetLastError());
   HIPCHK(h, hipStreamSynchronize(st));
   return GMRF_OK;
+}
+
+gmrf_status gmrf_gn_burgers(gmrf_t h, int64_t nx, int64_t nt, double dt, double nu, const double* mass,
+                            const double* stiff3, int iters, int precision, int refine, int use_graph,
+                            double* u, double* rec_out) {
+  if (!h || !mass || !stiff3 || !u || iters < 1 || refine < 0) return fail(h, GMRF_ERR_ARG, "bad argument");
+  if (precision != GMRF_FP64 && precision != GMRF_FP32_REFINE) return fail(h, GMRF_ERR_ARG, "unknown precision");
+  if (!(h->state & ST_ANALYZED)) return fail(h, GMRF_ERR_STATE, "gmrf_gn_burgers before gmrf_analyze");
+  if (nx < 2 || nt < 2 || h->n != nx * nt || h->m != nx * nt || !(dt > 0.0))
+    return fail(h, GMRF_ERR_ARG, "sizes do not match the assembled Burgers problem");
+  // the rows of A must have the Burgers layout
+  for (int64_t r = 0; r < h->m; ++r) {
+    const int64_t e0 = h->arp[r], e1 = h->arp[r + 1];
+    if (r < nx) {
+      if (e1 - e0 != 1 || h->aci[e0] != r) return fail(h, GMRF_ERR_PATTERN, "A row " + std::to_string(r) + " is not an initial-condition row");
+      continue;
+    }
+    const int64_t q = r - nx, k = q / nx + 1, i = q % nx;
+    int64_t want[4], c = 0;
+    want[c++] = (k - 1) * nx + i;
+    if (i > 0) want[c++] = k * nx + i - 1;
+    want[c++] = k * nx + i;
+    if (i + 1 < nx) want[c++] = k * nx + i + 1;
+    if (e1 - e0 != c) return fail(h, GMRF_ERR_PATTERN, "A row " + std::to_string(r) + " has the wrong length");
+    for (int64_t t = 0; t < c; ++t)
+      if (h->aci[e0 + t] != want[t]) return fail(h, GMRF_ERR_PATTERN, "A row " + std::to_string(r) + " has wrong columns");
+  }
+  if (hipSetDevice(h->device) != hipSuccess) return fail(h, GMRF_ERR_HIP, "hipSetDevice failed");
+  hipStream_t user = h->stream;
+  if (!h->gn_stream) HIPCHK(h, hipStreamCreateWithFlags(&h->gn_stream, hipStreamNonBlocking));
+  HIPCHK(h, user ? hipStreamSynchronize(user) : hipDeviceSynchronize());
+  h->stream = h->gn_stream;
+  struct Restore { gmrf_t h; hipStream_t s; ~Restore() { h->stream = s; } } restore{h, user};
+  const bool prof = h->prof;
+  h->prof = false;
+  HIPCHK(h, h->d_gn_x.alloc(h->n));
+  HIPCHK(h, h->d_gn_d.alloc(h->n));
+  HIPCHK(h, h->d_gn_tmp.alloc(h->n));
+  HIPCHK(h, h->d_gn_part.alloc(10 * 256));
+  HIPCHK(h, h->d_gn_quad.alloc(4));
+  HIPCHK(h, h->d_gn_sel.alloc(1));
+  HIPCHK(h, h->d_gn_rec.alloc(4));
+  gmrf_status rc = alloc_solve(h, 1);
+  if (rc != GMRF_OK) return rc;
+  rc = precision == GMRF_FP64 ? alloc_numeric<double>(h) : alloc_numeric<float>(h);
+  if (rc != GMRF_OK) return rc;
+  h->has_b = true;
+  GNArgs a{nx, nt, dt, nu, mass, stiff3, u, refine};
+  std::vector<double> rec(4 * (size_t)iters, 0.0);
+  auto body = [&]() { return precision == GMRF_FP64 ? gn_body<double>(h, a) : gn_body<float>(h, a); };
+  HIPCHK(h, hipEventRecord(h->ev[0], h->stream));
+  for (int it = 0; it < iters; ++it) {
+    const bool graph = use_graph && it > 0;
+    if (graph && (!h->gn_exec || h->gn_exec_prec != precision)) {
+      if (h->gn_exec) { (void)hipGraphExecDestroy(h->gn_exec); h->gn_exec = nullptr; }
+      hipGraph_t g = nullptr;
+      HIPCHK(h, hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+      rc = body();
+      hipError_t ce = hipStreamEndCapture(h->stream, &g);
+      if (rc != GMRF_OK) { if (g) (void)hipGraphDestroy(g); return rc; }
+      HIPCHK(h, ce);
+      hipError_t ie = hipGraphInstantiate(&h->gn_exec, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      HIPCHK(h, ie);
+      h->gn_exec_prec = precision;
+    }
+    if (graph) {
+      HIPCHK(h, hipGraphLaunch(h->gn_exec, h->stream));
+    } else {
+      rc = body();
+      if (rc != GMRF_OK) return rc;
+    }
+    HIPCHK(h, hipMemcpyAsync(rec.data() + 4 * it, h->d_gn_rec.p, 4 * sizeof(double), hipMemcpyDeviceToHost,
+                             h->stream));
+  }
+  HIPCHK(h, hipEventRecord(h->ev[1], h->stream));
+  // Laplace approximation at the final iterate (Sec. 3.3): relinearise and refactor so that
+  // logdet / sample / selinv describe N(u*, (Q + J*^T Q_eps J*)^-1)
+  launch_burgers_linearize(h->stream, nx, nt, dt, nu, mass, stiff3, u, h->d_arp.p, h->d_aval.p, h->d_b.p);
+  rc = assemble_device(h);
+  if (rc != GMRF_OK) return rc;
+  rc = precision == GMRF_FP64 ? run_factor<double>(h) : run_factor<float>(h);
+  if (rc != GMRF_OK) return rc;
+  HIPCHK(h, copy_d2d(h->d_mu_post.p, u, h->n * sizeof(double), h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  h->ev_factor = false;
+  float ms = 0.f;
+  if (hipEventElapsedTime(&ms, h->ev[0], h->ev[1]) == hipSuccess) h->phase_ms[0] = ms;
+  h->prof = prof;
+  h->prec = precision;
+  h->state |= ST_FACTORED | ST_SOLVED;
+  if (rec_out) std::memcpy(rec_out, rec.data(), rec.size() * sizeof(double));
+  return check_status(h);
 }
 
 gmrf_status gmrf_sample(gmrf_t h, int64_t k, const float* z, double* x_out) {

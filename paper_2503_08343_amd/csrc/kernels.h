@@ -115,6 +115,16 @@ void launch_spmv(hipStream_t st, int64_t n, const int64_t* rp, const int32_t* ci
                  const double* x, double* y);
 void launch_weighted_resid(hipStream_t st, int64_t m, const int64_t* arp, const int32_t* aci, const double* aval,
                            const double* qeps, const double* y, const double* b, const double* x, double* w);
+// Gauss-Newton (Burgers): linearisation, batched line search (part: 10 * 256 doubles;
+// quad: u^T Q u, u^T Q d, d^T Q d), direction and update
+void launch_burgers_linearize(hipStream_t st, int64_t nx, int64_t nt, double dt, double nu, const double* mass,
+                              const double* s3, const double* u, const int64_t* arp, double* aval, double* b);
+void launch_gn_linesearch(hipStream_t st, int64_t nx, int64_t nt, double dt, double nu, const double* mass,
+                          const double* s3, const double* u, const double* d, const double* y, const double* qeps,
+                          const int64_t* arp, const int32_t* aci, const double* aval, double* part,
+                          const double* quad, double* sel, double* rec);
+void launch_gn_direction(hipStream_t st, int64_t n, const double* x, const double* u, double* d);
+void launch_gn_update(hipStream_t st, int64_t n, const double* sel, const double* d, double* u);
 void launch_add(hipStream_t st, int64_t n, const double* a, const double* b, double* out);
 void launch_norm2(hipStream_t st, int64_t n, const double* v, double* partial, double* out);
 

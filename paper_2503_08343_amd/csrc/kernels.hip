@@ -889,6 +889,134 @@ __global__ void k_weighted_resid(int64_t m, const int64_t* __restrict__ arp, con
   }
 }
 
+// ---- Gauss-Newton for the Galerkin implicit-Euler Burgers residual (Sec. 3.3) ----
+// Unknowns u^k_i at slice k (0..nt-1) and interior node i (0..nx-1), index k*nx + i;
+// homogeneous Dirichlet values outside.  Rows of A: i (k = 0) observe u^0_i; row
+// nx + (k-1)*nx + i (k >= 1) is the Galerkin residual
+//   f = m_i (u^k_i - u^(k-1)_i)/dt + nu (S u^k)_i + B_i(u^k),
+//   B_i(u) = (u_{i+1}^2 + u_i u_{i+1} - u_{i-1} u_i - u_{i-1}^2) / 6   (P1, exact quadrature of
+//   the weak form of u u_x = (u^2/2)_x), stored as [(k-1)nx+i, k nx+i-1, k nx+i, k nx+i+1].
+// B is quadratic, so the linearisation f(u) ~ J(u_bar) u + b has b = -B(u_bar).
+__device__ __forceinline__ double burg_B(double um, double u0, double up) {
+  return (up * up + u0 * up - um * u0 - um * um) * (1.0 / 6.0);
+}
+
+__global__ void k_burgers_linearize(int64_t nx, int64_t nt, double dt, double nu, const double* __restrict__ mass,
+                                    const double* __restrict__ s3, const double* __restrict__ u,
+                                    const int64_t* __restrict__ arp, double* __restrict__ aval,
+                                    double* __restrict__ b) {
+  const int64_t m = nx * nt;
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < m; r += (int64_t)gridDim.x * blockDim.x) {
+    int64_t e = arp[r];
+    if (r < nx) { aval[e] = 1.0; b[r] = 0.0; continue; }
+    const int64_t q = r - nx, k = q / nx + 1, i = q % nx;
+    const double* uk = u + k * nx;
+    const double um = i > 0 ? uk[i - 1] : 0.0, u0 = uk[i], up = i + 1 < nx ? uk[i + 1] : 0.0;
+    aval[e++] = -mass[i] / dt;
+    if (i > 0) aval[e++] = nu * s3[3 * i] + (-u0 - 2.0 * um) * (1.0 / 6.0);
+    aval[e++] = mass[i] / dt + nu * s3[3 * i + 1] + (up - um) * (1.0 / 6.0);
+    if (i + 1 < nx) aval[e++] = nu * s3[3 * i + 2] + (2.0 * up + u0) * (1.0 / 6.0);
+    b[r] = -burg_B(um, u0, up);
+  }
+}
+
+// Residual of row r at u + alpha d (the nonlinear f, minus the data y)
+__device__ __forceinline__ double burg_resid(int64_t r, int64_t nx, double dt, double nu,
+                                             const double* __restrict__ mass, const double* __restrict__ s3,
+                                             const double* __restrict__ u, const double* __restrict__ d,
+                                             double alpha, const double* __restrict__ y) {
+  if (r < nx) return (u[r] + alpha * d[r]) - y[r];
+  const int64_t q = r - nx, k = q / nx + 1, i = q % nx;
+  const int64_t c = k * nx + i, cp = (k - 1) * nx + i;
+  auto U = [&](int64_t j) { return u[j] + alpha * d[j]; };
+  const double um = i > 0 ? U(c - 1) : 0.0, u0 = U(c), up = i + 1 < nx ? U(c + 1) : 0.0;
+  const double su = s3[3 * i] * um + s3[3 * i + 1] * u0 + s3[3 * i + 2] * up;
+  return mass[i] * (u0 - U(cp)) / dt + nu * su + burg_B(um, u0, up) - y[r];
+}
+
+// partial sums for 9 trial step lengths alpha_j = 2^-j (j = 0..7) and alpha = 0 (index 8):
+// part[j * kRedBlocksGN + block] = sum_r q_eps_r f_r(u + alpha_j d)^2; also the directional
+// term part[9 * kRedBlocksGN + block] = sum_r q_eps_r f_r(u) (J d)_r with J from aval
+constexpr int kRedBlocksGN = 256;
+__global__ __launch_bounds__(256) void k_burgers_trials(int64_t nx, int64_t nt, double dt, double nu,
+                                                        const double* __restrict__ mass, const double* __restrict__ s3,
+                                                        const double* __restrict__ u, const double* __restrict__ d,
+                                                        const double* __restrict__ y, const double* __restrict__ qeps,
+                                                        const int64_t* __restrict__ arp, const int32_t* __restrict__ aci,
+                                                        const double* __restrict__ aval, double* __restrict__ part) {
+  __shared__ double red[256];
+  const int64_t m = nx * nt;
+  double acc[10];
+#pragma unroll
+  for (int j = 0; j < 10; ++j) acc[j] = 0.0;
+  for (int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x; r < m; r += (int64_t)kRedBlocksGN * 256) {
+    const double w = qeps[r];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const double f = burg_resid(r, nx, dt, nu, mass, s3, u, d, ldexp(1.0, -j), y);
+      acc[j] += w * f * f;
+    }
+    const double f0 = burg_resid(r, nx, dt, nu, mass, s3, u, d, 0.0, y);
+    acc[8] += w * f0 * f0;
+    double jd = 0.0;
+    for (int64_t e = arp[r]; e < arp[r + 1]; ++e) jd += aval[e] * d[aci[e]];
+    acc[9] += w * f0 * jd;
+  }
+  for (int j = 0; j < 10; ++j) {
+    red[threadIdx.x] = acc[j];
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+      if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) part[j * kRedBlocksGN + blockIdx.x] = red[0];
+    __syncthreads();
+  }
+}
+
+// Sums the partials in a fixed order and picks the step: quad[0] = u^T Q u,
+// quad[1] = u^T Q d, quad[2] = d^T Q d; phi(alpha) = 1/2 (u+ad)^T Q (u+ad) + 1/2 data(alpha);
+// Armijo with c = 1e-4 on the first of alpha = 1, 1/2, ..., 1/128 that passes (else the
+// last); writes alpha to sel[0] and the iteration record (phi0, alpha, decrement,
+// slope) to rec[0..3].
+__global__ void k_gn_select(const double* __restrict__ part, const double* __restrict__ quad,
+                            double* __restrict__ sel, double* __restrict__ rec) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double data[10];
+  for (int j = 0; j < 10; ++j) {
+    double s = 0.0;
+    for (int b = 0; b < kRedBlocksGN; ++b) s += part[j * kRedBlocksGN + b];
+    data[j] = s;
+  }
+  const double uQu = quad[0], uQd = quad[1], dQd = quad[2];
+  const double phi0 = 0.5 * uQu + 0.5 * data[8];
+  const double slope = uQd + data[9];          // grad phi^T d
+  double alpha = ldexp(1.0, -7);
+  for (int j = 0; j < 8; ++j) {
+    const double a = ldexp(1.0, -j);
+    const double phi = 0.5 * (uQu + 2.0 * a * uQd + a * a * dQd) + 0.5 * data[j];
+    if (phi <= phi0 + 1e-4 * a * slope) { alpha = a; break; }
+  }
+  sel[0] = alpha;
+  rec[0] = phi0;
+  rec[1] = alpha;
+  rec[2] = -slope;                              // Newton decrement lambda^2 = -grad^T d
+  rec[3] = slope;
+}
+
+// d = x - u (GN direction from the linearised posterior mean x); then u += sel[0] * d
+__global__ void k_gn_direction(int64_t n, const double* __restrict__ x, const double* __restrict__ u,
+                               double* __restrict__ d) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    d[i] = x[i] - u[i];
+}
+__global__ void k_gn_update(int64_t n, const double* __restrict__ sel, const double* __restrict__ d,
+                            double* __restrict__ u) {
+  const double a = sel[0];
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    u[i] += a * d[i];
+}
+
 constexpr int kRedBlocks = 512;
 
 // deterministic two-pass sum of a[i]*b[i] (b == nullptr: a[i]^2)
@@ -1318,6 +1446,25 @@ void launch_weighted_resid(hipStream_t st, int64_t m, const int64_t* arp, const 
                            const double* qeps, const double* y, const double* b, const double* x, double* w) {
   if (m <= 0) return;
   hipLaunchKernelGGL(k_weighted_resid, dim3(grid_for(m)), dim3(kThreads), 0, st, m, arp, aci, aval, qeps, y, b, x, w);
+}
+void launch_burgers_linearize(hipStream_t st, int64_t nx, int64_t nt, double dt, double nu, const double* mass,
+                              const double* s3, const double* u, const int64_t* arp, double* aval, double* b) {
+  hipLaunchKernelGGL(k_burgers_linearize, dim3(grid_for(nx * nt)), dim3(kThreads), 0, st, nx, nt, dt, nu, mass, s3, u,
+                     arp, aval, b);
+}
+void launch_gn_linesearch(hipStream_t st, int64_t nx, int64_t nt, double dt, double nu, const double* mass,
+                          const double* s3, const double* u, const double* d, const double* y, const double* qeps,
+                          const int64_t* arp, const int32_t* aci, const double* aval, double* part,
+                          const double* quad, double* sel, double* rec) {
+  hipLaunchKernelGGL(k_burgers_trials, dim3(kRedBlocksGN), dim3(256), 0, st, nx, nt, dt, nu, mass, s3, u, d, y, qeps,
+                     arp, aci, aval, part);
+  hipLaunchKernelGGL(k_gn_select, dim3(1), dim3(64), 0, st, (const double*)part, quad, sel, rec);
+}
+void launch_gn_direction(hipStream_t st, int64_t n, const double* x, const double* u, double* d) {
+  hipLaunchKernelGGL(k_gn_direction, dim3(grid_for(n)), dim3(kThreads), 0, st, n, x, u, d);
+}
+void launch_gn_update(hipStream_t st, int64_t n, const double* sel, const double* d, double* u) {
+  hipLaunchKernelGGL(k_gn_update, dim3(grid_for(n)), dim3(kThreads), 0, st, n, sel, d, u);
 }
 void launch_add(hipStream_t st, int64_t n, const double* a, const double* b, double* out) {
   hipLaunchKernelGGL(k_add, dim3(grid_for(n)), dim3(kThreads), 0, st, n, a, b, out);
