@@ -48,6 +48,7 @@ enum : int { ST_ASSEMBLED = 1, ST_ANALYZED = 2, ST_FACTORED = 4, ST_SOLVED = 8 }
 
 struct HostList {  // a launch list before upload
   int64_t f_off = 0, p_off = 0;
+  int64_t m_off = -1;   // offset of the work-group map, -1 if the list has none
   int32_t count = 0;
   int64_t total = 0;
   double flops = 0.0;   // algorithmic flops of the launch
@@ -108,6 +109,7 @@ struct gmrf_ctx {
   DevArr<int64_t> d_map_e, d_map_off;
   DevArr<int32_t> d_lfronts;
   DevArr<int64_t> d_lprefix;
+  DevArr<int2> d_wgmap;
   DevArr<int64_t> d_bptr, d_D2off;
   int64_t D2size = 0;
   DevArr<int32_t> d_bpiv;
@@ -117,7 +119,7 @@ struct gmrf_ctx {
   int64_t bpart_max = 0;  // largest backward-solve partial launch (work-groups)
 
   int prec = -1;
-  DevArr<char> d_L, d_D, d_D2, d_W0, d_W1, d_Y, d_part;
+  DevArr<char> d_L, d_D, d_D2, d_D2T, d_W0, d_W1, d_Y, d_part;
   DevArr<double> d_piv, d_V0, d_V1, d_xp, d_w, d_r, d_red, d_norm, d_ld, d_mu_post, d_bpart;
   DevArr<int32_t> d_status;
   int refine_iters = 0;
@@ -247,8 +249,11 @@ int64_t find_entry(const std::vector<int64_t>& rp, const std::vector<int32_t>& c
 struct Cost { double flops, elems; };
 
 struct ListBuilder {
+  // work-group maps beyond this many entries are not kept (kernels then search the prefix)
+  static constexpr int64_t kMaxMap = int64_t(1) << 27;
   std::vector<int32_t> fronts;
   std::vector<int64_t> prefix;
+  std::vector<int2> wgmap;
   template <typename F>
   HostList add(const std::vector<int32_t>& cand, F tiles) {
     return add(cand, tiles, [](int32_t) { return Cost{0.0, 0.0}; });
@@ -272,6 +277,13 @@ struct ListBuilder {
     }
     prefix.push_back(tot);
     L.total = tot;
+    if (L.count > 1 && (int64_t)wgmap.size() + tot <= kMaxMap) {
+      L.m_off = (int64_t)wgmap.size();
+      for (int32_t i = 0; i < L.count; ++i) {
+        const int64_t a = prefix[L.p_off + i], b = prefix[L.p_off + i + 1];
+        for (int64_t w = a; w < b; ++w) wgmap.push_back(make_int2(i, (int)(w - a)));
+      }
+    }
     return L;
   }
 };
@@ -280,6 +292,7 @@ LaunchList dev_list(const gmrf_ctx* h, const HostList& L) {
   LaunchList d;
   d.fronts = h->d_lfronts.p + L.f_off;
   d.prefix = h->d_lprefix.p + L.p_off;
+  d.wgmap = L.m_off >= 0 ? h->d_wgmap.p + L.m_off : nullptr;
   d.count = L.count;
   d.total = L.total;
   return d;
@@ -474,7 +487,7 @@ gmrf_status build_plan(gmrf_t h) {
       auto fact = [&](int32_t s) { return pF(s) > (int64_t)t * kNB2; };
       auto fkb2 = [&](int32_t s) { return std::min<int64_t>(kNB2, pF(s) - (int64_t)t * kNB2); };
       auto fbelow = [&](int32_t s) { return nF(s) - (int64_t)t * kNB2 - fkb2(s); };
-      lv.fblk.push_back(B.add(lv.fronts, [&](int32_t s) -> int64_t { return fact(s) ? 1 : 0; },
+      lv.fblk.push_back(B.add(lv.fronts, [&](int32_t s) -> int64_t { return fact(s) ? (fkb2(s) + 63) / 64 : 0; },
                               [&](int32_t s) { const double b = (double)fkb2(s); return Cost{b * b, 0.5 * b * b}; }));
       lv.fout.push_back(B.add(lv.fronts, [&](int32_t s) -> int64_t {
         return fact(s) ? (fbelow(s) + 63) / 64 : 0;
@@ -489,7 +502,7 @@ gmrf_status build_plan(gmrf_t h) {
         return Cost{2.0 * r * b, r * b};
       }));
       h->bpart_max = std::max(h->bpart_max, lv.bpart.back().total);
-      lv.bblk.push_back(B.add(lv.fronts, [&](int32_t s) -> int64_t { return oact(s) ? 1 : 0; },
+      lv.bblk.push_back(B.add(lv.fronts, [&](int32_t s) -> int64_t { return oact(s) ? (okb2(s) + 63) / 64 : 0; },
                               [&](int32_t s) { const double b = (double)okb2(s); return Cost{b * b, 0.5 * b * b}; }));
       lv.sfin2.push_back(B.add(lv.fronts, [&](int32_t s) -> int64_t { return oact(s) ? onsub(s) * onsub(s) : 0; },
                                [&](int32_t s) { const double b = (double)okb2(s); return Cost{b * b * b / 3.0, 2.0 * b * b}; }));
@@ -513,6 +526,7 @@ gmrf_status build_plan(gmrf_t h) {
   hipStream_t st = h->stream;
   HIPCHK(h, upload(h->d_lfronts, B.fronts, st));
   HIPCHK(h, upload(h->d_lprefix, B.prefix, st));
+  HIPCHK(h, upload(h->d_wgmap, B.wgmap, st));
   HIPCHK(h, upload(h->d_map_e, map_e, st));
   HIPCHK(h, upload(h->d_map_off, map_off, st));
   HIPCHK(h, upload(h->d_perm, Y.perm, st));
@@ -563,6 +577,7 @@ gmrf_status alloc_numeric(gmrf_t h) {
   HIPCHK(h, h->d_L.alloc((size_t)Y.Lsize * sizeof(T)));
   HIPCHK(h, h->d_D.alloc((size_t)Y.Dsize * sizeof(T)));
   HIPCHK(h, h->d_D2.alloc((size_t)std::max<int64_t>(h->D2size, 1) * sizeof(T)));
+  HIPCHK(h, h->d_D2T.alloc((size_t)std::max<int64_t>(h->D2size, 1) * sizeof(T)));
   HIPCHK(h, h->d_W0.alloc((size_t)std::max<int64_t>(Y.Wsize[0], 1) * sizeof(T)));
   HIPCHK(h, h->d_W1.alloc((size_t)std::max<int64_t>(Y.Wsize[1], 1) * sizeof(T)));
   HIPCHK(h, h->d_piv.alloc(h->n));
@@ -621,7 +636,8 @@ gmrf_status run_factor(gmrf_t h) {
       prof_launch(h, KC_SYRK, lv.syrk.flops, lv.syrk.elems,
                   [&] { launch_update<T>(st, S, dev_list(h, lv.syrk), 0, 2, B); });
     prof_launch(h, KC_POTRF, lv.inv256.flops, lv.inv256.elems, [&] {
-      launch_inv256<T>(st, S, dev_list(h, lv.inv256), B.Wcur, 1, B.D, h->d_D2off.p, (T*)h->d_D2.p);
+      launch_inv256<T>(st, S, dev_list(h, lv.inv256), B.Wcur, 1, B.D, h->d_D2off.p, (T*)h->d_D2.p,
+                       (T*)h->d_D2T.p);
     });
     prof_launch(h, KC_COPYL, 0.0, lv.copyL.elems, [&] { launch_copy_L<T>(st, S, dev_list(h, lv.copyL), B); });
   }
@@ -676,7 +692,7 @@ void run_solve(gmrf_t h, int nrhs, bool forward) {
     for (int t = 0; t < lv.nsteps2; ++t) {
       prof_launch(h, KC_BWD, nrhs * (lv.bpart[t].flops + lv.bblk[t].flops), lv.bpart[t].elems + lv.bblk[t].elems, [&] {
         launch_bwd_part<T>(st, S, dev_list(h, lv.bpart[t]), t, Lp, B, h->d_bpart.p);
-        launch_bwd_block<T>(st, S, dev_list(h, lv.bblk[t]), dev_list(h, lv.bpart[t]), t, (const T*)h->d_D2.p,
+        launch_bwd_block<T>(st, S, dev_list(h, lv.bblk[t]), dev_list(h, lv.bpart[t]), t, (const T*)h->d_D2T.p,
                             h->d_D2off.p, B, h->d_bpart.p);
       });
     }

@@ -30,6 +30,7 @@ struct DevSym {
 struct LaunchList {
   const int32_t* fronts;
   const int64_t* prefix;
+  const int2* wgmap;        // per work-group (list index, local index), or null
   int32_t count;
   int64_t total;            // number of work-groups
 };
@@ -93,13 +94,13 @@ template <typename T> void launch_fwd_block(hipStream_t st, const DevSym& S, con
                                             const T* D2, const int64_t* D2off, SolveBufs V);
 // inverses of the 256-wide diagonal blocks (Lbase: front buffer if from_front, else L storage)
 template <typename T> void launch_inv256(hipStream_t st, const DevSym& S, const LaunchList& L, const T* Lbase,
-                                         int from_front, const T* Dinv, const int64_t* D2off, T* D2);
+                                         int from_front, const T* Dinv, const int64_t* D2off, T* D2, T* D2T);
 template <typename T> void launch_fwd_outer(hipStream_t st, const DevSym& S, const LaunchList& L, int t,
                                             const T* Lp, SolveBufs V);
 template <typename T> void launch_bwd_part(hipStream_t st, const DevSym& S, const LaunchList& L, int t,
                                            const T* Lp, SolveBufs V, double* part);
 template <typename T> void launch_bwd_block(hipStream_t st, const DevSym& S, const LaunchList& L,
-                                            const LaunchList& Lpart, int t, const T* D2, const int64_t* D2off,
+                                            const LaunchList& Lpart, int t, const T* D2T, const int64_t* D2off,
                                             SolveBufs V, const double* part);
 void launch_permute_in(hipStream_t st, int64_t n, int nrhs, const int32_t* perm, const double* scale,
                        const double* src, int64_t lds, double* xp);

@@ -40,8 +40,21 @@ __device__ __forceinline__ V4<float>::type mfma(float a, float b, V4<float>::typ
 __device__ __forceinline__ int fn(const DevSym& S, int s) { return (int)(S.rowptr[s + 1] - S.rowptr[s]); }
 __device__ __forceinline__ int fp(const DevSym& S, int s) { return S.sfirst[s + 1] - S.sfirst[s]; }
 
-// work-group -> (list index, local work-group index) by binary search on the prefix
+// work-group -> (list index, local work-group index): one load from the list's
+// work-group map; lists without a map (a single front, or a map too large to keep)
+// fall back to a binary search on the prefix
 __device__ __forceinline__ void find_front(const LaunchList& L, int64_t wg, int& fi, int64_t& loc) {
+  if (L.count == 1) {
+    fi = 0;
+    loc = wg;
+    return;
+  }
+  if (L.wgmap) {
+    const int2 m = L.wgmap[wg];
+    fi = m.x;
+    loc = m.y;
+    return;
+  }
   int lo = 0, hi = L.count - 1;
   while (lo < hi) {
     int mid = (lo + hi + 1) >> 1;
@@ -636,88 +649,130 @@ __global__ __launch_bounds__(kThreads) void k_fvec_extend(DevSym S, LaunchList L
 }
 
 // ---- solves blocked by 256-wide outer blocks ----
-// Forward, one work-group per front and outer block t (left to right):
-// x_K = Linv_KK v_K with the stored inverse of the 256-wide diagonal block; x is written
-// to the front vector and to the pivot-order vector.
-template <typename T>
+// The top separators turn the solves into a chain of short launches, so each launch is
+// latency bound: every kernel keeps batches of 16-32 independent loads in flight per
+// lane, and LDS is sized for NR right-hand sides (NR = 1, or 16 for the general case,
+// nrhs <= NR) so that the many small fronts of the deep levels run at full occupancy.
+template <int NR> struct RhsPad { static constexpr int v = NR == 1 ? 1 : NR + 1; };
+
+// Forward, diagonal block of outer block t (left to right): x_K = Linv_KK v_K with the
+// stored inverse.  Work-group (front, g) computes rows 64g..64g+63; its four waves take a
+// quarter of the columns each and add their sums in a fixed order.  x_K goes to the
+// pivot-order vector only, because the other work-groups of the launch still read v_K.
+template <typename T, int NR>
 __global__ __launch_bounds__(kThreads) void k_fwd_block(DevSym S, LaunchList L, int t, const T* __restrict__ D2,
                                                         const int64_t* __restrict__ D2off, SolveBufs V) {
-  __shared__ double xv[kNB2 * 16];
-  const int s = L.fronts[blockIdx.x];
+  constexpr int NP = RhsPad<NR>::v;
+  __shared__ double xv[kNB2 * NR];
+  __shared__ double red[kThreads * NP];
+  int fi; int64_t loc;
+  find_front(L, wg_id(), fi, loc);
+  const int s = L.fronts[fi], g = (int)loc;
   const int n = fn(S, s), p = fp(S, s);
-  const int nr = V.nrhs;
+  const int nr = NR == 1 ? 1 : V.nrhs;
   const int k2 = t * kNB2, kb2 = min(kNB2, p - k2);
-  double* v = V.Vcur + S.Voff[s] * nr;
+  const int lend = 64 * g + 64;
+  const double* v = V.Vcur + S.Voff[s] * nr;
   const T* X = D2 + D2off[s] + (int64_t)t * kNB2 * kNB2;
-  for (int idx = threadIdx.x; idx < kb2 * nr; idx += kThreads) {
-    const int i = idx % kb2, r = idx / kb2;
-    xv[i + r * kNB2] = v[k2 + i + r * n];
+  for (int idx = threadIdx.x; idx < lend * nr; idx += kThreads) {
+    const int l = idx % lend, r = idx / lend;
+    xv[l + r * kNB2] = l < kb2 ? v[k2 + l + (int64_t)r * n] : 0.0;
   }
   __syncthreads();
-  for (int idx = threadIdx.x; idx < kb2 * nr; idx += kThreads) {
-    const int i = idx % kb2, r = idx / kb2;
-    double acc = 0.0;
-    for (int l = 0; l <= i; ++l) acc += (double)X[i + (int64_t)l * kb2] * xv[l + r * kNB2];
-    v[k2 + i + r * n] = acc;
-    V.xp[S.sfirst[s] + k2 + i + (int64_t)r * S.n] = acc;
+  const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
+  const int i = 64 * g + lane;
+  double acc[NR];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) acc[r] = 0.0;
+  if (q <= g && i < kb2) {
+    for (int l0 = 64 * q; l0 < 64 * q + 64; l0 += 16) {
+      double xl[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) xl[u] = l0 + u <= i ? (double)X[i + (int64_t)(l0 + u) * kb2] : 0.0;
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+#pragma unroll
+        for (int r = 0; r < NR; ++r)
+          if (r < nr) acc[r] += xl[u] * xv[l0 + u + r * kNB2];
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < NR; ++r) red[threadIdx.x * NP + r] = acc[r];
+  __syncthreads();
+  if (q == 0 && i < kb2) {
+    for (int r = 0; r < nr; ++r)
+      V.xp[S.sfirst[s] + k2 + i + (int64_t)r * S.n] = (red[lane * NP + r] + red[(64 + lane) * NP + r]) +
+                                                      (red[(128 + lane) * NP + r] + red[(192 + lane) * NP + r]);
   }
 }
 
 // Forward, rows below outer block t: v[rows] -= L[rows, K] x_K; 64 rows per work-group,
 // the 256 columns split over the 4 waves and reduced through LDS.
-template <typename T>
+template <typename T, int NR>
 __global__ __launch_bounds__(kThreads) void k_fwd_outer(DevSym S, LaunchList L, int t, const T* __restrict__ Lp,
                                                         SolveBufs V) {
-  __shared__ double xs[kNB2 * 16];
-  __shared__ double red[4][64][17];
+  constexpr int NP = RhsPad<NR>::v;
+  __shared__ double xs[kNB2 * NR];
+  __shared__ double red[kThreads * NP];
   int fi; int64_t loc;
   find_front(L, wg_id(), fi, loc);
   const int s = L.fronts[fi];
   const int n = fn(S, s), p = fp(S, s);
-  const int nr = V.nrhs;
+  const int nr = NR == 1 ? 1 : V.nrhs;
   const int k2 = t * kNB2, kb2 = min(kNB2, p - k2);
+  const int64_t f0 = S.sfirst[s];
   double* v = V.Vcur + S.Voff[s] * nr;
-  for (int idx = threadIdx.x; idx < kb2 * nr; idx += kThreads) {
-    const int i = idx % kb2, r = idx / kb2;
-    xs[i + r * kNB2] = v[k2 + i + r * n];
+  for (int idx = threadIdx.x; idx < kNB2 * nr; idx += kThreads) {
+    const int i = idx % kNB2, r = idx / kNB2;
+    xs[i + r * kNB2] = i < kb2 ? V.xp[f0 + k2 + i + (int64_t)r * S.n] : 0.0;
   }
   __syncthreads();
   const int i = threadIdx.x & 63, cg = threadIdx.x >> 6;
   const int row = k2 + kb2 + 64 * (int)loc + i;
-  double acc[16];
+  double acc[NR];
 #pragma unroll
-  for (int r = 0; r < 16; ++r) acc[r] = 0.0;
+  for (int r = 0; r < NR; ++r) acc[r] = 0.0;
   if (row < n) {
     const T* Lr = Lp + S.Loff[s] + row + (int64_t)k2 * n;
-    for (int c = cg * 64; c < min(kb2, cg * 64 + 64); ++c) {
-      const double l = (double)Lr[(int64_t)c * n];
+    const int c0 = cg * 64, c1 = min(kb2, c0 + 64);
+    for (int cb = c0; cb < c1; cb += 16) {
+      double lv[16];
 #pragma unroll
-      for (int r = 0; r < 16; ++r)
-        if (r < nr) acc[r] += l * xs[c + r * kNB2];
+      for (int u = 0; u < 16; ++u) lv[u] = cb + u < c1 ? (double)Lr[(int64_t)(cb + u) * n] : 0.0;
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+#pragma unroll
+        for (int r = 0; r < NR; ++r)
+          if (r < nr) acc[r] += lv[u] * xs[cb + u + r * kNB2];
+      }
     }
   }
 #pragma unroll
-  for (int r = 0; r < 16; ++r)
-    if (r < nr) red[cg][i][r] = acc[r];
+  for (int r = 0; r < NR; ++r) red[threadIdx.x * NP + r] = acc[r];
   __syncthreads();
   if (cg == 0 && row < n) {
     for (int r = 0; r < nr; ++r)
-      v[row + r * n] -= (red[0][i][r] + red[1][i][r]) + (red[2][i][r] + red[3][i][r]);
+      v[row + (int64_t)r * n] -= (red[i * NP + r] + red[(64 + i) * NP + r]) +
+                                 (red[(128 + i) * NP + r] + red[(192 + i) * NP + r]);
   }
 }
 
 // Backward split-K partials for outer block t (from the right): work-group (front,
-// chunk of 256 rows below the block) computes part = L[chunk, K]^T x[chunk] (256 x nrhs)
-template <typename T>
+// chunk of 256 rows below the block) computes part = L[chunk, K]^T x[chunk] (256 x nrhs);
+// the front's first work-group also subtracts the right-hand side y_K, so that
+// r_K = -(sum of the front's partials).
+template <typename T, int NR>
 __global__ __launch_bounds__(kThreads) void k_bwd_part(DevSym S, LaunchList L, int t, const T* __restrict__ Lp,
                                                        SolveBufs V, double* __restrict__ part) {
+  constexpr int NP = RhsPad<NR>::v;
   __shared__ T Ls[32][kNB2 + 1];
-  __shared__ double Xs[32][17];
+  __shared__ double Xs[32 * NP];
   int fi; int64_t loc;
   find_front(L, wg_id(), fi, loc);
   const int s = L.fronts[fi];
   const int n = fn(S, s), p = fp(S, s);
-  const int nr = V.nrhs;
+  const int nr = NR == 1 ? 1 : V.nrhs;
   const int nK = (p + kNB2 - 1) / kNB2, K = nK - 1 - t;
   const int k2 = K * kNB2, kb2 = min(kNB2, p - k2);
   const int rs = k2 + kb2;
@@ -725,79 +780,131 @@ __global__ __launch_bounds__(kThreads) void k_bwd_part(DevSym S, LaunchList L, i
   const int32_t* rows = S.rows + S.rowptr[s];
   const T* Lf = Lp + S.Loff[s];
   const int c = threadIdx.x;
-  double acc[16];
+  double acc[NR];
 #pragma unroll
-  for (int r = 0; r < 16; ++r) acc[r] = 0.0;
+  for (int r = 0; r < NR; ++r) acc[r] = 0.0;
   for (int i0 = r0; i0 < r1; i0 += 32) {
     const int mi = min(32, r1 - i0);
-    for (int idx = threadIdx.x; idx < 32 * kNB2; idx += kThreads) {
+    T tmp[32];
+#pragma unroll
+    for (int k = 0; k < 32; ++k) {
+      const int idx = threadIdx.x + k * kThreads;
       const int ii = idx & 31, cc = idx >> 5;
-      Ls[ii][cc] = (ii < mi && cc < kb2) ? Lf[(i0 + ii) + (int64_t)(k2 + cc) * n] : T(0);
+      tmp[k] = (ii < mi && cc < kb2) ? Lf[(i0 + ii) + (int64_t)(k2 + cc) * n] : T(0);
     }
     for (int idx = threadIdx.x; idx < 32 * nr; idx += kThreads) {
       const int ii = idx & 31, r = idx >> 5;
-      Xs[ii][r] = ii < mi ? V.xp[rows[i0 + ii] + (int64_t)r * S.n] : 0.0;
+      Xs[ii * NP + r] = ii < mi ? V.xp[rows[i0 + ii] + (int64_t)r * S.n] : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < 32; ++k) {
+      const int idx = threadIdx.x + k * kThreads;
+      Ls[idx & 31][idx >> 5] = tmp[k];
     }
     __syncthreads();
-    for (int ii = 0; ii < mi; ++ii) {
+#pragma unroll 8
+    for (int ii = 0; ii < 32; ++ii) {
       const double l = (double)Ls[ii][c];
 #pragma unroll
-      for (int r = 0; r < 16; ++r)
-        if (r < nr) acc[r] += l * Xs[ii][r];
+      for (int r = 0; r < NR; ++r)
+        if (r < nr) acc[r] += l * Xs[ii * NP + r];
     }
     __syncthreads();
   }
+  if (loc == 0 && c < kb2) {
+    const int64_t f0 = S.sfirst[s];
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+      if (r < nr) acc[r] -= V.xp[f0 + k2 + c + (int64_t)r * S.n];
+  }
   double* out = part + wg_id() * (int64_t)(kNB2 * 16);
 #pragma unroll
-  for (int r = 0; r < 16; ++r)
+  for (int r = 0; r < NR; ++r)
     if (r < nr) out[c + r * kNB2] = acc[r];
 }
 
-// Backward, one work-group per front and outer block t (from the right):
-// r_K = y_K - sum of the partials, x_K = Linv_KK^T r_K, written to the pivot vector.
-template <typename T>
+// Backward, diagonal block from the right: r_K = -(sum of the partials) and
+// x_K = Linv_KK^T r_K, read from the stored transpose XT of the inverse so that lanes
+// walk rows.  Work-group (front, g) computes x for columns 64g..64g+63: it first forms
+// r_l for l >= 64g (the threads splitting the partials when fewer l remain), then the
+// four waves take a quarter of l each.
+template <typename T, int NR>
 __global__ __launch_bounds__(kThreads) void k_bwd_block(DevSym S, LaunchList L, LaunchList Lpart, int t,
-                                                        const T* __restrict__ D2, const int64_t* __restrict__ D2off,
-                                                        SolveBufs V, const double* __restrict__ part) {
-  __shared__ double rv[kNB2 * 16];
-  const int fi = blockIdx.x;
-  const int s = L.fronts[fi];
+                                                        const T* __restrict__ D2T,
+                                                        const int64_t* __restrict__ D2off, SolveBufs V,
+                                                        const double* __restrict__ part) {
+  constexpr int NP = RhsPad<NR>::v;
+  __shared__ double rv[kNB2 * NR];
+  __shared__ double red[kThreads * NP];
+  int fi; int64_t loc;
+  find_front(L, wg_id(), fi, loc);
+  const int s = L.fronts[fi], g = (int)loc;
   const int p = fp(S, s);
-  const int nr = V.nrhs;
+  const int nr = NR == 1 ? 1 : V.nrhs;
   const int nK = (p + kNB2 - 1) / kNB2, K = nK - 1 - t;
   const int k2 = K * kNB2, kb2 = min(kNB2, p - k2);
   const int64_t f0 = S.sfirst[s];
   const int64_t q0 = Lpart.prefix[fi], q1 = Lpart.prefix[fi + 1];
-  const T* X = D2 + D2off[s] + (int64_t)K * kNB2 * kNB2;
-  for (int idx = threadIdx.x; idx < kb2 * nr; idx += kThreads) {
-    const int i = idx % kb2, r = idx / kb2;
-    double sp = 0.0;
-    for (int64_t q = q0; q < q1; ++q) sp += part[q * (kNB2 * 16) + i + r * kNB2];
-    rv[i + r * kNB2] = V.xp[f0 + k2 + i + (int64_t)r * S.n] - sp;
-  }
-  __syncthreads();
-  // x_i = sum_{l >= i} X[l][i] r_l: column i of X is contiguous, so one wave sweeps it with
-  // coalesced loads and reduces across its lanes
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  for (int i = wv; i < kb2; i += kThreads / 64) {
-    const T* Xc = X + (int64_t)i * kb2;
-    double acc[16];
+  const T* XT = D2T + D2off[s] + (int64_t)K * kNB2 * kNB2;
+  const int l0 = 64 * g;
+  const int nch = (kb2 - l0 + 63) / 64;           // 1..4 chunks of l
+  const int split = 4 / nch;                      // threads per l
+  const int span = 64 * nch;
+  const int li = threadIdx.x % span, pid = threadIdx.x / span;
+  {
+    double acc[NR];
 #pragma unroll
-    for (int r = 0; r < 16; ++r) acc[r] = 0.0;
-    for (int l = i + lane; l < kb2; l += 64) {
-      const double xv = (double)Xc[l];
+    for (int r = 0; r < NR; ++r) acc[r] = 0.0;
+    const int l = l0 + li;
+    if (pid < split && l < kb2) {
+#pragma unroll 8
+      for (int64_t q = q0 + pid; q < q1; q += split) {
+        const double* pq = part + q * (kNB2 * 16) + l;
 #pragma unroll
-      for (int r = 0; r < 16; ++r)
-        if (r < nr) acc[r] += xv * rv[l + r * kNB2];
-    }
-#pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      if (r < nr) {
-        double a = acc[r];
-        for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off, 64);
-        if (lane == 0) V.xp[f0 + k2 + i + (int64_t)r * S.n] = a;
+        for (int r = 0; r < NR; ++r)
+          if (r < nr) acc[r] += pq[r * kNB2];
       }
     }
+#pragma unroll
+    for (int r = 0; r < NR; ++r) red[threadIdx.x * NP + r] = acc[r];
+    __syncthreads();
+    if (pid == 0) {
+      for (int r = 0; r < nr; ++r) {
+        double a = red[li * NP + r];
+        for (int pp = 1; pp < split; ++pp) a += red[(pp * span + li) * NP + r];
+        rv[l + r * kNB2] = l < kb2 ? -a : 0.0;
+      }
+    }
+    __syncthreads();
+  }
+  const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
+  const int i = l0 + lane;
+  double acc[NR];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) acc[r] = 0.0;
+  if (q >= g && 64 * q < kb2 && i < kb2) {
+    for (int lb = 64 * q; lb < 64 * q + 64; lb += 16) {
+      double xl[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int l = lb + u;
+        xl[u] = (l >= i && l < kb2) ? (double)XT[i + (int64_t)l * kb2] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+#pragma unroll
+        for (int r = 0; r < NR; ++r)
+          if (r < nr) acc[r] += xl[u] * rv[lb + u + r * kNB2];
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < NR; ++r) red[threadIdx.x * NP + r] = acc[r];
+  __syncthreads();
+  if (q == 0 && i < kb2) {
+    for (int r = 0; r < nr; ++r)
+      V.xp[f0 + k2 + i + (int64_t)r * S.n] = (red[lane * NP + r] + red[(64 + lane) * NP + r]) +
+                                             (red[(128 + lane) * NP + r] + red[(192 + lane) * NP + r]);
   }
 }
 
@@ -1095,7 +1202,8 @@ __device__ __forceinline__ OuterBlk outer_blk(int p, int n, int step) {
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_inv256(DevSym S, LaunchList L, const T* __restrict__ Lbase,
                                                      int from_front, const T* __restrict__ Dinv,
-                                                     const int64_t* __restrict__ D2off, T* __restrict__ D2) {
+                                                     const int64_t* __restrict__ D2off, T* __restrict__ D2,
+                                                     T* __restrict__ D2T) {
   __shared__ T sA[kTK * kP];
   __shared__ T sB[kTK * kP];
   int fi; int64_t loc;
@@ -1107,6 +1215,7 @@ __global__ __launch_bounds__(kThreads) void k_inv256(DevSym S, LaunchList L, con
   const int nsub = (kb2 + kNB - 1) / kNB;
   const int sbj = min(kNB, kb2 - kNB * j);
   T* X = D2 + D2off[s] + (int64_t)K * kNB2 * kNB2;
+  T* XT = D2T + D2off[s] + (int64_t)K * kNB2 * kNB2;
   const T* Lf = Lbase + (from_front ? S.Woff[s] : S.Loff[s]);
   const int blk0 = k2 / kNB;
   for (int idx = threadIdx.x; idx < kb2 * kNB; idx += kThreads) {
@@ -1117,6 +1226,13 @@ __global__ __launch_bounds__(kThreads) void k_inv256(DevSym S, LaunchList L, con
         v = Dinv[S.Doff[s] + (int64_t)(blk0 + j) * kNB * kNB + (r - kNB * j) + c * kNB];
       X[r + (int64_t)(kNB * j + c) * kb2] = v;
     }
+  }
+  for (int idx = threadIdx.x; idx < kb2 * sbj; idx += kThreads) {
+    const int c = idx % sbj, r = idx / sbj;
+    T v = T(0);
+    if (r >= kNB * j && r < kNB * j + sbj)
+      v = Dinv[S.Doff[s] + (int64_t)(blk0 + j) * kNB * kNB + (r - kNB * j) + c * kNB];
+    XT[(kNB * j + c) + (int64_t)r * kb2] = v;
   }
   __threadfence();
   __syncthreads();
@@ -1136,8 +1252,12 @@ __global__ __launch_bounds__(kThreads) void k_inv256(DevSym S, LaunchList L, con
     gemm_tile<T, false, true>(Dinv + S.Doff[s] + (int64_t)(blk0 + i) * kNB * kNB, kNB, Xij, kb2, sbi, sbj, sbi,
                               acc, sA, sB);
     __syncthreads();
+    T* XTji = XT + kNB * j + (int64_t)(kNB * i) * kb2;
     for_acc<T>(acc, [&](int r, int c, T v) {
-      if (r < sbi && c < sbj) Xij[r + (int64_t)c * kb2] = -v;
+      if (r < sbi && c < sbj) {
+        Xij[r + (int64_t)c * kb2] = -v;
+        XTji[c + (int64_t)r * kb2] = -v;
+      }
     });
     __threadfence();
     __syncthreads();
@@ -1389,31 +1509,44 @@ template <typename T> void launch_fvec_extend(hipStream_t st, const DevSym& S, c
 }
 template <typename T> void launch_fwd_block(hipStream_t st, const DevSym& S, const LaunchList& L, int t,
                                             const T* D2, const int64_t* D2off, SolveBufs V) {
-  if (L.count <= 0) return;
-  hipLaunchKernelGGL(k_fwd_block<T>, dim3((unsigned)L.count), dim3(kThreads), 0, st, S, L, t, D2, D2off, V);
+  if (L.total <= 0) return;
+  if (V.nrhs == 1)
+    hipLaunchKernelGGL((k_fwd_block<T, 1>), dim3((unsigned)L.total), dim3(kThreads), 0, st, S, L, t, D2, D2off, V);
+  else
+    hipLaunchKernelGGL((k_fwd_block<T, 16>), dim3((unsigned)L.total), dim3(kThreads), 0, st, S, L, t, D2, D2off, V);
 }
 template <typename T> void launch_inv256(hipStream_t st, const DevSym& S, const LaunchList& L, const T* Lbase,
-                                         int from_front, const T* Dinv, const int64_t* D2off, T* D2) {
+                                         int from_front, const T* Dinv, const int64_t* D2off, T* D2, T* D2T) {
   if (L.total <= 0) return;
   hipLaunchKernelGGL(k_inv256<T>, dim3((unsigned)L.total), dim3(kThreads), 0, st, S, L, Lbase, from_front, Dinv,
-                     D2off, D2);
+                     D2off, D2, D2T);
 }
 template <typename T> void launch_fwd_outer(hipStream_t st, const DevSym& S, const LaunchList& L, int t,
                                             const T* Lp, SolveBufs V) {
   if (L.total <= 0) return;
-  hipLaunchKernelGGL(k_fwd_outer<T>, dim3((unsigned)L.total), dim3(kThreads), 0, st, S, L, t, Lp, V);
+  if (V.nrhs == 1)
+    hipLaunchKernelGGL((k_fwd_outer<T, 1>), dim3((unsigned)L.total), dim3(kThreads), 0, st, S, L, t, Lp, V);
+  else
+    hipLaunchKernelGGL((k_fwd_outer<T, 16>), dim3((unsigned)L.total), dim3(kThreads), 0, st, S, L, t, Lp, V);
 }
 template <typename T> void launch_bwd_part(hipStream_t st, const DevSym& S, const LaunchList& L, int t,
                                            const T* Lp, SolveBufs V, double* part) {
   if (L.total <= 0) return;
-  hipLaunchKernelGGL(k_bwd_part<T>, dim3((unsigned)L.total), dim3(kThreads), 0, st, S, L, t, Lp, V, part);
+  if (V.nrhs == 1)
+    hipLaunchKernelGGL((k_bwd_part<T, 1>), dim3((unsigned)L.total), dim3(kThreads), 0, st, S, L, t, Lp, V, part);
+  else
+    hipLaunchKernelGGL((k_bwd_part<T, 16>), dim3((unsigned)L.total), dim3(kThreads), 0, st, S, L, t, Lp, V, part);
 }
 template <typename T> void launch_bwd_block(hipStream_t st, const DevSym& S, const LaunchList& L,
-                                            const LaunchList& Lpart, int t, const T* D2, const int64_t* D2off,
+                                            const LaunchList& Lpart, int t, const T* D2T, const int64_t* D2off,
                                             SolveBufs V, const double* part) {
-  if (L.count <= 0) return;
-  hipLaunchKernelGGL(k_bwd_block<T>, dim3((unsigned)L.count), dim3(kThreads), 0, st, S, L, Lpart, t, D2, D2off, V,
-                     part);
+  if (L.total <= 0) return;
+  if (V.nrhs == 1)
+    hipLaunchKernelGGL((k_bwd_block<T, 1>), dim3((unsigned)L.total), dim3(kThreads), 0, st, S, L, Lpart, t, D2T,
+                       D2off, V, part);
+  else
+    hipLaunchKernelGGL((k_bwd_block<T, 16>), dim3((unsigned)L.total), dim3(kThreads), 0, st, S, L, Lpart, t, D2T,
+                       D2off, V, part);
 }
 void launch_permute_in(hipStream_t st, int64_t n, int nrhs, const int32_t* perm, const double* scale,
                        const double* src, int64_t lds, double* xp) {
@@ -1533,7 +1666,7 @@ template <typename T> void launch_sel_pattern(hipStream_t st, int64_t cnt, const
   template void launch_bwd_part<T>(hipStream_t, const DevSym&, const LaunchList&, int, const T*, SolveBufs, double*); \
   template void launch_bwd_block<T>(hipStream_t, const DevSym&, const LaunchList&, const LaunchList&, int, const T*, const int64_t*, SolveBufs, const double*); \
   template void launch_sel_gather<T>(hipStream_t, const DevSym&, const LaunchList&, const int32_t*, SelBufs<T>); \
-  template void launch_inv256<T>(hipStream_t, const DevSym&, const LaunchList&, const T*, int, const T*, const int64_t*, T*); \
+  template void launch_inv256<T>(hipStream_t, const DevSym&, const LaunchList&, const T*, int, const T*, const int64_t*, T*, T*); \
   template void launch_sel_Y2<T>(hipStream_t, const DevSym&, const LaunchList&, int, SelBufs<T>, const int64_t*, const T*); \
   template void launch_sel_gemm2<T>(hipStream_t, const DevSym&, const LaunchList&, int, SelBufs<T>); \
   template void launch_sel_part2<T>(hipStream_t, const DevSym&, const LaunchList&, int, SelBufs<T>); \
