@@ -116,12 +116,23 @@ def main():
     ap.add_argument("--small", action="store_true", help="16k-dof workload (debugging only)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--modes", default="fp32,fp64")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run three 1 GiB device-to-device copies (scale for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
                                    "(multi-GPU sharding of the elimination tree is not built)"}))
         sys.exit(2)
     import torch
+    if args.copy_calibration:
+        # a plain copy of known size: each dispatch reads and writes exactly 1 GiB of HBM
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes": 1 << 30, "dispatches": 3}))
+        return
     from paper_2503_08343_amd import binding
     binding.load()
     assert torch.cuda.is_available(), "no GPU visible"

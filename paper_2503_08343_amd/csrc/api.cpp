@@ -11,6 +11,9 @@
 #include <cmath>
 #include <cstring>
 #include <string>
+#include <type_traits>
+#include <unordered_map>
+#include <utility>
 #include <vector>
 
 #include "kernels.h"
@@ -49,6 +52,7 @@ enum : int { ST_ASSEMBLED = 1, ST_ANALYZED = 2, ST_FACTORED = 4, ST_SOLVED = 8 }
 struct HostList {  // a launch list before upload
   int64_t f_off = 0, p_off = 0;
   int64_t m_off = -1;   // offset of the work-group map, -1 if the list has none
+  int64_t a_off = -1;   // offset of the per-front aux pairs, -1 if the list has none
   int32_t count = 0;
   int64_t total = 0;
   double flops = 0.0;   // algorithmic flops of the launch
@@ -59,12 +63,12 @@ struct HostList {  // a launch list before upload
 enum KClass : int {
   KC_ASSEMBLE = 0, KC_EQUIL, KC_ZERO, KC_SCATTER, KC_EXTEND, KC_POTRF, KC_TRSM, KC_UPDATE,
   KC_SYRK, KC_COPYL, KC_LOGDET, KC_FWD, KC_BWD, KC_RESID, KC_PERMUTE, KC_SEL_GATHER, KC_SEL_Y,
-  KC_SEL_GEMM, KC_SEL_DIAG, KC_SEL_OUT, KC_COUNT
+  KC_SEL_GEMM, KC_SEL_DIAG, KC_SEL_OUT, KC_SEL_RED, KC_COUNT
 };
 const char* const kClassNames[KC_COUNT] = {
   "assemble", "equilibrate", "front_zero", "front_scatter", "extend_add", "potrf_diag", "trsm_panel",
   "update_panel", "syrk_update", "copy_L", "logdet", "solve_fwd", "solve_bwd", "residual",
-  "permute", "sel_gather", "sel_Y", "sel_gemm", "sel_diag", "sel_extract"};
+  "permute", "sel_gather", "sel_Y", "sel_gemm", "sel_diag", "sel_extract", "sel_reduce"};
 
 struct Level {
   std::vector<int32_t> fronts;     // sorted by column count p descending
@@ -79,7 +83,7 @@ struct Level {
   HostList sgather;
   int nsteps2 = 0;                                // 256-wide outer blocks of the widest front
   std::vector<HostList> fblk, fout, bpart, bblk;  // solves per outer block
-  std::vector<HostList> sY2, sgemm2, spart2, sfin2;
+  std::vector<HostList> sY2, sgemm2, sgred, spart2, sfin2;
   double wsize_elems_scatter = 0.0;
 };
 
@@ -110,16 +114,18 @@ struct gmrf_ctx {
   DevArr<int32_t> d_lfronts;
   DevArr<int64_t> d_lprefix;
   DevArr<int2> d_wgmap;
+  DevArr<int32_t> d_aux;
   DevArr<int64_t> d_bptr, d_D2off;
   int64_t D2size = 0;
   DevArr<int32_t> d_bpiv;
   std::vector<Level> levels;
   int64_t max_front = 0;
   int64_t part_max = 0;   // largest split-K partial launch (work-groups)
+  int64_t gpart_max = 0;  // largest split Sigma[R', K] launch (work-groups)
   int64_t bpart_max = 0;  // largest backward-solve partial launch (work-groups)
 
   int prec = -1;
-  DevArr<char> d_L, d_D, d_D2, d_D2T, d_W0, d_W1, d_Y, d_part;
+  DevArr<char> d_L, d_D, d_D2, d_D2T, d_W0, d_W1, d_Y, d_part, d_gpart;
   DevArr<double> d_piv, d_V0, d_V1, d_xp, d_w, d_r, d_red, d_norm, d_ld, d_mu_post, d_bpart;
   DevArr<int32_t> d_status;
   int refine_iters = 0;
@@ -248,18 +254,29 @@ int64_t find_entry(const std::vector<int64_t>& rp, const std::vector<int32_t>& c
 // ------------------------------------------------------------------ plan construction
 struct Cost { double flops, elems; };
 
+// split-K of the Sigma[R', K] products: aim at this many work-groups per launch (three
+// rounds of 256 CUs x 3 resident work-groups), with parts of at least kSplitMinK rows
+constexpr int64_t kSplitTarget = 2304;
+constexpr int64_t kSplitMinK = 512;
+
 struct ListBuilder {
   // work-group maps beyond this many entries are not kept (kernels then search the prefix)
   static constexpr int64_t kMaxMap = int64_t(1) << 27;
   std::vector<int32_t> fronts;
   std::vector<int64_t> prefix;
   std::vector<int2> wgmap;
+  std::vector<int32_t> aux;
   template <typename F>
   HostList add(const std::vector<int32_t>& cand, F tiles) {
     return add(cand, tiles, [](int32_t) { return Cost{0.0, 0.0}; });
   }
   template <typename F, typename C>
   HostList add(const std::vector<int32_t>& cand, F tiles, C cost) {
+    return add(cand, tiles, cost, nullptr);
+  }
+  // auxf(s) -> std::pair<int32_t, int32_t> stored per listed front (two ints)
+  template <typename F, typename C, typename A>
+  HostList add(const std::vector<int32_t>& cand, F tiles, C cost, A auxf) {
     HostList L;
     L.f_off = (int64_t)fronts.size();
     L.p_off = (int64_t)prefix.size();
@@ -271,6 +288,12 @@ struct ListBuilder {
       prefix.push_back(tot);
       tot += t;
       L.count++;
+      if constexpr (!std::is_same_v<A, std::nullptr_t>) {
+        if (L.count == 1) L.a_off = (int64_t)aux.size();
+        const std::pair<int32_t, int32_t> a = auxf(s);
+        aux.push_back(a.first);
+        aux.push_back(a.second);
+      }
       const Cost c = cost(s);
       L.flops += c.flops;
       L.elems += c.elems;
@@ -293,6 +316,7 @@ LaunchList dev_list(const gmrf_ctx* h, const HostList& L) {
   d.fronts = h->d_lfronts.p + L.f_off;
   d.prefix = h->d_lprefix.p + L.p_off;
   d.wgmap = L.m_off >= 0 ? h->d_wgmap.p + L.m_off : nullptr;
+  d.aux = L.a_off >= 0 ? h->d_aux.p + L.a_off : nullptr;
   d.count = L.count;
   d.total = L.total;
   return d;
@@ -396,6 +420,7 @@ gmrf_status build_plan(gmrf_t h) {
 
   ListBuilder B;
   h->part_max = 0;
+  h->gpart_max = 0;
   h->bpart_max = 0;
   for (int d = 0; d <= Y.max_depth; ++d) {
     Level& lv = h->levels[d];
@@ -470,12 +495,37 @@ gmrf_status build_plan(gmrf_t h) {
         const double r = (double)otail(s), b = (double)okb2(s);
         return Cost{r * b * b, 2.0 * r * b + b * b};
       }));
-      lv.sgemm2.push_back(B.add(lv.fronts, [&](int32_t s) -> int64_t {
+      // Sigma[R', K] = -Sigma[R', R'] Y: 128 x 128 output tiles; when a depth has too few
+      // tiles to fill the chip (top of the tree), the long K = |R'| is split into parts
+      // whose partial tiles a second launch adds in a fixed order
+      auto gtiles = [&](int32_t s) -> int64_t {
         return oact(s) ? ((otail(s) + kBigTile - 1) / kBigTile) * onct(s) : 0;
-      }, [&](int32_t s) {
+      };
+      int64_t gtot = 0;
+      for (int32_t s : lv.fronts) gtot += gtiles(s);
+      auto gsplit = [&](int32_t s) -> int64_t {
+        if (gtot >= kSplitTarget || gtiles(s) == 0) return 1;
+        const int64_t want = (kSplitTarget + gtot - 1) / gtot;
+        return std::max<int64_t>(1, std::min<int64_t>(want, otail(s) / kSplitMinK));
+      };
+      lv.sgemm2.push_back(B.add(lv.fronts, [&](int32_t s) -> int64_t { return gtiles(s) * gsplit(s); },
+                                [&](int32_t s) {
         const double r = (double)otail(s), b = (double)okb2(s);
         return Cost{2.0 * r * r * b, r * r + 3.0 * r * b};
-      }));
+      }, [&](int32_t s) { return std::make_pair((int32_t)gsplit(s), (int32_t)0); }));
+      {
+        const HostList& G = lv.sgemm2.back();
+        std::unordered_map<int32_t, int64_t> gbase;
+        bool any = false;
+        for (int32_t i = 0; i < G.count; ++i) gbase[B.fronts[G.f_off + i]] = B.prefix[G.p_off + i];
+        for (int32_t s : lv.fronts) any = any || gsplit(s) > 1;
+        if (any) h->gpart_max = std::max(h->gpart_max, G.total);
+        lv.sgred.push_back(B.add(lv.fronts, [&](int32_t s) -> int64_t { return gsplit(s) > 1 ? 2 * gtiles(s) : 0; },
+                                 [&](int32_t s) {
+          const double r = (double)otail(s), b = (double)okb2(s);
+          return Cost{0.0, (double)gsplit(s) * r * b + 2.0 * r * b};
+        }, [&](int32_t s) { return std::make_pair((int32_t)gsplit(s), (int32_t)gbase[s]); }));
+      }
       lv.spart2.push_back(B.add(lv.fronts, [&](int32_t s) -> int64_t {
         return oact(s) ? std::max<int64_t>(1, (otail(s) + 511) / 512) * onsub(s) * onsub(s) : 0;
       }, [&](int32_t s) {
@@ -527,6 +577,7 @@ gmrf_status build_plan(gmrf_t h) {
   HIPCHK(h, upload(h->d_lfronts, B.fronts, st));
   HIPCHK(h, upload(h->d_lprefix, B.prefix, st));
   HIPCHK(h, upload(h->d_wgmap, B.wgmap, st));
+  HIPCHK(h, upload(h->d_aux, B.aux, st));
   HIPCHK(h, upload(h->d_map_e, map_e, st));
   HIPCHK(h, upload(h->d_map_off, map_off, st));
   HIPCHK(h, upload(h->d_perm, Y.perm, st));
@@ -722,6 +773,7 @@ gmrf_status run_selinv(gmrf_t h, double* var, double* sigq) {
   int64_t ysz = std::max<int64_t>(std::max(Y.Vsize[0], Y.Vsize[1]), 1) * kNB2;
   HIPCHK(h, h->d_Y.alloc((size_t)ysz * sizeof(T)));
   HIPCHK(h, h->d_part.alloc((size_t)std::max<int64_t>(h->part_max, 1) * kNB * kNB * sizeof(T)));
+  HIPCHK(h, h->d_gpart.alloc((size_t)std::max<int64_t>(h->gpart_max, 1) * kBigTile * kBigTile * sizeof(T)));
   T* W[2] = {(T*)h->d_W0.p, (T*)h->d_W1.p};
   T* D2 = (T*)h->d_D2.p;
   for (int d = 0; d <= Y.max_depth; ++d) {
@@ -733,6 +785,7 @@ gmrf_status run_selinv(gmrf_t h, double* var, double* sigq) {
     B.Spar = W[(d + 1) & 1];   // parent depth d-1 has the other parity
     B.Y = (T*)h->d_Y.p;
     B.part = (T*)h->d_part.p;
+    B.gpart = (T*)h->d_gpart.p;
     prof_launch(h, KC_SEL_GATHER, 0.0, lv.sgather.elems,
                 [&] { launch_sel_gather<T>(st, S, dev_list(h, lv.sgather), h->d_sparent.p, B); });
     for (int t = 0; t < lv.nsteps2; ++t) {
@@ -741,6 +794,9 @@ gmrf_status run_selinv(gmrf_t h, double* var, double* sigq) {
       if (lv.sgemm2[t].total > 0)
         prof_launch(h, KC_SEL_GEMM, lv.sgemm2[t].flops, lv.sgemm2[t].elems,
                     [&] { launch_sel_gemm2<T>(st, S, dev_list(h, lv.sgemm2[t]), t, B); });
+      if (lv.sgred[t].total > 0)
+        prof_launch(h, KC_SEL_RED, 0.0, lv.sgred[t].elems,
+                    [&] { launch_sel_gemm_reduce<T>(st, S, dev_list(h, lv.sgred[t]), t, B); });
       prof_launch(h, KC_SEL_DIAG, lv.spart2[t].flops + lv.sfin2[t].flops, lv.spart2[t].elems + lv.sfin2[t].elems, [&] {
         launch_sel_part2<T>(st, S, dev_list(h, lv.spart2[t]), t, B);
         launch_sel_fin2<T>(st, S, dev_list(h, lv.sfin2[t]), dev_list(h, lv.spart2[t]), t, B, h->d_D2off.p, D2);

@@ -31,6 +31,7 @@ struct LaunchList {
   const int32_t* fronts;
   const int64_t* prefix;
   const int2* wgmap;        // per work-group (list index, local index), or null
+  const int32_t* aux;       // two ints per listed front (meaning set by the kernel), or null
   int32_t count;
   int64_t total;            // number of work-groups
 };
@@ -137,13 +138,16 @@ struct SelBufs {
   T* Scur;         // square Sigma fronts of the current depth
   T* Spar;         // square Sigma fronts of the parent depth
   T* Y;            // n_s x 256 scratch per front (offset Voff * 256)
-  T* part;         // split-K partials
+  T* part;         // split-K partials of the diagonal Sigma blocks
+  T* gpart;        // split-K partials of Sigma[R', K] (128 x 128 per work-group)
 };
 template <typename T> void launch_sel_gather(hipStream_t st, const DevSym& S, const LaunchList& L, const int32_t* sparent, SelBufs<T> B);
 // two-level selected inversion (256-wide outer blocks counted from the right by `step`)
 template <typename T> void launch_sel_Y2(hipStream_t st, const DevSym& S, const LaunchList& L, int step,
                                          SelBufs<T> B, const int64_t* D2off, const T* D2);
 template <typename T> void launch_sel_gemm2(hipStream_t st, const DevSym& S, const LaunchList& L, int step, SelBufs<T> B);
+template <typename T> void launch_sel_gemm_reduce(hipStream_t st, const DevSym& S, const LaunchList& L, int step,
+                                                  SelBufs<T> B);
 template <typename T> void launch_sel_part2(hipStream_t st, const DevSym& S, const LaunchList& L, int step, SelBufs<T> B);
 template <typename T> void launch_sel_fin2(hipStream_t st, const DevSym& S, const LaunchList& L, const LaunchList& Lpart,
                                            int step, SelBufs<T> B, const int64_t* D2off, const T* D2);

@@ -1300,22 +1300,78 @@ __global__ __launch_bounds__(kThreads) void k_sel_gemm2(DevSym S, LaunchList L, 
   const int s = L.fronts[fi];
   const int n = fn(S, s), p = fp(S, s);
   const OuterBlk o = outer_blk(p, n, step);
+  const int split = L.aux[2 * fi];
   const int nct = (o.kb2 + kBT - 1) / kBT;
-  const int rt = (int)(loc / nct), ctile = (int)(loc % nct);
+  const int tile = (int)(loc / split), sp = (int)(loc % split);
+  const int rt = tile / nct, ctile = tile % nct;
   const int row0 = o.rs + kBT * rt, col0 = kBT * ctile;
   const int M = min(kBT, n - row0), N = min(kBT, o.kb2 - col0);
+  const int np = n - o.rs;
+  const int kpart = ((np + split - 1) / split + BigTK<T>::v - 1) / BigTK<T>::v * BigTK<T>::v;
+  const int kb = min(np, sp * kpart), ke = min(np, kb + kpart);
   T* Sf = B.Scur + S.Woff[s];
   const T* Y = B.Y + S.Voff[s] * kNB2;
   typename V4<T>::type acc[4][4];
   zero_acc128<T>(acc);
-  gemm_tile128<T, false, true>(Sf + row0 + (int64_t)o.rs * n, n, Y + (int64_t)col0 * n, n, M, N, n - o.rs,
-                               acc, sA, sB);
-  for_acc128<T>(acc, [&](int r, int c, T v) {
-    if (r < M && c < N) {
-      Sf[(row0 + r) + (int64_t)(o.k2 + col0 + c) * n] = -v;
-      Sf[(o.k2 + col0 + c) + (int64_t)(row0 + r) * n] = -v;
+  gemm_tile128<T, false, true>(Sf + row0 + (int64_t)(o.rs + kb) * n, n, Y + kb + (int64_t)col0 * n, n, M, N,
+                               ke - kb, acc, sA, sB);
+  if (split == 1) {
+    for_acc128<T>(acc, [&](int r, int c, T v) {
+      if (r < M && c < N) {
+        Sf[(row0 + r) + (int64_t)(o.k2 + col0 + c) * n] = -v;
+        Sf[(o.k2 + col0 + c) + (int64_t)(row0 + r) * n] = -v;
+      }
+    });
+  } else {
+    T* out = B.gpart + wg_id() * (int64_t)(kBT * kBT);
+    for_acc128<T>(acc, [&](int r, int c, T v) { out[r + c * kBT] = v; });
+  }
+}
+
+// Sum of the split-K partials of one 128 x 128 tile of Sigma[R', K] in a fixed order,
+// written to Sigma[R', K] and its mirror Sigma[K, R'].  aux = (split, first work-group of
+// the front in the partial launch).  One work-group per 64-column half of a tile: the
+// sums are formed with coalesced reads, written down the columns, and staged in LDS so
+// that the mirror is written along its rows.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_sel_gemm_reduce(DevSym S, LaunchList L, int step, SelBufs<T> B) {
+  __shared__ T tileS[64][kBT + 1];
+  int fi; int64_t loc;
+  find_front(L, wg_id(), fi, loc);
+  const int s = L.fronts[fi];
+  const int n = fn(S, s), p = fp(S, s);
+  const OuterBlk o = outer_blk(p, n, step);
+  const int split = L.aux[2 * fi];
+  const int64_t base = L.aux[2 * fi + 1];
+  const int nct = (o.kb2 + kBT - 1) / kBT;
+  const int tile = (int)(loc >> 1), half = (int)(loc & 1);
+  const int rt = tile / nct, ctile = tile % nct;
+  const int row0 = o.rs + kBT * rt, col0 = kBT * ctile + 64 * half;
+  const int M = min(kBT, n - row0), N = min(64, o.kb2 - col0);
+  if (N <= 0) return;
+  const T* pp = B.gpart + (base + (int64_t)tile * split) * (kBT * kBT) + (int64_t)(64 * half) * kBT;
+  T* Sf = B.Scur + S.Woff[s];
+  for (int e = threadIdx.x; e < kBT * 64; e += kThreads) {
+    const int r = e % kBT, c = e / kBT;
+    T a = T(0);
+    int q = 0;
+    for (; q + 4 <= split; q += 4) {
+      const T v0 = pp[(int64_t)q * (kBT * kBT) + e], v1 = pp[(int64_t)(q + 1) * (kBT * kBT) + e];
+      const T v2 = pp[(int64_t)(q + 2) * (kBT * kBT) + e], v3 = pp[(int64_t)(q + 3) * (kBT * kBT) + e];
+      a += v0;
+      a += v1;
+      a += v2;
+      a += v3;
     }
-  });
+    for (; q < split; ++q) a += pp[(int64_t)q * (kBT * kBT) + e];
+    tileS[c][r] = -a;
+    if (r < M && c < N) Sf[(row0 + r) + (int64_t)(o.k2 + col0 + c) * n] = -a;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < kBT * 64; e += kThreads) {
+    const int c = e & 63, r = e >> 6;
+    if (r < M && c < N) Sf[(o.k2 + col0 + c) + (int64_t)(row0 + r) * n] = tileS[c][r];
+  }
 }
 
 // split-K partials of X^T Sigma[R', K]: work-group (front, chunk, ti, tj) computes the
@@ -1626,6 +1682,11 @@ template <typename T> void launch_sel_gemm2(hipStream_t st, const DevSym& S, con
   if (L.total <= 0) return;
   hipLaunchKernelGGL(k_sel_gemm2<T>, dim3((unsigned)L.total), dim3(kThreads), 0, st, S, L, step, B);
 }
+template <typename T> void launch_sel_gemm_reduce(hipStream_t st, const DevSym& S, const LaunchList& L, int step,
+                                                  SelBufs<T> B) {
+  if (L.total <= 0) return;
+  hipLaunchKernelGGL(k_sel_gemm_reduce<T>, dim3((unsigned)L.total), dim3(kThreads), 0, st, S, L, step, B);
+}
 template <typename T> void launch_sel_part2(hipStream_t st, const DevSym& S, const LaunchList& L, int step,
                                             SelBufs<T> B) {
   if (L.total <= 0) return;
@@ -1669,6 +1730,7 @@ template <typename T> void launch_sel_pattern(hipStream_t st, int64_t cnt, const
   template void launch_inv256<T>(hipStream_t, const DevSym&, const LaunchList&, const T*, int, const T*, const int64_t*, T*, T*); \
   template void launch_sel_Y2<T>(hipStream_t, const DevSym&, const LaunchList&, int, SelBufs<T>, const int64_t*, const T*); \
   template void launch_sel_gemm2<T>(hipStream_t, const DevSym&, const LaunchList&, int, SelBufs<T>); \
+  template void launch_sel_gemm_reduce<T>(hipStream_t, const DevSym&, const LaunchList&, int, SelBufs<T>); \
   template void launch_sel_part2<T>(hipStream_t, const DevSym&, const LaunchList&, int, SelBufs<T>); \
   template void launch_sel_fin2<T>(hipStream_t, const DevSym&, const LaunchList&, const LaunchList&, int, SelBufs<T>, const int64_t*, const T*); \
   template void launch_sel_extract<T>(hipStream_t, const DevSym&, const LaunchList&, SelBufs<T>, const double*, double*); \
