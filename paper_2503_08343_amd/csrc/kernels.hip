@@ -412,72 +412,114 @@ __global__ __launch_bounds__(kThreads) void k_extend_add(DevSym S, LaunchList L,
   for (int a = b + threadIdx.x; a < uc; a += blockDim.x) dst[rel[a]] += src[a];
 }
 
-// FP64 Cholesky of the step-th 64x64 diagonal block of each listed front, in LDS, and
-// the inverse of the resulting lower-triangular block.
+// FP64 Cholesky of the step-th 64x64 diagonal block of each listed front and the inverse
+// of the resulting lower-triangular block, both held in registers: thread (ti, tl) owns
+// rows ti + 16a and columns tl + 16b (a, b < 4) of the block and of its inverse X.  Each
+// phase j needs one barrier: the owners of column j finish it (their 16 lanes share one
+// wave, so the pivot is a lane shuffle) and publish it through LDS; every thread applies
+// the previous column to its trailing elements; the inverse follows two phases behind
+// (forward substitution L X = I: row j-1 of X is scaled and published, row j-2 applied).
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_potrf(DevSym S, LaunchList L, int step, NumBufs<T> B) {
-  __shared__ double A[kNB][kNB + 1];
-  __shared__ double X[kNB][kNB + 1];
+  __shared__ double colb[4][kNB];
+  __shared__ double rowb[4][kNB];
   __shared__ int fail;
   const int s = L.fronts[blockIdx.x];
   const int n = fn(S, s), p = fp(S, s);
   const int k0 = step * kNB;
   const int kb = min(kNB, p - k0);
   T* F = B.Wcur + S.Woff[s];
-  const int t = threadIdx.x;
-  for (int idx = t; idx < kNB * kNB; idx += kThreads) {
-    const int i = idx & (kNB - 1), j = idx >> 6;
-    double v = 0.0;
-    if (i < kb && j < kb && i >= j) v = (double)F[(k0 + i) + (int64_t)(k0 + j) * n];
-    A[i][j] = v;
-  }
-  if (t == 0) fail = -1;
-  __syncthreads();
-  for (int j = 0; j < kb; ++j) {
-    const double d = A[j][j];
-    const bool bad = !(d > 0.0);
-    const double ljj = bad ? 1.0 : sqrt(d);
-    __syncthreads();
-    if (t == 0) {
-      A[j][j] = ljj;
-      if (bad && fail < 0) fail = j;
+  const int t = threadIdx.x, ti = t & 15, tl = t >> 4;
+  double a_r[4][4], x_r[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int i = ti + 16 * a, l = tl + 16 * b;
+      double v = 0.0;
+      if (i < kb && l < kb && i >= l) v = (double)F[(k0 + i) + (int64_t)(k0 + l) * n];
+      a_r[a][b] = v;
+      x_r[a][b] = i == l ? 1.0 : 0.0;
     }
-    for (int i = j + 1 + t; i < kb; i += kThreads) A[i][j] = A[i][j] / ljj;
+  if (t == 0) fail = INT_MAX;
+  for (int j = 0; j < kb + 2; ++j) {
     __syncthreads();
-    const int m = kb - j - 1;
-    for (int idx = t; idx < m * m; idx += kThreads) {
-      const int ii = idx % m, ll = idx / m;
-      if (ii >= ll) {
-        const int i = j + 1 + ii, l = j + 1 + ll;
-        A[i][l] -= A[i][j] * A[l][j];
+    // trailing update with column j-1
+    if (j >= 1 && j - 1 < kb) {
+      const double* c1 = colb[(j - 1) & 3];
+      double ci[4], cl[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) { ci[a] = c1[ti + 16 * a]; cl[a] = c1[tl + 16 * a]; }
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+          if (ti + 16 * a > j - 1 && tl + 16 * b > j - 1) a_r[a][b] -= ci[a] * cl[b];
+    }
+    // inverse: apply row j-2 of X, then scale and publish row j-1
+    if (j >= 2 && j - 2 < kb) {
+      const double* c2 = colb[(j - 2) & 3];
+      const double* r2 = rowb[(j - 2) & 3];
+      double ci[4], rc[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) { ci[a] = c2[ti + 16 * a]; rc[a] = r2[tl + 16 * a]; }
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+          if (ti + 16 * a > j - 2) x_r[a][b] -= ci[a] * rc[b];
+    }
+    if (j >= 1 && j - 1 < kb && ti == ((j - 1) & 15)) {
+      const int ja = (j - 1) >> 4;
+      const double rinv = 1.0 / colb[(j - 1) & 3][j - 1];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+        if (a == ja) {
+#pragma unroll
+          for (int b = 0; b < 4; ++b) {
+            x_r[a][b] *= rinv;
+            rowb[(j - 1) & 3][tl + 16 * b] = x_r[a][b];
+          }
+        }
+    }
+    // finish column j
+    if (j < kb && (t >> 6) == ((j & 15) >> 2)) {
+      const int jb = j >> 4, jr = j & 15;
+      double cv[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) cv[a] = jb == 0 ? a_r[a][0] : jb == 1 ? a_r[a][1] : jb == 2 ? a_r[a][2] : a_r[a][3];
+      const double dsel = jb == 0 ? cv[0] : jb == 1 ? cv[1] : jb == 2 ? cv[2] : cv[3];
+      const double d = __shfl(dsel, 16 * (jr & 3) + jr, 64);
+      if (tl == jr) {
+        const bool bad = !(d > 0.0);
+        const double ljj = bad ? 1.0 : sqrt(d);
+        const double linv = 1.0 / ljj;
+        if (bad && ti == jr) atomicMin(&fail, j);
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+          const int i = ti + 16 * a;
+          const double v = i > j ? cv[a] * linv : (i == j ? ljj : 0.0);
+          colb[j & 3][i] = v;
+#pragma unroll
+          for (int b = 0; b < 4; ++b)
+            if (b == jb) a_r[a][b] = v;
+        }
       }
     }
-    __syncthreads();
-  }
-  if (t < kNB) {
-    const int c = t;
-    for (int i = 0; i < kNB; ++i) X[i][c] = 0.0;
-    if (c < kb) {
-      X[c][c] = 1.0 / A[c][c];
-      for (int i = c + 1; i < kb; ++i) {
-        double acc = 0.0;
-        for (int l = c; l < i; ++l) acc += A[i][l] * X[l][c];
-        X[i][c] = -acc / A[i][i];
-      }
-    }
   }
   __syncthreads();
-  for (int idx = t; idx < kNB * kNB; idx += kThreads) {
-    const int i = idx & (kNB - 1), j = idx >> 6;
-    if (i < kb && j < kb && i >= j) F[(k0 + i) + (int64_t)(k0 + j) * n] = (T)A[i][j];
-  }
   T* Dblk = B.D + S.Doff[s] + (int64_t)step * kNB * kNB;
-  for (int idx = t; idx < kNB * kNB; idx += kThreads) {
-    const int i = idx & (kNB - 1), j = idx >> 6;
-    Dblk[i + j * kNB] = (T)X[i][j];
-  }
-  if (t < kb) B.piv[S.sfirst[s] + k0 + t] = A[t][t];
-  if (t == 0 && fail >= 0) atomicMin(B.status, S.sfirst[s] + k0 + fail);
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int i = ti + 16 * a, l = tl + 16 * b;
+      const bool in = i < kb && l < kb && i >= l;
+      if (in) F[(k0 + i) + (int64_t)(k0 + l) * n] = (T)a_r[a][b];
+      Dblk[i + l * kNB] = in ? (T)x_r[a][b] : T(0);
+      if (in && i == l) B.piv[S.sfirst[s] + k0 + i] = a_r[a][b];
+    }
+  if (t == 0 && fail != INT_MAX) atomicMin(B.status, S.sfirst[s] + k0 + fail);
 }
 
 // panel rows below the step-th diagonal block: F[r, blk] = F[r, blk] * Linv^T
@@ -557,8 +599,8 @@ __global__ __launch_bounds__(kThreads) void k_update(DevSym S, LaunchList L, int
       if (rr < M && cc < N && gi >= gj) F[gi + (int64_t)gj * n] -= v;
     });
   } else {
-    __shared__ T sA[BigLds<T>::v];
-    __shared__ T sB[BigLds<T>::v];
+    __shared__ __attribute__((aligned(16))) T sA[BigLds<T>::v];
+    __shared__ __attribute__((aligned(16))) T sB[BigLds<T>::v];
     typename V4<T>::type acc[4][4];
     zero_acc128<T>(acc);
     gemm_tile128<T, false, false>(F + row0 + (int64_t)klo * n, n, F + col0 + (int64_t)klo * n, n, M, N,
@@ -1268,8 +1310,8 @@ __global__ __launch_bounds__(kThreads) void k_inv256(DevSym S, LaunchList L, con
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_sel_Y2(DevSym S, LaunchList L, int step, SelBufs<T> B,
                                                      const int64_t* __restrict__ D2off, const T* __restrict__ D2) {
-  __shared__ T sA[BigLds<T>::v];
-  __shared__ T sB[BigLds<T>::v];
+  __shared__ __attribute__((aligned(16))) T sA[BigLds<T>::v];
+  __shared__ __attribute__((aligned(16))) T sB[BigLds<T>::v];
   int fi; int64_t loc;
   find_front(L, wg_id(), fi, loc);
   const int s = L.fronts[fi];
@@ -1293,8 +1335,8 @@ __global__ __launch_bounds__(kThreads) void k_sel_Y2(DevSym S, LaunchList L, int
 // Sigma[R', K] = -Sigma[R', R'] Y, mirrored into Sigma[K, R']; 128x128 tiles
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_sel_gemm2(DevSym S, LaunchList L, int step, SelBufs<T> B) {
-  __shared__ T sA[BigLds<T>::v];
-  __shared__ T sB[BigLds<T>::v];
+  __shared__ __attribute__((aligned(16))) T sA[BigLds<T>::v];
+  __shared__ __attribute__((aligned(16))) T sB[BigLds<T>::v];
   int fi; int64_t loc;
   find_front(L, wg_id(), fi, loc);
   const int s = L.fronts[fi];
