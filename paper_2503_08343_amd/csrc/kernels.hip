@@ -412,6 +412,16 @@ __global__ __launch_bounds__(kThreads) void k_extend_add(DevSym S, LaunchList L,
   for (int a = b + threadIdx.x; a < uc; a += blockDim.x) dst[rel[a]] += src[a];
 }
 
+// 1/sqrt(d) for d > 0 (normal range): the hardware estimate refined by two Newton steps
+// y <- y (3/2 - (d/2) y^2), each of which roughly doubles the number of correct bits
+__device__ __forceinline__ double rsqrt_newton(double d) {
+  double y = __builtin_amdgcn_rsq(d);
+  const double h = 0.5 * d;
+  y = y * (1.5 - h * y * y);
+  y = y * (1.5 - h * y * y);
+  return y;
+}
+
 // FP64 Cholesky of the step-th 64x64 diagonal block of each listed front and the inverse
 // of the resulting lower-triangular block, both held in registers: thread (ti, tl) owns
 // rows ti + 16a and columns tl + 16b (a, b < 4) of the block and of its inverse X.  Each
@@ -423,6 +433,7 @@ template <typename T>
 __global__ __launch_bounds__(kThreads) void k_potrf(DevSym S, LaunchList L, int step, NumBufs<T> B) {
   __shared__ double colb[4][kNB];
   __shared__ double rowb[4][kNB];
+  __shared__ double pinv[4];
   __shared__ int fail;
   const int s = L.fronts[blockIdx.x];
   const int n = fn(S, s), p = fp(S, s);
@@ -471,7 +482,7 @@ __global__ __launch_bounds__(kThreads) void k_potrf(DevSym S, LaunchList L, int 
     }
     if (j >= 1 && j - 1 < kb && ti == ((j - 1) & 15)) {
       const int ja = (j - 1) >> 4;
-      const double rinv = 1.0 / colb[(j - 1) & 3][j - 1];
+      const double rinv = pinv[(j - 1) & 3];
 #pragma unroll
       for (int a = 0; a < 4; ++a)
         if (a == ja) {
@@ -492,9 +503,12 @@ __global__ __launch_bounds__(kThreads) void k_potrf(DevSym S, LaunchList L, int 
       const double d = __shfl(dsel, 16 * (jr & 3) + jr, 64);
       if (tl == jr) {
         const bool bad = !(d > 0.0);
-        const double ljj = bad ? 1.0 : sqrt(d);
-        const double linv = 1.0 / ljj;
-        if (bad && ti == jr) atomicMin(&fail, j);
+        const double linv = bad ? 1.0 : rsqrt_newton(d);
+        const double ljj = bad ? 1.0 : d * linv;
+        if (ti == jr) {
+          pinv[j & 3] = linv;
+          if (bad) atomicMin(&fail, j);
+        }
 #pragma unroll
         for (int a = 0; a < 4; ++a) {
           const int i = ti + 16 * a;
