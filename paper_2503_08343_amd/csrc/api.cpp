@@ -84,6 +84,8 @@ struct Level {
   int nsteps2 = 0;                                // 256-wide outer blocks of the widest front
   std::vector<HostList> fblk, fout, bpart, bblk;  // solves per outer block
   std::vector<HostList> sY2, sgemm2, sgred, spart2, sfin2;
+  std::vector<HostList> sgemm3, sgred3;   // FP32: 256 x 128 tiles of the Sigma[R', K] products
+  HostList syrk3;                          // FP32: 256 x 128 tiles of the trailing SYRK
   double wsize_elems_scatter = 0.0;
 };
 
@@ -121,7 +123,8 @@ struct gmrf_ctx {
   std::vector<Level> levels;
   int64_t max_front = 0;
   int64_t part_max = 0;   // largest split-K partial launch (work-groups)
-  int64_t gpart_max = 0;  // largest split Sigma[R', K] launch (work-groups)
+  int64_t gpart_max = 0;  // largest split Sigma[R', K] launch (work-groups of 128 x 128)
+  int64_t gpart3_max = 0; // same for the FP32 256 x 128 tiles
   int64_t bpart_max = 0;  // largest backward-solve partial launch (work-groups)
 
   int prec = -1;
@@ -254,10 +257,25 @@ int64_t find_entry(const std::vector<int64_t>& rp, const std::vector<int32_t>& c
 // ------------------------------------------------------------------ plan construction
 struct Cost { double flops, elems; };
 
-// split-K of the Sigma[R', K] products: aim at this many work-groups per launch (three
-// rounds of 256 CUs x 3 resident work-groups), with parts of at least kSplitMinK rows
-constexpr int64_t kSplitTarget = 2304;
+// split-K of the Sigma[R', K] products at the top of the tree: with T output tiles and
+// `slots` work-groups resident at once, a launch of T*S parts takes ceil(T S / slots)
+// rounds of 1/S of the work each.  Take the smallest S whose round count per unit of work
+// is within 10% of the ideal T / slots (parts of at least kSplitMinK rows).
 constexpr int64_t kSplitMinK = 512;
+constexpr int64_t kSlots128 = 256;   // 128 x 128 tiles (FP64): one resident work-group per CU
+constexpr int64_t kSlots256 = 512;   // FP32 256 x 128 tiles: two per CU
+int64_t choose_split(int64_t T, int64_t slots, int64_t smax) {
+  if (T <= 0 || T >= 8 * slots) return 1;
+  const double ideal = (double)T / (double)slots;
+  int64_t best = 1;
+  double best_r = 1e300;
+  for (int64_t S = 1; S <= std::max<int64_t>(1, smax); ++S) {
+    const double r = (double)((T * S + slots - 1) / slots) / (double)S;
+    if (r <= 1.1 * ideal) return S;
+    if (r < best_r - 1e-12) { best_r = r; best = S; }
+  }
+  return best;
+}
 
 struct ListBuilder {
   // work-group maps beyond this many entries are not kept (kernels then search the prefix)
@@ -354,11 +372,12 @@ void upd_region(int mode, int64_t step, int64_t n, int64_t p, int64_t& clo, int6
   clo = k0 + kb; chi = oe; klo = k0; khi = k0 + kb;
 }
 
-int64_t upd_tiles(int64_t n, int64_t p, int mode, int64_t step, int64_t ts) {
+int64_t upd_tiles(int64_t n, int64_t p, int mode, int64_t step, int64_t ts, int64_t tr = 0) {
   int64_t clo, chi, klo, khi;
   upd_region(mode, step, n, p, clo, chi, klo, khi);
+  if (tr <= 0) tr = ts;   // tile rows (default: square tiles)
   int64_t t = 0;
-  for (int64_t c0 = clo; c0 < chi; c0 += ts) t += (n - c0 + ts - 1) / ts;
+  for (int64_t c0 = clo; c0 < chi; c0 += ts) t += (n - c0 + tr - 1) / tr;
   return t;
 }
 
@@ -421,6 +440,7 @@ gmrf_status build_plan(gmrf_t h) {
   ListBuilder B;
   h->part_max = 0;
   h->gpart_max = 0;
+  h->gpart3_max = 0;
   h->bpart_max = 0;
   for (int d = 0; d <= Y.max_depth; ++d) {
     Level& lv = h->levels[d];
@@ -503,10 +523,12 @@ gmrf_status build_plan(gmrf_t h) {
       };
       int64_t gtot = 0;
       for (int32_t s : lv.fronts) gtot += gtiles(s);
+      int64_t gmaxk = 0;
+      for (int32_t s : lv.fronts) if (gtiles(s) > 0) gmaxk = std::max<int64_t>(gmaxk, otail(s) / kSplitMinK);
+      const int64_t gS = choose_split(gtot, kSlots128, gmaxk);
       auto gsplit = [&](int32_t s) -> int64_t {
-        if (gtot >= kSplitTarget || gtiles(s) == 0) return 1;
-        const int64_t want = (kSplitTarget + gtot - 1) / gtot;
-        return std::max<int64_t>(1, std::min<int64_t>(want, otail(s) / kSplitMinK));
+        if (gtiles(s) == 0) return 1;
+        return std::max<int64_t>(1, std::min<int64_t>(gS, otail(s) / kSplitMinK));
       };
       lv.sgemm2.push_back(B.add(lv.fronts, [&](int32_t s) -> int64_t { return gtiles(s) * gsplit(s); },
                                 [&](int32_t s) {
@@ -525,6 +547,38 @@ gmrf_status build_plan(gmrf_t h) {
           const double r = (double)otail(s), b = (double)okb2(s);
           return Cost{0.0, (double)gsplit(s) * r * b + 2.0 * r * b};
         }, [&](int32_t s) { return std::make_pair((int32_t)gsplit(s), (int32_t)gbase[s]); }));
+      }
+      {
+        // FP32 variant: 256-row tiles
+        auto gtiles3 = [&](int32_t s) -> int64_t {
+          return oact(s) ? ((otail(s) + 255) / 256) * onct(s) : 0;
+        };
+        int64_t gtot3 = 0;
+        for (int32_t s : lv.fronts) gtot3 += gtiles3(s);
+        int64_t gmaxk3 = 0;
+        for (int32_t s : lv.fronts) if (gtiles3(s) > 0) gmaxk3 = std::max<int64_t>(gmaxk3, otail(s) / kSplitMinK);
+        const int64_t gS3 = choose_split(gtot3, kSlots256, gmaxk3);
+        auto gsplit3 = [&](int32_t s) -> int64_t {
+          if (gtiles3(s) == 0) return 1;
+          return std::max<int64_t>(1, std::min<int64_t>(gS3, otail(s) / kSplitMinK));
+        };
+        lv.sgemm3.push_back(B.add(lv.fronts, [&](int32_t s) -> int64_t { return gtiles3(s) * gsplit3(s); },
+                                  [&](int32_t s) {
+          const double r = (double)otail(s), b = (double)okb2(s);
+          return Cost{2.0 * r * r * b, r * r + 3.0 * r * b};
+        }, [&](int32_t s) { return std::make_pair((int32_t)gsplit3(s), (int32_t)0); }));
+        const HostList& G = lv.sgemm3.back();
+        std::unordered_map<int32_t, int64_t> gbase;
+        bool any = false;
+        for (int32_t i = 0; i < G.count; ++i) gbase[B.fronts[G.f_off + i]] = B.prefix[G.p_off + i];
+        for (int32_t s : lv.fronts) any = any || gsplit3(s) > 1;
+        if (any) h->gpart3_max = std::max(h->gpart3_max, G.total);
+        lv.sgred3.push_back(B.add(lv.fronts, [&](int32_t s) -> int64_t {
+          return gsplit3(s) > 1 ? 2 * gtiles3(s) : 0;
+        }, [&](int32_t s) {
+          const double r = (double)otail(s), b = (double)okb2(s);
+          return Cost{0.0, (double)gsplit3(s) * r * b + 2.0 * r * b};
+        }, [&](int32_t s) { return std::make_pair((int32_t)gsplit3(s), (int32_t)gbase[s]); }));
       }
       lv.spart2.push_back(B.add(lv.fronts, [&](int32_t s) -> int64_t {
         return oact(s) ? std::max<int64_t>(1, (otail(s) + 511) / 512) * onsub(s) * onsub(s) : 0;
@@ -559,6 +613,9 @@ gmrf_status build_plan(gmrf_t h) {
     }
     lv.syrk = B.add(lv.fronts, [&](int32_t s) -> int64_t {
       return nF(s) > pF(s) ? upd_tiles(nF(s), pF(s), 2, 0, kBigTile) : 0;
+    }, [&](int32_t s) { return upd_cost(nF(s), pF(s), 2, 0); });
+    lv.syrk3 = B.add(lv.fronts, [&](int32_t s) -> int64_t {
+      return nF(s) > pF(s) ? upd_tiles(nF(s), pF(s), 2, 0, 128, 256) : 0;
     }, [&](int32_t s) { return upd_cost(nF(s), pF(s), 2, 0); });
     lv.inv256 = B.add(lv.fronts, [&](int32_t s) -> int64_t { return (pF(s) + nb - 1) / nb; }, [&](int32_t s) {
       const double p = (double)pF(s);
@@ -683,9 +740,15 @@ gmrf_status run_factor(gmrf_t h) {
         prof_launch(h, KC_UPDATE, lv.upd_out[k].flops, lv.upd_out[k].elems,
                     [&] { launch_update<T>(st, S, dev_list(h, lv.upd_out[k]), k, 1, B); });
     }
-    if (lv.syrk.total > 0)
-      prof_launch(h, KC_SYRK, lv.syrk.flops, lv.syrk.elems,
-                  [&] { launch_update<T>(st, S, dev_list(h, lv.syrk), 0, 2, B); });
+    if constexpr (std::is_same<T, float>::value) {
+      if (lv.syrk3.total > 0)
+        prof_launch(h, KC_SYRK, lv.syrk3.flops, lv.syrk3.elems,
+                    [&] { launch_syrk2(st, S, dev_list(h, lv.syrk3), B); });
+    } else {
+      if (lv.syrk.total > 0)
+        prof_launch(h, KC_SYRK, lv.syrk.flops, lv.syrk.elems,
+                    [&] { launch_update<T>(st, S, dev_list(h, lv.syrk), 0, 2, B); });
+    }
     prof_launch(h, KC_POTRF, lv.inv256.flops, lv.inv256.elems, [&] {
       launch_inv256<T>(st, S, dev_list(h, lv.inv256), B.Wcur, 1, B.D, h->d_D2off.p, (T*)h->d_D2.p,
                        (T*)h->d_D2T.p);
@@ -773,7 +836,11 @@ gmrf_status run_selinv(gmrf_t h, double* var, double* sigq) {
   int64_t ysz = std::max<int64_t>(std::max(Y.Vsize[0], Y.Vsize[1]), 1) * kNB2;
   HIPCHK(h, h->d_Y.alloc((size_t)ysz * sizeof(T)));
   HIPCHK(h, h->d_part.alloc((size_t)std::max<int64_t>(h->part_max, 1) * kNB * kNB * sizeof(T)));
-  HIPCHK(h, h->d_gpart.alloc((size_t)std::max<int64_t>(h->gpart_max, 1) * kBigTile * kBigTile * sizeof(T)));
+  {
+    const size_t gp = std::is_same<T, float>::value ? (size_t)std::max<int64_t>(h->gpart3_max, 1) * 256 * 128
+                                                     : (size_t)std::max<int64_t>(h->gpart_max, 1) * kBigTile * kBigTile;
+    HIPCHK(h, h->d_gpart.alloc(gp * sizeof(T)));
+  }
   T* W[2] = {(T*)h->d_W0.p, (T*)h->d_W1.p};
   T* D2 = (T*)h->d_D2.p;
   for (int d = 0; d <= Y.max_depth; ++d) {
@@ -791,12 +858,17 @@ gmrf_status run_selinv(gmrf_t h, double* var, double* sigq) {
     for (int t = 0; t < lv.nsteps2; ++t) {
       prof_launch(h, KC_SEL_Y, lv.sY2[t].flops, lv.sY2[t].elems,
                   [&] { launch_sel_Y2<T>(st, S, dev_list(h, lv.sY2[t]), t, B, h->d_D2off.p, D2); });
-      if (lv.sgemm2[t].total > 0)
-        prof_launch(h, KC_SEL_GEMM, lv.sgemm2[t].flops, lv.sgemm2[t].elems,
-                    [&] { launch_sel_gemm2<T>(st, S, dev_list(h, lv.sgemm2[t]), t, B); });
-      if (lv.sgred[t].total > 0)
-        prof_launch(h, KC_SEL_RED, 0.0, lv.sgred[t].elems,
-                    [&] { launch_sel_gemm_reduce<T>(st, S, dev_list(h, lv.sgred[t]), t, B); });
+      const bool f32 = std::is_same<T, float>::value;
+      const HostList& G = f32 ? lv.sgemm3[t] : lv.sgemm2[t];
+      const HostList& R = f32 ? lv.sgred3[t] : lv.sgred[t];
+      if (G.total > 0)
+        prof_launch(h, KC_SEL_GEMM, G.flops, G.elems, [&] {
+          if constexpr (std::is_same<T, float>::value) launch_sel_gemm3(st, S, dev_list(h, G), t, B);
+          else launch_sel_gemm2<T>(st, S, dev_list(h, G), t, B);
+        });
+      if (R.total > 0)
+        prof_launch(h, KC_SEL_RED, 0.0, R.elems,
+                    [&] { launch_sel_gemm_reduce<T>(st, S, dev_list(h, R), t, B); });
       prof_launch(h, KC_SEL_DIAG, lv.spart2[t].flops + lv.sfin2[t].flops, lv.spart2[t].elems + lv.sfin2[t].elems, [&] {
         launch_sel_part2<T>(st, S, dev_list(h, lv.spart2[t]), t, B);
         launch_sel_fin2<T>(st, S, dev_list(h, lv.sfin2[t]), dev_list(h, lv.spart2[t]), t, B, h->d_D2off.p, D2);

@@ -148,6 +148,10 @@ template <typename T> void launch_sel_Y2(hipStream_t st, const DevSym& S, const 
 template <typename T> void launch_sel_gemm2(hipStream_t st, const DevSym& S, const LaunchList& L, int step, SelBufs<T> B);
 template <typename T> void launch_sel_gemm_reduce(hipStream_t st, const DevSym& S, const LaunchList& L, int step,
                                                   SelBufs<T> B);
+// FP32 256 x 128 tiles: Sigma[R', K] products (split over K like launch_sel_gemm2, partials
+// 256 x 128) and the trailing SYRK of the update matrices
+void launch_sel_gemm3(hipStream_t st, const DevSym& S, const LaunchList& L, int step, SelBufs<float> B);
+void launch_syrk2(hipStream_t st, const DevSym& S, const LaunchList& L, NumBufs<float> B);
 template <typename T> void launch_sel_part2(hipStream_t st, const DevSym& S, const LaunchList& L, int step, SelBufs<T> B);
 template <typename T> void launch_sel_fin2(hipStream_t st, const DevSym& S, const LaunchList& L, const LaunchList& Lpart,
                                            int step, SelBufs<T> B, const int64_t* D2off, const T* D2);

@@ -15,6 +15,7 @@
 #include "kernels.h"
 
 #include <climits>
+#include <type_traits>
 
 namespace gmrf {
 
@@ -299,6 +300,155 @@ __device__ __forceinline__ void zero_acc128(typename V4<T>::type (&acc)[4][4]) {
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = typename V4<T>::type{T(0), T(0), T(0), T(0)};
+}
+
+// ---- FP32 256 x 128 tiles for the long-K products (trailing SYRK, Sigma[R', K]) ----
+// Four waves (2 x 2) with 128 x 64 wave tiles of 8 x 4 MFMA 16x16x4 blocks.  Row i' of
+// block i is tile row 8 i' + i and column c' of block j is tile column 4 c' + j, so that
+// a lane's eight A values (four B values) of one k are contiguous in LDS and arrive in
+// 128-bit reads.  Operands are staged k-major with a one-chunk register prefetch.
+typedef float f4_t __attribute__((ext_vector_type(4)));
+constexpr int kG2M = 256, kG2N = 128, kG2K = 16;
+constexpr int kPA2 = kG2M + 4, kPB2 = kG2N + 4;
+struct G2Lds {
+  float a[2][kG2K * kPA2];
+  float b[2][kG2K * kPB2];
+};
+union __attribute__((aligned(16))) G2Smem {
+  G2Lds g;
+  float ep[64][kG2M + 1];   // epilogue staging of one 64-column half of the tile
+};
+
+__device__ __forceinline__ void zero_acc2(f4_t (&acc)[8][4]) {
+#pragma unroll
+  for (int i = 0; i < 8; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = f4_t{0.f, 0.f, 0.f, 0.f};
+}
+
+template <bool A_KC, bool B_KC>
+__device__ __forceinline__ void g2_load(const float* __restrict__ A, int64_t lda, const float* __restrict__ B,
+                                        int64_t ldb, int M, int N, int K, int k0, float (&ra)[16], float (&rb)[8]) {
+  const int t = threadIdx.x;
+  if (!A_KC) {
+#pragma unroll
+    for (int q = 0; q < 16; ++q) ra[q] = (t < M && k0 + q < K) ? A[t + (int64_t)(k0 + q) * lda] : 0.f;
+  } else {
+    const int k = t & 15;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int m = (t >> 4) + 16 * q;
+      ra[q] = (m < M && k0 + k < K) ? A[(k0 + k) + (int64_t)m * lda] : 0.f;
+    }
+  }
+  if (!B_KC) {
+    const int nn = t & 127;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int k = (t >> 7) + 2 * q;
+      rb[q] = (nn < N && k0 + k < K) ? B[nn + (int64_t)(k0 + k) * ldb] : 0.f;
+    }
+  } else {
+    const int k = t & 15;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int nn = (t >> 4) + 16 * q;
+      rb[q] = (nn < N && k0 + k < K) ? B[(k0 + k) + (int64_t)nn * ldb] : 0.f;
+    }
+  }
+}
+
+template <bool A_KC, bool B_KC>
+__device__ __forceinline__ void g2_store(float* a, float* b, const float (&ra)[16], const float (&rb)[8]) {
+  const int t = threadIdx.x;
+  if (!A_KC) {
+#pragma unroll
+    for (int q = 0; q < 16; ++q) a[q * kPA2 + t] = ra[q];
+  } else {
+    const int k = t & 15;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) a[k * kPA2 + (t >> 4) + 16 * q] = ra[q];
+  }
+  if (!B_KC) {
+    const int nn = t & 127;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) b[((t >> 7) + 2 * q) * kPB2 + nn] = rb[q];
+  } else {
+    const int k = t & 15;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) b[k * kPB2 + (t >> 4) + 16 * q] = rb[q];
+  }
+}
+
+// acc += A(M x K) B(N x K)^T for a 256 x 128 tile (operand conventions of gemm_tile)
+template <bool A_KC, bool B_KC>
+__device__ __forceinline__ void gemm_tile2(const float* __restrict__ A, int64_t lda, const float* __restrict__ B,
+                                           int64_t ldb, int M, int N, int K, f4_t (&acc)[8][4], G2Lds& S) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wm = (w & 1) * 128, wn = (w >> 1) * 64;
+  const int r = lane & 15, g = lane >> 4;
+  float ra[16], rb[8];
+  if (K <= 0) return;
+  g2_load<A_KC, B_KC>(A, lda, B, ldb, M, N, K, 0, ra, rb);
+  g2_store<A_KC, B_KC>(S.a[0], S.b[0], ra, rb);
+  __syncthreads();
+  int buf = 0;
+  for (int k0 = 0; k0 < K; k0 += kG2K) {
+    const bool more = k0 + kG2K < K;
+    if (more) g2_load<A_KC, B_KC>(A, lda, B, ldb, M, N, K, k0 + kG2K, ra, rb);
+    const float* cA = S.a[buf];
+    const float* cB = S.b[buf];
+#pragma unroll
+    for (int kk = 0; kk < kG2K; kk += 4) {
+      const f4_t a0 = *reinterpret_cast<const f4_t*>(cA + (kk + g) * kPA2 + wm + 8 * r);
+      const f4_t a1 = *reinterpret_cast<const f4_t*>(cA + (kk + g) * kPA2 + wm + 8 * r + 4);
+      const f4_t b0 = *reinterpret_cast<const f4_t*>(cB + (kk + g) * kPB2 + wn + 4 * r);
+      const float a[8] = {a0[0], a0[1], a0[2], a0[3], a1[0], a1[1], a1[2], a1[3]};
+      const float b[4] = {b0[0], b0[1], b0[2], b0[3]};
+#pragma unroll
+      for (int i = 0; i < 8; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+    if (more) g2_store<A_KC, B_KC>(S.a[buf ^ 1], S.b[buf ^ 1], ra, rb);
+    __syncthreads();
+    buf ^= 1;
+  }
+}
+
+// Epilogue of a 256 x 128 tile through LDS, one 64-column half at a time: frow(r, c, v)
+// is called with rows fastest across the work-group, then (if COLS) fcol(r, c, v) with
+// columns fastest, so that both a column-major block and its transpose are written with
+// coalesced accesses.  Starts and ends with a barrier (the staging area aliases the
+// operand buffers).
+template <bool COLS, typename FR, typename FC>
+__device__ __forceinline__ void g2_epilogue(const f4_t (&acc)[8][4], G2Smem& sm, FR frow, FC fcol) {
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int wm = (w & 1) * 128;
+  const int r = lane & 15, g = lane >> 4;
+  for (int h = 0; h < 2; ++h) {
+    __syncthreads();
+    if ((w >> 1) == h) {
+#pragma unroll
+      for (int i = 0; i < 8; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) sm.ep[4 * r + j][wm + 8 * (4 * g + q) + i] = acc[i][j][q];
+    }
+    __syncthreads();
+    for (int e = t; e < kG2M * 64; e += kThreads) {
+      const int row = e & (kG2M - 1), cl = e >> 8;
+      frow(row, 64 * h + cl, sm.ep[cl][row]);
+    }
+    if constexpr (COLS) {
+      for (int e = t; e < kG2M * 64; e += kThreads) {
+        const int cl = e & 63, row = e >> 6;
+        fcol(row, 64 * h + cl, sm.ep[cl][row]);
+      }
+    }
+  }
+  __syncthreads();
 }
 
 // ------------------------------------------------------------------ assembly kernels
@@ -624,6 +774,37 @@ __global__ __launch_bounds__(kThreads) void k_update(DevSym S, LaunchList L, int
       if (rr < M && cc < N && gi >= gj) F[gi + (int64_t)gj * n] -= v;
     });
   }
+}
+
+// FP32 trailing SYRK (the update matrix: columns [p, n), K = all p pivot columns) in
+// 256 x 128 tiles: 128-wide column tiles, rows from the tile's first column down.
+__global__ __launch_bounds__(kThreads) void k_syrk2(DevSym S, LaunchList L, NumBufs<float> B) {
+  __shared__ G2Smem sm;
+  int fi; int64_t loc;
+  find_front(L, wg_id(), fi, loc);
+  const int s = L.fronts[fi];
+  const int n = fn(S, s), p = fp(S, s);
+  int ct = 0;
+  int64_t r = loc;
+  while (true) {
+    const int c0 = p + kG2N * ct;
+    if (c0 >= n) return;   // unreachable for a consistent launch list
+    const int64_t nr = (n - c0 + kG2M - 1) / kG2M;
+    if (r < nr) break;
+    r -= nr;
+    ++ct;
+  }
+  const int col0 = p + kG2N * ct;
+  const int row0 = col0 + kG2M * (int)r;
+  const int M = min(kG2M, n - row0), N = min(kG2N, n - col0);
+  float* F = B.Wcur + S.Woff[s];
+  f4_t acc[8][4];
+  zero_acc2(acc);
+  gemm_tile2<false, false>(F + row0, n, F + col0, n, M, N, p, acc, sm.g);
+  g2_epilogue<false>(acc, sm, [&](int rr, int cc, float v) {
+    const int gi = row0 + rr, gj = col0 + cc;
+    if (rr < M && cc < N && gi >= gj) F[gi + (int64_t)gj * n] -= v;
+  }, [](int, int, float) {});
 }
 
 template <typename T>
@@ -1384,14 +1565,51 @@ __global__ __launch_bounds__(kThreads) void k_sel_gemm2(DevSym S, LaunchList L, 
   }
 }
 
-// Sum of the split-K partials of one 128 x 128 tile of Sigma[R', K] in a fixed order,
-// written to Sigma[R', K] and its mirror Sigma[K, R'].  aux = (split, first work-group of
-// the front in the partial launch).  One work-group per 64-column half of a tile: the
-// sums are formed with coalesced reads, written down the columns, and staged in LDS so
-// that the mirror is written along its rows.
-template <typename T>
+// FP32 Sigma[R', K] = -Sigma[R', R'] Y in 256 x 128 tiles, split over K like k_sel_gemm2
+// (partials are 256 x 128, column-major).
+__global__ __launch_bounds__(kThreads) void k_sel_gemm3(DevSym S, LaunchList L, int step, SelBufs<float> B) {
+  __shared__ G2Smem sm;
+  int fi; int64_t loc;
+  find_front(L, wg_id(), fi, loc);
+  const int s = L.fronts[fi];
+  const int n = fn(S, s), p = fp(S, s);
+  const OuterBlk o = outer_blk(p, n, step);
+  const int split = L.aux[2 * fi];
+  const int nct = (o.kb2 + kG2N - 1) / kG2N;
+  const int tile = (int)(loc / split), sp = (int)(loc % split);
+  const int rt = tile / nct, ctile = tile % nct;
+  const int row0 = o.rs + kG2M * rt, col0 = kG2N * ctile;
+  const int M = min(kG2M, n - row0), N = min(kG2N, o.kb2 - col0);
+  const int np = n - o.rs;
+  const int kpart = ((np + split - 1) / split + kG2K - 1) / kG2K * kG2K;
+  const int kb = min(np, sp * kpart), ke = min(np, kb + kpart);
+  float* Sf = B.Scur + S.Woff[s];
+  const float* Y = B.Y + S.Voff[s] * kNB2;
+  f4_t acc[8][4];
+  zero_acc2(acc);
+  gemm_tile2<false, true>(Sf + row0 + (int64_t)(o.rs + kb) * n, n, Y + kb + (int64_t)col0 * n, n, M, N, ke - kb,
+                          acc, sm.g);
+  if (split == 1) {
+    g2_epilogue<true>(acc, sm, [&](int r, int c, float v) {
+      if (r < M && c < N) Sf[(row0 + r) + (int64_t)(o.k2 + col0 + c) * n] = -v;
+    }, [&](int r, int c, float v) {
+      if (r < M && c < N) Sf[(o.k2 + col0 + c) + (int64_t)(row0 + r) * n] = -v;
+    });
+  } else {
+    float* out = B.gpart + wg_id() * (int64_t)(kG2M * kG2N);
+    g2_epilogue<false>(acc, sm, [&](int r, int c, float v) { out[r + c * kG2M] = v; }, [](int, int, float) {});
+  }
+}
+
+// Sum of the split-K partials of one TM x 128 tile of Sigma[R', K] (TM = 128 for the
+// 128 x 128 tiles, 256 for the FP32 256 x 128 tiles) in a fixed order, written to
+// Sigma[R', K] and its mirror Sigma[K, R'].  aux = (split, first work-group of the front
+// in the partial launch).  One work-group per 64-column half of a tile: the sums are
+// formed with coalesced reads, written down the columns, and staged in LDS so that the
+// mirror is written along its rows.
+template <typename T, int TM>
 __global__ __launch_bounds__(kThreads) void k_sel_gemm_reduce(DevSym S, LaunchList L, int step, SelBufs<T> B) {
-  __shared__ T tileS[64][kBT + 1];
+  __shared__ T tileS[64][TM + 1];
   int fi; int64_t loc;
   find_front(L, wg_id(), fi, loc);
   const int s = L.fronts[fi];
@@ -1399,32 +1617,33 @@ __global__ __launch_bounds__(kThreads) void k_sel_gemm_reduce(DevSym S, LaunchLi
   const OuterBlk o = outer_blk(p, n, step);
   const int split = L.aux[2 * fi];
   const int64_t base = L.aux[2 * fi + 1];
-  const int nct = (o.kb2 + kBT - 1) / kBT;
+  const int nct = (o.kb2 + 127) / 128;
   const int tile = (int)(loc >> 1), half = (int)(loc & 1);
   const int rt = tile / nct, ctile = tile % nct;
-  const int row0 = o.rs + kBT * rt, col0 = kBT * ctile + 64 * half;
-  const int M = min(kBT, n - row0), N = min(64, o.kb2 - col0);
+  const int row0 = o.rs + TM * rt, col0 = 128 * ctile + 64 * half;
+  const int M = min(TM, n - row0), N = min(64, o.kb2 - col0);
   if (N <= 0) return;
-  const T* pp = B.gpart + (base + (int64_t)tile * split) * (kBT * kBT) + (int64_t)(64 * half) * kBT;
+  constexpr int64_t PT = (int64_t)TM * 128;
+  const T* pp = B.gpart + (base + (int64_t)tile * split) * PT + (int64_t)(64 * half) * TM;
   T* Sf = B.Scur + S.Woff[s];
-  for (int e = threadIdx.x; e < kBT * 64; e += kThreads) {
-    const int r = e % kBT, c = e / kBT;
+  for (int e = threadIdx.x; e < TM * 64; e += kThreads) {
+    const int r = e % TM, c = e / TM;
     T a = T(0);
     int q = 0;
     for (; q + 4 <= split; q += 4) {
-      const T v0 = pp[(int64_t)q * (kBT * kBT) + e], v1 = pp[(int64_t)(q + 1) * (kBT * kBT) + e];
-      const T v2 = pp[(int64_t)(q + 2) * (kBT * kBT) + e], v3 = pp[(int64_t)(q + 3) * (kBT * kBT) + e];
+      const T v0 = pp[(int64_t)q * PT + e], v1 = pp[(int64_t)(q + 1) * PT + e];
+      const T v2 = pp[(int64_t)(q + 2) * PT + e], v3 = pp[(int64_t)(q + 3) * PT + e];
       a += v0;
       a += v1;
       a += v2;
       a += v3;
     }
-    for (; q < split; ++q) a += pp[(int64_t)q * (kBT * kBT) + e];
+    for (; q < split; ++q) a += pp[(int64_t)q * PT + e];
     tileS[c][r] = -a;
     if (r < M && c < N) Sf[(row0 + r) + (int64_t)(o.k2 + col0 + c) * n] = -a;
   }
   __syncthreads();
-  for (int e = threadIdx.x; e < kBT * 64; e += kThreads) {
+  for (int e = threadIdx.x; e < TM * 64; e += kThreads) {
     const int c = e & 63, r = e >> 6;
     if (r < M && c < N) Sf[(o.k2 + col0 + c) + (int64_t)(row0 + r) * n] = tileS[c][r];
   }
@@ -1741,7 +1960,19 @@ template <typename T> void launch_sel_gemm2(hipStream_t st, const DevSym& S, con
 template <typename T> void launch_sel_gemm_reduce(hipStream_t st, const DevSym& S, const LaunchList& L, int step,
                                                   SelBufs<T> B) {
   if (L.total <= 0) return;
-  hipLaunchKernelGGL(k_sel_gemm_reduce<T>, dim3((unsigned)L.total), dim3(kThreads), 0, st, S, L, step, B);
+  if constexpr (std::is_same<T, float>::value)
+    hipLaunchKernelGGL((k_sel_gemm_reduce<float, kG2M>), dim3((unsigned)L.total), dim3(kThreads), 0, st, S, L, step,
+                       B);
+  else
+    hipLaunchKernelGGL((k_sel_gemm_reduce<T, 128>), dim3((unsigned)L.total), dim3(kThreads), 0, st, S, L, step, B);
+}
+void launch_sel_gemm3(hipStream_t st, const DevSym& S, const LaunchList& L, int step, SelBufs<float> B) {
+  if (L.total <= 0) return;
+  hipLaunchKernelGGL(k_sel_gemm3, dim3((unsigned)L.total), dim3(kThreads), 0, st, S, L, step, B);
+}
+void launch_syrk2(hipStream_t st, const DevSym& S, const LaunchList& L, NumBufs<float> B) {
+  if (L.total <= 0) return;
+  hipLaunchKernelGGL(k_syrk2, dim3((unsigned)L.total), dim3(kThreads), 0, st, S, L, B);
 }
 template <typename T> void launch_sel_part2(hipStream_t st, const DevSym& S, const LaunchList& L, int step,
                                             SelBufs<T> B) {
