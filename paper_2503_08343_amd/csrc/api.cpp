@@ -86,6 +86,7 @@ struct Level {
   std::vector<HostList> sY2, sgemm2, sgred, spart2, sfin2;
   std::vector<HostList> sgemm3, sgred3;   // FP32: 256 x 128 tiles of the Sigma[R', K] products
   HostList syrk3;                          // FP32: 256 x 128 tiles of the trailing SYRK
+  std::vector<HostList> pupd3, pred3;      // FP32: left-looking panel update per outer block
   double wsize_elems_scatter = 0.0;
 };
 
@@ -499,6 +500,40 @@ gmrf_status build_plan(gmrf_t h) {
         return upd_tiles(nF(s), pF(s), 1, k, kBigTile);
       }, [&](int32_t s) { return upd_cost(nF(s), pF(s), 1, k); }));
     }
+    // FP32 left-looking panel updates, one per outer block K >= 1 (list K-1 unused for K = 0)
+    {
+      int nK = 0;
+      for (int32_t s : lv.fronts) nK = std::max<int>(nK, (int)((pF(s) + kNB2 - 1) / kNB2));
+      lv.pupd3.assign(std::max(nK, 1), HostList());
+      lv.pred3.assign(std::max(nK, 1), HostList());
+      for (int K = 1; K < nK; ++K) {
+        const int64_t k2 = (int64_t)K * kNB2;
+        auto pact = [&](int32_t s) { return pF(s) > k2; };
+        auto pkb2 = [&](int32_t s) { return std::min<int64_t>(kNB2, pF(s) - k2); };
+        auto ptiles = [&](int32_t s) -> int64_t {
+          return pact(s) ? ((nF(s) - k2 + 255) / 256) * ((pkb2(s) + 127) / 128) : 0;
+        };
+        int64_t ptot = 0;
+        for (int32_t s : lv.fronts) ptot += ptiles(s);
+        const int64_t pS = choose_split(ptot, kSlots256, k2 / kSplitMinK);
+        auto psplit = [&](int32_t s) -> int64_t { return ptiles(s) > 0 ? std::max<int64_t>(1, pS) : 1; };
+        lv.pupd3[K] = B.add(lv.fronts, [&](int32_t s) -> int64_t { return ptiles(s) * psplit(s); },
+                            [&](int32_t s) {
+          const double b = (double)pkb2(s), m = (double)(nF(s) - k2);
+          const double E = b * m - 0.5 * b * (b - 1.0);
+          return Cost{2.0 * (double)k2 * E, 2.0 * E + (m + b) * (double)k2};
+        }, [&](int32_t s) { return std::make_pair((int32_t)psplit(s), (int32_t)0); });
+        const HostList& G = lv.pupd3[K];
+        std::unordered_map<int32_t, int64_t> gbase;
+        for (int32_t i = 0; i < G.count; ++i) gbase[B.fronts[G.f_off + i]] = B.prefix[G.p_off + i];
+        if (pS > 1) h->gpart3_max = std::max(h->gpart3_max, G.total);
+        lv.pred3[K] = B.add(lv.fronts, [&](int32_t s) -> int64_t { return psplit(s) > 1 ? 2 * ptiles(s) : 0; },
+                            [&](int32_t s) {
+          const double b = (double)pkb2(s), m = (double)(nF(s) - k2);
+          return Cost{0.0, (double)psplit(s) * m * b + 2.0 * m * b};
+        }, [&](int32_t s) { return std::make_pair((int32_t)psplit(s), (int32_t)gbase[s]); });
+      }
+    }
     // two-level selected inversion: outer blocks of 256 columns, counted from the right
     lv.nsteps2 = 0;
     for (int32_t s : lv.fronts) lv.nsteps2 = std::max<int>(lv.nsteps2, (int)((pF(s) + kNB2 - 1) / kNB2));
@@ -693,6 +728,8 @@ gmrf_status alloc_numeric(gmrf_t h) {
   HIPCHK(h, h->d_scale.alloc(h->n));
   HIPCHK(h, h->d_sexp.alloc(h->n));
   HIPCHK(h, h->d_qhat.alloc(h->nnzq));
+  if (std::is_same<T, float>::value)
+    HIPCHK(h, h->d_gpart.alloc((size_t)std::max<int64_t>(h->gpart3_max, 1) * 256 * 128 * sizeof(float)));
   return GMRF_OK;
 }
 
@@ -729,6 +766,19 @@ gmrf_status run_factor(gmrf_t h) {
         launch_extend_add<T>(st, S, dev_list(h, lv.ext[c]), (int)c, B.Wchild, B.Wcur);
       });
     for (int k = 0; k < lv.nsteps; ++k) {
+      if constexpr (std::is_same<T, float>::value) {
+        const int K = k / (kNB2 / kNB);
+        if (k % (kNB2 / kNB) == 0 && K >= 1 && K < (int)lv.pupd3.size()) {
+          if (lv.pupd3[K].total > 0)
+            prof_launch(h, KC_UPDATE, lv.pupd3[K].flops, lv.pupd3[K].elems, [&] {
+              launch_panel_upd3(st, S, dev_list(h, lv.pupd3[K]), K, B, (float*)h->d_gpart.p);
+            });
+          if (lv.pred3[K].total > 0)
+            prof_launch(h, KC_UPDATE, 0.0, lv.pred3[K].elems, [&] {
+              launch_panel_red3(st, S, dev_list(h, lv.pred3[K]), K, B, (const float*)h->d_gpart.p);
+            });
+        }
+      }
       prof_launch(h, KC_POTRF, lv.potrf[k].flops, lv.potrf[k].elems,
                   [&] { launch_potrf<T>(st, S, dev_list(h, lv.potrf[k]), k, B); });
       prof_launch(h, KC_TRSM, lv.trsm[k].flops, lv.trsm[k].elems,
@@ -736,7 +786,7 @@ gmrf_status run_factor(gmrf_t h) {
       if (lv.upd[k].total > 0)
         prof_launch(h, KC_UPDATE, lv.upd[k].flops, lv.upd[k].elems,
                     [&] { launch_update<T>(st, S, dev_list(h, lv.upd[k]), k, 0, B); });
-      if (lv.upd_out[k].total > 0)
+      if (!std::is_same<T, float>::value && lv.upd_out[k].total > 0)
         prof_launch(h, KC_UPDATE, lv.upd_out[k].flops, lv.upd_out[k].elems,
                     [&] { launch_update<T>(st, S, dev_list(h, lv.upd_out[k]), k, 1, B); });
     }

@@ -152,6 +152,11 @@ template <typename T> void launch_sel_gemm_reduce(hipStream_t st, const DevSym& 
 // 256 x 128) and the trailing SYRK of the update matrices
 void launch_sel_gemm3(hipStream_t st, const DevSym& S, const LaunchList& L, int step, SelBufs<float> B);
 void launch_syrk2(hipStream_t st, const DevSym& S, const LaunchList& L, NumBufs<float> B);
+// FP32 left-looking update of outer block K of the pivot panels from all earlier outer
+// blocks (split-K partials in part, summed by launch_panel_red3)
+void launch_panel_upd3(hipStream_t st, const DevSym& S, const LaunchList& L, int K, NumBufs<float> B, float* part);
+void launch_panel_red3(hipStream_t st, const DevSym& S, const LaunchList& L, int K, NumBufs<float> B,
+                       const float* part);
 template <typename T> void launch_sel_part2(hipStream_t st, const DevSym& S, const LaunchList& L, int step, SelBufs<T> B);
 template <typename T> void launch_sel_fin2(hipStream_t st, const DevSym& S, const LaunchList& L, const LaunchList& Lpart,
                                            int step, SelBufs<T> B, const int64_t* D2off, const T* D2);

@@ -807,6 +807,83 @@ __global__ __launch_bounds__(kThreads) void k_syrk2(DevSym S, LaunchList L, NumB
   }, [](int, int, float) {});
 }
 
+// FP32 left-looking update of outer block K of the pivot panel: before its first 64-block
+// is factored, the block's columns [k2, k2 + kb2) (rows k2..n) receive
+// -L[rows, 0:k2] L[cols, 0:k2]^T from all earlier outer blocks in one long-K product
+// (256 x 128 tiles; split over K like the Sigma[R', K] products when a depth has too few
+// tiles).  With split 1 the tile is subtracted in place (lower part only), else its
+// partial goes to part + wg * 256 * 128 and k_panel_red3 subtracts the sum.
+__global__ __launch_bounds__(kThreads) void k_panel_upd3(DevSym S, LaunchList L, int K, NumBufs<float> B,
+                                                         float* __restrict__ part) {
+  __shared__ G2Smem sm;
+  int fi; int64_t loc;
+  find_front(L, wg_id(), fi, loc);
+  const int s = L.fronts[fi];
+  const int n = fn(S, s), p = fp(S, s);
+  const int k2 = K * kNB2, kb2 = min(kNB2, p - k2);
+  const int split = L.aux[2 * fi];
+  const int nct = (kb2 + kG2N - 1) / kG2N;
+  const int tile = (int)(loc / split), sp = (int)(loc % split);
+  const int rt = tile / nct, ctile = tile % nct;
+  const int row0 = k2 + kG2M * rt, col0 = k2 + kG2N * ctile;
+  const int M = min(kG2M, n - row0), N = min(kG2N, k2 + kb2 - col0);
+  const int kpart = ((k2 + split - 1) / split + kG2K - 1) / kG2K * kG2K;
+  const int kb = min(k2, sp * kpart), ke = min(k2, kb + kpart);
+  float* F = B.Wcur + S.Woff[s];
+  f4_t acc[8][4];
+  zero_acc2(acc);
+  gemm_tile2<false, false>(F + row0 + (int64_t)kb * n, n, F + col0 + (int64_t)kb * n, n, M, N, ke - kb, acc, sm.g);
+  if (split == 1) {
+    g2_epilogue<false>(acc, sm, [&](int r, int c, float v) {
+      const int gi = row0 + r, gj = col0 + c;
+      if (r < M && c < N && gi >= gj) F[gi + (int64_t)gj * n] -= v;
+    }, [](int, int, float) {});
+  } else {
+    float* out = part + wg_id() * (int64_t)(kG2M * kG2N);
+    g2_epilogue<false>(acc, sm, [&](int r, int c, float v) { out[r + c * kG2M] = v; }, [](int, int, float) {});
+  }
+}
+
+// Subtract the fixed-order sum of the split-K partials of k_panel_upd3 (one work-group per
+// 64-column half of a tile; aux = (split, first work-group of the front in that launch)).
+__global__ __launch_bounds__(kThreads) void k_panel_red3(DevSym S, LaunchList L, int K, NumBufs<float> B,
+                                                         const float* __restrict__ part) {
+  int fi; int64_t loc;
+  find_front(L, wg_id(), fi, loc);
+  const int s = L.fronts[fi];
+  const int n = fn(S, s), p = fp(S, s);
+  const int k2 = K * kNB2, kb2 = min(kNB2, p - k2);
+  const int split = L.aux[2 * fi];
+  const int64_t base = L.aux[2 * fi + 1];
+  const int nct = (kb2 + kG2N - 1) / kG2N;
+  const int tile = (int)(loc >> 1), half = (int)(loc & 1);
+  const int rt = tile / nct, ctile = tile % nct;
+  const int row0 = k2 + kG2M * rt, col0 = k2 + kG2N * ctile + 64 * half;
+  const int M = min(kG2M, n - row0), N = min(64, k2 + kb2 - col0);
+  if (N <= 0) return;
+  constexpr int64_t PT = (int64_t)kG2M * kG2N;
+  const float* pp = part + (base + (int64_t)tile * split) * PT + (int64_t)(64 * half) * kG2M;
+  float* F = B.Wcur + S.Woff[s];
+  for (int e = threadIdx.x; e < kG2M * 64; e += kThreads) {
+    const int r = e % kG2M, c = e / kG2M;
+    const int gi = row0 + r, gj = col0 + c;
+    if (r < M && c < N && gi >= gj) {
+      float a = 0.f;
+      int q = 0;
+      for (; q + 4 <= split; q += 4) {
+        const float v0 = pp[(int64_t)q * PT + e], v1 = pp[(int64_t)(q + 1) * PT + e];
+        const float v2 = pp[(int64_t)(q + 2) * PT + e], v3 = pp[(int64_t)(q + 3) * PT + e];
+        a += v0;
+        a += v1;
+        a += v2;
+        a += v3;
+      }
+      for (; q < split; ++q) a += pp[(int64_t)q * PT + e];
+      F[gi + (int64_t)gj * n] -= a;
+    }
+  }
+}
+
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_copy_L(DevSym S, LaunchList L, NumBufs<T> B) {
   int fi; int64_t loc;
@@ -1969,6 +2046,15 @@ template <typename T> void launch_sel_gemm_reduce(hipStream_t st, const DevSym& 
 void launch_sel_gemm3(hipStream_t st, const DevSym& S, const LaunchList& L, int step, SelBufs<float> B) {
   if (L.total <= 0) return;
   hipLaunchKernelGGL(k_sel_gemm3, dim3((unsigned)L.total), dim3(kThreads), 0, st, S, L, step, B);
+}
+void launch_panel_upd3(hipStream_t st, const DevSym& S, const LaunchList& L, int K, NumBufs<float> B, float* part) {
+  if (L.total <= 0) return;
+  hipLaunchKernelGGL(k_panel_upd3, dim3((unsigned)L.total), dim3(kThreads), 0, st, S, L, K, B, part);
+}
+void launch_panel_red3(hipStream_t st, const DevSym& S, const LaunchList& L, int K, NumBufs<float> B,
+                       const float* part) {
+  if (L.total <= 0) return;
+  hipLaunchKernelGGL(k_panel_red3, dim3((unsigned)L.total), dim3(kThreads), 0, st, S, L, K, B, part);
 }
 void launch_syrk2(hipStream_t st, const DevSym& S, const LaunchList& L, NumBufs<float> B) {
   if (L.total <= 0) return;
