@@ -30,6 +30,13 @@ sys.path.insert(0, ROOT)
 METRIC = "factor+solve+selinv GFLOP/s at 1M-dof space-time GMRF; FP32+refine vs FP64"
 PEAK_TFLOPS = {0: 78.6, 1: 157.3}   # MI355X dense FP64 / FP32 (vector = MFMA)
 HBM_GBS = 8000.0
+# HBM bytes per launch of the dominant kernel class, from two rocprofv3 counter passes
+# (FETCH_SIZE, WRITE_SIZE) scaled by the same counters over a plain 1 GiB copy; valid only
+# for the kernel build they were taken on (keyed by class and precision: 1 = FP32+refine)
+PMC_TRAFFIC = {
+    ("sel_gemm", 1): {"bytes_per_launch": 5.7277e9, "kernel": "k_sel_gemm3",
+                      "source": "profiles/sel_gemm3_advdiff128x128x64_fp32_hbm_bytes.md"},
+}
 
 
 def log(*a):
@@ -172,8 +179,11 @@ def main():
     # region give its live average launch time and rate
     ks, dname, d = hr["ks"]
     achieved = d["flops"] / (d["ms"] * 1e-3) / 1e12 if d["ms"] > 0 else 0.0
+    traffic = PMC_TRAFFIC.get((dname, prec_head))
     roof = dict(bound="mfma", kernel=dname, achieved=round(achieved, 3), peak=PEAK_TFLOPS[prec_head],
-                unit="TFLOP/s", frac=round(achieved / PEAK_TFLOPS[prec_head], 4), traffic=None,
+                unit="TFLOP/s", frac=round(achieved / PEAK_TFLOPS[prec_head], 4),
+                traffic=traffic["bytes_per_launch"] if traffic else None,
+                traffic_source=traffic["source"] if traffic else None,
                 launches=d["launches"], avg_launch_ms=round(d["ms"] / max(d["launches"], 1), 4),
                 flops_per_launch=d["flops"] / max(d["launches"], 1))
     # whole-path roofline time (factor+selinv at MFMA peak, solves at HBM peak)

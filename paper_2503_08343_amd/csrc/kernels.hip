@@ -533,6 +533,12 @@ __global__ void k_fill(V* p, int64_t n, V v) {
     p[i] = v;
 }
 
+__global__ void k_zero16(uint4* p, int64_t n16) {
+  const uint4 z = make_uint4(0u, 0u, 0u, 0u);
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = z;
+}
+
 template <typename T>
 __global__ void k_scatter(int64_t cnt, const int64_t* __restrict__ map_e, const int64_t* __restrict__ map_off,
                           const double* __restrict__ qhat, T* __restrict__ W) {
@@ -1864,7 +1870,11 @@ void launch_fill_f64(hipStream_t st, double* p, int64_t n, double v) {
 
 template <typename T> void launch_zero(hipStream_t st, T* p, int64_t n) {
   if (n <= 0) return;
-  hipLaunchKernelGGL(k_fill<T>, dim3(grid_for(n, 1 << 20)), dim3(kThreads), 0, st, p, n, T(0));
+  // 16-byte stores for the bulk (p is the start of a device allocation), then the tail
+  const int64_t bytes = n * (int64_t)sizeof(T), n16 = bytes / 16;
+  if (n16 > 0) hipLaunchKernelGGL(k_zero16, dim3(grid_for(n16, 1 << 20)), dim3(kThreads), 0, st, (uint4*)p, n16);
+  const int64_t done = n16 * 16 / (int64_t)sizeof(T);
+  if (done < n) hipLaunchKernelGGL(k_fill<T>, dim3(1), dim3(kThreads), 0, st, p + done, n - done, T(0));
 }
 template <typename T> void launch_scatter(hipStream_t st, int64_t cnt, const int64_t* map_e,
                                           const int64_t* map_off, const double* qhat, T* W) {
