@@ -581,10 +581,90 @@ __device__ __forceinline__ double rsqrt_newton(double d) {
 // FP64 Cholesky of the step-th 64x64 diagonal block of each listed front and the inverse
 // of the resulting lower-triangular block, both held in registers: thread (ti, tl) owns
 // rows ti + 16a and columns tl + 16b (a, b < 4) of the block and of its inverse X.  Each
-// phase j needs one barrier: the owners of column j finish it (their 16 lanes share one
-// wave, so the pivot is a lane shuffle) and publish it through LDS; every thread applies
-// the previous column to its trailing elements; the inverse follows two phases behind
-// (forward substitution L X = I: row j-1 of X is scaled and published, row j-2 applied).
+// phase j needs one barrier: the owners of column j (16 lanes of one wave, so the pivot is
+// a lane read) finish it and publish it through LDS with zeros on and above the diagonal,
+// which lets every thread apply the previous column to all its elements without
+// predicates; the inverse follows two phases behind (forward substitution L X = I: row
+// j-1 of X is scaled and published, row j-2 applied).  The phases are generated per
+// 16-column block JB so that every register index is a compile-time constant.
+__device__ __forceinline__ double readlane_f64(double v, int lane) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), lane);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+template <int A>
+__device__ __forceinline__ void potrf_scale_row(double (&x_r)[4][4], double* rowb, int tl, double rinv) {
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    x_r[A][b] *= rinv;
+    rowb[tl + 16 * b] = x_r[A][b];
+  }
+}
+
+template <int JB>
+__device__ __forceinline__ void potrf_phase(int jr, int kb, int t, int ti, int tl, double (&a_r)[4][4],
+                                            double (&x_r)[4][4], double (*colb)[kNB], double (*rowb)[kNB],
+                                            double* pinv, int* fail) {
+  const int j = 16 * JB + jr;
+  if (j >= kb + 2) return;
+  __syncthreads();
+  if (j >= 1 && j - 1 < kb) {
+    const double* c1 = colb[(j - 1) & 3];
+    double ci[4], cl[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) { ci[a] = c1[ti + 16 * a]; cl[a] = c1[tl + 16 * a]; }
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) a_r[a][b] -= ci[a] * cl[b];
+  }
+  if (j >= 2 && j - 2 < kb) {
+    const double* c2 = colb[(j - 2) & 3];
+    const double* r2 = rowb[(j - 2) & 3];
+    double ci[4], rc[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) { ci[a] = c2[ti + 16 * a]; rc[a] = r2[tl + 16 * a]; }
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) x_r[a][b] -= ci[a] * rc[b];
+  }
+  if (j >= 1 && j - 1 < kb && ti == ((j - 1) & 15)) {
+    const double rinv = pinv[(j - 1) & 3];
+    if (jr >= 1) {
+      if constexpr (JB < 4) potrf_scale_row<JB>(x_r, rowb[(j - 1) & 3], tl, rinv);
+    } else {
+      if constexpr (JB >= 1) potrf_scale_row<JB - 1>(x_r, rowb[(j - 1) & 3], tl, rinv);
+    }
+  }
+  if constexpr (JB < 4) {
+    if (j < kb && (t >> 6) == (jr >> 2)) {
+      double cv[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) cv[a] = a_r[a][JB];
+      const double d = readlane_f64(cv[JB], 16 * (jr & 3) + jr);
+      if (tl == jr) {
+        const bool bad = !(d > 0.0);
+        const double linv = bad ? 1.0 : rsqrt_newton(d);
+        const double ljj = bad ? 1.0 : d * linv;
+        if (ti == jr) {
+          pinv[j & 3] = linv;
+          if (bad) atomicMin(fail, j);
+        }
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+          const int i = ti + 16 * a;
+          const double v = i > j ? cv[a] * linv : 0.0;
+          colb[j & 3][i] = v;
+          a_r[a][JB] = i == j ? ljj : v;
+        }
+      }
+    }
+  }
+}
+
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_potrf(DevSym S, LaunchList L, int step, NumBufs<T> B) {
   __shared__ double colb[4][kNB];
@@ -609,74 +689,11 @@ __global__ __launch_bounds__(kThreads) void k_potrf(DevSym S, LaunchList L, int 
       x_r[a][b] = i == l ? 1.0 : 0.0;
     }
   if (t == 0) fail = INT_MAX;
-  for (int j = 0; j < kb + 2; ++j) {
-    __syncthreads();
-    // trailing update with column j-1
-    if (j >= 1 && j - 1 < kb) {
-      const double* c1 = colb[(j - 1) & 3];
-      double ci[4], cl[4];
-#pragma unroll
-      for (int a = 0; a < 4; ++a) { ci[a] = c1[ti + 16 * a]; cl[a] = c1[tl + 16 * a]; }
-#pragma unroll
-      for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b)
-          if (ti + 16 * a > j - 1 && tl + 16 * b > j - 1) a_r[a][b] -= ci[a] * cl[b];
-    }
-    // inverse: apply row j-2 of X, then scale and publish row j-1
-    if (j >= 2 && j - 2 < kb) {
-      const double* c2 = colb[(j - 2) & 3];
-      const double* r2 = rowb[(j - 2) & 3];
-      double ci[4], rc[4];
-#pragma unroll
-      for (int a = 0; a < 4; ++a) { ci[a] = c2[ti + 16 * a]; rc[a] = r2[tl + 16 * a]; }
-#pragma unroll
-      for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b)
-          if (ti + 16 * a > j - 2) x_r[a][b] -= ci[a] * rc[b];
-    }
-    if (j >= 1 && j - 1 < kb && ti == ((j - 1) & 15)) {
-      const int ja = (j - 1) >> 4;
-      const double rinv = pinv[(j - 1) & 3];
-#pragma unroll
-      for (int a = 0; a < 4; ++a)
-        if (a == ja) {
-#pragma unroll
-          for (int b = 0; b < 4; ++b) {
-            x_r[a][b] *= rinv;
-            rowb[(j - 1) & 3][tl + 16 * b] = x_r[a][b];
-          }
-        }
-    }
-    // finish column j
-    if (j < kb && (t >> 6) == ((j & 15) >> 2)) {
-      const int jb = j >> 4, jr = j & 15;
-      double cv[4];
-#pragma unroll
-      for (int a = 0; a < 4; ++a) cv[a] = jb == 0 ? a_r[a][0] : jb == 1 ? a_r[a][1] : jb == 2 ? a_r[a][2] : a_r[a][3];
-      const double dsel = jb == 0 ? cv[0] : jb == 1 ? cv[1] : jb == 2 ? cv[2] : cv[3];
-      const double d = __shfl(dsel, 16 * (jr & 3) + jr, 64);
-      if (tl == jr) {
-        const bool bad = !(d > 0.0);
-        const double linv = bad ? 1.0 : rsqrt_newton(d);
-        const double ljj = bad ? 1.0 : d * linv;
-        if (ti == jr) {
-          pinv[j & 3] = linv;
-          if (bad) atomicMin(&fail, j);
-        }
-#pragma unroll
-        for (int a = 0; a < 4; ++a) {
-          const int i = ti + 16 * a;
-          const double v = i > j ? cv[a] * linv : (i == j ? ljj : 0.0);
-          colb[j & 3][i] = v;
-#pragma unroll
-          for (int b = 0; b < 4; ++b)
-            if (b == jb) a_r[a][b] = v;
-        }
-      }
-    }
-  }
+  for (int jr = 0; jr < 16; ++jr) potrf_phase<0>(jr, kb, t, ti, tl, a_r, x_r, colb, rowb, pinv, &fail);
+  for (int jr = 0; jr < 16; ++jr) potrf_phase<1>(jr, kb, t, ti, tl, a_r, x_r, colb, rowb, pinv, &fail);
+  for (int jr = 0; jr < 16; ++jr) potrf_phase<2>(jr, kb, t, ti, tl, a_r, x_r, colb, rowb, pinv, &fail);
+  for (int jr = 0; jr < 16; ++jr) potrf_phase<3>(jr, kb, t, ti, tl, a_r, x_r, colb, rowb, pinv, &fail);
+  for (int jr = 0; jr < 2; ++jr) potrf_phase<4>(jr, kb, t, ti, tl, a_r, x_r, colb, rowb, pinv, &fail);
   __syncthreads();
   T* Dblk = B.D + S.Doff[s] + (int64_t)step * kNB * kNB;
 #pragma unroll
