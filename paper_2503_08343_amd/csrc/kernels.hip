@@ -72,67 +72,99 @@ __device__ __forceinline__ int64_t wg_id() { return (int64_t)blockIdx.x; }
 //  B_KC=true:  Bop[k][n] = B[k + n*ldb];  B_KC=false: Bop[k][n] = B[n + k*ldb]
 // Wave w owns the 32x32 sub-tile at rows 32*(w&1), cols 32*(w>>1): 2x2 MFMA 16x16 blocks.
 // acc[i][j][r] holds C[32*(w&1) + 16 i + acc_row<T>(lane, r)][32*(w>>1) + 16 j + (lane&15)].
+// sA, sB hold two K chunks each (kTile64Lds elements): the next chunk is loaded into
+// registers while the current one is multiplied.  Ends with a barrier, so the buffers
+// can be reused by the caller.
+constexpr int kTile64Lds = 2 * kTK * kP;
+
+template <typename T, bool A_KC, bool B_KC>
+__device__ __forceinline__ void tile64_load(const T* __restrict__ A, int64_t lda, const T* __restrict__ B,
+                                            int64_t ldb, int M, int N, int K, int k0, T (&ra)[4], T (&rb)[4]) {
+  const int t = threadIdx.x;
+  if (!A_KC) {
+    const int m = t & 63;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int k = (t >> 6) + 4 * i;
+      ra[i] = (m < M && k0 + k < K) ? A[m + (int64_t)(k0 + k) * lda] : T(0);
+    }
+  } else {
+    const int k = t & 15;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int m = (t >> 4) + 16 * i;
+      ra[i] = (m < M && k0 + k < K) ? A[(k0 + k) + (int64_t)m * lda] : T(0);
+    }
+  }
+  if (!B_KC) {
+    const int nn = t & 63;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int k = (t >> 6) + 4 * i;
+      rb[i] = (nn < N && k0 + k < K) ? B[nn + (int64_t)(k0 + k) * ldb] : T(0);
+    }
+  } else {
+    const int k = t & 15;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int nn = (t >> 4) + 16 * i;
+      rb[i] = (nn < N && k0 + k < K) ? B[(k0 + k) + (int64_t)nn * ldb] : T(0);
+    }
+  }
+}
+
+template <typename T, bool A_KC, bool B_KC>
+__device__ __forceinline__ void tile64_store(T* sA, T* sB, const T (&ra)[4], const T (&rb)[4]) {
+  const int t = threadIdx.x;
+  if (!A_KC) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) sA[((t >> 6) + 4 * i) * kP + (t & 63)] = ra[i];
+  } else {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) sA[(t & 15) * kP + (t >> 4) + 16 * i] = ra[i];
+  }
+  if (!B_KC) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) sB[((t >> 6) + 4 * i) * kP + (t & 63)] = rb[i];
+  } else {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) sB[(t & 15) * kP + (t >> 4) + 16 * i] = rb[i];
+  }
+}
+
 template <typename T, bool A_KC, bool B_KC>
 __device__ __forceinline__ void gemm_tile(const T* __restrict__ A, int64_t lda,
                                           const T* __restrict__ B, int64_t ldb, int M, int N,
                                           int K, typename V4<T>::type (&acc)[2][2], T* sA, T* sB) {
-  const int t = threadIdx.x;
-  const int lane = t & 63;
-  const int w = t >> 6;
+  const int lane = threadIdx.x & 63;
+  const int w = threadIdx.x >> 6;
   const int wm = (w & 1) * 32, wn = (w >> 1) * 32;
+  if (K <= 0) return;
+  T ra[4], rb[4];
+  tile64_load<T, A_KC, B_KC>(A, lda, B, ldb, M, N, K, 0, ra, rb);
+  tile64_store<T, A_KC, B_KC>(sA, sB, ra, rb);
+  __syncthreads();
+  int buf = 0;
   for (int k0 = 0; k0 < K; k0 += kTK) {
-    if (!A_KC) {
-      const int m = t & 63;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int k = (t >> 6) + 4 * i;
-        T v = T(0);
-        if (m < M && k0 + k < K) v = A[m + (int64_t)(k0 + k) * lda];
-        sA[k * kP + m] = v;
-      }
-    } else {
-      const int k = t & 15;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int m = (t >> 4) + 16 * i;
-        T v = T(0);
-        if (m < M && k0 + k < K) v = A[(k0 + k) + (int64_t)m * lda];
-        sA[k * kP + m] = v;
-      }
-    }
-    if (!B_KC) {
-      const int nn = t & 63;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int k = (t >> 6) + 4 * i;
-        T v = T(0);
-        if (nn < N && k0 + k < K) v = B[nn + (int64_t)(k0 + k) * ldb];
-        sB[k * kP + nn] = v;
-      }
-    } else {
-      const int k = t & 15;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int nn = (t >> 4) + 16 * i;
-        T v = T(0);
-        if (nn < N && k0 + k < K) v = B[(k0 + k) + (int64_t)nn * ldb];
-        sB[k * kP + nn] = v;
-      }
-    }
-    __syncthreads();
+    const bool more = k0 + kTK < K;
+    if (more) tile64_load<T, A_KC, B_KC>(A, lda, B, ldb, M, N, K, k0 + kTK, ra, rb);
+    const T* cA = sA + buf * (kTK * kP);
+    const T* cB = sB + buf * (kTK * kP);
 #pragma unroll
     for (int kk = 0; kk < kTK; kk += 4) {
       T a[2], b[2];
 #pragma unroll
-      for (int i = 0; i < 2; ++i) a[i] = sA[(kk + (lane >> 4)) * kP + wm + 16 * i + (lane & 15)];
+      for (int i = 0; i < 2; ++i) a[i] = cA[(kk + (lane >> 4)) * kP + wm + 16 * i + (lane & 15)];
 #pragma unroll
-      for (int j = 0; j < 2; ++j) b[j] = sB[(kk + (lane >> 4)) * kP + wn + 16 * j + (lane & 15)];
+      for (int j = 0; j < 2; ++j) b[j] = cB[(kk + (lane >> 4)) * kP + wn + 16 * j + (lane & 15)];
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = mfma(a[i], b[j], acc[i][j]);
     }
+    if (more) tile64_store<T, A_KC, B_KC>(sA + (buf ^ 1) * (kTK * kP), sB + (buf ^ 1) * (kTK * kP), ra, rb);
     __syncthreads();
+    buf ^= 1;
   }
 }
 
@@ -712,8 +744,8 @@ __global__ __launch_bounds__(kThreads) void k_potrf(DevSym S, LaunchList L, int 
 // panel rows below the step-th diagonal block: F[r, blk] = F[r, blk] * Linv^T
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_trsm(DevSym S, LaunchList L, int step, NumBufs<T> B) {
-  __shared__ T sA[kTK * kP];
-  __shared__ T sB[kTK * kP];
+  __shared__ T sA[kTile64Lds];
+  __shared__ T sB[kTile64Lds];
   int fi; int64_t loc;
   find_front(L, wg_id(), fi, loc);
   const int s = L.fronts[fi];
@@ -775,8 +807,8 @@ __global__ __launch_bounds__(kThreads) void k_update(DevSym S, LaunchList L, int
   const int M = min(TS, n - row0), N = min(TS, chi - col0);
   T* F = B.Wcur + S.Woff[s];
   if constexpr (TS == 64) {
-    __shared__ T sA[kTK * kP];
-    __shared__ T sB[kTK * kP];
+    __shared__ T sA[kTile64Lds];
+    __shared__ T sB[kTile64Lds];
     typename V4<T>::type acc[2][2];
     zero_acc<T>(acc);
     gemm_tile<T, false, false>(F + row0 + (int64_t)klo * n, n, F + col0 + (int64_t)klo * n, n, M, N,
@@ -1541,8 +1573,8 @@ __global__ __launch_bounds__(kThreads) void k_inv256(DevSym S, LaunchList L, con
                                                      int from_front, const T* __restrict__ Dinv,
                                                      const int64_t* __restrict__ D2off, T* __restrict__ D2,
                                                      T* __restrict__ D2T) {
-  __shared__ T sA[kTK * kP];
-  __shared__ T sB[kTK * kP];
+  __shared__ T sA[kTile64Lds];
+  __shared__ T sB[kTile64Lds];
   int fi; int64_t loc;
   find_front(L, wg_id(), fi, loc);
   const int s = L.fronts[fi];
@@ -1753,8 +1785,8 @@ __global__ __launch_bounds__(kThreads) void k_sel_gemm_reduce(DevSym S, LaunchLi
 // 64x64 tile (ti, tj) over kChunk rows of R' into part + wg * 64^2
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_sel_part2(DevSym S, LaunchList L, int step, SelBufs<T> B) {
-  __shared__ T sA[kTK * kP];
-  __shared__ T sB[kTK * kP];
+  __shared__ T sA[kTile64Lds];
+  __shared__ T sB[kTile64Lds];
   int fi; int64_t loc;
   find_front(L, wg_id(), fi, loc);
   const int s = L.fronts[fi];
@@ -1783,8 +1815,8 @@ template <typename T>
 __global__ __launch_bounds__(kThreads) void k_sel_fin2(DevSym S, LaunchList L, LaunchList Lpart, int step,
                                                        SelBufs<T> B, const int64_t* __restrict__ D2off,
                                                        const T* __restrict__ D2) {
-  __shared__ T sA[kTK * kP];
-  __shared__ T sB[kTK * kP];
+  __shared__ T sA[kTile64Lds];
+  __shared__ T sB[kTile64Lds];
   int fi; int64_t loc;
   find_front(L, wg_id(), fi, loc);
   const int s = L.fronts[fi];
@@ -1802,11 +1834,22 @@ __global__ __launch_bounds__(kThreads) void k_sel_fin2(DevSym S, LaunchList L, L
   const int64_t q0 = Lpart.prefix[fi];
   const int nchunks = (int)((Lpart.prefix[fi + 1] - q0) / nt);
   T* Sf = B.Scur + S.Woff[s];
+  const T* pp = B.part + (q0 + ti * o.nsub + tj) * (int64_t)(kNB * kNB);
+  const int64_t pstride = (int64_t)nt * (kNB * kNB);
   for_acc<T>(acc, [&](int r, int c, T v) {
     if (r < M && c < N) {
+      // fixed-order sum of the chunk partials, eight independent loads in flight
+      const T* q = pp + r + c * kNB;
       T sp = T(0);
-      for (int ch = 0; ch < nchunks; ++ch)
-        sp += B.part[(q0 + (int64_t)ch * nt + ti * o.nsub + tj) * (kNB * kNB) + r + c * kNB];
+      int ch = 0;
+      for (; ch + 8 <= nchunks; ch += 8) {
+        T w[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) w[u] = q[(ch + u) * pstride];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) sp += w[u];
+      }
+      for (; ch < nchunks; ++ch) sp += q[ch * pstride];
       const T val = v - sp;
       if (ti == tj && r < c) return;   // the diagonal tile writes its lower half only
       const int gi = o.k2 + kNB * ti + r, gj = o.k2 + kNB * tj + c;
