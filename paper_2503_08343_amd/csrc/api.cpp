@@ -465,7 +465,7 @@ gmrf_status build_plan(gmrf_t h) {
       auto child = [&](int32_t s) { return Y.child_idx[Y.child_ptr[s] + c]; };
       auto has = [&](int32_t s) { return Y.child_ptr[s + 1] - Y.child_ptr[s] > c; };
       lv.ext.push_back(B.add(lv.fronts, [&](int32_t s) -> int64_t {
-        return has(s) ? nF(child(s)) - pF(child(s)) : 0;
+        return has(s) ? (nF(child(s)) - pF(child(s)) + kExtCols - 1) / kExtCols : 0;
       }, [&](int32_t s) {
         const double u = (double)(nF(child(s)) - pF(child(s)));
         return Cost{0.5 * u * (u + 1), 1.5 * u * (u + 1)};
@@ -661,7 +661,7 @@ gmrf_status build_plan(gmrf_t h) {
       return Cost{0.0, 2.0 * (p * n - 0.5 * p * (p - 1.0))};
     });
     lv.sgather = B.add(lv.fronts, [&](int32_t s) -> int64_t {
-      return Y.sparent[s] >= 0 ? nF(s) - pF(s) : 0;
+      return Y.sparent[s] >= 0 ? (nF(s) - pF(s) + kExtCols - 1) / kExtCols : 0;
     }, [&](int32_t s) { const double u = (double)(nF(s) - pF(s)); return Cost{0.0, 2.0 * u * u}; });
     lv.wsize_elems_scatter = (double)(lv.map_end - lv.map_begin);
   }

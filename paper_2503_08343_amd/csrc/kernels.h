@@ -9,6 +9,7 @@ constexpr int kTile = 64;     // dense tile edge (rows/cols) of the front kernel
 constexpr int kNB = 64;       // diagonal block width; equals the analysis option nb
 constexpr int kNB2 = 256;     // outer block width of the two-level blocking
 constexpr int kBigTile = 128; // tile edge of the long-K MFMA kernels
+constexpr int kExtCols = 4;   // columns per work-group of the extend-add and the Sigma gather
 
 // Read-only symbolic arrays on the device (pivot numbering).
 struct DevSym {

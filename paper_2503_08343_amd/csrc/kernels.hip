@@ -26,6 +26,7 @@ constexpr int kP = 80;        // LDS row pitch of the MFMA operand tiles (bank s
 constexpr int kTK = 16;       // K chunk of the MFMA tile loop
 constexpr int kChunk = 512;   // rows per split-K partial in the Sigma diagonal blocks
 constexpr int kSub = kNB2 / kNB;
+constexpr int kExtUnroll = 4;  // relative-index batches in flight per thread
 
 template <typename T> struct V4;
 template <> struct V4<double> { typedef double type __attribute__((ext_vector_type(4))); };
@@ -587,17 +588,39 @@ __global__ void k_scatter(int64_t cnt, const int64_t* __restrict__ map_e, const 
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_extend_add(DevSym S, LaunchList L, int slot,
                                                          const T* __restrict__ Wc, T* __restrict__ Wp) {
+  // work-group: kExtCols consecutive columns b of the child's update matrix; each thread
+  // loads a batch of relative row indices once and applies them to all of those columns
   int fi; int64_t loc;
   find_front(L, wg_id(), fi, loc);
   const int s = L.fronts[fi];
   const int c = S.child_idx[S.child_ptr[s] + slot];
   const int nc = fn(S, c), pc = fp(S, c), uc = nc - pc;
-  const int b = (int)loc;
+  const int b0 = (int)loc * kExtCols;
   const int32_t* rel = S.relpos + S.rowptr[c] + pc;
   const int ns = fn(S, s);
-  const T* src = Wc + S.Woff[c] + (int64_t)(pc + b) * nc + pc;
-  T* dst = Wp + S.Woff[s] + (int64_t)rel[b] * ns;
-  for (int a = b + threadIdx.x; a < uc; a += blockDim.x) dst[rel[a]] += src[a];
+  const T* src0 = Wc + S.Woff[c] + (int64_t)pc * nc + pc;
+  T* dstf = Wp + S.Woff[s];
+  int64_t dcol[kExtCols];
+#pragma unroll
+  for (int q = 0; q < kExtCols; ++q) dcol[q] = b0 + q < uc ? (int64_t)rel[b0 + q] * ns : 0;
+  for (int a0 = b0 + threadIdx.x; a0 < uc; a0 += kThreads * kExtUnroll) {
+    int ra[kExtUnroll];
+#pragma unroll
+    for (int v = 0; v < kExtUnroll; ++v) {
+      const int a = a0 + kThreads * v;
+      ra[v] = a < uc ? rel[a] : 0;
+    }
+#pragma unroll
+    for (int q = 0; q < kExtCols; ++q) {
+      const int b = b0 + q;
+      const T* src = src0 + (int64_t)b * nc;
+#pragma unroll
+      for (int v = 0; v < kExtUnroll; ++v) {
+        const int a = a0 + kThreads * v;
+        if (b < uc && a >= b && a < uc) dstf[dcol[q] + ra[v]] += src[a];
+      }
+    }
+  }
 }
 
 // 1/sqrt(d) for d > 0 (normal range): the hardware estimate refined by two Newton steps
@@ -1531,17 +1554,39 @@ __global__ __launch_bounds__(kThreads) void k_dot_final(const double* __restrict
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_sel_gather(DevSym S, LaunchList L, const int32_t* __restrict__ sparent,
                                                           SelBufs<T> B) {
+  // work-group: kExtCols consecutive columns of the child's Sigma_RR block, gathered from
+  // the parent's square Sigma front through the relative indices (loaded once per batch)
   int fi; int64_t loc;
   find_front(L, wg_id(), fi, loc);
   const int s = L.fronts[fi];
   const int n = fn(S, s), p = fp(S, s), u = n - p;
   const int par = sparent[s];
   const int np = fn(S, par);
-  const int b = (int)loc;
+  const int b0 = (int)loc * kExtCols;
   const int32_t* rel = S.relpos + S.rowptr[s] + p;
-  T* dst = B.Scur + S.Woff[s] + (int64_t)(p + b) * n + p;
-  const T* src = B.Spar + S.Woff[par] + (int64_t)rel[b] * np;
-  for (int a = threadIdx.x; a < u; a += blockDim.x) dst[a] = src[rel[a]];
+  T* dst0 = B.Scur + S.Woff[s] + (int64_t)p * n + p;
+  const T* srcf = B.Spar + S.Woff[par];
+  int64_t scol[kExtCols];
+#pragma unroll
+  for (int q = 0; q < kExtCols; ++q) scol[q] = b0 + q < u ? (int64_t)rel[b0 + q] * np : 0;
+  for (int a0 = threadIdx.x; a0 < u; a0 += kThreads * kExtUnroll) {
+    int ra[kExtUnroll];
+#pragma unroll
+    for (int v = 0; v < kExtUnroll; ++v) {
+      const int a = a0 + kThreads * v;
+      ra[v] = a < u ? rel[a] : 0;
+    }
+#pragma unroll
+    for (int q = 0; q < kExtCols; ++q) {
+      const int b = b0 + q;
+      T* dst = dst0 + (int64_t)b * n;
+#pragma unroll
+      for (int v = 0; v < kExtUnroll; ++v) {
+        const int a = a0 + kThreads * v;
+        if (b < u && a < u) dst[a] = srcf[scol[q] + ra[v]];
+      }
+    }
+  }
 }
 
 // ---- two-level selected inversion: 256-wide outer blocks K (counted from the right) ----
