@@ -169,6 +169,11 @@ __device__ __forceinline__ void gemm_tile(const T* __restrict__ A, int64_t lda,
   }
 }
 
+// Loads whose predicate differs per element compile to one branch and one wait per load;
+// the kernels below therefore load from clamped (always valid, finite) addresses and mask
+// the value afterwards (by a product where the compiler would otherwise sink the load
+// into a branch) or predicate only the stores, so that a batch of loads is in flight.
+
 template <typename T>
 __device__ __forceinline__ void zero_acc(typename V4<T>::type (&acc)[2][2]) {
 #pragma unroll
@@ -209,6 +214,37 @@ __device__ __forceinline__ void for_acc128(typename V4<T>::type (&acc)[4][4], F 
 #pragma unroll
       for (int r = 0; r < 4; ++r)
         f(wm + 16 * i + acc_row<T>(lane, r), wn + 16 * j + (lane & 15), acc[i][j][r]);
+}
+
+// F[gi + gj ld] -= C for the elements of a 64 x 64 (NT = 2) or 128 x 128 (NT = 4) tile
+// with r < M, c < N and gi >= gj, gi = row0 + r, gj = col0 + c: all old values are
+// loaded first from clamped addresses (M, N >= 1), then the valid ones are stored.
+template <typename T, int NT>
+__device__ __forceinline__ void acc_sub_lower(const typename V4<T>::type (&acc)[NT][NT], T* F, int64_t ld, int row0,
+                                              int col0, int M, int N) {
+  constexpr int WS = NT * 16;    // wave sub-tile edge
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wm = (w & 1) * WS, wn = (w >> 1) * WS;
+  T old[NT][NT][4];
+#pragma unroll
+  for (int i = 0; i < NT; ++i)
+#pragma unroll
+    for (int j = 0; j < NT; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int rr = min(wm + 16 * i + acc_row<T>(lane, r), M - 1), cc = min(wn + 16 * j + (lane & 15), N - 1);
+        old[i][j][r] = F[(row0 + rr) + (int64_t)(col0 + cc) * ld];
+      }
+#pragma unroll
+  for (int i = 0; i < NT; ++i)
+#pragma unroll
+    for (int j = 0; j < NT; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int rr = wm + 16 * i + acc_row<T>(lane, r), cc = wn + 16 * j + (lane & 15);
+        const int gi = row0 + rr, gj = col0 + cc;
+        if (rr < M && cc < N && gi >= gj) F[gi + (int64_t)gj * ld] = old[i][j][r] - acc[i][j][r];
+      }
 }
 
 
@@ -484,6 +520,46 @@ __device__ __forceinline__ void g2_epilogue(const f4_t (&acc)[8][4], G2Smem& sm,
   __syncthreads();
 }
 
+// F[gi + gj ld] -= C for a 256 x 128 tile (gi = row0 + r, gj = col0 + c, r < M, c < N,
+// gi >= gj), staged through LDS one 64-column half at a time; each thread loads its 64
+// old values of a half in eight batches of 8 from clamped addresses before storing.
+__device__ __forceinline__ void g2_epilogue_sub(const f4_t (&acc)[8][4], G2Smem& sm, float* F, int64_t ld,
+                                                int row0, int col0, int M, int N) {
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int wm = (w & 1) * 128;
+  const int r = lane & 15, g = lane >> 4;
+  for (int h = 0; h < 2; ++h) {
+    __syncthreads();
+    if ((w >> 1) == h) {
+#pragma unroll
+      for (int i = 0; i < 8; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) sm.ep[4 * r + j][wm + 8 * (4 * g + q) + i] = acc[i][j][q];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int e0 = 0; e0 < kG2M * 64; e0 += 8 * kThreads) {
+      float old[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = e0 + u * kThreads + t;
+        const int row = min(e & (kG2M - 1), M - 1), c = min(64 * h + (e >> 8), N - 1);
+        old[u] = F[(row0 + row) + (int64_t)(col0 + c) * ld];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = e0 + u * kThreads + t;
+        const int row = e & (kG2M - 1), cl = e >> 8, c = 64 * h + cl;
+        const int gi = row0 + row, gj = col0 + c;
+        if (row < M && c < N && gi >= gj) F[gi + (int64_t)gj * ld] = old[u] - sm.ep[cl][row];
+      }
+    }
+  }
+  __syncthreads();
+}
+
 // ------------------------------------------------------------------ assembly kernels
 __global__ void k_assemble_qpost(int64_t nnzq, const double* __restrict__ qval,
                                  const int64_t* __restrict__ cptr, const int32_t* __restrict__ cpair,
@@ -602,22 +678,28 @@ __global__ __launch_bounds__(kThreads) void k_extend_add(DevSym S, LaunchList L,
   T* dstf = Wp + S.Woff[s];
   int64_t dcol[kExtCols];
 #pragma unroll
-  for (int q = 0; q < kExtCols; ++q) dcol[q] = b0 + q < uc ? (int64_t)rel[b0 + q] * ns : 0;
+  for (int q = 0; q < kExtCols; ++q) dcol[q] = (int64_t)rel[min(b0 + q, uc - 1)] * ns;
   for (int a0 = b0 + threadIdx.x; a0 < uc; a0 += kThreads * kExtUnroll) {
     int ra[kExtUnroll];
 #pragma unroll
-    for (int v = 0; v < kExtUnroll; ++v) {
-      const int a = a0 + kThreads * v;
-      ra[v] = a < uc ? rel[a] : 0;
+    for (int v = 0; v < kExtUnroll; ++v) ra[v] = rel[min(a0 + kThreads * v, uc - 1)];
+    T sv[kExtCols][kExtUnroll], dv[kExtCols][kExtUnroll];
+#pragma unroll
+    for (int q = 0; q < kExtCols; ++q) {
+      const T* src = src0 + (int64_t)min(b0 + q, uc - 1) * nc;
+#pragma unroll
+      for (int v = 0; v < kExtUnroll; ++v) {
+        sv[q][v] = src[min(a0 + kThreads * v, uc - 1)];
+        dv[q][v] = dstf[dcol[q] + ra[v]];
+      }
     }
 #pragma unroll
     for (int q = 0; q < kExtCols; ++q) {
       const int b = b0 + q;
-      const T* src = src0 + (int64_t)b * nc;
 #pragma unroll
       for (int v = 0; v < kExtUnroll; ++v) {
         const int a = a0 + kThreads * v;
-        if (b < uc && a >= b && a < uc) dstf[dcol[q] + ra[v]] += src[a];
+        if (b < uc && a >= b && a < uc) dstf[dcol[q] + ra[v]] = dv[q][v] + sv[q][v];
       }
     }
   }
@@ -738,9 +820,8 @@ __global__ __launch_bounds__(kThreads) void k_potrf(DevSym S, LaunchList L, int 
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
       const int i = ti + 16 * a, l = tl + 16 * b;
-      double v = 0.0;
-      if (i < kb && l < kb && i >= l) v = (double)F[(k0 + i) + (int64_t)(k0 + l) * n];
-      a_r[a][b] = v;
+      const double v = (double)F[(k0 + min(i, kb - 1)) + (int64_t)(k0 + min(l, kb - 1)) * n];
+      a_r[a][b] = (i < kb && l < kb && i >= l) ? v : 0.0;
       x_r[a][b] = i == l ? 1.0 : 0.0;
     }
   if (t == 0) fail = INT_MAX;
@@ -836,10 +917,7 @@ __global__ __launch_bounds__(kThreads) void k_update(DevSym S, LaunchList L, int
     zero_acc<T>(acc);
     gemm_tile<T, false, false>(F + row0 + (int64_t)klo * n, n, F + col0 + (int64_t)klo * n, n, M, N,
                                khi - klo, acc, sA, sB);
-    for_acc<T>(acc, [&](int rr, int cc, T v) {
-      const int gi = row0 + rr, gj = col0 + cc;
-      if (rr < M && cc < N && gi >= gj) F[gi + (int64_t)gj * n] -= v;
-    });
+    acc_sub_lower<T, 2>(acc, F, n, row0, col0, M, N);
   } else {
     __shared__ __attribute__((aligned(16))) T sA[BigLds<T>::v];
     __shared__ __attribute__((aligned(16))) T sB[BigLds<T>::v];
@@ -847,10 +925,7 @@ __global__ __launch_bounds__(kThreads) void k_update(DevSym S, LaunchList L, int
     zero_acc128<T>(acc);
     gemm_tile128<T, false, false>(F + row0 + (int64_t)klo * n, n, F + col0 + (int64_t)klo * n, n, M, N,
                                   khi - klo, acc, sA, sB);
-    for_acc128<T>(acc, [&](int rr, int cc, T v) {
-      const int gi = row0 + rr, gj = col0 + cc;
-      if (rr < M && cc < N && gi >= gj) F[gi + (int64_t)gj * n] -= v;
-    });
+    acc_sub_lower<T, 4>(acc, F, n, row0, col0, M, N);
   }
 }
 
@@ -879,10 +954,7 @@ __global__ __launch_bounds__(kThreads) void k_syrk2(DevSym S, LaunchList L, NumB
   f4_t acc[8][4];
   zero_acc2(acc);
   gemm_tile2<false, false>(F + row0, n, F + col0, n, M, N, p, acc, sm.g);
-  g2_epilogue<false>(acc, sm, [&](int rr, int cc, float v) {
-    const int gi = row0 + rr, gj = col0 + cc;
-    if (rr < M && cc < N && gi >= gj) F[gi + (int64_t)gj * n] -= v;
-  }, [](int, int, float) {});
+  g2_epilogue_sub(acc, sm, F, n, row0, col0, M, N);
 }
 
 // FP32 left-looking update of outer block K of the pivot panel: before its first 64-block
@@ -912,10 +984,7 @@ __global__ __launch_bounds__(kThreads) void k_panel_upd3(DevSym S, LaunchList L,
   zero_acc2(acc);
   gemm_tile2<false, false>(F + row0 + (int64_t)kb * n, n, F + col0 + (int64_t)kb * n, n, M, N, ke - kb, acc, sm.g);
   if (split == 1) {
-    g2_epilogue<false>(acc, sm, [&](int r, int c, float v) {
-      const int gi = row0 + r, gj = col0 + c;
-      if (r < M && c < N && gi >= gj) F[gi + (int64_t)gj * n] -= v;
-    }, [](int, int, float) {});
+    g2_epilogue_sub(acc, sm, F, n, row0, col0, M, N);
   } else {
     float* out = part + wg_id() * (int64_t)(kG2M * kG2N);
     g2_epilogue<false>(acc, sm, [&](int r, int c, float v) { out[r + c * kG2M] = v; }, [](int, int, float) {});
@@ -1066,17 +1135,36 @@ __global__ __launch_bounds__(kThreads) void k_fwd_block(DevSym S, LaunchList L, 
   const int lend = 64 * g + 64;
   const double* v = V.Vcur + S.Voff[s] * nr;
   const T* X = D2 + D2off[s] + (int64_t)t * kNB2 * kNB2;
+  const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
+  const int i = 64 * g + lane;
+  // NR = 1: the wave's 64 inverse entries are requested before the right-hand side is
+  // staged, so that both memory round trips overlap
+  T xr[NR == 1 ? 64 : 1];
+  if constexpr (NR == 1) {
+    // the stored inverse is zero above its diagonal, so only the block edges need masks
+    const bool act = q <= g && i < kb2;
+    const int ic = min(i, kb2 - 1);
+#pragma unroll
+    for (int u = 0; u < 64; ++u) {
+      const int l = 64 * q + u;
+      const T x = X[ic + (int64_t)min(l, kb2 - 1) * kb2];
+      xr[u] = x * (T)(act && l < kb2);   // a product, not a select: keeps the load unconditional
+    }
+  }
   for (int idx = threadIdx.x; idx < lend * nr; idx += kThreads) {
     const int l = idx % lend, r = idx / lend;
     xv[l + r * kNB2] = l < kb2 ? v[k2 + l + (int64_t)r * n] : 0.0;
   }
   __syncthreads();
-  const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
-  const int i = 64 * g + lane;
   double acc[NR];
 #pragma unroll
   for (int r = 0; r < NR; ++r) acc[r] = 0.0;
-  if (q <= g && i < kb2) {
+  if constexpr (NR == 1) {
+    if (q <= g) {
+#pragma unroll
+      for (int u = 0; u < 64; ++u) acc[0] += (double)xr[u] * xv[64 * q + u];
+    }
+  } else if (q <= g && i < kb2) {
     for (int l0 = 64 * q; l0 < 64 * q + 64; l0 += 16) {
       double xl[16];
 #pragma unroll
@@ -1115,19 +1203,33 @@ __global__ __launch_bounds__(kThreads) void k_fwd_outer(DevSym S, LaunchList L, 
   const int k2 = t * kNB2, kb2 = min(kNB2, p - k2);
   const int64_t f0 = S.sfirst[s];
   double* v = V.Vcur + S.Voff[s] * nr;
-  for (int idx = threadIdx.x; idx < kNB2 * nr; idx += kThreads) {
-    const int i = idx % kNB2, r = idx / kNB2;
-    xs[i + r * kNB2] = i < kb2 ? V.xp[f0 + k2 + i + (int64_t)r * S.n] : 0.0;
-  }
-  __syncthreads();
   const int i = threadIdx.x & 63, cg = threadIdx.x >> 6;
   const int row = k2 + kb2 + 64 * (int)loc + i;
+  const int c0 = cg * 64, c1 = min(kb2, c0 + 64);
+  const T* Lr = Lp + S.Loff[s] + row + (int64_t)k2 * n;
+  // NR = 1: all 64 column loads of the thread are in flight at once, requested before x_K
+  // is staged (rows past n and columns past kb2 read as zero)
+  T lv[NR == 1 ? 64 : 1];
+  if constexpr (NR == 1) {
+    const T* Lc = Lp + S.Loff[s] + min(row, n - 1) + (int64_t)k2 * n;
+#pragma unroll
+    for (int u = 0; u < 64; ++u) {
+      const T x = Lc[(int64_t)min(c0 + u, kb2 - 1) * n];
+      lv[u] = x * (T)(row < n && c0 + u < c1);
+    }
+  }
+  for (int idx = threadIdx.x; idx < kNB2 * nr; idx += kThreads) {
+    const int ii = idx % kNB2, r = idx / kNB2;
+    xs[ii + r * kNB2] = ii < kb2 ? V.xp[f0 + k2 + ii + (int64_t)r * S.n] : 0.0;
+  }
+  __syncthreads();
   double acc[NR];
 #pragma unroll
   for (int r = 0; r < NR; ++r) acc[r] = 0.0;
-  if (row < n) {
-    const T* Lr = Lp + S.Loff[s] + row + (int64_t)k2 * n;
-    const int c0 = cg * 64, c1 = min(kb2, c0 + 64);
+  if constexpr (NR == 1) {
+#pragma unroll
+    for (int u = 0; u < 64; ++u) acc[0] += (double)lv[u] * xs[c0 + u];
+  } else if (row < n) {
     for (int cb = c0; cb < c1; cb += 16) {
       double lv[16];
 #pragma unroll
@@ -1157,9 +1259,12 @@ __global__ __launch_bounds__(kThreads) void k_fwd_outer(DevSym S, LaunchList L, 
 template <typename T, int NR>
 __global__ __launch_bounds__(kThreads) void k_bwd_part(DevSym S, LaunchList L, int t, const T* __restrict__ Lp,
                                                        SolveBufs V, double* __restrict__ part) {
+  // The x values of the work-group's 256 rows are gathered once into LDS; the L chunks
+  // (32 rows x 256 columns) are software-pipelined: the next chunk's loads are issued
+  // before the current chunk is multiplied, so one memory round trip stays exposed.
   constexpr int NP = RhsPad<NR>::v;
   __shared__ T Ls[32][kNB2 + 1];
-  __shared__ double Xs[32 * NP];
+  __shared__ double Xs[256 * NP];
   int fi; int64_t loc;
   find_front(L, wg_id(), fi, loc);
   const int s = L.fronts[fi];
@@ -1172,34 +1277,40 @@ __global__ __launch_bounds__(kThreads) void k_bwd_part(DevSym S, LaunchList L, i
   const int32_t* rows = S.rows + S.rowptr[s];
   const T* Lf = Lp + S.Loff[s];
   const int c = threadIdx.x;
-  double acc[NR];
-#pragma unroll
-  for (int r = 0; r < NR; ++r) acc[r] = 0.0;
-  for (int i0 = r0; i0 < r1; i0 += 32) {
+  T tmp[32];
+  auto load_chunk = [&](int i0) {
     const int mi = min(32, r1 - i0);
-    T tmp[32];
 #pragma unroll
     for (int k = 0; k < 32; ++k) {
       const int idx = threadIdx.x + k * kThreads;
       const int ii = idx & 31, cc = idx >> 5;
-      tmp[k] = (ii < mi && cc < kb2) ? Lf[(i0 + ii) + (int64_t)(k2 + cc) * n] : T(0);
+      const T x = Lf[(i0 + min(ii, mi - 1)) + (int64_t)(k2 + min(cc, kb2 - 1)) * n];
+      tmp[k] = x * (T)(ii < mi && cc < kb2);
     }
-    for (int idx = threadIdx.x; idx < 32 * nr; idx += kThreads) {
-      const int ii = idx & 31, r = idx >> 5;
-      Xs[ii * NP + r] = ii < mi ? V.xp[rows[i0 + ii] + (int64_t)r * S.n] : 0.0;
-    }
+  };
+  if (r0 < r1) load_chunk(r0);
+  for (int idx = threadIdx.x; idx < 256 * nr; idx += kThreads) {
+    const int ii = idx & 255, r = idx >> 8;
+    Xs[ii * NP + r] = r0 + ii < r1 ? V.xp[rows[r0 + ii] + (int64_t)r * S.n] : 0.0;
+  }
+  double acc[NR];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) acc[r] = 0.0;
+  for (int i0 = r0; i0 < r1; i0 += 32) {
 #pragma unroll
     for (int k = 0; k < 32; ++k) {
       const int idx = threadIdx.x + k * kThreads;
       Ls[idx & 31][idx >> 5] = tmp[k];
     }
+    if (i0 + 32 < r1) load_chunk(i0 + 32);
     __syncthreads();
+    const double* xc = Xs + (i0 - r0) * NP;
 #pragma unroll 8
     for (int ii = 0; ii < 32; ++ii) {
       const double l = (double)Ls[ii][c];
 #pragma unroll
       for (int r = 0; r < NR; ++r)
-        if (r < nr) acc[r] += l * Xs[ii * NP + r];
+        if (r < nr) acc[r] += l * xc[ii * NP + r];
     }
     __syncthreads();
   }
@@ -1243,12 +1354,40 @@ __global__ __launch_bounds__(kThreads) void k_bwd_block(DevSym S, LaunchList L, 
   const int split = 4 / nch;                      // threads per l
   const int span = 64 * nch;
   const int li = threadIdx.x % span, pid = threadIdx.x / span;
+  const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
+  const int i = l0 + lane;
+  // NR = 1: the wave's 64 entries of the transposed inverse are requested first (they do
+  // not depend on r), and the partials are summed in batches of 32 loads in flight
+  T xt[NR == 1 ? 64 : 1];
+  if constexpr (NR == 1) {
+    // the stored transpose is zero below its diagonal, so only the block edges need masks
+    const bool act = q >= g && 64 * q < kb2 && i < kb2;
+    const int ic = min(i, kb2 - 1);
+#pragma unroll
+    for (int u = 0; u < 64; ++u) {
+      const int l = 64 * q + u;
+      const T x = XT[ic + (int64_t)min(l, kb2 - 1) * kb2];
+      xt[u] = x * (T)(act && l < kb2);
+    }
+  }
   {
     double acc[NR];
 #pragma unroll
     for (int r = 0; r < NR; ++r) acc[r] = 0.0;
     const int l = l0 + li;
-    if (pid < split && l < kb2) {
+    if (NR == 1 && pid < split && l < kb2) {
+      for (int64_t qb = q0 + pid; qb < q1; qb += (int64_t)split * 32) {
+        double w[32];
+#pragma unroll
+        for (int u = 0; u < 32; ++u) {
+          const int64_t qq = qb + (int64_t)u * split;
+          const double x = part[min(qq, q1 - 1) * (kNB2 * 16) + l];
+          w[u] = x * (double)(qq < q1);
+        }
+#pragma unroll
+        for (int u = 0; u < 32; ++u) acc[0] += w[u];
+      }
+    } else if (pid < split && l < kb2) {
 #pragma unroll 8
       for (int64_t q = q0 + pid; q < q1; q += split) {
         const double* pq = part + q * (kNB2 * 16) + l;
@@ -1269,12 +1408,15 @@ __global__ __launch_bounds__(kThreads) void k_bwd_block(DevSym S, LaunchList L, 
     }
     __syncthreads();
   }
-  const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
-  const int i = l0 + lane;
   double acc[NR];
 #pragma unroll
   for (int r = 0; r < NR; ++r) acc[r] = 0.0;
-  if (q >= g && 64 * q < kb2 && i < kb2) {
+  if constexpr (NR == 1) {
+    if (q >= g && 64 * q < kb2) {
+#pragma unroll
+      for (int u = 0; u < 64; ++u) acc[0] += (double)xt[u] * rv[64 * q + u];
+    }
+  } else if (q >= g && 64 * q < kb2 && i < kb2) {
     for (int lb = 64 * q; lb < 64 * q + 64; lb += 16) {
       double xl[16];
 #pragma unroll
@@ -1568,14 +1710,16 @@ __global__ __launch_bounds__(kThreads) void k_sel_gather(DevSym S, LaunchList L,
   const T* srcf = B.Spar + S.Woff[par];
   int64_t scol[kExtCols];
 #pragma unroll
-  for (int q = 0; q < kExtCols; ++q) scol[q] = b0 + q < u ? (int64_t)rel[b0 + q] * np : 0;
+  for (int q = 0; q < kExtCols; ++q) scol[q] = (int64_t)rel[min(b0 + q, u - 1)] * np;
   for (int a0 = threadIdx.x; a0 < u; a0 += kThreads * kExtUnroll) {
     int ra[kExtUnroll];
 #pragma unroll
-    for (int v = 0; v < kExtUnroll; ++v) {
-      const int a = a0 + kThreads * v;
-      ra[v] = a < u ? rel[a] : 0;
-    }
+    for (int v = 0; v < kExtUnroll; ++v) ra[v] = rel[min(a0 + kThreads * v, u - 1)];
+    T val[kExtCols][kExtUnroll];
+#pragma unroll
+    for (int q = 0; q < kExtCols; ++q)
+#pragma unroll
+      for (int v = 0; v < kExtUnroll; ++v) val[q][v] = srcf[scol[q] + ra[v]];
 #pragma unroll
     for (int q = 0; q < kExtCols; ++q) {
       const int b = b0 + q;
@@ -1583,7 +1727,7 @@ __global__ __launch_bounds__(kThreads) void k_sel_gather(DevSym S, LaunchList L,
 #pragma unroll
       for (int v = 0; v < kExtUnroll; ++v) {
         const int a = a0 + kThreads * v;
-        if (b < u && a < u) dst[a] = srcf[scol[q] + ra[v]];
+        if (b < u && a < u) dst[a] = val[q][v];
       }
     }
   }
