@@ -395,34 +395,47 @@ __device__ __forceinline__ void zero_acc2(f4_t (&acc)[8][4]) {
     for (int j = 0; j < 4; ++j) acc[i][j] = f4_t{0.f, 0.f, 0.f, 0.f};
 }
 
+// Unconditional loads from clamped addresses (M, N, K >= 1), masked by a product so that
+// no branch separates the batch of loads.
 template <bool A_KC, bool B_KC>
 __device__ __forceinline__ void g2_load(const float* __restrict__ A, int64_t lda, const float* __restrict__ B,
                                         int64_t ldb, int M, int N, int K, int k0, float (&ra)[16], float (&rb)[8]) {
   const int t = threadIdx.x;
   if (!A_KC) {
+    const float* Ar = A + min(t, M - 1);
+    const float mm = (float)(t < M);
 #pragma unroll
-    for (int q = 0; q < 16; ++q) ra[q] = (t < M && k0 + q < K) ? A[t + (int64_t)(k0 + q) * lda] : 0.f;
+    for (int q = 0; q < 16; ++q) {
+      const int k = k0 + q;
+      ra[q] = Ar[(int64_t)min(k, K - 1) * lda] * (mm * (float)(k < K));
+    }
   } else {
-    const int k = t & 15;
+    const int k = k0 + (t & 15);
+    const float* Ak = A + min(k, K - 1);
+    const float mk = (float)(k < K);
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
       const int m = (t >> 4) + 16 * q;
-      ra[q] = (m < M && k0 + k < K) ? A[(k0 + k) + (int64_t)m * lda] : 0.f;
+      ra[q] = Ak[(int64_t)min(m, M - 1) * lda] * (mk * (float)(m < M));
     }
   }
   if (!B_KC) {
     const int nn = t & 127;
+    const float* Bn = B + min(nn, N - 1);
+    const float mn = (float)(nn < N);
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
-      const int k = (t >> 7) + 2 * q;
-      rb[q] = (nn < N && k0 + k < K) ? B[nn + (int64_t)(k0 + k) * ldb] : 0.f;
+      const int k = k0 + (t >> 7) + 2 * q;
+      rb[q] = Bn[(int64_t)min(k, K - 1) * ldb] * (mn * (float)(k < K));
     }
   } else {
-    const int k = t & 15;
+    const int k = k0 + (t & 15);
+    const float* Bk = B + min(k, K - 1);
+    const float mk = (float)(k < K);
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
       const int nn = (t >> 4) + 16 * q;
-      rb[q] = (nn < N && k0 + k < K) ? B[(k0 + k) + (int64_t)nn * ldb] : 0.f;
+      rb[q] = Bk[(int64_t)min(nn, N - 1) * ldb] * (mk * (float)(nn < N));
     }
   }
 }
@@ -931,7 +944,7 @@ __global__ __launch_bounds__(kThreads) void k_update(DevSym S, LaunchList L, int
 
 // FP32 trailing SYRK (the update matrix: columns [p, n), K = all p pivot columns) in
 // 256 x 128 tiles: 128-wide column tiles, rows from the tile's first column down.
-__global__ __launch_bounds__(kThreads) void k_syrk2(DevSym S, LaunchList L, NumBufs<float> B) {
+__global__ __launch_bounds__(kThreads, 2) void k_syrk2(DevSym S, LaunchList L, NumBufs<float> B) {
   __shared__ G2Smem sm;
   int fi; int64_t loc;
   find_front(L, wg_id(), fi, loc);
@@ -963,7 +976,7 @@ __global__ __launch_bounds__(kThreads) void k_syrk2(DevSym S, LaunchList L, NumB
 // (256 x 128 tiles; split over K like the Sigma[R', K] products when a depth has too few
 // tiles).  With split 1 the tile is subtracted in place (lower part only), else its
 // partial goes to part + wg * 256 * 128 and k_panel_red3 subtracts the sum.
-__global__ __launch_bounds__(kThreads) void k_panel_upd3(DevSym S, LaunchList L, int K, NumBufs<float> B,
+__global__ __launch_bounds__(kThreads, 2) void k_panel_upd3(DevSym S, LaunchList L, int K, NumBufs<float> B,
                                                          float* __restrict__ part) {
   __shared__ G2Smem sm;
   int fi; int64_t loc;
@@ -1888,7 +1901,7 @@ __global__ __launch_bounds__(kThreads) void k_sel_gemm2(DevSym S, LaunchList L, 
 
 // FP32 Sigma[R', K] = -Sigma[R', R'] Y in 256 x 128 tiles, split over K like k_sel_gemm2
 // (partials are 256 x 128, column-major).
-__global__ __launch_bounds__(kThreads) void k_sel_gemm3(DevSym S, LaunchList L, int step, SelBufs<float> B) {
+__global__ __launch_bounds__(kThreads, 2) void k_sel_gemm3(DevSym S, LaunchList L, int step, SelBufs<float> B) {
   __shared__ G2Smem sm;
   int fi; int64_t loc;
   find_front(L, wg_id(), fi, loc);
