@@ -265,6 +265,37 @@ struct Cost { double flops, elems; };
 constexpr int64_t kSplitMinK = 512;
 constexpr int64_t kSlots128 = 256;   // 128 x 128 tiles (FP64): one resident work-group per CU
 constexpr int64_t kSlots256 = 512;   // FP32 256 x 128 tiles: two per CU
+// Fronts of one launch have different K (their |R'|): pick one part length P and split
+// every front's K into ceil(K / P) parts, so that all parts carry about the same work.
+// P minimises rounds * (P + overhead of a partial tile) over P = Kmax / S, S = 1..64, with
+// parts of at least kSplitMinK rows; the overhead of writing and summing a partial tile is
+// counted as kPartCost rows of K.
+constexpr int64_t kPartCost = 512;
+int64_t choose_part(const std::vector<std::pair<int64_t, int64_t>>& tk, int64_t slots) {
+  int64_t kmax = 1;
+  for (const auto& x : tk) kmax = std::max(kmax, x.second);
+  int64_t best = kmax;
+  double best_t = 1e300;
+  for (int64_t S = 1; S <= 64; ++S) {
+    int64_t P = (kmax + S - 1) / S;
+    P = std::max<int64_t>(std::min<int64_t>(kSplitMinK, kmax), (P + 15) / 16 * 16);
+    int64_t wgs = 0;
+    bool split = false;
+    for (const auto& x : tk) {
+      const int64_t parts = std::max<int64_t>(1, (x.second + P - 1) / P);
+      split = split || parts > 1;
+      wgs += x.first * parts;
+    }
+    const double t = (double)((wgs + slots - 1) / slots) * (double)(P + (split ? kPartCost : 0));
+    if (t < best_t * 0.999) {
+      best_t = t;
+      best = P;
+    }
+    if (P <= kSplitMinK) break;
+  }
+  return best;
+}
+
 int64_t choose_split(int64_t T, int64_t slots, int64_t smax) {
   if (T <= 0 || T >= 8 * slots) return 1;
   const double ideal = (double)T / (double)slots;
@@ -590,12 +621,13 @@ gmrf_status build_plan(gmrf_t h) {
         };
         int64_t gtot3 = 0;
         for (int32_t s : lv.fronts) gtot3 += gtiles3(s);
-        int64_t gmaxk3 = 0;
-        for (int32_t s : lv.fronts) if (gtiles3(s) > 0) gmaxk3 = std::max<int64_t>(gmaxk3, otail(s) / kSplitMinK);
-        const int64_t gS3 = choose_split(gtot3, kSlots256, gmaxk3);
+        std::vector<std::pair<int64_t, int64_t>> tk3;
+        for (int32_t s : lv.fronts)
+          if (gtiles3(s) > 0) tk3.emplace_back(gtiles3(s), otail(s));
+        const int64_t gP3 = choose_part(tk3, kSlots256);
         auto gsplit3 = [&](int32_t s) -> int64_t {
           if (gtiles3(s) == 0) return 1;
-          return std::max<int64_t>(1, std::min<int64_t>(gS3, otail(s) / kSplitMinK));
+          return std::max<int64_t>(1, (otail(s) + gP3 - 1) / gP3);
         };
         lv.sgemm3.push_back(B.add(lv.fronts, [&](int32_t s) -> int64_t { return gtiles3(s) * gsplit3(s); },
                                   [&](int32_t s) {
