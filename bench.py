@@ -59,11 +59,14 @@ def run_mode(binding, ctx, dev, prob, precision, steps, warmup, z_kn, profile):
     def step():
         ctx.update_values(q_data=dev["q_data"], a_data=dev["a_data"], q_eps=dev["q_eps"], y=dev["y"])
         ctx.factor(precision)
+        # the selected inversion runs on the library's second stream, overlapped with
+        # the log-determinant, the refined mean and the samples of the same factor
+        var = ctx.selinv_submit()
         ld = ctx.logdet()
         mu, it, res = ctx.solve(max_refine=30 if precision == binding.GMRF_FP32_REFINE else 0, tol=tol,
                                 raise_not_converged=False)
         x = ctx.sample(z_kn)
-        var = ctx.selinv()
+        ctx.selinv_wait()
         return ld, mu, it, res, x, var
     for _ in range(warmup):
         step()

@@ -187,6 +187,18 @@ gmrf_status gmrf_sample(gmrf_t h, int64_t k, const float* z, double* x_out);
    entries of Q_post^-1 at every stored entry of Q, in Q's CSR order.  The factor is kept. */
 gmrf_status gmrf_selinv(gmrf_t h, double* var_out, double* sigma_q_out);
 
+/* The same selected inversion started asynchronously: it is queued after the work
+   already on the context's stream, runs on a second stream owned by the context, and
+   the call returns at once, so that gmrf_solve, gmrf_sample and gmrf_logdet of the same
+   factor overlap with it.  var_out and sigma_q_out must stay allocated and unread until
+   gmrf_selinv_wait returns.  Every call that writes or reallocates what the inversion
+   reads (gmrf_assemble, gmrf_update_values, gmrf_analyze, gmrf_factor, gmrf_gn_burgers,
+   another gmrf_selinv*) and gmrf_destroy first wait for it. */
+gmrf_status gmrf_selinv_submit(gmrf_t h, double* var_out, double* sigma_q_out);
+
+/* Host wait for the inversion started by gmrf_selinv_submit (no-op if none). */
+gmrf_status gmrf_selinv_wait(gmrf_t h);
+
 /* Deterministic sum_e a[e] * b[e] over len entries (device inputs, host output); used
    for traces tr(Q_post^-1 dQ) = sum over Q's pattern of Sigma_e dQ_e. */
 gmrf_status gmrf_dot(gmrf_t h, int64_t len, const double* a, const double* b, double* out);

@@ -26,7 +26,8 @@ GMRF_FP64 = 0
 GMRF_FP32_REFINE = 1
 
 EXPORTS = ["gmrf_create", "gmrf_destroy", "gmrf_assemble", "gmrf_update_values", "gmrf_analyze",
-           "gmrf_factor", "gmrf_logdet", "gmrf_solve", "gmrf_sample", "gmrf_selinv", "gmrf_dot",
+           "gmrf_factor", "gmrf_logdet", "gmrf_solve", "gmrf_sample", "gmrf_selinv", "gmrf_selinv_submit",
+           "gmrf_selinv_wait", "gmrf_dot",
            "gmrf_stats", "gmrf_pivot_order", "gmrf_phase_ms", "gmrf_last_error",
            "gmrf_symbolic_host", "gmrf_profile", "gmrf_kernel_stats", "gmrf_matern_values",
            "gmrf_spmv", "gmrf_misfit", "gmrf_solve_rhs", "gmrf_gn_burgers"]
@@ -101,6 +102,8 @@ def load():
         "gmrf_solve": ([P, P, ctypes.c_int, d, P, P], i32),
         "gmrf_sample": ([P, i64, P, P], i32),
         "gmrf_selinv": ([P, P, P], i32),
+        "gmrf_selinv_submit": ([P, P, P], i32),
+        "gmrf_selinv_wait": ([P], i32),
         "gmrf_dot": ([P, i64, P, P, P], i32),
         "gmrf_stats": ([P, P], i32),
         "gmrf_pivot_order": ([P, P], i32),
@@ -281,6 +284,23 @@ class Context:
             sq = T.empty(int(nnzq), dtype=T.float64, device=f"cuda:{self.device}")
         self._check(self.lib.gmrf_selinv(self.h, _t_ptr(var), _t_ptr(sq)))
         return var if sq is None else (var, sq)
+
+    def selinv_submit(self, with_pattern=False, nnzq=None):
+        """Start the selected inversion on the library's second stream; the returned
+        tensors are valid after selinv_wait().  Solves, samples and log-determinants of
+        the same factor may be called meanwhile."""
+        T = self.torch
+        var = T.empty(self.n, dtype=T.float64, device=f"cuda:{self.device}")
+        sq = None
+        if with_pattern:
+            sq = T.empty(int(nnzq), dtype=T.float64, device=f"cuda:{self.device}")
+        self._check(self.lib.gmrf_selinv_submit(self.h, _t_ptr(var), _t_ptr(sq)))
+        self._sel_pending = (var, sq)
+        return var if sq is None else (var, sq)
+
+    def selinv_wait(self):
+        self._check(self.lib.gmrf_selinv_wait(self.h))
+        self._sel_pending = None
 
     def dot(self, a, b):
         out = np.zeros(1)

@@ -136,6 +136,11 @@ struct gmrf_ctx {
   double refine_resid = 0.0;
   int64_t failed_index = -1;
   hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  // asynchronous selected inversion: its own stream (default priority, non-blocking),
+  // ordered after the factorisation and joined by every call that writes shared buffers
+  hipStream_t sel_stream = nullptr;
+  hipEvent_t ev_sel_start = nullptr, ev_sel_done = nullptr;
+  bool sel_inflight = false;
   double phase_ms[3] = {0, 0, 0};
   bool ev_factor = false, ev_solve = false, ev_sel = false;
   // per-launch profiler (events around every launch of a class while enabled)
@@ -199,6 +204,7 @@ void prof_launch(gmrf_t h, int cls, double flops, double elems, F launch) {
 void prof_fold(gmrf_t h) {
   if (h->marks.empty()) return;
   (void)hipStreamSynchronize(h->stream);
+  if (h->sel_stream) (void)hipStreamSynchronize(h->sel_stream);
   for (const auto& m : h->marks) {
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, h->evpool[m.e0], h->evpool[m.e1]) == hipSuccess) h->cls_ms[m.cls] += ms;
@@ -208,6 +214,14 @@ void prof_fold(gmrf_t h) {
   }
   h->marks.clear();
   h->evused = 0;
+}
+
+// host wait for an in-flight selected inversion: every call that writes or reallocates
+// buffers the inversion reads (factor, front buffers, launch lists) waits for it first
+hipError_t sel_sync(gmrf_t h) {
+  if (!h->sel_inflight) return hipSuccess;
+  h->sel_inflight = false;
+  return hipEventSynchronize(h->ev_sel_done);
 }
 
 template <typename T>
@@ -1068,8 +1082,12 @@ gmrf_status gmrf_create(gmrf_t* out, int device, void* hip_stream) {
 gmrf_status gmrf_destroy(gmrf_t h) {
   if (!h) return GMRF_OK;
   (void)hipSetDevice(h->device);
+  (void)sel_sync(h);
   if (h->stream) (void)hipStreamSynchronize(h->stream);
   else (void)hipDeviceSynchronize();
+  if (h->sel_stream) (void)hipStreamDestroy(h->sel_stream);
+  if (h->ev_sel_start) (void)hipEventDestroy(h->ev_sel_start);
+  if (h->ev_sel_done) (void)hipEventDestroy(h->ev_sel_done);
   for (auto& e : h->ev)
     if (e) (void)hipEventDestroy(e);
   for (auto& e : h->evpool)
@@ -1090,6 +1108,7 @@ gmrf_status gmrf_assemble(gmrf_t h, int64_t n, const int64_t* q_rowptr, const in
                           const double* a_val, const double* q_eps, const double* y, const double* b,
                           const double* mu_prior, int64_t n_blocks, const int64_t* block_ptr) {
   if (!h) return GMRF_ERR_ARG;
+  HIPCHK(h, sel_sync(h));
   if (hipSetDevice(h->device) != hipSuccess) return fail(h, GMRF_ERR_HIP, "hipSetDevice failed");
   hipStream_t st = h->stream;
   if (n <= 0 || m < 0 || !q_rowptr || !q_col || !q_val) return fail(h, GMRF_ERR_ARG, "bad sizes or null Q");
@@ -1220,6 +1239,7 @@ gmrf_status gmrf_assemble(gmrf_t h, int64_t n, const int64_t* q_rowptr, const in
 gmrf_status gmrf_update_values(gmrf_t h, const double* q_val, const double* a_val, const double* q_eps,
                                const double* y, const double* b) {
   if (!h) return GMRF_ERR_ARG;
+  HIPCHK(h, sel_sync(h));
   if (!(h->state & ST_ASSEMBLED)) return fail(h, GMRF_ERR_STATE, "gmrf_update_values before gmrf_assemble");
   hipStream_t st = h->stream;
   if (q_val) HIPCHK(h, copy_d2d(h->d_qval.p, q_val, h->nnzq * sizeof(double), st));
@@ -1246,6 +1266,7 @@ static void fill_opts(const gmrf_options* o, AnalyzeOptions& opt) {
 
 gmrf_status gmrf_analyze(gmrf_t h, const double* coords, int dim, const gmrf_options* opts) {
   if (!h) return GMRF_ERR_ARG;
+  HIPCHK(h, sel_sync(h));
   if (!(h->state & ST_ASSEMBLED)) return fail(h, GMRF_ERR_STATE, "gmrf_analyze before gmrf_assemble");
   if (coords && (dim < 1 || dim > 3)) return fail(h, GMRF_ERR_ARG, "dim must be 1..3");
   if (hipSetDevice(h->device) != hipSuccess) return fail(h, GMRF_ERR_HIP, "hipSetDevice failed");
@@ -1262,6 +1283,7 @@ gmrf_status gmrf_analyze(gmrf_t h, const double* coords, int dim, const gmrf_opt
 
 gmrf_status gmrf_factor(gmrf_t h, gmrf_precision p) {
   if (!h) return GMRF_ERR_ARG;
+  HIPCHK(h, sel_sync(h));
   if (!(h->state & ST_ANALYZED)) return fail(h, GMRF_ERR_STATE, "gmrf_factor before gmrf_analyze");
   if (p != GMRF_FP64 && p != GMRF_FP32_REFINE) return fail(h, GMRF_ERR_ARG, "unknown precision");
   if (hipSetDevice(h->device) != hipSuccess) return fail(h, GMRF_ERR_HIP, "hipSetDevice failed");
@@ -1368,6 +1390,7 @@ gmrf_status gmrf_gn_burgers(gmrf_t h, int64_t nx, int64_t nt, double dt, double 
                             const double* stiff3, int iters, int precision, int refine, int use_graph,
                             double* u, double* rec_out) {
   if (!h || !mass || !stiff3 || !u || iters < 1 || refine < 0) return fail(h, GMRF_ERR_ARG, "bad argument");
+  HIPCHK(h, sel_sync(h));
   if (precision != GMRF_FP64 && precision != GMRF_FP32_REFINE) return fail(h, GMRF_ERR_ARG, "unknown precision");
   if (!(h->state & ST_ANALYZED)) return fail(h, GMRF_ERR_STATE, "gmrf_gn_burgers before gmrf_analyze");
   if (nx < 2 || nt < 2 || h->n != nx * nt || h->m != nx * nt || !(dt > 0.0))
@@ -1475,19 +1498,46 @@ gmrf_status gmrf_sample(gmrf_t h, int64_t k, const float* z, double* x_out) {
   return GMRF_OK;
 }
 
-gmrf_status gmrf_selinv(gmrf_t h, double* var_out, double* sigma_q_out) {
+gmrf_status gmrf_selinv_submit(gmrf_t h, double* var_out, double* sigma_q_out) {
   if (!h || !var_out) return fail(h, GMRF_ERR_ARG, "null argument");
   if (!(h->state & ST_FACTORED)) return fail(h, GMRF_ERR_STATE, "gmrf_selinv before gmrf_factor");
+  HIPCHK(h, sel_sync(h));
   gmrf_status rc = check_status(h);
   if (rc != GMRF_OK) return rc;
+  if (!h->sel_stream) {
+    HIPCHK(h, hipStreamCreateWithFlags(&h->sel_stream, hipStreamNonBlocking));
+    HIPCHK(h, hipEventCreateWithFlags(&h->ev_sel_start, hipEventDisableTiming));
+    HIPCHK(h, hipEventCreateWithFlags(&h->ev_sel_done, hipEventDisableTiming));
+  }
+  // the inversion reads the factor and reuses the front buffers: order it after
+  // everything already queued on the context's stream
+  HIPCHK(h, hipEventRecord(h->ev_sel_start, h->stream));
+  HIPCHK(h, hipStreamWaitEvent(h->sel_stream, h->ev_sel_start, 0));
+  hipStream_t user = h->stream;
+  h->stream = h->sel_stream;
+  struct Restore { gmrf_t h; hipStream_t s; ~Restore() { h->stream = s; } } restore{h, user};
   HIPCHK(h, hipEventRecord(h->ev[4], h->stream));
   rc = h->prec == GMRF_FP32_REFINE ? run_selinv<float>(h, var_out, sigma_q_out)
                                    : run_selinv<double>(h, var_out, sigma_q_out);
   if (rc != GMRF_OK) return rc;
   HIPCHK(h, hipEventRecord(h->ev[5], h->stream));
+  HIPCHK(h, hipEventRecord(h->ev_sel_done, h->stream));
   h->ev_sel = true;
-  HIPCHK(h, hipStreamSynchronize(h->stream));
+  h->sel_inflight = true;
   return GMRF_OK;
+}
+
+gmrf_status gmrf_selinv_wait(gmrf_t h) {
+  if (!h) return GMRF_ERR_ARG;
+  HIPCHK(h, sel_sync(h));
+  HIPCHK(h, hipGetLastError());
+  return GMRF_OK;
+}
+
+gmrf_status gmrf_selinv(gmrf_t h, double* var_out, double* sigma_q_out) {
+  gmrf_status rc = gmrf_selinv_submit(h, var_out, sigma_q_out);
+  if (rc != GMRF_OK) return rc;
+  return gmrf_selinv_wait(h);
 }
 
 gmrf_status gmrf_dot(gmrf_t h, int64_t len, const double* a, const double* b, double* out) {
@@ -1604,6 +1654,7 @@ gmrf_status gmrf_kernel_stats(gmrf_t h, gmrf_kernel_stat_t* out, int capacity, i
 gmrf_status gmrf_phase_ms(gmrf_t h, double* out3) {
   if (!h || !out3) return fail(h, GMRF_ERR_ARG, "null argument");
   HIPCHK(h, hipStreamSynchronize(h->stream));
+  HIPCHK(h, sel_sync(h));
   out3[0] = h->ev_factor ? elapsed(h->ev[0], h->ev[1]) : 0.0;
   out3[1] = h->ev_solve ? elapsed(h->ev[2], h->ev[3]) : 0.0;
   out3[2] = h->ev_sel ? elapsed(h->ev[4], h->ev[5]) : 0.0;

@@ -164,3 +164,31 @@ def test_call_order_errors(gpu_lib):
     with pytest.raises(gpu_lib.GmrfError) as e:
         ctx.factor(0)
     assert e.value.code == gpu_lib.GMRF_ERR_STATE
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_async_selinv_overlapping_solves_matches_sequential(gpu_lib, precision):
+    """The selected inversion started on the second stream while the mean, a sample and
+    the log-determinant are computed on the context's stream gives bitwise the results of
+    the sequential calls (every reduction has a fixed order), also when repeated after a
+    refactorisation."""
+    import torch
+    p = gi.advdiff_spacetime(ns=24, nt=16, seed=61)
+    ctx = gpu_lib.posterior_context(p, precision=precision)
+    refine = 20 if precision == 1 else 0
+    z = torch.from_numpy(gi.rng_for(62).standard_normal((2, p.n)).astype(np.float32)).cuda()
+    var_s, sq_s = ctx.selinv(with_pattern=True, nnzq=p.Q.nnz)
+    mu_s = ctx.solve(max_refine=refine, tol=1e-12)[0].clone()
+    x_s = ctx.sample(z).clone()
+    ld_s = ctx.logdet()
+    for _ in range(2):
+        ctx.factor(precision)
+        var_a, sq_a = ctx.selinv_submit(with_pattern=True, nnzq=p.Q.nnz)
+        mu_a = ctx.solve(max_refine=refine, tol=1e-12)[0].clone()
+        x_a = ctx.sample(z).clone()
+        ld_a = ctx.logdet()
+        ctx.selinv_wait()
+        assert torch.equal(var_a, var_s) and torch.equal(sq_a, sq_s)
+        assert torch.equal(mu_a, mu_s) and torch.equal(x_a, x_s)
+        assert np.array_equal(ld_a, ld_s)
+    ctx.close()
