@@ -254,6 +254,22 @@ gmrf_status gmrf_profile(gmrf_t h, int enable);
    synchronises the stream. */
 gmrf_status gmrf_kernel_stats(gmrf_t h, gmrf_kernel_stat_t* out, int capacity, int* count);
 
+/* One profiled launch: its class (index of the gmrf_kernel_stats record), the
+   algorithmic flops and bytes it was charged, and its duration between the events
+   recorded around it (ms). */
+typedef struct {
+  int32_t cls;
+  int32_t reserved;
+  double flops;
+  double bytes;
+  double ms;
+} gmrf_launch_rec_t;
+
+/* Copy up to `capacity` records (host) of the launches profiled since the last
+   gmrf_profile call, in launch order, and their total number to *count (out may be NULL
+   to query the count); synchronises the streams. */
+gmrf_status gmrf_launch_records(gmrf_t h, gmrf_launch_rec_t* out, int64_t capacity, int64_t* count);
+
 /* Message of the last failing call on this context (never NULL). */
 const char* gmrf_last_error(gmrf_t h);
 

@@ -30,7 +30,7 @@ EXPORTS = ["gmrf_create", "gmrf_destroy", "gmrf_assemble", "gmrf_update_values",
            "gmrf_selinv_wait", "gmrf_dot",
            "gmrf_stats", "gmrf_pivot_order", "gmrf_phase_ms", "gmrf_last_error",
            "gmrf_symbolic_host", "gmrf_profile", "gmrf_kernel_stats", "gmrf_matern_values",
-           "gmrf_spmv", "gmrf_misfit", "gmrf_solve_rhs", "gmrf_gn_burgers"]
+           "gmrf_spmv", "gmrf_misfit", "gmrf_solve_rhs", "gmrf_gn_burgers", "gmrf_launch_records"]
 
 
 class gmrf_options(ctypes.Structure):
@@ -118,6 +118,7 @@ def load():
         "gmrf_gn_burgers": ([P, i64, i64, d, d, P, P, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                              ctypes.c_int, P, P], i32),
         "gmrf_kernel_stats": ([P, P, ctypes.c_int, P], i32),
+        "gmrf_launch_records": ([P, P, ctypes.c_int64, P], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -368,6 +369,23 @@ class Context:
         self._check(self.lib.gmrf_kernel_stats(self.h, arr, cnt.value, ctypes.byref(cnt)))
         return {a.name.decode(): dict(launches=a.launches, ms=a.ms, flops=a.flops, bytes=a.bytes)
                 for a in arr}
+
+    def launch_records(self):
+        """Per-launch profile records since the last profile() call: structured array
+        with fields cls (class name), flops, bytes, ms."""
+        cnt = ctypes.c_int64(0)
+        self._check(self.lib.gmrf_launch_records(self.h, None, 0, ctypes.byref(cnt)))
+        raw = np.zeros(cnt.value, dtype=[("cls", np.int32), ("reserved", np.int32), ("flops", np.float64),
+                                         ("bytes", np.float64), ("ms", np.float64)])
+        if cnt.value:
+            self._check(self.lib.gmrf_launch_records(self.h, _np_ptr(raw), cnt.value, ctypes.byref(cnt)))
+        names = np.array(KERNEL_CLASSES)
+        out = np.zeros(len(raw), dtype=[("cls", "U16"), ("flops", np.float64), ("bytes", np.float64),
+                                        ("ms", np.float64)])
+        out["cls"] = names[raw["cls"]] if len(raw) else []
+        for f in ("flops", "bytes", "ms"):
+            out[f] = raw[f]
+        return out
 
     def phase_ms(self):
         out = np.zeros(3)

@@ -154,6 +154,7 @@ struct gmrf_ctx {
   double cls_flops[KC_COUNT] = {0};
   double cls_bytes[KC_COUNT] = {0};
   int64_t cls_n[KC_COUNT] = {0};
+  std::vector<gmrf_launch_rec_t> recs;   // per-launch records since profiling was reset
   int tsize = 8;   // bytes per working-precision element of the current numeric phase
   // Gauss-Newton scratch
   DevArr<double> d_gn_x, d_gn_d, d_gn_tmp, d_gn_part, d_gn_quad, d_gn_sel, d_gn_rec;
@@ -208,6 +209,7 @@ void prof_fold(gmrf_t h) {
   for (const auto& m : h->marks) {
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, h->evpool[m.e0], h->evpool[m.e1]) == hipSuccess) h->cls_ms[m.cls] += ms;
+    h->recs.push_back({m.cls, 0, m.flops, m.bytes, (double)ms});
     h->cls_flops[m.cls] += m.flops;
     h->cls_bytes[m.cls] += m.bytes;
     h->cls_n[m.cls] += 1;
@@ -1630,6 +1632,7 @@ gmrf_status gmrf_profile(gmrf_t h, int enable) {
   if (!h) return GMRF_ERR_ARG;
   prof_fold(h);
   for (int c = 0; c < KC_COUNT; ++c) { h->cls_ms[c] = 0; h->cls_flops[c] = 0; h->cls_bytes[c] = 0; h->cls_n[c] = 0; }
+  h->recs.clear();
   h->prof = enable != 0;
   h->prof_mask = enable == 1 ? 0xffffffffu : (uint32_t)enable;
   return GMRF_OK;
@@ -1647,6 +1650,17 @@ gmrf_status gmrf_kernel_stats(gmrf_t h, gmrf_kernel_stat_t* out, int capacity, i
     out[c].ms = h->cls_ms[c];
     out[c].flops = h->cls_flops[c];
     out[c].bytes = h->cls_bytes[c];
+  }
+  return GMRF_OK;
+}
+
+gmrf_status gmrf_launch_records(gmrf_t h, gmrf_launch_rec_t* out, int64_t capacity, int64_t* count) {
+  if (!h || capacity < 0) return fail(h, GMRF_ERR_ARG, "bad argument");
+  prof_fold(h);
+  if (count) *count = (int64_t)h->recs.size();
+  if (out) {
+    const size_t c = std::min((size_t)capacity, h->recs.size());
+    if (c) std::memcpy(out, h->recs.data(), c * sizeof(gmrf_launch_rec_t));
   }
   return GMRF_OK;
 }

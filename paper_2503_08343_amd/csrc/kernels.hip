@@ -78,58 +78,66 @@ __device__ __forceinline__ int64_t wg_id() { return (int64_t)blockIdx.x; }
 // can be reused by the caller.
 constexpr int kTile64Lds = 2 * kTK * kP;
 
+// Loads of one K chunk from clamped addresses (M, N, K >= 1), left unmasked so that no
+// consumer sits between them and the multiplication of the current chunk; tile64_store
+// zeroes the out-of-range entries.
 template <typename T, bool A_KC, bool B_KC>
 __device__ __forceinline__ void tile64_load(const T* __restrict__ A, int64_t lda, const T* __restrict__ B,
                                             int64_t ldb, int M, int N, int K, int k0, T (&ra)[4], T (&rb)[4]) {
   const int t = threadIdx.x;
   if (!A_KC) {
-    const int m = t & 63;
+    const T* Am = A + min(t & 63, M - 1);
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int k = (t >> 6) + 4 * i;
-      ra[i] = (m < M && k0 + k < K) ? A[m + (int64_t)(k0 + k) * lda] : T(0);
-    }
+    for (int i = 0; i < 4; ++i) ra[i] = Am[(int64_t)min(k0 + (t >> 6) + 4 * i, K - 1) * lda];
   } else {
-    const int k = t & 15;
+    const T* Ak = A + min(k0 + (t & 15), K - 1);
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int m = (t >> 4) + 16 * i;
-      ra[i] = (m < M && k0 + k < K) ? A[(k0 + k) + (int64_t)m * lda] : T(0);
-    }
+    for (int i = 0; i < 4; ++i) ra[i] = Ak[(int64_t)min((t >> 4) + 16 * i, M - 1) * lda];
   }
   if (!B_KC) {
-    const int nn = t & 63;
+    const T* Bn = B + min(t & 63, N - 1);
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int k = (t >> 6) + 4 * i;
-      rb[i] = (nn < N && k0 + k < K) ? B[nn + (int64_t)(k0 + k) * ldb] : T(0);
-    }
+    for (int i = 0; i < 4; ++i) rb[i] = Bn[(int64_t)min(k0 + (t >> 6) + 4 * i, K - 1) * ldb];
   } else {
-    const int k = t & 15;
+    const T* Bk = B + min(k0 + (t & 15), K - 1);
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int nn = (t >> 4) + 16 * i;
-      rb[i] = (nn < N && k0 + k < K) ? B[(k0 + k) + (int64_t)nn * ldb] : T(0);
-    }
+    for (int i = 0; i < 4; ++i) rb[i] = Bk[(int64_t)min((t >> 4) + 16 * i, N - 1) * ldb];
   }
 }
 
 template <typename T, bool A_KC, bool B_KC>
-__device__ __forceinline__ void tile64_store(T* sA, T* sB, const T (&ra)[4], const T (&rb)[4]) {
+__device__ __forceinline__ void tile64_store(T* sA, T* sB, const T (&ra)[4], const T (&rb)[4], int M, int N, int K,
+                                             int k0) {
   const int t = threadIdx.x;
   if (!A_KC) {
+    const T mm = (T)((t & 63) < M);
 #pragma unroll
-    for (int i = 0; i < 4; ++i) sA[((t >> 6) + 4 * i) * kP + (t & 63)] = ra[i];
+    for (int i = 0; i < 4; ++i) {
+      const int k = (t >> 6) + 4 * i;
+      sA[k * kP + (t & 63)] = ra[i] * (mm * (T)(k0 + k < K));
+    }
   } else {
+    const T mk = (T)(k0 + (t & 15) < K);
 #pragma unroll
-    for (int i = 0; i < 4; ++i) sA[(t & 15) * kP + (t >> 4) + 16 * i] = ra[i];
+    for (int i = 0; i < 4; ++i) {
+      const int m = (t >> 4) + 16 * i;
+      sA[(t & 15) * kP + m] = ra[i] * (mk * (T)(m < M));
+    }
   }
   if (!B_KC) {
+    const T mn = (T)((t & 63) < N);
 #pragma unroll
-    for (int i = 0; i < 4; ++i) sB[((t >> 6) + 4 * i) * kP + (t & 63)] = rb[i];
+    for (int i = 0; i < 4; ++i) {
+      const int k = (t >> 6) + 4 * i;
+      sB[k * kP + (t & 63)] = rb[i] * (mn * (T)(k0 + k < K));
+    }
   } else {
+    const T mk = (T)(k0 + (t & 15) < K);
 #pragma unroll
-    for (int i = 0; i < 4; ++i) sB[(t & 15) * kP + (t >> 4) + 16 * i] = rb[i];
+    for (int i = 0; i < 4; ++i) {
+      const int nn = (t >> 4) + 16 * i;
+      sB[(t & 15) * kP + nn] = rb[i] * (mk * (T)(nn < N));
+    }
   }
 }
 
@@ -143,7 +151,7 @@ __device__ __forceinline__ void gemm_tile(const T* __restrict__ A, int64_t lda,
   if (K <= 0) return;
   T ra[4], rb[4];
   tile64_load<T, A_KC, B_KC>(A, lda, B, ldb, M, N, K, 0, ra, rb);
-  tile64_store<T, A_KC, B_KC>(sA, sB, ra, rb);
+  tile64_store<T, A_KC, B_KC>(sA, sB, ra, rb, M, N, K, 0);
   __syncthreads();
   int buf = 0;
   for (int k0 = 0; k0 < K; k0 += kTK) {
@@ -163,7 +171,8 @@ __device__ __forceinline__ void gemm_tile(const T* __restrict__ A, int64_t lda,
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = mfma(a[i], b[j], acc[i][j]);
     }
-    if (more) tile64_store<T, A_KC, B_KC>(sA + (buf ^ 1) * (kTK * kP), sB + (buf ^ 1) * (kTK * kP), ra, rb);
+    if (more) tile64_store<T, A_KC, B_KC>(sA + (buf ^ 1) * (kTK * kP), sB + (buf ^ 1) * (kTK * kP), ra, rb, M, N, K,
+                                            k0 + kTK);
     __syncthreads();
     buf ^= 1;
   }
@@ -259,6 +268,7 @@ constexpr int kBP = 144;   // LDS pitch: rows of a K slice start 32 banks apart 
 // per CU; 32 halved the occupancy and ran slower)
 template <typename T> struct BigTK { static constexpr int v = 16; };
 
+// Same division of work as tile64_load / tile64_store for the 128 x 128 tiles.
 template <typename T, bool A_KC, bool B_KC>
 __device__ __forceinline__ void big_load(const T* __restrict__ A, int64_t lda, const T* __restrict__ B,
                                          int64_t ldb, int M, int N, int K, int k0,
@@ -266,59 +276,63 @@ __device__ __forceinline__ void big_load(const T* __restrict__ A, int64_t lda, c
   constexpr int TK = BigTK<T>::v, NL = TK / 2;
   const int t = threadIdx.x;
   if (!A_KC) {
-    const int m = t & 127;
+    const T* Am = A + min(t & 127, M - 1);
 #pragma unroll
-    for (int i = 0; i < NL; ++i) {
-      const int k = (t >> 7) + 2 * i;
-      ra[i] = (m < M && k0 + k < K) ? A[m + (int64_t)(k0 + k) * lda] : T(0);
-    }
+    for (int i = 0; i < NL; ++i) ra[i] = Am[(int64_t)min(k0 + (t >> 7) + 2 * i, K - 1) * lda];
   } else {
-    const int k = t & (TK - 1);
+    const T* Ak = A + min(k0 + (t & (TK - 1)), K - 1);
 #pragma unroll
-    for (int i = 0; i < NL; ++i) {
-      const int m = t / TK + (kThreads / TK) * i;
-      ra[i] = (m < M && k0 + k < K) ? A[(k0 + k) + (int64_t)m * lda] : T(0);
-    }
+    for (int i = 0; i < NL; ++i) ra[i] = Ak[(int64_t)min(t / TK + (kThreads / TK) * i, M - 1) * lda];
   }
   if (!B_KC) {
-    const int nn = t & 127;
+    const T* Bn = B + min(t & 127, N - 1);
 #pragma unroll
-    for (int i = 0; i < NL; ++i) {
-      const int k = (t >> 7) + 2 * i;
-      rb[i] = (nn < N && k0 + k < K) ? B[nn + (int64_t)(k0 + k) * ldb] : T(0);
-    }
+    for (int i = 0; i < NL; ++i) rb[i] = Bn[(int64_t)min(k0 + (t >> 7) + 2 * i, K - 1) * ldb];
   } else {
-    const int k = t & (TK - 1);
+    const T* Bk = B + min(k0 + (t & (TK - 1)), K - 1);
 #pragma unroll
-    for (int i = 0; i < NL; ++i) {
-      const int nn = t / TK + (kThreads / TK) * i;
-      rb[i] = (nn < N && k0 + k < K) ? B[(k0 + k) + (int64_t)nn * ldb] : T(0);
-    }
+    for (int i = 0; i < NL; ++i) rb[i] = Bk[(int64_t)min(t / TK + (kThreads / TK) * i, N - 1) * ldb];
   }
 }
 
 template <typename T, bool A_KC, bool B_KC>
 __device__ __forceinline__ void big_store(T* sA, T* sB, const T (&ra)[BigTK<T>::v / 2],
-                                          const T (&rb)[BigTK<T>::v / 2]) {
+                                          const T (&rb)[BigTK<T>::v / 2], int M, int N, int K, int k0) {
   constexpr int TK = BigTK<T>::v, NL = TK / 2;
   const int t = threadIdx.x;
   if (!A_KC) {
     const int m = t & 127;
+    const T mm = (T)(m < M);
 #pragma unroll
-    for (int i = 0; i < NL; ++i) sA[((t >> 7) + 2 * i) * kBP + m] = ra[i];
+    for (int i = 0; i < NL; ++i) {
+      const int k = (t >> 7) + 2 * i;
+      sA[k * kBP + m] = ra[i] * (mm * (T)(k0 + k < K));
+    }
   } else {
     const int k = t & (TK - 1);
+    const T mk = (T)(k0 + k < K);
 #pragma unroll
-    for (int i = 0; i < NL; ++i) sA[k * kBP + t / TK + (kThreads / TK) * i] = ra[i];
+    for (int i = 0; i < NL; ++i) {
+      const int m = t / TK + (kThreads / TK) * i;
+      sA[k * kBP + m] = ra[i] * (mk * (T)(m < M));
+    }
   }
   if (!B_KC) {
     const int nn = t & 127;
+    const T mn = (T)(nn < N);
 #pragma unroll
-    for (int i = 0; i < NL; ++i) sB[((t >> 7) + 2 * i) * kBP + nn] = rb[i];
+    for (int i = 0; i < NL; ++i) {
+      const int k = (t >> 7) + 2 * i;
+      sB[k * kBP + nn] = rb[i] * (mn * (T)(k0 + k < K));
+    }
   } else {
     const int k = t & (TK - 1);
+    const T mk = (T)(k0 + k < K);
 #pragma unroll
-    for (int i = 0; i < NL; ++i) sB[k * kBP + t / TK + (kThreads / TK) * i] = rb[i];
+    for (int i = 0; i < NL; ++i) {
+      const int nn = t / TK + (kThreads / TK) * i;
+      sB[k * kBP + nn] = rb[i] * (mk * (T)(nn < N));
+    }
   }
 }
 
@@ -337,7 +351,7 @@ __device__ __forceinline__ void gemm_tile128(const T* __restrict__ A, int64_t ld
   T ra[TK / 2], rb[TK / 2];
   if (K <= 0) return;
   big_load<T, A_KC, B_KC>(A, lda, B, ldb, M, N, K, 0, ra, rb);
-  big_store<T, A_KC, B_KC>(sA, sB, ra, rb);
+  big_store<T, A_KC, B_KC>(sA, sB, ra, rb, M, N, K, 0);
   __syncthreads();
   int buf = 0;
   for (int k0 = 0; k0 < K; k0 += TK) {
@@ -357,7 +371,8 @@ __device__ __forceinline__ void gemm_tile128(const T* __restrict__ A, int64_t ld
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = mfma(a[i], b[j], acc[i][j]);
     }
-    if (more) big_store<T, A_KC, B_KC>(sA + (buf ^ 1) * (TK * kBP), sB + (buf ^ 1) * (TK * kBP), ra, rb);
+    if (more) big_store<T, A_KC, B_KC>(sA + (buf ^ 1) * (TK * kBP), sB + (buf ^ 1) * (TK * kBP), ra, rb, M, N, K,
+                                         k0 + TK);
     __syncthreads();
     buf ^= 1;
   }
@@ -395,89 +410,155 @@ __device__ __forceinline__ void zero_acc2(f4_t (&acc)[8][4]) {
     for (int j = 0; j < 4; ++j) acc[i][j] = f4_t{0.f, 0.f, 0.f, 0.f};
 }
 
-// Unconditional loads from clamped addresses (M, N, K >= 1), masked by a product so that
-// no branch separates the batch of loads.
+// Unconditional loads from clamped addresses (M, N, K >= 1): no branch separates the batch
+// of loads, and nothing consumes the values before g2_store, so the loads of the next K
+// chunk stay in flight while the current one is multiplied.
 template <bool A_KC, bool B_KC>
 __device__ __forceinline__ void g2_load(const float* __restrict__ A, int64_t lda, const float* __restrict__ B,
                                         int64_t ldb, int M, int N, int K, int k0, float (&ra)[16], float (&rb)[8]) {
   const int t = threadIdx.x;
   if (!A_KC) {
     const float* Ar = A + min(t, M - 1);
+#pragma unroll
+    for (int q = 0; q < 16; ++q) ra[q] = Ar[(int64_t)min(k0 + q, K - 1) * lda];
+  } else {
+    const float* Ak = A + min(k0 + (t & 15), K - 1);
+#pragma unroll
+    for (int q = 0; q < 16; ++q) ra[q] = Ak[(int64_t)min((t >> 4) + 16 * q, M - 1) * lda];
+  }
+  if (!B_KC) {
+    const float* Bn = B + min(t & 127, N - 1);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) rb[q] = Bn[(int64_t)min(k0 + (t >> 7) + 2 * q, K - 1) * ldb];
+  } else {
+    const float* Bk = B + min(k0 + (t & 15), K - 1);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) rb[q] = Bk[(int64_t)min((t >> 4) + 16 * q, N - 1) * ldb];
+  }
+}
+
+// Stores a chunk loaded by g2_load into LDS (k-major), zeroing the entries outside the
+// M x N x K operands by a product with the in-range mask.
+template <bool A_KC, bool B_KC>
+__device__ __forceinline__ void g2_store(float* a, float* b, const float (&ra)[16], const float (&rb)[8], int M,
+                                         int N, int K, int k0) {
+  const int t = threadIdx.x;
+  if (!A_KC) {
     const float mm = (float)(t < M);
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int k = k0 + q;
-      ra[q] = Ar[(int64_t)min(k, K - 1) * lda] * (mm * (float)(k < K));
-    }
+    for (int q = 0; q < 16; ++q) a[q * kPA2 + t] = ra[q] * (mm * (float)(k0 + q < K));
   } else {
-    const int k = k0 + (t & 15);
-    const float* Ak = A + min(k, K - 1);
-    const float mk = (float)(k < K);
+    const int k = t & 15;
+    const float mk = (float)(k0 + k < K);
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
       const int m = (t >> 4) + 16 * q;
-      ra[q] = Ak[(int64_t)min(m, M - 1) * lda] * (mk * (float)(m < M));
+      a[k * kPA2 + m] = ra[q] * (mk * (float)(m < M));
     }
   }
   if (!B_KC) {
     const int nn = t & 127;
-    const float* Bn = B + min(nn, N - 1);
     const float mn = (float)(nn < N);
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
-      const int k = k0 + (t >> 7) + 2 * q;
-      rb[q] = Bn[(int64_t)min(k, K - 1) * ldb] * (mn * (float)(k < K));
+      const int k = (t >> 7) + 2 * q;
+      b[k * kPB2 + nn] = rb[q] * (mn * (float)(k0 + k < K));
     }
   } else {
-    const int k = k0 + (t & 15);
-    const float* Bk = B + min(k, K - 1);
-    const float mk = (float)(k < K);
+    const int k = t & 15;
+    const float mk = (float)(k0 + k < K);
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
       const int nn = (t >> 4) + 16 * q;
-      rb[q] = Bk[(int64_t)min(nn, N - 1) * ldb] * (mk * (float)(nn < N));
+      b[k * kPB2 + nn] = rb[q] * (mk * (float)(nn < N));
     }
   }
 }
 
-template <bool A_KC, bool B_KC>
-__device__ __forceinline__ void g2_store(float* a, float* b, const float (&ra)[16], const float (&rb)[8]) {
-  const int t = threadIdx.x;
-  if (!A_KC) {
+// 16 columns k0 .. k0+15 (all < K) of rows [0, R) of a column-major operand (rows
+// contiguous) copied straight from global memory into the k-major LDS chunk (row k at
+// lds + k * pitch) by LDS-DMA loads: no registers, no LDS store instructions.  Rows >= M
+// read row M - 1; the products they feed land in output rows / columns the epilogues
+// discard.  The compiler waits for the copies before the next barrier.
+template <int R>
+__device__ __forceinline__ void g2_dma_chunk(const float* __restrict__ A, int64_t lda, int M, int k0, float* lds,
+                                             int pitch) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if constexpr (R == kG2M) {
+    const float* Am = A + min(64 * w + lane, M - 1) + (int64_t)k0 * lda;
 #pragma unroll
-    for (int q = 0; q < 16; ++q) a[q * kPA2 + t] = ra[q];
+    for (int q = 0; q < kG2K; ++q)
+      __builtin_amdgcn_global_load_lds(Am + (int64_t)q * lda, lds + q * pitch + 64 * w, 4, 0, 0);
   } else {
-    const int k = t & 15;
+    static_assert(R == kG2N, "operand tiles are 256 or 128 rows");
+    const int h = w & 1;
+    const float* An = A + min(64 * h + lane, M - 1) + (int64_t)k0 * lda;
 #pragma unroll
-    for (int q = 0; q < 16; ++q) a[k * kPA2 + (t >> 4) + 16 * q] = ra[q];
-  }
-  if (!B_KC) {
-    const int nn = t & 127;
-#pragma unroll
-    for (int q = 0; q < 8; ++q) b[((t >> 7) + 2 * q) * kPB2 + nn] = rb[q];
-  } else {
-    const int k = t & 15;
-#pragma unroll
-    for (int q = 0; q < 8; ++q) b[k * kPB2 + (t >> 4) + 16 * q] = rb[q];
+    for (int q = 0; q < kG2K / 2; ++q) {
+      const int k = (w >> 1) + 2 * q;
+      __builtin_amdgcn_global_load_lds(An + (int64_t)k * lda, lds + k * pitch + 64 * h, 4, 0, 0);
+    }
   }
 }
 
-// acc += A(M x K) B(N x K)^T for a 256 x 128 tile (operand conventions of gemm_tile)
+// register path of a k-contiguous B operand (B[k + n ldb]) for a full K chunk
+__device__ __forceinline__ void g2_load_bkc(const float* __restrict__ B, int64_t ldb, int N, int K, int k0,
+                                            float (&rb)[8]) {
+  const int t = threadIdx.x;
+  const float* Bk = B + min(k0 + (t & 15), K - 1);
+#pragma unroll
+  for (int q = 0; q < 8; ++q) rb[q] = Bk[(int64_t)min((t >> 4) + 16 * q, N - 1) * ldb];
+}
+__device__ __forceinline__ void g2_store_bkc(float* b, const float (&rb)[8], int N, int K, int k0) {
+  const int t = threadIdx.x, k = t & 15;
+  const float mk = (float)(k0 + k < K);
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const int nn = (t >> 4) + 16 * q;
+    b[k * kPB2 + nn] = rb[q] * (mk * (float)(nn < N));
+  }
+}
+
+// acc += A(M x K) B(N x K)^T for a 256 x 128 tile (operand conventions of gemm_tile; A is
+// column-major).  Full 16-wide K chunks of column-major operands arrive by LDS-DMA into the
+// idle buffer while the current chunk is multiplied; a k-contiguous B and the ragged last
+// chunk go through registers (clamped loads, masked LDS stores).  Rows of the result at or
+// beyond M, N are undefined.
 template <bool A_KC, bool B_KC>
 __device__ __forceinline__ void gemm_tile2(const float* __restrict__ A, int64_t lda, const float* __restrict__ B,
                                            int64_t ldb, int M, int N, int K, f4_t (&acc)[8][4], G2Lds& S) {
+  static_assert(!A_KC, "the 256-row operand is column-major");
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int wm = (w & 1) * 128, wn = (w >> 1) * 64;
   const int r = lane & 15, g = lane >> 4;
   float ra[16], rb[8];
   if (K <= 0) return;
-  g2_load<A_KC, B_KC>(A, lda, B, ldb, M, N, K, 0, ra, rb);
-  g2_store<A_KC, B_KC>(S.a[0], S.b[0], ra, rb);
+  if (K >= kG2K) {
+    g2_dma_chunk<kG2M>(A, lda, M, 0, S.a[0], kPA2);
+    if (!B_KC) {
+      g2_dma_chunk<kG2N>(B, ldb, N, 0, S.b[0], kPB2);
+    } else {
+      g2_load_bkc(B, ldb, N, K, 0, rb);
+      g2_store_bkc(S.b[0], rb, N, K, 0);
+    }
+  } else {
+    g2_load<false, B_KC>(A, lda, B, ldb, M, N, K, 0, ra, rb);
+    g2_store<false, B_KC>(S.a[0], S.b[0], ra, rb, M, N, K, 0);
+  }
   __syncthreads();
   int buf = 0;
   for (int k0 = 0; k0 < K; k0 += kG2K) {
-    const bool more = k0 + kG2K < K;
-    if (more) g2_load<A_KC, B_KC>(A, lda, B, ldb, M, N, K, k0 + kG2K, ra, rb);
+    const int kn = k0 + kG2K;
+    const bool more = kn < K, full = kn + kG2K <= K;
+    if (more) {
+      if (full) {
+        g2_dma_chunk<kG2M>(A, lda, M, kn, S.a[buf ^ 1], kPA2);
+        if (!B_KC) g2_dma_chunk<kG2N>(B, ldb, N, kn, S.b[buf ^ 1], kPB2);
+        else g2_load_bkc(B, ldb, N, K, kn, rb);
+      } else {
+        g2_load<false, B_KC>(A, lda, B, ldb, M, N, K, kn, ra, rb);
+      }
+    }
     const float* cA = S.a[buf];
     const float* cB = S.b[buf];
 #pragma unroll
@@ -492,7 +573,13 @@ __device__ __forceinline__ void gemm_tile2(const float* __restrict__ A, int64_t 
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
     }
-    if (more) g2_store<A_KC, B_KC>(S.a[buf ^ 1], S.b[buf ^ 1], ra, rb);
+    if (more) {
+      if (full) {
+        if (B_KC) g2_store_bkc(S.b[buf ^ 1], rb, N, K, kn);
+      } else {
+        g2_store<false, B_KC>(S.a[buf ^ 1], S.b[buf ^ 1], ra, rb, M, N, K, kn);
+      }
+    }
     __syncthreads();
     buf ^= 1;
   }
