@@ -138,7 +138,7 @@ struct SelBufs {
   const T* D;
   T* Scur;         // square Sigma fronts of the current depth
   T* Spar;         // square Sigma fronts of the parent depth
-  T* Y;            // n_s x 256 scratch per front (offset Voff * 256)
+  T* Y;            // 256 x n_s scratch per front (offset Voff * 256), block columns contiguous
   T* part;         // split-K partials of the diagonal Sigma blocks
   T* gpart;        // split-K partials of Sigma[R', K] (128 x 128 per work-group)
 };

@@ -1922,7 +1922,9 @@ __global__ __launch_bounds__(kThreads) void k_inv256(DevSym S, LaunchList L, con
   }
 }
 
-// X = L[R', K] Linv_KK into Y (ld n_s, row 0 = first row of R'); 128x128 tiles
+// X = L[R', K] Linv_KK, stored transposed: Y[c + r * 256] holds X[r, c] (r = 0 is the
+// first row of R'), so that every product reading Y takes it with its block columns
+// contiguous; 128x128 tiles
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_sel_Y2(DevSym S, LaunchList L, int step, SelBufs<T> B,
                                                      const int64_t* __restrict__ D2off, const T* __restrict__ D2) {
@@ -1944,7 +1946,7 @@ __global__ __launch_bounds__(kThreads) void k_sel_Y2(DevSym S, LaunchList L, int
                                M, N, o.kb2, acc, sA, sB);
   T* Y = B.Y + S.Voff[s] * kNB2;
   for_acc128<T>(acc, [&](int r, int c, T v) {
-    if (r < M && c < N) Y[(row0 - o.rs + r) + (int64_t)(col0 + c) * n] = v;
+    if (r < M && c < N) Y[(col0 + c) + (int64_t)(row0 - o.rs + r) * kNB2] = v;
   });
 }
 
@@ -1971,8 +1973,8 @@ __global__ __launch_bounds__(kThreads) void k_sel_gemm2(DevSym S, LaunchList L, 
   const T* Y = B.Y + S.Voff[s] * kNB2;
   typename V4<T>::type acc[4][4];
   zero_acc128<T>(acc);
-  gemm_tile128<T, false, true>(Sf + row0 + (int64_t)(o.rs + kb) * n, n, Y + kb + (int64_t)col0 * n, n, M, N,
-                               ke - kb, acc, sA, sB);
+  gemm_tile128<T, false, false>(Sf + row0 + (int64_t)(o.rs + kb) * n, n, Y + col0 + (int64_t)kb * kNB2, kNB2, M,
+                                N, ke - kb, acc, sA, sB);
   if (split == 1) {
     for_acc128<T>(acc, [&](int r, int c, T v) {
       if (r < M && c < N) {
@@ -2008,8 +2010,8 @@ __global__ __launch_bounds__(kThreads, 2) void k_sel_gemm3(DevSym S, LaunchList 
   const float* Y = B.Y + S.Voff[s] * kNB2;
   f4_t acc[8][4];
   zero_acc2(acc);
-  gemm_tile2<false, true>(Sf + row0 + (int64_t)(o.rs + kb) * n, n, Y + kb + (int64_t)col0 * n, n, M, N, ke - kb,
-                          acc, sm.g);
+  gemm_tile2<false, false>(Sf + row0 + (int64_t)(o.rs + kb) * n, n, Y + col0 + (int64_t)kb * kNB2, kNB2, M, N,
+                           ke - kb, acc, sm.g);
   if (split == 1) {
     g2_epilogue<true>(acc, sm, [&](int r, int c, float v) {
       if (r < M && c < N) Sf[(row0 + r) + (int64_t)(o.k2 + col0 + c) * n] = -v;
@@ -2092,8 +2094,8 @@ __global__ __launch_bounds__(kThreads) void k_sel_part2(DevSym S, LaunchList L, 
   typename V4<T>::type acc[2][2];
   zero_acc<T>(acc);
   if (kr > 0)
-    gemm_tile<T, true, true>(Y + r0 + (int64_t)(kNB * ti) * n, n,
-                             Sf + (o.rs + r0) + (int64_t)(o.k2 + kNB * tj) * n, n, M, N, kr, acc, sA, sB);
+    gemm_tile<T, false, true>(Y + kNB * ti + (int64_t)r0 * kNB2, kNB2,
+                              Sf + (o.rs + r0) + (int64_t)(o.k2 + kNB * tj) * n, n, M, N, kr, acc, sA, sB);
   T* out = B.part + wg_id() * (kNB * kNB);
   for_acc<T>(acc, [&](int r, int c, T v) { out[r + c * kNB] = v; });
 }
