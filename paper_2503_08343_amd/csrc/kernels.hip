@@ -1057,6 +1057,39 @@ __global__ __launch_bounds__(kThreads, 2) void k_syrk2(DevSym S, LaunchList L, N
   g2_epilogue_sub(acc, sm, F, n, row0, col0, M, N);
 }
 
+// a[u] = sum over q = 0 .. split-1, in that order, of p[q PT + e0 + u stride] (u < U):
+// four partials of U elements are loaded before they are added, so that 4 U independent
+// loads are in flight per thread.
+template <typename T, int U>
+__device__ __forceinline__ void sum_parts(const T* __restrict__ p, int64_t PT, int split, int e0, int stride,
+                                          T (&a)[U]) {
+#pragma unroll
+  for (int u = 0; u < U; ++u) a[u] = T(0);
+  const T* pe = p + e0;
+  int q = 0;
+  for (; q + 4 <= split; q += 4) {
+    T v[4][U];
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int u = 0; u < U; ++u) v[j][u] = pe[(int64_t)(q + j) * PT + u * stride];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      a[u] += v[0][u];
+      a[u] += v[1][u];
+      a[u] += v[2][u];
+      a[u] += v[3][u];
+    }
+  }
+  for (; q < split; ++q) {
+    T v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = pe[(int64_t)q * PT + u * stride];
+#pragma unroll
+    for (int u = 0; u < U; ++u) a[u] += v[u];
+  }
+}
+
 // FP32 left-looking update of outer block K of the pivot panel: before its first 64-block
 // is factored, the block's columns [k2, k2 + kb2) (rows k2..n) receive
 // -L[rows, 0:k2] L[cols, 0:k2]^T from all earlier outer blocks in one long-K product
@@ -1111,22 +1144,20 @@ __global__ __launch_bounds__(kThreads) void k_panel_red3(DevSym S, LaunchList L,
   constexpr int64_t PT = (int64_t)kG2M * kG2N;
   const float* pp = part + (base + (int64_t)tile * split) * PT + (int64_t)(64 * half) * kG2M;
   float* F = B.Wcur + S.Woff[s];
-  for (int e = threadIdx.x; e < kG2M * 64; e += kThreads) {
-    const int r = e % kG2M, c = e / kG2M;
-    const int gi = row0 + r, gj = col0 + c;
-    if (r < M && c < N && gi >= gj) {
-      float a = 0.f;
-      int q = 0;
-      for (; q + 4 <= split; q += 4) {
-        const float v0 = pp[(int64_t)q * PT + e], v1 = pp[(int64_t)(q + 1) * PT + e];
-        const float v2 = pp[(int64_t)(q + 2) * PT + e], v3 = pp[(int64_t)(q + 3) * PT + e];
-        a += v0;
-        a += v1;
-        a += v2;
-        a += v3;
-      }
-      for (; q < split; ++q) a += pp[(int64_t)q * PT + e];
-      F[gi + (int64_t)gj * n] -= a;
+  constexpr int U = 8;
+  for (int e0 = threadIdx.x; e0 < kG2M * 64; e0 += kThreads * U) {
+    float a[U], old[U];
+    sum_parts<float, U>(pp, PT, split, e0, kThreads, a);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = e0 + u * kThreads, r = min(e % kG2M, M - 1), c = min(e / kG2M, N - 1);
+      old[u] = F[(row0 + r) + (int64_t)(col0 + c) * n];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = e0 + u * kThreads, r = e % kG2M, c = e / kG2M;
+      const int gi = row0 + r, gj = col0 + c;
+      if (r < M && c < N && gi >= gj) F[gi + (int64_t)gj * n] = old[u] - a[u];
     }
   }
 }
@@ -2049,21 +2080,16 @@ __global__ __launch_bounds__(kThreads) void k_sel_gemm_reduce(DevSym S, LaunchLi
   constexpr int64_t PT = (int64_t)TM * 128;
   const T* pp = B.gpart + (base + (int64_t)tile * split) * PT + (int64_t)(64 * half) * TM;
   T* Sf = B.Scur + S.Woff[s];
-  for (int e = threadIdx.x; e < TM * 64; e += kThreads) {
-    const int r = e % TM, c = e / TM;
-    T a = T(0);
-    int q = 0;
-    for (; q + 4 <= split; q += 4) {
-      const T v0 = pp[(int64_t)q * PT + e], v1 = pp[(int64_t)(q + 1) * PT + e];
-      const T v2 = pp[(int64_t)(q + 2) * PT + e], v3 = pp[(int64_t)(q + 3) * PT + e];
-      a += v0;
-      a += v1;
-      a += v2;
-      a += v3;
+  constexpr int U = 8;
+  for (int e0 = threadIdx.x; e0 < TM * 64; e0 += kThreads * U) {
+    T a[U];
+    sum_parts<T, U>(pp, PT, split, e0, kThreads, a);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = e0 + u * kThreads, r = e % TM, c = e / TM;
+      tileS[c][r] = -a[u];
+      if (r < M && c < N) Sf[(row0 + r) + (int64_t)(o.k2 + col0 + c) * n] = -a[u];
     }
-    for (; q < split; ++q) a += pp[(int64_t)q * PT + e];
-    tileS[c][r] = -a;
-    if (r < M && c < N) Sf[(row0 + r) + (int64_t)(o.k2 + col0 + c) * n] = -a;
   }
   __syncthreads();
   for (int e = threadIdx.x; e < TM * 64; e += kThreads) {
