@@ -34,7 +34,7 @@ HBM_GBS = 8000.0
 # (FETCH_SIZE, WRITE_SIZE) scaled by the same counters over a plain 1 GiB copy; valid only
 # for the kernel build they were taken on (keyed by class and precision: 1 = FP32+refine)
 PMC_TRAFFIC = {
-    ("sel_gemm", 1): {"bytes_per_launch": 5.7277e9, "kernel": "k_sel_gemm3",
+    ("sel_gemm", 1): {"bytes_per_launch": 5.6868e9, "kernel": "k_sel_gemm3",
                       "source": "profiles/sel_gemm3_advdiff128x128x64_fp32_hbm_bytes.md"},
 }
 
