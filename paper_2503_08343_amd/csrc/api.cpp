@@ -84,7 +84,7 @@ struct Level {
   int nsteps2 = 0;                                // 256-wide outer blocks of the widest front
   std::vector<HostList> fblk, fout, bpart, bblk;  // solves per outer block
   std::vector<HostList> sY2, sgemm2, sgred, spart2, sfin2;
-  std::vector<HostList> sgemm3, sgred3;   // FP32: 256 x 128 tiles of the Sigma[R', K] products
+  std::vector<HostList> sgemm4, sgred4;   // FP32: 256 x 256 tiles of the Sigma[R', K] products
   HostList syrk3;                          // FP32: 256 x 128 tiles of the trailing SYRK
   std::vector<HostList> pupd3, pred3;      // FP32: left-looking panel update per outer block
   double wsize_elems_scatter = 0.0;
@@ -281,6 +281,7 @@ struct Cost { double flops, elems; };
 constexpr int64_t kSplitMinK = 512;
 constexpr int64_t kSlots128 = 256;   // 128 x 128 tiles (FP64): one resident work-group per CU
 constexpr int64_t kSlots256 = 512;   // FP32 256 x 128 tiles: two per CU
+constexpr int64_t kSlots4 = 256;     // FP32 256 x 256 tiles: one per CU
 // Fronts of one launch have different K (their |R'|): pick one part length P and split
 // every front's K into ceil(K / P) parts, so that all parts carry about the same work.
 // P minimises rounds * (P + overhead of a partial tile) over P = Kmax / S, S = 1..64, with
@@ -631,37 +632,34 @@ gmrf_status build_plan(gmrf_t h) {
         }, [&](int32_t s) { return std::make_pair((int32_t)gsplit(s), (int32_t)gbase[s]); }));
       }
       {
-        // FP32 variant: 256-row tiles
-        auto gtiles3 = [&](int32_t s) -> int64_t {
-          return oact(s) ? ((otail(s) + 255) / 256) * onct(s) : 0;
-        };
-        int64_t gtot3 = 0;
-        for (int32_t s : lv.fronts) gtot3 += gtiles3(s);
-        std::vector<std::pair<int64_t, int64_t>> tk3;
+        // FP32 variant: 256 x 256 tiles (one work-group per 256 rows of R' and K part), one
+        // resident work-group per CU
+        auto gtiles4 = [&](int32_t s) -> int64_t { return oact(s) ? (otail(s) + 255) / 256 : 0; };
+        std::vector<std::pair<int64_t, int64_t>> tk4;
         for (int32_t s : lv.fronts)
-          if (gtiles3(s) > 0) tk3.emplace_back(gtiles3(s), otail(s));
-        const int64_t gP3 = choose_part(tk3, kSlots256);
-        auto gsplit3 = [&](int32_t s) -> int64_t {
-          if (gtiles3(s) == 0) return 1;
-          return std::max<int64_t>(1, (otail(s) + gP3 - 1) / gP3);
+          if (gtiles4(s) > 0) tk4.emplace_back(gtiles4(s), otail(s));
+        const int64_t gP4 = choose_part(tk4, kSlots4);
+        auto gsplit4 = [&](int32_t s) -> int64_t {
+          if (gtiles4(s) == 0) return 1;
+          return std::max<int64_t>(1, (otail(s) + gP4 - 1) / gP4);
         };
-        lv.sgemm3.push_back(B.add(lv.fronts, [&](int32_t s) -> int64_t { return gtiles3(s) * gsplit3(s); },
+        lv.sgemm4.push_back(B.add(lv.fronts, [&](int32_t s) -> int64_t { return gtiles4(s) * gsplit4(s); },
                                   [&](int32_t s) {
           const double r = (double)otail(s), b = (double)okb2(s);
           return Cost{2.0 * r * r * b, r * r + 3.0 * r * b};
-        }, [&](int32_t s) { return std::make_pair((int32_t)gsplit3(s), (int32_t)0); }));
-        const HostList& G = lv.sgemm3.back();
+        }, [&](int32_t s) { return std::make_pair((int32_t)gsplit4(s), (int32_t)0); }));
+        const HostList& G = lv.sgemm4.back();
         std::unordered_map<int32_t, int64_t> gbase;
         bool any = false;
         for (int32_t i = 0; i < G.count; ++i) gbase[B.fronts[G.f_off + i]] = B.prefix[G.p_off + i];
-        for (int32_t s : lv.fronts) any = any || gsplit3(s) > 1;
-        if (any) h->gpart3_max = std::max(h->gpart3_max, G.total);
-        lv.sgred3.push_back(B.add(lv.fronts, [&](int32_t s) -> int64_t {
-          return gsplit3(s) > 1 ? 2 * gtiles3(s) : 0;
+        for (int32_t s : lv.fronts) any = any || gsplit4(s) > 1;
+        if (any) h->gpart3_max = std::max(h->gpart3_max, 2 * G.total);   // 256 x 128 units
+        lv.sgred4.push_back(B.add(lv.fronts, [&](int32_t s) -> int64_t {
+          return gsplit4(s) > 1 ? 4 * gtiles4(s) : 0;
         }, [&](int32_t s) {
           const double r = (double)otail(s), b = (double)okb2(s);
-          return Cost{0.0, (double)gsplit3(s) * r * b + 2.0 * r * b};
-        }, [&](int32_t s) { return std::make_pair((int32_t)gsplit3(s), (int32_t)gbase[s]); }));
+          return Cost{0.0, (double)gsplit4(s) * r * b + 2.0 * r * b};
+        }, [&](int32_t s) { return std::make_pair((int32_t)gsplit4(s), (int32_t)gbase[s]); }));
       }
       lv.spart2.push_back(B.add(lv.fronts, [&](int32_t s) -> int64_t {
         return oact(s) ? std::max<int64_t>(1, (otail(s) + 511) / 512) * onsub(s) * onsub(s) : 0;
@@ -957,11 +955,11 @@ gmrf_status run_selinv(gmrf_t h, double* var, double* sigq) {
       prof_launch(h, KC_SEL_Y, lv.sY2[t].flops, lv.sY2[t].elems,
                   [&] { launch_sel_Y2<T>(st, S, dev_list(h, lv.sY2[t]), t, B, h->d_D2off.p, D2); });
       const bool f32 = std::is_same<T, float>::value;
-      const HostList& G = f32 ? lv.sgemm3[t] : lv.sgemm2[t];
-      const HostList& R = f32 ? lv.sgred3[t] : lv.sgred[t];
+      const HostList& G = f32 ? lv.sgemm4[t] : lv.sgemm2[t];
+      const HostList& R = f32 ? lv.sgred4[t] : lv.sgred[t];
       if (G.total > 0)
         prof_launch(h, KC_SEL_GEMM, G.flops, G.elems, [&] {
-          if constexpr (std::is_same<T, float>::value) launch_sel_gemm3(st, S, dev_list(h, G), t, B);
+          if constexpr (std::is_same<T, float>::value) launch_sel_gemm4(st, S, dev_list(h, G), t, B);
           else launch_sel_gemm2<T>(st, S, dev_list(h, G), t, B);
         });
       if (R.total > 0)

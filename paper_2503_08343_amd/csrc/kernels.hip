@@ -660,6 +660,142 @@ __device__ __forceinline__ void g2_epilogue_sub(const f4_t (&acc)[8][4], G2Smem&
   __syncthreads();
 }
 
+// ---- FP32 256 x 256 tiles for the Sigma[R', K] products ----
+// Eight waves (2 x 4) of 128 x 64, the layout of the 256 x 128 tiles with four column
+// groups: one work-group covers the whole 256-wide outer block, so every Sigma row panel is
+// read once per K part instead of once per 128 columns.  Both operands are column-major.
+constexpr int kG4 = 256, kThreads4 = 512;
+constexpr int kPA4 = kG4 + 4;
+struct G4Lds {
+  float a[2][kG2K * kPA4];
+  float b[2][kG2K * kPA4];
+};
+union __attribute__((aligned(16))) G4Smem {
+  G4Lds g;
+  float ep[64][kG4 + 1];   // epilogue staging of one 64-column group
+};
+
+// LDS-DMA copy of columns k0 .. k0+15 (all < K) of rows [0, 256) (rows >= M read row M - 1):
+// wave w covers rows 64 (w & 3) .. +63 for k = (w >> 2) + 2 q
+__device__ __forceinline__ void g4_dma_chunk(const float* __restrict__ A, int64_t lda, int M, int k0, float* lds) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int h = w & 3;
+  const float* Am = A + min(64 * h + lane, M - 1) + (int64_t)k0 * lda;
+#pragma unroll
+  for (int q = 0; q < kG2K / 2; ++q) {
+    const int k = (w >> 2) + 2 * q;
+    __builtin_amdgcn_global_load_lds(Am + (int64_t)k * lda, lds + k * kPA4 + 64 * h, 4, 0, 0);
+  }
+}
+
+// register path of a ragged last chunk: thread t holds row t & 255 of k = (t >> 8) + 2 q
+__device__ __forceinline__ void g4_load(const float* __restrict__ A, int64_t lda, const float* __restrict__ B,
+                                        int64_t ldb, int M, int N, int K, int k0, float (&ra)[8], float (&rb)[8]) {
+  const int t = threadIdx.x;
+  const float* Am = A + min(t & 255, M - 1);
+  const float* Bn = B + min(t & 255, N - 1);
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const int64_t k = min(k0 + (t >> 8) + 2 * q, K - 1);
+    ra[q] = Am[k * lda];
+    rb[q] = Bn[k * ldb];
+  }
+}
+__device__ __forceinline__ void g4_store(float* a, float* b, const float (&ra)[8], const float (&rb)[8], int M, int N,
+                                         int K, int k0) {
+  const int t = threadIdx.x, m = t & 255;
+  const float mm = (float)(m < M), mn = (float)(m < N);
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const int k = (t >> 8) + 2 * q;
+    const float mk = (float)(k0 + k < K);
+    a[k * kPA4 + m] = ra[q] * (mm * mk);
+    b[k * kPA4 + m] = rb[q] * (mn * mk);
+  }
+}
+
+// acc += A(M x K) B(N x K)^T for a 256 x 256 tile, both operands column-major; full K
+// chunks by LDS-DMA into the idle buffer, a ragged last chunk through registers.  Rows and
+// columns of the result at or beyond M, N are undefined.
+__device__ __forceinline__ void gemm_tile4(const float* __restrict__ A, int64_t lda, const float* __restrict__ B,
+                                           int64_t ldb, int M, int N, int K, f4_t (&acc)[8][4], G4Lds& S) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wm = (w & 1) * 128, wn = (w >> 1) * 64;
+  const int r = lane & 15, g = lane >> 4;
+  float ra[8], rb[8];
+  if (K <= 0) return;
+  if (K >= kG2K) {
+    g4_dma_chunk(A, lda, M, 0, S.a[0]);
+    g4_dma_chunk(B, ldb, N, 0, S.b[0]);
+  } else {
+    g4_load(A, lda, B, ldb, M, N, K, 0, ra, rb);
+    g4_store(S.a[0], S.b[0], ra, rb, M, N, K, 0);
+  }
+  __syncthreads();
+  int buf = 0;
+  for (int k0 = 0; k0 < K; k0 += kG2K) {
+    const int kn = k0 + kG2K;
+    const bool more = kn < K, full = kn + kG2K <= K;
+    if (more) {
+      if (full) {
+        g4_dma_chunk(A, lda, M, kn, S.a[buf ^ 1]);
+        g4_dma_chunk(B, ldb, N, kn, S.b[buf ^ 1]);
+      } else {
+        g4_load(A, lda, B, ldb, M, N, K, kn, ra, rb);
+      }
+    }
+    const float* cA = S.a[buf];
+    const float* cB = S.b[buf];
+#pragma unroll
+    for (int kk = 0; kk < kG2K; kk += 4) {
+      const f4_t a0 = *reinterpret_cast<const f4_t*>(cA + (kk + g) * kPA4 + wm + 8 * r);
+      const f4_t a1 = *reinterpret_cast<const f4_t*>(cA + (kk + g) * kPA4 + wm + 8 * r + 4);
+      const f4_t b0 = *reinterpret_cast<const f4_t*>(cB + (kk + g) * kPA4 + wn + 4 * r);
+      const float a[8] = {a0[0], a0[1], a0[2], a0[3], a1[0], a1[1], a1[2], a1[3]};
+      const float b[4] = {b0[0], b0[1], b0[2], b0[3]};
+#pragma unroll
+      for (int i = 0; i < 8; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+    if (more && !full) g4_store(S.a[buf ^ 1], S.b[buf ^ 1], ra, rb, M, N, K, kn);
+    __syncthreads();
+    buf ^= 1;
+  }
+}
+
+// Epilogue of a 256 x 256 tile through LDS, one 64-column group at a time, with the
+// conventions of g2_epilogue (rows fastest in frow, columns fastest in fcol).
+template <bool COLS, typename FR, typename FC>
+__device__ __forceinline__ void g4_epilogue(const f4_t (&acc)[8][4], G4Smem& sm, FR frow, FC fcol) {
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int wm = (w & 1) * 128;
+  const int r = lane & 15, g = lane >> 4;
+  for (int h = 0; h < 4; ++h) {
+    __syncthreads();
+    if ((w >> 1) == h) {
+#pragma unroll
+      for (int i = 0; i < 8; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) sm.ep[4 * r + j][wm + 8 * (4 * g + q) + i] = acc[i][j][q];
+    }
+    __syncthreads();
+    for (int e = t; e < kG4 * 64; e += kThreads4) {
+      const int row = e & (kG4 - 1), cl = e >> 8;
+      frow(row, 64 * h + cl, sm.ep[cl][row]);
+    }
+    if constexpr (COLS) {
+      for (int e = t; e < kG4 * 64; e += kThreads4) {
+        const int cl = e & 63, row = e >> 6;
+        fcol(row, 64 * h + cl, sm.ep[cl][row]);
+      }
+    }
+  }
+  __syncthreads();
+}
+
 // ------------------------------------------------------------------ assembly kernels
 __global__ void k_assemble_qpost(int64_t nnzq, const double* __restrict__ qval,
                                  const int64_t* __restrict__ cptr, const int32_t* __restrict__ cpair,
@@ -2019,21 +2155,19 @@ __global__ __launch_bounds__(kThreads) void k_sel_gemm2(DevSym S, LaunchList L, 
   }
 }
 
-// FP32 Sigma[R', K] = -Sigma[R', R'] Y in 256 x 128 tiles, split over K like k_sel_gemm2
-// (partials are 256 x 128, column-major).
-__global__ __launch_bounds__(kThreads, 2) void k_sel_gemm3(DevSym S, LaunchList L, int step, SelBufs<float> B) {
-  __shared__ G2Smem sm;
+// FP32 Sigma[R', K] = -Sigma[R', R'] Y in 256 x 256 tiles (the whole outer block per
+// work-group), split over K like k_sel_gemm2 (partials are 256 x 256, column-major).
+__global__ __launch_bounds__(kThreads4, 1) void k_sel_gemm4(DevSym S, LaunchList L, int step, SelBufs<float> B) {
+  __shared__ G4Smem sm;
   int fi; int64_t loc;
   find_front(L, wg_id(), fi, loc);
   const int s = L.fronts[fi];
   const int n = fn(S, s), p = fp(S, s);
   const OuterBlk o = outer_blk(p, n, step);
   const int split = L.aux[2 * fi];
-  const int nct = (o.kb2 + kG2N - 1) / kG2N;
-  const int tile = (int)(loc / split), sp = (int)(loc % split);
-  const int rt = tile / nct, ctile = tile % nct;
-  const int row0 = o.rs + kG2M * rt, col0 = kG2N * ctile;
-  const int M = min(kG2M, n - row0), N = min(kG2N, o.kb2 - col0);
+  const int rt = (int)(loc / split), sp = (int)(loc % split);
+  const int row0 = o.rs + kG4 * rt;
+  const int M = min(kG4, n - row0), N = o.kb2;
   const int np = n - o.rs;
   const int kpart = ((np + split - 1) / split + kG2K - 1) / kG2K * kG2K;
   const int kb = min(np, sp * kpart), ke = min(np, kb + kpart);
@@ -2041,27 +2175,25 @@ __global__ __launch_bounds__(kThreads, 2) void k_sel_gemm3(DevSym S, LaunchList 
   const float* Y = B.Y + S.Voff[s] * kNB2;
   f4_t acc[8][4];
   zero_acc2(acc);
-  gemm_tile2<false, false>(Sf + row0 + (int64_t)(o.rs + kb) * n, n, Y + col0 + (int64_t)kb * kNB2, kNB2, M, N,
-                           ke - kb, acc, sm.g);
+  gemm_tile4(Sf + row0 + (int64_t)(o.rs + kb) * n, n, Y + (int64_t)kb * kNB2, kNB2, M, N, ke - kb, acc, sm.g);
   if (split == 1) {
-    g2_epilogue<true>(acc, sm, [&](int r, int c, float v) {
-      if (r < M && c < N) Sf[(row0 + r) + (int64_t)(o.k2 + col0 + c) * n] = -v;
+    g4_epilogue<true>(acc, sm, [&](int r, int c, float v) {
+      if (r < M && c < N) Sf[(row0 + r) + (int64_t)(o.k2 + c) * n] = -v;
     }, [&](int r, int c, float v) {
-      if (r < M && c < N) Sf[(o.k2 + col0 + c) + (int64_t)(row0 + r) * n] = -v;
+      if (r < M && c < N) Sf[(o.k2 + c) + (int64_t)(row0 + r) * n] = -v;
     });
   } else {
-    float* out = B.gpart + wg_id() * (int64_t)(kG2M * kG2N);
-    g2_epilogue<false>(acc, sm, [&](int r, int c, float v) { out[r + c * kG2M] = v; }, [](int, int, float) {});
+    float* out = B.gpart + wg_id() * (int64_t)(kG4 * kG4);
+    g4_epilogue<false>(acc, sm, [&](int r, int c, float v) { out[r + c * kG4] = v; }, [](int, int, float) {});
   }
 }
 
-// Sum of the split-K partials of one TM x 128 tile of Sigma[R', K] (TM = 128 for the
-// 128 x 128 tiles, 256 for the FP32 256 x 128 tiles) in a fixed order, written to
-// Sigma[R', K] and its mirror Sigma[K, R'].  aux = (split, first work-group of the front
-// in the partial launch).  One work-group per 64-column half of a tile: the sums are
-// formed with coalesced reads, written down the columns, and staged in LDS so that the
-// mirror is written along its rows.
-template <typename T, int TM>
+// Sum of the split-K partials of one TM x NC tile of Sigma[R', K] (128 x 128 tiles, FP32
+// 256 x 256 tiles) in a fixed order, written to Sigma[R', K] and its mirror Sigma[K, R'].
+// aux = (split, first work-group of the front in the partial launch).  One work-group per
+// 64-column group of a tile: the sums are formed with coalesced reads, written down the
+// columns, and staged in LDS so that the mirror is written along its rows.
+template <typename T, int TM, int NC>
 __global__ __launch_bounds__(kThreads) void k_sel_gemm_reduce(DevSym S, LaunchList L, int step, SelBufs<T> B) {
   __shared__ T tileS[64][TM + 1];
   int fi; int64_t loc;
@@ -2071,14 +2203,15 @@ __global__ __launch_bounds__(kThreads) void k_sel_gemm_reduce(DevSym S, LaunchLi
   const OuterBlk o = outer_blk(p, n, step);
   const int split = L.aux[2 * fi];
   const int64_t base = L.aux[2 * fi + 1];
-  const int nct = (o.kb2 + 127) / 128;
-  const int tile = (int)(loc >> 1), half = (int)(loc & 1);
+  constexpr int NQ = NC / 64;
+  const int nct = (o.kb2 + NC - 1) / NC;
+  const int tile = (int)(loc / NQ), quarter = (int)(loc % NQ);
   const int rt = tile / nct, ctile = tile % nct;
-  const int row0 = o.rs + TM * rt, col0 = 128 * ctile + 64 * half;
+  const int row0 = o.rs + TM * rt, col0 = NC * ctile + 64 * quarter;
   const int M = min(TM, n - row0), N = min(64, o.kb2 - col0);
   if (N <= 0) return;
-  constexpr int64_t PT = (int64_t)TM * 128;
-  const T* pp = B.gpart + (base + (int64_t)tile * split) * PT + (int64_t)(64 * half) * TM;
+  constexpr int64_t PT = (int64_t)TM * NC;
+  const T* pp = B.gpart + (base + (int64_t)tile * split) * PT + (int64_t)(64 * quarter) * TM;
   T* Sf = B.Scur + S.Woff[s];
   constexpr int U = 8;
   for (int e0 = threadIdx.x; e0 < TM * 64; e0 += kThreads * U) {
@@ -2425,14 +2558,15 @@ template <typename T> void launch_sel_gemm_reduce(hipStream_t st, const DevSym& 
                                                   SelBufs<T> B) {
   if (L.total <= 0) return;
   if constexpr (std::is_same<T, float>::value)
-    hipLaunchKernelGGL((k_sel_gemm_reduce<float, kG2M>), dim3((unsigned)L.total), dim3(kThreads), 0, st, S, L, step,
-                       B);
+    hipLaunchKernelGGL((k_sel_gemm_reduce<float, kG4, kG4>), dim3((unsigned)L.total), dim3(kThreads), 0, st, S, L,
+                       step, B);
   else
-    hipLaunchKernelGGL((k_sel_gemm_reduce<T, 128>), dim3((unsigned)L.total), dim3(kThreads), 0, st, S, L, step, B);
+    hipLaunchKernelGGL((k_sel_gemm_reduce<T, 128, 128>), dim3((unsigned)L.total), dim3(kThreads), 0, st, S, L, step,
+                       B);
 }
-void launch_sel_gemm3(hipStream_t st, const DevSym& S, const LaunchList& L, int step, SelBufs<float> B) {
+void launch_sel_gemm4(hipStream_t st, const DevSym& S, const LaunchList& L, int step, SelBufs<float> B) {
   if (L.total <= 0) return;
-  hipLaunchKernelGGL(k_sel_gemm3, dim3((unsigned)L.total), dim3(kThreads), 0, st, S, L, step, B);
+  hipLaunchKernelGGL(k_sel_gemm4, dim3((unsigned)L.total), dim3(kThreads4), 0, st, S, L, step, B);
 }
 void launch_panel_upd3(hipStream_t st, const DevSym& S, const LaunchList& L, int K, NumBufs<float> B, float* part) {
   if (L.total <= 0) return;
