@@ -86,7 +86,7 @@ struct Level {
   std::vector<HostList> sY2, sgemm2, sgred, spart2, sfin2;
   std::vector<HostList> sgemm4, sgred4;   // FP32: 256 x 256 tiles of the Sigma[R', K] products
   HostList syrk3;                          // FP32: 256 x 128 tiles of the trailing SYRK
-  std::vector<HostList> pupd3, pred3;      // FP32: left-looking panel update per outer block
+  std::vector<HostList> pupd4, pred4;      // FP32: left-looking panel update per outer block
   double wsize_elems_scatter = 0.0;
 };
 
@@ -280,7 +280,6 @@ struct Cost { double flops, elems; };
 // is within 10% of the ideal T / slots (parts of at least kSplitMinK rows).
 constexpr int64_t kSplitMinK = 512;
 constexpr int64_t kSlots128 = 256;   // 128 x 128 tiles (FP64): one resident work-group per CU
-constexpr int64_t kSlots256 = 512;   // FP32 256 x 128 tiles: two per CU
 constexpr int64_t kSlots4 = 256;     // FP32 256 x 256 tiles: one per CU
 // Fronts of one launch have different K (their |R'|): pick one part length P and split
 // every front's K into ceil(K / P) parts, so that all parts carry about the same work.
@@ -552,30 +551,28 @@ gmrf_status build_plan(gmrf_t h) {
     {
       int nK = 0;
       for (int32_t s : lv.fronts) nK = std::max<int>(nK, (int)((pF(s) + kNB2 - 1) / kNB2));
-      lv.pupd3.assign(std::max(nK, 1), HostList());
-      lv.pred3.assign(std::max(nK, 1), HostList());
+      lv.pupd4.assign(std::max(nK, 1), HostList());
+      lv.pred4.assign(std::max(nK, 1), HostList());
       for (int K = 1; K < nK; ++K) {
         const int64_t k2 = (int64_t)K * kNB2;
         auto pact = [&](int32_t s) { return pF(s) > k2; };
         auto pkb2 = [&](int32_t s) { return std::min<int64_t>(kNB2, pF(s) - k2); };
-        auto ptiles = [&](int32_t s) -> int64_t {
-          return pact(s) ? ((nF(s) - k2 + 255) / 256) * ((pkb2(s) + 127) / 128) : 0;
-        };
+        auto ptiles = [&](int32_t s) -> int64_t { return pact(s) ? (nF(s) - k2 + 255) / 256 : 0; };
         int64_t ptot = 0;
         for (int32_t s : lv.fronts) ptot += ptiles(s);
-        const int64_t pS = choose_split(ptot, kSlots256, k2 / kSplitMinK);
+        const int64_t pS = choose_split(ptot, kSlots4, k2 / kSplitMinK);
         auto psplit = [&](int32_t s) -> int64_t { return ptiles(s) > 0 ? std::max<int64_t>(1, pS) : 1; };
-        lv.pupd3[K] = B.add(lv.fronts, [&](int32_t s) -> int64_t { return ptiles(s) * psplit(s); },
+        lv.pupd4[K] = B.add(lv.fronts, [&](int32_t s) -> int64_t { return ptiles(s) * psplit(s); },
                             [&](int32_t s) {
           const double b = (double)pkb2(s), m = (double)(nF(s) - k2);
           const double E = b * m - 0.5 * b * (b - 1.0);
           return Cost{2.0 * (double)k2 * E, 2.0 * E + (m + b) * (double)k2};
         }, [&](int32_t s) { return std::make_pair((int32_t)psplit(s), (int32_t)0); });
-        const HostList& G = lv.pupd3[K];
+        const HostList& G = lv.pupd4[K];
         std::unordered_map<int32_t, int64_t> gbase;
         for (int32_t i = 0; i < G.count; ++i) gbase[B.fronts[G.f_off + i]] = B.prefix[G.p_off + i];
-        if (pS > 1) h->gpart3_max = std::max(h->gpart3_max, G.total);
-        lv.pred3[K] = B.add(lv.fronts, [&](int32_t s) -> int64_t { return psplit(s) > 1 ? 2 * ptiles(s) : 0; },
+        if (pS > 1) h->gpart3_max = std::max(h->gpart3_max, 2 * G.total);   // 256 x 128 units
+        lv.pred4[K] = B.add(lv.fronts, [&](int32_t s) -> int64_t { return psplit(s) > 1 ? 4 * ptiles(s) : 0; },
                             [&](int32_t s) {
           const double b = (double)pkb2(s), m = (double)(nF(s) - k2);
           return Cost{0.0, (double)psplit(s) * m * b + 2.0 * m * b};
@@ -814,14 +811,14 @@ gmrf_status run_factor(gmrf_t h) {
     for (int k = 0; k < lv.nsteps; ++k) {
       if constexpr (std::is_same<T, float>::value) {
         const int K = k / (kNB2 / kNB);
-        if (k % (kNB2 / kNB) == 0 && K >= 1 && K < (int)lv.pupd3.size()) {
-          if (lv.pupd3[K].total > 0)
-            prof_launch(h, KC_UPDATE, lv.pupd3[K].flops, lv.pupd3[K].elems, [&] {
-              launch_panel_upd3(st, S, dev_list(h, lv.pupd3[K]), K, B, (float*)h->d_gpart.p);
+        if (k % (kNB2 / kNB) == 0 && K >= 1 && K < (int)lv.pupd4.size()) {
+          if (lv.pupd4[K].total > 0)
+            prof_launch(h, KC_UPDATE, lv.pupd4[K].flops, lv.pupd4[K].elems, [&] {
+              launch_panel_upd4(st, S, dev_list(h, lv.pupd4[K]), K, B, (float*)h->d_gpart.p);
             });
-          if (lv.pred3[K].total > 0)
-            prof_launch(h, KC_UPDATE, 0.0, lv.pred3[K].elems, [&] {
-              launch_panel_red3(st, S, dev_list(h, lv.pred3[K]), K, B, (const float*)h->d_gpart.p);
+          if (lv.pred4[K].total > 0)
+            prof_launch(h, KC_UPDATE, 0.0, lv.pred4[K].elems, [&] {
+              launch_panel_red4(st, S, dev_list(h, lv.pred4[K]), K, B, (const float*)h->d_gpart.p);
             });
         }
       }

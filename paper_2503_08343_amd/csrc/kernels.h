@@ -155,9 +155,9 @@ void launch_sel_gemm4(hipStream_t st, const DevSym& S, const LaunchList& L, int 
 // FP32 trailing SYRK of the update matrices in 256 x 128 tiles
 void launch_syrk2(hipStream_t st, const DevSym& S, const LaunchList& L, NumBufs<float> B);
 // FP32 left-looking update of outer block K of the pivot panels from all earlier outer
-// blocks (split-K partials in part, summed by launch_panel_red3)
-void launch_panel_upd3(hipStream_t st, const DevSym& S, const LaunchList& L, int K, NumBufs<float> B, float* part);
-void launch_panel_red3(hipStream_t st, const DevSym& S, const LaunchList& L, int K, NumBufs<float> B,
+// blocks in 256 x 256 tiles (split-K partials in part, summed by launch_panel_red4)
+void launch_panel_upd4(hipStream_t st, const DevSym& S, const LaunchList& L, int K, NumBufs<float> B, float* part);
+void launch_panel_red4(hipStream_t st, const DevSym& S, const LaunchList& L, int K, NumBufs<float> B,
                        const float* part);
 template <typename T> void launch_sel_part2(hipStream_t st, const DevSym& S, const LaunchList& L, int step, SelBufs<T> B);
 template <typename T> void launch_sel_fin2(hipStream_t st, const DevSym& S, const LaunchList& L, const LaunchList& Lpart,

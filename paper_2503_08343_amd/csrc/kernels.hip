@@ -1226,43 +1226,82 @@ __device__ __forceinline__ void sum_parts(const T* __restrict__ p, int64_t PT, i
   }
 }
 
+// F[gi + gj ld] -= C for a 256 x 256 tile (gi = row0 + r, gj = col0 + c, r < M, c < N,
+// gi >= gj), staged through LDS one 64-column group at a time; each thread loads the old
+// values of a group in batches of 8 from clamped addresses before storing.
+__device__ __forceinline__ void g4_epilogue_sub(const f4_t (&acc)[8][4], G4Smem& sm, float* F, int64_t ld,
+                                                int row0, int col0, int M, int N) {
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int wm = (w & 1) * 128;
+  const int r = lane & 15, g = lane >> 4;
+  for (int h = 0; h < 4; ++h) {
+    __syncthreads();
+    if ((w >> 1) == h) {
+#pragma unroll
+      for (int i = 0; i < 8; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) sm.ep[4 * r + j][wm + 8 * (4 * g + q) + i] = acc[i][j][q];
+    }
+    __syncthreads();
+    if (64 * h >= N) continue;
+#pragma unroll
+    for (int e0 = 0; e0 < kG4 * 64; e0 += 8 * kThreads4) {
+      float old[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = e0 + u * kThreads4 + t;
+        const int row = min(e & (kG4 - 1), M - 1), c = min(64 * h + (e >> 8), N - 1);
+        old[u] = F[(row0 + row) + (int64_t)(col0 + c) * ld];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = e0 + u * kThreads4 + t;
+        const int row = e & (kG4 - 1), cl = e >> 8, c = 64 * h + cl;
+        const int gi = row0 + row, gj = col0 + c;
+        if (row < M && c < N && gi >= gj) F[gi + (int64_t)gj * ld] = old[u] - sm.ep[cl][row];
+      }
+    }
+  }
+  __syncthreads();
+}
+
 // FP32 left-looking update of outer block K of the pivot panel: before its first 64-block
 // is factored, the block's columns [k2, k2 + kb2) (rows k2..n) receive
 // -L[rows, 0:k2] L[cols, 0:k2]^T from all earlier outer blocks in one long-K product
-// (256 x 128 tiles; split over K like the Sigma[R', K] products when a depth has too few
-// tiles).  With split 1 the tile is subtracted in place (lower part only), else its
-// partial goes to part + wg * 256 * 128 and k_panel_red3 subtracts the sum.
-__global__ __launch_bounds__(kThreads, 2) void k_panel_upd3(DevSym S, LaunchList L, int K, NumBufs<float> B,
-                                                         float* __restrict__ part) {
-  __shared__ G2Smem sm;
+// (256 x 256 tiles, one per 256 rows; split over K like the Sigma[R', K] products when a
+// depth has too few tiles).  With split 1 the tile is subtracted in place (lower part
+// only), else its partial goes to part + wg * 256^2 and k_panel_red4 subtracts the sum.
+__global__ __launch_bounds__(kThreads4, 1) void k_panel_upd4(DevSym S, LaunchList L, int K, NumBufs<float> B,
+                                                          float* __restrict__ part) {
+  __shared__ G4Smem sm;
   int fi; int64_t loc;
   find_front(L, wg_id(), fi, loc);
   const int s = L.fronts[fi];
   const int n = fn(S, s), p = fp(S, s);
   const int k2 = K * kNB2, kb2 = min(kNB2, p - k2);
   const int split = L.aux[2 * fi];
-  const int nct = (kb2 + kG2N - 1) / kG2N;
-  const int tile = (int)(loc / split), sp = (int)(loc % split);
-  const int rt = tile / nct, ctile = tile % nct;
-  const int row0 = k2 + kG2M * rt, col0 = k2 + kG2N * ctile;
-  const int M = min(kG2M, n - row0), N = min(kG2N, k2 + kb2 - col0);
+  const int rt = (int)(loc / split), sp = (int)(loc % split);
+  const int row0 = k2 + kG4 * rt;
+  const int M = min(kG4, n - row0), N = kb2;
   const int kpart = ((k2 + split - 1) / split + kG2K - 1) / kG2K * kG2K;
   const int kb = min(k2, sp * kpart), ke = min(k2, kb + kpart);
   float* F = B.Wcur + S.Woff[s];
   f4_t acc[8][4];
   zero_acc2(acc);
-  gemm_tile2<false, false>(F + row0 + (int64_t)kb * n, n, F + col0 + (int64_t)kb * n, n, M, N, ke - kb, acc, sm.g);
+  gemm_tile4(F + row0 + (int64_t)kb * n, n, F + k2 + (int64_t)kb * n, n, M, N, ke - kb, acc, sm.g);
   if (split == 1) {
-    g2_epilogue_sub(acc, sm, F, n, row0, col0, M, N);
+    g4_epilogue_sub(acc, sm, F, n, row0, k2, M, N);
   } else {
-    float* out = part + wg_id() * (int64_t)(kG2M * kG2N);
-    g2_epilogue<false>(acc, sm, [&](int r, int c, float v) { out[r + c * kG2M] = v; }, [](int, int, float) {});
+    float* out = part + wg_id() * (int64_t)(kG4 * kG4);
+    g4_epilogue<false>(acc, sm, [&](int r, int c, float v) { out[r + c * kG4] = v; }, [](int, int, float) {});
   }
 }
 
-// Subtract the fixed-order sum of the split-K partials of k_panel_upd3 (one work-group per
-// 64-column half of a tile; aux = (split, first work-group of the front in that launch)).
-__global__ __launch_bounds__(kThreads) void k_panel_red3(DevSym S, LaunchList L, int K, NumBufs<float> B,
+// Subtract the fixed-order sum of the split-K partials of k_panel_upd4 (one work-group per
+// 64-column group of a tile; aux = (split, first work-group of the front in that launch)).
+__global__ __launch_bounds__(kThreads) void k_panel_red4(DevSym S, LaunchList L, int K, NumBufs<float> B,
                                                          const float* __restrict__ part) {
   int fi; int64_t loc;
   find_front(L, wg_id(), fi, loc);
@@ -1271,27 +1310,25 @@ __global__ __launch_bounds__(kThreads) void k_panel_red3(DevSym S, LaunchList L,
   const int k2 = K * kNB2, kb2 = min(kNB2, p - k2);
   const int split = L.aux[2 * fi];
   const int64_t base = L.aux[2 * fi + 1];
-  const int nct = (kb2 + kG2N - 1) / kG2N;
-  const int tile = (int)(loc >> 1), half = (int)(loc & 1);
-  const int rt = tile / nct, ctile = tile % nct;
-  const int row0 = k2 + kG2M * rt, col0 = k2 + kG2N * ctile + 64 * half;
-  const int M = min(kG2M, n - row0), N = min(64, k2 + kb2 - col0);
+  const int tile = (int)(loc >> 2), quarter = (int)(loc & 3);
+  const int row0 = k2 + kG4 * tile, col0 = k2 + 64 * quarter;
+  const int M = min(kG4, n - row0), N = min(64, k2 + kb2 - col0);
   if (N <= 0) return;
-  constexpr int64_t PT = (int64_t)kG2M * kG2N;
-  const float* pp = part + (base + (int64_t)tile * split) * PT + (int64_t)(64 * half) * kG2M;
+  constexpr int64_t PT = (int64_t)kG4 * kG4;
+  const float* pp = part + (base + (int64_t)tile * split) * PT + (int64_t)(64 * quarter) * kG4;
   float* F = B.Wcur + S.Woff[s];
   constexpr int U = 8;
-  for (int e0 = threadIdx.x; e0 < kG2M * 64; e0 += kThreads * U) {
+  for (int e0 = threadIdx.x; e0 < kG4 * 64; e0 += kThreads * U) {
     float a[U], old[U];
     sum_parts<float, U>(pp, PT, split, e0, kThreads, a);
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int e = e0 + u * kThreads, r = min(e % kG2M, M - 1), c = min(e / kG2M, N - 1);
+      const int e = e0 + u * kThreads, r = min(e % kG4, M - 1), c = min(e / kG4, N - 1);
       old[u] = F[(row0 + r) + (int64_t)(col0 + c) * n];
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int e = e0 + u * kThreads, r = e % kG2M, c = e / kG2M;
+      const int e = e0 + u * kThreads, r = e % kG4, c = e / kG4;
       const int gi = row0 + r, gj = col0 + c;
       if (r < M && c < N && gi >= gj) F[gi + (int64_t)gj * n] = old[u] - a[u];
     }
@@ -2568,14 +2605,14 @@ void launch_sel_gemm4(hipStream_t st, const DevSym& S, const LaunchList& L, int 
   if (L.total <= 0) return;
   hipLaunchKernelGGL(k_sel_gemm4, dim3((unsigned)L.total), dim3(kThreads4), 0, st, S, L, step, B);
 }
-void launch_panel_upd3(hipStream_t st, const DevSym& S, const LaunchList& L, int K, NumBufs<float> B, float* part) {
+void launch_panel_upd4(hipStream_t st, const DevSym& S, const LaunchList& L, int K, NumBufs<float> B, float* part) {
   if (L.total <= 0) return;
-  hipLaunchKernelGGL(k_panel_upd3, dim3((unsigned)L.total), dim3(kThreads), 0, st, S, L, K, B, part);
+  hipLaunchKernelGGL(k_panel_upd4, dim3((unsigned)L.total), dim3(kThreads4), 0, st, S, L, K, B, part);
 }
-void launch_panel_red3(hipStream_t st, const DevSym& S, const LaunchList& L, int K, NumBufs<float> B,
+void launch_panel_red4(hipStream_t st, const DevSym& S, const LaunchList& L, int K, NumBufs<float> B,
                        const float* part) {
   if (L.total <= 0) return;
-  hipLaunchKernelGGL(k_panel_red3, dim3((unsigned)L.total), dim3(kThreads), 0, st, S, L, K, B, part);
+  hipLaunchKernelGGL(k_panel_red4, dim3((unsigned)L.total), dim3(kThreads), 0, st, S, L, K, B, part);
 }
 void launch_syrk2(hipStream_t st, const DevSym& S, const LaunchList& L, NumBufs<float> B) {
   if (L.total <= 0) return;
