@@ -85,7 +85,7 @@ struct Level {
   std::vector<HostList> fblk, fout, bpart, bblk;  // solves per outer block
   std::vector<HostList> sY2, sgemm2, sgred, spart2, sfin2;
   std::vector<HostList> sgemm4, sgred4;   // FP32: 256 x 256 tiles of the Sigma[R', K] products
-  HostList syrk3;                          // FP32: 256 x 128 tiles of the trailing SYRK
+  HostList syrk3;                          // FP32: 256 x 256 tiles of the trailing SYRK
   std::vector<HostList> pupd4, pred4;      // FP32: left-looking panel update per outer block
   double wsize_elems_scatter = 0.0;
 };
@@ -693,7 +693,7 @@ gmrf_status build_plan(gmrf_t h) {
       return nF(s) > pF(s) ? upd_tiles(nF(s), pF(s), 2, 0, kBigTile) : 0;
     }, [&](int32_t s) { return upd_cost(nF(s), pF(s), 2, 0); });
     lv.syrk3 = B.add(lv.fronts, [&](int32_t s) -> int64_t {
-      return nF(s) > pF(s) ? upd_tiles(nF(s), pF(s), 2, 0, 128, 256) : 0;
+      return nF(s) > pF(s) ? upd_tiles(nF(s), pF(s), 2, 0, 256, 256) : 0;
     }, [&](int32_t s) { return upd_cost(nF(s), pF(s), 2, 0); });
     lv.inv256 = B.add(lv.fronts, [&](int32_t s) -> int64_t { return (pF(s) + nb - 1) / nb; }, [&](int32_t s) {
       const double p = (double)pF(s);
@@ -836,7 +836,7 @@ gmrf_status run_factor(gmrf_t h) {
     if constexpr (std::is_same<T, float>::value) {
       if (lv.syrk3.total > 0)
         prof_launch(h, KC_SYRK, lv.syrk3.flops, lv.syrk3.elems,
-                    [&] { launch_syrk2(st, S, dev_list(h, lv.syrk3), B); });
+                    [&] { launch_syrk4(st, S, dev_list(h, lv.syrk3), B); });
     } else {
       if (lv.syrk.total > 0)
         prof_launch(h, KC_SYRK, lv.syrk.flops, lv.syrk.elems,

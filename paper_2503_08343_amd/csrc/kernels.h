@@ -152,8 +152,8 @@ template <typename T> void launch_sel_gemm_reduce(hipStream_t st, const DevSym& 
 // FP32 Sigma[R', K] in 256 x 256 tiles (one work-group per 256 rows and K part, split over K
 // like launch_sel_gemm2; partials 256 x 256)
 void launch_sel_gemm4(hipStream_t st, const DevSym& S, const LaunchList& L, int step, SelBufs<float> B);
-// FP32 trailing SYRK of the update matrices in 256 x 128 tiles
-void launch_syrk2(hipStream_t st, const DevSym& S, const LaunchList& L, NumBufs<float> B);
+// FP32 trailing SYRK of the update matrices in 256 x 256 tiles
+void launch_syrk4(hipStream_t st, const DevSym& S, const LaunchList& L, NumBufs<float> B);
 // FP32 left-looking update of outer block K of the pivot panels from all earlier outer
 // blocks in 256 x 256 tiles (split-K partials in part, summed by launch_panel_red4)
 void launch_panel_upd4(hipStream_t st, const DevSym& S, const LaunchList& L, int K, NumBufs<float> B, float* part);

@@ -386,22 +386,16 @@ __device__ __forceinline__ void zero_acc128(typename V4<T>::type (&acc)[4][4]) {
     for (int j = 0; j < 4; ++j) acc[i][j] = typename V4<T>::type{T(0), T(0), T(0), T(0)};
 }
 
-// ---- FP32 256 x 128 tiles for the long-K products (trailing SYRK, Sigma[R', K]) ----
-// Four waves (2 x 2) with 128 x 64 wave tiles of 8 x 4 MFMA 16x16x4 blocks.  Row i' of
-// block i is tile row 8 i' + i and column c' of block j is tile column 4 c' + j, so that
-// a lane's eight A values (four B values) of one k are contiguous in LDS and arrive in
-// 128-bit reads.  Operands are staged k-major with a one-chunk register prefetch.
+// ---- FP32 256 x 256 tiles for the long-K products (Sigma[R', K], the left-looking panel
+// update, the trailing SYRK) ----
+// Eight waves (2 x 4) with 128 x 64 wave tiles of 8 x 4 MFMA 16x16x4 blocks.  Row i' of
+// block i is tile row 8 i' + i and column c' of block j is tile column 4 c' + j, so that a
+// lane's eight A values (four B values) of one k are contiguous in LDS and arrive in 128-bit
+// reads.  Operands are staged k-major in 16-wide K chunks, double-buffered.  One work-group
+// covers a whole 256-wide outer block, so every row panel is read once per K part.  Both
+// operands are column-major.
 typedef float f4_t __attribute__((ext_vector_type(4)));
-constexpr int kG2M = 256, kG2N = 128, kG2K = 16;
-constexpr int kPA2 = kG2M + 4, kPB2 = kG2N + 4;
-struct G2Lds {
-  float a[2][kG2K * kPA2];
-  float b[2][kG2K * kPB2];
-};
-union __attribute__((aligned(16))) G2Smem {
-  G2Lds g;
-  float ep[64][kG2M + 1];   // epilogue staging of one 64-column half of the tile
-};
+constexpr int kG4K = 16;   // K chunk
 
 __device__ __forceinline__ void zero_acc2(f4_t (&acc)[8][4]) {
 #pragma unroll
@@ -410,279 +404,29 @@ __device__ __forceinline__ void zero_acc2(f4_t (&acc)[8][4]) {
     for (int j = 0; j < 4; ++j) acc[i][j] = f4_t{0.f, 0.f, 0.f, 0.f};
 }
 
-// Unconditional loads from clamped addresses (M, N, K >= 1): no branch separates the batch
-// of loads, and nothing consumes the values before g2_store, so the loads of the next K
-// chunk stay in flight while the current one is multiplied.
-template <bool A_KC, bool B_KC>
-__device__ __forceinline__ void g2_load(const float* __restrict__ A, int64_t lda, const float* __restrict__ B,
-                                        int64_t ldb, int M, int N, int K, int k0, float (&ra)[16], float (&rb)[8]) {
-  const int t = threadIdx.x;
-  if (!A_KC) {
-    const float* Ar = A + min(t, M - 1);
-#pragma unroll
-    for (int q = 0; q < 16; ++q) ra[q] = Ar[(int64_t)min(k0 + q, K - 1) * lda];
-  } else {
-    const float* Ak = A + min(k0 + (t & 15), K - 1);
-#pragma unroll
-    for (int q = 0; q < 16; ++q) ra[q] = Ak[(int64_t)min((t >> 4) + 16 * q, M - 1) * lda];
-  }
-  if (!B_KC) {
-    const float* Bn = B + min(t & 127, N - 1);
-#pragma unroll
-    for (int q = 0; q < 8; ++q) rb[q] = Bn[(int64_t)min(k0 + (t >> 7) + 2 * q, K - 1) * ldb];
-  } else {
-    const float* Bk = B + min(k0 + (t & 15), K - 1);
-#pragma unroll
-    for (int q = 0; q < 8; ++q) rb[q] = Bk[(int64_t)min((t >> 4) + 16 * q, N - 1) * ldb];
-  }
-}
-
-// Stores a chunk loaded by g2_load into LDS (k-major), zeroing the entries outside the
-// M x N x K operands by a product with the in-range mask.
-template <bool A_KC, bool B_KC>
-__device__ __forceinline__ void g2_store(float* a, float* b, const float (&ra)[16], const float (&rb)[8], int M,
-                                         int N, int K, int k0) {
-  const int t = threadIdx.x;
-  if (!A_KC) {
-    const float mm = (float)(t < M);
-#pragma unroll
-    for (int q = 0; q < 16; ++q) a[q * kPA2 + t] = ra[q] * (mm * (float)(k0 + q < K));
-  } else {
-    const int k = t & 15;
-    const float mk = (float)(k0 + k < K);
-#pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int m = (t >> 4) + 16 * q;
-      a[k * kPA2 + m] = ra[q] * (mk * (float)(m < M));
-    }
-  }
-  if (!B_KC) {
-    const int nn = t & 127;
-    const float mn = (float)(nn < N);
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const int k = (t >> 7) + 2 * q;
-      b[k * kPB2 + nn] = rb[q] * (mn * (float)(k0 + k < K));
-    }
-  } else {
-    const int k = t & 15;
-    const float mk = (float)(k0 + k < K);
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const int nn = (t >> 4) + 16 * q;
-      b[k * kPB2 + nn] = rb[q] * (mk * (float)(nn < N));
-    }
-  }
-}
-
-// 16 columns k0 .. k0+15 (all < K) of rows [0, R) of a column-major operand (rows
-// contiguous) copied straight from global memory into the k-major LDS chunk (row k at
-// lds + k * pitch) by LDS-DMA loads: no registers, no LDS store instructions.  Rows >= M
-// read row M - 1; the products they feed land in output rows / columns the epilogues
-// discard.  The compiler waits for the copies before the next barrier.
-template <int R>
-__device__ __forceinline__ void g2_dma_chunk(const float* __restrict__ A, int64_t lda, int M, int k0, float* lds,
-                                             int pitch) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  if constexpr (R == kG2M) {
-    const float* Am = A + min(64 * w + lane, M - 1) + (int64_t)k0 * lda;
-#pragma unroll
-    for (int q = 0; q < kG2K; ++q)
-      __builtin_amdgcn_global_load_lds(Am + (int64_t)q * lda, lds + q * pitch + 64 * w, 4, 0, 0);
-  } else {
-    static_assert(R == kG2N, "operand tiles are 256 or 128 rows");
-    const int h = w & 1;
-    const float* An = A + min(64 * h + lane, M - 1) + (int64_t)k0 * lda;
-#pragma unroll
-    for (int q = 0; q < kG2K / 2; ++q) {
-      const int k = (w >> 1) + 2 * q;
-      __builtin_amdgcn_global_load_lds(An + (int64_t)k * lda, lds + k * pitch + 64 * h, 4, 0, 0);
-    }
-  }
-}
-
-// register path of a k-contiguous B operand (B[k + n ldb]) for a full K chunk
-__device__ __forceinline__ void g2_load_bkc(const float* __restrict__ B, int64_t ldb, int N, int K, int k0,
-                                            float (&rb)[8]) {
-  const int t = threadIdx.x;
-  const float* Bk = B + min(k0 + (t & 15), K - 1);
-#pragma unroll
-  for (int q = 0; q < 8; ++q) rb[q] = Bk[(int64_t)min((t >> 4) + 16 * q, N - 1) * ldb];
-}
-__device__ __forceinline__ void g2_store_bkc(float* b, const float (&rb)[8], int N, int K, int k0) {
-  const int t = threadIdx.x, k = t & 15;
-  const float mk = (float)(k0 + k < K);
-#pragma unroll
-  for (int q = 0; q < 8; ++q) {
-    const int nn = (t >> 4) + 16 * q;
-    b[k * kPB2 + nn] = rb[q] * (mk * (float)(nn < N));
-  }
-}
-
-// acc += A(M x K) B(N x K)^T for a 256 x 128 tile (operand conventions of gemm_tile; A is
-// column-major).  Full 16-wide K chunks of column-major operands arrive by LDS-DMA into the
-// idle buffer while the current chunk is multiplied; a k-contiguous B and the ragged last
-// chunk go through registers (clamped loads, masked LDS stores).  Rows of the result at or
-// beyond M, N are undefined.
-template <bool A_KC, bool B_KC>
-__device__ __forceinline__ void gemm_tile2(const float* __restrict__ A, int64_t lda, const float* __restrict__ B,
-                                           int64_t ldb, int M, int N, int K, f4_t (&acc)[8][4], G2Lds& S) {
-  static_assert(!A_KC, "the 256-row operand is column-major");
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int wm = (w & 1) * 128, wn = (w >> 1) * 64;
-  const int r = lane & 15, g = lane >> 4;
-  float ra[16], rb[8];
-  if (K <= 0) return;
-  if (K >= kG2K) {
-    g2_dma_chunk<kG2M>(A, lda, M, 0, S.a[0], kPA2);
-    if (!B_KC) {
-      g2_dma_chunk<kG2N>(B, ldb, N, 0, S.b[0], kPB2);
-    } else {
-      g2_load_bkc(B, ldb, N, K, 0, rb);
-      g2_store_bkc(S.b[0], rb, N, K, 0);
-    }
-  } else {
-    g2_load<false, B_KC>(A, lda, B, ldb, M, N, K, 0, ra, rb);
-    g2_store<false, B_KC>(S.a[0], S.b[0], ra, rb, M, N, K, 0);
-  }
-  __syncthreads();
-  int buf = 0;
-  for (int k0 = 0; k0 < K; k0 += kG2K) {
-    const int kn = k0 + kG2K;
-    const bool more = kn < K, full = kn + kG2K <= K;
-    if (more) {
-      if (full) {
-        g2_dma_chunk<kG2M>(A, lda, M, kn, S.a[buf ^ 1], kPA2);
-        if (!B_KC) g2_dma_chunk<kG2N>(B, ldb, N, kn, S.b[buf ^ 1], kPB2);
-        else g2_load_bkc(B, ldb, N, K, kn, rb);
-      } else {
-        g2_load<false, B_KC>(A, lda, B, ldb, M, N, K, kn, ra, rb);
-      }
-    }
-    const float* cA = S.a[buf];
-    const float* cB = S.b[buf];
-#pragma unroll
-    for (int kk = 0; kk < kG2K; kk += 4) {
-      const f4_t a0 = *reinterpret_cast<const f4_t*>(cA + (kk + g) * kPA2 + wm + 8 * r);
-      const f4_t a1 = *reinterpret_cast<const f4_t*>(cA + (kk + g) * kPA2 + wm + 8 * r + 4);
-      const f4_t b0 = *reinterpret_cast<const f4_t*>(cB + (kk + g) * kPB2 + wn + 4 * r);
-      const float a[8] = {a0[0], a0[1], a0[2], a0[3], a1[0], a1[1], a1[2], a1[3]};
-      const float b[4] = {b0[0], b0[1], b0[2], b0[3]};
-#pragma unroll
-      for (int i = 0; i < 8; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
-    }
-    if (more) {
-      if (full) {
-        if (B_KC) g2_store_bkc(S.b[buf ^ 1], rb, N, K, kn);
-      } else {
-        g2_store<false, B_KC>(S.a[buf ^ 1], S.b[buf ^ 1], ra, rb, M, N, K, kn);
-      }
-    }
-    __syncthreads();
-    buf ^= 1;
-  }
-}
-
-// Epilogue of a 256 x 128 tile through LDS, one 64-column half at a time: frow(r, c, v)
-// is called with rows fastest across the work-group, then (if COLS) fcol(r, c, v) with
-// columns fastest, so that both a column-major block and its transpose are written with
-// coalesced accesses.  Starts and ends with a barrier (the staging area aliases the
-// operand buffers).
-template <bool COLS, typename FR, typename FC>
-__device__ __forceinline__ void g2_epilogue(const f4_t (&acc)[8][4], G2Smem& sm, FR frow, FC fcol) {
-  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  const int wm = (w & 1) * 128;
-  const int r = lane & 15, g = lane >> 4;
-  for (int h = 0; h < 2; ++h) {
-    __syncthreads();
-    if ((w >> 1) == h) {
-#pragma unroll
-      for (int i = 0; i < 8; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-#pragma unroll
-          for (int q = 0; q < 4; ++q) sm.ep[4 * r + j][wm + 8 * (4 * g + q) + i] = acc[i][j][q];
-    }
-    __syncthreads();
-    for (int e = t; e < kG2M * 64; e += kThreads) {
-      const int row = e & (kG2M - 1), cl = e >> 8;
-      frow(row, 64 * h + cl, sm.ep[cl][row]);
-    }
-    if constexpr (COLS) {
-      for (int e = t; e < kG2M * 64; e += kThreads) {
-        const int cl = e & 63, row = e >> 6;
-        fcol(row, 64 * h + cl, sm.ep[cl][row]);
-      }
-    }
-  }
-  __syncthreads();
-}
-
-// F[gi + gj ld] -= C for a 256 x 128 tile (gi = row0 + r, gj = col0 + c, r < M, c < N,
-// gi >= gj), staged through LDS one 64-column half at a time; each thread loads its 64
-// old values of a half in eight batches of 8 from clamped addresses before storing.
-__device__ __forceinline__ void g2_epilogue_sub(const f4_t (&acc)[8][4], G2Smem& sm, float* F, int64_t ld,
-                                                int row0, int col0, int M, int N) {
-  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  const int wm = (w & 1) * 128;
-  const int r = lane & 15, g = lane >> 4;
-  for (int h = 0; h < 2; ++h) {
-    __syncthreads();
-    if ((w >> 1) == h) {
-#pragma unroll
-      for (int i = 0; i < 8; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-#pragma unroll
-          for (int q = 0; q < 4; ++q) sm.ep[4 * r + j][wm + 8 * (4 * g + q) + i] = acc[i][j][q];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int e0 = 0; e0 < kG2M * 64; e0 += 8 * kThreads) {
-      float old[8];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int e = e0 + u * kThreads + t;
-        const int row = min(e & (kG2M - 1), M - 1), c = min(64 * h + (e >> 8), N - 1);
-        old[u] = F[(row0 + row) + (int64_t)(col0 + c) * ld];
-      }
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int e = e0 + u * kThreads + t;
-        const int row = e & (kG2M - 1), cl = e >> 8, c = 64 * h + cl;
-        const int gi = row0 + row, gj = col0 + c;
-        if (row < M && c < N && gi >= gj) F[gi + (int64_t)gj * ld] = old[u] - sm.ep[cl][row];
-      }
-    }
-  }
-  __syncthreads();
-}
-
-// ---- FP32 256 x 256 tiles for the Sigma[R', K] products ----
-// Eight waves (2 x 4) of 128 x 64, the layout of the 256 x 128 tiles with four column
-// groups: one work-group covers the whole 256-wide outer block, so every Sigma row panel is
-// read once per K part instead of once per 128 columns.  Both operands are column-major.
 constexpr int kG4 = 256, kThreads4 = 512;
 constexpr int kPA4 = kG4 + 4;
 struct G4Lds {
-  float a[2][kG2K * kPA4];
-  float b[2][kG2K * kPA4];
+  float a[2][kG4K * kPA4];
+  float b[2][kG4K * kPA4];
 };
 union __attribute__((aligned(16))) G4Smem {
   G4Lds g;
   float ep[64][kG4 + 1];   // epilogue staging of one 64-column group
 };
 
-// LDS-DMA copy of columns k0 .. k0+15 (all < K) of rows [0, 256) (rows >= M read row M - 1):
-// wave w covers rows 64 (w & 3) .. +63 for k = (w >> 2) + 2 q
+// Columns k0 .. k0+15 (all < K) of rows [0, 256) of a column-major operand copied straight
+// from global memory into the k-major LDS chunk (row k at lds + k * kPA4) by LDS-DMA loads:
+// no registers, no LDS store instructions; wave w covers rows 64 (w & 3) .. +63 for
+// k = (w >> 2) + 2 q.  Rows >= M read row M - 1; the products they feed land in output
+// rows / columns the epilogues discard.  The compiler waits for the copies before the next
+// barrier.
 __device__ __forceinline__ void g4_dma_chunk(const float* __restrict__ A, int64_t lda, int M, int k0, float* lds) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int h = w & 3;
   const float* Am = A + min(64 * h + lane, M - 1) + (int64_t)k0 * lda;
 #pragma unroll
-  for (int q = 0; q < kG2K / 2; ++q) {
+  for (int q = 0; q < kG4K / 2; ++q) {
     const int k = (w >> 2) + 2 * q;
     __builtin_amdgcn_global_load_lds(Am + (int64_t)k * lda, lds + k * kPA4 + 64 * h, 4, 0, 0);
   }
@@ -724,7 +468,7 @@ __device__ __forceinline__ void gemm_tile4(const float* __restrict__ A, int64_t 
   const int r = lane & 15, g = lane >> 4;
   float ra[8], rb[8];
   if (K <= 0) return;
-  if (K >= kG2K) {
+  if (K >= kG4K) {
     g4_dma_chunk(A, lda, M, 0, S.a[0]);
     g4_dma_chunk(B, ldb, N, 0, S.b[0]);
   } else {
@@ -733,9 +477,9 @@ __device__ __forceinline__ void gemm_tile4(const float* __restrict__ A, int64_t 
   }
   __syncthreads();
   int buf = 0;
-  for (int k0 = 0; k0 < K; k0 += kG2K) {
-    const int kn = k0 + kG2K;
-    const bool more = kn < K, full = kn + kG2K <= K;
+  for (int k0 = 0; k0 < K; k0 += kG4K) {
+    const int kn = k0 + kG4K;
+    const bool more = kn < K, full = kn + kG4K <= K;
     if (more) {
       if (full) {
         g4_dma_chunk(A, lda, M, kn, S.a[buf ^ 1]);
@@ -747,7 +491,7 @@ __device__ __forceinline__ void gemm_tile4(const float* __restrict__ A, int64_t 
     const float* cA = S.a[buf];
     const float* cB = S.b[buf];
 #pragma unroll
-    for (int kk = 0; kk < kG2K; kk += 4) {
+    for (int kk = 0; kk < kG4K; kk += 4) {
       const f4_t a0 = *reinterpret_cast<const f4_t*>(cA + (kk + g) * kPA4 + wm + 8 * r);
       const f4_t a1 = *reinterpret_cast<const f4_t*>(cA + (kk + g) * kPA4 + wm + 8 * r + 4);
       const f4_t b0 = *reinterpret_cast<const f4_t*>(cB + (kk + g) * kPA4 + wn + 4 * r);
@@ -764,8 +508,11 @@ __device__ __forceinline__ void gemm_tile4(const float* __restrict__ A, int64_t 
   }
 }
 
-// Epilogue of a 256 x 256 tile through LDS, one 64-column group at a time, with the
-// conventions of g2_epilogue (rows fastest in frow, columns fastest in fcol).
+// Epilogue of a 256 x 256 tile through LDS, one 64-column group at a time: frow(r, c, v)
+// is called with rows fastest across the work-group, then (if COLS) fcol(r, c, v) with
+// columns fastest, so that both a column-major block and its transpose are written with
+// coalesced accesses.  Starts and ends with a barrier (the staging area aliases the
+// operand buffers).
 template <bool COLS, typename FR, typename FC>
 __device__ __forceinline__ void g4_epilogue(const f4_t (&acc)[8][4], G4Smem& sm, FR frow, FC fcol) {
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
@@ -790,6 +537,47 @@ __device__ __forceinline__ void g4_epilogue(const f4_t (&acc)[8][4], G4Smem& sm,
       for (int e = t; e < kG4 * 64; e += kThreads4) {
         const int cl = e & 63, row = e >> 6;
         fcol(row, 64 * h + cl, sm.ep[cl][row]);
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// F[gi + gj ld] -= C for a 256 x 256 tile (gi = row0 + r, gj = col0 + c, r < M, c < N,
+// gi >= gj), staged through LDS one 64-column group at a time; each thread loads the old
+// values of a group in batches of 8 from clamped addresses before storing.
+__device__ __forceinline__ void g4_epilogue_sub(const f4_t (&acc)[8][4], G4Smem& sm, float* F, int64_t ld,
+                                                int row0, int col0, int M, int N) {
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int wm = (w & 1) * 128;
+  const int r = lane & 15, g = lane >> 4;
+  for (int h = 0; h < 4; ++h) {
+    __syncthreads();
+    if ((w >> 1) == h) {
+#pragma unroll
+      for (int i = 0; i < 8; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) sm.ep[4 * r + j][wm + 8 * (4 * g + q) + i] = acc[i][j][q];
+    }
+    __syncthreads();
+    if (64 * h >= N) continue;
+#pragma unroll
+    for (int e0 = 0; e0 < kG4 * 64; e0 += 8 * kThreads4) {
+      float old[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = e0 + u * kThreads4 + t;
+        const int row = min(e & (kG4 - 1), M - 1), c = min(64 * h + (e >> 8), N - 1);
+        old[u] = F[(row0 + row) + (int64_t)(col0 + c) * ld];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = e0 + u * kThreads4 + t;
+        const int row = e & (kG4 - 1), cl = e >> 8, c = 64 * h + cl;
+        const int gi = row0 + row, gj = col0 + c;
+        if (row < M && c < N && gi >= gj) F[gi + (int64_t)gj * ld] = old[u] - sm.ep[cl][row];
       }
     }
   }
@@ -1166,9 +954,9 @@ __global__ __launch_bounds__(kThreads) void k_update(DevSym S, LaunchList L, int
 }
 
 // FP32 trailing SYRK (the update matrix: columns [p, n), K = all p pivot columns) in
-// 256 x 128 tiles: 128-wide column tiles, rows from the tile's first column down.
-__global__ __launch_bounds__(kThreads, 2) void k_syrk2(DevSym S, LaunchList L, NumBufs<float> B) {
-  __shared__ G2Smem sm;
+// 256 x 256 tiles: 256-wide column tiles, rows from the tile's first column down.
+__global__ __launch_bounds__(kThreads4, 1) void k_syrk4(DevSym S, LaunchList L, NumBufs<float> B) {
+  __shared__ G4Smem sm;
   int fi; int64_t loc;
   find_front(L, wg_id(), fi, loc);
   const int s = L.fronts[fi];
@@ -1176,21 +964,21 @@ __global__ __launch_bounds__(kThreads, 2) void k_syrk2(DevSym S, LaunchList L, N
   int ct = 0;
   int64_t r = loc;
   while (true) {
-    const int c0 = p + kG2N * ct;
+    const int c0 = p + kG4 * ct;
     if (c0 >= n) return;   // unreachable for a consistent launch list
-    const int64_t nr = (n - c0 + kG2M - 1) / kG2M;
+    const int64_t nr = (n - c0 + kG4 - 1) / kG4;
     if (r < nr) break;
     r -= nr;
     ++ct;
   }
-  const int col0 = p + kG2N * ct;
-  const int row0 = col0 + kG2M * (int)r;
-  const int M = min(kG2M, n - row0), N = min(kG2N, n - col0);
+  const int col0 = p + kG4 * ct;
+  const int row0 = col0 + kG4 * (int)r;
+  const int M = min(kG4, n - row0), N = min(kG4, n - col0);
   float* F = B.Wcur + S.Woff[s];
   f4_t acc[8][4];
   zero_acc2(acc);
-  gemm_tile2<false, false>(F + row0, n, F + col0, n, M, N, p, acc, sm.g);
-  g2_epilogue_sub(acc, sm, F, n, row0, col0, M, N);
+  gemm_tile4(F + row0, n, F + col0, n, M, N, p, acc, sm.g);
+  g4_epilogue_sub(acc, sm, F, n, row0, col0, M, N);
 }
 
 // a[u] = sum over q = 0 .. split-1, in that order, of p[q PT + e0 + u stride] (u < U):
@@ -1226,47 +1014,6 @@ __device__ __forceinline__ void sum_parts(const T* __restrict__ p, int64_t PT, i
   }
 }
 
-// F[gi + gj ld] -= C for a 256 x 256 tile (gi = row0 + r, gj = col0 + c, r < M, c < N,
-// gi >= gj), staged through LDS one 64-column group at a time; each thread loads the old
-// values of a group in batches of 8 from clamped addresses before storing.
-__device__ __forceinline__ void g4_epilogue_sub(const f4_t (&acc)[8][4], G4Smem& sm, float* F, int64_t ld,
-                                                int row0, int col0, int M, int N) {
-  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  const int wm = (w & 1) * 128;
-  const int r = lane & 15, g = lane >> 4;
-  for (int h = 0; h < 4; ++h) {
-    __syncthreads();
-    if ((w >> 1) == h) {
-#pragma unroll
-      for (int i = 0; i < 8; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-#pragma unroll
-          for (int q = 0; q < 4; ++q) sm.ep[4 * r + j][wm + 8 * (4 * g + q) + i] = acc[i][j][q];
-    }
-    __syncthreads();
-    if (64 * h >= N) continue;
-#pragma unroll
-    for (int e0 = 0; e0 < kG4 * 64; e0 += 8 * kThreads4) {
-      float old[8];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int e = e0 + u * kThreads4 + t;
-        const int row = min(e & (kG4 - 1), M - 1), c = min(64 * h + (e >> 8), N - 1);
-        old[u] = F[(row0 + row) + (int64_t)(col0 + c) * ld];
-      }
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int e = e0 + u * kThreads4 + t;
-        const int row = e & (kG4 - 1), cl = e >> 8, c = 64 * h + cl;
-        const int gi = row0 + row, gj = col0 + c;
-        if (row < M && c < N && gi >= gj) F[gi + (int64_t)gj * ld] = old[u] - sm.ep[cl][row];
-      }
-    }
-  }
-  __syncthreads();
-}
-
 // FP32 left-looking update of outer block K of the pivot panel: before its first 64-block
 // is factored, the block's columns [k2, k2 + kb2) (rows k2..n) receive
 // -L[rows, 0:k2] L[cols, 0:k2]^T from all earlier outer blocks in one long-K product
@@ -1285,7 +1032,7 @@ __global__ __launch_bounds__(kThreads4, 1) void k_panel_upd4(DevSym S, LaunchLis
   const int rt = (int)(loc / split), sp = (int)(loc % split);
   const int row0 = k2 + kG4 * rt;
   const int M = min(kG4, n - row0), N = kb2;
-  const int kpart = ((k2 + split - 1) / split + kG2K - 1) / kG2K * kG2K;
+  const int kpart = ((k2 + split - 1) / split + kG4K - 1) / kG4K * kG4K;
   const int kb = min(k2, sp * kpart), ke = min(k2, kb + kpart);
   float* F = B.Wcur + S.Woff[s];
   f4_t acc[8][4];
@@ -2206,7 +1953,7 @@ __global__ __launch_bounds__(kThreads4, 1) void k_sel_gemm4(DevSym S, LaunchList
   const int row0 = o.rs + kG4 * rt;
   const int M = min(kG4, n - row0), N = o.kb2;
   const int np = n - o.rs;
-  const int kpart = ((np + split - 1) / split + kG2K - 1) / kG2K * kG2K;
+  const int kpart = ((np + split - 1) / split + kG4K - 1) / kG4K * kG4K;
   const int kb = min(np, sp * kpart), ke = min(np, kb + kpart);
   float* Sf = B.Scur + S.Woff[s];
   const float* Y = B.Y + S.Voff[s] * kNB2;
@@ -2614,9 +2361,9 @@ void launch_panel_red4(hipStream_t st, const DevSym& S, const LaunchList& L, int
   if (L.total <= 0) return;
   hipLaunchKernelGGL(k_panel_red4, dim3((unsigned)L.total), dim3(kThreads), 0, st, S, L, K, B, part);
 }
-void launch_syrk2(hipStream_t st, const DevSym& S, const LaunchList& L, NumBufs<float> B) {
+void launch_syrk4(hipStream_t st, const DevSym& S, const LaunchList& L, NumBufs<float> B) {
   if (L.total <= 0) return;
-  hipLaunchKernelGGL(k_syrk2, dim3((unsigned)L.total), dim3(kThreads), 0, st, S, L, B);
+  hipLaunchKernelGGL(k_syrk4, dim3((unsigned)L.total), dim3(kThreads4), 0, st, S, L, B);
 }
 template <typename T> void launch_sel_part2(hipStream_t st, const DevSym& S, const LaunchList& L, int step,
                                             SelBufs<T> B) {
