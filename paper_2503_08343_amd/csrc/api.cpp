@@ -74,12 +74,12 @@ struct Level {
   std::vector<int32_t> fronts;     // sorted by column count p descending
   int nsteps = 0;
   int64_t map_begin = 0, map_end = 0;
-  int64_t wsize = 0;               // elements of the square fronts at this depth
   HostList all;                    // every front, one work-group each
   std::vector<HostList> ext;       // extend-add per child slot (tiles = child u)
   std::vector<HostList> fvec_ext;  // vector extend-add per child slot (1 per parent)
   std::vector<HostList> potrf, trsm, upd, upd_out;   // per 64-block step
   HostList syrk, copyL, inv256;
+  HostList zlow;                           // lower triangles of the fronts, 4 columns per work-group
   HostList sgather;
   int nsteps2 = 0;                                // 256-wide outer blocks of the widest front
   std::vector<HostList> fblk, fout, bpart, bblk;  // solves per outer block
@@ -497,11 +497,9 @@ gmrf_status build_plan(gmrf_t h) {
     std::stable_sort(lv.fronts.begin(), lv.fronts.end(),
                      [&](int32_t a, int32_t b) { return Y.p(a) > Y.p(b); });
     lv.nsteps = 0;
-    lv.wsize = 0;
     int maxch = 0;
     for (int32_t s : lv.fronts) {
       lv.nsteps = std::max(lv.nsteps, (Y.p(s) + nb - 1) / nb);
-      lv.wsize = std::max<int64_t>(lv.wsize, Y.Woff[s] + (int64_t)Y.nf(s) * Y.nf(s));
       maxch = std::max(maxch, Y.child_ptr[s + 1] - Y.child_ptr[s]);
     }
     auto nF = [&](int32_t s) { return (int64_t)Y.nf(s); };
@@ -699,6 +697,10 @@ gmrf_status build_plan(gmrf_t h) {
       const double p = (double)pF(s);
       return Cost{p * (double)kNB2 * (double)kNB2 / 3.0, p * (double)kNB2};
     });
+    lv.zlow = B.add(lv.fronts, [&](int32_t s) -> int64_t { return (nF(s) + 3) / 4; }, [&](int32_t s) {
+      const double n = (double)nF(s);
+      return Cost{0.0, 0.5 * n * (n + 1.0)};
+    });
     lv.copyL = B.add(lv.fronts, [&](int32_t s) -> int64_t { return pF(s); }, [&](int32_t s) {
       const double p = (double)pF(s), n = (double)nF(s);
       return Cost{0.0, 2.0 * (p * n - 0.5 * p * (p - 1.0))};
@@ -799,7 +801,7 @@ gmrf_status run_factor(gmrf_t h) {
     B.Wcur = W[d & 1];
     B.Wchild = W[(d + 1) & 1];
     B.status = h->d_status.p;
-    prof_launch(h, KC_ZERO, 0.0, (double)lv.wsize, [&] { launch_zero<T>(st, B.Wcur, lv.wsize); });
+    prof_launch(h, KC_ZERO, 0.0, lv.zlow.elems, [&] { launch_zero_lower<T>(st, S, dev_list(h, lv.zlow), B.Wcur); });
     prof_launch(h, KC_SCATTER, 0.0, 2.0 * lv.wsize_elems_scatter, [&] {
       launch_scatter<T>(st, lv.map_end - lv.map_begin, h->d_map_e.p + lv.map_begin,
                         h->d_map_off.p + lv.map_begin, h->d_qhat.p, B.Wcur);

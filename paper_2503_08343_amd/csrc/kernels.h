@@ -63,7 +63,8 @@ void launch_fill_i32(hipStream_t st, int32_t* p, int64_t n, int32_t v);
 void launch_fill_f64(hipStream_t st, double* p, int64_t n, double v);
 
 // ---- factorisation ----
-template <typename T> void launch_zero(hipStream_t st, T* p, int64_t n);
+// lower triangles (diagonal included) of the listed fronts, 4 columns per work-group
+template <typename T> void launch_zero_lower(hipStream_t st, const DevSym& S, const LaunchList& L, T* W);
 template <typename T> void launch_scatter(hipStream_t st, int64_t cnt, const int64_t* map_e,
                                           const int64_t* map_off, const double* qhat, T* W);
 template <typename T> void launch_extend_add(hipStream_t st, const DevSym& S, const LaunchList& L,

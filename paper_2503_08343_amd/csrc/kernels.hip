@@ -666,10 +666,24 @@ __global__ void k_fill(V* p, int64_t n, V v) {
     p[i] = v;
 }
 
-__global__ void k_zero16(uint4* p, int64_t n16) {
-  const uint4 z = make_uint4(0u, 0u, 0u, 0u);
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += (int64_t)gridDim.x * blockDim.x)
-    p[i] = z;
+// Zero the lower triangle (diagonal included) of every listed front: work-group = 4
+// consecutive columns.  The factorisation reads and writes only the lower triangles of the
+// fronts, and the selected inversion writes every entry it reads.
+constexpr int kZeroCols = 4;
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_zero_lower(DevSym S, LaunchList L, T* __restrict__ W) {
+  int fi; int64_t loc;
+  find_front(L, wg_id(), fi, loc);
+  const int s = L.fronts[fi];
+  const int n = fn(S, s);
+  T* F = W + S.Woff[s];
+#pragma unroll
+  for (int q = 0; q < kZeroCols; ++q) {
+    const int j = (int)loc * kZeroCols + q;
+    if (j >= n) break;
+    T* col = F + (int64_t)j * n;
+    for (int i = j + threadIdx.x; i < n; i += kThreads) col[i] = T(0);
+  }
 }
 
 template <typename T>
@@ -2162,13 +2176,9 @@ void launch_fill_f64(hipStream_t st, double* p, int64_t n, double v) {
   hipLaunchKernelGGL(k_fill<double>, dim3(grid_for(n)), dim3(kThreads), 0, st, p, n, v);
 }
 
-template <typename T> void launch_zero(hipStream_t st, T* p, int64_t n) {
-  if (n <= 0) return;
-  // 16-byte stores for the bulk (p is the start of a device allocation), then the tail
-  const int64_t bytes = n * (int64_t)sizeof(T), n16 = bytes / 16;
-  if (n16 > 0) hipLaunchKernelGGL(k_zero16, dim3(grid_for(n16, 1 << 20)), dim3(kThreads), 0, st, (uint4*)p, n16);
-  const int64_t done = n16 * 16 / (int64_t)sizeof(T);
-  if (done < n) hipLaunchKernelGGL(k_fill<T>, dim3(1), dim3(kThreads), 0, st, p + done, n - done, T(0));
+template <typename T> void launch_zero_lower(hipStream_t st, const DevSym& S, const LaunchList& L, T* W) {
+  if (L.total <= 0) return;
+  hipLaunchKernelGGL(k_zero_lower<T>, dim3((unsigned)L.total), dim3(kThreads), 0, st, S, L, W);
 }
 template <typename T> void launch_scatter(hipStream_t st, int64_t cnt, const int64_t* map_e,
                                           const int64_t* map_off, const double* qhat, T* W) {
@@ -2391,7 +2401,7 @@ template <typename T> void launch_sel_pattern(hipStream_t st, int64_t cnt, const
 
 
 #define GMRF_INST(T)                                                                                  \
-  template void launch_zero<T>(hipStream_t, T*, int64_t);                                            \
+  template void launch_zero_lower<T>(hipStream_t, const DevSym&, const LaunchList&, T*);            \
   template void launch_scatter<T>(hipStream_t, int64_t, const int64_t*, const int64_t*, const double*, T*); \
   template void launch_extend_add<T>(hipStream_t, const DevSym&, const LaunchList&, int, const T*, T*); \
   template void launch_potrf<T>(hipStream_t, const DevSym&, const LaunchList&, int, NumBufs<T>);     \
