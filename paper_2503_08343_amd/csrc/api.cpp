@@ -952,7 +952,7 @@ gmrf_status run_selinv(gmrf_t h, double* var, double* sigq) {
                 [&] { launch_sel_gather<T>(st, S, dev_list(h, lv.sgather), h->d_sparent.p, B); });
     for (int t = 0; t < lv.nsteps2; ++t) {
       prof_launch(h, KC_SEL_Y, lv.sY2[t].flops, lv.sY2[t].elems,
-                  [&] { launch_sel_Y2<T>(st, S, dev_list(h, lv.sY2[t]), t, B, h->d_D2off.p, D2); });
+                  [&] { launch_sel_Y2<T>(st, S, dev_list(h, lv.sY2[t]), t, B, h->d_D2off.p, (const T*)h->d_D2T.p); });
       const bool f32 = std::is_same<T, float>::value;
       const HostList& G = f32 ? lv.sgemm4[t] : lv.sgemm2[t];
       const HostList& R = f32 ? lv.sgred4[t] : lv.sgred[t];

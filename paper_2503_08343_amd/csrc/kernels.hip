@@ -1889,10 +1889,10 @@ __global__ __launch_bounds__(kThreads) void k_inv256(DevSym S, LaunchList L, con
 
 // X = L[R', K] Linv_KK, stored transposed: Y[c + r * 256] holds X[r, c] (r = 0 is the
 // first row of R'), so that every product reading Y takes it with its block columns
-// contiguous; 128x128 tiles
+// contiguous; 128x128 tiles, Linv_KK read through its stored transpose D2T
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_sel_Y2(DevSym S, LaunchList L, int step, SelBufs<T> B,
-                                                     const int64_t* __restrict__ D2off, const T* __restrict__ D2) {
+                                                     const int64_t* __restrict__ D2off, const T* __restrict__ D2T) {
   __shared__ __attribute__((aligned(16))) T sA[BigLds<T>::v];
   __shared__ __attribute__((aligned(16))) T sB[BigLds<T>::v];
   int fi; int64_t loc;
@@ -1904,11 +1904,11 @@ __global__ __launch_bounds__(kThreads) void k_sel_Y2(DevSym S, LaunchList L, int
   const int rt = (int)(loc / nct), ctile = (int)(loc % nct);
   const int row0 = o.rs + kBT * rt, col0 = kBT * ctile;
   const int M = min(kBT, n - row0), N = min(kBT, o.kb2 - col0);
-  const T* X = D2 + D2off[s] + (int64_t)o.K * kNB2 * kNB2;
+  const T* XT = D2T + D2off[s] + (int64_t)o.K * kNB2 * kNB2;
   typename V4<T>::type acc[4][4];
   zero_acc128<T>(acc);
-  gemm_tile128<T, false, true>(B.L + S.Loff[s] + row0 + (int64_t)o.k2 * n, n, X + (int64_t)col0 * o.kb2, o.kb2,
-                               M, N, o.kb2, acc, sA, sB);
+  gemm_tile128<T, false, false>(B.L + S.Loff[s] + row0 + (int64_t)o.k2 * n, n, XT + col0, o.kb2, M, N, o.kb2, acc,
+                                sA, sB);
   T* Y = B.Y + S.Voff[s] * kNB2;
   for_acc128<T>(acc, [&](int r, int c, T v) {
     if (r < M && c < N) Y[(col0 + c) + (int64_t)(row0 - o.rs + r) * kNB2] = v;
@@ -2030,7 +2030,8 @@ __global__ __launch_bounds__(kThreads) void k_sel_gemm_reduce(DevSym S, LaunchLi
 }
 
 // split-K partials of X^T Sigma[R', K]: work-group (front, chunk, ti, tj) computes the
-// 64x64 tile (ti, tj) over kChunk rows of R' into part + wg * 64^2
+// 64x64 tile (ti, tj) over kChunk rows of R' into part + wg * 64^2; Sigma[R', K] is read
+// through its stored mirror Sigma[K, R'] (rows contiguous)
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_sel_part2(DevSym S, LaunchList L, int step, SelBufs<T> B) {
   __shared__ T sA[kTile64Lds];
@@ -2051,8 +2052,8 @@ __global__ __launch_bounds__(kThreads) void k_sel_part2(DevSym S, LaunchList L, 
   typename V4<T>::type acc[2][2];
   zero_acc<T>(acc);
   if (kr > 0)
-    gemm_tile<T, false, true>(Y + kNB * ti + (int64_t)r0 * kNB2, kNB2,
-                              Sf + (o.rs + r0) + (int64_t)(o.k2 + kNB * tj) * n, n, M, N, kr, acc, sA, sB);
+    gemm_tile<T, false, false>(Y + kNB * ti + (int64_t)r0 * kNB2, kNB2,
+                               Sf + (o.k2 + kNB * tj) + (int64_t)(o.rs + r0) * n, n, M, N, kr, acc, sA, sB);
   T* out = B.part + wg_id() * (kNB * kNB);
   for_acc<T>(acc, [&](int r, int c, T v) { out[r + c * kNB] = v; });
 }
