@@ -283,18 +283,30 @@ constexpr int64_t kSlots128 = 256;   // 128 x 128 tiles (FP64): one resident wor
 constexpr int64_t kSlots4 = 256;     // FP32 256 x 256 tiles: one per CU
 // Fronts of one launch have different K (their |R'|): pick one part length P and split
 // every front's K into ceil(K / P) parts, so that all parts carry about the same work.
-// P minimises rounds * (P + overhead of a partial tile) over P = Kmax / S, S = 1..64, with
-// parts of at least kSplitMinK rows; the overhead of writing and summing a partial tile is
-// counted as kPartCost rows of K.
+// P minimises rounds * (P + overhead of a partial tile) over P = Kmax / S (S = 1..128) and
+// P = K_f / m for every front f (m = 1..64), with parts of at least kSplitMinK rows; the
+// overhead of writing and summing a partial tile is counted as kPartCost rows of K.
 constexpr int64_t kPartCost = 512;
 int64_t choose_part(const std::vector<std::pair<int64_t, int64_t>>& tk, int64_t slots) {
   int64_t kmax = 1;
   for (const auto& x : tk) kmax = std::max(kmax, x.second);
+  const int64_t pmin = std::min<int64_t>(kSplitMinK, kmax);
+  // candidate lengths: kmax / S and, for every front, its K / m (parts of one front equal)
+  std::vector<int64_t> cand;
+  auto push = [&](int64_t P) {
+    P = std::max<int64_t>(pmin, (P + 15) / 16 * 16);
+    if (P <= kmax) cand.push_back(P);
+  };
+  for (int64_t S = 1; S <= 128; ++S) push((kmax + S - 1) / S);
+  for (const auto& x : tk)
+    for (int64_t m = 1; m <= 64; ++m) push((x.second + m - 1) / m);
+  cand.push_back(kmax);
+  std::sort(cand.begin(), cand.end());
+  cand.erase(std::unique(cand.begin(), cand.end()), cand.end());
   int64_t best = kmax;
   double best_t = 1e300;
-  for (int64_t S = 1; S <= 64; ++S) {
-    int64_t P = (kmax + S - 1) / S;
-    P = std::max<int64_t>(std::min<int64_t>(kSplitMinK, kmax), (P + 15) / 16 * 16);
+  for (auto it = cand.rbegin(); it != cand.rend(); ++it) {   // longest first: ties keep fewer parts
+    const int64_t P = *it;
     int64_t wgs = 0;
     bool split = false;
     for (const auto& x : tk) {
@@ -307,7 +319,6 @@ int64_t choose_part(const std::vector<std::pair<int64_t, int64_t>>& tk, int64_t 
       best_t = t;
       best = P;
     }
-    if (P <= kSplitMinK) break;
   }
   return best;
 }
