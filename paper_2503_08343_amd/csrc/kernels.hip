@@ -1385,10 +1385,13 @@ __global__ __launch_bounds__(kThreads) void k_bwd_part(DevSym S, LaunchList L, i
     for (int r = 0; r < NR; ++r)
       if (r < nr) acc[r] -= V.xp[f0 + k2 + c + (int64_t)r * S.n];
   }
+  // only the block's kb2 columns are read back (small fronts have few)
   double* out = part + wg_id() * (int64_t)(kNB2 * 16);
+  if (c < kb2) {
 #pragma unroll
-  for (int r = 0; r < NR; ++r)
-    if (r < nr) out[c + r * kNB2] = acc[r];
+    for (int r = 0; r < NR; ++r)
+      if (r < nr) out[c + r * kNB2] = acc[r];
+  }
 }
 
 // Backward, diagonal block from the right: r_K = -(sum of the partials) and
@@ -1539,14 +1542,31 @@ __global__ void k_permute_out(int64_t n, int nrhs, const int32_t* __restrict__ p
   }
 }
 
+// CSR rows of Q: a group of kRowG lanes per row, lane j summing entries j, j + kRowG, ...
+// (coalesced, few dependent loads per lane), then a fixed butterfly over the group, so
+// the sum order is the same on every call.
+constexpr int kRowG = 16;
+__device__ __forceinline__ double csr_row_dot(const int64_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                                              const double* __restrict__ val, const double* __restrict__ x,
+                                              int64_t i, int j) {
+  double s = 0.0;
+  const int64_t e1 = rp[i + 1];
+  for (int64_t e = rp[i] + j; e < e1; e += kRowG) s += val[e] * x[ci[e]];
+  s += __shfl_xor(s, 8, kRowG);
+  s += __shfl_xor(s, 4, kRowG);
+  s += __shfl_xor(s, 2, kRowG);
+  s += __shfl_xor(s, 1, kRowG);
+  return s;
+}
+
 __global__ void k_resid(int64_t n, const int64_t* __restrict__ rp, const int32_t* __restrict__ ci,
                         const double* __restrict__ val, const double* __restrict__ h,
                         const double* __restrict__ x, double* __restrict__ r) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    double s = 0.0;
-    for (int64_t e = rp[i]; e < rp[i + 1]; ++e) s += val[e] * x[ci[e]];
-    r[i] = h[i] - s;
+  const int j = threadIdx.x & (kRowG - 1);
+  const int64_t gs = (int64_t)gridDim.x * blockDim.x / kRowG;
+  for (int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kRowG; i < n; i += gs) {
+    const double s = csr_row_dot(rp, ci, val, x, i, j);
+    if (j == 0) r[i] = h[i] - s;
   }
 }
 
@@ -1573,11 +1593,11 @@ __global__ void k_matern_values(int64_t nnz, const double* __restrict__ mv, cons
 
 __global__ void k_spmv(int64_t n, const int64_t* __restrict__ rp, const int32_t* __restrict__ ci,
                        const double* __restrict__ val, const double* __restrict__ x, double* __restrict__ y) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    double s = 0.0;
-    for (int64_t e = rp[i]; e < rp[i + 1]; ++e) s += val[e] * x[ci[e]];
-    y[i] = s;
+  const int j = threadIdx.x & (kRowG - 1);
+  const int64_t gs = (int64_t)gridDim.x * blockDim.x / kRowG;
+  for (int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kRowG; i < n; i += gs) {
+    const double s = csr_row_dot(rp, ci, val, x, i, j);
+    if (j == 0) y[i] = s;
   }
 }
 
@@ -2287,7 +2307,7 @@ void launch_permute_out(hipStream_t st, int64_t n, int nrhs, const int32_t* perm
 }
 void launch_resid(hipStream_t st, int64_t n, const int64_t* rp, const int32_t* ci, const double* val,
                   const double* h, const double* x, double* r) {
-  hipLaunchKernelGGL(k_resid, dim3(grid_for(n)), dim3(kThreads), 0, st, n, rp, ci, val, h, x, r);
+  hipLaunchKernelGGL(k_resid, dim3(grid_for(n * kRowG)), dim3(kThreads), 0, st, n, rp, ci, val, h, x, r);
 }
 void launch_matern_values(hipStream_t st, int64_t nnz, const double* mv, const double* sv, const double* smsv,
                           double kappa, double tau, double* q, double* dq) {
@@ -2296,7 +2316,7 @@ void launch_matern_values(hipStream_t st, int64_t nnz, const double* mv, const d
 }
 void launch_spmv(hipStream_t st, int64_t n, const int64_t* rp, const int32_t* ci, const double* val,
                  const double* x, double* y) {
-  hipLaunchKernelGGL(k_spmv, dim3(grid_for(n)), dim3(kThreads), 0, st, n, rp, ci, val, x, y);
+  hipLaunchKernelGGL(k_spmv, dim3(grid_for(n * kRowG)), dim3(kThreads), 0, st, n, rp, ci, val, x, y);
 }
 void launch_weighted_resid(hipStream_t st, int64_t m, const int64_t* arp, const int32_t* aci, const double* aval,
                            const double* qeps, const double* y, const double* b, const double* x, double* w) {
