@@ -34,7 +34,7 @@ HBM_GBS = 8000.0
 # (FETCH_SIZE, WRITE_SIZE) scaled by the same counters over a plain 1 GiB copy; valid only
 # for the kernel build they were taken on (keyed by class and precision: 1 = FP32+refine)
 PMC_TRAFFIC = {
-    ("sel_gemm", 1): {"bytes_per_launch": 3.3761e9, "kernel": "k_sel_gemm4",
+    ("sel_gemm", 1): {"bytes_per_launch": 3.3465e9, "kernel": "k_sel_gemm4",
                       "source": "profiles/sel_gemm4_advdiff128x128x64_fp32_hbm_bytes.md"},
 }
 
@@ -118,6 +118,95 @@ def cpu_baseline():
                 seconds=t)
 
 
+def secondary(binding, which, steps, warmup):
+    """The other workloads of the method at full size, timed the same way (events-free wall
+    time around synchronised steps, warm-up first): a batch of 256 Matern problems
+    (factor + log-dets + mean + 16 samples + selected inversion), Gauss-Newton on the
+    1024 x 1024 Burgers space-time problem (10 hipGraph-captured iterations), and the LML
+    with its adjoint gradient at 64^3.  Rates use the exact-pattern flops of each factor."""
+    import torch
+    import gmrf_inputs as gi
+    res = {}
+    if "c4" in which:
+        p = gi.matern_batch()
+        k = 16
+        z = torch.from_numpy(np.random.Generator(np.random.PCG64(61)).standard_normal((k, p.n))
+                             .astype(np.float32)).cuda()
+        out = {"workload": f"matern_batch: 256 problems, {p.n:,} unknowns, 16 samples each"}
+        for mname, prec in (("fp32", binding.GMRF_FP32_REFINE), ("fp64", binding.GMRF_FP64)):
+            ctx = binding.posterior_context(p, precision=prec)
+            st = ctx.stats()
+            F = st["flops_factor"] + st["flops_selinv"] + (1 + k) * st["flops_solve"]
+
+            def step():
+                ctx.factor(prec)
+                ctx.logdet()
+                ctx.solve(max_refine=30 if prec == binding.GMRF_FP32_REFINE else 0, tol=1e-12,
+                          raise_not_converged=False)
+                ctx.sample(z)
+                ctx.selinv()
+            for _ in range(warmup):
+                step()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                step()
+            torch.cuda.synchronize()
+            wall = (time.perf_counter() - t0) / steps
+            out[mname] = {"ms_per_step": round(wall * 1e3, 2), "GFLOP/s": round(F / wall / 1e9, 1),
+                          "flops_per_step": F}
+            ctx.close()
+            log(f"[bench] c4 {mname}: {wall * 1e3:.1f} ms/step")
+        res["c4_batch"] = out
+    if "c3" in which:
+        p = gi.burgers_spacetime()
+        m = p.meta
+        mass = torch.from_numpy(np.ascontiguousarray(m["mass"])).cuda()
+        s3 = torch.from_numpy(np.ascontiguousarray(m["s3"].ravel())).cuda()
+        out = {"workload": f"burgers_spacetime {m['nx']}x{m['nt']} ({p.n:,} unknowns), 10 GN iterations"}
+        for mname, prec in (("fp32", binding.GMRF_FP32_REFINE), ("fp64", binding.GMRF_FP64)):
+            ctx = binding.posterior_context(p, precision=prec)
+            st = ctx.stats()
+            ts = []
+            for rep in range(warmup + steps):
+                u = torch.zeros(p.n, dtype=torch.float64, device="cuda")
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                ctx.gn_burgers(m["nx"], m["nt"], m["dt"], m["nu"], mass, s3, u, iters=10, precision=prec,
+                               refine=8 if prec == binding.GMRF_FP32_REFINE else 1, use_graph=True)
+                torch.cuda.synchronize()
+                if rep >= warmup:
+                    ts.append(time.perf_counter() - t0)
+            wall = float(np.mean(ts))
+            out[mname] = {"ms_per_10_iterations": round(wall * 1e3, 2),
+                          "factor_GFLOP/s": round(10 * st["flops_factor"] / wall / 1e9, 1)}
+            ctx.close()
+            log(f"[bench] c3 {mname}: {wall * 1e3:.1f} ms for 10 iterations")
+        res["c3_gauss_newton"] = out
+    if "c5" in which:
+        import math
+        from paper_2503_08343_amd import adjoint
+        p = gi.matern3d()
+        pieces = gi.matern_pieces(p)
+        eng = adjoint.MaternLML(p.Q.indptr, p.Q.indices, *pieces, p.A, p.y, p.b, p.coords,
+                                precision=binding.GMRF_FP64)
+        th = (math.log(10.0), 0.0, math.log(0.05))
+        ts = []
+        for rep in range(warmup + steps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            eng.evaluate(*th)
+            torch.cuda.synchronize()
+            if rep >= warmup:
+                ts.append(time.perf_counter() - t0)
+        wall = float(np.mean(ts))
+        res["c5_lml_gradient"] = {"workload": f"matern3d 64^3 ({p.n:,} unknowns), 5000 points, FP64",
+                                  "ms_per_evaluation": round(wall * 1e3, 2)}
+        eng.close()
+        log(f"[bench] c5: {wall * 1e3:.1f} ms per LML + gradient")
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -126,6 +215,9 @@ def main():
     ap.add_argument("--small", action="store_true", help="16k-dof workload (debugging only)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--modes", default="fp32,fp64")
+    ap.add_argument("--configs", default="c2",
+                    help="c2 (the headline workload) plus any of c3 (Gauss-Newton), c4 (batch), "
+                         "c5 (LML gradient), reported under 'secondary'")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run three 1 GiB device-to-device copies (scale for HBM byte counters)")
     args = ap.parse_args()
@@ -238,6 +330,9 @@ def main():
         log("[bench] cpu baseline (oracle on a bounded sample)")
         out["cpu_baseline"] = cpu_baseline()
     ctx.close()
+    which = [c.strip() for c in args.configs.split(",")]
+    if any(c in which for c in ("c3", "c4", "c5")):
+        out["secondary"] = secondary(binding, which, args.steps, args.warmup)
     print(json.dumps(out))
 
 
