@@ -515,6 +515,8 @@ gmrf_status build_plan(gmrf_t h) {
     }
     auto nF = [&](int32_t s) { return (int64_t)Y.nf(s); };
     auto pF = [&](int32_t s) { return (int64_t)Y.p(s); };
+    // fronts of at most kNB rows are factored whole by the diagonal-block kernel
+    auto small = [&](int32_t s) { return nF(s) <= (int64_t)kNB; };
     lv.all = B.add(lv.fronts, [](int32_t) { return (int64_t)1; },
                    [&](int32_t s) { return Cost{0.0, (double)pF(s) + (double)nF(s)}; });
     for (int c = 0; c < maxch; ++c) {
@@ -536,10 +538,16 @@ gmrf_status build_plan(gmrf_t h) {
       lv.potrf.push_back(B.add(lv.fronts, [&](int32_t s) -> int64_t { return active(s) ? 1 : 0; },
                                [&](int32_t s) {
                                  const double b3 = (double)kb(s);
+                                 if (small(s)) {
+                                   const double r = below(s), nn = (double)nF(s);
+                                   const Cost u = nF(s) > pF(s) ? upd_cost(nF(s), pF(s), 2, 0) : Cost{0.0, 0.0};
+                                   return Cost{2.0 * b3 * b3 * b3 / 3.0 + r * b3 * b3 + u.flops,
+                                               nn * (nn + 1.0) + b3 * b3};
+                                 }
                                  return Cost{2.0 * b3 * b3 * b3 / 3.0, 3.0 * b3 * b3};
                                }));
       lv.trsm.push_back(B.add(lv.fronts, [&](int32_t s) -> int64_t {
-        if (!active(s)) return 0;
+        if (!active(s) || small(s)) return 0;
         const int64_t rows = nF(s) - k0 - kb(s);
         return (rows + kTile - 1) / kTile;
       }, [&](int32_t s) {
@@ -547,7 +555,7 @@ gmrf_status build_plan(gmrf_t h) {
         return Cost{r * b * b, 2.0 * r * b + b * b};
       }));
       lv.upd.push_back(B.add(lv.fronts, [&](int32_t s) -> int64_t {
-        if (!active(s)) return 0;
+        if (!active(s) || small(s)) return 0;
         return upd_tiles(nF(s), pF(s), 0, k, kTile);
       }, [&](int32_t s) { return upd_cost(nF(s), pF(s), 0, k); }));
       const bool outer_here = (k + 1) % (kNB2 / nb) == 0;
@@ -699,11 +707,11 @@ gmrf_status build_plan(gmrf_t h) {
                                [&](int32_t s) { const double b = (double)okb2(s); return Cost{b * b * b / 3.0, 2.0 * b * b}; }));
     }
     lv.syrk = B.add(lv.fronts, [&](int32_t s) -> int64_t {
-      return nF(s) > pF(s) ? upd_tiles(nF(s), pF(s), 2, 0, kBigTile) : 0;
-    }, [&](int32_t s) { return upd_cost(nF(s), pF(s), 2, 0); });
+      return nF(s) > pF(s) && !small(s) ? upd_tiles(nF(s), pF(s), 2, 0, kBigTile) : 0;
+    }, [&](int32_t s) { return small(s) ? Cost{0.0, 0.0} : upd_cost(nF(s), pF(s), 2, 0); });
     lv.syrk3 = B.add(lv.fronts, [&](int32_t s) -> int64_t {
-      return nF(s) > pF(s) ? upd_tiles(nF(s), pF(s), 2, 0, 256, 256) : 0;
-    }, [&](int32_t s) { return upd_cost(nF(s), pF(s), 2, 0); });
+      return nF(s) > pF(s) && !small(s) ? upd_tiles(nF(s), pF(s), 2, 0, 256, 256) : 0;
+    }, [&](int32_t s) { return small(s) ? Cost{0.0, 0.0} : upd_cost(nF(s), pF(s), 2, 0); });
     lv.inv256 = B.add(lv.fronts, [&](int32_t s) -> int64_t { return (pF(s) + nb - 1) / nb; }, [&](int32_t s) {
       const double p = (double)pF(s);
       return Cost{p * (double)kNB2 * (double)kNB2 / 3.0, p * (double)kNB2};
@@ -837,8 +845,9 @@ gmrf_status run_factor(gmrf_t h) {
       }
       prof_launch(h, KC_POTRF, lv.potrf[k].flops, lv.potrf[k].elems,
                   [&] { launch_potrf<T>(st, S, dev_list(h, lv.potrf[k]), k, B); });
-      prof_launch(h, KC_TRSM, lv.trsm[k].flops, lv.trsm[k].elems,
-                  [&] { launch_trsm<T>(st, S, dev_list(h, lv.trsm[k]), k, B); });
+      if (lv.trsm[k].total > 0)
+        prof_launch(h, KC_TRSM, lv.trsm[k].flops, lv.trsm[k].elems,
+                    [&] { launch_trsm<T>(st, S, dev_list(h, lv.trsm[k]), k, B); });
       if (lv.upd[k].total > 0)
         prof_launch(h, KC_UPDATE, lv.upd[k].flops, lv.upd[k].elems,
                     [&] { launch_update<T>(st, S, dev_list(h, lv.upd[k]), k, 0, B); });

@@ -388,124 +388,156 @@ __device__ __forceinline__ void zero_acc128(typename V4<T>::type (&acc)[4][4]) {
 
 // ---- FP32 256 x 256 tiles for the long-K products (Sigma[R', K], the left-looking panel
 // update, the trailing SYRK) ----
-// Eight waves (2 x 4) with 128 x 64 wave tiles of 8 x 4 MFMA 16x16x4 blocks.  Row i' of
-// block i is tile row 8 i' + i and column c' of block j is tile column 4 c' + j, so that a
-// lane's eight A values (four B values) of one k are contiguous in LDS and arrive in 128-bit
-// reads.  Operands are staged k-major in 16-wide K chunks, double-buffered.  One work-group
-// covers a whole 256-wide outer block, so every row panel is read once per K part.  Both
-// operands are column-major.
-typedef float f4_t __attribute__((ext_vector_type(4)));
+// FP32 products on the bf16 matrix cores.  Each FP32 operand value x is split into three
+// bf16 terms x = h + m + l, each the round-to-nearest of what the earlier terms leave, so
+// that the residue is below 2^-24 |x|.  A product a b is accumulated in FP32 as the six
+// term products of relative order 2^-16 or more (m m, l h, h l, m h, h m, h h, smallest
+// first); the three dropped ones are below 2^-24 |a b|.  The result carries the error of
+// an FP32 dot product (measured against FP64 dot products it is no larger than that of
+// the FP32 16x16x4 MFMA).  For a 32 x 32 x 16 block this takes six 32x32x16 bf16 MFMAs
+// instead of sixteen 16x16x4 FP32 ones of the same pass count: 8/3 fewer matrix-core
+// cycles.
+// Eight waves (2 x 4) with 128 x 64 wave tiles of 4 x 2 blocks of 32 x 32.  Operands are
+// staged in 16-wide K chunks, row-major in LDS: a row holds the h, m and l planes of its
+// 16 k values (32 bytes each) plus 16 bytes of padding, so a lane's eight k values of one
+// plane are one 128-bit read and the 64 lanes of a read fall in distinct bank groups.
+// Thread t converts row t & 255, k values 8 (t >> 8) .. +7 of both operands (the
+// transpose of the column-major operands happens in registers).  Two LDS buffers; the
+// registers run one chunk ahead, so that the split of chunk c + 1 into the idle buffer
+// and the loads of chunk c + 2 overlap the MFMAs of chunk c.  One work-group covers a
+// whole 256-wide outer block, so every row panel is read once per K part.
+typedef __bf16 bf8_t __attribute__((ext_vector_type(8)));
+typedef float f16v_t __attribute__((ext_vector_type(16)));
 constexpr int kG4K = 16;   // K chunk
+constexpr int kG4 = 256, kThreads4 = 512;
+constexpr int kRec4 = 7;   // 16-byte units per LDS row: 3 planes x 2 k halves + padding
 
-__device__ __forceinline__ void zero_acc2(f4_t (&acc)[8][4]) {
+__device__ __forceinline__ void zero_acc6(f16v_t (&acc)[4][2]) {
 #pragma unroll
-  for (int i = 0; i < 8; ++i)
+  for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = f4_t{0.f, 0.f, 0.f, 0.f};
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
 }
 
-constexpr int kG4 = 256, kThreads4 = 512;
-constexpr int kPA4 = kG4 + 4;
 struct G4Lds {
-  float a[2][kG4K * kPA4];
-  float b[2][kG4K * kPA4];
+  uint4 a[2][kG4 * kRec4];
+  uint4 b[2][kG4 * kRec4];
 };
 union __attribute__((aligned(16))) G4Smem {
   G4Lds g;
   float ep[64][kG4 + 1];   // epilogue staging of one 64-column group
 };
 
-// Columns k0 .. k0+15 (all < K) of rows [0, 256) of a column-major operand copied straight
-// from global memory into the k-major LDS chunk (row k at lds + k * kPA4) by LDS-DMA loads:
-// no registers, no LDS store instructions; wave w covers rows 64 (w & 3) .. +63 for
-// k = (w >> 2) + 2 q.  Rows >= M read row M - 1; the products they feed land in output
-// rows / columns the epilogues discard.  The compiler waits for the copies before the next
-// barrier.
-__device__ __forceinline__ void g4_dma_chunk(const float* __restrict__ A, int64_t lda, int M, int k0, float* lds) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int h = w & 3;
-  const float* Am = A + min(64 * h + lane, M - 1) + (int64_t)k0 * lda;
+__device__ __forceinline__ void split3_bf16(const float (&x)[8], uint4& h, uint4& m, uint4& l) {
+  bf8_t vh, vm, vl;
 #pragma unroll
-  for (int q = 0; q < kG4K / 2; ++q) {
-    const int k = (w >> 2) + 2 * q;
-    __builtin_amdgcn_global_load_lds(Am + (int64_t)k * lda, lds + k * kPA4 + 64 * h, 4, 0, 0);
+  for (int q = 0; q < 8; ++q) {
+    const __bf16 a = (__bf16)x[q];
+    const float r1 = x[q] - (float)a;
+    const __bf16 b = (__bf16)r1;
+    vh[q] = a;
+    vm[q] = b;
+    vl[q] = (__bf16)(r1 - (float)b);
   }
+  h = __builtin_bit_cast(uint4, vh);
+  m = __builtin_bit_cast(uint4, vm);
+  l = __builtin_bit_cast(uint4, vl);
 }
 
-// register path of a ragged last chunk: thread t holds row t & 255 of k = (t >> 8) + 2 q
+// row t & 255 (clamped to M - 1, N - 1: the products of such rows land in output rows /
+// columns the epilogues discard), k = k0 + 8 (t >> 8) .. +7 clamped to K - 1
 __device__ __forceinline__ void g4_load(const float* __restrict__ A, int64_t lda, const float* __restrict__ B,
                                         int64_t ldb, int M, int N, int K, int k0, float (&ra)[8], float (&rb)[8]) {
   const int t = threadIdx.x;
   const float* Am = A + min(t & 255, M - 1);
   const float* Bn = B + min(t & 255, N - 1);
+  const int kb = k0 + 8 * (t >> 8);
 #pragma unroll
   for (int q = 0; q < 8; ++q) {
-    const int64_t k = min(k0 + (t >> 8) + 2 * q, K - 1);
+    const int64_t k = min(kb + q, K - 1);
     ra[q] = Am[k * lda];
     rb[q] = Bn[k * ldb];
   }
 }
-__device__ __forceinline__ void g4_store(float* a, float* b, const float (&ra)[8], const float (&rb)[8], int M, int N,
-                                         int K, int k0) {
-  const int t = threadIdx.x, m = t & 255;
-  const float mm = (float)(m < M), mn = (float)(m < N);
+// zero the k >= K values of chunk k0, split, store into LDS buffer (a, b)
+__device__ __forceinline__ void g4_store(uint4* a, uint4* b, float (&ra)[8], float (&rb)[8], int K, int k0) {
+  const int t = threadIdx.x, kb = k0 + 8 * (t >> 8);
 #pragma unroll
   for (int q = 0; q < 8; ++q) {
-    const int k = (t >> 8) + 2 * q;
-    const float mk = (float)(k0 + k < K);
-    a[k * kPA4 + m] = ra[q] * (mm * mk);
-    b[k * kPA4 + m] = rb[q] * (mn * mk);
+    const bool ok = kb + q < K;
+    ra[q] = ok ? ra[q] : 0.f;
+    rb[q] = ok ? rb[q] : 0.f;
   }
+  const int u = (t & 255) * kRec4 + (t >> 8);
+  uint4 h, m, l;
+  split3_bf16(ra, h, m, l);
+  a[u] = h; a[u + 2] = m; a[u + 4] = l;
+  split3_bf16(rb, h, m, l);
+  b[u] = h; b[u + 2] = m; b[u + 4] = l;
 }
 
-// acc += A(M x K) B(N x K)^T for a 256 x 256 tile, both operands column-major; full K
-// chunks by LDS-DMA into the idle buffer, a ragged last chunk through registers.  Rows and
-// columns of the result at or beyond M, N are undefined.
+__device__ __forceinline__ f16v_t mfma_bf16(uint4 a, uint4 b, f16v_t c) {
+  return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf8_t, a), __builtin_bit_cast(bf8_t, b), c,
+                                                0, 0, 0);
+}
+
+// acc += A(M x K) B(N x K)^T for a 256 x 256 tile, both operands column-major.  Rows and
+// columns of the result at or beyond M, N are undefined.  Lane l of a wave holds, for
+// block (i, j), rows wm + 32 i + 8 (r >> 2) + 4 (l >> 5) + (r & 3) of column
+// wn + 32 j + (l & 31) in acc[i][j][r].
 __device__ __forceinline__ void gemm_tile4(const float* __restrict__ A, int64_t lda, const float* __restrict__ B,
-                                           int64_t ldb, int M, int N, int K, f4_t (&acc)[8][4], G4Lds& S) {
+                                           int64_t ldb, int M, int N, int K, f16v_t (&acc)[4][2], G4Lds& S) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int wm = (w & 1) * 128, wn = (w >> 1) * 64;
-  const int r = lane & 15, g = lane >> 4;
+  const int rl = lane & 31, kh = lane >> 5;
   float ra[8], rb[8];
   if (K <= 0) return;
-  if (K >= kG4K) {
-    g4_dma_chunk(A, lda, M, 0, S.a[0]);
-    g4_dma_chunk(B, ldb, N, 0, S.b[0]);
-  } else {
-    g4_load(A, lda, B, ldb, M, N, K, 0, ra, rb);
-    g4_store(S.a[0], S.b[0], ra, rb, M, N, K, 0);
-  }
+  g4_load(A, lda, B, ldb, M, N, K, 0, ra, rb);
+  g4_store(S.a[0], S.b[0], ra, rb, K, 0);
+  g4_load(A, lda, B, ldb, M, N, K, kG4K, ra, rb);
   __syncthreads();
   int buf = 0;
   for (int k0 = 0; k0 < K; k0 += kG4K) {
-    const int kn = k0 + kG4K;
-    const bool more = kn < K, full = kn + kG4K <= K;
-    if (more) {
-      if (full) {
-        g4_dma_chunk(A, lda, M, kn, S.a[buf ^ 1]);
-        g4_dma_chunk(B, ldb, N, kn, S.b[buf ^ 1]);
-      } else {
-        g4_load(A, lda, B, ldb, M, N, K, kn, ra, rb);
-      }
-    }
-    const float* cA = S.a[buf];
-    const float* cB = S.b[buf];
+    const uint4* cA = S.a[buf];
+    const uint4* cB = S.b[buf];
+    uint4 bf[2][3], af[4][3];
 #pragma unroll
-    for (int kk = 0; kk < kG4K; kk += 4) {
-      const f4_t a0 = *reinterpret_cast<const f4_t*>(cA + (kk + g) * kPA4 + wm + 8 * r);
-      const f4_t a1 = *reinterpret_cast<const f4_t*>(cA + (kk + g) * kPA4 + wm + 8 * r + 4);
-      const f4_t b0 = *reinterpret_cast<const f4_t*>(cB + (kk + g) * kPA4 + wn + 4 * r);
-      const float a[8] = {a0[0], a0[1], a0[2], a0[3], a1[0], a1[1], a1[2], a1[3]};
-      const float b[4] = {b0[0], b0[1], b0[2], b0[3]};
+    for (int j = 0; j < 2; ++j)
 #pragma unroll
-      for (int i = 0; i < 8; ++i)
+      for (int p = 0; p < 3; ++p) bf[j][p] = cB[(wn + 32 * j + rl) * kRec4 + 2 * p + kh];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
-    }
-    if (more && !full) g4_store(S.a[buf ^ 1], S.b[buf ^ 1], ra, rb, M, N, K, kn);
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int p = 0; p < 3; ++p) af[i][p] = cA[(wm + 32 * i + rl) * kRec4 + 2 * p + kh];
+    // chunk k0 + 16 into the idle buffer (all zero beyond K), then fetch chunk k0 + 32
+    g4_store(S.a[buf ^ 1], S.b[buf ^ 1], ra, rb, K, k0 + kG4K);
+    g4_load(A, lda, B, ldb, M, N, K, k0 + 2 * kG4K, ra, rb);
+    constexpr int PA[6] = {1, 2, 0, 1, 0, 0}, PB[6] = {1, 0, 2, 0, 1, 0};
+#pragma unroll
+    for (int q = 0; q < 6; ++q)
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = mfma_bf16(af[i][PA[q]], bf[j][PB[q]], acc[i][j]);
     __syncthreads();
     buf ^= 1;
   }
+}
+
+// columns 64 h .. 64 h + 63 of the tile into sm.ep[column - 64 h][row] (waves w >> 1 == h)
+__device__ __forceinline__ void g4_stage(const f16v_t (&acc)[4][2], G4Smem& sm, int h) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if ((w >> 1) != h) return;
+  const int wm = (w & 1) * 128;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r)
+        sm.ep[32 * j + (lane & 31)][wm + 32 * i + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3)] = acc[i][j][r];
 }
 
 // Epilogue of a 256 x 256 tile through LDS, one 64-column group at a time: frow(r, c, v)
@@ -514,20 +546,11 @@ __device__ __forceinline__ void gemm_tile4(const float* __restrict__ A, int64_t 
 // coalesced accesses.  Starts and ends with a barrier (the staging area aliases the
 // operand buffers).
 template <bool COLS, typename FR, typename FC>
-__device__ __forceinline__ void g4_epilogue(const f4_t (&acc)[8][4], G4Smem& sm, FR frow, FC fcol) {
-  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  const int wm = (w & 1) * 128;
-  const int r = lane & 15, g = lane >> 4;
+__device__ __forceinline__ void g4_epilogue(const f16v_t (&acc)[4][2], G4Smem& sm, FR frow, FC fcol) {
+  const int t = threadIdx.x;
   for (int h = 0; h < 4; ++h) {
     __syncthreads();
-    if ((w >> 1) == h) {
-#pragma unroll
-      for (int i = 0; i < 8; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-#pragma unroll
-          for (int q = 0; q < 4; ++q) sm.ep[4 * r + j][wm + 8 * (4 * g + q) + i] = acc[i][j][q];
-    }
+    g4_stage(acc, sm, h);
     __syncthreads();
     for (int e = t; e < kG4 * 64; e += kThreads4) {
       const int row = e & (kG4 - 1), cl = e >> 8;
@@ -546,21 +569,12 @@ __device__ __forceinline__ void g4_epilogue(const f4_t (&acc)[8][4], G4Smem& sm,
 // F[gi + gj ld] -= C for a 256 x 256 tile (gi = row0 + r, gj = col0 + c, r < M, c < N,
 // gi >= gj), staged through LDS one 64-column group at a time; each thread loads the old
 // values of a group in batches of 8 from clamped addresses before storing.
-__device__ __forceinline__ void g4_epilogue_sub(const f4_t (&acc)[8][4], G4Smem& sm, float* F, int64_t ld,
+__device__ __forceinline__ void g4_epilogue_sub(const f16v_t (&acc)[4][2], G4Smem& sm, float* F, int64_t ld,
                                                 int row0, int col0, int M, int N) {
-  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  const int wm = (w & 1) * 128;
-  const int r = lane & 15, g = lane >> 4;
+  const int t = threadIdx.x;
   for (int h = 0; h < 4; ++h) {
     __syncthreads();
-    if ((w >> 1) == h) {
-#pragma unroll
-      for (int i = 0; i < 8; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-#pragma unroll
-          for (int q = 0; q < 4; ++q) sm.ep[4 * r + j][wm + 8 * (4 * g + q) + i] = acc[i][j][q];
-    }
+    g4_stage(acc, sm, h);
     __syncthreads();
     if (64 * h >= N) continue;
 #pragma unroll
@@ -850,6 +864,10 @@ __global__ __launch_bounds__(kThreads) void k_potrf(DevSym S, LaunchList L, int 
   const int n = fn(S, s), p = fp(S, s);
   const int k0 = step * kNB;
   const int kb = min(kNB, p - k0);
+  // a front of at most 64 rows is factored whole: its kb = p pivots are taken and the
+  // rest of the block receives their update, so the panel below the diagonal block and
+  // the update matrix come out of the same registers (no separate TRSM or SYRK)
+  const int nbk = (step == 0 && n <= kNB) ? n : kb;
   T* F = B.Wcur + S.Woff[s];
   const int t = threadIdx.x, ti = t & 15, tl = t >> 4;
   double a_r[4][4], x_r[4][4];
@@ -858,8 +876,8 @@ __global__ __launch_bounds__(kThreads) void k_potrf(DevSym S, LaunchList L, int 
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
       const int i = ti + 16 * a, l = tl + 16 * b;
-      const double v = (double)F[(k0 + min(i, kb - 1)) + (int64_t)(k0 + min(l, kb - 1)) * n];
-      a_r[a][b] = (i < kb && l < kb && i >= l) ? v : 0.0;
+      const double v = (double)F[(k0 + min(i, nbk - 1)) + (int64_t)(k0 + min(l, nbk - 1)) * n];
+      a_r[a][b] = (i < nbk && l < nbk && i >= l) ? v : 0.0;
       x_r[a][b] = i == l ? 1.0 : 0.0;
     }
   if (t == 0) fail = INT_MAX;
@@ -876,7 +894,7 @@ __global__ __launch_bounds__(kThreads) void k_potrf(DevSym S, LaunchList L, int 
     for (int b = 0; b < 4; ++b) {
       const int i = ti + 16 * a, l = tl + 16 * b;
       const bool in = i < kb && l < kb && i >= l;
-      if (in) F[(k0 + i) + (int64_t)(k0 + l) * n] = (T)a_r[a][b];
+      if (i < nbk && l < nbk && i >= l) F[(k0 + i) + (int64_t)(k0 + l) * n] = (T)a_r[a][b];
       Dblk[i + l * kNB] = in ? (T)x_r[a][b] : T(0);
       if (in && i == l) B.piv[S.sfirst[s] + k0 + i] = a_r[a][b];
     }
@@ -989,8 +1007,8 @@ __global__ __launch_bounds__(kThreads4, 1) void k_syrk4(DevSym S, LaunchList L, 
   const int row0 = col0 + kG4 * (int)r;
   const int M = min(kG4, n - row0), N = min(kG4, n - col0);
   float* F = B.Wcur + S.Woff[s];
-  f4_t acc[8][4];
-  zero_acc2(acc);
+  f16v_t acc[4][2];
+  zero_acc6(acc);
   gemm_tile4(F + row0, n, F + col0, n, M, N, p, acc, sm.g);
   g4_epilogue_sub(acc, sm, F, n, row0, col0, M, N);
 }
@@ -1049,8 +1067,8 @@ __global__ __launch_bounds__(kThreads4, 1) void k_panel_upd4(DevSym S, LaunchLis
   const int kpart = ((k2 + split - 1) / split + kG4K - 1) / kG4K * kG4K;
   const int kb = min(k2, sp * kpart), ke = min(k2, kb + kpart);
   float* F = B.Wcur + S.Woff[s];
-  f4_t acc[8][4];
-  zero_acc2(acc);
+  f16v_t acc[4][2];
+  zero_acc6(acc);
   gemm_tile4(F + row0 + (int64_t)kb * n, n, F + k2 + (int64_t)kb * n, n, M, N, ke - kb, acc, sm.g);
   if (split == 1) {
     g4_epilogue_sub(acc, sm, F, n, row0, k2, M, N);
@@ -1991,8 +2009,8 @@ __global__ __launch_bounds__(kThreads4, 1) void k_sel_gemm4(DevSym S, LaunchList
   const int kb = min(np, sp * kpart), ke = min(np, kb + kpart);
   float* Sf = B.Scur + S.Woff[s];
   const float* Y = B.Y + S.Voff[s] * kNB2;
-  f4_t acc[8][4];
-  zero_acc2(acc);
+  f16v_t acc[4][2];
+  zero_acc6(acc);
   gemm_tile4(Sf + row0 + (int64_t)(o.rs + kb) * n, n, Y + (int64_t)kb * kNB2, kNB2, M, N, ke - kb, acc, sm.g);
   if (split == 1) {
     g4_epilogue<true>(acc, sm, [&](int r, int c, float v) {
