@@ -37,7 +37,10 @@ HBM_GBS = 8000.0
 # HBM bytes per launch of the dominant kernel class, from two rocprofv3 counter passes
 # (FETCH_SIZE, WRITE_SIZE) scaled by the same counters over a plain 1 GiB copy; valid only
 # for the kernel build they were taken on (keyed by class and precision: 1 = FP32+refine)
-PMC_TRAFFIC = {}
+PMC_TRAFFIC = {
+    ("sel_gemm", 1): {"bytes_per_launch": 3.3455e9, "kernel": "k_sel_gemm4",
+                      "source": "profiles/sel_gemm4_advdiff128x128x64_fp32_hbm_bytes.md"},
+}
 
 
 def log(*a):
