@@ -303,8 +303,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f32" if head == "fp32" else "f64",
         "data": "synthetic",
-        "config": {"workload": wname, "mode": "FP32 factor/selinv + FP64 pivots, log-det and refinement"
-                   if head == "fp32" else "FP64", "nnz_L": st["nnz_l"], "flops_per_step": F,
+        "config": {"workload": wname, "mode": "FP32 factor/selinv (long FP32 products as six bf16 MFMA term "
+                   "products) + FP64 pivots, log-det and refinement" if head == "fp32" else "FP64", "nnz_L": st["nnz_l"], "flops_per_step": F,
                    "flops_factor": st["flops_factor"], "flops_selinv": st["flops_selinv"],
                    "flops_solve": st["flops_solve"], "max_front": st["max_front"],
                    "analyze_s": round(t_an, 2)},

@@ -36,12 +36,22 @@ CASES_FP64 = {
 }
 
 
+_ORACLE = {}
+
+
+def _oracle(name):
+    """oracle posterior of a named case, computed once per test session"""
+    if name not in _ORACLE:
+        p = CASES_FP64[name]()
+        _ORACLE[name] = (p, O.posterior(p))
+    return _ORACLE[name]
+
+
 @pytest.mark.parametrize("name", sorted(CASES_FP64))
 def test_fp64_mean_var_logdet_match_oracle(gpu_lib, name):
-    p = CASES_FP64[name]()
+    p, r = _oracle(name)
     print(f"[case] {name} n={p.n}", flush=True)
     ctx, ld, mu, var, _, res = _run(gpu_lib, p, gpu_lib.GMRF_FP64)
-    r = O.posterior(p)
     assert _rel(mu, r["mean"]) <= 1e-10, _rel(mu, r["mean"])
     vrel = np.max(np.abs(var - r["var"]) / r["var"])
     assert vrel <= 1e-10, vrel
@@ -50,6 +60,25 @@ def test_fp64_mean_var_logdet_match_oracle(gpu_lib, name):
     st = ctx.stats()
     assert st["failed_index"] == -1
     assert res < 1e-12
+    ctx.close()
+
+
+# FP32 factor / selected inversion (long products as six bf16 term products on the matrix
+# cores) on the cases with multi-block fronts and ragged tails: mean within 1e-8 after FP64
+# refinement, variances and log-det within the first-order bound of FP32 rounding
+@pytest.mark.parametrize("name", ["matern2d_45_ragged", "matern3d_12", "spacetime_24x24x16_multiblock"])
+def test_fp32_refine_matches_oracle(gpu_lib, name):
+    p, r = _oracle(name)
+    print(f"[case fp32] {name} n={p.n}", flush=True)
+    ctx, ld, mu, var, it, res = _run(gpu_lib, p, gpu_lib.GMRF_FP32_REFINE, refine=30, tol=1e-14)
+    vrel = float(np.max(np.abs(var - r["var"]) / r["var"]))
+    ldrel = abs(ld[0] - r["logdet"]) / abs(r["logdet"])
+    print(f"[case fp32] {name}: iters={it} resid={res:.3e} mean {_rel(mu, r['mean']):.3e} "
+          f"var {vrel:.3e} logdet {ldrel:.3e}", flush=True)
+    assert _rel(mu, r["mean"]) <= 1e-8
+    assert vrel <= 5e-3
+    assert ldrel <= 1e-5
+    assert ctx.stats()["failed_index"] == -1
     ctx.close()
 
 
