@@ -1,7 +1,8 @@
 """Pins of the oracle against facts fixed by the paper and by the mathematics, not by
 the oracle itself: dense inverse / eigenvalue log-det on tiny grids, closed forms of
 the 1-node space-time prior (random walk and AR(1)), the state-space log-det identity
-of the block-tridiagonal prior (App. A), the Matern log-det through a factorisation of
+of the block-tridiagonal prior (App. A), Kalman filtering + RTS smoothing of the same
+state-space model, the Matern log-det through a factorisation of
 K, trace identities, the covariance (Woodbury) form of conditioning, sample
 identities, ordering invariance and structural invariants."""
 import math
@@ -176,6 +177,57 @@ def test_P7_sample_covariance_monte_carlo():
     ref = np.linalg.inv(Qp.toarray())
     se = np.sqrt((np.outer(np.diag(ref), np.diag(ref)) + ref**2) / n_draw)
     assert np.max(np.abs(C - ref) / se) < 6.0
+
+
+@pytest.mark.parametrize("seed", [81, 82])
+def test_P8_kalman_rts_smoother(seed):
+    """The space-time GMRF is the precision form of a linear-Gaussian state-space model
+    (Sec. 2.4, App. A): u_1 ~ N(0, Q1^-1), u_(k+1) = A u_k + e_k, e_k ~ N(0, F) with
+    A = G^-1 M~ and F = tau^2 dt G^-1 M~ Sigma M~ G^-T (white noise in space: Sigma = M~^-1).
+    With point data on single slices, a Kalman filter followed by the Rauch-Tung-Striebel
+    smoother, run densely slice by slice, gives the posterior mean and marginal variances
+    without the block-tridiagonal precision, its factorisation or the Takahashi recursion."""
+    p = gi.advdiff_spacetime(ns=5, nt=6, obs_frac=0.3, pde_rows=False, seed=seed)
+    meta = p.meta
+    ns, nt, dt, tau = meta["mesh"].n, meta["nt"], meta["dt"], meta["tau"]
+    G = meta["G"].toarray()
+    M = np.diag(meta["m"])
+    At = np.linalg.solve(G, M)
+    Gi = np.linalg.inv(G)
+    F = tau * tau * dt * Gi @ M @ Gi.T
+    A = p.A.tocsr()
+    slice_of_row = np.array([A.indices[A.indptr[i]] // ns for i in range(A.shape[0])])
+    for i in range(A.shape[0]):
+        assert np.all(A.indices[A.indptr[i]:A.indptr[i + 1]] // ns == slice_of_row[i])
+    # filter
+    mf, Pf, mp, Pp = [], [], [], []
+    m_pred, P_pred = np.zeros(ns), np.linalg.inv(meta["Q1"].toarray())
+    for k in range(nt):
+        rows = np.flatnonzero(slice_of_row == k)
+        m_k, P_k = m_pred, P_pred
+        if rows.size:
+            H = A[rows][:, k * ns:(k + 1) * ns].toarray()
+            R = np.diag(1.0 / p.q_eps[rows])
+            Sk = H @ P_k @ H.T + R
+            K = np.linalg.solve(Sk, H @ P_k).T
+            m_k = m_k + K @ (p.y[rows] - p.b[rows] - H @ m_k)
+            IKH = np.eye(ns) - K @ H
+            P_k = IKH @ P_k @ IKH.T + K @ R @ K.T     # Joseph form (data noise 1e-3)
+        mp.append(m_pred); Pp.append(P_pred); mf.append(m_k); Pf.append(P_k)
+        m_pred, P_pred = At @ m_k, At @ P_k @ At.T + F
+    # smoother
+    ms, Ps = [None] * nt, [None] * nt
+    ms[-1], Ps[-1] = mf[-1], Pf[-1]
+    for k in range(nt - 2, -1, -1):
+        C = np.linalg.solve(Pp[k + 1], At @ Pf[k]).T
+        ms[k] = mf[k] + C @ (ms[k + 1] - mp[k + 1])
+        Ps[k] = Pf[k] + C @ (Ps[k + 1] - Pp[k + 1]) @ C.T
+    mean = np.concatenate(ms)
+    var = np.concatenate([np.diag(P) for P in Ps])
+    r = O.posterior(p)
+    # a wrong noise covariance (M~ dropped, or dt^2 for dt) moves these by 1e-5 .. 1
+    assert _rel(r["mean"], mean) <= 1e-8
+    assert np.max(np.abs(r["var"] - var) / var) <= 1e-8
 
 
 def test_P9_woodbury_covariance_form():
