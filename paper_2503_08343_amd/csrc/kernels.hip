@@ -5,8 +5,11 @@
 // the same batched launch.  Dense front work is blocked in 64-wide column blocks:
 //   * diagonal 64x64 blocks are factored in FP64 in LDS (also in the FP32 mode) and
 //     inverted (the inverse drives the panel TRSM and the solves),
-//   * panel TRSM, panel update and the trailing SYRK are 64x64 MFMA tiles
-//     (v_mfma_f64_16x16x4f64 / v_mfma_f32_16x16x4f32), operands staged in LDS,
+//   * panel TRSM and the inner panel update are 64x64 MFMA tiles, the long-K products
+//     (outer panel update, trailing SYRK, Sigma[R', K]) 128x128 FP64 tiles or, in the
+//     FP32 mode, 256x256 tiles whose FP32 products run as six bf16 MFMA term products
+//     (v_mfma_f64_16x16x4f64 / v_mfma_f32_16x16x4f32 / v_mfma_f32_32x32x16_bf16),
+//     operands staged in LDS,
 //   * children's update matrices are pulled into the parent front one child slot at
 //     a time (deterministic, no floating-point atomics).
 // Solves pass update vectors up the tree (forward) and read ancestors' solution
