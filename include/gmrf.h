@@ -63,7 +63,10 @@ enum {
 
 typedef enum {
   GMRF_FP64 = 0,          /* every factor, solve and selected-inverse operation in FP64 */
-  GMRF_FP32_REFINE = 1    /* FP32 fronts and updates on MFMA with FP32 accumulation; FP64
+  GMRF_FP32_REFINE = 1    /* FP32 fronts and updates on MFMA with FP32 accumulation (the
+                             long-K products -- outer panel update, trailing SYRK,
+                             Sigma[R', K] -- as six bf16 term products of a three-way bf16
+                             split of each FP32 operand, with FP32-level error); FP64
                              diagonal-block pivots, log-det sum, residuals and iterative
                              refinement of the mean */
 } gmrf_precision;

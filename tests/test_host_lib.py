@@ -77,3 +77,16 @@ def test_disconnected_blocks_are_ordered_independently():
     owner = np.searchsorted(p.block_ptr, perm, side="right") - 1
     cols = np.repeat(np.arange(p.n), np.diff(F.Lp))
     assert np.all(owner[F.Li] == owner[cols])
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """the benchmark runs on one GPU: --gpus N > 1 prints one JSON line saying so and exits
+    with status 2 before touching a device"""
+    import json
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    line = json.loads(r.stdout.strip().splitlines()[-1])
+    assert "one GPU" in line["error"]
