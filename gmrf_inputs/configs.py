@@ -140,7 +140,37 @@ def advdiff_spacetime(ns: int = 128, nt: int = 64, c: float = 0.5, nu: float = 0
                    meta=dict(workload="advdiff_spacetime", ns=ns, nt=nt, dt=dt, c=c, nu=nu,
                              tau=tau, kappa1=kappa1, tau1=tau1, sigma_pde=sigma_pde,
                              sigma=sigma, n_pts=n_pts, seed=seed, G=G, m=m, Q1=Q1,
-                             mesh=mesh, u_true=u))
+                             mesh=mesh, u_true=u, pde_rows=pde_rows))
+
+
+def advdiff_derivatives(problem: Problem) -> dict:
+    """Derivatives of the advection-diffusion workload's prior precision and of its
+    Galerkin PDE observation rows with respect to the advection speed c and the
+    viscosity nu (L_s = nu S + c C: dL_s/dc = C, dL_s/dnu = S); Q1, the noise and the
+    point rows do not depend on them.  Returns {"c": (dq, da), "nu": (dq, da)} with dq
+    aligned with problem.Q.data and da with problem.A.data (same stored patterns)."""
+    meta = problem.meta
+    mesh, nt, dt, m = meta["mesh"], meta["nt"], meta["dt"], meta["m"]
+    S = fem.stiffness(mesh)
+    C = fem.convection(mesh, axis=0)
+    Ls = meta["nu"] * S + meta["c"] * C
+    out = {}
+    for name, dLs in (("c", C), ("nu", S)):
+        dQ = priors.spacetime_precision_derivative(mesh, nt, dt, Ls, dLs, meta["tau"], m)
+        dq = fem.on_pattern(dQ, problem.Q).data
+        dQt = fem.on_pattern(dQ.T.tocsr(), problem.Q).data
+        dq = 0.5 * (dq + dQt)
+        blocks = []
+        if meta.get("pde_rows", True):
+            P1 = priors._pattern(fem.ring_pattern(mesh, 1) + sp.eye(mesh.n))
+            dG = fem.on_pattern((dt * dLs).tocsr(), P1)
+            blocks.append(obs.galerkin_euler_rows(dG, np.zeros(mesh.n), nt, dt, first_slice=1))
+        n_pts = problem.A.shape[0] - (blocks[0].shape[0] if blocks else 0)
+        blocks.append(sp.csr_matrix((n_pts, problem.n)))
+        dA = sp.vstack(blocks, format="csr")
+        da = fem.on_pattern(dA, problem.A).data
+        out[name] = (dq, da)
+    return out
 
 
 def matern_batch(n_prob: int = 256, side_lo: int = 64, side_hi: int = 256,

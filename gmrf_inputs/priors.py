@@ -88,3 +88,30 @@ def spacetime_precision(mesh: fem.Mesh, nt: int, dt: float, Ls: sp.spmatrix,
     Po = _pattern(PG.T @ PS)
     P = _pattern(sp.kron(sp.eye(nt), Pd) + sp.kron(sub, Po) + sp.kron(sub.T, Po.T))
     return fem.on_pattern(Q, P), G
+
+
+def spacetime_precision_derivative(mesh: fem.Mesh, nt: int, dt: float, Ls: sp.spmatrix,
+                                   dLs: sp.spmatrix, tau: float, m: np.ndarray,
+                                   sigma_inv: sp.spmatrix | None = None) -> sp.csr_matrix:
+    """dQ_ST for a change dLs of the spatial operator (Q1 and Sigma^-1 held fixed):
+    with G = M~ + dt Ls, dG = dt dLs and W = M~^-1 Sigma^-1 M~^-1,
+        d(F^-1)   = tau^-2 dt^-1 (dG^T W G + G^T W dG)
+        d(F^-1 A) = tau^-2 dt^-1 dG^T M~^-1 Sigma^-1
+        d(A^T F^-1 A) = 0,
+    placed in the blocks of Q_ST like spacetime_precision (unstructured pattern; callers
+    put it on Q's pattern)."""
+    ns = mesh.n
+    Mt = sp.diags(m).tocsr()
+    Minv = sp.diags(1.0 / m)
+    P1 = _pattern(fem.ring_pattern(mesh, 1) + sp.eye(ns))
+    G = fem.on_pattern((Mt + dt * Ls).tocsr(), P1)
+    dG = fem.on_pattern((dt * dLs).tocsr(), P1)
+    Sinv = Mt if sigma_inv is None else sigma_inv.tocsr()
+    c = 1.0 / (tau * tau * dt)
+    W = Minv @ Sinv @ Minv
+    dFinv = c * (dG.T @ W @ G + G.T @ W @ dG)
+    dFA = c * (dG.T @ Minv @ Sinv)
+    mid_f = np.ones(nt); mid_f[0] = 0.0
+    sub = sp.diags([np.ones(nt - 1)], [-1], shape=(nt, nt))
+    dQ = sp.kron(sp.diags(mid_f), dFinv) - sp.kron(sub, dFA) - sp.kron(sub.T, dFA.T)
+    return dQ.tocsr()

@@ -294,3 +294,36 @@ def dense_posterior(problem):
     ev = np.linalg.eigvalsh(D)
     return dict(mean=x, var=np.diag(Sig).copy(), logdet=float(np.sum(np.log(ev))),
                 cov=Sig, Qpost=Qp, h=h)
+
+
+# ------------------------------------------- conditioning of the scaled posterior precision
+U32 = 2.0 ** -24    # unit roundoff of FP32 (round to nearest)
+U64 = 2.0 ** -53    # unit roundoff of FP64
+
+
+def jacobi_scaled(Q):
+    """D^-1/2 Q D^-1/2 with D = diag(Q): the symmetric diagonal scaling a factorisation
+    in reduced precision works on (unit diagonal)."""
+    Q = sp.csr_matrix(Q)
+    s = 1.0 / np.sqrt(Q.diagonal())
+    return sp.csr_matrix(sp.diags(s) @ Q @ sp.diags(s))
+
+
+def condition_number(Q, dense_max=2000):
+    """2-norm condition number lambda_max / lambda_min of the Jacobi-scaled Q (Sec. 3.2
+    concerns the cost of factoring Q; the accuracy of a reduced-precision factor is
+    governed by this number: a backward error E with ||E|| ~ u ||Q^|| moves the inverse
+    by about kappa u relative).  Dense eigenvalues up to dense_max unknowns, else
+    Lanczos for the largest and shift-invert Lanczos (sigma = 0) for the smallest.
+    Returns (kappa, lambda_min, lambda_max)."""
+    Qh = jacobi_scaled(Q)
+    n = Qh.shape[0]
+    if n <= dense_max:
+        w = np.linalg.eigvalsh(Qh.toarray())
+        lo, hi = float(w[0]), float(w[-1])
+    else:
+        import scipy.sparse.linalg as spla
+        hi = float(spla.eigsh(Qh, k=1, which="LA", tol=1e-6, return_eigenvectors=False)[0])
+        lo = float(spla.eigsh(sp.csc_matrix(Qh), k=1, sigma=0.0, which="LM", tol=1e-6,
+                              return_eigenvectors=False)[0])
+    return hi / lo, lo, hi

@@ -10,7 +10,11 @@ with log-dets from the oracle's sparse Cholesky factors (Sec. 3.2) of Q and Q_po
 gradient for given derivative matrices (dQ on Q's pattern, dq_eps diagonal):
     dLML = 1/2 tr(Q^-1 dQ) + 1/2 sum(dq_eps / q_eps) - 1/2 tr(Q_post^-1 (dQ + A^T diag(dq_eps) A))
            - 1/2 mu^T dQ mu - 1/2 sum(dq_eps r^2),
-the traces read from the Takahashi selected inverses on the pattern (Sec. 3.2).
+the traces read from the Takahashi selected inverses on the pattern (Sec. 3.2).  When the
+observation operator depends on the parameter too (Galerkin PDE rows built from the
+space-time operator G, Sec. 2.4 and 3.1), a derivative dA of A adds
+    + r^T Q_eps dA mu      and   dQ_post += dA^T Q_eps A + A^T Q_eps dA
+(the identity holds for every u, so at u = mu_post only the explicit dependence remains).
 """
 from __future__ import annotations
 
@@ -54,14 +58,21 @@ def lml_sparse(Q, A, q_eps, y, b=None, coords=None, derivs=()):
     if derivs:
         S0 = core.selinv(F0)
         S1 = core.selinv(F1)
-        for dQ, dqe in derivs:
+        for dv in derivs:
+            dQ, dqe = dv[0], dv[1]
+            dA = sp.csr_matrix(dv[2]) if len(dv) > 2 and dv[2] is not None else None
             dQ = sp.csr_matrix(dQ)
             dqe = np.zeros(M) if dqe is None else np.asarray(dqe, dtype=np.float64)
             tr0 = float(np.dot(core.sigma_on_pattern(F0, S0, dQ), dQ.data)) if dQ.nnz else 0.0
-            D1 = (dQ + A.T @ sp.diags(dqe) @ A).tocsr()
+            D1 = dQ + A.T @ sp.diags(dqe) @ A
+            if dA is not None:
+                D1 = D1 + dA.T @ sp.diags(q_eps) @ A + A.T @ sp.diags(q_eps) @ dA
+            D1 = sp.csr_matrix(D1)
             D1.sum_duplicates()
             tr1 = float(np.dot(core.sigma_on_pattern(F1, S1, D1), D1.data)) if D1.nnz else 0.0
             g = (0.5 * tr0 + 0.5 * float(np.sum(dqe / q_eps)) - 0.5 * tr1
                  - 0.5 * float(mu @ (dQ @ mu)) - 0.5 * float(np.sum(dqe * r * r)))
+            if dA is not None:
+                g += float((q_eps * r) @ (dA @ mu))
             grads.append(g)
     return lml, grads, dict(mu=mu, r=r, quad=quad, misfit=misfit, logdet_prior=ld0, logdet_post=ld1)

@@ -56,3 +56,64 @@ def test_objective_decreases_along_iteration():
         phis.append(rec["phi0"])
         assert rec["decrement"] >= -1e-12 * abs(rec["phi0"])
     assert all(b <= a for a, b in zip(phis, phis[1:]))
+
+
+def _quadrature_residual(u, nx, nt, dt, nu):
+    """The Galerkin implicit-Euler Burgers residual rebuilt element by element from the
+    P1 hat functions on [-1, 1] (nx interior nodes, zero Dirichlet values at +-1) with
+    3-point Gauss-Legendre quadrature, exact for the cubic integrands here (Sec. 2.3 weak
+    form of u_t + u u_x = nu u_xx; lumped mass = integral of each hat function).  Rows:
+    u^0_i, then slices 1..nt-1."""
+    h = 2.0 / (nx + 1)
+    xg, wg = np.polynomial.legendre.leggauss(3)
+    U = np.asarray(u, dtype=np.float64).reshape(nt, nx)
+    out = [U[0].copy()]
+    for k in range(1, nt):
+        full = np.concatenate([[0.0], U[k], [0.0]])          # node values incl. boundary
+        prev = np.concatenate([[0.0], U[k - 1], [0.0]])
+        r = np.zeros(nx + 2)
+        lump = np.zeros(nx + 2)
+        for e in range(nx + 1):                                # element [x_e, x_{e+1}]
+            xa = -1.0 + e * h
+            for xi, w in zip(xg, wg):
+                x = xa + 0.5 * h * (xi + 1.0)
+                phi = np.array([(xa + h - x) / h, (x - xa) / h])
+                dphi = np.array([-1.0 / h, 1.0 / h])
+                uq = full[e] * phi[0] + full[e + 1] * phi[1]
+                ux = full[e] * dphi[0] + full[e + 1] * dphi[1]
+                for loc in range(2):
+                    node = e + loc
+                    jac = 0.5 * h * w
+                    lump[node] += jac * phi[loc]
+                    r[node] += jac * (nu * dphi[loc] * ux + phi[loc] * uq * ux)
+        r += lump * (full - prev) / dt
+        out.append(r[1:nx + 1])
+    return np.concatenate(out)
+
+
+def test_residual_matches_elementwise_quadrature():
+    """The oracle's residual (mass, viscous and nonlinear terms) equals an independent
+    element-by-element quadrature of the weak form on random iterates."""
+    p, m, S = _prob(nx=11, nt=5, seed=97)
+    for seed in (98, 99):
+        u = gi.rng_for(seed).standard_normal(p.n)
+        f, _ = O.burgers_residual_and_jacobian(u, m["nx"], m["nt"], m["dt"], m["nu"], m["mass"], S)
+        g = _quadrature_residual(u, m["nx"], m["nt"], m["dt"], m["nu"])
+        assert np.max(np.abs(f - g)) <= 1e-12 * max(1.0, np.max(np.abs(g)))
+
+
+def test_nonlinear_term_closed_form_for_linear_u():
+    """u = a + b x on a slice equal to its predecessor: the time term vanishes, the
+    discrete Laplacian of a linear function is zero at nodes with two interior
+    neighbours, and the weak nonlinear term is exactly b (a + b x_i) h there."""
+    p, m, S = _prob(nx=15, nt=3, seed=90)
+    nx, nt = m["nx"], m["nt"]
+    h = 2.0 / (nx + 1)
+    x = -1.0 + h * np.arange(1, nx + 1)
+    a, b = 0.7, -1.3
+    u = np.tile(a + b * x, nt)
+    f, _ = O.burgers_residual_and_jacobian(u, nx, nt, m["dt"], m["nu"], m["mass"], S)
+    f_pde = f[nx:].reshape(nt - 1, nx)
+    want = b * (a + b * x) * h
+    for k in range(nt - 1):
+        assert np.max(np.abs(f_pde[k, 1:-1] - want[1:-1])) <= 1e-13

@@ -293,3 +293,21 @@ def test_block_diagonal_batch_equals_separate_problems():
         assert _rel(r["mean"][lo:hi], d["mean"]) <= 1e-10
         assert np.max(np.abs(r["var"][lo:hi] - d["var"]) / d["var"]) <= 1e-10
         assert abs(lds[b] - d["logdet"]) <= 1e-10 * abs(d["logdet"])
+
+
+def test_condition_number_estimate_pins():
+    """The condition estimate: the Lanczos branch against dense eigenvalues on a grid
+    just above the dense limit; the 1-node RW1 precision (tridiagonal Toeplitz in the
+    interior) against its closed-form eigenvalues 2 - 2 cos(k pi / (n+1)) for the
+    Dirichlet second-difference matrix."""
+    p = gi.matern2d(side=24, n_obs=40, seed=31)
+    Qp, _ = O.assemble(p.Q, p.A, p.q_eps, p.y)
+    k_l, lo_l, hi_l = O.condition_number(Qp, dense_max=100)
+    w = np.linalg.eigvalsh(O.jacobi_scaled(Qp).toarray())
+    assert abs(lo_l - w[0]) <= 1e-6 * w[0] and abs(hi_l - w[-1]) <= 1e-6 * w[-1]
+    assert abs(k_l - w[-1] / w[0]) <= 1e-5 * w[-1] / w[0]
+    n = 50
+    T = sp.diags([-np.ones(n - 1), 2.0 * np.ones(n), -np.ones(n - 1)], [-1, 0, 1], format="csr")
+    k, lo, hi = O.condition_number(T)
+    lam = 2.0 - 2.0 * np.cos(np.arange(1, n + 1) * np.pi / (n + 1))
+    assert abs(lo - lam[0] / 2.0) <= 1e-12 and abs(hi - lam[-1] / 2.0) <= 1e-12
