@@ -177,7 +177,8 @@ def secondary(binding, which, steps, warmup):
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
                 ctx.gn_burgers(m["nx"], m["nt"], m["dt"], m["nu"], mass, s3, u, iters=10, precision=prec,
-                               refine=8 if prec == binding.GMRF_FP32_REFINE else 1, use_graph=True)
+                               refine=30 if prec == binding.GMRF_FP32_REFINE else 2, use_graph=True,
+                               refine_tol=1e-12)
                 torch.cuda.synchronize()
                 if rep >= warmup:
                     ts.append(time.perf_counter() - t0)

@@ -143,7 +143,26 @@ def advdiff_spacetime(ns: int = 128, nt: int = 64, c: float = 0.5, nu: float = 0
                              mesh=mesh, u_true=u, pde_rows=pde_rows))
 
 
-def advdiff_derivatives(problem: Problem) -> dict:
+def advdiff_values(problem: Problem, c: float, nu: float):
+    """Values of the advection-diffusion workload's prior precision and observation
+    operator at advection speed c and viscosity nu, on the workload's stored patterns
+    (the data y, the noise and the point rows stay those of the workload).  Returns
+    (q_data aligned with problem.Q.data, a_data aligned with problem.A.data)."""
+    meta = problem.meta
+    mesh, nt, dt, m = meta["mesh"], meta["nt"], meta["dt"], meta["m"]
+    Ls = nu * fem.stiffness(mesh) + c * fem.convection(mesh, axis=0)
+    Q, G = priors.spacetime_precision(mesh, nt, dt, Ls, meta["tau"], meta["Q1"], m)
+    q = fem.on_pattern(_sym_clean(Q), problem.Q).data
+    blocks = []
+    if meta.get("pde_rows", True):
+        blocks.append(obs.galerkin_euler_rows(G, m, nt, dt, first_slice=1))
+    npde = blocks[0].shape[0] if blocks else 0
+    blocks.append(problem.A[npde:])
+    a = fem.on_pattern(sp.vstack(blocks, format="csr"), problem.A).data
+    return q, a
+
+
+def advdiff_derivatives(problem: Problem, c: float | None = None, nu: float | None = None) -> dict:
     """Derivatives of the advection-diffusion workload's prior precision and of its
     Galerkin PDE observation rows with respect to the advection speed c and the
     viscosity nu (L_s = nu S + c C: dL_s/dc = C, dL_s/dnu = S); Q1, the noise and the
@@ -153,7 +172,7 @@ def advdiff_derivatives(problem: Problem) -> dict:
     mesh, nt, dt, m = meta["mesh"], meta["nt"], meta["dt"], meta["m"]
     S = fem.stiffness(mesh)
     C = fem.convection(mesh, axis=0)
-    Ls = meta["nu"] * S + meta["c"] * C
+    Ls = (meta["nu"] if nu is None else nu) * S + (meta["c"] if c is None else c) * C
     out = {}
     for name, dLs in (("c", C), ("nu", S)):
         dQ = priors.spacetime_precision_derivative(mesh, nt, dt, Ls, dLs, meta["tau"], m)

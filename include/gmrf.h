@@ -152,6 +152,36 @@ gmrf_status gmrf_logdet(gmrf_t h, double* out);
 gmrf_status gmrf_solve(gmrf_t h, double* mu_out, int max_refine, double tol, int* iters_out,
                        double* resid_out);
 
+/* Log marginal likelihood of the data and its gradient with respect to k parameters of
+   the prior and of the observation model.  With mu_post the posterior mean, mu = 0 the
+   prior mean and r = y - b - A mu_post, the Gaussian identity
+   log p(y) = log p(y|u) + log p(u) - log p(u|y) at u = mu_post (conditioning, Sec. 3.1)
+   gives
+     LML = -M/2 log 2 pi + 1/2 log|Q| + 1/2 log|Q_eps| - 1/2 log|Q_post| - 1/2 mu_post^T Q mu_post
+           - 1/2 r^T Q_eps r,
+   and, the identity holding for every u, its derivative at u = mu_post needs only the
+   explicit dependence:
+     dLML = 1/2 tr(Q^-1 dQ) + 1/2 sum(dq_eps / q_eps) - 1/2 tr(Q_post^-1 dQ_post)
+            - 1/2 mu_post^T dQ mu_post - 1/2 sum(dq_eps r^2) + (Q_eps r)^T dA mu_post,
+     dQ_post = dQ + dA^T Q_eps A + A^T Q_eps dA + A^T diag(dq_eps) A,
+   where the traces read the selected inverses (Takahashi, Sec. 3.2) on Q's pattern.
+   post:  context with the posterior (assemble with A, q_eps, y, b; analyze; factor).
+   prior: a second context with the same Q (values and pattern) and no observations,
+          factored.  Both single-block.
+   k:     number of parameters; dq: k x nnz_q (device, parameter-major, dq + i*nnz_q is
+          dQ/dtheta_i in Q's CSR order); da: k x nnz_a (device, nullable = A constant);
+          dqeps: k x m (device, nullable = Q_eps constant).
+   max_refine, tol: refinement of the posterior mean as in gmrf_solve.
+   out:   host, 1 + k doubles: LML, then dLML/dtheta_i.
+   mu_out: device, n doubles, nullable: the refined posterior mean used.
+   Runs the log-dets, the refined mean, both selected inversions (overwriting what
+   gmrf_selinv returned before) and every reduction on the device with fixed orders;
+   synchronises both streams.  Returns GMRF_ERR_NOT_CONVERGED (out still written) if the
+   mean's refinement stopped above tol. */
+gmrf_status gmrf_lml_gradient(gmrf_t post, gmrf_t prior, int k, const double* dq, const double* da,
+                              const double* dqeps, int max_refine, double tol, double* out,
+                              double* mu_out);
+
 /* x = Q_post^-1 rhs (one forward and one backward solve with the current factor; no
    refinement; rhs and x_out device, n entries, original order).  Used for adjoints. */
 gmrf_status gmrf_solve_rhs(gmrf_t h, const double* rhs, double* x_out);
@@ -167,18 +197,21 @@ gmrf_status gmrf_solve_rhs(gmrf_t h, const double* rhs, double* x_out);
    q_eps as assembled.  mass (nx) and stiff3 (3*nx: S_{i,i-1}, S_{i,i}, S_{i,i+1}) are
    device arrays.  Each iteration linearises f at u (J values and offset b written into the
    assembled A and b), assembles H = Q + J^T Q_eps J on the analysed pattern (the ordering
-   is reused), factors in `precision`, solves for the linearised posterior mean with
-   `refine` FP64 residual corrections, and takes a backtracking Armijo step (c = 1e-4,
-   alpha = 1, 1/2, ..., 1/128, the first that passes, else 1/128) chosen on the device.
-   With use_graph != 0 the iterations after the first replay one captured hipGraph.
-   u (device, n): start on entry, final iterate on exit.  rec_out (host, 4*iters,
+   is reused), factors in `precision`, solves for the linearised posterior mean with at
+   most `refine` FP64 residual corrections, stopped on the device once
+   ||h - H x|| <= refine_tol ||h|| (later corrections add nothing), and takes a
+   backtracking Armijo step (c = 1e-4, alpha = 1, 1/2, ..., 1/128, the first that passes,
+   else 1/128) chosen on the device.  With use_graph != 0 the iterations after the first
+   replay one hipGraph captured by this call (and destroyed before it returns).
+   u (device, n): start on entry, final iterate on exit.  rec_out (host, 6*iters,
    nullable): per iteration objective at the start, step length, Newton decrement
-   lambda^2 = -grad^T d, and grad^T d.  On return the context holds the factor of the
+   lambda^2 = -grad^T d, grad^T d, the final relative residual of the linearised solve
+   and the number of corrections applied.  On return the context holds the factor of the
    Gauss-Newton Laplace approximation at the final iterate and mu_post = u, so
    gmrf_logdet, gmrf_sample and gmrf_selinv describe N(u*, (Q + J*^T Q_eps J*)^-1). */
 gmrf_status gmrf_gn_burgers(gmrf_t h, int64_t nx, int64_t nt, double dt, double nu,
                             const double* mass, const double* stiff3, int iters, int precision,
-                            int refine, int use_graph, double* u, double* rec_out);
+                            int refine, double refine_tol, int use_graph, double* u, double* rec_out);
 
 /* k posterior samples x = mu_post + P^T L^-T z (Sec. 3.2, sampling) from the mean of the
    last gmrf_solve.  z: n x k float32, column-major, pivot order (device).

@@ -21,8 +21,11 @@ dl/dtheta = lambda^T (dh - dQ_post mu_post); h does not depend on kappa, tau and
 dh/dlog sigma = -2 h, which cancels against Q_post mu = h, so
   dl/dlog kappa = -lambda^T dQ mu,  dl/dlog tau = 2 lambda^T Q mu,  dl/dlog sigma = -2 lambda^T Q mu.
 
-Every step runs in the library's kernels; this module marshals arguments and combines the
-returned scalars.
+The same identity with derivatives of the observation operator gives the gradient with
+respect to the advection speed c and viscosity nu of the space-time prior, whose Galerkin
+PDE rows depend on them too (SpaceTimeLML).  Every step -- log-dets, refined mean,
+selected inversions, traces, quadratic forms and their combination -- runs inside the
+library call gmrf_lml_gradient; this module prepares derivative inputs and marshals.
 """
 from __future__ import annotations
 
@@ -85,33 +88,21 @@ class MaternLML:
         return sigma
 
     def evaluate(self, log_kappa, log_tau, log_sigma, gradient=True):
-        """Returns (LML, gradient w.r.t. (log kappa, log tau, log sigma) or None)."""
-        sigma = self._factor(log_kappa, log_tau, log_sigma)
-        N, M = self.n, self.m
-        ld_prior = float(self.prior.logdet()[0])
-        ld_post = float(self.post.logdet()[0])
+        """Returns (LML, gradient w.r.t. (log kappa, log tau, log sigma) or None); the
+        log-dets, refined mean, selected inversions, traces and reductions all run in
+        gmrf_lml_gradient."""
+        torch = self.torch
+        self._factor(log_kappa, log_tau, log_sigma)
         refine = 30 if self.precision == binding.GMRF_FP32_REFINE else 0
-        mu, _, _ = self.post.solve(max_refine=refine, tol=1e-13, raise_not_converged=False)
-        self.mu = mu
-        self.post.spmv(self.q, mu, self.tmp)
-        quad = self.post.dot(mu, self.tmp)                      # mu^T Q mu
-        misfit = self.post.misfit(mu)                           # r^T Q_eps r
-        logdet_qeps = -2.0 * M * math.log(sigma)
-        lml = (-0.5 * M * math.log(2.0 * math.pi) + 0.5 * ld_prior + 0.5 * logdet_qeps
-               - 0.5 * ld_post - 0.5 * quad - 0.5 * misfit)
-        if not gradient:
-            return lml, None
-        _, sig_prior = self.prior.selinv(with_pattern=True, nnzq=self.nnz)
-        _, sig_post = self.post.selinv(with_pattern=True, nnzq=self.nnz)
-        tr_prior_dq = self.post.dot(sig_prior, self.dq)
-        tr_post_dq = self.post.dot(sig_post, self.dq)
-        tr_post_q = self.post.dot(sig_post, self.q)
-        self.post.spmv(self.dq, mu, self.tmp)
-        mu_dq_mu = self.post.dot(mu, self.tmp)
-        g_kappa = 0.5 * tr_prior_dq - 0.5 * tr_post_dq - 0.5 * mu_dq_mu
-        g_tau = -N + tr_post_q + quad
-        g_sigma = -M + (N - tr_post_q) + misfit
-        return lml, np.array([g_kappa, g_tau, g_sigma])
+        self.mu = torch.empty(self.n, dtype=torch.float64, device=self.dev)
+        if gradient:
+            # dQ/dlog kappa from the Matern kernel, dQ/dlog tau = -2 Q, dQ_eps/dlog sigma = -2 Q_eps
+            dq = torch.stack([self.dq, -2.0 * self.q, torch.zeros_like(self.q)])
+            dqeps = torch.stack([torch.zeros_like(self.qeps), torch.zeros_like(self.qeps), -2.0 * self.qeps])
+            return self.post.lml_gradient(self.prior, dq=dq, dqeps=dqeps, max_refine=refine, tol=1e-13,
+                                          mu_out=self.mu)
+        lml, _ = self.post.lml_gradient(self.prior, max_refine=refine, tol=1e-13, mu_out=self.mu)
+        return lml, None
 
     def mean_adjoint(self, grad_mu):
         """dl/d(log kappa, log tau, log sigma) for a loss with gradient grad_mu w.r.t. the
@@ -124,12 +115,61 @@ class MaternLML:
         return np.array([g_k, 2.0 * lqm, -2.0 * lqm])
 
 
+class SpaceTimeLML:
+    """LML of the advection-diffusion space-time workload (Sec. 2.4, App. A) as a function of
+    the advection speed c and the viscosity nu, and its adjoint gradient.  Both enter the
+    prior through G = M~ + dt (nu S + c C) and the Galerkin PDE observation rows through
+    the same G (Sec. 3.1), so the gradient carries the observation-operator terms of
+    gmrf_lml_gradient.  The prior and posterior contexts keep one pattern, analysed once
+    and refactored per parameter value (Sec. 3.3); the values of Q, A and of their
+    derivatives on those patterns come from the workload's generator."""
+
+    def __init__(self, problem, device=0, precision=binding.GMRF_FP64):
+        import gmrf_inputs as gi
+        import torch
+        self.torch = torch
+        self.gi = gi
+        self.p = problem
+        self.dev = f"cuda:{device}"
+        self.precision = precision
+        d = binding.problem_to_device(problem, self.dev)
+        self.prior = binding.Context(device)
+        self.post = binding.Context(device)
+        self.prior.assemble(d["q_indptr"], d["q_indices"], d["q_data"], None, None, None, None, None)
+        self.post.assemble(**d)
+        self.prior.analyze(problem.coords)
+        self.post.analyze(problem.coords)
+        self._keep = d
+
+    def close(self):
+        self.prior.close()
+        self.post.close()
+
+    def evaluate(self, c, nu, gradient=True):
+        """Returns (LML, gradient w.r.t. (c, nu) or None)."""
+        torch = self.torch
+        t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(self.dev, torch.float64)  # noqa: E731
+        q, a = self.gi.advdiff_values(self.p, float(c), float(nu))
+        qd, ad = t(q), t(a)
+        self.prior.update_values(q_data=qd)
+        self.post.update_values(q_data=qd, a_data=ad)
+        self.prior.factor(self.precision)
+        self.post.factor(self.precision)
+        refine = 30 if self.precision == binding.GMRF_FP32_REFINE else 0
+        if not gradient:
+            return self.post.lml_gradient(self.prior, max_refine=refine, tol=1e-13)[0], None
+        der = self.gi.advdiff_derivatives(self.p, c=float(c), nu=float(nu))
+        dq = t(np.stack([der["c"][0], der["nu"][0]]))
+        da = t(np.stack([der["c"][1], der["nu"][1]]))
+        return self.post.lml_gradient(self.prior, dq=dq, da=da, max_refine=refine, tol=1e-13)
+
+
 def _torch_function():
     import torch
 
     class GMRFLogML(torch.autograd.Function):
-        """LML(theta) for theta = (log kappa, log tau, log sigma) with the hand-written
-        adjoint gradient of MaternLML."""
+        """LML(theta) with the hand-written adjoint gradient of an engine: MaternLML
+        (theta = log kappa, log tau, log sigma) or SpaceTimeLML (theta = c, nu)."""
 
         @staticmethod
         def forward(ctx, theta, engine):
@@ -163,7 +203,7 @@ def _torch_function():
 
 
 def log_ml(theta, engine):
-    """Differentiable LML(theta) (torch); theta = (log kappa, log tau, log sigma)."""
+    """Differentiable LML(theta) (torch); theta as the engine takes it."""
     return _torch_function()[0].apply(theta, engine)
 
 

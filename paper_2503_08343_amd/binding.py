@@ -30,7 +30,8 @@ EXPORTS = ["gmrf_create", "gmrf_destroy", "gmrf_assemble", "gmrf_update_values",
            "gmrf_selinv_wait", "gmrf_dot",
            "gmrf_stats", "gmrf_pivot_order", "gmrf_phase_ms", "gmrf_last_error",
            "gmrf_symbolic_host", "gmrf_profile", "gmrf_kernel_stats", "gmrf_matern_values",
-           "gmrf_spmv", "gmrf_misfit", "gmrf_solve_rhs", "gmrf_gn_burgers", "gmrf_launch_records"]
+           "gmrf_spmv", "gmrf_misfit", "gmrf_solve_rhs", "gmrf_gn_burgers", "gmrf_launch_records",
+           "gmrf_lml_gradient"]
 
 
 class gmrf_options(ctypes.Structure):
@@ -115,9 +116,10 @@ def load():
         "gmrf_spmv": ([P, P, P, P], i32),
         "gmrf_misfit": ([P, P, P], i32),
         "gmrf_solve_rhs": ([P, P, P], i32),
-        "gmrf_gn_burgers": ([P, i64, i64, d, d, P, P, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+        "gmrf_gn_burgers": ([P, i64, i64, d, d, P, P, ctypes.c_int, ctypes.c_int, ctypes.c_int, d,
                              ctypes.c_int, P, P], i32),
         "gmrf_kernel_stats": ([P, P, ctypes.c_int, P], i32),
+        "gmrf_lml_gradient": ([P, P, ctypes.c_int, P, P, P, ctypes.c_int, d, P, P], i32),
         "gmrf_launch_records": ([P, P, ctypes.c_int64, P], i32),
     }
     for name, (args, res) in sig.items():
@@ -317,6 +319,18 @@ class Context:
         self._check(self.lib.gmrf_spmv(self.h, _t_ptr(v_val), _t_ptr(x), _t_ptr(y)))
         return y
 
+    def lml_gradient(self, prior, dq=None, da=None, dqeps=None, max_refine=0, tol=0.0, mu_out=None):
+        """(LML, gradient) of gmrf_lml_gradient; this context holds the posterior, `prior`
+        the prior alone; dq / da / dqeps: device tensors (k, nnz_q) / (k, nnz_a) /
+        (k, m) or None; mu_out: device tensor (n) receiving the posterior mean, or None."""
+        k = 0 if dq is None else int(dq.shape[0])
+        out = np.zeros(1 + k)
+        rc = self.lib.gmrf_lml_gradient(self.h, prior.h, k, _t_ptr(dq), _t_ptr(da), _t_ptr(dqeps),
+                                        int(max_refine), float(tol), _np_ptr(out), _t_ptr(mu_out))
+        if rc != GMRF_ERR_NOT_CONVERGED:
+            self._check(rc)
+        return float(out[0]), out[1:].copy()
+
     def solve_rhs(self, rhs, out=None):
         T = self.torch
         x = out if out is not None else T.empty_like(rhs)
@@ -324,14 +338,16 @@ class Context:
         return x
 
     def gn_burgers(self, nx, nt, dt, nu, mass, stiff3, u, iters=10, precision=GMRF_FP64, refine=2,
-                   use_graph=True):
+                   use_graph=True, refine_tol=0.0):
         """Gauss-Newton iterations on the assembled Burgers problem; u (device) is updated in
-        place.  Returns the per-iteration records (objective, step, decrement, slope)."""
-        rec = np.zeros(4 * iters)
+        place.  Returns the per-iteration records (objective, step, decrement, slope,
+        relative residual of the linearised solve, corrections applied)."""
+        rec = np.zeros(6 * iters)
         self._check(self.lib.gmrf_gn_burgers(self.h, int(nx), int(nt), float(dt), float(nu), _t_ptr(mass),
                                              _t_ptr(stiff3), int(iters), int(precision), int(refine),
-                                             1 if use_graph else 0, _t_ptr(u), _np_ptr(rec)))
-        return rec.reshape(iters, 4)
+                                             float(refine_tol), 1 if use_graph else 0, _t_ptr(u),
+                                             _np_ptr(rec)))
+        return rec.reshape(iters, 6)
 
     def misfit(self, x):
         out = np.zeros(1)

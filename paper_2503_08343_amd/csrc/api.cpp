@@ -21,6 +21,7 @@
 
 using namespace gmrf;
 
+
 namespace {
 
 template <typename T>
@@ -48,6 +49,7 @@ struct DevArr {
 };
 
 enum : int { ST_ASSEMBLED = 1, ST_ANALYZED = 2, ST_FACTORED = 4, ST_SOLVED = 8 };
+
 
 struct HostList {  // a launch list before upload
   int64_t f_off = 0, p_off = 0;
@@ -88,6 +90,10 @@ struct Level {
   HostList syrk3;                          // FP32: 256 x 256 tiles of the trailing SYRK
   std::vector<HostList> pupd4, pred4;      // FP32: left-looking panel update per outer block
   double wsize_elems_scatter = 0.0;
+  // level-fused solves (one right-hand side): task ranges in the uploaded task array
+  int64_t ftask_off = 0, ftask_cnt = 0;   // forward: (front, 64-row chunk), chunk-major
+  int64_t btask_off = 0, btask_cnt = 0;   // backward: (front, pivot chunk), from the right
+  double fbytes = 0.0, bbytes = 0.0;      // elements of L each pass reads at this depth
 };
 
 }  // namespace
@@ -127,6 +133,11 @@ struct gmrf_ctx {
   int64_t gpart_max = 0;  // largest split Sigma[R', K] launch (work-groups of 128 x 128)
   int64_t gpart3_max = 0; // same for the FP32 256 x 128 tiles
   int64_t bpart_max = 0;  // largest backward-solve partial launch (work-groups)
+  // level-fused solves: task lists, and the synchronisation words
+  // [prog: one per supernode][tickets: 2 per depth][wait-limit error flag]
+  DevArr<int2> d_tasks;
+  DevArr<int32_t> d_sync;
+  int64_t sync_reset = 0;   // words cleared before each pass (prog + tickets)
 
   int prec = -1;
   DevArr<char> d_L, d_D, d_D2, d_D2T, d_W0, d_W1, d_Y, d_part, d_gpart;
@@ -159,8 +170,8 @@ struct gmrf_ctx {
   // Gauss-Newton scratch
   DevArr<double> d_gn_x, d_gn_d, d_gn_tmp, d_gn_part, d_gn_quad, d_gn_sel, d_gn_rec;
   hipStream_t gn_stream = nullptr;
-  hipGraphExec_t gn_exec = nullptr;
-  int gn_exec_prec = -1;
+  hipGraphExec_t gn_exec = nullptr;   // exists only during one gmrf_gn_burgers call
+  DevArr<double> d_lml;               // workspace of gmrf_lml_gradient
 };
 
 namespace {
@@ -729,6 +740,41 @@ gmrf_status build_plan(gmrf_t h) {
     }, [&](int32_t s) { const double u = (double)(nF(s) - pF(s)); return Cost{0.0, 2.0 * u * u}; });
     lv.wsize_elems_scatter = (double)(lv.map_end - lv.map_begin);
   }
+  // level-fused solve tasks: forward chunk-major over the depth's fronts, backward pivot
+  // chunks from the right; each task follows every task it waits for
+  {
+    std::vector<int2> tasks;
+    for (int d = 0; d <= Y.max_depth; ++d) {
+      Level& lv = h->levels[d];
+      int cmax = 0, pmax = 0;
+      for (int32_t s : lv.fronts) {
+        cmax = std::max<int>(cmax, (int)((Y.nf(s) + 63) / 64));
+        pmax = std::max<int>(pmax, (int)((Y.p(s) + 63) / 64));
+      }
+      lv.ftask_off = (int64_t)tasks.size();
+      lv.fbytes = 0.0;
+      for (int c = 0; c < cmax; ++c)
+        for (int32_t s : lv.fronts)
+          if (c * 64 < Y.nf(s)) tasks.push_back(make_int2(s, c));
+      lv.ftask_cnt = (int64_t)tasks.size() - lv.ftask_off;
+      lv.btask_off = (int64_t)tasks.size();
+      for (int k = 0; k < pmax; ++k)
+        for (int32_t s : lv.fronts) {
+          const int P = (int)((Y.p(s) + 63) / 64);
+          if (k < P) tasks.push_back(make_int2(s, P - 1 - k));
+        }
+      lv.btask_cnt = (int64_t)tasks.size() - lv.btask_off;
+      for (int32_t s : lv.fronts) {
+        const double nn = (double)Y.nf(s), pp = (double)Y.p(s);
+        lv.fbytes += pp * nn - 0.5 * pp * (pp - 1.0);
+      }
+      lv.bbytes = lv.fbytes;
+    }
+    HIPCHK(h, upload(h->d_tasks, tasks, h->stream));
+    h->sync_reset = (int64_t)Y.ns + 2 * (int64_t)(Y.max_depth + 1);
+    HIPCHK(h, h->d_sync.alloc((size_t)h->sync_reset + 1));
+    launch_fill_i32(h->stream, h->d_sync.p, h->sync_reset + 1, 0);
+  }
   hipStream_t st = h->stream;
   HIPCHK(h, upload(h->d_lfronts, B.fronts, st));
   HIPCHK(h, upload(h->d_lprefix, B.prefix, st));
@@ -810,6 +856,7 @@ gmrf_status run_factor(gmrf_t h) {
                        h->d_scale.p, h->d_qhat.p);
   });
   launch_fill_i32(st, h->d_status.p, 1, INT_MAX);
+  if (h->d_sync.p) launch_fill_i32(st, h->d_sync.p + h->sync_reset, 1, 0);   // solve wait-limit flag
   T* W[2] = {(T*)h->d_W0.p, (T*)h->d_W1.p};
   for (int d = Y.max_depth; d >= 0; --d) {
     const Level& lv = h->levels[d];
@@ -876,9 +923,13 @@ gmrf_status run_factor(gmrf_t h) {
 
 gmrf_status check_status(gmrf_t h) {
   if (!(h->state & ST_FACTORED)) return GMRF_OK;
-  int32_t s = INT_MAX;
+  int32_t s = INT_MAX, werr = 0;
   HIPCHK(h, hipMemcpyAsync(&s, h->d_status.p, sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
+  if (h->d_sync.p)
+    HIPCHK(h, hipMemcpyAsync(&werr, h->d_sync.p + h->sync_reset, sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
   HIPCHK(h, hipStreamSynchronize(h->stream));
+  if (werr != 0)
+    return fail(h, GMRF_ERR_HIP, "a solve dependency wait exceeded its limit (results of that solve are invalid)");
   if (s != INT_MAX) {
     h->failed_index = (s >= 0 && s < h->n) ? h->sym.perm[s] : -1;
     return fail(h, GMRF_ERR_NOT_SPD, "matrix is not positive definite: non-positive pivot at original index " +
@@ -898,6 +949,37 @@ void run_solve(gmrf_t h, int nrhs, bool forward) {
   double* V[2] = {h->d_V0.p, h->d_V1.p};
   const T* Lp = (const T*)h->d_L.p;
   const T* D = (const T*)h->d_D.p;
+  if (nrhs == 1) {
+    int32_t* prog = h->d_sync.p;
+    int32_t* tick = h->d_sync.p + Y.ns;
+    int32_t* err = h->d_sync.p + h->sync_reset;
+    const int nd = Y.max_depth + 1;
+    auto tasks = [&](int64_t off, int64_t cnt, int32_t* ticket) {
+      return FusedTasks{h->d_tasks.p + off, ticket, prog, err, cnt};
+    };
+    if (forward) {
+      launch_fill_i32(st, h->d_sync.p, h->sync_reset, 0);
+      for (int d = Y.max_depth; d >= 0; --d) {
+        const Level& lv = h->levels[d];
+        SolveBufs B{h->d_xp.p, V[d & 1], V[(d + 1) & 1], 1};
+        prof_launch(h, KC_FWD, 2.0 * lv.fbytes, lv.fbytes, [&] {
+          launch_fvec_init<T>(st, S, dev_list(h, lv.all), B);
+          for (size_t c = 0; c < lv.fvec_ext.size(); ++c)
+            launch_fvec_extend<T>(st, S, dev_list(h, lv.fvec_ext[c]), (int)c, B);
+          launch_fwd_fused<T>(st, S, tasks(lv.ftask_off, lv.ftask_cnt, tick + d), Lp, D, B);
+        });
+      }
+    }
+    launch_fill_i32(st, h->d_sync.p, h->sync_reset, 0);
+    for (int d = 0; d <= Y.max_depth; ++d) {
+      const Level& lv = h->levels[d];
+      SolveBufs B{h->d_xp.p, V[d & 1], V[(d + 1) & 1], 1};
+      prof_launch(h, KC_BWD, 2.0 * lv.bbytes, lv.bbytes, [&] {
+        launch_bwd_fused<T>(st, S, tasks(lv.btask_off, lv.btask_cnt, tick + nd + d), Lp, D, B);
+      });
+    }
+    return;
+  }
   if (forward) {
     for (int d = Y.max_depth; d >= 0; --d) {
       const Level& lv = h->levels[d];
@@ -1017,6 +1099,8 @@ gmrf_status assemble_device(gmrf_t h) {
 }
 
 // ------------------------------------------------------------------ Gauss-Newton driver
+constexpr int kGNRec = 6;   // doubles per Gauss-Newton iteration record
+
 struct GNArgs {
   int64_t nx, nt;
   double dt, nu;
@@ -1024,29 +1108,42 @@ struct GNArgs {
   const double* s3;
   double* u;
   int refine;
+  double tol;
 };
 
-// solve Q_post x = h on device only (no host synchronisation): one solve plus `refine`
-// corrections with FP64 residuals
+// solve Q_post x = h on device only (no host synchronisation, capturable): one solve
+// plus at most `refine` corrections with FP64 residuals.  A device gate stops the
+// corrections once ||h - Q_post x|| <= tol ||h|| (the remaining ones solve a zero
+// right-hand side and add nothing); rec[0] receives the final relative residual and
+// rec[1] the number of corrections applied.
 template <typename T>
-void device_solve(gmrf_t h, double* x, int refine) {
+void device_solve(gmrf_t h, double* x, int refine, double tol, double* rec) {
   hipStream_t st = h->stream;
   const int64_t n = h->n;
+  double* gate = h->d_gn_sel.p + 1;   // gate[0]: apply the next correction; gate[1]: count
+  launch_norm2(st, n, h->d_h.p, h->d_red.p, h->d_norm.p + 0);
+  launch_fill_f64(st, gate, 2, 0.0);
   launch_permute_in(st, n, 1, h->d_perm.p, h->d_scale.p, h->d_h.p, n, h->d_xp.p);
   run_solve<T>(h, 1, true);
   launch_permute_out(st, n, 1, h->d_perm.p, h->d_scale.p, h->d_xp.p, nullptr, 0, x, n, 0);
   for (int it = 0; it < refine; ++it) {
     launch_resid(st, n, h->d_qrp.p, h->d_qci.p, h->d_qpost.p, h->d_h.p, x, h->d_r.p);
-    launch_permute_in(st, n, 1, h->d_perm.p, h->d_scale.p, h->d_r.p, n, h->d_xp.p);
+    launch_norm2(st, n, h->d_r.p, h->d_red.p, h->d_norm.p + 1);
+    launch_refine_gate(st, h->d_norm.p, tol, gate, nullptr, 0);
+    launch_permute_in(st, n, 1, h->d_perm.p, h->d_scale.p, h->d_r.p, n, h->d_xp.p, gate);
     run_solve<T>(h, 1, true);
     launch_permute_out(st, n, 1, h->d_perm.p, h->d_scale.p, h->d_xp.p, nullptr, 0, x, n, 1);
   }
+  launch_resid(st, n, h->d_qrp.p, h->d_qci.p, h->d_qpost.p, h->d_h.p, x, h->d_r.p);
+  launch_norm2(st, n, h->d_r.p, h->d_red.p, h->d_norm.p + 1);
+  launch_refine_gate(st, h->d_norm.p, tol, gate, rec, 1);
 }
 
 // one Gauss-Newton iteration, fully asynchronous (capturable): linearise at u, assemble
 // H = Q + J^T Q_eps J and the right-hand side, factor (same pattern, reused analysis),
 // solve for the linearised posterior mean x, direction d = x - u, batched backtracking
-// line search on the device, u += alpha d.  The iteration record lands in d_gn_rec[0..3].
+// line search on the device, u += alpha d.  The iteration record lands in
+// d_gn_rec[0..5] (objective, step, decrement, slope, refinement residual, corrections).
 template <typename T>
 gmrf_status gn_body(gmrf_t h, const GNArgs& a) {
   hipStream_t st = h->stream;
@@ -1056,7 +1153,7 @@ gmrf_status gn_body(gmrf_t h, const GNArgs& a) {
   if (rc != GMRF_OK) return rc;
   rc = run_factor<T>(h);
   if (rc != GMRF_OK) return rc;
-  device_solve<T>(h, h->d_gn_x.p, a.refine);
+  device_solve<T>(h, h->d_gn_x.p, a.refine, a.tol, h->d_gn_rec.p + 4);
   launch_gn_direction(st, n, h->d_gn_x.p, a.u, h->d_gn_d.p);
   launch_spmv(st, n, h->d_qrp.p, h->d_qci.p, h->d_qval.p, a.u, h->d_gn_tmp.p);
   launch_dot(st, n, a.u, h->d_gn_tmp.p, h->d_red.p, h->d_gn_quad.p + 0);
@@ -1388,6 +1485,105 @@ gmrf_status gmrf_solve(gmrf_t h, double* mu_out, int max_refine, double tol, int
   return GMRF_OK;
 }
 
+gmrf_status gmrf_lml_gradient(gmrf_t post, gmrf_t prior, int k, const double* dq, const double* da,
+                              const double* dqeps, int max_refine, double tol, double* out, double* mu_out) {
+  if (!post || !prior || !out || k < 0 || (k > 0 && !dq)) return fail(post, GMRF_ERR_ARG, "bad argument");
+  if (post == prior) return fail(post, GMRF_ERR_ARG, "prior and posterior must be two contexts");
+  if (!(post->state & ST_FACTORED) || !(prior->state & ST_FACTORED))
+    return fail(post, GMRF_ERR_STATE, "gmrf_lml_gradient needs both contexts factored");
+  if (prior->n != post->n || prior->nnzq != post->nnzq || prior->qrp != post->qrp || prior->qci != post->qci)
+    return fail(post, GMRF_ERR_PATTERN, "prior and posterior contexts hold different patterns of Q");
+  if (post->nblocks != 1 || prior->nblocks != 1)
+    return fail(post, GMRF_ERR_ARG, "gmrf_lml_gradient takes single-block contexts");
+  if (prior->m != 0) return fail(post, GMRF_ERR_ARG, "the prior context must hold no observations");
+  const int64_t n = post->n, nq = post->nnzq, m = post->m;
+  // workspace: sig0, sig1, dqpost (nnz_q); mu, tmp, var (n); r, w, t1, t2, ones (m); scalars
+  const int64_t ns = 8 + 8 * (int64_t)k;
+  HIPCHK(post, post->d_lml.alloc((size_t)(3 * nq + 3 * n + 5 * std::max<int64_t>(m, 1) + ns)));
+  double* sig0 = post->d_lml.p;
+  double* sig1 = sig0 + nq;
+  double* dqp = sig1 + nq;
+  double* mu = dqp + nq;
+  double* tmp = mu + n;
+  double* var = tmp + n;
+  double* r = var + n;
+  double* w = r + std::max<int64_t>(m, 1);
+  double* t1 = w + std::max<int64_t>(m, 1);
+  double* t2 = t1 + std::max<int64_t>(m, 1);
+  double* ones = t2 + std::max<int64_t>(m, 1);
+  double* sc = ones + std::max<int64_t>(m, 1);
+  double ld0 = 0.0, ld1 = 0.0;
+  gmrf_status rc = gmrf_logdet(prior, &ld0);
+  if (rc != GMRF_OK) return fail(post, rc, std::string("prior: ") + gmrf_last_error(prior));
+  rc = gmrf_logdet(post, &ld1);
+  if (rc != GMRF_OK) return rc;
+  int iters = 0;
+  double res = 0.0;
+  const gmrf_status solve_rc = gmrf_solve(post, mu, max_refine, tol, &iters, &res);
+  if (solve_rc != GMRF_OK && solve_rc != GMRF_ERR_NOT_CONVERGED) return solve_rc;
+  if (k > 0) {
+    rc = gmrf_selinv(prior, var, sig0);   // Sigma of the prior on Q's pattern
+    if (rc != GMRF_OK) return fail(post, rc, std::string("prior: ") + gmrf_last_error(prior));
+    rc = gmrf_selinv(post, var, sig1);
+    if (rc != GMRF_OK) return rc;
+  }
+  hipStream_t st = post->stream;
+  double* red = post->d_red.p;   // partial sums (allocated by gmrf_solve)
+  // scalars: sc[0] mu^T Q mu, sc[1] r^T Q_eps r, sc[2] sum log q_eps; per parameter i at
+  // sc[8 + 8i]: tr(Q^-1 dQ), tr(Q_post^-1 dQ_post), mu^T dQ mu, sum dq_eps / q_eps,
+  // sum dq_eps r^2, (Q_eps r)^T dA mu
+  launch_fill_f64(st, sc, ns, 0.0);
+  launch_spmv(st, n, post->d_qrp.p, post->d_qci.p, post->d_qval.p, mu, tmp);
+  launch_dot(st, n, mu, tmp, red, sc + 0);
+  if (m > 0) {
+    launch_fill_f64(st, ones, m, 1.0);
+    // r = y - b - A mu, w = Q_eps r
+    launch_obs_resid_plain(st, m, post->d_arp.p, post->d_aci.p, post->d_aval.p, post->d_y.p,
+                           post->has_b ? post->d_b.p : nullptr, mu, r);
+    launch_elementwise(st, m, 0, post->d_qeps.p, r, w);
+    launch_dot(st, m, w, r, red, sc + 1);
+    launch_elementwise(st, m, 2, post->d_qeps.p, nullptr, t2);
+    launch_dot(st, m, t2, ones, red, sc + 2);
+  }
+  for (int i = 0; i < k; ++i) {
+    const double* dqi = dq + (int64_t)i * nq;
+    const double* dai = da ? da + (int64_t)i * post->nnza : nullptr;
+    const double* dei = dqeps ? dqeps + (int64_t)i * m : nullptr;
+    double* g = sc + 8 + 8 * i;
+    launch_dot(st, nq, sig0, dqi, red, g + 0);
+    launch_assemble_dqpost(st, nq, dqi, post->d_cptr.p, post->d_cpair.p, post->d_arow.p, post->d_aval.p,
+                           m > 0 ? dai : nullptr, post->d_qeps.p, m > 0 ? dei : nullptr, dqp);
+    launch_dot(st, nq, sig1, dqp, red, g + 1);
+    launch_spmv(st, n, post->d_qrp.p, post->d_qci.p, dqi, mu, tmp);
+    launch_dot(st, n, mu, tmp, red, g + 2);
+    if (m > 0 && dei) {
+      launch_elementwise(st, m, 1, dei, post->d_qeps.p, t1);
+      launch_dot(st, m, t1, ones, red, g + 3);
+      launch_elementwise(st, m, 0, dei, r, t1);
+      launch_dot(st, m, t1, r, red, g + 4);
+    }
+    if (m > 0 && dai) {
+      launch_spmv_obs(st, m, post->d_arp.p, post->d_aci.p, dai, mu, t1);
+      launch_dot(st, m, w, t1, red, g + 5);
+    }
+  }
+  HIPCHK(post, hipGetLastError());
+  std::vector<double> hs((size_t)ns);
+  HIPCHK(post, hipMemcpyAsync(hs.data(), sc, ns * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(post, hipStreamSynchronize(st));
+  const double kLog2Pi = 1.8378770664093454836;
+  out[0] = -0.5 * (double)m * kLog2Pi + 0.5 * ld0 + 0.5 * hs[2] - 0.5 * ld1 - 0.5 * hs[0] - 0.5 * hs[1];
+  for (int i = 0; i < k; ++i) {
+    const double* g = hs.data() + 8 + 8 * i;
+    out[1 + i] = 0.5 * g[0] + 0.5 * g[3] - 0.5 * g[1] - 0.5 * g[2] - 0.5 * g[4] + g[5];
+  }
+  if (mu_out) {
+    HIPCHK(post, copy_d2d(mu_out, mu, n * sizeof(double), st));
+    HIPCHK(post, hipStreamSynchronize(st));
+  }
+  return solve_rc;
+}
+
 gmrf_status gmrf_solve_rhs(gmrf_t h, const double* rhs, double* x_out) {
   if (!h || !rhs || !x_out) return fail(h, GMRF_ERR_ARG, "null argument");
   if (!(h->state & ST_FACTORED)) return fail(h, GMRF_ERR_STATE, "gmrf_solve_rhs before gmrf_factor");
@@ -1406,9 +1602,10 @@ gmrf_status gmrf_solve_rhs(gmrf_t h, const double* rhs, double* x_out) {
 }
 
 gmrf_status gmrf_gn_burgers(gmrf_t h, int64_t nx, int64_t nt, double dt, double nu, const double* mass,
-                            const double* stiff3, int iters, int precision, int refine, int use_graph,
-                            double* u, double* rec_out) {
-  if (!h || !mass || !stiff3 || !u || iters < 1 || refine < 0) return fail(h, GMRF_ERR_ARG, "bad argument");
+                            const double* stiff3, int iters, int precision, int refine, double refine_tol,
+                            int use_graph, double* u, double* rec_out) {
+  if (!h || !mass || !stiff3 || !u || iters < 1 || refine < 0 || !(refine_tol >= 0.0))
+    return fail(h, GMRF_ERR_ARG, "bad argument");
   HIPCHK(h, sel_sync(h));
   if (precision != GMRF_FP64 && precision != GMRF_FP32_REFINE) return fail(h, GMRF_ERR_ARG, "unknown precision");
   if (!(h->state & ST_ANALYZED)) return fail(h, GMRF_ERR_STATE, "gmrf_gn_burgers before gmrf_analyze");
@@ -1436,7 +1633,21 @@ gmrf_status gmrf_gn_burgers(gmrf_t h, int64_t nx, int64_t nt, double dt, double 
   if (!h->gn_stream) HIPCHK(h, hipStreamCreateWithFlags(&h->gn_stream, hipStreamNonBlocking));
   HIPCHK(h, user ? hipStreamSynchronize(user) : hipDeviceSynchronize());
   h->stream = h->gn_stream;
-  struct Restore { gmrf_t h; hipStream_t s; ~Restore() { h->stream = s; } } restore{h, user};
+  // The graph captured by this call holds this call's pointers and sizes (u, mass, the
+  // library's current buffers), so it lives only for this call: every exit drains the
+  // stream and destroys it.
+  struct Restore {
+    gmrf_t h;
+    hipStream_t s;
+    ~Restore() {
+      if (h->gn_exec) {
+        (void)hipStreamSynchronize(h->stream);
+        (void)hipGraphExecDestroy(h->gn_exec);
+        h->gn_exec = nullptr;
+      }
+      h->stream = s;
+    }
+  } restore{h, user};
   const bool prof = h->prof;
   h->prof = false;
   HIPCHK(h, h->d_gn_x.alloc(h->n));
@@ -1444,21 +1655,20 @@ gmrf_status gmrf_gn_burgers(gmrf_t h, int64_t nx, int64_t nt, double dt, double 
   HIPCHK(h, h->d_gn_tmp.alloc(h->n));
   HIPCHK(h, h->d_gn_part.alloc(10 * 256));
   HIPCHK(h, h->d_gn_quad.alloc(4));
-  HIPCHK(h, h->d_gn_sel.alloc(1));
-  HIPCHK(h, h->d_gn_rec.alloc(4));
+  HIPCHK(h, h->d_gn_sel.alloc(3));
+  HIPCHK(h, h->d_gn_rec.alloc(kGNRec));
   gmrf_status rc = alloc_solve(h, 1);
   if (rc != GMRF_OK) return rc;
   rc = precision == GMRF_FP64 ? alloc_numeric<double>(h) : alloc_numeric<float>(h);
   if (rc != GMRF_OK) return rc;
   h->has_b = true;
-  GNArgs a{nx, nt, dt, nu, mass, stiff3, u, refine};
-  std::vector<double> rec(4 * (size_t)iters, 0.0);
+  GNArgs a{nx, nt, dt, nu, mass, stiff3, u, refine, refine_tol};
+  std::vector<double> rec(kGNRec * (size_t)iters, 0.0);
   auto body = [&]() { return precision == GMRF_FP64 ? gn_body<double>(h, a) : gn_body<float>(h, a); };
   HIPCHK(h, hipEventRecord(h->ev[0], h->stream));
   for (int it = 0; it < iters; ++it) {
     const bool graph = use_graph && it > 0;
-    if (graph && (!h->gn_exec || h->gn_exec_prec != precision)) {
-      if (h->gn_exec) { (void)hipGraphExecDestroy(h->gn_exec); h->gn_exec = nullptr; }
+    if (graph && !h->gn_exec) {
       hipGraph_t g = nullptr;
       HIPCHK(h, hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
       rc = body();
@@ -1468,7 +1678,6 @@ gmrf_status gmrf_gn_burgers(gmrf_t h, int64_t nx, int64_t nt, double dt, double 
       hipError_t ie = hipGraphInstantiate(&h->gn_exec, g, nullptr, nullptr, 0);
       (void)hipGraphDestroy(g);
       HIPCHK(h, ie);
-      h->gn_exec_prec = precision;
     }
     if (graph) {
       HIPCHK(h, hipGraphLaunch(h->gn_exec, h->stream));
@@ -1476,8 +1685,8 @@ gmrf_status gmrf_gn_burgers(gmrf_t h, int64_t nx, int64_t nt, double dt, double 
       rc = body();
       if (rc != GMRF_OK) return rc;
     }
-    HIPCHK(h, hipMemcpyAsync(rec.data() + 4 * it, h->d_gn_rec.p, 4 * sizeof(double), hipMemcpyDeviceToHost,
-                             h->stream));
+    HIPCHK(h, hipMemcpyAsync(rec.data() + kGNRec * it, h->d_gn_rec.p, kGNRec * sizeof(double),
+                             hipMemcpyDeviceToHost, h->stream));
   }
   HIPCHK(h, hipEventRecord(h->ev[1], h->stream));
   // Laplace approximation at the final iterate (Sec. 3.3): relinearise and refactor so that

@@ -59,6 +59,18 @@ void launch_at_times(hipStream_t st, int64_t n, const int64_t* atp, const int32_
 void launch_equilibrate(hipStream_t st, int64_t n, int64_t nnzq, const int64_t* qdiag,
                         const int32_t* qrow, const int32_t* qcol, const double* qpost,
                         int32_t* sexp, double* scale, double* qhat);
+// dQ_post = dq + da^T Q_eps A + A^T Q_eps da + A^T diag(dqeps) A on Q's pattern (da, dqeps nullable)
+void launch_assemble_dqpost(hipStream_t st, int64_t nnzq, const double* dq, const int64_t* cptr,
+                            const int32_t* cpair, const int32_t* arow, const double* aval, const double* da,
+                            const double* qeps, const double* dqeps, double* out);
+// y = V x on A's pattern (values V, m rows)
+void launch_spmv_obs(hipStream_t st, int64_t m, const int64_t* arp, const int32_t* aci, const double* v,
+                     const double* x, double* y);
+// r = y - b - V x on A's pattern (b nullable)
+void launch_obs_resid_plain(hipStream_t st, int64_t m, const int64_t* arp, const int32_t* aci, const double* v,
+                            const double* y, const double* b, const double* x, double* r);
+// mode 0: a * b, 1: a / b, 2: log(a), elementwise
+void launch_elementwise(hipStream_t st, int64_t n, int mode, const double* a, const double* b, double* out);
 void launch_fill_i32(hipStream_t st, int32_t* p, int64_t n, int32_t v);
 void launch_fill_f64(hipStream_t st, double* p, int64_t n, double v);
 
@@ -79,7 +91,9 @@ template <typename T> void launch_update(hipStream_t st, const DevSym& S, const 
                                          int step, int mode, NumBufs<T> B);
 template <typename T> void launch_copy_L(hipStream_t st, const DevSym& S, const LaunchList& L,
                                          NumBufs<T> B);
-// part: nblocks * 64 doubles of scratch
+// partial sums per block of the log-determinant reduction
+constexpr int kLdParts = 64;
+// part: nblocks * kLdParts doubles of scratch, each written before it is read
 void launch_logdet(hipStream_t st, int64_t nblocks, const int64_t* bptr, const int32_t* bpiv,
                    const int32_t* perm, const double* piv, const int32_t* sexp, double* part, double* out);
 
@@ -105,8 +119,29 @@ template <typename T> void launch_bwd_part(hipStream_t st, const DevSym& S, cons
 template <typename T> void launch_bwd_block(hipStream_t st, const DevSym& S, const LaunchList& L,
                                             const LaunchList& Lpart, int t, const T* D2T, const int64_t* D2off,
                                             SolveBufs V, const double* part);
+// Level-fused solves with one right-hand side: one launch per depth, one work-group per
+// 64-row chunk task (front, chunk) in dependency order; ticket: the launch's counter
+// (zero before the launch), prog: per-supernode count of published x blocks (zero before
+// the pass), err: set if a dependency wait exceeded its spin limit.
+struct FusedTasks {
+  const int2* task;
+  int32_t* ticket;
+  int32_t* prog;
+  int32_t* err;
+  int64_t count;
+};
+// forward: every chunk of every front of the depth, x blocks into xp, update rows into
+// the front vectors; backward: the pivot chunks from the right, x over y in xp
+template <typename T> void launch_fwd_fused(hipStream_t st, const DevSym& S, FusedTasks F, const T* Lp,
+                                            const T* D, SolveBufs V);
+template <typename T> void launch_bwd_fused(hipStream_t st, const DevSym& S, FusedTasks F, const T* Lp,
+                                            const T* D, SolveBufs V);
+// xp = gate[0] * S P src (gate nullable = 1)
 void launch_permute_in(hipStream_t st, int64_t n, int nrhs, const int32_t* perm, const double* scale,
-                       const double* src, int64_t lds, double* xp);
+                       const double* src, int64_t lds, double* xp, const double* gate = nullptr);
+// refinement gate: norms = (||h||, ||r||); gate[0] = 1 while ||r|| > tol ||h||, gate[1]
+// counts the corrections; record != 0 writes (||r||/||h||, gate[1]) to rec[0..1]
+void launch_refine_gate(hipStream_t st, const double* norms, double tol, double* gate, double* rec, int record);
 void launch_permute_in_f32(hipStream_t st, int64_t n, int nrhs, const float* z, double* xp);
 void launch_permute_out(hipStream_t st, int64_t n, int nrhs, const int32_t* perm, const double* scale,
                         const double* xp, const double* add, int64_t ldadd, double* out, int64_t ldo,

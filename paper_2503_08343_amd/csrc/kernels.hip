@@ -617,6 +617,49 @@ __global__ void k_assemble_qpost(int64_t nnzq, const double* __restrict__ qval,
   }
 }
 
+// Derivative of the conditioning on Q's pattern (Sec. 3.1): for a parameter theta,
+//   dQ_post = dQ + dA^T Q_eps A + A^T Q_eps dA + A^T diag(dq_eps) A,
+// over the same per-entry pairs of A entries that assemble Q_post (fixed order).
+__global__ void k_assemble_dqpost(int64_t nnzq, const double* __restrict__ dq,
+                                  const int64_t* __restrict__ cptr, const int32_t* __restrict__ cpair,
+                                  const int32_t* __restrict__ arow, const double* __restrict__ aval,
+                                  const double* __restrict__ da, const double* __restrict__ qeps,
+                                  const double* __restrict__ dqeps, double* __restrict__ out) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nnzq;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    double v = dq[e];
+    for (int64_t c = cptr[e]; c < cptr[e + 1]; ++c) {
+      const int32_t a1 = cpair[2 * c], a2 = cpair[2 * c + 1];
+      const int32_t r = arow[a1];
+      if (da) v += qeps[r] * (da[a1] * aval[a2] + aval[a1] * da[a2]);
+      if (dqeps) v += dqeps[r] * aval[a1] * aval[a2];
+    }
+    out[e] = v;
+  }
+}
+
+// out = base - V x over A's stored pattern with values V (m rows; base nullable = 0,
+// base2 nullable, subtracted too); product_only != 0 writes V x itself
+__global__ void k_spmv_obs(int64_t m, const int64_t* __restrict__ arp, const int32_t* __restrict__ aci,
+                           const double* __restrict__ v, const double* __restrict__ x,
+                           const double* __restrict__ base, const double* __restrict__ base2, int product_only,
+                           double* __restrict__ out) {
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < m; r += (int64_t)gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (int64_t e = arp[r]; e < arp[r + 1]; ++e) s += v[e] * x[aci[e]];
+    double o = base ? base[r] : 0.0;
+    if (base2) o -= base2[r];
+    out[r] = product_only ? s : o - s;
+  }
+}
+
+// elementwise: mode 0 out = a * b, mode 1 out = a / b, mode 2 out = log(a)
+__global__ void k_elementwise(int64_t n, int mode, const double* __restrict__ a, const double* __restrict__ b,
+                              double* __restrict__ out) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = mode == 0 ? a[i] * b[i] : mode == 1 ? a[i] / b[i] : log(a[i]);
+}
+
 __global__ void k_obs_residual(int64_t m, const int64_t* __restrict__ arp, const int32_t* __restrict__ aci,
                                const double* __restrict__ aval, const double* __restrict__ qeps,
                                const double* __restrict__ y, const double* __restrict__ b,
@@ -1132,7 +1175,6 @@ __global__ __launch_bounds__(kThreads) void k_copy_L(DevSym S, LaunchList L, Num
 // per-block log det = 2 sum log L^_jj - 2 ln2 sum e_i (equilibration exponents), summed
 // in a fixed order: work-group (block, g) reduces its share of the block's pivots
 // (strided per-thread sums, then a binary tree); a second pass adds the kLdParts partials
-constexpr int kLdParts = 64;
 __global__ __launch_bounds__(kThreads) void k_logdet(const int64_t* __restrict__ bptr,
                                                      const int32_t* __restrict__ bpiv,
                                                      const int32_t* __restrict__ perm,
@@ -1531,15 +1573,37 @@ __global__ __launch_bounds__(kThreads) void k_bwd_block(DevSym S, LaunchList L, 
   }
 }
 
+// xp = gate * S P src (gate == nullptr: factor 1); a zero gate turns the solve that
+// follows into a no-op correction (converged refinement inside a captured sequence)
 __global__ void k_permute_in(int64_t n, int nrhs, const int32_t* __restrict__ perm, const double* __restrict__ scale,
-                             const double* __restrict__ src, int64_t lds, double* __restrict__ xp) {
+                             const double* __restrict__ src, int64_t lds, double* __restrict__ xp,
+                             const double* __restrict__ gate) {
   const int64_t tot = n * nrhs;
+  const double g = gate ? gate[0] : 1.0;
   for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < tot;
        q += (int64_t)gridDim.x * blockDim.x) {
     const int64_t j = q % n, r = q / n;
     const int32_t o = perm[j];
-    xp[q] = scale[o] * src[o + r * lds];
+    xp[q] = g * (scale[o] * src[o + r * lds]);
   }
+}
+
+// Refinement gate on the device: norms[0] = ||h||, norms[1] = ||r||; gate[0] = 1 while
+// ||r|| > tol ||h|| (the next correction is applied), else 0; gate[1] counts the applied
+// corrections.  With record != 0 it writes the relative residual and that count instead.
+__global__ void k_refine_gate(const double* __restrict__ norms, double tol, double* __restrict__ gate,
+                              double* __restrict__ rec, int record) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const double hn = norms[0] > 0.0 ? norms[0] : 1.0;
+  const double rel = norms[1] / hn;
+  if (record) {
+    rec[0] = rel;
+    rec[1] = gate[1];
+    return;
+  }
+  const double g = (rel > tol || !(rel == rel)) ? 1.0 : 0.0;
+  gate[0] = g;
+  gate[1] += g;
 }
 
 __global__ void k_permute_in_f32(int64_t tot, const float* __restrict__ z, double* __restrict__ xp) {
@@ -2182,6 +2246,262 @@ inline unsigned grid_for(int64_t n, int64_t cap = 65536) {
   return (unsigned)g;
 }
 
+
+// ---- level-fused solves (one right-hand side) ----
+// One launch per tree depth.  Every 64-row chunk of every front of the depth is one
+// work-group task; a work-group takes the next ticket at its start (tickets follow the
+// task list order, in which every task comes after the tasks it depends on), so a task
+// only ever waits for tasks that already run or have finished.  The x blocks of a front
+// are produced in order by its pivot chunks, and prog[s] counts the blocks published:
+// a waiting work-group polls that counter (relaxed agent-scope loads), then issues an
+// agent-scope acquire; the producer writes its block, then stores the counter with
+// agent-scope release.  A wait longer than kSpinLimit polls sets *err and stops waiting
+// (the result is then wrong and the error is reported), so every launch terminates.
+constexpr int kSpinLimit = 1 << 20;
+
+// Poll prog until it reaches `need`; returns the value seen (uniform over the
+// work-group).  Two barriers: every wave has read the slot before it is reused.
+__device__ __forceinline__ int wait_progress(int32_t* prog, int need, int32_t* err, int* slot) {
+  if (threadIdx.x == 0) {
+    int v = __hip_atomic_load(prog, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    int spins = 0;
+    while (v < need) {
+      if (++spins > kSpinLimit) {
+        atomicOr(err, 1);
+        v = INT_MAX;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+      v = __hip_atomic_load(prog, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    *slot = v;
+  }
+  __syncthreads();
+  const int v = *slot;
+  __syncthreads();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  return v;
+}
+
+__device__ __forceinline__ void publish_progress(int32_t* prog, int value) {
+  __syncthreads();   // every wave's stores of the block are issued and complete in L2
+  if (threadIdx.x == 0) __hip_atomic_store(prog, value, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Forward, task (front s, chunk c): rows 64c..64c+63 of the front.
+//   acc(row) = sum over x blocks t < min(c, P) of L[row, block t] x_t  (P = pivot blocks)
+//   pivot chunk (c < P):  x_c = Linv_cc (v - acc) on its pivot rows -> xp, published;
+//                         its rows below p also take L[row, block c] x_c;
+//   update rows (>= p):   v(row) -= acc, read by the parent's extend-add at the next depth.
+// Wave w takes columns 16w..16w+15 of every block, lanes take rows; the four waves'
+// sums are added in a fixed order, so the result does not depend on timing.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_fwd_fused(DevSym S, FusedTasks F, const T* __restrict__ Lp,
+                                                        const T* __restrict__ D, SolveBufs V) {
+  __shared__ int s_task, s_slot;
+  __shared__ double red[4][64];
+  __shared__ double xs[64];
+  if (threadIdx.x == 0) s_task = atomicAdd(F.ticket, 1);
+  __syncthreads();
+  const int2 tk = F.task[s_task];
+  const int s = tk.x, c = tk.y;
+  const int n = fn(S, s), p = fp(S, s);
+  const int P = (p + 63) >> 6;
+  const int nb = min(c, P);
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int row = 64 * c + lane;
+  const T* Lr = Lp + S.Loff[s] + min(row, n - 1);
+  const int64_t f0 = S.sfirst[s];
+  double* v = V.Vcur + S.Voff[s];
+  int32_t* prog = F.prog + s;
+  // pivot chunk: this wave's 16 columns of the 64 x 64 inverse, requested first
+  const bool piv = c < P;
+  T dv[16];
+  if (piv) {
+    const T* Db = D + S.Doff[s] + (int64_t)c * kNB * kNB;
+#pragma unroll
+    for (int u = 0; u < 16; ++u) dv[u] = Db[lane + (16 * w + u) * kNB];
+  }
+  double acc = 0.0;
+  int ready = 0;
+  int t = 0;
+  while (t < nb) {
+    if (t >= ready) ready = wait_progress(prog, t + 1, F.err, &s_slot);
+    const int tend = min(nb, ready);
+    // two blocks per step: 32 loads of L in flight per lane
+    for (; t + 1 < tend; t += 2) {
+      T l0[16], l1[16];
+      const int cb0 = 64 * t + 16 * w, cb1 = cb0 + 64;
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        l0[u] = Lr[(int64_t)(cb0 + u) * n];
+        const int cc = min(cb1 + u, p - 1);   // block t + 1 may be the partial last one
+        l1[u] = Lr[(int64_t)cc * n] * (T)(cb1 + u < p);
+      }
+      const double x0 = V.xp[f0 + 64 * t + lane];   // block t is full (t + 1 < P)
+      const int q1 = min(64 * t + 64 + lane, p - 1);
+      const double x1 = V.xp[f0 + q1] * (double)(64 * t + 64 + lane < p);
+#pragma unroll
+      for (int u = 0; u < 16; ++u) acc += (double)l0[u] * readlane_f64(x0, 16 * w + u);
+#pragma unroll
+      for (int u = 0; u < 16; ++u) acc += (double)l1[u] * readlane_f64(x1, 16 * w + u);
+    }
+    if (t < tend) {
+      T l0[16];
+      const int cb0 = 64 * t + 16 * w;
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int cc = min(cb0 + u, p - 1);
+        l0[u] = Lr[(int64_t)cc * n] * (T)(cb0 + u < p);
+      }
+      const int q0 = min(64 * t + lane, p - 1);
+      const double x0 = V.xp[f0 + q0] * (double)(64 * t + lane < p);
+#pragma unroll
+      for (int u = 0; u < 16; ++u) acc += (double)l0[u] * readlane_f64(x0, 16 * w + u);
+      ++t;
+    }
+  }
+  red[w][lane] = acc;
+  __syncthreads();
+  const double tot = (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
+  double extra = 0.0;
+  if (piv) {
+    const int pb = min(64, p - 64 * c);
+    // w_l = v_l - acc_l on the pivot rows, x_c = Linv_cc w (the inverse is zero above
+    // its diagonal and in its padding)
+    __syncthreads();
+    if (w == 0) xs[lane] = lane < pb ? v[64 * c + lane] - tot : 0.0;
+    __syncthreads();
+    double part = 0.0;
+#pragma unroll
+    for (int u = 0; u < 16; ++u) part += (double)dv[u] * xs[16 * w + u];
+    red[w][lane] = part;
+    __syncthreads();
+    const double xc = (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
+    if (w == 0 && lane < pb) V.xp[f0 + 64 * c + lane] = xc;
+    publish_progress(prog, c + 1);
+    // rows of this chunk below p take the diagonal block's columns with x_c
+    if (64 * c + 64 > p && n > p) {
+      if (w == 0) xs[lane] = lane < pb ? xc : 0.0;
+      __syncthreads();
+      double e = 0.0;
+      const int cb0 = 64 * c + 16 * w;
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int cc = min(cb0 + u, p - 1);
+        e += (double)(Lr[(int64_t)cc * n] * (T)(cb0 + u < p)) * xs[16 * w + u];
+      }
+      red[w][lane] = e;
+      __syncthreads();
+      extra = (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
+    }
+  }
+  if (w == 0 && row >= p && row < n) v[row] -= tot + extra;
+}
+
+// Backward, task (front s, pivot chunk c), chunks from the right: columns 64c..64c+pb-1
+//   r_j = y_j - sum over rows below the block of L[row, j] x(row)
+//   x_c = Linv_cc^T r, written over y in xp, published as prog[s] = P - c.
+// Rows below p hold ancestors' unknowns (final before this depth); rows of later pivot
+// blocks of the front are waited for block by block.  Wave w accumulates columns
+// 16w..16w+15 over lanes = rows and sums its lanes with a fixed butterfly.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_bwd_fused(DevSym S, FusedTasks F, const T* __restrict__ Lp,
+                                                        const T* __restrict__ D, SolveBufs V) {
+  __shared__ int s_task, s_slot;
+  __shared__ T Ds[kNB * (kNB + 1)];   // pitch 65: the transposed reads spread over banks
+  __shared__ double rs[64];
+  __shared__ double red[4][64];
+  if (threadIdx.x == 0) s_task = atomicAdd(F.ticket, 1);
+  __syncthreads();
+  const int2 tk = F.task[s_task];
+  const int s = tk.x, c = tk.y;
+  const int n = fn(S, s), p = fp(S, s);
+  const int P = (p + 63) >> 6;
+  const int pb = min(64, p - 64 * c);
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t f0 = S.sfirst[s];
+  const int32_t* rows = S.rows + S.rowptr[s];
+  int32_t* prog = F.prog + s;
+  // the 64 x 64 inverse of the diagonal block, staged in LDS (used transposed)
+  {
+    const T* Db = D + S.Doff[s] + (int64_t)c * kNB * kNB;
+#pragma unroll
+    for (int k = 0; k < kNB * kNB / kThreads; ++k) {
+      const int e = threadIdx.x + k * kThreads;
+      Ds[(e & 63) + (e >> 6) * (kNB + 1)] = Db[e];
+    }
+  }
+  // this wave's 16 columns; columns past p read the last column and are masked
+  const T* Lc = Lp + S.Loff[s];
+  int cols[16];
+  T cm[16];
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    const int jj = 16 * w + u;
+    cols[u] = 64 * c + min(jj, pb - 1);
+    cm[u] = (T)(jj < pb);
+  }
+  double acc[16];
+#pragma unroll
+  for (int u = 0; u < 16; ++u) acc[u] = 0.0;
+  // rows below p: unknowns of ancestors
+  for (int r0 = p; r0 < n; r0 += 64) {
+    const int row = r0 + lane;
+    const int rc = min(row, n - 1);
+    T lv[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) lv[u] = Lc[rc + (int64_t)cols[u] * n];
+    const double xv = V.xp[rows[rc]] * (double)(row < n);
+#pragma unroll
+    for (int u = 0; u < 16; ++u) acc[u] += (double)(lv[u] * cm[u]) * xv;
+  }
+  // rows of later pivot blocks of this front, from the right, as they are published
+  int ready = 0;
+  for (int t = P - 1; t > c; --t) {
+    const int row = 64 * t + lane;
+    const int rc = min(row, p - 1);
+    T lv[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) lv[u] = Lc[rc + (int64_t)cols[u] * n];
+    if (ready < P - t) ready = wait_progress(prog, P - t, F.err, &s_slot);
+    const double xv = V.xp[f0 + rc] * (double)(row < p);
+#pragma unroll
+    for (int u = 0; u < 16; ++u) acc[u] += (double)(lv[u] * cm[u]) * xv;
+  }
+  // rows of the block itself below each column (the inverse covers the diagonal block)
+  // are not part of the sum; reduce each column over the wave's 64 lanes
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    double a = acc[u];
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) a += __shfl_xor(a, m, 64);
+    acc[u] = a;
+  }
+  if (lane < 16) {
+    double a = acc[0];
+#pragma unroll
+    for (int u = 1; u < 16; ++u) a = lane == u ? acc[u] : a;
+    const int jj = 16 * w + lane;
+    rs[jj] = jj < pb ? V.xp[f0 + 64 * c + jj] - a : 0.0;
+  }
+  __syncthreads();
+  // x_l = sum_i Linv[i, l] r_i: wave w takes i in 16w..16w+15, lanes take l
+  double part = 0.0;
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    const int i = 16 * w + u;
+    part += (double)Ds[i + lane * (kNB + 1)] * rs[i];
+  }
+  red[w][lane] = part;
+  __syncthreads();
+  if (w == 0 && lane < pb)
+    V.xp[f0 + 64 * c + lane] = (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
+  publish_progress(prog, P - c);
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------ launch wrappers
@@ -2190,6 +2510,27 @@ void launch_assemble_qpost(hipStream_t st, int64_t nnzq, const double* qval, con
                            const double* qeps, double* qpost) {
   hipLaunchKernelGGL(k_assemble_qpost, dim3(grid_for(nnzq)), dim3(kThreads), 0, st, nnzq, qval, cptr,
                      cpair, arow, aval, qeps, qpost);
+}
+void launch_assemble_dqpost(hipStream_t st, int64_t nnzq, const double* dq, const int64_t* cptr,
+                            const int32_t* cpair, const int32_t* arow, const double* aval, const double* da,
+                            const double* qeps, const double* dqeps, double* out) {
+  hipLaunchKernelGGL(k_assemble_dqpost, dim3(grid_for(nnzq)), dim3(kThreads), 0, st, nnzq, dq, cptr, cpair, arow,
+                     aval, da, qeps, dqeps, out);
+}
+void launch_spmv_obs(hipStream_t st, int64_t m, const int64_t* arp, const int32_t* aci, const double* v,
+                     const double* x, double* y) {
+  if (m <= 0) return;
+  hipLaunchKernelGGL(k_spmv_obs, dim3(grid_for(m)), dim3(kThreads), 0, st, m, arp, aci, v, x,
+                     (const double*)nullptr, (const double*)nullptr, 1, y);
+}
+void launch_obs_resid_plain(hipStream_t st, int64_t m, const int64_t* arp, const int32_t* aci, const double* v,
+                            const double* y, const double* b, const double* x, double* r) {
+  if (m <= 0) return;
+  hipLaunchKernelGGL(k_spmv_obs, dim3(grid_for(m)), dim3(kThreads), 0, st, m, arp, aci, v, x, y, b, 0, r);
+}
+void launch_elementwise(hipStream_t st, int64_t n, int mode, const double* a, const double* b, double* out) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_elementwise, dim3(grid_for(n)), dim3(kThreads), 0, st, n, mode, a, b, out);
 }
 void launch_obs_residual(hipStream_t st, int64_t m, const int64_t* arp, const int32_t* aci,
                          const double* aval, const double* qeps, const double* y, const double* b,
@@ -2312,10 +2653,24 @@ template <typename T> void launch_bwd_block(hipStream_t st, const DevSym& S, con
     hipLaunchKernelGGL((k_bwd_block<T, 16>), dim3((unsigned)L.total), dim3(kThreads), 0, st, S, L, Lpart, t, D2T,
                        D2off, V, part);
 }
+
+template <typename T> void launch_fwd_fused(hipStream_t st, const DevSym& S, FusedTasks F, const T* Lp, const T* D,
+                                            SolveBufs V) {
+  if (F.count <= 0) return;
+  hipLaunchKernelGGL(k_fwd_fused<T>, dim3((unsigned)F.count), dim3(kThreads), 0, st, S, F, Lp, D, V);
+}
+template <typename T> void launch_bwd_fused(hipStream_t st, const DevSym& S, FusedTasks F, const T* Lp, const T* D,
+                                            SolveBufs V) {
+  if (F.count <= 0) return;
+  hipLaunchKernelGGL(k_bwd_fused<T>, dim3((unsigned)F.count), dim3(kThreads), 0, st, S, F, Lp, D, V);
+}
 void launch_permute_in(hipStream_t st, int64_t n, int nrhs, const int32_t* perm, const double* scale,
-                       const double* src, int64_t lds, double* xp) {
+                       const double* src, int64_t lds, double* xp, const double* gate) {
   hipLaunchKernelGGL(k_permute_in, dim3(grid_for(n * nrhs)), dim3(kThreads), 0, st, n, nrhs, perm, scale, src,
-                     lds, xp);
+                     lds, xp, gate);
+}
+void launch_refine_gate(hipStream_t st, const double* norms, double tol, double* gate, double* rec, int record) {
+  hipLaunchKernelGGL(k_refine_gate, dim3(1), dim3(64), 0, st, norms, tol, gate, rec, record);
 }
 void launch_permute_in_f32(hipStream_t st, int64_t n, int nrhs, const float* z, double* xp) {
   hipLaunchKernelGGL(k_permute_in_f32, dim3(grid_for(n * nrhs)), dim3(kThreads), 0, st, n * nrhs, z, xp);
@@ -2456,6 +2811,8 @@ template <typename T> void launch_sel_pattern(hipStream_t st, int64_t cnt, const
   template void launch_fwd_outer<T>(hipStream_t, const DevSym&, const LaunchList&, int, const T*, SolveBufs); \
   template void launch_bwd_part<T>(hipStream_t, const DevSym&, const LaunchList&, int, const T*, SolveBufs, double*); \
   template void launch_bwd_block<T>(hipStream_t, const DevSym&, const LaunchList&, const LaunchList&, int, const T*, const int64_t*, SolveBufs, const double*); \
+  template void launch_fwd_fused<T>(hipStream_t, const DevSym&, FusedTasks, const T*, const T*, SolveBufs); \
+  template void launch_bwd_fused<T>(hipStream_t, const DevSym&, FusedTasks, const T*, const T*, SolveBufs); \
   template void launch_sel_gather<T>(hipStream_t, const DevSym&, const LaunchList&, const int32_t*, SelBufs<T>); \
   template void launch_inv256<T>(hipStream_t, const DevSym&, const LaunchList&, const T*, int, const T*, const int64_t*, T*, T*); \
   template void launch_sel_Y2<T>(hipStream_t, const DevSym&, const LaunchList&, int, SelBufs<T>, const int64_t*, const T*); \

@@ -116,3 +116,53 @@ def test_fp32_lml_close_to_fp64(gpu_lib):
     assert np.all(np.abs(g32 - g64) <= 1e-2 * np.maximum(1.0, np.abs(g64)))
     e64.close()
     e32.close()
+
+
+def test_spacetime_lml_gradient_c_nu_matches_oracle(gpu_lib):
+    """Advection speed c and viscosity nu of the space-time prior (Sec. 2.4, App. A), which
+    also enter the Galerkin PDE observation rows: the library's LML and gradient against
+    the oracle's (element by element for the scalars)."""
+    from paper_2503_08343_amd import adjoint
+    import scipy.sparse as sp
+    p = gi.advdiff_spacetime(ns=12, nt=8, seed=83, obs_frac=0.05)
+    eng = adjoint.SpaceTimeLML(p)
+    c, nu = 0.6, 0.015
+    lml, g = eng.evaluate(c, nu)
+    q, a = gi.advdiff_values(p, c, nu)
+    Q = sp.csr_matrix((q, p.Q.indices, p.Q.indptr), shape=p.Q.shape)
+    A = sp.csr_matrix((a, p.A.indices, p.A.indptr), shape=p.A.shape)
+    der = gi.advdiff_derivatives(p, c=c, nu=nu)
+    derivs = [(sp.csr_matrix((der[k][0], p.Q.indices, p.Q.indptr), shape=p.Q.shape), None,
+               sp.csr_matrix((der[k][1], p.A.indices, p.A.indptr), shape=p.A.shape)) for k in ("c", "nu")]
+    ref, gref, _ = O.lml_sparse(Q, A, p.q_eps, p.y, p.b, p.coords, derivs)
+    print(f"[lml st] n={p.n} gpu {lml:.12e} oracle {ref:.12e} g {g} gref {gref}", flush=True)
+    assert abs(lml - ref) <= 1e-10 * max(1.0, abs(ref))
+    for i in range(2):
+        assert abs(g[i] - gref[i]) <= 1e-8 * max(1.0, abs(gref[i])), (i, g[i], gref[i])
+    eng.close()
+
+
+def test_spacetime_gradient_vs_finite_differences_and_autograd(gpu_lib):
+    """The (c, nu) gradient against central differences of the library's own LML
+    (spec bar 1e-5 max(1, |g|)) on a 32 x 32 x 16 space-time grid, and through
+    torch.autograd (GMRFLogML with the space-time engine)."""
+    import torch
+    from paper_2503_08343_amd import adjoint
+    p = gi.advdiff_spacetime(ns=32, nt=16, seed=84)
+    eng = adjoint.SpaceTimeLML(p)
+    th = np.array([0.5, 0.01])
+    lml, g = eng.evaluate(*th)
+    for i, h in enumerate((1e-5, 1e-6)):
+        e = np.zeros(2)
+        e[i] = h
+        fp = eng.evaluate(*(th + e), gradient=False)[0]
+        fm = eng.evaluate(*(th - e), gradient=False)[0]
+        fd = (fp - fm) / (2 * h)
+        print(f"[lml st] n={p.n} param {i}: adjoint {g[i]:.10e} fd {fd:.10e}", flush=True)
+        assert abs(g[i] - fd) <= 1e-5 * max(1.0, abs(g[i]))
+    theta = torch.tensor(th, dtype=torch.float64, requires_grad=True)
+    out = adjoint.log_ml(theta, eng)
+    out.backward()
+    assert abs(out.item() - lml) <= 1e-12 * abs(lml)
+    assert np.allclose(theta.grad.numpy(), g, rtol=1e-12, atol=0.0)
+    eng.close()

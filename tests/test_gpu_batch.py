@@ -47,7 +47,6 @@ def test_batch_full_size(gpu_lib, batch, precision):
     # element-wise parity on the smallest blocks
     sizes = np.diff(p.block_ptr)
     small = np.argsort(sizes)[:4]
-    tol_mu, tol_var, tol_ld = (1e-10, 1e-10, 1e-10) if precision == 0 else (1e-8, 5e-3, 1e-6)
     for b in small:
         sub = gi.batch_block(p, int(b))
         r = O.posterior(sub)
@@ -55,16 +54,35 @@ def test_batch_full_size(gpu_lib, batch, precision):
         e_mu = np.linalg.norm(mu[lo:hi] - r["mean"]) / np.linalg.norm(r["mean"])
         e_var = np.max(np.abs(var[lo:hi] - r["var"]) / r["var"])
         e_ld = abs(ld[b] - r["logdet"]) / abs(r["logdet"])
-        print(f"[batch] block {b} n={hi - lo} mean {e_mu:.2e} var {e_var:.2e} logdet {e_ld:.2e}", flush=True)
-        assert e_mu <= tol_mu and e_var <= tol_var and e_ld <= tol_ld
+        if precision == 0:
+            kappa, bvar, bld = float("nan"), 1e-10, 1e-10
+            assert e_mu <= 1e-10
+        else:
+            # first-order FP32 bounds c kappa u32 (variances) and c n kappa u32 (log-det,
+            # absolute), and 10x of the errors measured on MI355X
+            kappa = O.condition_number(r["Qpost"])[0]
+            v_m, l_m = BATCH_FP32_MEASURED[int(b)]
+            bvar = min(C_BOUND * kappa * O.U32, 10.0 * v_m)
+            bld = min(C_BOUND * (hi - lo) * kappa * O.U32 / abs(r["logdet"]), 10.0 * l_m)
+            assert e_mu <= 1e-8
+        print(f"[batch] block {b} n={hi - lo} kappa {kappa:.3e} mean {e_mu:.2e} var {e_var:.2e} (tol {bvar:.2e}) "
+              f"logdet {e_ld:.2e} (tol {bld:.2e})", flush=True)
+        assert e_var <= bvar and e_ld <= bld
     # samples: (x - mu)^T Q_post (x - mu) = z^T z per right-hand side, whole batch
     Qp, _ = O.assemble(p.Q, p.A, p.q_eps, p.y)
     for r_ in range(k):
         d = x[r_] - mu
         zz = float(z[r_].astype(np.float64) @ z[r_].astype(np.float64))
         rel = abs(d @ (Qp @ d) - zz) / zz
+        print(f"[batch] sample {r_}: quadratic form / z'z - 1 = {rel:.3e}", flush=True)
         assert rel <= (1e-9 if precision == 0 else 1e-3), rel
     ctx.close()
+
+
+C_BOUND = 10.0
+# FP32 errors of the four smallest blocks measured on MI355X: (variances, log-det), relative
+BATCH_FP32_MEASURED = {196: (1.65e-4, 4.86e-8), 130: (3.20e-5, 7.10e-9), 233: (9.52e-5, 8.35e-8),
+                       210: (4.03e-3, 5.76e-7)}
 
 
 def test_batch_prior_logdet_identity(gpu_lib, batch):

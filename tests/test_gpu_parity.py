@@ -2,7 +2,9 @@
 seeded inputs at sizes the oracle finishes in seconds that still span several tiles,
 multi-block fronts and ragged tails.  FP64 results must match the oracle within 1e-10
 (relative); the FP32-factor path must give the mean within 1e-8 after FP64 refinement,
-and variances / log-det within the first-order bound of its rounding (c kappa u32)."""
+and variances / log-det within the first-order bound of its rounding (c kappa u32, with
+kappa the condition number of the Jacobi-scaled posterior precision) and within 10x of
+the errors measured on the device."""
 import math
 
 import numpy as np
@@ -16,6 +18,19 @@ pytestmark = pytest.mark.gpu
 
 def _rel(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+# FP32 bounds (first order in the factor's backward error E, ||E|| <= c u32 ||Q^||, on the
+# Jacobi-scaled posterior precision Q^ with condition number kappa): relative variance
+# error and sample quadratic-form error <= c kappa u32 (|dSigma_ii| <= ||E|| ||Sigma|| Sigma_ii,
+# z^T L^-1 E L^-T z <= ||E|| / lambda_min z^T z); absolute log-det error <= c n kappa u32
+# (|tr(Sigma E)| <= n ||E|| / lambda_min).  c = 10 covers the accumulation constants.
+C_BOUND = 10.0
+
+
+def _fp32_bound(Qp):
+    kappa, lo, hi = O.condition_number(Qp)
+    return kappa, C_BOUND * kappa * O.U32
 
 
 def _run(gpu_lib, p, precision, refine=0, tol=0.0, opts=None):
@@ -65,19 +80,36 @@ def test_fp64_mean_var_logdet_match_oracle(gpu_lib, name):
 
 # FP32 factor / selected inversion (long products as six bf16 term products on the matrix
 # cores) on the cases with multi-block fronts and ragged tails: mean within 1e-8 after FP64
-# refinement, variances and log-det within the first-order bound of FP32 rounding
+# refinement; variances and log-det within the first-order bound c kappa u32 of FP32
+# rounding, and within about 10x of the error measured on MI355X (a regression guard:
+# FP32_MEASURED holds the errors measured with the current kernels).
+FP32_MEASURED = {
+    # name: (max relative variance error, relative log-det error)
+    "matern2d_45_ragged": (1.420e-05, 1.520e-08),
+    "matern3d_12": (1.000e-06, 2.250e-09),
+    "spacetime_24x24x16_multiblock": (2.975e-05, 7.611e-09),
+    "spacetime_20x20x10": (1.491e-05, 1.081e-08),
+}
+
+
 @pytest.mark.parametrize("name", ["matern2d_45_ragged", "matern3d_12", "spacetime_24x24x16_multiblock"])
 def test_fp32_refine_matches_oracle(gpu_lib, name):
     p, r = _oracle(name)
     print(f"[case fp32] {name} n={p.n}", flush=True)
     ctx, ld, mu, var, it, res = _run(gpu_lib, p, gpu_lib.GMRF_FP32_REFINE, refine=30, tol=1e-14)
     vrel = float(np.max(np.abs(var - r["var"]) / r["var"]))
-    ldrel = abs(ld[0] - r["logdet"]) / abs(r["logdet"])
-    print(f"[case fp32] {name}: iters={it} resid={res:.3e} mean {_rel(mu, r['mean']):.3e} "
-          f"var {vrel:.3e} logdet {ldrel:.3e}", flush=True)
+    ldabs = abs(ld[0] - r["logdet"])
+    kappa, bound = _fp32_bound(r["Qpost"])
+    print(f"[case fp32] {name}: kappa={kappa:.3e} bound c*kappa*u32={bound:.3e} iters={it} resid={res:.3e} "
+          f"mean {_rel(mu, r['mean']):.3e} var {vrel:.3e} logdet abs {ldabs:.3e} "
+          f"rel {ldabs / abs(r['logdet']):.3e} (bound n*c*kappa*u32 = {p.n * bound:.3e})", flush=True)
     assert _rel(mu, r["mean"]) <= 1e-8
-    assert vrel <= 5e-3
-    assert ldrel <= 1e-5
+    assert vrel <= bound
+    assert ldabs <= p.n * bound
+    if name in FP32_MEASURED:
+        v_m, ld_m = FP32_MEASURED[name]
+        assert vrel <= 10.0 * v_m
+        assert ldabs / abs(r["logdet"]) <= 10.0 * ld_m
     assert ctx.stats()["failed_index"] == -1
     ctx.close()
 
@@ -108,12 +140,24 @@ def test_samples_match_oracle_with_library_pivot_order(gpu_lib, precision):
     xo = O.sample(F, mu_o, z)
     if precision == 0:
         assert np.max(np.abs(x - xo)) <= 1e-10 * np.max(np.abs(xo - mu_o[:, None]))
-    # ordering-free identity (x - mu)^T Q_post (x - mu) = z^T z
+    # ordering-free identity (x - mu)^T Q_post (x - mu) = z^T z; FP32 factor: within
+    # c kappa u32 and within 10x of the error measured on MI355X (SAMPLE_FP32_MEASURED)
+    if precision == 0:
+        tolr = 1e-9
+    else:
+        kappa, tolr = _fp32_bound(Qp)
+        if SAMPLE_FP32_MEASURED is not None:
+            tolr = min(tolr, 10.0 * SAMPLE_FP32_MEASURED)
+    errs = []
     for c in range(k):
         d = x[:, c] - mu.cpu().numpy()
         zz = float(z[:, c].astype(np.float64) @ z[:, c].astype(np.float64))
-        tolr = 1e-9 if precision == 0 else 2e-2
-        assert abs(d @ (Qp @ d) - zz) <= tolr * zz
+        errs.append(abs(d @ (Qp @ d) - zz) / zz)
+    print(f"[samples p={precision}] quadratic-form errors {max(errs):.3e} (tolerance {tolr:.3e})", flush=True)
+    assert max(errs) <= tolr
+
+
+SAMPLE_FP32_MEASURED = 1.197e-07   # max relative quadratic-form error of the FP32 samples
 
 
 def test_fp32_refine_mean_and_bounds(gpu_lib):
@@ -124,9 +168,14 @@ def test_fp32_refine_mean_and_bounds(gpu_lib):
     assert _rel(mu, r["mean"]) <= 1e-8
     vrel = np.max(np.abs(var - r["var"]) / r["var"])
     ldrel = abs(ld[0] - r["logdet"]) / abs(r["logdet"])
-    print(f"[fp32] var max rel err {vrel:.3e}  logdet rel err {ldrel:.3e}", flush=True)
-    assert vrel <= 5e-3
-    assert ldrel <= 1e-5
+    kappa, bound = _fp32_bound(r["Qpost"])
+    print(f"[fp32] kappa={kappa:.3e} bound={bound:.3e} var max rel err {vrel:.3e}  logdet rel err {ldrel:.3e}",
+          flush=True)
+    assert vrel <= bound
+    assert abs(ld[0] - r["logdet"]) <= p.n * bound
+    if "spacetime_20x20x10" in FP32_MEASURED:
+        v_m, ld_m = FP32_MEASURED["spacetime_20x20x10"]
+        assert vrel <= 10.0 * v_m and ldrel <= 10.0 * ld_m
 
 
 def test_batched_block_logdets_and_outputs(gpu_lib):
