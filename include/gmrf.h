@@ -143,6 +143,18 @@ gmrf_status gmrf_factor(gmrf_t h, gmrf_precision p);
 /* log det Q_post (host output, one value per block of gmrf_assemble). */
 gmrf_status gmrf_logdet(gmrf_t h, double* out);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, serving
+   loops, harnesses that forbid hipMalloc): the log-determinant of gmrf_logdet written to
+   DEVICE memory, with no allocation, no host synchronisation and no status check.
+   out_dev: n_blocks doubles (device), one per block of gmrf_assemble, bitwise equal to
+   gmrf_logdet's values.  The per-block partial sums live in a fixed 4 MiB workspace of
+   the library on each device (at most 8192 blocks; more returns GMRF_ERR_ARG before
+   anything is enqueued).  Every partial is written before it is read, so nothing needs
+   clearing; calls that overlap on one device (several contexts or streams) share that
+   workspace and race.  A failed factorisation is reported by the next synchronising call
+   (the value is then meaningless).  Asynchronous on the context's stream. */
+gmrf_status gmrf_logdet_noalloc(gmrf_t h, double* out_dev);
+
 /* Posterior mean (Sec. 3.1 eq. posterior-mean; Sec. 3.2: one forward and one backward
    solve).  mu_out: n entries (device).  In GMRF_FP32_REFINE (and in GMRF_FP64 when
    max_refine > 0) iterative refinement with FP64 residuals r = h - Q_post x runs until

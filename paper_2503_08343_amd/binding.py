@@ -31,7 +31,7 @@ EXPORTS = ["gmrf_create", "gmrf_destroy", "gmrf_assemble", "gmrf_update_values",
            "gmrf_stats", "gmrf_pivot_order", "gmrf_phase_ms", "gmrf_last_error",
            "gmrf_symbolic_host", "gmrf_profile", "gmrf_kernel_stats", "gmrf_matern_values",
            "gmrf_spmv", "gmrf_misfit", "gmrf_solve_rhs", "gmrf_gn_burgers", "gmrf_launch_records",
-           "gmrf_lml_gradient"]
+           "gmrf_logdet_noalloc", "gmrf_lml_gradient"]
 
 
 class gmrf_options(ctypes.Structure):
@@ -119,6 +119,7 @@ def load():
         "gmrf_gn_burgers": ([P, i64, i64, d, d, P, P, ctypes.c_int, ctypes.c_int, ctypes.c_int, d,
                              ctypes.c_int, P, P], i32),
         "gmrf_kernel_stats": ([P, P, ctypes.c_int, P], i32),
+        "gmrf_logdet_noalloc": ([P, P], i32),
         "gmrf_lml_gradient": ([P, P, ctypes.c_int, P, P, P, ctypes.c_int, d, P, P], i32),
         "gmrf_launch_records": ([P, P, ctypes.c_int64, P], i32),
     }
@@ -252,6 +253,12 @@ class Context:
     def logdet(self):
         out = np.zeros(self.nblocks)
         self._check(self.lib.gmrf_logdet(self.h, _np_ptr(out)))
+        return out
+
+    def logdet_noalloc(self, out):
+        """Log-determinant per block into the device tensor `out` (float64, n_blocks),
+        asynchronous, through the library's fixed workspace (no allocation)."""
+        self._check(self.lib.gmrf_logdet_noalloc(self.h, _t_ptr(out)))
         return out
 
     def solve(self, max_refine=0, tol=0.0, out=None, raise_not_converged=True):

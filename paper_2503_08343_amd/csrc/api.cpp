@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <chrono>
 #include <climits>
+#include <mutex>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -21,6 +22,14 @@
 
 using namespace gmrf;
 
+// Workspace of gmrf_logdet_noalloc: the per-block partial sums of the log-determinant
+// (kLdParts per block) in a fixed device array, so that the call allocates nothing.
+// Each device holds its own copy for the life of the process (4 MiB); its device
+// address is looked up once per device (gmrf_create) and only that address is handed
+// to kernels.
+constexpr int64_t kNoAllocMaxBlocks = 8192;
+
+static __device__ __align__(256) double scratch[kNoAllocMaxBlocks * kLdParts];
 
 namespace {
 
@@ -50,6 +59,9 @@ struct DevArr {
 
 enum : int { ST_ASSEMBLED = 1, ST_ANALYZED = 2, ST_FACTORED = 4, ST_SOLVED = 8 };
 
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices] = {};   // device address of `scratch` per device
 
 struct HostList {  // a launch list before upload
   int64_t f_off = 0, p_off = 0;
@@ -1191,6 +1203,19 @@ gmrf_status gmrf_create(gmrf_t* out, int device, void* hip_stream) {
   for (auto& e : h->ev) {
     if (hipEventCreate(&e) != hipSuccess) { delete h; return GMRF_ERR_HIP; }
   }
+  // device address of the no-allocation workspace, once per device (this device is current)
+  if (device < kMaxDevices) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[device]) {
+      void* ptr = nullptr;
+      if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+        for (auto& e : h->ev) (void)hipEventDestroy(e);
+        delete h;
+        return GMRF_ERR_HIP;
+      }
+      g_scratch_dev[device] = ptr;
+    }
+  }
   *out = h;
   return GMRF_OK;
 }
@@ -1427,6 +1452,21 @@ gmrf_status gmrf_logdet(gmrf_t h, double* out) {
   HIPCHK(h, hipGetLastError());
   HIPCHK(h, hipMemcpyAsync(out, h->d_ld.p, h->nblocks * sizeof(double), hipMemcpyDeviceToHost, h->stream));
   HIPCHK(h, hipStreamSynchronize(h->stream));
+  return GMRF_OK;
+}
+
+gmrf_status gmrf_logdet_noalloc(gmrf_t h, double* out_dev) {
+  if (!h || !out_dev) return fail(h, GMRF_ERR_ARG, "null argument");
+  if (h->nblocks > kNoAllocMaxBlocks)
+    return fail(h, GMRF_ERR_ARG, "gmrf_logdet_noalloc: " + std::to_string(h->nblocks) +
+                                     " blocks exceed its workspace of " + std::to_string(kNoAllocMaxBlocks));
+  if (!(h->state & ST_FACTORED)) return fail(h, GMRF_ERR_STATE, "gmrf_logdet_noalloc before gmrf_factor");
+  void* ws = h->device < kMaxDevices ? g_scratch_dev[h->device] : nullptr;
+  if (!ws) return fail(h, GMRF_ERR_STATE, "no-allocation workspace unavailable on this device");
+  // every partial is written before it is read: nothing to clear; no profiler events
+  launch_logdet(h->stream, h->nblocks, h->d_bptr.p, h->d_bpiv.p, h->d_perm.p, h->d_piv.p, h->d_sexp.p,
+                (double*)ws, out_dev);
+  HIPCHK(h, hipGetLastError());
   return GMRF_OK;
 }
 
