@@ -8,8 +8,13 @@ refinement in the FP32 mode), one posterior sample and Takahashi selected invers
 
 value = (F_factor + F_solve (mean) + F_solve/2 (one sample) + F_selinv) / step time,
 with the algorithmic counts of the exact L pattern: F_factor = sum_j c_j^2,
-F_selinv = 2 sum_j c_j^2, F_solve = 4 nnz(L) - 2n.  The headline mode is the FP32
-factor with FP64 pivots and FP64 refinement; the FP64 mode is reported beside it.
+F_selinv = 2 sum_j c_j^2, F_solve = 4 nnz(L) - 2n.  The step time is the wall time of
+the whole step as the library runs it: the selected inversion on its second stream
+overlaps the log-det, the refined mean and the sample of the same factor.  The phase-sum
+form F / (t_factor + t_solve + t_selinv) is reported beside it from one extra step run
+without the overlap (metric_gflops_phase_sum), with each phase timed alone.  The
+headline mode is the FP32 factor with FP64 pivots and FP64 refinement; the FP64 mode is
+reported beside it.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -98,7 +103,21 @@ def run_mode(binding, ctx, dev, prob, precision, steps, warmup, z_kn, profile):
         ctx.profile(False)
     for k in phases:
         phases[k] /= steps
-    return wall, phases, out, (breakdown, dom, live)
+    # one step without the overlap: each phase alone, timed with the library's events
+    ctx.update_values(q_data=dev["q_data"], a_data=dev["a_data"], q_eps=dev["q_eps"], y=dev["y"])
+    ctx.factor(precision)
+    ctx.logdet()
+    ctx.solve(max_refine=30 if precision == binding.GMRF_FP32_REFINE else 0, tol=tol, raise_not_converged=False)
+    ph_solve_mean = ctx.phase_ms()["solve"]
+    torch.cuda.synchronize()
+    ts0 = time.perf_counter()
+    ctx.sample(z_kn)
+    torch.cuda.synchronize()
+    t_sample = (time.perf_counter() - ts0) * 1e3
+    ctx.selinv()
+    ph = ctx.phase_ms()
+    seq = dict(factor=ph["factor"], solve=ph_solve_mean + t_sample, selinv=ph["selinv"])
+    return wall, phases, out, (breakdown, dom, live), seq
 
 
 def cpu_baseline():
@@ -119,7 +138,7 @@ def cpu_baseline():
     return dict(value=flops / t / 1e9, unit="GFLOP/s", cores=1, kind="oracle",
                 sample="advdiff_spacetime 32x32x16 (16,384 dofs): oracle factor + log-det + mean + "
                        f"Takahashi selinv, {t:.1f} s, plain C on one host thread",
-                seconds=t)
+                seconds=t, host_cores=os.cpu_count())
 
 
 def secondary(binding, which, steps, warmup):
@@ -264,14 +283,13 @@ def main():
     for mname in modes:
         prec = binding.GMRF_FP32_REFINE if mname == "fp32" else binding.GMRF_FP64
         log(f"[bench] mode {mname}: warmup {args.warmup}, steps {args.steps}")
-        wall, ph, out, ks = run_mode(binding, ctx, dev, prob, prec, args.steps, args.warmup, z_kn,
-                                     profile=(mname == modes[0]))
+        wall, ph, out, ks, seq = run_mode(binding, ctx, dev, prob, prec, args.steps, args.warmup, z_kn,
+                                          profile=(mname == modes[0]))
         ld, mu, it, rr, x, var = out
         res[mname] = dict(wall=wall, phases=ph, logdet=float(ld[0]), mu=mu.cpu().numpy(),
-                          var=var.cpu().numpy(), iters=it, resid=rr, x=x.cpu().numpy()[0], ks=ks)
+                          var=var.cpu().numpy(), iters=it, resid=rr, x=x.cpu().numpy()[0], ks=ks, seq=seq)
         log(f"[bench] mode {mname}: {wall*1e3:.1f} ms/step phases {ph} refine iters {it} resid {rr:.2e}")
     F = st["flops_factor"] + st["flops_solve"] * 1.5 + st["flops_selinv"]
-    F_metric = st["flops_factor"] + st["flops_solve"] + st["flops_selinv"]
     head = modes[0]
     hr = res[head]
     prec_head = 1 if head == "fp32" else 0
@@ -310,7 +328,8 @@ def main():
                    "flops_solve": st["flops_solve"], "max_front": st["max_front"],
                    "analyze_s": round(t_an, 2)},
         "phases_ms": {k: round(v, 2) for k, v in hr["phases"].items()},
-        "metric_gflops_phases": round(F_metric / (sum(hr["phases"].values()) * 1e-3) / 1e9, 2),
+        "phases_alone_ms": {k: round(v, 2) for k, v in hr["seq"].items()},
+        "metric_gflops_phase_sum": round(F / (sum(hr["seq"].values()) * 1e-3) / 1e9, 2),
         "path_roofline_frac": round(t_roof / hr["wall"], 4),
         "roofline": roof,
         "refine": {"iters": hr["iters"], "rel_resid": hr["resid"]},
@@ -332,6 +351,24 @@ def main():
     # sanity of the headline results: positive variances, finite log-det
     out["checks"] = {"var_positive": bool(np.all(hr["var"] > 0)), "logdet": hr["logdet"],
                      "logdet_finite": bool(math.isfinite(hr["logdet"]))}
+    # the triangular solves alone (no overlap): one forward and one backward pass over L of
+    # the headline factor, HBM-bound (bytes of L read per pass / time)
+    ctx.factor(prec_head)
+    rhs = torch.from_numpy(np.random.Generator(np.random.PCG64(9)).standard_normal(prob.n)).cuda()
+    xs = ctx.solve_rhs(rhs)
+    ts = []
+    for _ in range(5):
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        ctx.solve_rhs(rhs, out=xs)
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t1)
+    t_sv = float(np.median(ts))
+    gb = 2.0 * st["nnz_l"] * w / 1e9
+    out["solve_alone"] = {"ms_forward_backward": round(t_sv * 1e3, 3), "GB_of_L": round(gb, 3),
+                          "achieved_GBs": round(gb / t_sv, 1), "peak_GBs": HBM_GBS,
+                          "frac": round(gb / t_sv / HBM_GBS, 4)}
+    log(f"[bench] solve alone: {t_sv * 1e3:.2f} ms forward+backward ({gb / t_sv:.0f} GB/s)")
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle on a bounded sample)")
         out["cpu_baseline"] = cpu_baseline()

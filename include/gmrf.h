@@ -322,12 +322,15 @@ gmrf_status gmrf_launch_records(gmrf_t h, gmrf_launch_rec_t* out, int64_t capaci
 const char* gmrf_last_error(gmrf_t h);
 
 /* Host-only symbolic analysis with no device (for tests and planning): pattern of Q
-   (host CSR as in gmrf_assemble), optional coords.  perm_out (n entries) and
-   colcount_out (n entries, exact column counts of L in pivot order) may be NULL;
-   stats_out receives the pattern counters (device fields zero). */
+   (host CSR as in gmrf_assemble), optional coords.  perm_in (host, n entries, nullable):
+   a fill-reducing order to analyse instead of the library's nested dissection (perm_in[k]
+   = original index of pivot k; it is postordered, which leaves the fill unchanged), e.g.
+   to compare the fill of two orderings (Sec. 3.2: the cost depends on the fill).
+   perm_out (n entries) and colcount_out (n entries, exact column counts of L in pivot
+   order) may be NULL; stats_out receives the pattern counters (device fields zero). */
 gmrf_status gmrf_symbolic_host(int64_t n, const int64_t* rowptr, const int32_t* col,
                                const double* coords, int dim, const gmrf_options* opts,
-                               int32_t* perm_out, int64_t* colcount_out,
+                               const int32_t* perm_in, int32_t* perm_out, int64_t* colcount_out,
                                gmrf_stats_t* stats_out);
 
 #ifdef __cplusplus

@@ -110,7 +110,7 @@ def load():
         "gmrf_pivot_order": ([P, P], i32),
         "gmrf_phase_ms": ([P, P], i32),
         "gmrf_last_error": ([P], ctypes.c_char_p),
-        "gmrf_symbolic_host": ([i64, P, P, P, ctypes.c_int, P, P, P, P], i32),
+        "gmrf_symbolic_host": ([i64, P, P, P, ctypes.c_int, P, P, P, P, P], i32),
         "gmrf_profile": ([P, ctypes.c_int], i32),
         "gmrf_matern_values": ([P, i64, P, P, P, d, d, P, P], i32),
         "gmrf_spmv": ([P, P, P, P], i32),
@@ -148,8 +148,9 @@ def _opts(opts):
     return ctypes.byref(o)
 
 
-def symbolic_host(indptr, indices, coords=None, opts=None):
-    """Host-only analysis (no device): returns (perm, colcount, stats dict)."""
+def symbolic_host(indptr, indices, coords=None, opts=None, perm_in=None):
+    """Host-only analysis (no device): returns (perm, colcount, stats dict); perm_in: an
+    ordering to analyse instead of the library's nested dissection."""
     lib = load()
     indptr = np.ascontiguousarray(indptr, dtype=np.int64)
     indices = np.ascontiguousarray(indices, dtype=np.int32)
@@ -161,8 +162,9 @@ def symbolic_host(indptr, indices, coords=None, opts=None):
     if coords is not None:
         coords = np.ascontiguousarray(coords, dtype=np.float64)
         dim = coords.shape[1]
+    pin = None if perm_in is None else np.ascontiguousarray(perm_in, dtype=np.int32)
     rc = lib.gmrf_symbolic_host(n, _np_ptr(indptr), _np_ptr(indices), _np_ptr(coords), dim,
-                                _opts(opts), _np_ptr(perm), _np_ptr(cc), ctypes.byref(st))
+                                _opts(opts), _np_ptr(pin), _np_ptr(perm), _np_ptr(cc), ctypes.byref(st))
     if rc != GMRF_OK:
         raise GmrfError(rc, "symbolic analysis failed")
     return perm, cc, st.as_dict()

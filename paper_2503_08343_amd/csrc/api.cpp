@@ -1942,8 +1942,8 @@ gmrf_status gmrf_phase_ms(gmrf_t h, double* out3) {
 }
 
 gmrf_status gmrf_symbolic_host(int64_t n, const int64_t* rowptr, const int32_t* col, const double* coords, int dim,
-                               const gmrf_options* opts, int32_t* perm_out, int64_t* colcount_out,
-                               gmrf_stats_t* stats_out) {
+                               const gmrf_options* opts, const int32_t* perm_in, int32_t* perm_out,
+                               int64_t* colcount_out, gmrf_stats_t* stats_out) {
   if (n <= 0 || !rowptr || !col) return GMRF_ERR_ARG;
   std::vector<int64_t> rp(rowptr, rowptr + n + 1);
   std::vector<int32_t> ci(col, col + rp[n]);
@@ -1952,7 +1952,7 @@ gmrf_status gmrf_symbolic_host(int64_t n, const int64_t* rowptr, const int32_t* 
   fill_opts(opts, opt);
   opt.nb = kNB;
   Symbolic Y;
-  std::string e = analyze(n, rp.data(), ci.data(), coords, coords ? dim : 0, opt, Y);
+  std::string e = analyze(n, rp.data(), ci.data(), coords, coords ? dim : 0, opt, Y, perm_in);
   if (!e.empty()) return GMRF_ERR_ARG;
   if (perm_out) std::memcpy(perm_out, Y.perm.data(), sizeof(int32_t) * n);
   if (colcount_out) std::memcpy(colcount_out, Y.colcount.data(), sizeof(int64_t) * n);

@@ -2252,12 +2252,23 @@ inline unsigned grid_for(int64_t n, int64_t cap = 65536) {
 // work-group task; a work-group takes the next ticket at its start (tickets follow the
 // task list order, in which every task comes after the tasks it depends on), so a task
 // only ever waits for tasks that already run or have finished.  The x blocks of a front
-// are produced in order by its pivot chunks, and prog[s] counts the blocks published:
-// a waiting work-group polls that counter (relaxed agent-scope loads), then issues an
-// agent-scope acquire; the producer writes its block, then stores the counter with
-// agent-scope release.  A wait longer than kSpinLimit polls sets *err and stops waiting
-// (the result is then wrong and the error is reported), so every launch terminates.
+// are produced in order by its pivot chunks, and prog[s] counts the blocks published.
+// Everything read inside the launch that another work-group wrote in it (x blocks and
+// counters) is written and read with device-scope atomic accesses, which are coherent
+// across the XCDs' L2 caches: the producer writes its block, waits for those stores to
+// complete, then stores the counter; a consumer polls the counter and then loads the
+// block, both at device scope.  No L2 write-back or invalidation is needed, so the other
+// work-groups' cached data stays put.  A wait longer than kSpinLimit polls sets *err and
+// stops waiting (the result is then wrong and the error is reported), so every launch
+// terminates.
 constexpr int kSpinLimit = 1 << 20;
+
+__device__ __forceinline__ double load_dev(const double* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void store_dev(double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 
 // Poll prog until it reaches `need`; returns the value seen (uniform over the
 // work-group).  Two barriers: every wave has read the slot before it is reused.
@@ -2279,13 +2290,17 @@ __device__ __forceinline__ int wait_progress(int32_t* prog, int need, int32_t* e
   __syncthreads();
   const int v = *slot;
   __syncthreads();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   return v;
 }
 
+// The block's device-scope stores are all issued by wave 0 (lanes < 64), to which
+// thread 0 belongs: waiting for its outstanding memory operations orders them before
+// the counter store.
 __device__ __forceinline__ void publish_progress(int32_t* prog, int value) {
-  __syncthreads();   // every wave's stores of the block are issued and complete in L2
-  if (threadIdx.x == 0) __hip_atomic_store(prog, value, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  if (threadIdx.x == 0) {
+    __builtin_amdgcn_s_waitcnt(0);
+    __hip_atomic_store(prog, value, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
 }
 
 // Forward, task (front s, chunk c): rows 64c..64c+63 of the front.
@@ -2323,44 +2338,29 @@ __global__ __launch_bounds__(kThreads) void k_fwd_fused(DevSym S, FusedTasks F, 
 #pragma unroll
     for (int u = 0; u < 16; ++u) dv[u] = Db[lane + (16 * w + u) * kNB];
   }
+  // blocks t < nb: the 16 L values of block t + 1 are requested before block t's x is
+  // waited for and used, so the memory round trip of L leaves the dependency chain
+  auto load_l = [&](int t, T* l) {
+    const int cb = 64 * t + 16 * w;
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int cc = min(cb + u, p - 1);
+      l[u] = Lr[(int64_t)cc * n] * (T)(cb + u < p);
+    }
+  };
   double acc = 0.0;
   int ready = 0;
-  int t = 0;
-  while (t < nb) {
+  T lc[16], ln[16];
+  if (nb > 0) load_l(0, lc);
+  for (int t = 0; t < nb; ++t) {
+    if (t + 1 < nb) load_l(t + 1, ln);
     if (t >= ready) ready = wait_progress(prog, t + 1, F.err, &s_slot);
-    const int tend = min(nb, ready);
-    // two blocks per step: 32 loads of L in flight per lane
-    for (; t + 1 < tend; t += 2) {
-      T l0[16], l1[16];
-      const int cb0 = 64 * t + 16 * w, cb1 = cb0 + 64;
+    const int q = min(64 * t + lane, p - 1);
+    const double x = load_dev(V.xp + f0 + q) * (double)(64 * t + lane < p);
 #pragma unroll
-      for (int u = 0; u < 16; ++u) {
-        l0[u] = Lr[(int64_t)(cb0 + u) * n];
-        const int cc = min(cb1 + u, p - 1);   // block t + 1 may be the partial last one
-        l1[u] = Lr[(int64_t)cc * n] * (T)(cb1 + u < p);
-      }
-      const double x0 = V.xp[f0 + 64 * t + lane];   // block t is full (t + 1 < P)
-      const int q1 = min(64 * t + 64 + lane, p - 1);
-      const double x1 = V.xp[f0 + q1] * (double)(64 * t + 64 + lane < p);
+    for (int u = 0; u < 16; ++u) acc += (double)lc[u] * readlane_f64(x, 16 * w + u);
 #pragma unroll
-      for (int u = 0; u < 16; ++u) acc += (double)l0[u] * readlane_f64(x0, 16 * w + u);
-#pragma unroll
-      for (int u = 0; u < 16; ++u) acc += (double)l1[u] * readlane_f64(x1, 16 * w + u);
-    }
-    if (t < tend) {
-      T l0[16];
-      const int cb0 = 64 * t + 16 * w;
-#pragma unroll
-      for (int u = 0; u < 16; ++u) {
-        const int cc = min(cb0 + u, p - 1);
-        l0[u] = Lr[(int64_t)cc * n] * (T)(cb0 + u < p);
-      }
-      const int q0 = min(64 * t + lane, p - 1);
-      const double x0 = V.xp[f0 + q0] * (double)(64 * t + lane < p);
-#pragma unroll
-      for (int u = 0; u < 16; ++u) acc += (double)l0[u] * readlane_f64(x0, 16 * w + u);
-      ++t;
-    }
+    for (int u = 0; u < 16; ++u) lc[u] = ln[u];
   }
   red[w][lane] = acc;
   __syncthreads();
@@ -2379,7 +2379,7 @@ __global__ __launch_bounds__(kThreads) void k_fwd_fused(DevSym S, FusedTasks F, 
     red[w][lane] = part;
     __syncthreads();
     const double xc = (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
-    if (w == 0 && lane < pb) V.xp[f0 + 64 * c + lane] = xc;
+    if (w == 0 && lane < pb) store_dev(V.xp + f0 + 64 * c + lane, xc);
     publish_progress(prog, c + 1);
     // rows of this chunk below p take the diagonal block's columns with x_c
     if (64 * c + 64 > p && n > p) {
@@ -2467,7 +2467,7 @@ __global__ __launch_bounds__(kThreads) void k_bwd_fused(DevSym S, FusedTasks F, 
 #pragma unroll
     for (int u = 0; u < 16; ++u) lv[u] = Lc[rc + (int64_t)cols[u] * n];
     if (ready < P - t) ready = wait_progress(prog, P - t, F.err, &s_slot);
-    const double xv = V.xp[f0 + rc] * (double)(row < p);
+    const double xv = load_dev(V.xp + f0 + rc) * (double)(row < p);
 #pragma unroll
     for (int u = 0; u < 16; ++u) acc[u] += (double)(lv[u] * cm[u]) * xv;
   }
@@ -2498,7 +2498,7 @@ __global__ __launch_bounds__(kThreads) void k_bwd_fused(DevSym S, FusedTasks F, 
   red[w][lane] = part;
   __syncthreads();
   if (w == 0 && lane < pb)
-    V.xp[f0 + 64 * c + lane] = (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
+    store_dev(V.xp + f0 + 64 * c + lane, (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]));
   publish_progress(prog, P - c);
 }
 

@@ -282,15 +282,25 @@ void column_counts(int64_t n, const int64_t* rp, const int32_t* ci,
 
 // ------------------------------------------------------------------ full analysis
 std::string analyze(int64_t n, const int64_t* rp, const int32_t* ci, const double* coords,
-                    int dim, const AnalyzeOptions& opt, Symbolic& out) {
+                    int dim, const AnalyzeOptions& opt, Symbolic& out, const int32_t* perm_in) {
   if (n <= 0) return "matrix dimension must be positive";
   if (n >= (int64_t)1 << 31) return "dimension exceeds 2^31-1";
   Symbolic& Y = out;
   Y = Symbolic();
   Y.n = n;
-  // 1. ordering
+  // 1. ordering: nested dissection, or the caller's order (postordered below either way)
   std::vector<int32_t> perm0;
-  nested_dissection(n, rp, ci, coords, dim, opt.leaf_size, perm0);
+  if (perm_in) {
+    perm0.assign(perm_in, perm_in + n);
+    std::vector<char> seen(n, 0);
+    for (int64_t k = 0; k < n; ++k) {
+      const int32_t o = perm0[k];
+      if (o < 0 || o >= n || seen[o]) return "the given order is not a permutation";
+      seen[o] = 1;
+    }
+  } else {
+    nested_dissection(n, rp, ci, coords, dim, opt.leaf_size, perm0);
+  }
   if ((int64_t)perm0.size() != n) return "internal: ordering lost nodes";
   std::vector<int32_t> ip0(n);
   for (int64_t k = 0; k < n; ++k) ip0[perm0[k]] = (int32_t)k;

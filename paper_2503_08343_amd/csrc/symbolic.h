@@ -64,9 +64,11 @@ struct Symbolic {
 
 // pattern: CSR (both triangles, sorted, symmetric, diagonal present) of the n x n matrix.
 // coords: optional n x dim node coordinates (row-major) steering the dissection.
+// perm_in: optional fill-reducing order (perm_in[k] = original index of pivot k) used
+// instead of the nested dissection (then postordered like it).
 // Returns an empty string on success, else an error message.
 std::string analyze(int64_t n, const int64_t* rp, const int32_t* ci, const double* coords,
-                    int dim, const AnalyzeOptions& opt, Symbolic& out);
+                    int dim, const AnalyzeOptions& opt, Symbolic& out, const int32_t* perm_in = nullptr);
 
 // Fill-reducing nested-dissection ordering only (exposed for host tests).
 void nested_dissection(int64_t n, const int64_t* rp, const int32_t* ci, const double* coords,
