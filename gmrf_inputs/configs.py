@@ -93,14 +93,21 @@ def matern2d(side: int = 32, kappa: float = 5.0, tau: float = 1.0, n_obs: int = 
 def advdiff_spacetime(ns: int = 128, nt: int = 64, c: float = 0.5, nu: float = 0.01,
                       tau: float = 1.0, kappa1: float = 10.0, sigma_pde: float = 1e-3,
                       sigma: float = 1e-3, obs_frac: float = 0.01, seed: int = 2,
-                      pde_rows: bool = True) -> Problem:
+                      pde_rows: bool = True, noise: str = "white",
+                      noise_range: float = 0.1) -> Problem:
     """du/dt + c du/dx - nu Laplace u = tau W on [0,1]^2 x [0,1]: Nt slices, dt=1/(Nt-1).
     Q1 = 2D Matern (alpha=2) with kappa1 and unit marginal variance
     tau1 = 1/(sqrt(4 pi) kappa1).  Observations: Galerkin implicit-Euler residual rows
     (G u^k - M~ u^(k-1))/dt = 0 on slices 2..Nt with noise sigma_pde, plus
     ceil(obs_frac N) points at uniform locations and uniform slice indices with noise
     sigma; the data come from the noiseless implicit-Euler FEM solution started from
-    the seeded smooth target."""
+    the seeded smooth target.
+
+    noise = "white": white noise in space, Sigma^-1 = M~.  noise = "matern": spatial
+    Matern noise (App. A), Sigma^-1 = Q_s = tau_s^-2 K_s M~^-1 K_s with K_s = kappa_s^2 M~ + S
+    (alpha = 2, i.e. nu_s = 1 in 2D), kappa_s = sqrt(8 nu_s) / noise_range and
+    tau_s = sqrt(4 pi) kappa_s (unit marginal variance tau_s^2 / (4 pi kappa_s^2)); the
+    prior's blocks then reach the 4-ring (diagonal) and 3-ring (off-diagonal)."""
     rng = rng_for(seed)
     mesh = fem.structured_mesh((ns, ns))
     dt = 1.0 / (nt - 1)
@@ -110,7 +117,15 @@ def advdiff_spacetime(ns: int = 128, nt: int = 64, c: float = 0.5, nu: float = 0
     tau1 = 1.0 / (math.sqrt(4.0 * math.pi) * kappa1)
     Q1, _, _ = priors.matern_precision(mesh, kappa1, tau1, S=S, m=m)
     Ls = nu * S + c * C
-    Q, G = priors.spacetime_precision(mesh, nt, dt, Ls, tau, Q1, m)
+    if noise == "white":
+        Sinv, kappa_s, tau_s = None, None, None
+    elif noise == "matern":
+        kappa_s = priors.matern_range_to_kappa(noise_range, 1.0)
+        tau_s = math.sqrt(4.0 * math.pi) * kappa_s
+        Sinv, _, _ = priors.matern_precision(mesh, kappa_s, tau_s, S=S, m=m)
+    else:
+        raise ValueError(f"unknown noise {noise!r}")
+    Q, G = priors.spacetime_precision(mesh, nt, dt, Ls, tau, Q1, m, sigma_inv=Sinv)
     Q = _sym_clean(Q)
     N = ns * ns * nt
     # deterministic implicit-Euler trajectory from the smooth initial condition
@@ -140,7 +155,8 @@ def advdiff_spacetime(ns: int = 128, nt: int = 64, c: float = 0.5, nu: float = 0
                    meta=dict(workload="advdiff_spacetime", ns=ns, nt=nt, dt=dt, c=c, nu=nu,
                              tau=tau, kappa1=kappa1, tau1=tau1, sigma_pde=sigma_pde,
                              sigma=sigma, n_pts=n_pts, seed=seed, G=G, m=m, Q1=Q1,
-                             mesh=mesh, u_true=u, pde_rows=pde_rows))
+                             mesh=mesh, u_true=u, pde_rows=pde_rows, noise=noise,
+                             Sigma_inv=Sinv, kappa_s=kappa_s, tau_s=tau_s))
 
 
 def advdiff_values(problem: Problem, c: float, nu: float):
@@ -151,7 +167,8 @@ def advdiff_values(problem: Problem, c: float, nu: float):
     meta = problem.meta
     mesh, nt, dt, m = meta["mesh"], meta["nt"], meta["dt"], meta["m"]
     Ls = nu * fem.stiffness(mesh) + c * fem.convection(mesh, axis=0)
-    Q, G = priors.spacetime_precision(mesh, nt, dt, Ls, meta["tau"], meta["Q1"], m)
+    Q, G = priors.spacetime_precision(mesh, nt, dt, Ls, meta["tau"], meta["Q1"], m,
+                                      sigma_inv=meta.get("Sigma_inv"))
     q = fem.on_pattern(_sym_clean(Q), problem.Q).data
     blocks = []
     if meta.get("pde_rows", True):
@@ -175,7 +192,8 @@ def advdiff_derivatives(problem: Problem, c: float | None = None, nu: float | No
     Ls = (meta["nu"] if nu is None else nu) * S + (meta["c"] if c is None else c) * C
     out = {}
     for name, dLs in (("c", C), ("nu", S)):
-        dQ = priors.spacetime_precision_derivative(mesh, nt, dt, Ls, dLs, meta["tau"], m)
+        dQ = priors.spacetime_precision_derivative(mesh, nt, dt, Ls, dLs, meta["tau"], m,
+                                                   sigma_inv=meta.get("Sigma_inv"))
         dq = fem.on_pattern(dQ, problem.Q).data
         dQt = fem.on_pattern(dQ.T.tocsr(), problem.Q).data
         dq = 0.5 * (dq + dQt)

@@ -124,6 +124,41 @@ def test_P4_spacetime_prior_logdet_identity(ns, nt):
     assert abs(O.logdet(F) - ref) <= 1e-9 * abs(ref)
 
 
+def test_P4_spacetime_prior_logdet_identity_matern_noise():
+    """The state-space log-det identity with spatial Matern noise (App. A):
+    log|F^-1| = -Ns log(tau^2 dt) + 2 log|det G| - 2 log|M~| + log|Sigma^-1|, where
+    log|Sigma^-1| = -2 Ns log tau_s + 2 log|det K_s| - log|M~| through K_s (a 1-ring matrix)."""
+    ns, nt = 7, 6
+    p = gi.advdiff_spacetime(ns=ns, nt=nt, seed=24, noise="matern", noise_range=0.3)
+    meta = p.meta
+    m, G, Q1 = meta["m"], meta["G"], meta["Q1"]
+    Ns = ns * ns
+    logM = float(np.sum(np.log(m)))
+    Ks = sp.diags(meta["kappa_s"] ** 2 * m) + fem.stiffness(meta["mesh"])
+    logSinv = -2 * Ns * math.log(meta["tau_s"]) + 2 * _splu_logabsdet(Ks) - logM
+    logFinv = -Ns * math.log(meta["tau"] ** 2 * meta["dt"]) + 2 * _splu_logabsdet(G) - 2 * logM + logSinv
+    logQ1 = (-2 * Ns * math.log(meta["tau1"])
+             + 2 * _splu_logabsdet(sp.diags(meta["kappa1"] ** 2 * m) + fem.stiffness(meta["mesh"])) - logM)
+    ref = logQ1 + (nt - 1) * logFinv
+    F = O.cholesky(p.Q, O.nd_order(p.coords, p.Q))
+    assert abs(O.logdet(F) - ref) <= 1e-9 * abs(ref)
+
+
+@pytest.mark.parametrize("side,bound", [(33, 0.12), (65, 0.05)])
+def test_P16_matern_interior_variance(side, bound):
+    """Matern sanity check (Sec. 2.2): with (kappa^2 - Laplace) u = tau W in 2D (alpha = 2),
+    the marginal variance away from the boundary tends to tau^2 / (4 pi kappa^2); the
+    FEM prior's centre variance is within the discretisation error, which shrinks with h."""
+    mesh = fem.structured_mesh((side, side))
+    kappa, tau = 20.0, 2.0
+    Q, _, _ = priors.matern_precision(mesh, kappa, tau)
+    r = O.posterior(gi.Problem(mesh.n, Q, sp.csr_matrix((0, mesh.n)), np.zeros(0), np.zeros(0), np.zeros(0),
+                               mesh.coords))
+    centre = (side // 2) * side + side // 2
+    rel = r["var"][centre] / (tau * tau / (4.0 * math.pi * kappa * kappa)) - 1.0
+    assert 0.0 < rel <= bound
+
+
 def test_P5_matern_logdet_via_K():
     p = gi.matern2d(side=20, kappa=3.0, tau=0.7, seed=22)
     K, m = p.meta["K"], p.meta["m"]
@@ -179,22 +214,25 @@ def test_P7_sample_covariance_monte_carlo():
     assert np.max(np.abs(C - ref) / se) < 6.0
 
 
-@pytest.mark.parametrize("seed", [81, 82])
-def test_P8_kalman_rts_smoother(seed):
+@pytest.mark.parametrize("seed,noise", [(81, "white"), (82, "white"), (83, "matern"), (84, "matern")])
+def test_P8_kalman_rts_smoother(seed, noise):
     """The space-time GMRF is the precision form of a linear-Gaussian state-space model
     (Sec. 2.4, App. A): u_1 ~ N(0, Q1^-1), u_(k+1) = A u_k + e_k, e_k ~ N(0, F) with
-    A = G^-1 M~ and F = tau^2 dt G^-1 M~ Sigma M~ G^-T (white noise in space: Sigma = M~^-1).
+    A = G^-1 M~ and F = tau^2 dt G^-1 M~ Sigma M~ G^-T (white noise in space: Sigma = M~^-1;
+    Matern noise in space: Sigma = Q_s^-1, the covariance of the discretised spatial noise).
     With point data on single slices, a Kalman filter followed by the Rauch-Tung-Striebel
     smoother, run densely slice by slice, gives the posterior mean and marginal variances
     without the block-tridiagonal precision, its factorisation or the Takahashi recursion."""
-    p = gi.advdiff_spacetime(ns=5, nt=6, obs_frac=0.3, pde_rows=False, seed=seed)
+    p = gi.advdiff_spacetime(ns=5, nt=6, obs_frac=0.3, pde_rows=False, seed=seed, noise=noise,
+                             noise_range=0.5)
     meta = p.meta
     ns, nt, dt, tau = meta["mesh"].n, meta["nt"], meta["dt"], meta["tau"]
     G = meta["G"].toarray()
     M = np.diag(meta["m"])
     At = np.linalg.solve(G, M)
     Gi = np.linalg.inv(G)
-    F = tau * tau * dt * Gi @ M @ Gi.T
+    Sig = np.linalg.inv(M) if noise == "white" else np.linalg.inv(meta["Sigma_inv"].toarray())
+    F = tau * tau * dt * Gi @ M @ Sig @ M @ Gi.T
     A = p.A.tocsr()
     slice_of_row = np.array([A.indices[A.indptr[i]] // ns for i in range(A.shape[0])])
     for i in range(A.shape[0]):
