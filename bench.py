@@ -141,7 +141,7 @@ def cpu_baseline():
                 seconds=t, host_cores=os.cpu_count())
 
 
-def secondary(binding, which, steps, warmup):
+def secondary(binding, which, steps, warmup, autotune=False):
     """The other workloads of the method at full size, timed the same way (events-free wall
     time around synchronised steps, warm-up first): a batch of 256 Matern problems
     (factor + log-dets + mean + 16 samples + selected inversion), Gauss-Newton on the
@@ -157,7 +157,12 @@ def secondary(binding, which, steps, warmup):
                              .astype(np.float32)).cuda()
         out = {"workload": f"matern_batch: 256 problems, {p.n:,} unknowns, 16 samples each"}
         for mname, prec in (("fp32", binding.GMRF_FP32_REFINE), ("fp64", binding.GMRF_FP64)):
-            ctx = binding.posterior_context(p, precision=prec)
+            opts = None
+            if autotune:
+                from paper_2503_08343_amd import autotune as at
+                opts, rec = at.tune(p, precision=prec, log=log)
+                out[mname + "_autotune"] = {"options": rec["best"], "ms": rec["ms"], "default_ms": rec["default_ms"]}
+            ctx = binding.posterior_context(p, precision=prec, opts=opts)
             st = ctx.stats()
             F = st["flops_factor"] + st["flops_selinv"] + (1 + k) * st["flops_solve"]
 
@@ -207,6 +212,39 @@ def secondary(binding, which, steps, warmup):
             ctx.close()
             log(f"[bench] c3 {mname}: {wall * 1e3:.1f} ms for 10 iterations")
         res["c3_gauss_newton"] = out
+    if "c2m" in which:
+        # the same space-time workload with the paper's spatial Matern noise (App. A)
+        p = gi.advdiff_spacetime(noise="matern")
+        zk = torch.from_numpy(np.random.Generator(np.random.PCG64(7)).standard_normal((1, p.n))
+                              .astype(np.float32)).cuda()
+        out = {"workload": f"advdiff_spacetime 128x128x64, Matern noise in space ({p.n:,} unknowns)"}
+        for mname, prec in (("fp32", binding.GMRF_FP32_REFINE), ("fp64", binding.GMRF_FP64)):
+            ctx = binding.posterior_context(p, precision=prec)
+            st = ctx.stats()
+            F = st["flops_factor"] + st["flops_selinv"] + 1.5 * st["flops_solve"]
+
+            def step():
+                ctx.factor(prec)
+                ctx.selinv_submit()
+                ctx.logdet()
+                ctx.solve(max_refine=40 if prec == binding.GMRF_FP32_REFINE else 0, tol=1e-12,
+                          raise_not_converged=False)
+                ctx.sample(zk)
+                ctx.selinv_wait()
+            for _ in range(warmup):
+                step()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                step()
+            torch.cuda.synchronize()
+            wall = (time.perf_counter() - t0) / steps
+            out[mname] = {"ms_per_step": round(wall * 1e3, 2), "GFLOP/s": round(F / wall / 1e9, 1),
+                          "nnz_L": st["nnz_l"], "flops_per_step": F}
+            ctx.close()
+            torch.cuda.empty_cache()
+            log(f"[bench] c2m {mname}: {wall * 1e3:.1f} ms per step, {F / wall / 1e9:.0f} GFLOP/s")
+        res["c2m_matern_noise"] = out
     if "c5" in which:
         import math
         from paper_2503_08343_amd import adjoint
@@ -240,8 +278,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--modes", default="fp32,fp64")
     ap.add_argument("--configs", default="c2",
-                    help="c2 (the headline workload) plus any of c3 (Gauss-Newton), c4 (batch), "
-                         "c5 (LML gradient), reported under 'secondary'")
+                    help="c2 (the headline workload) plus any of c2m (the same with Matern noise in "
+                         "space), c3 (Gauss-Newton), c4 (batch), c5 (LML gradient), reported under "
+                         "'secondary'")
+    ap.add_argument("--autotune", action="store_true",
+                    help="pick the batch's supernode options with the autotuner (cached) before timing it")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run three 1 GiB device-to-device copies (scale for HBM byte counters)")
     args = ap.parse_args()
@@ -374,8 +415,8 @@ def main():
         out["cpu_baseline"] = cpu_baseline()
     ctx.close()
     which = [c.strip() for c in args.configs.split(",")]
-    if any(c in which for c in ("c3", "c4", "c5")):
-        out["secondary"] = secondary(binding, which, args.steps, args.warmup)
+    if any(c in which for c in ("c2m", "c3", "c4", "c5")):
+        out["secondary"] = secondary(binding, which, args.steps, args.warmup, autotune=args.autotune)
     print(json.dumps(out))
 
 

@@ -150,6 +150,12 @@ struct gmrf_ctx {
   DevArr<int2> d_tasks;
   DevArr<int32_t> d_sync;
   int64_t sync_reset = 0;   // words cleared before each pass (prog + tickets)
+  // whole-forest solves: task lists (forward deepest first, backward roots first), the
+  // children's update gather map and the update parts of all fronts
+  DevArr<int2> d_ftasks, d_btasks;
+  DevArr<int32_t> d_fneed;
+  DevArr<int64_t> d_froff, d_fgptr, d_fgsrc, d_fuoff;
+  DevArr<double> d_fU;
 
   int prec = -1;
   DevArr<char> d_L, d_D, d_D2, d_D2T, d_W0, d_W1, d_Y, d_part, d_gpart;
@@ -783,9 +789,58 @@ gmrf_status build_plan(gmrf_t h) {
       lv.bbytes = lv.fbytes;
     }
     HIPCHK(h, upload(h->d_tasks, tasks, h->stream));
-    h->sync_reset = (int64_t)Y.ns + 2 * (int64_t)(Y.max_depth + 1);
+    // sync words: [prog: ns][kids: ns][tickets: 2 per depth + 2 forest][wait-limit flag]
+    h->sync_reset = 2 * (int64_t)Y.ns + 2 * (int64_t)(Y.max_depth + 1) + 2;
     HIPCHK(h, h->d_sync.alloc((size_t)h->sync_reset + 1));
     launch_fill_i32(h->stream, h->d_sync.p, h->sync_reset + 1, 0);
+    // whole-forest task lists: each depth's list, deepest depth first (forward) or the
+    // roots first (backward); inside a depth the order of the level lists above
+    std::vector<int2> ft, bt;
+    for (int d = Y.max_depth; d >= 0; --d) {
+      const Level& lv = h->levels[d];
+      ft.insert(ft.end(), tasks.begin() + lv.ftask_off, tasks.begin() + lv.ftask_off + lv.ftask_cnt);
+    }
+    for (int d = 0; d <= Y.max_depth; ++d) {
+      const Level& lv = h->levels[d];
+      bt.insert(bt.end(), tasks.begin() + lv.btask_off, tasks.begin() + lv.btask_off + lv.btask_cnt);
+    }
+    // update parts, children's gather map (rows of every front; children in ascending
+    // slot order, then their update rows in order), and per-front child chunk counts
+    std::vector<int64_t> uoff(Y.ns + 1, 0), roff(Y.ns + 1, 0);
+    for (int32_t s2 = 0; s2 < Y.ns; ++s2) {
+      uoff[s2 + 1] = uoff[s2] + (Y.nf(s2) - Y.p(s2));
+      roff[s2 + 1] = roff[s2] + Y.nf(s2);
+    }
+    std::vector<int64_t> gptr(roff[Y.ns] + 1, 0);
+    std::vector<int32_t> need(Y.ns, 0);
+    for (int32_t s2 = 0; s2 < Y.ns; ++s2) {
+      for (int32_t k = Y.child_ptr[s2]; k < Y.child_ptr[s2 + 1]; ++k) {
+        const int32_t ch = Y.child_idx[k];
+        const int64_t pc = Y.p(ch), nc = Y.nf(ch);
+        for (int64_t a = pc; a < nc; ++a) gptr[roff[s2] + Y.relpos[Y.rowptr[ch] + a] + 1]++;
+        if (nc > pc) need[s2] += (int32_t)((nc + 63) / 64 - pc / 64);
+      }
+    }
+    for (size_t i = 0; i + 1 < gptr.size(); ++i) gptr[i + 1] += gptr[i];
+    std::vector<int64_t> gsrc(gptr.back());
+    {
+      std::vector<int64_t> fill(gptr.begin(), gptr.end() - 1);
+      for (int32_t s2 = 0; s2 < Y.ns; ++s2)
+        for (int32_t k = Y.child_ptr[s2]; k < Y.child_ptr[s2 + 1]; ++k) {
+          const int32_t ch = Y.child_idx[k];
+          const int64_t pc = Y.p(ch), nc = Y.nf(ch);
+          for (int64_t a = pc; a < nc; ++a)
+            gsrc[fill[roff[s2] + Y.relpos[Y.rowptr[ch] + a]]++] = uoff[ch] + (a - pc);
+        }
+    }
+    HIPCHK(h, upload(h->d_ftasks, ft, h->stream));
+    HIPCHK(h, upload(h->d_btasks, bt, h->stream));
+    HIPCHK(h, upload(h->d_fneed, need, h->stream));
+    HIPCHK(h, upload(h->d_froff, roff, h->stream));
+    HIPCHK(h, upload(h->d_fgptr, gptr, h->stream));
+    HIPCHK(h, upload(h->d_fgsrc, gsrc, h->stream));
+    HIPCHK(h, upload(h->d_fuoff, uoff, h->stream));
+    HIPCHK(h, h->d_fU.alloc((size_t)std::max<int64_t>(uoff[Y.ns], 1)));
   }
   hipStream_t st = h->stream;
   HIPCHK(h, upload(h->d_lfronts, B.fronts, st));
@@ -962,34 +1017,27 @@ void run_solve(gmrf_t h, int nrhs, bool forward) {
   const T* Lp = (const T*)h->d_L.p;
   const T* D = (const T*)h->d_D.p;
   if (nrhs == 1) {
+    // one launch per pass over the whole elimination forest
     int32_t* prog = h->d_sync.p;
-    int32_t* tick = h->d_sync.p + Y.ns;
+    int32_t* kids = h->d_sync.p + Y.ns;
+    int32_t* tick = h->d_sync.p + 2 * Y.ns + 2 * (Y.max_depth + 1);
     int32_t* err = h->d_sync.p + h->sync_reset;
-    const int nd = Y.max_depth + 1;
-    auto tasks = [&](int64_t off, int64_t cnt, int32_t* ticket) {
-      return FusedTasks{h->d_tasks.p + off, ticket, prog, err, cnt};
-    };
+    const ForestBufs G{h->d_sparent.p, h->d_fneed.p, kids, h->d_froff.p, h->d_fgptr.p, h->d_fgsrc.p,
+                       h->d_fuoff.p, h->d_fU.p};
+    double fb = 0.0;
+    for (const Level& lv : h->levels) fb += lv.fbytes;
     if (forward) {
       launch_fill_i32(st, h->d_sync.p, h->sync_reset, 0);
-      for (int d = Y.max_depth; d >= 0; --d) {
-        const Level& lv = h->levels[d];
-        SolveBufs B{h->d_xp.p, V[d & 1], V[(d + 1) & 1], 1};
-        prof_launch(h, KC_FWD, 2.0 * lv.fbytes, lv.fbytes, [&] {
-          launch_fvec_init<T>(st, S, dev_list(h, lv.all), B);
-          for (size_t c = 0; c < lv.fvec_ext.size(); ++c)
-            launch_fvec_extend<T>(st, S, dev_list(h, lv.fvec_ext[c]), (int)c, B);
-          launch_fwd_fused<T>(st, S, tasks(lv.ftask_off, lv.ftask_cnt, tick + d), Lp, D, B);
-        });
-      }
-    }
-    launch_fill_i32(st, h->d_sync.p, h->sync_reset, 0);
-    for (int d = 0; d <= Y.max_depth; ++d) {
-      const Level& lv = h->levels[d];
-      SolveBufs B{h->d_xp.p, V[d & 1], V[(d + 1) & 1], 1};
-      prof_launch(h, KC_BWD, 2.0 * lv.bbytes, lv.bbytes, [&] {
-        launch_bwd_fused<T>(st, S, tasks(lv.btask_off, lv.btask_cnt, tick + nd + d), Lp, D, B);
+      prof_launch(h, KC_FWD, 2.0 * fb, fb, [&] {
+        launch_fwd_forest<T>(st, S, FusedTasks{h->d_ftasks.p, tick, prog, err, (int64_t)h->d_ftasks.n}, G, Lp, D,
+                             h->d_xp.p);
       });
     }
+    launch_fill_i32(st, h->d_sync.p, h->sync_reset, 0);
+    prof_launch(h, KC_BWD, 2.0 * fb, fb, [&] {
+      launch_bwd_forest<T>(st, S, FusedTasks{h->d_btasks.p, tick + 1, prog, err, (int64_t)h->d_btasks.n}, G, Lp, D,
+                           h->d_xp.p);
+    });
     return;
   }
   if (forward) {

@@ -119,10 +119,10 @@ template <typename T> void launch_bwd_part(hipStream_t st, const DevSym& S, cons
 template <typename T> void launch_bwd_block(hipStream_t st, const DevSym& S, const LaunchList& L,
                                             const LaunchList& Lpart, int t, const T* D2T, const int64_t* D2off,
                                             SolveBufs V, const double* part);
-// Level-fused solves with one right-hand side: one launch per depth, one work-group per
-// 64-row chunk task (front, chunk) in dependency order; ticket: the launch's counter
-// (zero before the launch), prog: per-supernode count of published x blocks (zero before
-// the pass), err: set if a dependency wait exceeded its spin limit.
+// Solves with one right-hand side: one work-group per 64-row chunk task (front, chunk) in
+// dependency order; ticket: the launch's counter (zero before the launch), prog:
+// per-supernode count of published x blocks (zero before the pass), err: set if a
+// dependency wait exceeded its spin limit.
 struct FusedTasks {
   const int2* task;
   int32_t* ticket;
@@ -130,12 +130,27 @@ struct FusedTasks {
   int32_t* err;
   int64_t count;
 };
-// forward: every chunk of every front of the depth, x blocks into xp, update rows into
-// the front vectors; backward: the pivot chunks from the right, x over y in xp
-template <typename T> void launch_fwd_fused(hipStream_t st, const DevSym& S, FusedTasks F, const T* Lp,
-                                            const T* D, SolveBufs V);
-template <typename T> void launch_bwd_fused(hipStream_t st, const DevSym& S, FusedTasks F, const T* Lp,
-                                            const T* D, SolveBufs V);
+// Whole-forest solves (one launch per pass over every depth): the front vectors' update
+// parts live in one array (uoff per front), a front's rows gather their children's update
+// entries through a row-CSR map (gptr over rows of all fronts, roff per front; gsrc =
+// positions in the update array, children in fixed order), and kids[s] counts the
+// children's chunks whose update rows are final (need[s] of them).
+struct ForestBufs {
+  const int32_t* parent;   // supernodal parent, -1 for roots
+  const int32_t* need;     // per front: number of child chunks holding update rows
+  int32_t* kids;           // per front: child chunks finished (zero before the pass)
+  const int64_t* roff;     // per front: first row entry in gptr
+  const int64_t* gptr;     // row-CSR into gsrc
+  const int64_t* gsrc;     // update-array positions of the children's entries
+  const int64_t* uoff;     // per front: offset of its update part in U
+  double* U;               // update parts of all fronts
+};
+// one launch over the whole forest (tasks deepest first for the forward, from the roots
+// for the backward); xp holds the right-hand side on entry and the solution on exit
+template <typename T> void launch_fwd_forest(hipStream_t st, const DevSym& S, FusedTasks F, ForestBufs G,
+                                             const T* Lp, const T* D, double* xp);
+template <typename T> void launch_bwd_forest(hipStream_t st, const DevSym& S, FusedTasks F, ForestBufs G,
+                                             const T* Lp, const T* D, double* xp);
 // xp = gate[0] * S P src (gate nullable = 1)
 void launch_permute_in(hipStream_t st, int64_t n, int nrhs, const int32_t* perm, const double* scale,
                        const double* src, int64_t lds, double* xp, const double* gate = nullptr);

@@ -2303,19 +2303,38 @@ __device__ __forceinline__ void publish_progress(int32_t* prog, int value) {
   }
 }
 
-// Forward, task (front s, chunk c): rows 64c..64c+63 of the front.
-//   acc(row) = sum over x blocks t < min(c, P) of L[row, block t] x_t  (P = pivot blocks)
-//   pivot chunk (c < P):  x_c = Linv_cc (v - acc) on its pivot rows -> xp, published;
-//                         its rows below p also take L[row, block c] x_c;
-//   update rows (>= p):   v(row) -= acc, read by the parent's extend-add at the next depth.
-// Wave w takes columns 16w..16w+15 of every block, lanes take rows; the four waves'
-// sums are added in a fixed order, so the result does not depend on timing.
+// ---- whole-forest solves: one launch per pass ----
+// Forward, task (front s, chunk c), rows 64c..64c+63 of the front:
+//   acc(row) = sum over x blocks t < min(c, P) of L[row, block t] x_t  (P = pivot blocks);
+//   pivot chunk (c < P): x_c = Linv_cc (v - acc) on its pivot rows -> xp, published; its
+//   rows below p also take L[row, block c] x_c; update rows (>= p): v(row) - acc goes to
+//   the front's update part, read by the parent.  Wave w takes columns 16w..16w+15 of
+//   every block, lanes take rows, and the waves' sums are added in a fixed order.
+// Backward, task (front s, pivot chunk c), chunks from the right: r_j = y_j - sum over the
+//   rows below the block of L[row, j] x(row); x_c = Linv_cc^T r over y in xp, published as
+//   prog[s] = P - c.  Wave w accumulates columns 16w..16w+15 over lanes = rows and sums its
+//   lanes with a fixed butterfly.
+// The tasks of every depth in one launch: the forward takes the deepest fronts first,
+// the backward the roots first.  On top of the within-front x-block waits of the
+// level-fused kernels, a forward task first waits until its front's children have
+// written their update rows (kids[s] == need[s]) and then forms its rows of the front
+// vector itself -- the right-hand side on pivot rows plus the children's entries in a
+// fixed child order through the gather map -- so no separate extend-add pass is needed;
+// a backward task first waits until its parent front has published all of its x blocks,
+// which implies every ancestor has.  Tasks only wait for lower tickets, so the launch
+// always progresses.
+__device__ __forceinline__ int wait_count(int32_t* ctr, int need, int32_t* err, int* slot) {
+  return wait_progress(ctr, need, err, slot);
+}
+
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_fwd_fused(DevSym S, FusedTasks F, const T* __restrict__ Lp,
-                                                        const T* __restrict__ D, SolveBufs V) {
+__global__ __launch_bounds__(kThreads) void k_fwd_forest(DevSym S, FusedTasks F, ForestBufs G,
+                                                         const T* __restrict__ Lp, const T* __restrict__ D,
+                                                         double* xp) {
   __shared__ int s_task, s_slot;
   __shared__ double red[4][64];
   __shared__ double xs[64];
+  __shared__ double vin[64];
   if (threadIdx.x == 0) s_task = atomicAdd(F.ticket, 1);
   __syncthreads();
   const int2 tk = F.task[s_task];
@@ -2328,9 +2347,7 @@ __global__ __launch_bounds__(kThreads) void k_fwd_fused(DevSym S, FusedTasks F, 
   const int row = 64 * c + lane;
   const T* Lr = Lp + S.Loff[s] + min(row, n - 1);
   const int64_t f0 = S.sfirst[s];
-  double* v = V.Vcur + S.Voff[s];
   int32_t* prog = F.prog + s;
-  // pivot chunk: this wave's 16 columns of the 64 x 64 inverse, requested first
   const bool piv = c < P;
   T dv[16];
   if (piv) {
@@ -2338,8 +2355,6 @@ __global__ __launch_bounds__(kThreads) void k_fwd_fused(DevSym S, FusedTasks F, 
 #pragma unroll
     for (int u = 0; u < 16; ++u) dv[u] = Db[lane + (16 * w + u) * kNB];
   }
-  // blocks t < nb: the 16 L values of block t + 1 are requested before block t's x is
-  // waited for and used, so the memory round trip of L leaves the dependency chain
   auto load_l = [&](int t, T* l) {
     const int cb = 64 * t + 16 * w;
 #pragma unroll
@@ -2348,15 +2363,27 @@ __global__ __launch_bounds__(kThreads) void k_fwd_fused(DevSym S, FusedTasks F, 
       l[u] = Lr[(int64_t)cc * n] * (T)(cb + u < p);
     }
   };
-  double acc = 0.0;
-  int ready = 0;
   T lc[16], ln[16];
   if (nb > 0) load_l(0, lc);
+  // this chunk's rows of the front vector: right-hand side on pivot rows, plus the
+  // children's update entries once every child chunk holding update rows has finished
+  if (G.need[s] > 0) (void)wait_count(G.kids + s, G.need[s], F.err, &s_slot);
+  if (w == 0) {
+    double vi = 0.0;
+    if (row < n) {
+      vi = row < p ? xp[f0 + row] : 0.0;
+      const int64_t r0 = G.roff[s] + row;
+      for (int64_t e = G.gptr[r0]; e < G.gptr[r0 + 1]; ++e) vi += load_dev(G.U + G.gsrc[e]);
+    }
+    vin[lane] = vi;
+  }
+  double acc = 0.0;
+  int ready = 0;
   for (int t = 0; t < nb; ++t) {
     if (t + 1 < nb) load_l(t + 1, ln);
     if (t >= ready) ready = wait_progress(prog, t + 1, F.err, &s_slot);
     const int q = min(64 * t + lane, p - 1);
-    const double x = load_dev(V.xp + f0 + q) * (double)(64 * t + lane < p);
+    const double x = load_dev(xp + f0 + q) * (double)(64 * t + lane < p);
 #pragma unroll
     for (int u = 0; u < 16; ++u) acc += (double)lc[u] * readlane_f64(x, 16 * w + u);
 #pragma unroll
@@ -2368,10 +2395,8 @@ __global__ __launch_bounds__(kThreads) void k_fwd_fused(DevSym S, FusedTasks F, 
   double extra = 0.0;
   if (piv) {
     const int pb = min(64, p - 64 * c);
-    // w_l = v_l - acc_l on the pivot rows, x_c = Linv_cc w (the inverse is zero above
-    // its diagonal and in its padding)
     __syncthreads();
-    if (w == 0) xs[lane] = lane < pb ? v[64 * c + lane] - tot : 0.0;
+    if (w == 0) xs[lane] = lane < pb ? vin[lane] - tot : 0.0;
     __syncthreads();
     double part = 0.0;
 #pragma unroll
@@ -2379,9 +2404,8 @@ __global__ __launch_bounds__(kThreads) void k_fwd_fused(DevSym S, FusedTasks F, 
     red[w][lane] = part;
     __syncthreads();
     const double xc = (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
-    if (w == 0 && lane < pb) store_dev(V.xp + f0 + 64 * c + lane, xc);
+    if (w == 0 && lane < pb) store_dev(xp + f0 + 64 * c + lane, xc);
     publish_progress(prog, c + 1);
-    // rows of this chunk below p take the diagonal block's columns with x_c
     if (64 * c + 64 > p && n > p) {
       if (w == 0) xs[lane] = lane < pb ? xc : 0.0;
       __syncthreads();
@@ -2397,20 +2421,23 @@ __global__ __launch_bounds__(kThreads) void k_fwd_fused(DevSym S, FusedTasks F, 
       extra = (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
     }
   }
-  if (w == 0 && row >= p && row < n) v[row] -= tot + extra;
+  // update rows -> the front's update part; the chunk then counts for its parent
+  if (64 * c + 63 >= p && n > p) {
+    if (w == 0 && row >= p && row < n) store_dev(G.U + G.uoff[s] + (row - p), vin[lane] - tot - extra);
+    const int par = G.parent[s];
+    if (threadIdx.x == 0 && par >= 0) {
+      __builtin_amdgcn_s_waitcnt(0);
+      __hip_atomic_fetch_add(G.kids + par, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
 }
 
-// Backward, task (front s, pivot chunk c), chunks from the right: columns 64c..64c+pb-1
-//   r_j = y_j - sum over rows below the block of L[row, j] x(row)
-//   x_c = Linv_cc^T r, written over y in xp, published as prog[s] = P - c.
-// Rows below p hold ancestors' unknowns (final before this depth); rows of later pivot
-// blocks of the front are waited for block by block.  Wave w accumulates columns
-// 16w..16w+15 over lanes = rows and sums its lanes with a fixed butterfly.
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_bwd_fused(DevSym S, FusedTasks F, const T* __restrict__ Lp,
-                                                        const T* __restrict__ D, SolveBufs V) {
+__global__ __launch_bounds__(kThreads) void k_bwd_forest(DevSym S, FusedTasks F, ForestBufs G,
+                                                         const T* __restrict__ Lp, const T* __restrict__ D,
+                                                         double* xp) {
   __shared__ int s_task, s_slot;
-  __shared__ T Ds[kNB * (kNB + 1)];   // pitch 65: the transposed reads spread over banks
+  __shared__ T Ds[kNB * (kNB + 1)];
   __shared__ double rs[64];
   __shared__ double red[4][64];
   if (threadIdx.x == 0) s_task = atomicAdd(F.ticket, 1);
@@ -2425,7 +2452,6 @@ __global__ __launch_bounds__(kThreads) void k_bwd_fused(DevSym S, FusedTasks F, 
   const int64_t f0 = S.sfirst[s];
   const int32_t* rows = S.rows + S.rowptr[s];
   int32_t* prog = F.prog + s;
-  // the 64 x 64 inverse of the diagonal block, staged in LDS (used transposed)
   {
     const T* Db = D + S.Doff[s] + (int64_t)c * kNB * kNB;
 #pragma unroll
@@ -2434,7 +2460,6 @@ __global__ __launch_bounds__(kThreads) void k_bwd_fused(DevSym S, FusedTasks F, 
       Ds[(e & 63) + (e >> 6) * (kNB + 1)] = Db[e];
     }
   }
-  // this wave's 16 columns; columns past p read the last column and are masked
   const T* Lc = Lp + S.Loff[s];
   int cols[16];
   T cm[16];
@@ -2447,18 +2472,22 @@ __global__ __launch_bounds__(kThreads) void k_bwd_fused(DevSym S, FusedTasks F, 
   double acc[16];
 #pragma unroll
   for (int u = 0; u < 16; ++u) acc[u] = 0.0;
-  // rows below p: unknowns of ancestors
+  // rows below p: ancestors' unknowns, final once the parent front has published them all
+  const int par = G.parent[s];
+  if (par >= 0 && n > p) {
+    const int Pp = (fp(S, par) + 63) >> 6;
+    (void)wait_count(F.prog + par, Pp, F.err, &s_slot);
+  }
   for (int r0 = p; r0 < n; r0 += 64) {
     const int row = r0 + lane;
     const int rc = min(row, n - 1);
     T lv[16];
 #pragma unroll
     for (int u = 0; u < 16; ++u) lv[u] = Lc[rc + (int64_t)cols[u] * n];
-    const double xv = V.xp[rows[rc]] * (double)(row < n);
+    const double xv = load_dev(xp + rows[rc]) * (double)(row < n);
 #pragma unroll
     for (int u = 0; u < 16; ++u) acc[u] += (double)(lv[u] * cm[u]) * xv;
   }
-  // rows of later pivot blocks of this front, from the right, as they are published
   int ready = 0;
   for (int t = P - 1; t > c; --t) {
     const int row = 64 * t + lane;
@@ -2467,12 +2496,10 @@ __global__ __launch_bounds__(kThreads) void k_bwd_fused(DevSym S, FusedTasks F, 
 #pragma unroll
     for (int u = 0; u < 16; ++u) lv[u] = Lc[rc + (int64_t)cols[u] * n];
     if (ready < P - t) ready = wait_progress(prog, P - t, F.err, &s_slot);
-    const double xv = load_dev(V.xp + f0 + rc) * (double)(row < p);
+    const double xv = load_dev(xp + f0 + rc) * (double)(row < p);
 #pragma unroll
     for (int u = 0; u < 16; ++u) acc[u] += (double)(lv[u] * cm[u]) * xv;
   }
-  // rows of the block itself below each column (the inverse covers the diagonal block)
-  // are not part of the sum; reduce each column over the wave's 64 lanes
 #pragma unroll
   for (int u = 0; u < 16; ++u) {
     double a = acc[u];
@@ -2485,10 +2512,9 @@ __global__ __launch_bounds__(kThreads) void k_bwd_fused(DevSym S, FusedTasks F, 
 #pragma unroll
     for (int u = 1; u < 16; ++u) a = lane == u ? acc[u] : a;
     const int jj = 16 * w + lane;
-    rs[jj] = jj < pb ? V.xp[f0 + 64 * c + jj] - a : 0.0;
+    rs[jj] = jj < pb ? xp[f0 + 64 * c + jj] - a : 0.0;
   }
   __syncthreads();
-  // x_l = sum_i Linv[i, l] r_i: wave w takes i in 16w..16w+15, lanes take l
   double part = 0.0;
 #pragma unroll
   for (int u = 0; u < 16; ++u) {
@@ -2498,7 +2524,7 @@ __global__ __launch_bounds__(kThreads) void k_bwd_fused(DevSym S, FusedTasks F, 
   red[w][lane] = part;
   __syncthreads();
   if (w == 0 && lane < pb)
-    store_dev(V.xp + f0 + 64 * c + lane, (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]));
+    store_dev(xp + f0 + 64 * c + lane, (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]));
   publish_progress(prog, P - c);
 }
 
@@ -2654,15 +2680,15 @@ template <typename T> void launch_bwd_block(hipStream_t st, const DevSym& S, con
                        D2off, V, part);
 }
 
-template <typename T> void launch_fwd_fused(hipStream_t st, const DevSym& S, FusedTasks F, const T* Lp, const T* D,
-                                            SolveBufs V) {
+template <typename T> void launch_fwd_forest(hipStream_t st, const DevSym& S, FusedTasks F, ForestBufs G,
+                                             const T* Lp, const T* D, double* xp) {
   if (F.count <= 0) return;
-  hipLaunchKernelGGL(k_fwd_fused<T>, dim3((unsigned)F.count), dim3(kThreads), 0, st, S, F, Lp, D, V);
+  hipLaunchKernelGGL(k_fwd_forest<T>, dim3((unsigned)F.count), dim3(kThreads), 0, st, S, F, G, Lp, D, xp);
 }
-template <typename T> void launch_bwd_fused(hipStream_t st, const DevSym& S, FusedTasks F, const T* Lp, const T* D,
-                                            SolveBufs V) {
+template <typename T> void launch_bwd_forest(hipStream_t st, const DevSym& S, FusedTasks F, ForestBufs G,
+                                             const T* Lp, const T* D, double* xp) {
   if (F.count <= 0) return;
-  hipLaunchKernelGGL(k_bwd_fused<T>, dim3((unsigned)F.count), dim3(kThreads), 0, st, S, F, Lp, D, V);
+  hipLaunchKernelGGL(k_bwd_forest<T>, dim3((unsigned)F.count), dim3(kThreads), 0, st, S, F, G, Lp, D, xp);
 }
 void launch_permute_in(hipStream_t st, int64_t n, int nrhs, const int32_t* perm, const double* scale,
                        const double* src, int64_t lds, double* xp, const double* gate) {
@@ -2811,8 +2837,8 @@ template <typename T> void launch_sel_pattern(hipStream_t st, int64_t cnt, const
   template void launch_fwd_outer<T>(hipStream_t, const DevSym&, const LaunchList&, int, const T*, SolveBufs); \
   template void launch_bwd_part<T>(hipStream_t, const DevSym&, const LaunchList&, int, const T*, SolveBufs, double*); \
   template void launch_bwd_block<T>(hipStream_t, const DevSym&, const LaunchList&, const LaunchList&, int, const T*, const int64_t*, SolveBufs, const double*); \
-  template void launch_fwd_fused<T>(hipStream_t, const DevSym&, FusedTasks, const T*, const T*, SolveBufs); \
-  template void launch_bwd_fused<T>(hipStream_t, const DevSym&, FusedTasks, const T*, const T*, SolveBufs); \
+  template void launch_fwd_forest<T>(hipStream_t, const DevSym&, FusedTasks, ForestBufs, const T*, const T*, double*); \
+  template void launch_bwd_forest<T>(hipStream_t, const DevSym&, FusedTasks, ForestBufs, const T*, const T*, double*); \
   template void launch_sel_gather<T>(hipStream_t, const DevSym&, const LaunchList&, const int32_t*, SelBufs<T>); \
   template void launch_inv256<T>(hipStream_t, const DevSym&, const LaunchList&, const T*, int, const T*, const int64_t*, T*, T*); \
   template void launch_sel_Y2<T>(hipStream_t, const DevSym&, const LaunchList&, int, SelBufs<T>, const int64_t*, const T*); \
