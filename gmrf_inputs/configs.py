@@ -159,6 +159,108 @@ def advdiff_spacetime(ns: int = 128, nt: int = 64, c: float = 0.5, nu: float = 0
                              Sigma_inv=Sinv, kappa_s=kappa_s, tau_s=tau_s))
 
 
+def manufactured_cubic(x1: np.ndarray, x2: np.ndarray, terms: int = 600):
+    """u*(x) = sum_{k=1}^{terms} k^-6 sin(k pi x1) sin(k pi x2) and f = -Laplace u* + u*^3 on the
+    grid x1 (nx1) x x2 (nx2), as (nx1, nx2) arrays: u* vanishes on the boundary of the unit
+    square and -Laplace u* = sum 2 k^2 pi^2 k^-6 sin sin."""
+    k = np.arange(1, terms + 1, dtype=np.float64)
+    s1 = np.sin(np.pi * k[:, None] * x1[None, :])
+    s2 = np.sin(np.pi * k[:, None] * x2[None, :])
+    u = s1.T @ (k[:, None] ** -6 * s2)
+    lap = s1.T @ ((2.0 * np.pi**2 * k[:, None] ** -4) * s2)
+    return u, lap + u**3
+
+
+def elliptic_cubic(side: int = 1024, prior_range: float = 0.1, sigma_pde: float = 1e-3,
+                   sigma_bdry: float = 1e-3, bdry_spacing: float = 1e-3) -> Problem:
+    """Nonlinear elliptic -Laplace u + u^3 = f on [0, 1]^2, u = 0 on the boundary, with the
+    manufactured solution of manufactured_cubic.  P1 on a side x side grid.
+
+    Prior: Matern with effective range prior_range and nu = 2 (alpha = 3): kappa =
+    sqrt(8 nu) / range, tau = sqrt(8 pi) kappa^2 (unit marginal variance
+    tau^2 / (8 pi kappa^4)).  Observations (the linear part in A, the pointwise cubic in
+    meta): Galerkin rows at the interior nodes i,
+        f_i(u) = (S u)_i + m_i u_i^3 = m_i f(x_i)   (lumped quadrature of the cubic and the load),
+    with noise sigma_pde * m_i (a pointwise residual noise sigma_pde), and the boundary
+    condition as point data u(x_b) = 0 at points spaced bdry_spacing along the boundary
+    (noise sigma_bdry).  A holds the linear part; meta: nl_col (per row, the unknown of
+    the cubic term or -1), nl_coef (m_i or 0), power 3, u_true (u* at the nodes)."""
+    mesh = fem.structured_mesh((side, side))
+    S = fem.stiffness(mesh)
+    m = fem.lumped_mass(mesh)
+    nu_m = 2.0
+    kappa = math.sqrt(8.0 * nu_m) / prior_range
+    tau = math.sqrt(8.0 * math.pi) * kappa * kappa
+    Q, _, _ = priors.matern_precision_alpha3(mesh, kappa, tau, S=S, m=m)
+    Q = _sym_clean(Q)
+    x = mesh.coords
+    g = np.linspace(0.0, 1.0, side)
+    U, F = manufactured_cubic(g, g)
+    u_true = U.ravel(order="F")          # node id = i + side * j, x1 fastest
+    f_nodes = F.ravel(order="F")
+    on_b = (np.isclose(x[:, 0], 0.0) | np.isclose(x[:, 0], 1.0) | np.isclose(x[:, 1], 0.0) |
+            np.isclose(x[:, 1], 1.0))
+    interior = np.flatnonzero(~on_b)
+    A_pde = S[interior].tocsr()
+    nb = int(round(1.0 / bdry_spacing))
+    t = np.arange(nb) * bdry_spacing
+    pts = np.concatenate([np.stack([t, np.zeros(nb)], 1), np.stack([np.ones(nb), t], 1),
+                          np.stack([1.0 - t, np.ones(nb)], 1), np.stack([np.zeros(nb), 1.0 - t], 1)])
+    A_bd = obs.point_rows(mesh, pts, mesh.n)
+    A = sp.vstack([A_pde, A_bd], format="csr")
+    A.sum_duplicates(); A.sort_indices()
+    npde = interior.size
+    y = np.concatenate([m[interior] * f_nodes[interior], np.zeros(A_bd.shape[0])])
+    q_eps = np.concatenate([1.0 / (sigma_pde * m[interior]) ** 2, np.full(A_bd.shape[0], 1.0 / sigma_bdry**2)])
+    nl_col = np.concatenate([interior, -np.ones(A_bd.shape[0], dtype=np.int64)]).astype(np.int32)
+    nl_coef = np.concatenate([m[interior], np.zeros(A_bd.shape[0])])
+    return Problem(mesh.n, Q, A, q_eps, y, np.zeros(y.size), mesh.coords.copy(),
+                   meta=dict(workload="elliptic_cubic", side=side, kappa=kappa, tau=tau, mesh=mesh, m=m,
+                             S=S, nl_col=nl_col, nl_coef=nl_coef, power=3, u_true=u_true, f=f_nodes,
+                             n_pde=npde, sigma_pde=sigma_pde, sigma_bdry=sigma_bdry))
+
+
+def prior_sqrt(problem: Problem) -> sp.csr_matrix:
+    """A left square root R of the workload's prior precision, Q = R R^T, sparse (Sec. 3.2, CG
+    sampling; App. A, square root of the space-time prior):
+      Matern (alpha = 2): R = tau^-1 K M~^-1/2;
+      space-time: block-bidiagonal with the slice-1 block Q1^1/2 = tau1^-1 K1 M~^-1/2 and, per
+        transition k, the column block [A^T F^-1/2 on slice k; -F^-1/2 on slice k+1] with
+        F^-1/2 = sqrt(c) G^T M~^-1 B, A^T F^-1/2 = sqrt(c) B, c = tau^-2 dt^-1 and Sigma^-1 = B B^T
+        (white noise B = M~^1/2; Matern noise B = tau_s^-1 K_s M~^-1/2)."""
+    meta = problem.meta
+    if meta["workload"] == "matern2d":
+        m = meta["m"]
+        return sp.csr_matrix(meta["K"] @ sp.diags(1.0 / np.sqrt(m)) / meta["tau"])
+    if meta["workload"] != "advdiff_spacetime":
+        raise ValueError("no square root for this workload")
+    mesh, nt, dt, m, G = meta["mesh"], meta["nt"], meta["dt"], meta["m"], meta["G"].tocsr()
+    ns = mesh.n
+    S = fem.stiffness(mesh)
+    K1 = (S + sp.diags(meta["kappa1"] ** 2 * m)).tocsr()
+    R1 = K1 @ sp.diags(1.0 / np.sqrt(m)) / meta["tau1"]
+    if meta.get("noise", "white") == "white":
+        B = sp.diags(np.sqrt(m))
+    else:
+        Ks = (S + sp.diags(meta["kappa_s"] ** 2 * m)).tocsr()
+        B = Ks @ sp.diags(1.0 / np.sqrt(m)) / meta["tau_s"]
+    c = 1.0 / (meta["tau"] ** 2 * dt)
+    Fm = math.sqrt(c) * (G.T @ sp.diags(1.0 / m) @ B)
+    AF = math.sqrt(c) * B
+    blocks = [[None] * nt for _ in range(nt)]
+    blocks[0][0] = R1
+    for k in range(nt - 1):
+        blocks[k][k + 1] = AF
+        blocks[k + 1][k + 1] = -Fm
+    for r in range(nt):
+        for cc in range(nt):
+            if blocks[r][cc] is None:
+                blocks[r][cc] = sp.csr_matrix((ns, ns))
+    R = sp.bmat(blocks, format="csr")
+    R.sum_duplicates(); R.sort_indices()
+    return R
+
+
 def advdiff_values(problem: Problem, c: float, nu: float):
     """Values of the advection-diffusion workload's prior precision and observation
     operator at advection speed c and viscosity nu, on the workload's stored patterns

@@ -115,3 +115,15 @@ def spacetime_precision_derivative(mesh: fem.Mesh, nt: int, dt: float, Ls: sp.sp
     sub = sp.diags([np.ones(nt - 1)], [-1], shape=(nt, nt))
     dQ = sp.kron(sp.diags(mid_f), dFinv) - sp.kron(sub, dFA) - sp.kron(sub.T, dFA.T)
     return dQ.tocsr()
+
+
+def matern_precision_alpha3(mesh: fem.Mesh, kappa: float, tau: float, S=None, m=None):
+    """(kappa^2 - Laplace)^(3/2) u = tau W (alpha = 3, i.e. nu = 2 in 2D):
+    Q = tau^-2 K M~^-1 K M~^-1 K on the 3-ring pattern, K = kappa^2 M~ + S."""
+    S = fem.stiffness(mesh) if S is None else S
+    m = fem.lumped_mass(mesh) if m is None else m
+    K = fem.on_pattern((S + sp.diags(kappa * kappa * m)).tocsr(), fem.ring_pattern(mesh, 1))
+    Mi = sp.diags(1.0 / m)
+    Q = (K.T @ Mi @ K @ Mi @ K) / (tau * tau)
+    Q = fem.on_pattern(Q.tocsr(), fem.ring_pattern(mesh, 3))
+    return Q, K, m

@@ -327,3 +327,28 @@ def condition_number(Q, dense_max=2000):
         lo = float(spla.eigsh(sp.csc_matrix(Qh), k=1, sigma=0.0, which="LM", tol=1e-6,
                               return_eigenvectors=False)[0])
     return hi / lo, lo, hi
+
+
+# ------------------------------------------------- CG sampling and Rao-Blackwellised variances
+def cg_sample_rhs(R, A, q_eps, w1, w2):
+    """Right-hand side of CG sampling (Sec. 3.2): with Q = R R^T and Q_post = Q + A^T Q_eps A =
+    [R, A^T Q_eps^1/2] [R, A^T Q_eps^1/2]^T, the vector R w1 + A^T Q_eps^1/2 w2 for standard
+    normal w1, w2 has covariance Q_post, so Q_post^-1 of it is a N(0, Q_post^-1) draw.
+    w1: (r, k), w2: (m, k); returns (n, k)."""
+    R = sp.csr_matrix(R)
+    A = sp.csr_matrix(A)
+    return R @ np.asarray(w1, dtype=np.float64) + A.T @ (np.sqrt(np.asarray(q_eps))[:, None] * np.asarray(w2))
+
+
+def rbmc_variances(Q, xs):
+    """Rao-Blackwellised Monte Carlo estimate of diag(Q^-1) from draws x_s ~ N(0, Q^-1)
+    (the estimator the paper cites as the alternative to the Takahashi recursion, Sec. 3.2):
+    x_i | x_-i ~ N(-(1/Q_ii) sum_{j != i} Q_ij x_j, 1/Q_ii), so
+      Var(x_i) = 1/Q_ii + E[((1/Q_ii) sum_{j != i} Q_ij x_j)^2]
+    with the expectation replaced by the sample mean over the columns of xs (n, k)."""
+    Q = sp.csr_matrix(Q)
+    xs = np.asarray(xs, dtype=np.float64)
+    d = Q.diagonal()
+    off = (Q - sp.diags(d)).tocsr()
+    t = (off @ xs) / d[:, None]
+    return 1.0 / d + np.mean(t * t, axis=1)

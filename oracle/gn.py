@@ -1,5 +1,7 @@
 """ORACLE -- test infrastructure only.  Gauss-Newton for the Galerkin implicit-Euler
-Burgers residual (Sec. 3.3), one step at a time from a given iterate, in FP64 on the CPU.
+Burgers residual and for residuals with a pointwise power nonlinearity (the lumped
+Galerkin rows of -Laplace u + u^3 = f) (Sec. 3.3), one step at a time from a given
+iterate, in FP64 on the CPU.
 
 The step from u: linearise f(v) ~ f(u) + J (v - u); the minimiser of the linearised
 objective 1/2 v^T Q v + 1/2 (f(u) + J (v - u) - y)^T Q_eps (...) is the affine posterior
@@ -74,6 +76,45 @@ def gn_step(Q, u, y, q_eps, nx, nt, dt, nu, mass, S, perm=None, nonlinear=True):
     for j in range(8):
         a = 2.0 ** -j
         fa, _ = burgers_residual_and_jacobian(u + a * d, nx, nt, dt, nu, mass, S, nonlinear)
+        if objective(Q, u + a * d, fa, y, q_eps) <= phi0 + 1e-4 * a * slope:
+            alpha = a
+            break
+    return u + alpha * d, dict(phi0=phi0, alpha=alpha, decrement=-slope, slope=slope, x=x)
+
+
+def pointwise_residual_and_jacobian(u, A_lin, nl_col, nl_coef, power):
+    """f(u) = A_lin u + c * u[j]^p per row (c = nl_coef, j = nl_col; rows with j < 0 are
+    linear) and its Jacobian A_lin + diag-placed p c u[j]^(p-1) (CSR, A_lin's rows)."""
+    u = np.asarray(u, dtype=np.float64)
+    A = sp.csr_matrix(A_lin)
+    nl = np.flatnonzero(np.asarray(nl_col) >= 0)
+    j = np.asarray(nl_col)[nl]
+    c = np.asarray(nl_coef, dtype=np.float64)[nl]
+    f = A @ u
+    f[nl] += c * u[j] ** power
+    D = sp.csr_matrix((power * c * u[j] ** (power - 1), (nl, j)), shape=A.shape)
+    return f, (A + D).tocsr()
+
+
+def gn_step_pointwise(Q, u, y, q_eps, A_lin, nl_col, nl_coef, power, perm=None):
+    """One Gauss-Newton step with the same line search as gn_step, for the residual of
+    pointwise_residual_and_jacobian; returns (new iterate, record dict)."""
+    Q = sp.csr_matrix(Q)
+    fun = lambda v: pointwise_residual_and_jacobian(v, A_lin, nl_col, nl_coef, power)  # noqa: E731
+    f, J = fun(u)
+    b = f - J @ u
+    Qp, h = core.assemble(Q, J, q_eps, y, b)
+    if perm is None:
+        perm = core.rcm_order(Qp)
+    F = core.cholesky(Qp, perm)
+    x = core.solve(F, h)
+    d = x - u
+    phi0 = objective(Q, u, f, y, q_eps)
+    slope = float((Q @ u) @ d) + float(np.sum(q_eps * (f - y) * (J @ d)))
+    alpha = 2.0 ** -7
+    for k in range(8):
+        a = 2.0 ** -k
+        fa, _ = fun(u + a * d)
         if objective(Q, u + a * d, fa, y, q_eps) <= phi0 + 1e-4 * a * slope:
             alpha = a
             break

@@ -117,3 +117,49 @@ def test_nonlinear_term_closed_form_for_linear_u():
     want = b * (a + b * x) * h
     for k in range(nt - 1):
         assert np.max(np.abs(f_pde[k, 1:-1] - want[1:-1])) <= 1e-13
+
+
+def _cubic(side, seed=None):
+    p = gi.elliptic_cubic(side=side)
+    m = p.meta
+    return p, m
+
+
+def test_pointwise_jacobian_matches_finite_differences():
+    p, m = _cubic(12)
+    u = gi.rng_for(111).standard_normal(p.n)
+    f, J = O.pointwise_residual_and_jacobian(u, p.A, m["nl_col"], m["nl_coef"], m["power"])
+    Jd = J.toarray()
+    h = 1e-6
+    for j in gi.rng_for(112).choice(p.n, size=15, replace=False):
+        e = np.zeros(p.n); e[j] = h
+        fp, _ = O.pointwise_residual_and_jacobian(u + e, p.A, m["nl_col"], m["nl_coef"], m["power"])
+        fm, _ = O.pointwise_residual_and_jacobian(u - e, p.A, m["nl_col"], m["nl_coef"], m["power"])
+        assert np.max(np.abs((fp - fm) / (2 * h) - Jd[:, j])) <= 1e-6 * max(1.0, np.max(np.abs(Jd[:, j])))
+
+
+def test_pointwise_linear_step_is_affine_posterior_mean():
+    p, m = _cubic(10)
+    u = gi.rng_for(113).standard_normal(p.n)
+    zero = np.zeros_like(m["nl_coef"])
+    unew, rec = O.gn_step_pointwise(p.Q, u, p.y, p.q_eps, p.A, m["nl_col"], zero, 3)
+    d = O.dense_posterior(gi.Problem(p.n, p.Q, p.A, p.q_eps, p.y, np.zeros(p.A.shape[0]), p.coords))
+    assert rec["alpha"] == 1.0
+    assert np.linalg.norm(unew - d["mean"]) <= 1e-9 * np.linalg.norm(d["mean"])
+
+
+def test_cubic_rows_vanish_on_the_manufactured_solution_at_second_order():
+    """The lumped Galerkin rows of -Laplace u + u^3 = f evaluated at the nodal values of
+    the manufactured solution: the pointwise residual (f_i(u*) - m_i f(x_i)) / m_i is a
+    consistency error that falls by about 4 per halving of h (second order); a wrong sign
+    of the cubic or of the Laplacian leaves an O(1) residual."""
+    errs = []
+    for side in (33, 65, 129):
+        p, m = _cubic(side)
+        f, _ = O.pointwise_residual_and_jacobian(m["u_true"], p.A, m["nl_col"], m["nl_coef"], m["power"])
+        npde = m["n_pde"]
+        r = (f[:npde] - p.y[:npde]) / m["nl_coef"][:npde]
+        errs.append(float(np.max(np.abs(r))))
+    print(f"[cubic] max pointwise residual of u*: {errs}")
+    assert errs[0] / errs[1] > 3.0 and errs[1] / errs[2] > 3.0
+    assert errs[2] < 2e-3

@@ -349,3 +349,49 @@ def test_condition_number_estimate_pins():
     k, lo, hi = O.condition_number(T)
     lam = 2.0 - 2.0 * np.cos(np.arange(1, n + 1) * np.pi / (n + 1))
     assert abs(lo - lam[0] / 2.0) <= 1e-12 and abs(hi - lam[-1] / 2.0) <= 1e-12
+
+
+@pytest.mark.parametrize("maker", [lambda: gi.matern2d(side=12, seed=121),
+                                   lambda: gi.advdiff_spacetime(ns=6, nt=5, seed=122),
+                                   lambda: gi.advdiff_spacetime(ns=6, nt=5, seed=123, noise="matern")])
+def test_prior_square_root_reproduces_precision(maker):
+    """The left square roots used by CG sampling (Sec. 3.2; App. A's block-bidiagonal
+    square root of the space-time prior, here with Q1 a precision): R R^T = Q."""
+    p = maker()
+    R = gi.prior_sqrt(p)
+    assert abs(R @ R.T - p.Q).max() <= 1e-13 * abs(p.Q).max()
+
+
+def test_cg_sampling_covariance_monte_carlo():
+    """Q_post^-1 (R w1 + A^T Q_eps^1/2 w2) has covariance Q_post^-1: the sample covariance of
+    40,000 draws on a tiny space-time grid against the dense inverse (MC error ~ 1/sqrt(N))."""
+    p = gi.advdiff_spacetime(ns=4, nt=3, obs_frac=0.3, seed=124)
+    Qp, _ = O.assemble(p.Q, p.A, p.q_eps, p.y)
+    R = gi.prior_sqrt(p)
+    rng = gi.rng_for(125)
+    N = 40000
+    rhs = O.cg_sample_rhs(R, p.A, p.q_eps, rng.standard_normal((R.shape[1], N)),
+                          rng.standard_normal((p.A.shape[0], N)))
+    X = np.linalg.solve(Qp.toarray(), rhs)
+    C = X @ X.T / N
+    Sig = np.linalg.inv(Qp.toarray())
+    sd = np.sqrt(np.outer(np.diag(Sig), np.diag(Sig)))
+    assert np.max(np.abs(C - Sig) / sd) <= 6.0 / np.sqrt(N) * 3
+
+
+def test_rbmc_variance_estimator_unbiased_and_consistent():
+    """Rao-Blackwellised MC variances: averaged over many independent draws the estimate
+    equals diag(Q^-1) (it is unbiased) within the MC error, and it is far less noisy than
+    the plain sample variance of the same draws."""
+    p = gi.matern2d(side=10, n_obs=20, seed=126)
+    Qp, _ = O.assemble(p.Q, p.A, p.q_eps, p.y)
+    Sig = np.diag(np.linalg.inv(Qp.toarray()))
+    F = O.cholesky(Qp, O.rcm_order(Qp))
+    rng = gi.rng_for(127)
+    z = rng.standard_normal((p.n, 4000))
+    xs = O.sample(F, np.zeros(p.n), z)
+    v = O.rbmc_variances(Qp, xs)
+    plain = np.mean(xs * xs, axis=1)
+    e_rb = np.max(np.abs(v - Sig) / Sig)
+    e_pl = np.max(np.abs(plain - Sig) / Sig)
+    assert e_rb <= 0.05 and e_rb < 0.5 * e_pl
