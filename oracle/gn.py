@@ -7,8 +7,9 @@ The step from u: linearise f(v) ~ f(u) + J (v - u); the minimiser of the lineari
 objective 1/2 v^T Q v + 1/2 (f(u) + J (v - u) - y)^T Q_eps (...) is the affine posterior
 mean with A = J, b = f(u) - J u (Sec. 3.1); d = x - u; backtracking line search on
 phi(v) = 1/2 v^T Q v + 1/2 (f(v) - y)^T Q_eps (f(v) - y) with Armijo constant 1e-4 over
-alpha = 1, 1/2, ..., 1/128 (the first that passes, else 1/128); Newton decrement
-lambda^2 = -grad phi(u)^T d.
+alpha = 1, 1/2, ..., 1/128, the first that passes; when none passes the step is not taken
+(alpha = 0: the direction carries no decrease the arithmetic can resolve, so the iterate
+is kept and the objective never increases).  Newton decrement lambda^2 = -grad phi(u)^T d.
 """
 from __future__ import annotations
 
@@ -72,7 +73,7 @@ def gn_step(Q, u, y, q_eps, nx, nt, dt, nu, mass, S, perm=None, nonlinear=True):
     d = x - u
     phi0 = objective(Q, u, f, y, q_eps)
     slope = float((Q @ u) @ d) + float(np.sum(q_eps * (f - y) * (J @ d)))
-    alpha = 2.0 ** -7
+    alpha = 0.0
     for j in range(8):
         a = 2.0 ** -j
         fa, _ = burgers_residual_and_jacobian(u + a * d, nx, nt, dt, nu, mass, S, nonlinear)
@@ -111,7 +112,7 @@ def gn_step_pointwise(Q, u, y, q_eps, A_lin, nl_col, nl_coef, power, perm=None):
     d = x - u
     phi0 = objective(Q, u, f, y, q_eps)
     slope = float((Q @ u) @ d) + float(np.sum(q_eps * (f - y) * (J @ d)))
-    alpha = 2.0 ** -7
+    alpha = 0.0
     for k in range(8):
         a = 2.0 ** -k
         fa, _ = fun(u + a * d)

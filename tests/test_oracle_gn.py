@@ -163,3 +163,21 @@ def test_cubic_rows_vanish_on_the_manufactured_solution_at_second_order():
     print(f"[cubic] max pointwise residual of u*: {errs}")
     assert errs[0] / errs[1] > 3.0 and errs[1] / errs[2] > 3.0
     assert errs[2] < 2e-3
+
+
+def test_step_not_taken_when_no_trial_decreases(monkeypatch):
+    """When the solve returns an ascent direction (here: the reflected minimiser, planted
+    on the CPU), no trial step passes the Armijo test; the iterate is kept (alpha = 0) and
+    the objective does not increase."""
+    p, m = _cubic(10)
+    u = gi.rng_for(114).standard_normal(p.n)
+    good = O.core.solve
+
+    def reflected(F, h):
+        x = good(F, h)
+        return 2.0 * u - x
+    monkeypatch.setattr(O.core, "solve", reflected)
+    unew, rec = O.gn_step_pointwise(p.Q, u, p.y, p.q_eps, p.A, m["nl_col"], m["nl_coef"], 3)
+    assert rec["slope"] > 0
+    assert rec["alpha"] == 0.0
+    assert np.array_equal(unew, u)
