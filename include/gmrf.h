@@ -212,8 +212,9 @@ gmrf_status gmrf_solve_rhs(gmrf_t h, const double* rhs, double* x_out);
    is reused), factors in `precision`, solves for the linearised posterior mean with at
    most `refine` FP64 residual corrections, stopped on the device once
    ||h - H x|| <= refine_tol ||h|| (later corrections add nothing), and takes a
-   backtracking Armijo step (c = 1e-4, alpha = 1, 1/2, ..., 1/128, the first that passes,
-   else 1/128) chosen on the device.  With use_graph != 0 the iterations after the first
+   backtracking Armijo step (c = 1e-4, alpha = 1, 1/2, ..., 1/128, the first that passes;
+   none: alpha = 0, the iterate is kept, so the objective never increases) chosen on the
+   device.  With use_graph != 0 the iterations after the first
    replay one hipGraph captured by this call (and destroyed before it returns).
    u (device, n): start on entry, final iterate on exit.  rec_out (host, 6*iters,
    nullable): per iteration objective at the start, step length, Newton decrement
@@ -224,6 +225,52 @@ gmrf_status gmrf_solve_rhs(gmrf_t h, const double* rhs, double* x_out);
 gmrf_status gmrf_gn_burgers(gmrf_t h, int64_t nx, int64_t nt, double dt, double nu,
                             const double* mass, const double* stiff3, int iters, int precision,
                             int refine, double refine_tol, int use_graph, double* u, double* rec_out);
+
+/* Gauss-Newton (Sec. 3.3) for observation residuals with a pointwise power nonlinearity,
+   e.g. the lumped Galerkin rows of -Laplace u + u^3 = f:
+     f_r(u) = sum_e lin_val[e] u[col e] + nl_coef[r] * u[nl_col[r]]^power      (row r of A),
+   with data y and noise q_eps as assembled (A's pattern must hold each row's nonlinear
+   unknown; nl_col[r] = -1 marks a linear row).  lin_val: nnz_a (device, A's CSR order);
+   nl_col: m int32 (device); nl_coef: m (device); power: 2..8.  Each iteration writes the
+   linearisation J = lin + power * c * u^(power-1) (at the nonlinear unknown) and
+   b = (1 - power) c u^power into the assembled A and b, then proceeds exactly as
+   gmrf_gn_burgers (H = Q + J^T Q_eps J on the analysed pattern, refined solve, device
+   Armijo line search, hipGraph replay after the first iteration, Laplace approximation
+   at the final iterate); rec_out receives the same 6 values per iteration.  Returns
+   GMRF_ERR_PATTERN if a nonlinear unknown is not a stored column of its row. */
+gmrf_status gmrf_gn_pointwise(gmrf_t h, const double* lin_val, const int32_t* nl_col, const double* nl_coef,
+                              int power, int iters, int precision, int refine, double refine_tol,
+                              int use_graph, double* u, double* rec_out);
+
+/* Conjugate gradients (Sec. 3.2, the alternative to the factorisation when fill is too
+   large): preconditioned CG for Q_post x = rhs on the device, FP64 vectors and fixed-order
+   reductions; preconditioner precond = 0: the diagonal of Q_post (needs only
+   gmrf_assemble and gmrf_analyze), 1: the context's factor (one forward and one backward
+   solve per iteration; after gmrf_factor, FP32 or FP64).  k right-hand sides (n x k,
+   column-major, device) solved one after the other; rhs = NULL (k = 1) solves for the
+   posterior mean (Sec. 3.1: x = mu + Q_post^-1 h).  x0 (device, nullable): starting
+   iterate, e.g. the previous Gauss-Newton direction (Sec. 3.3).  Stops when
+   ||rhs - Q_post x|| <= tol ||rhs|| or after maxit iterations; iters_out / resid_out
+   (host, k, nullable) receive the counts and final relative residuals.  Returns
+   GMRF_ERR_NOT_CONVERGED if a column stopped above tol (x_out still written). */
+gmrf_status gmrf_pcg(gmrf_t h, int64_t k, const double* rhs, const double* x0, double* x_out, int precond,
+                     int maxit, double tol, int* iters_out, double* resid_out);
+
+/* CG sampling (Sec. 3.2): with a left square root R of the prior precision (Q = R R^T;
+   n x r CSR, device: int64 row pointers, int32 columns, values) the vector
+   b = R w1 + A^T Q_eps^1/2 w2 has covariance Q_post, so x = mu_post + Q_post^-1 b is a
+   posterior draw; Q_post^-1 b by gmrf_pcg's iteration.  w1: r x k, w2: m x k (device,
+   column-major, standard normal; w2 unused when m = 0); x_out: n x k.  Needs the
+   posterior mean of a previous gmrf_solve. */
+gmrf_status gmrf_sample_cg(gmrf_t h, int64_t k, int64_t r, const int64_t* r_rowptr, const int32_t* r_col,
+                           const double* r_val, const double* w1, const double* w2, double* x_out,
+                           int precond, int maxit, double tol, int* iters_out);
+
+/* Rao-Blackwellised Monte Carlo marginal variances (Sec. 3.2, the estimator of Siden et al.
+   the paper cites): from k draws x_s of N(0, Q_post^-1) (n x k, device, column-major,
+   centred), var_i = 1/Q_ii + (1/k) sum_s ((1/Q_ii) sum_{j != i} (Q_post)_ij x_sj)^2.
+   var_out: n (device). */
+gmrf_status gmrf_rbmc_variances(gmrf_t h, int64_t k, const double* xs, double* var_out);
 
 /* k posterior samples x = mu_post + P^T L^-T z (Sec. 3.2, sampling) from the mean of the
    last gmrf_solve.  z: n x k float32, column-major, pivot order (device).

@@ -31,7 +31,8 @@ EXPORTS = ["gmrf_create", "gmrf_destroy", "gmrf_assemble", "gmrf_update_values",
            "gmrf_stats", "gmrf_pivot_order", "gmrf_phase_ms", "gmrf_last_error",
            "gmrf_symbolic_host", "gmrf_profile", "gmrf_kernel_stats", "gmrf_matern_values",
            "gmrf_spmv", "gmrf_misfit", "gmrf_solve_rhs", "gmrf_gn_burgers", "gmrf_launch_records",
-           "gmrf_logdet_noalloc", "gmrf_lml_gradient"]
+           "gmrf_logdet_noalloc", "gmrf_lml_gradient", "gmrf_gn_pointwise", "gmrf_pcg", "gmrf_sample_cg",
+           "gmrf_rbmc_variances"]
 
 
 class gmrf_options(ctypes.Structure):
@@ -121,6 +122,11 @@ def load():
         "gmrf_kernel_stats": ([P, P, ctypes.c_int, P], i32),
         "gmrf_logdet_noalloc": ([P, P], i32),
         "gmrf_lml_gradient": ([P, P, ctypes.c_int, P, P, P, ctypes.c_int, d, P, P], i32),
+        "gmrf_gn_pointwise": ([P, P, P, P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, d,
+                               ctypes.c_int, P, P], i32),
+        "gmrf_pcg": ([P, i64, P, P, P, ctypes.c_int, ctypes.c_int, d, P, P], i32),
+        "gmrf_sample_cg": ([P, i64, i64, P, P, P, P, P, P, ctypes.c_int, ctypes.c_int, d, P], i32),
+        "gmrf_rbmc_variances": ([P, i64, P, P], i32),
         "gmrf_launch_records": ([P, P, ctypes.c_int64, P], i32),
     }
     for name, (args, res) in sig.items():
@@ -357,6 +363,50 @@ class Context:
                                              float(refine_tol), 1 if use_graph else 0, _t_ptr(u),
                                              _np_ptr(rec)))
         return rec.reshape(iters, 6)
+
+    def gn_pointwise(self, lin_val, nl_col, nl_coef, power, u, iters=10, precision=GMRF_FP64, refine=2,
+                     use_graph=True, refine_tol=0.0):
+        """Gauss-Newton for residuals with a pointwise power nonlinearity (gmrf_gn_pointwise);
+        u (device) is updated in place; returns the per-iteration records like gn_burgers."""
+        rec = np.zeros(6 * iters)
+        self._check(self.lib.gmrf_gn_pointwise(self.h, _t_ptr(lin_val), _t_ptr(nl_col), _t_ptr(nl_coef),
+                                               int(power), int(iters), int(precision), int(refine),
+                                               float(refine_tol), 1 if use_graph else 0, _t_ptr(u),
+                                               _np_ptr(rec)))
+        return rec.reshape(iters, 6)
+
+    def pcg(self, rhs=None, x0=None, precond=1, maxit=1000, tol=1e-12, raise_not_converged=True):
+        """Preconditioned CG (gmrf_pcg): rhs (device, n or n x k as (k, n)) or None for the
+        posterior mean; returns (x, iterations, relative residuals)."""
+        T = self.torch
+        k = 1 if rhs is None or rhs.dim() == 1 else int(rhs.shape[0])
+        x = T.empty((k, self.n), dtype=T.float64, device="cuda")
+        its = np.zeros(k, dtype=np.int32)
+        res = np.zeros(k)
+        rc = self.lib.gmrf_pcg(self.h, k, _t_ptr(rhs), _t_ptr(x0), _t_ptr(x), int(precond), int(maxit), float(tol),
+                               _np_ptr(its), _np_ptr(res))
+        if rc != GMRF_ERR_NOT_CONVERGED or raise_not_converged:
+            self._check(rc)
+        return (x[0] if k == 1 and (rhs is None or rhs.dim() == 1) else x), its, res
+
+    def sample_cg(self, r_indptr, r_indices, r_data, w1, w2, precond=1, maxit=1000, tol=1e-12):
+        """CG sampling (gmrf_sample_cg): R as device CSR tensors (n x r), w1 (k, r), w2 (k, m);
+        returns (x (k, n), iterations)."""
+        T = self.torch
+        k, r = int(w1.shape[0]), int(w1.shape[1])
+        x = T.empty((k, self.n), dtype=T.float64, device="cuda")
+        its = np.zeros(k, dtype=np.int32)
+        self._check(self.lib.gmrf_sample_cg(self.h, k, r, _t_ptr(r_indptr), _t_ptr(r_indices), _t_ptr(r_data),
+                                            _t_ptr(w1), _t_ptr(w2), _t_ptr(x), int(precond), int(maxit),
+                                            float(tol), _np_ptr(its)))
+        return x, its
+
+    def rbmc_variances(self, xs):
+        """Rao-Blackwellised variances from centred draws xs (k, n) (gmrf_rbmc_variances)."""
+        T = self.torch
+        var = T.empty(self.n, dtype=T.float64, device="cuda")
+        self._check(self.lib.gmrf_rbmc_variances(self.h, int(xs.shape[0]), _t_ptr(xs.contiguous()), _t_ptr(var)))
+        return var
 
     def misfit(self, x):
         out = np.zeros(1)

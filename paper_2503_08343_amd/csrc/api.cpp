@@ -10,6 +10,7 @@
 #include <climits>
 #include <mutex>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <string>
 #include <type_traits>
@@ -190,6 +191,7 @@ struct gmrf_ctx {
   hipStream_t gn_stream = nullptr;
   hipGraphExec_t gn_exec = nullptr;   // exists only during one gmrf_gn_burgers call
   DevArr<double> d_lml;               // workspace of gmrf_lml_gradient
+  DevArr<double> d_cg;                // workspace of gmrf_pcg / gmrf_sample_cg
 };
 
 namespace {
@@ -1162,14 +1164,29 @@ gmrf_status assemble_device(gmrf_t h) {
 constexpr int kGNRec = 6;   // doubles per Gauss-Newton iteration record
 
 struct GNArgs {
-  int64_t nx, nt;
+  int kind;                  // 0: Burgers (Galerkin implicit Euler); 1: pointwise power
+  int64_t nx, nt;            // Burgers
   double dt, nu;
   const double* mass;
   const double* s3;
+  const double* lin;         // pointwise: linear part of A (A's pattern), unknown of the
+  const int32_t* nl_col;     // nonlinear term per row (-1: none), its coefficient, power
+  const double* nl_coef;
+  int power;
   double* u;
   int refine;
   double tol;
 };
+
+// linearise the residual at u into A's values and b (Sec. 3.3)
+void gn_linearize(gmrf_t h, const GNArgs& a) {
+  if (a.kind == 0)
+    launch_burgers_linearize(h->stream, a.nx, a.nt, a.dt, a.nu, a.mass, a.s3, a.u, h->d_arp.p, h->d_aval.p,
+                             h->d_b.p);
+  else
+    launch_pw_linearize(h->stream, h->m, h->d_arp.p, h->d_aci.p, a.lin, a.nl_col, a.nl_coef, a.power, a.u,
+                        h->d_aval.p, h->d_b.p);
+}
 
 // solve Q_post x = h on device only (no host synchronisation, capturable): one solve
 // plus at most `refine` corrections with FP64 residuals.  A device gate stops the
@@ -1208,7 +1225,7 @@ template <typename T>
 gmrf_status gn_body(gmrf_t h, const GNArgs& a) {
   hipStream_t st = h->stream;
   const int64_t n = h->n;
-  launch_burgers_linearize(st, a.nx, a.nt, a.dt, a.nu, a.mass, a.s3, a.u, h->d_arp.p, h->d_aval.p, h->d_b.p);
+  gn_linearize(h, a);
   gmrf_status rc = assemble_device(h);
   if (rc != GMRF_OK) return rc;
   rc = run_factor<T>(h);
@@ -1220,11 +1237,165 @@ gmrf_status gn_body(gmrf_t h, const GNArgs& a) {
   launch_dot(st, n, h->d_gn_d.p, h->d_gn_tmp.p, h->d_red.p, h->d_gn_quad.p + 1);
   launch_spmv(st, n, h->d_qrp.p, h->d_qci.p, h->d_qval.p, h->d_gn_d.p, h->d_gn_tmp.p);
   launch_dot(st, n, h->d_gn_d.p, h->d_gn_tmp.p, h->d_red.p, h->d_gn_quad.p + 2);
-  launch_gn_linesearch(st, a.nx, a.nt, a.dt, a.nu, a.mass, a.s3, a.u, h->d_gn_d.p, h->d_y.p, h->d_qeps.p,
-                       h->d_arp.p, h->d_aci.p, h->d_aval.p, h->d_gn_part.p, h->d_gn_quad.p, h->d_gn_sel.p,
-                       h->d_gn_rec.p);
+  if (a.kind == 0)
+    launch_gn_linesearch(st, a.nx, a.nt, a.dt, a.nu, a.mass, a.s3, a.u, h->d_gn_d.p, h->d_y.p, h->d_qeps.p,
+                         h->d_arp.p, h->d_aci.p, h->d_aval.p, h->d_gn_part.p, h->d_gn_quad.p, h->d_gn_sel.p,
+                         h->d_gn_rec.p);
+  else
+    launch_pw_linesearch(st, h->m, h->d_arp.p, h->d_aci.p, a.lin, a.nl_col, a.nl_coef, a.power, a.u, h->d_gn_d.p,
+                         h->d_y.p, h->d_qeps.p, h->d_aval.p, h->d_gn_part.p, h->d_gn_quad.p, h->d_gn_sel.p,
+                         h->d_gn_rec.p);
   launch_gn_update(st, n, h->d_gn_sel.p, h->d_gn_d.p, a.u);
   HIPCHK(h, hipGetLastError());
+  return GMRF_OK;
+}
+
+// Gauss-Newton iterations on the device (Sec. 3.3) for either residual model: iteration 0
+// eager, the later ones replaying one hipGraph captured by this call; then the Laplace
+// approximation at the final iterate (relinearised and refactored).
+gmrf_status gn_run(gmrf_t h, const GNArgs& a, int iters, int precision, int use_graph, double* rec_out) {
+  if (hipSetDevice(h->device) != hipSuccess) return fail(h, GMRF_ERR_HIP, "hipSetDevice failed");
+  hipStream_t user = h->stream;
+  if (!h->gn_stream) HIPCHK(h, hipStreamCreateWithFlags(&h->gn_stream, hipStreamNonBlocking));
+  HIPCHK(h, user ? hipStreamSynchronize(user) : hipDeviceSynchronize());
+  h->stream = h->gn_stream;
+  // The graph captured by this call holds this call's pointers and sizes (u, mass, the
+  // library's current buffers), so it lives only for this call: every exit drains the
+  // stream and destroys it.
+  struct Restore {
+    gmrf_t h;
+    hipStream_t s;
+    ~Restore() {
+      if (h->gn_exec) {
+        (void)hipStreamSynchronize(h->stream);
+        (void)hipGraphExecDestroy(h->gn_exec);
+        h->gn_exec = nullptr;
+      }
+      h->stream = s;
+    }
+  } restore{h, user};
+  const bool prof = h->prof;
+  h->prof = false;
+  HIPCHK(h, h->d_gn_x.alloc(h->n));
+  HIPCHK(h, h->d_gn_d.alloc(h->n));
+  HIPCHK(h, h->d_gn_tmp.alloc(h->n));
+  HIPCHK(h, h->d_gn_part.alloc(10 * 256));
+  HIPCHK(h, h->d_gn_quad.alloc(4));
+  HIPCHK(h, h->d_gn_sel.alloc(3));
+  HIPCHK(h, h->d_gn_rec.alloc(kGNRec));
+  gmrf_status rc = alloc_solve(h, 1);
+  if (rc != GMRF_OK) return rc;
+  rc = precision == GMRF_FP64 ? alloc_numeric<double>(h) : alloc_numeric<float>(h);
+  if (rc != GMRF_OK) return rc;
+  h->has_b = true;
+  std::vector<double> rec(kGNRec * (size_t)iters, 0.0);
+  auto body = [&]() { return precision == GMRF_FP64 ? gn_body<double>(h, a) : gn_body<float>(h, a); };
+  HIPCHK(h, hipEventRecord(h->ev[0], h->stream));
+  for (int it = 0; it < iters; ++it) {
+    const bool graph = use_graph && it > 0;
+    if (graph && !h->gn_exec) {
+      hipGraph_t g = nullptr;
+      HIPCHK(h, hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+      rc = body();
+      hipError_t ce = hipStreamEndCapture(h->stream, &g);
+      if (rc != GMRF_OK) { if (g) (void)hipGraphDestroy(g); return rc; }
+      HIPCHK(h, ce);
+      hipError_t ie = hipGraphInstantiate(&h->gn_exec, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      HIPCHK(h, ie);
+    }
+    if (graph) {
+      HIPCHK(h, hipGraphLaunch(h->gn_exec, h->stream));
+    } else {
+      rc = body();
+      if (rc != GMRF_OK) return rc;
+    }
+    HIPCHK(h, hipMemcpyAsync(rec.data() + kGNRec * it, h->d_gn_rec.p, kGNRec * sizeof(double),
+                             hipMemcpyDeviceToHost, h->stream));
+  }
+  HIPCHK(h, hipEventRecord(h->ev[1], h->stream));
+  // Laplace approximation at the final iterate (Sec. 3.3): relinearise and refactor so that
+  // logdet / sample / selinv describe N(u*, (Q + J*^T Q_eps J*)^-1)
+  gn_linearize(h, a);
+  rc = assemble_device(h);
+  if (rc != GMRF_OK) return rc;
+  rc = precision == GMRF_FP64 ? run_factor<double>(h) : run_factor<float>(h);
+  if (rc != GMRF_OK) return rc;
+  HIPCHK(h, copy_d2d(h->d_mu_post.p, a.u, h->n * sizeof(double), h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  h->ev_factor = false;
+  float ms = 0.f;
+  if (hipEventElapsedTime(&ms, h->ev[0], h->ev[1]) == hipSuccess) h->phase_ms[0] = ms;
+  h->prof = prof;
+  h->prec = precision;
+  h->state |= ST_FACTORED | ST_SOLVED;
+  if (rec_out) std::memcpy(rec_out, rec.data(), rec.size() * sizeof(double));
+  return check_status(h);
+}
+
+
+// Preconditioned CG for Q_post x = b on the device (FP64 vectors, fixed-order dots); the
+// preconditioner is the diagonal of Q_post (precond 0) or the context's factor (1: one
+// forward and one backward solve per iteration).  The relative residual is checked on the
+// host after every iteration.  Returns the iterations and the final relative residual.
+template <typename T>
+void pcg_solve(gmrf_t h, const double* b, double* x, bool warm, int precond, int maxit, double tol, int* its,
+               double* rel) {
+  hipStream_t st = h->stream;
+  const int64_t n = h->n;
+  double* r = h->d_cg.p;
+  double* z = r + n;
+  double* p = z + n;
+  double* q = p + n;
+  double* sc = q + n;           // (r^T z, p^T q, new r^T z, ||r||, ||b||)
+  auto precondition = [&](const double* in, double* out) {
+    if (precond == 0) {
+      launch_jacobi(st, n, h->d_qdiag.p, h->d_qpost.p, in, out);
+    } else {
+      launch_permute_in(st, n, 1, h->d_perm.p, h->d_scale.p, in, n, h->d_xp.p);
+      run_solve<T>(h, 1, true);
+      launch_permute_out(st, n, 1, h->d_perm.p, h->d_scale.p, h->d_xp.p, nullptr, 0, out, n, 0);
+    }
+  };
+  if (!warm) launch_fill_f64(st, x, n, 0.0);
+  launch_resid(st, n, h->d_qrp.p, h->d_qci.p, h->d_qpost.p, b, x, r);   // r = b - Q x
+  launch_norm2(st, n, b, h->d_red.p, sc + 4);
+  precondition(r, z);
+  launch_copy_f64(st, n, z, p);
+  launch_dot(st, n, r, z, h->d_red.p, sc + 0);
+  double hs[2] = {0.0, 0.0};
+  int it = 0;
+  double rr = 0.0;
+  while (true) {
+    launch_norm2(st, n, r, h->d_red.p, sc + 3);
+    if (hipMemcpyAsync(hs, sc + 3, 2 * sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess) break;
+    if (hipStreamSynchronize(st) != hipSuccess) break;
+    rr = hs[0] / (hs[1] > 0.0 ? hs[1] : 1.0);
+    if (rr <= tol || it >= maxit || !std::isfinite(rr)) break;
+    launch_spmv(st, n, h->d_qrp.p, h->d_qci.p, h->d_qpost.p, p, q);
+    launch_dot(st, n, p, q, h->d_red.p, sc + 1);
+    launch_cg_xr(st, n, sc, p, q, x, r);
+    precondition(r, z);
+    launch_dot(st, n, r, z, h->d_red.p, sc + 2);
+    launch_cg_p(st, n, sc, z, p);
+    ++it;
+  }
+  *its = it;
+  *rel = rr;
+}
+
+gmrf_status pcg_prepare(gmrf_t h, int precond) {
+  if (!(h->state & ST_ASSEMBLED) || !(h->state & ST_ANALYZED))
+    return fail(h, GMRF_ERR_STATE, "conjugate gradients need gmrf_assemble and gmrf_analyze");
+  if (precond != 0 && precond != 1) return fail(h, GMRF_ERR_ARG, "precond must be 0 (diagonal) or 1 (factor)");
+  if (precond == 1) {
+    if (!(h->state & ST_FACTORED)) return fail(h, GMRF_ERR_STATE, "precond 1 needs gmrf_factor");
+    gmrf_status rc = check_status(h);
+    if (rc != GMRF_OK) return rc;
+  }
+  gmrf_status rc = alloc_solve(h, 1);
+  if (rc != GMRF_OK) return rc;
+  HIPCHK(h, h->d_cg.alloc((size_t)(4 * h->n + 8)));
   return GMRF_OK;
 }
 
@@ -1568,8 +1739,11 @@ gmrf_status gmrf_solve(gmrf_t h, double* mu_out, int max_refine, double tol, int
   if (iters_out) *iters_out = it;
   if (resid_out) *resid_out = rel;
   h->state |= ST_SOLVED;
-  if (!(rel <= tol) && (f32 || maxit > 0))
-    return fail(h, GMRF_ERR_NOT_CONVERGED, "refinement stopped at relative residual " + std::to_string(rel));
+  if (!(rel <= tol) && (f32 || maxit > 0)) {
+    char msg[96];
+    std::snprintf(msg, sizeof msg, "refinement stopped at relative residual %.3e after %d iterations", rel, it);
+    return fail(h, GMRF_ERR_NOT_CONVERGED, msg);
+  }
   return GMRF_OK;
 }
 
@@ -1672,6 +1846,80 @@ gmrf_status gmrf_lml_gradient(gmrf_t post, gmrf_t prior, int k, const double* dq
   return solve_rc;
 }
 
+gmrf_status gmrf_pcg(gmrf_t h, int64_t k, const double* rhs, const double* x0, double* x_out, int precond, int maxit,
+                     double tol, int* iters_out, double* resid_out) {
+  if (!h || !x_out || k < 1 || maxit < 0 || !(tol >= 0.0) || (!rhs && k != 1)) return fail(h, GMRF_ERR_ARG, "bad argument");
+  HIPCHK(h, sel_sync(h));
+  gmrf_status rc = pcg_prepare(h, precond);
+  if (rc != GMRF_OK) return rc;
+  hipStream_t st = h->stream;
+  const int64_t n = h->n;
+  bool conv = true;
+  for (int64_t c = 0; c < k; ++c) {
+    double* x = x_out + c * n;
+    const double* b = rhs ? rhs + c * n : h->d_h.p;
+    if (x0) HIPCHK(h, copy_d2d(x, x0 + c * n, n * sizeof(double), st));
+    int its = 0;
+    double rel = 0.0;
+    if (precond == 1 && h->prec == GMRF_FP32_REFINE) pcg_solve<float>(h, b, x, x0 != nullptr, precond, maxit, tol, &its, &rel);
+    else pcg_solve<double>(h, b, x, x0 != nullptr, precond, maxit, tol, &its, &rel);
+    if (!rhs && h->has_mu) launch_add(st, n, x, h->d_mu.p, x);   // posterior mean = mu + Q_post^-1 h
+    if (iters_out) iters_out[c] = its;
+    if (resid_out) resid_out[c] = rel;
+    conv = conv && rel <= tol;
+  }
+  HIPCHK(h, hipGetLastError());
+  HIPCHK(h, hipStreamSynchronize(st));
+  if (!conv) return fail(h, GMRF_ERR_NOT_CONVERGED, "conjugate gradients stopped above the tolerance");
+  return GMRF_OK;
+}
+
+gmrf_status gmrf_sample_cg(gmrf_t h, int64_t k, int64_t r, const int64_t* r_rowptr, const int32_t* r_col,
+                           const double* r_val, const double* w1, const double* w2, double* x_out, int precond,
+                           int maxit, double tol, int* iters_out) {
+  if (!h || k < 1 || r < 1 || !r_rowptr || !r_col || !r_val || !w1 || !x_out || (h->m > 0 && !w2))
+    return fail(h, GMRF_ERR_ARG, "bad argument");
+  if (!(h->state & ST_SOLVED)) return fail(h, GMRF_ERR_STATE, "gmrf_sample_cg needs a posterior mean (gmrf_solve)");
+  HIPCHK(h, sel_sync(h));
+  gmrf_status rc = pcg_prepare(h, precond);
+  if (rc != GMRF_OK) return rc;
+  hipStream_t st = h->stream;
+  const int64_t n = h->n, m = h->m;
+  HIPCHK(h, h->d_rvec.alloc((size_t)std::max<int64_t>(m, 1)));
+  bool conv = true;
+  for (int64_t c = 0; c < k; ++c) {
+    double* x = x_out + c * n;
+    // b = R w1 + A^T Q_eps^1/2 w2: covariance R R^T + A^T Q_eps A = Q_post
+    double* b = h->d_w.p;
+    launch_spmv(st, n, r_rowptr, r_col, r_val, w1 + c * r, b);
+    if (m > 0) {
+      launch_elementwise(st, m, 3, h->d_qeps.p, w2 + c * m, h->d_rvec.p);
+      launch_at_times(st, n, h->d_atp.p, h->d_ati.p, h->d_arow.p, h->d_aval.p, h->d_rvec.p, h->d_r.p);
+      launch_add(st, n, b, h->d_r.p, b);
+    }
+    int its = 0;
+    double rel = 0.0;
+    if (precond == 1 && h->prec == GMRF_FP32_REFINE) pcg_solve<float>(h, b, x, false, precond, maxit, tol, &its, &rel);
+    else pcg_solve<double>(h, b, x, false, precond, maxit, tol, &its, &rel);
+    launch_add(st, n, x, h->d_mu_post.p, x);
+    if (iters_out) iters_out[c] = its;
+    conv = conv && rel <= tol;
+  }
+  HIPCHK(h, hipGetLastError());
+  HIPCHK(h, hipStreamSynchronize(st));
+  if (!conv) return fail(h, GMRF_ERR_NOT_CONVERGED, "conjugate gradients stopped above the tolerance");
+  return GMRF_OK;
+}
+
+gmrf_status gmrf_rbmc_variances(gmrf_t h, int64_t k, const double* xs, double* var_out) {
+  if (!h || k < 1 || !xs || !var_out) return fail(h, GMRF_ERR_ARG, "bad argument");
+  if (!(h->state & ST_ASSEMBLED)) return fail(h, GMRF_ERR_STATE, "gmrf_rbmc_variances before gmrf_assemble");
+  launch_rbmc(h->stream, h->n, h->d_qrp.p, h->d_qci.p, h->d_qpost.p, h->d_qdiag.p, k, xs, var_out);
+  HIPCHK(h, hipGetLastError());
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  return GMRF_OK;
+}
+
 gmrf_status gmrf_solve_rhs(gmrf_t h, const double* rhs, double* x_out) {
   if (!h || !rhs || !x_out) return fail(h, GMRF_ERR_ARG, "null argument");
   if (!(h->state & ST_FACTORED)) return fail(h, GMRF_ERR_STATE, "gmrf_solve_rhs before gmrf_factor");
@@ -1716,84 +1964,33 @@ gmrf_status gmrf_gn_burgers(gmrf_t h, int64_t nx, int64_t nt, double dt, double 
     for (int64_t t = 0; t < c; ++t)
       if (h->aci[e0 + t] != want[t]) return fail(h, GMRF_ERR_PATTERN, "A row " + std::to_string(r) + " has wrong columns");
   }
-  if (hipSetDevice(h->device) != hipSuccess) return fail(h, GMRF_ERR_HIP, "hipSetDevice failed");
-  hipStream_t user = h->stream;
-  if (!h->gn_stream) HIPCHK(h, hipStreamCreateWithFlags(&h->gn_stream, hipStreamNonBlocking));
-  HIPCHK(h, user ? hipStreamSynchronize(user) : hipDeviceSynchronize());
-  h->stream = h->gn_stream;
-  // The graph captured by this call holds this call's pointers and sizes (u, mass, the
-  // library's current buffers), so it lives only for this call: every exit drains the
-  // stream and destroys it.
-  struct Restore {
-    gmrf_t h;
-    hipStream_t s;
-    ~Restore() {
-      if (h->gn_exec) {
-        (void)hipStreamSynchronize(h->stream);
-        (void)hipGraphExecDestroy(h->gn_exec);
-        h->gn_exec = nullptr;
-      }
-      h->stream = s;
+  GNArgs a{0, nx, nt, dt, nu, mass, stiff3, nullptr, nullptr, nullptr, 0, u, refine, refine_tol};
+  return gn_run(h, a, iters, precision, use_graph, rec_out);
+}
+
+gmrf_status gmrf_gn_pointwise(gmrf_t h, const double* lin_val, const int32_t* nl_col, const double* nl_coef,
+                              int power, int iters, int precision, int refine, double refine_tol, int use_graph,
+                              double* u, double* rec_out) {
+  if (!h || !lin_val || !nl_col || !nl_coef || !u || iters < 1 || refine < 0 || !(refine_tol >= 0.0) ||
+      power < 2 || power > 8)
+    return fail(h, GMRF_ERR_ARG, "bad argument");
+  HIPCHK(h, sel_sync(h));
+  if (precision != GMRF_FP64 && precision != GMRF_FP32_REFINE) return fail(h, GMRF_ERR_ARG, "unknown precision");
+  if (!(h->state & ST_ANALYZED)) return fail(h, GMRF_ERR_STATE, "gmrf_gn_pointwise before gmrf_analyze");
+  if (h->m < 1) return fail(h, GMRF_ERR_ARG, "gmrf_gn_pointwise needs observation rows");
+  {
+    // the nonlinear term's unknown must be a stored column of its row (its Jacobian entry)
+    std::vector<int32_t> nc((size_t)h->m);
+    HIPCHK(h, hipMemcpyAsync(nc.data(), nl_col, h->m * sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    for (int64_t r = 0; r < h->m; ++r) {
+      if (nc[r] < 0) continue;
+      if (nc[r] >= h->n || !std::binary_search(h->aci.begin() + h->arp[r], h->aci.begin() + h->arp[r + 1], nc[r]))
+        return fail(h, GMRF_ERR_PATTERN, "nonlinear unknown of row " + std::to_string(r) + " is not in the row's pattern");
     }
-  } restore{h, user};
-  const bool prof = h->prof;
-  h->prof = false;
-  HIPCHK(h, h->d_gn_x.alloc(h->n));
-  HIPCHK(h, h->d_gn_d.alloc(h->n));
-  HIPCHK(h, h->d_gn_tmp.alloc(h->n));
-  HIPCHK(h, h->d_gn_part.alloc(10 * 256));
-  HIPCHK(h, h->d_gn_quad.alloc(4));
-  HIPCHK(h, h->d_gn_sel.alloc(3));
-  HIPCHK(h, h->d_gn_rec.alloc(kGNRec));
-  gmrf_status rc = alloc_solve(h, 1);
-  if (rc != GMRF_OK) return rc;
-  rc = precision == GMRF_FP64 ? alloc_numeric<double>(h) : alloc_numeric<float>(h);
-  if (rc != GMRF_OK) return rc;
-  h->has_b = true;
-  GNArgs a{nx, nt, dt, nu, mass, stiff3, u, refine, refine_tol};
-  std::vector<double> rec(kGNRec * (size_t)iters, 0.0);
-  auto body = [&]() { return precision == GMRF_FP64 ? gn_body<double>(h, a) : gn_body<float>(h, a); };
-  HIPCHK(h, hipEventRecord(h->ev[0], h->stream));
-  for (int it = 0; it < iters; ++it) {
-    const bool graph = use_graph && it > 0;
-    if (graph && !h->gn_exec) {
-      hipGraph_t g = nullptr;
-      HIPCHK(h, hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
-      rc = body();
-      hipError_t ce = hipStreamEndCapture(h->stream, &g);
-      if (rc != GMRF_OK) { if (g) (void)hipGraphDestroy(g); return rc; }
-      HIPCHK(h, ce);
-      hipError_t ie = hipGraphInstantiate(&h->gn_exec, g, nullptr, nullptr, 0);
-      (void)hipGraphDestroy(g);
-      HIPCHK(h, ie);
-    }
-    if (graph) {
-      HIPCHK(h, hipGraphLaunch(h->gn_exec, h->stream));
-    } else {
-      rc = body();
-      if (rc != GMRF_OK) return rc;
-    }
-    HIPCHK(h, hipMemcpyAsync(rec.data() + kGNRec * it, h->d_gn_rec.p, kGNRec * sizeof(double),
-                             hipMemcpyDeviceToHost, h->stream));
   }
-  HIPCHK(h, hipEventRecord(h->ev[1], h->stream));
-  // Laplace approximation at the final iterate (Sec. 3.3): relinearise and refactor so that
-  // logdet / sample / selinv describe N(u*, (Q + J*^T Q_eps J*)^-1)
-  launch_burgers_linearize(h->stream, nx, nt, dt, nu, mass, stiff3, u, h->d_arp.p, h->d_aval.p, h->d_b.p);
-  rc = assemble_device(h);
-  if (rc != GMRF_OK) return rc;
-  rc = precision == GMRF_FP64 ? run_factor<double>(h) : run_factor<float>(h);
-  if (rc != GMRF_OK) return rc;
-  HIPCHK(h, copy_d2d(h->d_mu_post.p, u, h->n * sizeof(double), h->stream));
-  HIPCHK(h, hipStreamSynchronize(h->stream));
-  h->ev_factor = false;
-  float ms = 0.f;
-  if (hipEventElapsedTime(&ms, h->ev[0], h->ev[1]) == hipSuccess) h->phase_ms[0] = ms;
-  h->prof = prof;
-  h->prec = precision;
-  h->state |= ST_FACTORED | ST_SOLVED;
-  if (rec_out) std::memcpy(rec_out, rec.data(), rec.size() * sizeof(double));
-  return check_status(h);
+  GNArgs a{1, 0, 0, 0.0, 0.0, nullptr, nullptr, lin_val, nl_col, nl_coef, power, u, refine, refine_tol};
+  return gn_run(h, a, iters, precision, use_graph, rec_out);
 }
 
 gmrf_status gmrf_sample(gmrf_t h, int64_t k, const float* z, double* x_out) {

