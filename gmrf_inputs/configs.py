@@ -172,7 +172,7 @@ def manufactured_cubic(x1: np.ndarray, x2: np.ndarray, terms: int = 600):
 
 
 def elliptic_cubic(side: int = 1024, prior_range: float = 0.1, sigma_pde: float = 1e-3,
-                   sigma_bdry: float = 1e-3, bdry_spacing: float = 1e-3) -> Problem:
+                   sigma_bdry: float | None = None, bdry_spacing: float = 1e-3) -> Problem:
     """Nonlinear elliptic -Laplace u + u^3 = f on [0, 1]^2, u = 0 on the boundary, with the
     manufactured solution of manufactured_cubic.  P1 on a side x side grid.
 
@@ -183,11 +183,17 @@ def elliptic_cubic(side: int = 1024, prior_range: float = 0.1, sigma_pde: float 
         f_i(u) = (S u)_i + m_i u_i^3 = m_i f(x_i)   (lumped quadrature of the cubic and the load),
     with noise sigma_pde * m_i (a pointwise residual noise sigma_pde), and the boundary
     condition as point data u(x_b) = 0 at points spaced bdry_spacing along the boundary
-    (noise sigma_bdry).  A holds the linear part; meta: nl_col (per row, the unknown of
+    with noise sigma_bdry, by default sigma_pde h^2: a Galerkin row (S u)_i has O(1)
+    coefficients, so its noise sigma_pde m_i ~ sigma_pde h^2 is that size in units of u, and
+    the boundary values are held as firmly as the equations.  (With a fixed sigma_bdry the
+    harmonic extensions of boundary values, which the Galerkin rows do not see, are held only
+    by the boundary data, and the condition number grows like h^-6 instead of h^-4.)  A holds the linear part; meta: nl_col (per row, the unknown of
     the cubic term or -1), nl_coef (m_i or 0), power 3, u_true (u* at the nodes)."""
     mesh = fem.structured_mesh((side, side))
     S = fem.stiffness(mesh)
     m = fem.lumped_mass(mesh)
+    if sigma_bdry is None:
+        sigma_bdry = sigma_pde / (side - 1) ** 2
     nu_m = 2.0
     kappa = math.sqrt(8.0 * nu_m) / prior_range
     tau = math.sqrt(8.0 * math.pi) * kappa * kappa
@@ -483,3 +489,89 @@ def burgers_spacetime(nx: int = 1024, nt: int = 1024, nu: float = 0.01 / math.pi
                    meta=dict(workload="burgers_spacetime", nx=nx, nt=nt, dt=dt, nu=nu, mass=m, s3=s3,
                              u0=u0, x=x, sigma_pde=sigma_pde, sigma_ic=sigma_ic, kappa_s=kappa_s,
                              tau_s=tau_s, seed=seed))
+
+
+def darcy_p2(n_el: int = 300, boundary: str = "dirichlet", alpha: int = 3, eps2: float = 1e-8,
+             sigma_pde: float = 1e-3, observations: str = "fem", n_obs: int = 2000,
+             sigma: float = 1e-2, a_hi: float = 12.0, a_lo: float = 3.0, seed: int = 7) -> Problem:
+    """GMRF-FEM for Darcy flow -div(a grad u) = 1 on the unit square (Sec. 5.1, App. C.1)
+    with quadratic Lagrange triangles: n_el elements per side, (2 n_el + 1)^2 unknowns.
+
+    Prior: Matern with nu = alpha - 1 (2D), effective range n_el^-1/2 and unit marginal
+    variance: Q = tau^-2 K M~^-1 K (alpha = 2) or tau^-2 K M~^-1 K M~^-1 K (alpha = 3),
+    K = kappa^2 M~ + S, M~ the HRZ-lumped P2 mass.  Boundary (App. B): "dirichlet"
+    constrains every boundary node to 0, "periodic" ties the nodes on x = 1 / y = 1 to their
+    mirrors on x = 0 / y = 0 (a torus), "natural" constrains nothing.  K and M~ are
+    eliminated as in classic FEM (rows and columns, so K stays symmetric); the mass entry at
+    a constrained node is (eps/tau)^(2/(alpha-1)), so that the constrained unknown is
+    N(0, eps2) in the final precision.
+
+    Observations: "fem" -- the Galerkin rows of -div(a grad u) = 1 at the unconstrained
+    nodes (the constraint's column operation applied), data the consistent load, noise
+    sigma_pde * m~_i (a pointwise residual noise sigma_pde); "points" -- n_obs uniform
+    point values of a seeded smooth target with noise sigma; "none" -- the prior alone.  The permeability a is a
+    seeded smooth random field thresholded to a_hi / a_lo per triangle (piecewise constant,
+    like the two-valued coefficients of the Darcy benchmark)."""
+    from . import p2
+    if boundary not in ("dirichlet", "periodic", "natural"):
+        raise ValueError(f"unknown boundary {boundary!r}")
+    if alpha not in (2, 3):
+        raise ValueError("alpha must be 2 or 3")
+    rng = rng_for(seed)
+    mesh = p2.P2Mesh(n_el + 1)
+    S = mesh.stiffness()
+    m = mesh.lumped_mass()
+    nu_m = float(alpha - 1)
+    kappa = priors.matern_range_to_kappa(n_el ** -0.5, nu_m)
+    # unit marginal variance: tau^2 Gamma(nu) / (Gamma(alpha) 4 pi kappa^(2 nu)) = 1
+    tau = math.sqrt(math.gamma(alpha) * 4.0 * math.pi * kappa ** (2.0 * nu_m) / math.gamma(nu_m))
+    if boundary == "dirichlet":
+        con = mesh.boundary_nodes()
+        tgt = -np.ones(con.size, dtype=np.int64)
+    elif boundary == "periodic":
+        con, tgt = mesh.periodic_pairs()
+    else:
+        con = np.zeros(0, dtype=np.int64)
+        tgt = np.zeros(0, dtype=np.int64)
+    coef = np.ones(con.size)
+    K = (S + sp.diags(kappa * kappa * m)).tocsr()
+    m_con = (math.sqrt(eps2) / tau) ** (2.0 / (alpha - 1))
+    Kc, mc = p2.constrain_fem(K, m, con, tgt, coef, m_con)
+    Mi = sp.diags(1.0 / mc)
+    Q = (Kc.T @ Mi @ Kc) if alpha == 2 else (Kc @ Mi @ Kc @ Mi @ Kc)
+    Q = sp.csr_matrix(Q / (tau * tau))
+    # the triple product is symmetric only up to rounding, and a cancelled entry can be stored
+    # on one side only: take the symmetric part on the union pattern
+    Q = sp.csr_matrix(0.5 * (Q + Q.T))
+    Q.sum_duplicates(); Q.sort_indices()
+    field_fn = smooth_target(rng, 2)
+    cl, cu = mesh.centroids()
+    a_l = np.where(field_fn(cl) > 0.0, a_hi, a_lo)
+    a_u = np.where(field_fn(cu) > 0.0, a_hi, a_lo)
+    free = np.setdiff1d(np.arange(mesh.n), con)
+    if observations == "fem":
+        Sa = mesh.stiffness(a_l, a_u)
+        load = np.asarray(mesh.mass() @ np.ones(mesh.n)).ravel()
+        A = p2.constrain_columns(Sa, con, tgt, coef)[free].tocsr()
+        A.eliminate_zeros(); A.sort_indices()
+        y = load[free].copy()
+        q_eps = 1.0 / (sigma_pde * m[free]) ** 2
+    elif observations == "points":
+        pts = rng.uniform(0.0, 1.0, size=(n_obs, 2))
+        A = p2.constrain_columns(mesh.point_rows(pts), con, tgt, coef)
+        A.eliminate_zeros(); A.sort_indices()
+        y = field_fn(pts) + sigma * rng.standard_normal(n_obs)
+        q_eps = np.full(n_obs, 1.0 / sigma**2)
+        Sa = load = None
+    elif observations == "none":
+        A = sp.csr_matrix((0, mesh.n))
+        y = np.zeros(0)
+        q_eps = np.zeros(0)
+        Sa = load = None
+    else:
+        raise ValueError(f"unknown observations {observations!r}")
+    return Problem(mesh.n, Q, A, q_eps, y, np.zeros(y.size), mesh.coords.copy(),
+                   meta=dict(workload="darcy_p2", n_el=n_el, boundary=boundary, alpha=alpha, eps2=eps2,
+                             kappa=kappa, tau=tau, mesh=mesh, constrained=con, targets=tgt, free=free,
+                             a_lower=a_l, a_upper=a_u, S_a=Sa, load=load, observations=observations,
+                             sigma_pde=sigma_pde, seed=seed))
