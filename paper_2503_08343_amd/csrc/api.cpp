@@ -154,6 +154,8 @@ struct gmrf_ctx {
   // whole-forest solves: task lists (forward deepest first, backward roots first), the
   // children's update gather map and the update parts of all fronts
   DevArr<int2> d_ftasks, d_btasks;
+  DevArr<int32_t> d_fgrp, d_bgrp;   // task groups of the whole-forest solves
+  int64_t n_fgrp = 0, n_bgrp = 0;   // group counts (the arrays may be larger after a re-analysis)
   DevArr<int32_t> d_fneed;
   DevArr<int64_t> d_froff, d_fgptr, d_fgsrc, d_fuoff;
   DevArr<double> d_fU;
@@ -835,8 +837,30 @@ gmrf_status build_plan(gmrf_t h) {
             gsrc[fill[roff[s2] + Y.relpos[Y.rowptr[ch] + a]]++] = uoff[ch] + (a - pc);
         }
     }
+    // task groups: up to 16 consecutive tasks of fronts with at most 256 rows share a
+    // work-group; a task of a larger front is a group of its own
+    auto groups = [&](const std::vector<int2>& tl) {
+      std::vector<int32_t> g{0};
+      int run = 0;
+      for (size_t i = 0; i < tl.size(); ++i) {
+        const bool small = Y.nf(tl[i].x) <= 256;
+        if (i > 0 && (!small || run == 16 || Y.nf(tl[i - 1].x) > 256)) {
+          g.push_back((int32_t)i);
+          run = 0;
+        }
+        ++run;
+      }
+      g.push_back((int32_t)tl.size());
+      if (tl.empty()) g.assign(1, 0);
+      return g;
+    };
+    const std::vector<int32_t> fg = groups(ft), bg = groups(bt);
     HIPCHK(h, upload(h->d_ftasks, ft, h->stream));
     HIPCHK(h, upload(h->d_btasks, bt, h->stream));
+    HIPCHK(h, upload(h->d_fgrp, fg, h->stream));
+    HIPCHK(h, upload(h->d_bgrp, bg, h->stream));
+    h->n_fgrp = (int64_t)fg.size() - 1;
+    h->n_bgrp = (int64_t)bg.size() - 1;
     HIPCHK(h, upload(h->d_fneed, need, h->stream));
     HIPCHK(h, upload(h->d_froff, roff, h->stream));
     HIPCHK(h, upload(h->d_fgptr, gptr, h->stream));
@@ -1018,7 +1042,12 @@ void run_solve(gmrf_t h, int nrhs, bool forward) {
   double* V[2] = {h->d_V0.p, h->d_V1.p};
   const T* Lp = (const T*)h->d_L.p;
   const T* D = (const T*)h->d_D.p;
-  if (nrhs == 1) {
+  // several right-hand sides on a forest of small fronts (average supernode below 16,384
+  // entries of L): one backward pass over the forest that takes the columns one after the
+  // other per task; large fronts keep the per-depth kernels, which read each L block once
+  // for all columns
+  const bool forest_multi = nrhs > 1 && !forward && Y.nnzL < (int64_t)16384 * Y.ns;
+  if (nrhs == 1 || forest_multi) {
     // one launch per pass over the whole elimination forest
     int32_t* prog = h->d_sync.p;
     int32_t* kids = h->d_sync.p + Y.ns;
@@ -1031,14 +1060,14 @@ void run_solve(gmrf_t h, int nrhs, bool forward) {
     if (forward) {
       launch_fill_i32(st, h->d_sync.p, h->sync_reset, 0);
       prof_launch(h, KC_FWD, 2.0 * fb, fb, [&] {
-        launch_fwd_forest<T>(st, S, FusedTasks{h->d_ftasks.p, tick, prog, err, (int64_t)h->d_ftasks.n}, G, Lp, D,
-                             h->d_xp.p);
+        launch_fwd_forest<T>(st, S, FusedTasks{h->d_ftasks.p, tick, prog, err, h->n_fgrp, h->d_fgrp.p},
+                             G, Lp, D, h->d_xp.p);
       });
     }
     launch_fill_i32(st, h->d_sync.p, h->sync_reset, 0);
-    prof_launch(h, KC_BWD, 2.0 * fb, fb, [&] {
-      launch_bwd_forest<T>(st, S, FusedTasks{h->d_btasks.p, tick + 1, prog, err, (int64_t)h->d_btasks.n}, G, Lp, D,
-                           h->d_xp.p);
+    prof_launch(h, KC_BWD, 2.0 * fb * nrhs, fb, [&] {
+      launch_bwd_forest<T>(st, S, FusedTasks{h->d_btasks.p, tick + 1, prog, err, h->n_bgrp, h->d_bgrp.p},
+                           G, Lp, D, h->d_xp.p, nrhs, h->n);
     });
     return;
   }

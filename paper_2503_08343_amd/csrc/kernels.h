@@ -139,7 +139,8 @@ struct FusedTasks {
   int32_t* ticket;
   int32_t* prog;
   int32_t* err;
-  int64_t count;
+  int64_t count;             // work-groups of the launch = task groups
+  const int32_t* group;      // group g holds tasks group[g] .. group[g + 1] - 1, in order
 };
 // Whole-forest solves (one launch per pass over every depth): the front vectors' update
 // parts live in one array (uoff per front), a front's rows gather their children's update
@@ -160,8 +161,9 @@ struct ForestBufs {
 // for the backward); xp holds the right-hand side on entry and the solution on exit
 template <typename T> void launch_fwd_forest(hipStream_t st, const DevSym& S, FusedTasks F, ForestBufs G,
                                              const T* Lp, const T* D, double* xp);
+// nrhs right-hand sides (column r at xp + r * ldx) in one backward pass
 template <typename T> void launch_bwd_forest(hipStream_t st, const DevSym& S, FusedTasks F, ForestBufs G,
-                                             const T* Lp, const T* D, double* xp);
+                                             const T* Lp, const T* D, double* xp, int nrhs = 1, int64_t ldx = 0);
 // xp = gate[0] * S P src (gate nullable = 1)
 void launch_permute_in(hipStream_t st, int64_t n, int nrhs, const int32_t* perm, const double* scale,
                        const double* src, int64_t lds, double* xp, const double* gate = nullptr);

@@ -2444,8 +2444,11 @@ __device__ __forceinline__ void publish_progress(int32_t* prog, int value) {
 // vector itself -- the right-hand side on pivot rows plus the children's entries in a
 // fixed child order through the gather map -- so no separate extend-add pass is needed;
 // a backward task first waits until its parent front has published all of its x blocks,
-// which implies every ancestor has.  Tasks only wait for lower tickets, so the launch
-// always progresses.
+// which implies every ancestor has.  A work-group takes one ticket and runs a group of
+// consecutive tasks in order (tasks of small fronts are grouped, up to 16, so that a pass
+// over a forest of many small fronts needs far fewer work-groups and ticket atomics).
+// Tasks only wait for tasks earlier in the list, which belong to lower tickets or come
+// earlier in the same group, so the launch always progresses.
 __device__ __forceinline__ int wait_count(int32_t* ctr, int need, int32_t* err, int* slot) {
   return wait_progress(ctr, need, err, slot);
 }
@@ -2460,7 +2463,10 @@ __global__ __launch_bounds__(kThreads) void k_fwd_forest(DevSym S, FusedTasks F,
   __shared__ double vin[64];
   if (threadIdx.x == 0) s_task = atomicAdd(F.ticket, 1);
   __syncthreads();
-  const int2 tk = F.task[s_task];
+  const int grp = s_task;
+  const int t_end = F.group[grp + 1];
+  for (int ti = F.group[grp]; ti < t_end; ++ti) {
+  const int2 tk = F.task[ti];
   const int s = tk.x, c = tk.y;
   const int n = fn(S, s), p = fp(S, s);
   const int P = (p + 63) >> 6;
@@ -2553,19 +2559,24 @@ __global__ __launch_bounds__(kThreads) void k_fwd_forest(DevSym S, FusedTasks F,
       __hip_atomic_fetch_add(G.kids + par, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
   }
+  __syncthreads();   // the shared buffers are reused by the group's next task
+  }
 }
 
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_bwd_forest(DevSym S, FusedTasks F, ForestBufs G,
                                                          const T* __restrict__ Lp, const T* __restrict__ D,
-                                                         double* xp) {
+                                                         double* xp, int nrhs, int64_t ldx) {
   __shared__ int s_task, s_slot;
   __shared__ T Ds[kNB * (kNB + 1)];
   __shared__ double rs[64];
   __shared__ double red[4][64];
   if (threadIdx.x == 0) s_task = atomicAdd(F.ticket, 1);
   __syncthreads();
-  const int2 tk = F.task[s_task];
+  const int grp = s_task;
+  const int t_end = F.group[grp + 1];
+  for (int ti = F.group[grp]; ti < t_end; ++ti) {
+  const int2 tk = F.task[ti];
   const int s = tk.x, c = tk.y;
   const int n = fn(S, s), p = fp(S, s);
   const int P = (p + 63) >> 6;
@@ -2592,26 +2603,30 @@ __global__ __launch_bounds__(kThreads) void k_bwd_forest(DevSym S, FusedTasks F,
     cols[u] = 64 * c + min(jj, pb - 1);
     cm[u] = (T)(jj < pb);
   }
-  double acc[16];
-#pragma unroll
-  for (int u = 0; u < 16; ++u) acc[u] = 0.0;
   // rows below p: ancestors' unknowns, final once the parent front has published them all
   const int par = G.parent[s];
   if (par >= 0 && n > p) {
     const int Pp = (fp(S, par) + 63) >> 6;
     (void)wait_count(F.prog + par, Pp, F.err, &s_slot);
   }
+  int ready = 0;
+  // the right-hand sides one after the other; the block's progress is published once all
+  // of them are final, so the waits of the first cover the rest
+  for (int rr = 0; rr < nrhs; ++rr) {
+  double* xr = xp + (int64_t)rr * ldx;
+  double acc[16];
+#pragma unroll
+  for (int u = 0; u < 16; ++u) acc[u] = 0.0;
   for (int r0 = p; r0 < n; r0 += 64) {
     const int row = r0 + lane;
     const int rc = min(row, n - 1);
     T lv[16];
 #pragma unroll
     for (int u = 0; u < 16; ++u) lv[u] = Lc[rc + (int64_t)cols[u] * n];
-    const double xv = load_dev(xp + rows[rc]) * (double)(row < n);
+    const double xv = load_dev(xr + rows[rc]) * (double)(row < n);
 #pragma unroll
     for (int u = 0; u < 16; ++u) acc[u] += (double)(lv[u] * cm[u]) * xv;
   }
-  int ready = 0;
   for (int t = P - 1; t > c; --t) {
     const int row = 64 * t + lane;
     const int rc = min(row, p - 1);
@@ -2619,7 +2634,7 @@ __global__ __launch_bounds__(kThreads) void k_bwd_forest(DevSym S, FusedTasks F,
 #pragma unroll
     for (int u = 0; u < 16; ++u) lv[u] = Lc[rc + (int64_t)cols[u] * n];
     if (ready < P - t) ready = wait_progress(prog, P - t, F.err, &s_slot);
-    const double xv = load_dev(xp + f0 + rc) * (double)(row < p);
+    const double xv = load_dev(xr + f0 + rc) * (double)(row < p);
 #pragma unroll
     for (int u = 0; u < 16; ++u) acc[u] += (double)(lv[u] * cm[u]) * xv;
   }
@@ -2635,7 +2650,7 @@ __global__ __launch_bounds__(kThreads) void k_bwd_forest(DevSym S, FusedTasks F,
 #pragma unroll
     for (int u = 1; u < 16; ++u) a = lane == u ? acc[u] : a;
     const int jj = 16 * w + lane;
-    rs[jj] = jj < pb ? xp[f0 + 64 * c + jj] - a : 0.0;
+    rs[jj] = jj < pb ? xr[f0 + 64 * c + jj] - a : 0.0;
   }
   __syncthreads();
   double part = 0.0;
@@ -2647,8 +2662,12 @@ __global__ __launch_bounds__(kThreads) void k_bwd_forest(DevSym S, FusedTasks F,
   red[w][lane] = part;
   __syncthreads();
   if (w == 0 && lane < pb)
-    store_dev(xp + f0 + 64 * c + lane, (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]));
+    store_dev(xr + f0 + 64 * c + lane, (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]));
+  __syncthreads();   // rs and red are reused by the next right-hand side
+  }
   publish_progress(prog, P - c);
+  __syncthreads();   // the shared buffers are reused by the group's next task
+  }
 }
 
 }  // namespace
@@ -2827,9 +2846,10 @@ template <typename T> void launch_fwd_forest(hipStream_t st, const DevSym& S, Fu
   hipLaunchKernelGGL(k_fwd_forest<T>, dim3((unsigned)F.count), dim3(kThreads), 0, st, S, F, G, Lp, D, xp);
 }
 template <typename T> void launch_bwd_forest(hipStream_t st, const DevSym& S, FusedTasks F, ForestBufs G,
-                                             const T* Lp, const T* D, double* xp) {
+                                             const T* Lp, const T* D, double* xp, int nrhs, int64_t ldx) {
   if (F.count <= 0) return;
-  hipLaunchKernelGGL(k_bwd_forest<T>, dim3((unsigned)F.count), dim3(kThreads), 0, st, S, F, G, Lp, D, xp);
+  hipLaunchKernelGGL(k_bwd_forest<T>, dim3((unsigned)F.count), dim3(kThreads), 0, st, S, F, G, Lp, D, xp, nrhs,
+                     ldx);
 }
 void launch_permute_in(hipStream_t st, int64_t n, int nrhs, const int32_t* perm, const double* scale,
                        const double* src, int64_t lds, double* xp, const double* gate) {
@@ -2993,7 +3013,7 @@ template <typename T> void launch_sel_pattern(hipStream_t st, int64_t cnt, const
   template void launch_bwd_part<T>(hipStream_t, const DevSym&, const LaunchList&, int, const T*, SolveBufs, double*); \
   template void launch_bwd_block<T>(hipStream_t, const DevSym&, const LaunchList&, const LaunchList&, int, const T*, const int64_t*, SolveBufs, const double*); \
   template void launch_fwd_forest<T>(hipStream_t, const DevSym&, FusedTasks, ForestBufs, const T*, const T*, double*); \
-  template void launch_bwd_forest<T>(hipStream_t, const DevSym&, FusedTasks, ForestBufs, const T*, const T*, double*); \
+  template void launch_bwd_forest<T>(hipStream_t, const DevSym&, FusedTasks, ForestBufs, const T*, const T*, double*, int, int64_t); \
   template void launch_sel_gather<T>(hipStream_t, const DevSym&, const LaunchList&, const int32_t*, SelBufs<T>); \
   template void launch_inv256<T>(hipStream_t, const DevSym&, const LaunchList&, const T*, int, const T*, const int64_t*, T*, T*); \
   template void launch_sel_Y2<T>(hipStream_t, const DevSym&, const LaunchList&, int, SelBufs<T>, const int64_t*, const T*); \
