@@ -420,6 +420,30 @@ def main():
                 traffic_source=traffic["source"] if traffic else None,
                 launches=d["launches"], avg_launch_ms=round(d["ms"] / max(d["launches"], 1), 4),
                 flops_per_launch=d["flops"] / max(d["launches"], 1))
+    # what a vendor library reaches on the same matrix cores (a reference, not the product
+    # path): hipBLASLt bf16 GEMM at 16384^3 through torch in the FP32 mode (whose products
+    # are six bf16 term products, so the reachable FP32 rate is that over six), FP64 GEMM
+    # at 8192^3 in the FP64 mode
+    ref_dt, ref_n = (torch.bfloat16, 16384) if prec_head == 1 else (torch.float64, 8192)
+    ra = torch.randn(ref_n, ref_n, device="cuda:0", dtype=ref_dt)
+    rb = torch.randn(ref_n, ref_n, device="cuda:0", dtype=ref_dt)
+    for _ in range(3):
+        rc = ra @ rb
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(5):
+        rc = ra @ rb
+    torch.cuda.synchronize()
+    lib_tf = 2.0 * ref_n ** 3 / ((time.perf_counter() - t0) / 5) / 1e12
+    del ra, rb, rc
+    torch.cuda.empty_cache()
+    lib_ceiling = lib_tf / 6.0 if prec_head == 1 else lib_tf
+    roof["library_gemm"] = {"what": f"torch.matmul {str(ref_dt).split('.')[-1]} {ref_n}^3 (hipBLASLt/rocBLAS)",
+                            "TFLOP/s": round(lib_tf, 1),
+                            "reachable_ceiling": round(lib_ceiling, 1),
+                            "frac_of_reachable": round(achieved / lib_ceiling, 4)}
+    log(f"[bench] library GEMM {ref_dt} {ref_n}^3: {lib_tf:.1f} TFLOP/s; dominant kernel at "
+        f"{achieved / lib_ceiling:.3f} of that ceiling")
     # whole-path roofline time (factor+selinv at MFMA peak, solves at HBM peak)
     w = 4.0 if prec_head == 1 else 8.0
     t_roof = ((st["flops_factor"] + st["flops_selinv"]) / (PEAK_TFLOPS[prec_head] * 1e12)

@@ -57,7 +57,7 @@ class gmrf_stats_t(ctypes.Structure):
 KERNEL_CLASSES = ["assemble", "equilibrate", "front_zero", "front_scatter", "extend_add",
                   "potrf_diag", "trsm_panel", "update_panel", "syrk_update", "copy_L", "logdet",
                   "solve_fwd", "solve_bwd", "residual", "permute", "sel_gather", "sel_Y",
-                  "sel_gemm", "sel_diag", "sel_extract", "sel_reduce"]
+                  "sel_gemm", "sel_diag", "sel_extract", "sel_reduce", "sel_gemm_small", "syrk_small"]
 
 
 class gmrf_kernel_stat_t(ctypes.Structure):

@@ -78,12 +78,13 @@ struct HostList {  // a launch list before upload
 enum KClass : int {
   KC_ASSEMBLE = 0, KC_EQUIL, KC_ZERO, KC_SCATTER, KC_EXTEND, KC_POTRF, KC_TRSM, KC_UPDATE,
   KC_SYRK, KC_COPYL, KC_LOGDET, KC_FWD, KC_BWD, KC_RESID, KC_PERMUTE, KC_SEL_GATHER, KC_SEL_Y,
-  KC_SEL_GEMM, KC_SEL_DIAG, KC_SEL_OUT, KC_SEL_RED, KC_COUNT
+  KC_SEL_GEMM, KC_SEL_DIAG, KC_SEL_OUT, KC_SEL_RED, KC_SEL_GEMM_S, KC_SYRK_S, KC_COUNT
 };
 const char* const kClassNames[KC_COUNT] = {
   "assemble", "equilibrate", "front_zero", "front_scatter", "extend_add", "potrf_diag", "trsm_panel",
   "update_panel", "syrk_update", "copy_L", "logdet", "solve_fwd", "solve_bwd", "residual",
-  "permute", "sel_gather", "sel_Y", "sel_gemm", "sel_diag", "sel_extract", "sel_reduce"};
+  "permute", "sel_gather", "sel_Y", "sel_gemm", "sel_diag", "sel_extract", "sel_reduce", "sel_gemm_small",
+  "syrk_small"};
 
 struct Level {
   std::vector<int32_t> fronts;     // sorted by column count p descending
@@ -100,7 +101,9 @@ struct Level {
   std::vector<HostList> fblk, fout, bpart, bblk;  // solves per outer block
   std::vector<HostList> sY2, sgemm2, sgred, spart2, sfin2;
   std::vector<HostList> sgemm4, sgred4;   // FP32: 256 x 256 tiles of the Sigma[R', K] products
+  std::vector<HostList> sgemm2s;          // FP32: the same products of small fronts, 128 x 128 tiles
   HostList syrk3;                          // FP32: 256 x 256 tiles of the trailing SYRK
+  HostList syrk_s;                         // FP32: the SYRK of small update matrices, 128 x 128 tiles
   std::vector<HostList> pupd4, pred4;      // FP32: left-looking panel update per outer block
   double wsize_elems_scatter = 0.0;
   // level-fused solves (one right-hand side): task ranges in the uploaded task array
@@ -314,6 +317,10 @@ struct Cost { double flops, elems; };
 constexpr int64_t kSplitMinK = 512;
 constexpr int64_t kSlots128 = 256;   // 128 x 128 tiles (FP64): one resident work-group per CU
 constexpr int64_t kSlots4 = 256;     // FP32 256 x 256 tiles: one per CU
+// FP32 mode: products with fewer rows than this (Sigma[R', K] with |R'| < kBig4, update
+// matrices of fewer than kBig4 rows) run on 128 x 128 FP32 tiles instead of the 256 x 256
+// bf16 tiles, which would be mostly padding
+constexpr int64_t kBig4 = 384;
 // Fronts of one launch have different K (their |R'|): pick one part length P and split
 // every front's K into ceil(K / P) parts, so that all parts carry about the same work.
 // P minimises rounds * (P + overhead of a partial tile) over P = Kmax / S (S = 1..128) and
@@ -680,8 +687,19 @@ gmrf_status build_plan(gmrf_t h) {
       }
       {
         // FP32 variant: 256 x 256 tiles (one work-group per 256 rows of R' and K part), one
-        // resident work-group per CU
-        auto gtiles4 = [&](int32_t s) -> int64_t { return oact(s) ? (otail(s) + 255) / 256 : 0; };
+        // resident work-group per CU.  When every product of the launch has fewer than kBig4
+        // rows (most of a 256 x 256 tile would be padding) they take the 128 x 128 FP32 tiles
+        // instead, unsplit; a launch with larger products keeps them all on the 256 x 256
+        // tiles, whose split-K choice covers the whole launch
+        bool any_big = false;
+        for (int32_t s : lv.fronts) any_big = any_big || (oact(s) && otail(s) >= kBig4);
+        auto big4 = [&](int32_t) { return any_big; };
+        auto gtiles4 = [&](int32_t s) -> int64_t { return oact(s) && big4(s) ? (otail(s) + 255) / 256 : 0; };
+        lv.sgemm2s.push_back(B.add(lv.fronts, [&](int32_t s) -> int64_t { return big4(s) ? 0 : gtiles(s); },
+                                   [&](int32_t s) {
+          const double r = (double)otail(s), b = (double)okb2(s);
+          return Cost{2.0 * r * r * b, r * r + 3.0 * r * b};
+        }, [&](int32_t) { return std::make_pair((int32_t)1, (int32_t)0); }));
         std::vector<std::pair<int64_t, int64_t>> tk4;
         for (int32_t s : lv.fronts)
           if (gtiles4(s) > 0) tk4.emplace_back(gtiles4(s), otail(s));
@@ -742,9 +760,17 @@ gmrf_status build_plan(gmrf_t h) {
     lv.syrk = B.add(lv.fronts, [&](int32_t s) -> int64_t {
       return nF(s) > pF(s) && !small(s) ? upd_tiles(nF(s), pF(s), 2, 0, kBigTile) : 0;
     }, [&](int32_t s) { return small(s) ? Cost{0.0, 0.0} : upd_cost(nF(s), pF(s), 2, 0); });
+    // FP32 SYRK: the 128 x 128 FP32 tiles when every update matrix of the depth has fewer
+    // than kBig4 rows, else all on the 256 x 256 tiles
+    bool any_big_u = false;
+    for (int32_t s : lv.fronts) any_big_u = any_big_u || (!small(s) && nF(s) - pF(s) >= kBig4);
+    auto big_syrk = [&](int32_t) { return any_big_u; };
     lv.syrk3 = B.add(lv.fronts, [&](int32_t s) -> int64_t {
-      return nF(s) > pF(s) && !small(s) ? upd_tiles(nF(s), pF(s), 2, 0, 256, 256) : 0;
-    }, [&](int32_t s) { return small(s) ? Cost{0.0, 0.0} : upd_cost(nF(s), pF(s), 2, 0); });
+      return nF(s) > pF(s) && !small(s) && big_syrk(s) ? upd_tiles(nF(s), pF(s), 2, 0, 256, 256) : 0;
+    }, [&](int32_t s) { return small(s) || !big_syrk(s) ? Cost{0.0, 0.0} : upd_cost(nF(s), pF(s), 2, 0); });
+    lv.syrk_s = B.add(lv.fronts, [&](int32_t s) -> int64_t {
+      return nF(s) > pF(s) && !small(s) && !big_syrk(s) ? upd_tiles(nF(s), pF(s), 2, 0, kBigTile) : 0;
+    }, [&](int32_t s) { return small(s) || big_syrk(s) ? Cost{0.0, 0.0} : upd_cost(nF(s), pF(s), 2, 0); });
     lv.inv256 = B.add(lv.fronts, [&](int32_t s) -> int64_t { return (pF(s) + nb - 1) / nb; }, [&](int32_t s) {
       const double p = (double)pF(s);
       return Cost{p * (double)kNB2 * (double)kNB2 / 3.0, p * (double)kNB2};
@@ -999,6 +1025,9 @@ gmrf_status run_factor(gmrf_t h) {
       if (lv.syrk3.total > 0)
         prof_launch(h, KC_SYRK, lv.syrk3.flops, lv.syrk3.elems,
                     [&] { launch_syrk4(st, S, dev_list(h, lv.syrk3), B); });
+      if (lv.syrk_s.total > 0)
+        prof_launch(h, KC_SYRK_S, lv.syrk_s.flops, lv.syrk_s.elems,
+                    [&] { launch_update<T>(st, S, dev_list(h, lv.syrk_s), 0, 2, B); });
     } else {
       if (lv.syrk.total > 0)
         prof_launch(h, KC_SYRK, lv.syrk.flops, lv.syrk.elems,
@@ -1157,6 +1186,9 @@ gmrf_status run_selinv(gmrf_t h, double* var, double* sigq) {
       if (R.total > 0)
         prof_launch(h, KC_SEL_RED, 0.0, R.elems,
                     [&] { launch_sel_gemm_reduce<T>(st, S, dev_list(h, R), t, B); });
+      if (f32 && lv.sgemm2s[t].total > 0)
+        prof_launch(h, KC_SEL_GEMM_S, lv.sgemm2s[t].flops, lv.sgemm2s[t].elems,
+                    [&] { launch_sel_gemm2<T>(st, S, dev_list(h, lv.sgemm2s[t]), t, B); });
       prof_launch(h, KC_SEL_DIAG, lv.spart2[t].flops + lv.sfin2[t].flops, lv.spart2[t].elems + lv.sfin2[t].elems, [&] {
         launch_sel_part2<T>(st, S, dev_list(h, lv.spart2[t]), t, B);
         launch_sel_fin2<T>(st, S, dev_list(h, lv.sfin2[t]), dev_list(h, lv.spart2[t]), t, B, h->d_D2off.p, D2);

@@ -2049,7 +2049,10 @@ __device__ __forceinline__ OuterBlk outer_blk(int p, int n, int step) {
 // X_ij = -Linv_ii sum_{j<=l<i} L_il X_lj for i > j.  One work-group per (front, 64-block
 // b), b = 4 K + j; X is column-major with ld kb2 at D2 + D2off[s] + K * 256^2 (zeros
 // above the diagonal).  `base` selects where L lives: the square front (during the
-// factorisation) or the L panel storage; both have leading dimension n_s.
+// factorisation) or the L panel storage; both have leading dimension n_s.  Each column
+// block is written and read back by the same work-group only, so its barriers (work-group
+// scope) order those stores; a device-scope fence here would write back the L2 cache in
+// every one of the (many, on a forest of small fronts) work-groups.
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_inv256(DevSym S, LaunchList L, const T* __restrict__ Lbase,
                                                      int from_front, const T* __restrict__ Dinv,
@@ -2085,8 +2088,7 @@ __global__ __launch_bounds__(kThreads) void k_inv256(DevSym S, LaunchList L, con
       v = Dinv[S.Doff[s] + (int64_t)(blk0 + j) * kNB * kNB + (r - kNB * j) + c * kNB];
     XT[(kNB * j + c) + (int64_t)r * kb2] = v;
   }
-  __threadfence();
-  __syncthreads();
+  __syncthreads();   // orders this work-group's global stores before its own reads
   for (int i = j + 1; i < nsub; ++i) {
     const int sbi = min(kNB, kb2 - kNB * i);
     typename V4<T>::type acc[2][2];
@@ -2097,7 +2099,6 @@ __global__ __launch_bounds__(kThreads) void k_inv256(DevSym S, LaunchList L, con
     for_acc<T>(acc, [&](int r, int c, T v) {
       if (r < sbi && c < sbj) Xij[r + (int64_t)c * kb2] = v;
     });
-    __threadfence();
     __syncthreads();
     zero_acc<T>(acc);
     gemm_tile<T, false, true>(Dinv + S.Doff[s] + (int64_t)(blk0 + i) * kNB * kNB, kNB, Xij, kb2, sbi, sbj, sbi,
@@ -2110,7 +2111,6 @@ __global__ __launch_bounds__(kThreads) void k_inv256(DevSym S, LaunchList L, con
         XTji[c + (int64_t)r * kb2] = -v;
       }
     });
-    __threadfence();
     __syncthreads();
   }
 }
@@ -2385,6 +2385,8 @@ inline unsigned grid_for(int64_t n, int64_t cap = 65536) {
 // stops waiting (the result is then wrong and the error is reported), so every launch
 // terminates.
 constexpr int kSpinLimit = 1 << 20;
+// groups whose fronts have at most this many rows run one task per wave
+constexpr int kWaveTaskRows = 0;
 
 __device__ __forceinline__ double load_dev(const double* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -2453,6 +2455,162 @@ __device__ __forceinline__ int wait_count(int32_t* ctr, int need, int32_t* err, 
   return wait_progress(ctr, need, err, slot);
 }
 
+// Wave-level tasks for the groups of small fronts (at most 256 rows): each wave of the
+// work-group runs its own tasks of the group (tasks w, w + 4, ... in order), with lanes
+// on the 64 rows (forward) or the 64 pivot columns (backward) of its chunk, values of other
+// lanes broadcast by lane reads, and waits polled by lane 0 without work-group barriers.
+// Every wave still only waits for earlier tasks, and the earliest unfinished task of a
+// group is always the one its wave is running, so the group progresses.
+__device__ __forceinline__ int wave_wait(int32_t* ctr, int need, int32_t* err) {
+  int v = 0;
+  if ((threadIdx.x & 63) == 0) {
+    v = __hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    int spins = 0;
+    while (v < need) {
+      if (++spins > kSpinLimit) {
+        atomicOr(err, 1);
+        v = INT_MAX;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+      v = __hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+  return __builtin_amdgcn_readfirstlane(v);
+}
+
+// the wave's stores are complete before lane 0 stores the counter
+__device__ __forceinline__ void wave_publish(int32_t* prog, int value) {
+  if ((threadIdx.x & 63) == 0) {
+    __builtin_amdgcn_s_waitcnt(0);
+    __hip_atomic_store(prog, value, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+// sum over k < kend of col(k)[lane] * v_k, v_k the value of lane k; column loads in
+// batches of 16
+template <typename T, typename Col>
+__device__ __forceinline__ double wave_gemv(Col col, double v, int kend) {
+  double acc = 0.0;
+  for (int k0 = 0; k0 < kend; k0 += 16) {
+    T cv[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) cv[u] = col(min(k0 + u, kend - 1));
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const double vk = readlane_f64(v, min(k0 + u, 63));
+      acc += k0 + u < kend ? (double)cv[u] * vk : 0.0;
+    }
+  }
+  return acc;
+}
+
+template <typename T>
+__device__ __forceinline__ void fwd_task_wave(const DevSym& S, const FusedTasks& F, const ForestBufs& G,
+                                              const T* __restrict__ Lp, const T* __restrict__ D, double* xp,
+                                              int s, int c) {
+  const int n = fn(S, s), p = fp(S, s);
+  const int P = (p + 63) >> 6;
+  const int nb = min(c, P);
+  const int lane = threadIdx.x & 63;
+  const int row = 64 * c + lane;
+  const T* Lr = Lp + S.Loff[s] + min(row, n - 1);
+  const int64_t f0 = S.sfirst[s];
+  int32_t* prog = F.prog + s;
+  if (G.need[s] > 0) (void)wave_wait(G.kids + s, G.need[s], F.err);
+  double vi = 0.0;
+  if (row < n) {
+    vi = row < p ? xp[f0 + row] : 0.0;
+    const int64_t r0 = G.roff[s] + row;
+    for (int64_t e = G.gptr[r0]; e < G.gptr[r0 + 1]; ++e) vi += load_dev(G.U + G.gsrc[e]);
+  }
+  double acc = 0.0;
+  for (int t = 0; t < nb; ++t) {
+    (void)wave_wait(prog, t + 1, F.err);
+    const int q = min(64 * t + lane, p - 1);
+    const double x = load_dev(xp + f0 + q);
+    acc += wave_gemv<T>([&](int k) { return Lr[(int64_t)(64 * t + k) * n]; }, x, min(64, p - 64 * t));
+  }
+  double extra = 0.0;
+  if (c < P) {
+    const int pb = min(64, p - 64 * c);
+    const T* Db = D + S.Doff[s] + (int64_t)c * kNB * kNB;
+    const double xsrc = lane < pb ? vi - acc : 0.0;
+    const double xc = wave_gemv<T>([&](int k) { return Db[lane + k * kNB]; }, xsrc, pb);
+    if (lane < pb) store_dev(xp + f0 + 64 * c + lane, xc);
+    wave_publish(prog, c + 1);
+    if (64 * c + 64 > p && n > p)
+      extra = wave_gemv<T>([&](int k) { return Lr[(int64_t)(64 * c + k) * n]; }, xc, pb);
+  }
+  if (64 * c + 63 >= p && n > p) {
+    if (row >= p && row < n) store_dev(G.U + G.uoff[s] + (row - p), vi - acc - extra);
+    const int par = G.parent[s];
+    if (lane == 0 && par >= 0) {
+      __builtin_amdgcn_s_waitcnt(0);
+      __hip_atomic_fetch_add(G.kids + par, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+}
+
+// lanes on the pivot columns j = 64 c + lane of the chunk: r_j = y_j - sum over the rows
+// below the block of L[row, j] x(row), then x_c = Linv_cc^T r
+template <typename T>
+__device__ __forceinline__ void bwd_task_wave(const DevSym& S, const FusedTasks& F, const ForestBufs& G,
+                                              const T* __restrict__ Lp, const T* __restrict__ D, double* xp,
+                                              int nrhs, int64_t ldx, int s, int c) {
+  const int n = fn(S, s), p = fp(S, s);
+  const int P = (p + 63) >> 6;
+  const int pb = min(64, p - 64 * c);
+  const int lane = threadIdx.x & 63;
+  const int64_t f0 = S.sfirst[s];
+  const int32_t* rows = S.rows + S.rowptr[s];
+  int32_t* prog = F.prog + s;
+  const int jc = 64 * c + min(lane, pb - 1);
+  const T* Lc = Lp + S.Loff[s] + (int64_t)jc * n;
+  const T* Db = D + S.Doff[s] + (int64_t)c * kNB * kNB;
+  const int par = G.parent[s];
+  if (par >= 0 && n > p) (void)wave_wait(F.prog + par, (fp(S, par) + 63) >> 6, F.err);
+  int ready = 0;
+  for (int rr = 0; rr < nrhs; ++rr) {
+    double* xr = xp + (int64_t)rr * ldx;
+    double acc = 0.0;
+    // rows below p: ancestors' unknowns; then the pivot blocks right of this one
+    for (int r0 = p; r0 < n; r0 += 16) {
+      double xv[16];
+      T lv[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int rc = min(r0 + u, n - 1);
+        xv[u] = load_dev(xr + rows[rc]);
+        lv[u] = Lc[rc];
+      }
+#pragma unroll
+      for (int u = 0; u < 16; ++u) acc += r0 + u < n ? (double)lv[u] * xv[u] : 0.0;
+    }
+    for (int t = P - 1; t > c; --t) {
+      if (ready < P - t) ready = wave_wait(prog, P - t, F.err);
+      const int tb = min(64, p - 64 * t);
+      for (int r0 = 0; r0 < tb; r0 += 16) {
+        double xv[16];
+        T lv[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+          const int rc = 64 * t + min(r0 + u, tb - 1);
+          xv[u] = load_dev(xr + f0 + rc);
+          lv[u] = Lc[rc];
+        }
+#pragma unroll
+        for (int u = 0; u < 16; ++u) acc += r0 + u < tb ? (double)lv[u] * xv[u] : 0.0;
+      }
+    }
+    const double rj = lane < pb ? xr[f0 + 64 * c + lane] - acc : 0.0;
+    // x_l = sum_i Linv[i][l] r_i: lane l reads column l of the stored inverse
+    const double xl = wave_gemv<T>([&](int i) { return Db[i + min(lane, pb - 1) * kNB]; }, rj, pb);
+    if (lane < pb) store_dev(xr + f0 + 64 * c + lane, xl);
+  }
+  wave_publish(prog, P - c);
+}
+
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_fwd_forest(DevSym S, FusedTasks F, ForestBufs G,
                                                          const T* __restrict__ Lp, const T* __restrict__ D,
@@ -2465,6 +2623,11 @@ __global__ __launch_bounds__(kThreads) void k_fwd_forest(DevSym S, FusedTasks F,
   __syncthreads();
   const int grp = s_task;
   const int t_end = F.group[grp + 1];
+  if (fn(S, F.task[F.group[grp]].x) <= kWaveTaskRows) {
+    for (int ti = F.group[grp] + (int)(threadIdx.x >> 6); ti < t_end; ti += kThreads / 64)
+      fwd_task_wave<T>(S, F, G, Lp, D, xp, F.task[ti].x, F.task[ti].y);
+    return;
+  }
   for (int ti = F.group[grp]; ti < t_end; ++ti) {
   const int2 tk = F.task[ti];
   const int s = tk.x, c = tk.y;
@@ -2575,6 +2738,11 @@ __global__ __launch_bounds__(kThreads) void k_bwd_forest(DevSym S, FusedTasks F,
   __syncthreads();
   const int grp = s_task;
   const int t_end = F.group[grp + 1];
+  if (fn(S, F.task[F.group[grp]].x) <= kWaveTaskRows) {
+    for (int ti = F.group[grp] + (int)(threadIdx.x >> 6); ti < t_end; ti += kThreads / 64)
+      bwd_task_wave<T>(S, F, G, Lp, D, xp, nrhs, ldx, F.task[ti].x, F.task[ti].y);
+    return;
+  }
   for (int ti = F.group[grp]; ti < t_end; ++ti) {
   const int2 tk = F.task[ti];
   const int s = tk.x, c = tk.y;
