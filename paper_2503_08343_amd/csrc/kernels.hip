@@ -2385,8 +2385,8 @@ inline unsigned grid_for(int64_t n, int64_t cap = 65536) {
 // stops waiting (the result is then wrong and the error is reported), so every launch
 // terminates.
 constexpr int kSpinLimit = 1 << 20;
-// groups whose fronts have at most this many rows run one task per wave
-constexpr int kWaveTaskRows = 0;
+// forward-pass groups whose fronts have at most this many rows run one task per wave
+constexpr int kWaveTaskRows = 256;
 
 __device__ __forceinline__ double load_dev(const double* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -2455,10 +2455,12 @@ __device__ __forceinline__ int wait_count(int32_t* ctr, int need, int32_t* err, 
   return wait_progress(ctr, need, err, slot);
 }
 
-// Wave-level tasks for the groups of small fronts (at most 256 rows): each wave of the
-// work-group runs its own tasks of the group (tasks w, w + 4, ... in order), with lanes
-// on the 64 rows (forward) or the 64 pivot columns (backward) of its chunk, values of other
-// lanes broadcast by lane reads, and waits polled by lane 0 without work-group barriers.
+// Wave-level forward tasks for the groups of small fronts (at most 256 rows): each wave of
+// the work-group runs its own tasks of the group (tasks w, w + 4, ... in order), with lanes
+// on the 64 rows of its chunk, values of other lanes broadcast by lane reads, and waits
+// polled by lane 0 without work-group barriers.  (The backward pass keeps one task per
+// work-group: with lanes on rows its column sums need cross-lane reductions, which the
+// four waves share there.)
 // Every wave still only waits for earlier tasks, and the earliest unfinished task of a
 // group is always the one its wave is running, so the group progresses.
 __device__ __forceinline__ int wave_wait(int32_t* ctr, int need, int32_t* err) {
@@ -2550,65 +2552,6 @@ __device__ __forceinline__ void fwd_task_wave(const DevSym& S, const FusedTasks&
       __hip_atomic_fetch_add(G.kids + par, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
   }
-}
-
-// lanes on the pivot columns j = 64 c + lane of the chunk: r_j = y_j - sum over the rows
-// below the block of L[row, j] x(row), then x_c = Linv_cc^T r
-template <typename T>
-__device__ __forceinline__ void bwd_task_wave(const DevSym& S, const FusedTasks& F, const ForestBufs& G,
-                                              const T* __restrict__ Lp, const T* __restrict__ D, double* xp,
-                                              int nrhs, int64_t ldx, int s, int c) {
-  const int n = fn(S, s), p = fp(S, s);
-  const int P = (p + 63) >> 6;
-  const int pb = min(64, p - 64 * c);
-  const int lane = threadIdx.x & 63;
-  const int64_t f0 = S.sfirst[s];
-  const int32_t* rows = S.rows + S.rowptr[s];
-  int32_t* prog = F.prog + s;
-  const int jc = 64 * c + min(lane, pb - 1);
-  const T* Lc = Lp + S.Loff[s] + (int64_t)jc * n;
-  const T* Db = D + S.Doff[s] + (int64_t)c * kNB * kNB;
-  const int par = G.parent[s];
-  if (par >= 0 && n > p) (void)wave_wait(F.prog + par, (fp(S, par) + 63) >> 6, F.err);
-  int ready = 0;
-  for (int rr = 0; rr < nrhs; ++rr) {
-    double* xr = xp + (int64_t)rr * ldx;
-    double acc = 0.0;
-    // rows below p: ancestors' unknowns; then the pivot blocks right of this one
-    for (int r0 = p; r0 < n; r0 += 16) {
-      double xv[16];
-      T lv[16];
-#pragma unroll
-      for (int u = 0; u < 16; ++u) {
-        const int rc = min(r0 + u, n - 1);
-        xv[u] = load_dev(xr + rows[rc]);
-        lv[u] = Lc[rc];
-      }
-#pragma unroll
-      for (int u = 0; u < 16; ++u) acc += r0 + u < n ? (double)lv[u] * xv[u] : 0.0;
-    }
-    for (int t = P - 1; t > c; --t) {
-      if (ready < P - t) ready = wave_wait(prog, P - t, F.err);
-      const int tb = min(64, p - 64 * t);
-      for (int r0 = 0; r0 < tb; r0 += 16) {
-        double xv[16];
-        T lv[16];
-#pragma unroll
-        for (int u = 0; u < 16; ++u) {
-          const int rc = 64 * t + min(r0 + u, tb - 1);
-          xv[u] = load_dev(xr + f0 + rc);
-          lv[u] = Lc[rc];
-        }
-#pragma unroll
-        for (int u = 0; u < 16; ++u) acc += r0 + u < tb ? (double)lv[u] * xv[u] : 0.0;
-      }
-    }
-    const double rj = lane < pb ? xr[f0 + 64 * c + lane] - acc : 0.0;
-    // x_l = sum_i Linv[i][l] r_i: lane l reads column l of the stored inverse
-    const double xl = wave_gemv<T>([&](int i) { return Db[i + min(lane, pb - 1) * kNB]; }, rj, pb);
-    if (lane < pb) store_dev(xr + f0 + 64 * c + lane, xl);
-  }
-  wave_publish(prog, P - c);
 }
 
 template <typename T>
@@ -2738,11 +2681,6 @@ __global__ __launch_bounds__(kThreads) void k_bwd_forest(DevSym S, FusedTasks F,
   __syncthreads();
   const int grp = s_task;
   const int t_end = F.group[grp + 1];
-  if (fn(S, F.task[F.group[grp]].x) <= kWaveTaskRows) {
-    for (int ti = F.group[grp] + (int)(threadIdx.x >> 6); ti < t_end; ti += kThreads / 64)
-      bwd_task_wave<T>(S, F, G, Lp, D, xp, nrhs, ldx, F.task[ti].x, F.task[ti].y);
-    return;
-  }
   for (int ti = F.group[grp]; ti < t_end; ++ti) {
   const int2 tk = F.task[ti];
   const int s = tk.x, c = tk.y;

@@ -63,8 +63,9 @@ def test_matern_noise_posterior_matches_oracle(gpu_lib, name, precision):
     ctx.close()
 
 
-# FP32 errors measured on MI355X: (max relative variance error, relative log-det error)
-MEASURED_FP32 = {"matern_noise_20x20x10": (1.93e-05, 1.29e-10), "matern_noise_28x28x12": (3.57e-05, 5.88e-09)}
+# FP32 errors measured on MI355X: (max relative variance error, relative log-det error);
+# the small update matrices of these cases run on the 128 x 128 FP32 tiles
+MEASURED_FP32 = {"matern_noise_20x20x10": (1.40e-05, 1.39e-09), "matern_noise_28x28x12": (3.57e-05, 5.88e-09)}
 
 
 def test_matern_noise_full_size(gpu_lib):
