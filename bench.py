@@ -43,7 +43,7 @@ HBM_GBS = 8000.0
 # (FETCH_SIZE, WRITE_SIZE) scaled by the same counters over a plain 1 GiB copy; valid only
 # for the kernel build they were taken on (keyed by class and precision: 1 = FP32+refine)
 PMC_TRAFFIC = {
-    ("sel_gemm", 1): {"bytes_per_launch": 3.3455e9, "kernel": "k_sel_gemm4",
+    ("sel_gemm", 1): {"bytes_per_launch": 3.4291e+09, "kernel": "k_sel_gemm4",
                       "source": "profiles/sel_gemm4_advdiff128x128x64_fp32_hbm_bytes.md"},
 }
 
@@ -192,8 +192,7 @@ def secondary(binding, which, steps, warmup, autotune=False):
         mass = torch.from_numpy(np.ascontiguousarray(m["mass"])).cuda()
         s3 = torch.from_numpy(np.ascontiguousarray(m["s3"].ravel())).cuda()
         out = {"workload": f"burgers_spacetime {m['nx']}x{m['nt']} ({p.n:,} unknowns), 10 GN iterations"}
-        # the condition number of this posterior (about 1.5e11) is beyond the FP32 factor
-        for mname, prec in (("fp64", binding.GMRF_FP64),):
+        for mname, prec in (("fp32", binding.GMRF_FP32_REFINE), ("fp64", binding.GMRF_FP64)):
             ctx = binding.posterior_context(p, precision=prec)
             st = ctx.stats()
             ts = []
@@ -273,9 +272,12 @@ def secondary(binding, which, steps, warmup, autotune=False):
                     ts.append(time.perf_counter() - t0)
             wall = float(np.mean(ts))
             l2 = hh * float(np.linalg.norm(u.cpu().numpy() - m["u_true"]))
-            below = np.flatnonzero(rec[:, 2] < 1e-5)
+            # converged: Newton decrement in [0, 1e-5), or no trial step decreases the objective
+            # any more (alpha = 0: the rounding floor of this system)
+            done = np.flatnonzero(((rec[:, 2] >= 0) & (rec[:, 2] < 1e-5)) | (rec[:, 1] == 0.0))
             out[mname] = {"ms_per_10_iterations": round(wall * 1e3, 2), "L2_error_vs_exact": l2,
-                          "first_iteration_below_1e-5": int(below[0]) if below.size else None,
+                          "first_converged_iteration": int(done[0]) if done.size else None,
+                          "objective": [float(v) for v in rec[:, 0]], "step": [float(v) for v in rec[:, 1]],
                           "factor_GFLOP/s": round(10 * st["flops_factor"] / wall / 1e9, 1)}
             ctx.close()
             log(f"[bench] c6 {mname}: {wall * 1e3:.1f} ms for 10 iterations, L2 error {l2:.3e}")
@@ -319,6 +321,57 @@ def secondary(binding, which, steps, warmup, autotune=False):
         ctx.close()
         torch.cuda.empty_cache()
         log(f"[bench] c7 fp64: {ms} ms, {F / tot / 1e9:.0f} GFLOP/s")
+    if "c8" in which:
+        # the conjugate-gradient path (Sec. 3.2) on the 1M-unknown space-time posterior:
+        # PCG for the mean with the FP32 factor as preconditioner, Jacobi PCG iterations
+        # (HBM-bound: one Q_post product, dots and vector updates per iteration), and one CG
+        # sample from the left square root of the prior
+        p = gi.advdiff_spacetime()
+        ctx = binding.posterior_context(p, precision=binding.GMRF_FP32_REFINE)
+        st = ctx.stats()
+        out = {"workload": f"advdiff_spacetime 128x128x64 ({p.n:,} unknowns, nnz(Q) {p.Q.nnz:,})"}
+        ts, its = [], None
+        for rep in range(warmup + steps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            x, its, rres = ctx.pcg(precond=1, maxit=100, tol=1e-10)
+            torch.cuda.synchronize()
+            if rep >= warmup:
+                ts.append(time.perf_counter() - t0)
+        out["pcg_factor_preconditioned"] = {"iterations": int(its[0]), "rel_resid": float(rres[0]),
+                                            "ms": round(1e3 * float(np.mean(ts)), 2)}
+        nj = 200
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x, its, rres = ctx.pcg(precond=0, maxit=nj, tol=1e-300, raise_not_converged=False)
+        torch.cuda.synchronize()
+        tj = (time.perf_counter() - t0) / max(int(its[0]), 1)
+        # algorithmic bytes of one Jacobi PCG iteration: Q_post in CSR (8-byte value, 4-byte
+        # column per entry, 8-byte row pointers), p read once and q written once by the
+        # product, and the vector kernels (two dots, the norm, x/r update, diagonal scaling,
+        # p update) 160 bytes per unknown
+        bj = 12.0 * p.Q.nnz + 8.0 * (p.n + 1) + 16.0 * p.n + 160.0 * p.n
+        out["pcg_jacobi"] = {"iterations": int(its[0]), "ms_per_iteration": round(1e3 * tj, 4),
+                             "rel_resid": float(rres[0]), "algorithmic_bytes_per_iteration": bj,
+                             "GB/s": round(bj / tj / 1e9, 1), "frac_of_hbm_peak": round(bj / tj / 1e9 / HBM_GBS, 4)}
+        R = gi.prior_sqrt(p)
+        t = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0", dt)  # noqa: E731
+        ri, rj, rv = t(R.indptr.astype(np.int64), torch.int64), t(R.indices.astype(np.int32), torch.int32), \
+            t(R.data, torch.float64)
+        rng = gi.rng_for(81)
+        w1 = t(rng.standard_normal((1, R.shape[1])), torch.float64)
+        w2 = t(rng.standard_normal((1, p.A.shape[0])), torch.float64)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        xs, its = ctx.sample_cg(ri, rj, rv, w1, w2, precond=1, maxit=100, tol=1e-10)
+        torch.cuda.synchronize()
+        out["cg_sample_factor_preconditioned"] = {"iterations": int(its[0]),
+                                                  "ms": round(1e3 * (time.perf_counter() - t0), 2)}
+        res["c8_cg_path"] = out
+        ctx.close()
+        torch.cuda.empty_cache()
+        log(f"[bench] c8: PCG(factor) {out['pcg_factor_preconditioned']}, Jacobi {out['pcg_jacobi']['ms_per_iteration']} "
+            f"ms/iteration ({out['pcg_jacobi']['GB/s']} GB/s), CG sample {out['cg_sample_factor_preconditioned']}")
     if "c5" in which:
         import math
         from paper_2503_08343_amd import adjoint
@@ -354,7 +407,8 @@ def main():
     ap.add_argument("--configs", default="c2",
                     help="c2 (the headline workload) plus any of c2m (the same with Matern noise in "
                          "space), c3 (Gauss-Newton), c4 (batch), c5 (LML gradient), reported under "
-                         "'secondary'; c6 (nonlinear elliptic Gauss-Newton); c7 (P2 Darcy with Dirichlet constraints)")
+                         "'secondary'; c6 (nonlinear elliptic Gauss-Newton); c7 (P2 Darcy with Dirichlet constraints); "
+                         "c8 (conjugate-gradient path)")
     ap.add_argument("--autotune", action="store_true",
                     help="pick the batch's supernode options with the autotuner (cached) before timing it")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -473,7 +527,8 @@ def main():
         "roofline": roof,
         "refine": {"iters": hr["iters"], "rel_resid": hr["resid"]},
         "kernels": {k: {"ms": round(v["ms"], 3), "launches": v["launches"],
-                        "tflops": round(v["flops"] / (v["ms"] * 1e-3) / 1e12, 3) if v["ms"] > 0 else 0.0}
+                        "tflops": round(v["flops"] / (v["ms"] * 1e-3) / 1e12, 3) if v["ms"] > 0 else 0.0,
+                        "algorithmic_bytes_per_launch": v["bytes"] / v["launches"]}
                     for k, v in ks.items() if v["launches"] > 0},
     }
     if "fp64" in res and "fp32" in res:
@@ -513,7 +568,7 @@ def main():
         out["cpu_baseline"] = cpu_baseline()
     ctx.close()
     which = [c.strip() for c in args.configs.split(",")]
-    if any(c in which for c in ("c2m", "c3", "c4", "c5", "c6", "c7")):
+    if any(c in which for c in ("c2m", "c3", "c4", "c5", "c6", "c7", "c8")):
         out["secondary"] = secondary(binding, which, args.steps, args.warmup, autotune=args.autotune)
     print(json.dumps(out))
 
