@@ -120,11 +120,11 @@ def run_mode(binding, ctx, dev, prob, precision, steps, warmup, z_kn, profile):
     return wall, phases, out, (breakdown, dom, live), seq
 
 
-def cpu_baseline():
+def cpu_baseline(ns=32, nt=16):
     """The oracle (plain C, one thread) on a bounded sample of the same workload."""
     import gmrf_inputs as gi
     import oracle as O
-    p = gi.advdiff_spacetime(ns=32, nt=16, seed=2)
+    p = gi.advdiff_spacetime(ns=ns, nt=nt, seed=2)
     Qp, h = O.assemble(p.Q, p.A, p.q_eps, p.y, p.b)
     perm = O.nd_order(p.coords, Qp)
     t0 = time.perf_counter()
@@ -136,7 +136,7 @@ def cpu_baseline():
     c = F.colcounts().astype(np.float64)
     flops = (c * c).sum() * 3.0 + 4.0 * F.nnz - 2.0 * F.n
     return dict(value=flops / t / 1e9, unit="GFLOP/s", cores=1, kind="oracle",
-                sample="advdiff_spacetime 32x32x16 (16,384 dofs): oracle factor + log-det + mean + "
+                sample=f"advdiff_spacetime {ns}x{ns}x{nt} ({p.n:,} dofs): oracle factor + log-det + mean + "
                        f"Takahashi selinv, {t:.1f} s, plain C on one host thread",
                 seconds=t, host_cores=os.cpu_count())
 
@@ -346,11 +346,11 @@ def secondary(binding, which, steps, warmup, autotune=False):
         x, its, rres = ctx.pcg(precond=0, maxit=nj, tol=1e-300, raise_not_converged=False)
         torch.cuda.synchronize()
         tj = (time.perf_counter() - t0) / max(int(its[0]), 1)
-        # algorithmic bytes of one Jacobi PCG iteration: Q_post in CSR (8-byte value, 4-byte
-        # column per entry, 8-byte row pointers), p read once and q written once by the
-        # product, and the vector kernels (two dots, the norm, x/r update, diagonal scaling,
-        # p update) 160 bytes per unknown
-        bj = 12.0 * p.Q.nnz + 8.0 * (p.n + 1) + 16.0 * p.n + 160.0 * p.n
+        # algorithmic bytes of one Jacobi PCG iteration in its three sweeps: the product reads
+        # Q_post in CSR (8-byte value, 4-byte column per entry, 8-byte row pointers) and p once
+        # and writes q (p^T q from registers); the update reads p, q, x, r and the diagonal and
+        # writes x, r, z (r^T z and r^T r from registers); the p update reads z, p and writes p
+        bj = 12.0 * p.Q.nnz + 8.0 * (p.n + 1) + 16.0 * p.n + 64.0 * p.n + 24.0 * p.n
         out["pcg_jacobi"] = {"iterations": int(its[0]), "ms_per_iteration": round(1e3 * tj, 4),
                              "rel_resid": float(rres[0]), "algorithmic_bytes_per_iteration": bj,
                              "GB/s": round(bj / tj / 1e9, 1), "frac_of_hbm_peak": round(bj / tj / 1e9 / HBM_GBS, 4)}
@@ -361,6 +361,7 @@ def secondary(binding, which, steps, warmup, autotune=False):
         rng = gi.rng_for(81)
         w1 = t(rng.standard_normal((1, R.shape[1])), torch.float64)
         w2 = t(rng.standard_normal((1, p.A.shape[0])), torch.float64)
+        ctx.solve(max_refine=30, tol=1e-12)          # the sample is mu_post + Q_post^-1 b
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         xs, its = ctx.sample_cg(ri, rj, rv, w1, w2, precond=1, maxit=100, tol=1e-10)
@@ -409,6 +410,8 @@ def main():
                          "space), c3 (Gauss-Newton), c4 (batch), c5 (LML gradient), reported under "
                          "'secondary'; c6 (nonlinear elliptic Gauss-Newton); c7 (P2 Darcy with Dirichlet constraints); "
                          "c8 (conjugate-gradient path)")
+    ap.add_argument("--cpu-midsize", action="store_true",
+                    help="also time the oracle on the 40x40x20 version of the workload (32,000 dofs)")
     ap.add_argument("--autotune", action="store_true",
                     help="pick the batch's supernode options with the autotuner (cached) before timing it")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -566,6 +569,9 @@ def main():
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle on a bounded sample)")
         out["cpu_baseline"] = cpu_baseline()
+        if args.cpu_midsize:
+            log("[bench] cpu baseline at 40x40x20 (about 40 s)")
+            out["cpu_baseline_midsize"] = cpu_baseline(40, 20)
     ctx.close()
     which = [c.strip() for c in args.configs.split(",")]
     if any(c in which for c in ("c2m", "c3", "c4", "c5", "c6", "c7", "c8")):

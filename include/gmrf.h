@@ -250,7 +250,9 @@ gmrf_status gmrf_gn_pointwise(gmrf_t h, const double* lin_val, const int32_t* nl
    column-major, device) solved one after the other; rhs = NULL (k = 1) solves for the
    posterior mean (Sec. 3.1: x = mu + Q_post^-1 h).  x0 (device, nullable): starting
    iterate, e.g. the previous Gauss-Newton direction (Sec. 3.3).  Stops when
-   ||rhs - Q_post x|| <= tol ||rhs|| or after maxit iterations; iters_out / resid_out
+   ||rhs - Q_post x|| <= tol ||rhs|| or after maxit iterations (with the diagonal
+   preconditioner the residual is checked every 8 iterations, so up to 7 iterations may
+   follow the one that met the tolerance); iters_out / resid_out
    (host, k, nullable) receive the counts and final relative residuals.  Returns
    GMRF_ERR_NOT_CONVERGED if a column stopped above tol (x_out still written). */
 gmrf_status gmrf_pcg(gmrf_t h, int64_t k, const double* rhs, const double* x0, double* x_out, int precond,

@@ -157,6 +157,7 @@ struct gmrf_ctx {
   // whole-forest solves: task lists (forward deepest first, backward roots first), the
   // children's update gather map and the update parts of all fronts
   DevArr<int2> d_ftasks, d_btasks;
+  DevArr<double> d_cgpart;             // partial sums of the fused Jacobi CG iteration
   DevArr<int32_t> d_fgrp, d_bgrp;   // task groups of the whole-forest solves
   int64_t n_fgrp = 0, n_bgrp = 0;   // group counts (the arrays may be larger after a re-analysis)
   DevArr<int32_t> d_fneed;
@@ -1421,6 +1422,36 @@ void pcg_solve(gmrf_t h, const double* b, double* x, bool warm, int precond, int
   if (!warm) launch_fill_f64(st, x, n, 0.0);
   launch_resid(st, n, h->d_qrp.p, h->d_qci.p, h->d_qpost.p, b, x, r);   // r = b - Q x
   launch_norm2(st, n, b, h->d_red.p, sc + 4);
+  if (precond == 0) {
+    // diagonal preconditioner: five launches per iteration (sc[0], sc[1]: r^T z of the
+    // current and next iteration, sc[2]: p^T q, sc[5]: ||r||^2); the residual norm is read on
+    // the host every kCgCheck iterations (and at maxit), so up to kCgCheck - 1 iterations
+    // may run past the one that first met the tolerance
+    constexpr int kCgCheck = 8;
+    launch_jacobi(st, n, h->d_qdiag.p, h->d_qpost.p, r, z);
+    launch_copy_f64(st, n, z, p);
+    launch_dot(st, n, r, z, h->d_red.p, sc + 0);
+    launch_norm2(st, n, r, h->d_red.p, sc + 3);
+    double hs[2] = {0.0, 0.0};
+    int it = 0, cur = 0;
+    double rr = 0.0;
+    while (true) {
+      if (it % kCgCheck == 0 || it >= maxit) {
+        if (it > 0) launch_partial_norm(st, h->d_cgpart.p, sc + 3);
+        if (hipMemcpyAsync(hs, sc + 3, 2 * sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess) break;
+        if (hipStreamSynchronize(st) != hipSuccess) break;
+        rr = hs[0] / (hs[1] > 0.0 ? hs[1] : 1.0);
+        if (rr <= tol || it >= maxit || !std::isfinite(rr)) break;
+      }
+      launch_cg_iteration(st, n, h->d_qrp.p, h->d_qci.p, h->d_qpost.p, h->d_qdiag.p, sc, cur, x, r, z, p, q,
+                          h->d_cgpart.p);
+      cur ^= 1;
+      ++it;
+    }
+    *its = it;
+    *rel = rr;
+    return;
+  }
   precondition(r, z);
   launch_copy_f64(st, n, z, p);
   launch_dot(st, n, r, z, h->d_red.p, sc + 0);
@@ -1457,6 +1488,7 @@ gmrf_status pcg_prepare(gmrf_t h, int precond) {
   gmrf_status rc = alloc_solve(h, 1);
   if (rc != GMRF_OK) return rc;
   HIPCHK(h, h->d_cg.alloc((size_t)(4 * h->n + 8)));
+  HIPCHK(h, h->d_cgpart.alloc((size_t)kCgPartials));
   return GMRF_OK;
 }
 

@@ -77,6 +77,16 @@ void launch_cg_p(hipStream_t st, int64_t n, double* sc, const double* z, double*
 void launch_copy_f64(hipStream_t st, int64_t n, const double* a, double* b);
 // z = r / diag(Q) (qdiag: index of each row's diagonal entry)
 void launch_jacobi(hipStream_t st, int64_t n, const int64_t* qdiag, const double* qv, const double* r, double* z);
+constexpr int kCgPartials = 3 * 2048;  // partial sums of launch_cg_iteration
+// one Jacobi-preconditioned CG iteration: q = Q p with the partials of p^T q (summed into
+// sc[2]); x, r, z updates with the partials of r^T z (summed into sc[1 - cur]) and r^T r;
+// p update.  sc[cur] holds r^T z on entry.  sc needs 6 doubles; part: kCgPartials doubles.
+void launch_cg_iteration(hipStream_t st, int64_t n, const int64_t* rp, const int32_t* ci, const double* val,
+                         const int64_t* qdiag, double* sc, int cur, double* x, double* r, double* z, double* p,
+                         double* q, double* part);
+// out[0] = ||r|| from the r^T r partials of the last launch_cg_iteration (out[2] is used
+// for the squared norm)
+void launch_partial_norm(hipStream_t st, const double* part, double* out);
 // Rao-Blackwellised marginal variances from k draws of N(0, Q^-1)
 void launch_rbmc(hipStream_t st, int64_t n, const int64_t* rp, const int32_t* ci, const double* qv,
                  const int64_t* qdiag, int64_t k, const double* xs, double* var);

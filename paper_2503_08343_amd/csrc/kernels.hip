@@ -1984,6 +1984,97 @@ __global__ __launch_bounds__(kThreads) void k_dot_final(const double* __restrict
   if (threadIdx.x == 0) out[0] = sq ? sqrt(red[0]) : red[0];
 }
 
+// ---- Jacobi-preconditioned CG, five launches per iteration ----
+// The streaming kernels run kCgBlocks work-groups (enough waves in flight for the gathers of
+// the CSR product) with a fixed assignment of rows; each writes one partial sum per
+// work-group, which a one-work-group kernel adds in a fixed order, so the iteration is
+// deterministic.  sc holds r^T z of the current iteration in slot `cur` and receives the next
+// one in slot 1 - cur; sc[2] receives p^T q, sc[5] the squared residual norm.
+constexpr int kCgBlocks = 2048;
+static_assert(kCgPartials == 3 * kCgBlocks, "CG partial buffer layout");
+
+__device__ __forceinline__ double block_sum(double v, double* red) {
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = kThreads / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  const double out = red[0];
+  __syncthreads();
+  return out;
+}
+
+// q = Q p (16 lanes per CSR row) and the partials of p^T q
+__global__ __launch_bounds__(kThreads) void k_cg_spmv_pq(int64_t n, const int64_t* __restrict__ rp,
+                                                         const int32_t* __restrict__ ci,
+                                                         const double* __restrict__ val,
+                                                         const double* __restrict__ p, double* __restrict__ q,
+                                                         double* __restrict__ part_pq) {
+  __shared__ double red[kThreads];
+  const int j = threadIdx.x & (kRowG - 1);
+  const int64_t gs = (int64_t)kCgBlocks * kThreads / kRowG;
+  double acc = 0.0;
+  for (int64_t i = ((int64_t)blockIdx.x * kThreads + threadIdx.x) / kRowG; i < n; i += gs) {
+    const double s = csr_row_dot(rp, ci, val, p, i, j);
+    if (j == 0) {
+      q[i] = s;
+      acc += p[i] * s;
+    }
+  }
+  const double t = block_sum(acc, red);
+  if (threadIdx.x == 0) part_pq[blockIdx.x] = t;
+}
+
+// out = sum of the kCgBlocks partials, in a fixed order (one work-group)
+__global__ __launch_bounds__(kThreads) void k_cg_sum(const double* __restrict__ part, double* __restrict__ out) {
+  __shared__ double red[kThreads];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < kCgBlocks; i += kThreads) acc += part[i];
+  const double t = block_sum(acc, red);
+  if (threadIdx.x == 0) out[0] = t;
+}
+
+// alpha = r^T z / p^T q; x += alpha p; r -= alpha q; z = r / diag(Q); partials of r^T z, r^T r
+__global__ __launch_bounds__(kThreads) void k_cg_update(int64_t n, const double* __restrict__ sc, int cur,
+                                                        const double* __restrict__ p, const double* __restrict__ q,
+                                                        double* __restrict__ x, double* __restrict__ r,
+                                                        const int64_t* __restrict__ qdiag,
+                                                        const double* __restrict__ qv, double* __restrict__ z,
+                                                        double* __restrict__ part_rz, double* __restrict__ part_rr) {
+  __shared__ double red[kThreads];
+  const double pq = sc[2];
+  const double alpha = pq != 0.0 ? sc[cur] / pq : 0.0;
+  double arz = 0.0, arr = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)kCgBlocks * kThreads) {
+    x[i] += alpha * p[i];
+    const double ri = r[i] - alpha * q[i];
+    r[i] = ri;
+    const double zi = ri / qv[qdiag[i]];
+    z[i] = zi;
+    arz += ri * zi;
+    arr += ri * ri;
+  }
+  const double trz = block_sum(arz, red);
+  const double trr = block_sum(arr, red);
+  if (threadIdx.x == 0) {
+    part_rz[blockIdx.x] = trz;
+    part_rr[blockIdx.x] = trr;
+  }
+}
+
+__global__ void k_cg_sqrt(double* __restrict__ v) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) v[0] = sqrt(v[2]);
+}
+
+// beta = new r^T z / r^T z; p = z + beta p
+__global__ __launch_bounds__(kThreads) void k_cg_pupdate(int64_t n, const double* __restrict__ sc, int cur,
+                                                         const double* __restrict__ z, double* __restrict__ p) {
+  const double beta = sc[cur] != 0.0 ? sc[1 - cur] / sc[cur] : 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)kCgBlocks * kThreads)
+    p[i] = z[i] + beta * p[i];
+}
+
 // ------------------------------------------------------------------ selected inversion
 // Sigma front of s: square n_s x n_s (both triangles) at Scur + Woff[s].
 template <typename T>
@@ -3061,6 +3152,25 @@ template <typename T> void launch_sel_gemm_reduce(hipStream_t st, const DevSym& 
   else
     hipLaunchKernelGGL((k_sel_gemm_reduce<T, 128, 128>), dim3((unsigned)L.total), dim3(kThreads), 0, st, S, L, step,
                        B);
+}
+void launch_cg_iteration(hipStream_t st, int64_t n, const int64_t* rp, const int32_t* ci, const double* val,
+                         const int64_t* qdiag, double* sc, int cur, double* x, double* r, double* z, double* p,
+                         double* q, double* part) {
+  double* part_pq = part;
+  double* part_rz = part + kCgBlocks;
+  double* part_rr = part + 2 * kCgBlocks;
+  hipLaunchKernelGGL(k_cg_spmv_pq, dim3(kCgBlocks), dim3(kThreads), 0, st, n, rp, ci, val, (const double*)p, q,
+                     part_pq);
+  hipLaunchKernelGGL(k_cg_sum, dim3(1), dim3(kThreads), 0, st, (const double*)part_pq, sc + 2);
+  hipLaunchKernelGGL(k_cg_update, dim3(kCgBlocks), dim3(kThreads), 0, st, n, (const double*)sc, cur,
+                     (const double*)p, (const double*)q, x, r, qdiag, val, z, part_rz, part_rr);
+  hipLaunchKernelGGL(k_cg_sum, dim3(1), dim3(kThreads), 0, st, (const double*)part_rz, sc + (1 - cur));
+  hipLaunchKernelGGL(k_cg_pupdate, dim3(kCgBlocks), dim3(kThreads), 0, st, n, (const double*)sc, cur,
+                     (const double*)z, p);
+}
+void launch_partial_norm(hipStream_t st, const double* part, double* out) {
+  hipLaunchKernelGGL(k_cg_sum, dim3(1), dim3(kThreads), 0, st, part + 2 * kCgBlocks, out + 2);
+  hipLaunchKernelGGL(k_cg_sqrt, dim3(1), dim3(1), 0, st, out);
 }
 void launch_sel_gemm4(hipStream_t st, const DevSym& S, const LaunchList& L, int step, SelBufs<float> B) {
   if (L.total <= 0) return;
