@@ -167,12 +167,15 @@ def secondary(binding, which, steps, warmup, autotune=False):
             F = st["flops_factor"] + st["flops_selinv"] + (1 + k) * st["flops_solve"]
 
             def step():
+                # as in the headline step: the selected inversion on the library's second
+                # stream, overlapped with the log-determinants, the refined means and the samples
                 ctx.factor(prec)
+                ctx.selinv_submit()
                 ctx.logdet()
                 ctx.solve(max_refine=30 if prec == binding.GMRF_FP32_REFINE else 0, tol=1e-12,
                           raise_not_converged=False)
                 ctx.sample(z)
-                ctx.selinv()
+                ctx.selinv_wait()
             for _ in range(warmup):
                 step()
             torch.cuda.synchronize()

@@ -1073,9 +1073,9 @@ void run_solve(gmrf_t h, int nrhs, bool forward) {
   const T* Lp = (const T*)h->d_L.p;
   const T* D = (const T*)h->d_D.p;
   // several right-hand sides on a forest of small fronts (average supernode below 16,384
-  // entries of L): one backward pass over the forest that takes the columns one after the
-  // other per task; large fronts keep the per-depth kernels, which read each L block once
-  // for all columns
+  // entries of L): one backward pass over the forest whose tasks take the columns in pairs,
+  // each load of L serving both; large fronts keep the per-depth kernels, which read each
+  // L block once for all columns
   const bool forest_multi = nrhs > 1 && !forward && Y.nnzL < (int64_t)16384 * Y.ns;
   if (nrhs == 1 || forest_multi) {
     // one launch per pass over the whole elimination forest

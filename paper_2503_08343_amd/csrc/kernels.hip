@@ -2760,14 +2760,47 @@ __global__ __launch_bounds__(kThreads) void k_fwd_forest(DevSym S, FusedTasks F,
   }
 }
 
-template <typename T>
+// Sums over the 64 lanes of a wave of NV values per lane (NV = 16 or 64): a butterfly in
+// which each of the first log2(NV) levels hands half of the lane's values to its partner
+// and keeps the partner's half of the other values, and the remaining levels add plainly.
+// Lane l ends with the total of value (l & (64 - 64 / NV)) * NV / 64, after NV - 1 +
+// 6 - log2(NV) exchanges instead of 6 NV.  Every total adds the lanes in the same tree
+// (partners at distance 32, 16, ..., 1), whatever NV.
+template <int NV, int CNT>
+struct LaneFold {
+  static __device__ __forceinline__ void run(double* v, int lane) {
+    constexpr int H = CNT / 2;
+    constexpr int M = 32 * CNT / NV;
+    const bool up = (lane & M) != 0;
+#pragma unroll
+    for (int i = 0; i < H; ++i) {
+      const double send = up ? v[i] : v[i + H];
+      const double keep = up ? v[i + H] : v[i];
+      v[i] = keep + __shfl_xor(send, M, 64);
+    }
+    LaneFold<NV, H>::run(v, lane);
+  }
+};
+template <int NV>
+struct LaneFold<NV, 1> {
+  static __device__ __forceinline__ void run(double* v, int) {
+#pragma unroll
+    for (int m = 32 / NV; m >= 1; m >>= 1) v[0] += __shfl_xor(v[0], m, 64);
+  }
+};
+
+// Backward pass; NR right-hand sides share each load of L (NR = 1, or 2 for a multi-RHS
+// pass, whose last group may be partial).  Each wave holds 16 column sums per right-hand
+// side and folds them across its lanes in one butterfly.
+template <typename T, int NR>
 __global__ __launch_bounds__(kThreads) void k_bwd_forest(DevSym S, FusedTasks F, ForestBufs G,
                                                          const T* __restrict__ Lp, const T* __restrict__ D,
                                                          double* xp, int nrhs, int64_t ldx) {
+  constexpr int NV = 16 * NR;
   __shared__ int s_task, s_slot;
   __shared__ T Ds[kNB * (kNB + 1)];
-  __shared__ double rs[64];
-  __shared__ double red[4][64];
+  __shared__ double rs[NR][64];
+  __shared__ double red[NR][4][64];
   if (threadIdx.x == 0) s_task = atomicAdd(F.ticket, 1);
   __syncthreads();
   const int grp = s_task;
@@ -2784,22 +2817,20 @@ __global__ __launch_bounds__(kThreads) void k_bwd_forest(DevSym S, FusedTasks F,
   const int32_t* rows = S.rows + S.rowptr[s];
   int32_t* prog = F.prog + s;
   {
+    // the pb x pb part of the inverse diagonal block; a wave's columns are uniform, so the
+    // columns past pb are not read at all
     const T* Db = D + S.Doff[s] + (int64_t)c * kNB * kNB;
 #pragma unroll
     for (int k = 0; k < kNB * kNB / kThreads; ++k) {
       const int e = threadIdx.x + k * kThreads;
-      Ds[(e & 63) + (e >> 6) * (kNB + 1)] = Db[e];
+      const int i = e & 63, j = e >> 6;
+      Ds[i + j * (kNB + 1)] = (i < pb && j < pb) ? Db[e] : (T)0;
     }
   }
   const T* Lc = Lp + S.Loff[s];
   int cols[16];
-  T cm[16];
 #pragma unroll
-  for (int u = 0; u < 16; ++u) {
-    const int jj = 16 * w + u;
-    cols[u] = 64 * c + min(jj, pb - 1);
-    cm[u] = (T)(jj < pb);
-  }
+  for (int u = 0; u < 16; ++u) cols[u] = 64 * c + min(16 * w + u, pb - 1);
   // rows below p: ancestors' unknowns, final once the parent front has published them all
   const int par = G.parent[s];
   if (par >= 0 && n > p) {
@@ -2807,22 +2838,29 @@ __global__ __launch_bounds__(kThreads) void k_bwd_forest(DevSym S, FusedTasks F,
     (void)wait_count(F.prog + par, Pp, F.err, &s_slot);
   }
   int ready = 0;
-  // the right-hand sides one after the other; the block's progress is published once all
-  // of them are final, so the waits of the first cover the rest
-  for (int rr = 0; rr < nrhs; ++rr) {
-  double* xr = xp + (int64_t)rr * ldx;
-  double acc[16];
+  // groups of NR right-hand sides one after the other; the block's progress is published
+  // once all of them are final, so the waits of the first group cover the rest
+  for (int r0 = 0; r0 < nrhs; r0 += NR) {
+  const double* xg[NR];
 #pragma unroll
-  for (int u = 0; u < 16; ++u) acc[u] = 0.0;
-  for (int r0 = p; r0 < n; r0 += 64) {
-    const int row = r0 + lane;
+  for (int g = 0; g < NR; ++g) xg[g] = xp + (int64_t)min(r0 + g, nrhs - 1) * ldx;
+  double acc[NV];
+#pragma unroll
+  for (int u = 0; u < NV; ++u) acc[u] = 0.0;
+  for (int rw = p; rw < n; rw += 64) {
+    const int row = rw + lane;
     const int rc = min(row, n - 1);
     T lv[16];
 #pragma unroll
     for (int u = 0; u < 16; ++u) lv[u] = Lc[rc + (int64_t)cols[u] * n];
-    const double xv = load_dev(xr + rows[rc]) * (double)(row < n);
+    const int xi = rows[rc];
+    const double m = (double)(row < n);
 #pragma unroll
-    for (int u = 0; u < 16; ++u) acc[u] += (double)(lv[u] * cm[u]) * xv;
+    for (int g = 0; g < NR; ++g) {
+      const double xv = load_dev(xg[g] + xi) * m;
+#pragma unroll
+      for (int u = 0; u < 16; ++u) acc[16 * g + u] += (double)lv[u] * xv;
+    }
   }
   for (int t = P - 1; t > c; --t) {
     const int row = 64 * t + lane;
@@ -2831,36 +2869,42 @@ __global__ __launch_bounds__(kThreads) void k_bwd_forest(DevSym S, FusedTasks F,
 #pragma unroll
     for (int u = 0; u < 16; ++u) lv[u] = Lc[rc + (int64_t)cols[u] * n];
     if (ready < P - t) ready = wait_progress(prog, P - t, F.err, &s_slot);
-    const double xv = load_dev(xr + f0 + rc) * (double)(row < p);
+    const double m = (double)(row < p);
 #pragma unroll
-    for (int u = 0; u < 16; ++u) acc[u] += (double)(lv[u] * cm[u]) * xv;
+    for (int g = 0; g < NR; ++g) {
+      const double xv = load_dev(xg[g] + f0 + rc) * m;
+#pragma unroll
+      for (int u = 0; u < 16; ++u) acc[16 * g + u] += (double)lv[u] * xv;
+    }
   }
-#pragma unroll
-  for (int u = 0; u < 16; ++u) {
-    double a = acc[u];
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) a += __shfl_xor(a, m, 64);
-    acc[u] = a;
-  }
-  if (lane < 16) {
-    double a = acc[0];
-#pragma unroll
-    for (int u = 1; u < 16; ++u) a = lane == u ? acc[u] : a;
-    const int jj = 16 * w + lane;
-    rs[jj] = jj < pb ? xr[f0 + 64 * c + jj] - a : 0.0;
+  LaneFold<NV, NV>::run(acc, lane);
+  {
+    const int idx = (lane & (64 - 64 / NV)) * NV / 64;   // right-hand side idx / 16, column idx % 16
+    const int g = idx >> 4, jj = 16 * w + (idx & 15);
+    if ((lane & (64 / NV - 1)) == 0) rs[g][jj] = jj < pb ? xg[g][f0 + 64 * c + jj] - acc[0] : 0.0;
   }
   __syncthreads();
-  double part = 0.0;
+  double part[NR];
+#pragma unroll
+  for (int g = 0; g < NR; ++g) part[g] = 0.0;
 #pragma unroll
   for (int u = 0; u < 16; ++u) {
     const int i = 16 * w + u;
-    part += (double)Ds[i + lane * (kNB + 1)] * rs[i];
+    const double d = (double)Ds[i + lane * (kNB + 1)];
+#pragma unroll
+    for (int g = 0; g < NR; ++g) part[g] += d * rs[g][i];
   }
-  red[w][lane] = part;
+#pragma unroll
+  for (int g = 0; g < NR; ++g) red[g][w][lane] = part[g];
   __syncthreads();
-  if (w == 0 && lane < pb)
-    store_dev(xr + f0 + 64 * c + lane, (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]));
-  __syncthreads();   // rs and red are reused by the next right-hand side
+  if (w == 0 && lane < pb) {
+#pragma unroll
+    for (int g = 0; g < NR; ++g)
+      if (r0 + g < nrhs)
+        store_dev(xp + (int64_t)(r0 + g) * ldx + f0 + 64 * c + lane,
+                  (red[g][0][lane] + red[g][1][lane]) + (red[g][2][lane] + red[g][3][lane]));
+  }
+  __syncthreads();   // rs and red are reused by the next group of right-hand sides
   }
   publish_progress(prog, P - c);
   __syncthreads();   // the shared buffers are reused by the group's next task
@@ -3045,8 +3089,12 @@ template <typename T> void launch_fwd_forest(hipStream_t st, const DevSym& S, Fu
 template <typename T> void launch_bwd_forest(hipStream_t st, const DevSym& S, FusedTasks F, ForestBufs G,
                                              const T* Lp, const T* D, double* xp, int nrhs, int64_t ldx) {
   if (F.count <= 0) return;
-  hipLaunchKernelGGL(k_bwd_forest<T>, dim3((unsigned)F.count), dim3(kThreads), 0, st, S, F, G, Lp, D, xp, nrhs,
-                     ldx);
+  if (nrhs > 1)
+    hipLaunchKernelGGL((k_bwd_forest<T, 2>), dim3((unsigned)F.count), dim3(kThreads), 0, st, S, F, G, Lp, D, xp,
+                       nrhs, ldx);
+  else
+    hipLaunchKernelGGL((k_bwd_forest<T, 1>), dim3((unsigned)F.count), dim3(kThreads), 0, st, S, F, G, Lp, D, xp,
+                       nrhs, ldx);
 }
 void launch_permute_in(hipStream_t st, int64_t n, int nrhs, const int32_t* perm, const double* scale,
                        const double* src, int64_t lds, double* xp, const double* gate) {

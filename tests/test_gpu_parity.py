@@ -160,6 +160,22 @@ def test_samples_match_oracle_with_library_pivot_order(gpu_lib, precision):
 SAMPLE_FP32_MEASURED = 1.197e-07   # max relative quadratic-form error of the FP32 samples
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_multi_rhs_sample_equals_single_rhs_samples(gpu_lib, precision):
+    """Several right-hand sides in one backward pass (pairs sharing each load of L, a
+    partial last pair) give bitwise the samples of one right-hand side per call: every
+    column sum adds its terms in the same order either way."""
+    import torch
+    p = gi.matern_batch(n_prob=10, side_lo=8, side_hi=30, seed=49)
+    ctx = gpu_lib.posterior_context(p, precision=precision)
+    ctx.solve(max_refine=20 if precision else 0, tol=1e-12, raise_not_converged=False)
+    z = torch.from_numpy(gi.rng_for(50).standard_normal((5, p.n)).astype(np.float32)).cuda()
+    x = ctx.sample(z).clone()
+    for r in range(5):
+        assert torch.equal(ctx.sample(z[r:r + 1].contiguous())[0], x[r]), r
+    ctx.close()
+
+
 def test_fp32_refine_mean_and_bounds(gpu_lib):
     p = gi.advdiff_spacetime(ns=20, nt=10, seed=48)
     ctx, ld, mu, var, it, res = _run(gpu_lib, p, gpu_lib.GMRF_FP32_REFINE, refine=30, tol=1e-14)
