@@ -2478,6 +2478,10 @@ inline unsigned grid_for(int64_t n, int64_t cap = 65536) {
 constexpr int kSpinLimit = 1 << 20;
 // forward-pass groups whose fronts have at most this many rows run one task per wave
 constexpr int kWaveTaskRows = 256;
+// work-groups of a whole-forest pass (four per CU, more than fit at once); each takes groups
+// of tasks by ticket until none is left, so that a pass over a forest of many fronts is not
+// one work-group dispatch per group
+constexpr int kForestGrid = 1024;
 
 __device__ __forceinline__ double load_dev(const double* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -2653,14 +2657,17 @@ __global__ __launch_bounds__(kThreads) void k_fwd_forest(DevSym S, FusedTasks F,
   __shared__ double red[4][64];
   __shared__ double xs[64];
   __shared__ double vin[64];
+  for (;;) {
   if (threadIdx.x == 0) s_task = atomicAdd(F.ticket, 1);
   __syncthreads();
   const int grp = s_task;
+  __syncthreads();   // every wave has read the ticket before thread 0 takes the next one
+  if (grp >= F.count) break;
   const int t_end = F.group[grp + 1];
   if (fn(S, F.task[F.group[grp]].x) <= kWaveTaskRows) {
     for (int ti = F.group[grp] + (int)(threadIdx.x >> 6); ti < t_end; ti += kThreads / 64)
       fwd_task_wave<T>(S, F, G, Lp, D, xp, F.task[ti].x, F.task[ti].y);
-    return;
+    continue;
   }
   for (int ti = F.group[grp]; ti < t_end; ++ti) {
   const int2 tk = F.task[ti];
@@ -2758,6 +2765,7 @@ __global__ __launch_bounds__(kThreads) void k_fwd_forest(DevSym S, FusedTasks F,
   }
   __syncthreads();   // the shared buffers are reused by the group's next task
   }
+  }
 }
 
 // Sums over the 64 lanes of a wave of NV values per lane (NV = 16 or 64): a butterfly in
@@ -2801,9 +2809,12 @@ __global__ __launch_bounds__(kThreads) void k_bwd_forest(DevSym S, FusedTasks F,
   __shared__ T Ds[kNB * (kNB + 1)];
   __shared__ double rs[NR][64];
   __shared__ double red[NR][4][64];
+  for (;;) {
   if (threadIdx.x == 0) s_task = atomicAdd(F.ticket, 1);
   __syncthreads();
   const int grp = s_task;
+  __syncthreads();   // every wave has read the ticket before thread 0 takes the next one
+  if (grp >= F.count) break;
   const int t_end = F.group[grp + 1];
   for (int ti = F.group[grp]; ti < t_end; ++ti) {
   const int2 tk = F.task[ti];
@@ -2908,6 +2919,7 @@ __global__ __launch_bounds__(kThreads) void k_bwd_forest(DevSym S, FusedTasks F,
   }
   publish_progress(prog, P - c);
   __syncthreads();   // the shared buffers are reused by the group's next task
+  }
   }
 }
 
@@ -3084,17 +3096,18 @@ template <typename T> void launch_bwd_block(hipStream_t st, const DevSym& S, con
 template <typename T> void launch_fwd_forest(hipStream_t st, const DevSym& S, FusedTasks F, ForestBufs G,
                                              const T* Lp, const T* D, double* xp) {
   if (F.count <= 0) return;
-  hipLaunchKernelGGL(k_fwd_forest<T>, dim3((unsigned)F.count), dim3(kThreads), 0, st, S, F, G, Lp, D, xp);
+  hipLaunchKernelGGL(k_fwd_forest<T>, dim3((unsigned)min(F.count, kForestGrid)), dim3(kThreads), 0, st, S, F, G,
+                     Lp, D, xp);
 }
 template <typename T> void launch_bwd_forest(hipStream_t st, const DevSym& S, FusedTasks F, ForestBufs G,
                                              const T* Lp, const T* D, double* xp, int nrhs, int64_t ldx) {
   if (F.count <= 0) return;
   if (nrhs > 1)
-    hipLaunchKernelGGL((k_bwd_forest<T, 2>), dim3((unsigned)F.count), dim3(kThreads), 0, st, S, F, G, Lp, D, xp,
-                       nrhs, ldx);
+    hipLaunchKernelGGL((k_bwd_forest<T, 2>), dim3((unsigned)min(F.count, kForestGrid)), dim3(kThreads), 0, st, S,
+                       F, G, Lp, D, xp, nrhs, ldx);
   else
-    hipLaunchKernelGGL((k_bwd_forest<T, 1>), dim3((unsigned)F.count), dim3(kThreads), 0, st, S, F, G, Lp, D, xp,
-                       nrhs, ldx);
+    hipLaunchKernelGGL((k_bwd_forest<T, 1>), dim3((unsigned)min(F.count, kForestGrid)), dim3(kThreads), 0, st, S,
+                       F, G, Lp, D, xp, nrhs, ldx);
 }
 void launch_permute_in(hipStream_t st, int64_t n, int nrhs, const int32_t* perm, const double* scale,
                        const double* src, int64_t lds, double* xp, const double* gate) {
