@@ -1062,9 +1062,11 @@ gmrf_status check_status(gmrf_t h) {
   return GMRF_OK;
 }
 
-// forward + backward (or backward only) solve of the FP64 pivot-order block xp (n x nrhs)
+// forward + backward (or backward only) solve of the FP64 pivot-order block xp (n x nrhs).
+// skip (device, nullable, one right-hand side): when skip[0] == 0 the right-hand side is
+// zero and the forest passes return at once.
 template <typename T>
-void run_solve(gmrf_t h, int nrhs, bool forward) {
+void run_solve(gmrf_t h, int nrhs, bool forward, const double* skip = nullptr) {
   const Symbolic& Y = h->sym;
   h->tsize = (int)sizeof(T);
   hipStream_t st = h->stream;
@@ -1091,13 +1093,13 @@ void run_solve(gmrf_t h, int nrhs, bool forward) {
       launch_fill_i32(st, h->d_sync.p, h->sync_reset, 0);
       prof_launch(h, KC_FWD, 2.0 * fb, fb, [&] {
         launch_fwd_forest<T>(st, S, FusedTasks{h->d_ftasks.p, tick, prog, err, h->n_fgrp, h->d_fgrp.p},
-                             G, Lp, D, h->d_xp.p);
+                             G, Lp, D, h->d_xp.p, skip);
       });
     }
     launch_fill_i32(st, h->d_sync.p, h->sync_reset, 0);
     prof_launch(h, KC_BWD, 2.0 * fb * nrhs, fb, [&] {
       launch_bwd_forest<T>(st, S, FusedTasks{h->d_btasks.p, tick + 1, prog, err, h->n_bgrp, h->d_bgrp.p},
-                           G, Lp, D, h->d_xp.p, nrhs, h->n);
+                           G, Lp, D, h->d_xp.p, nrhs, h->n, skip);
     });
     return;
   }
@@ -1252,9 +1254,9 @@ void gn_linearize(gmrf_t h, const GNArgs& a) {
 
 // solve Q_post x = h on device only (no host synchronisation, capturable): one solve
 // plus at most `refine` corrections with FP64 residuals.  A device gate stops the
-// corrections once ||h - Q_post x|| <= tol ||h|| (the remaining ones solve a zero
-// right-hand side and add nothing); rec[0] receives the final relative residual and
-// rec[1] the number of corrections applied.
+// corrections once ||h - Q_post x|| <= tol ||h|| (the remaining ones have a zero
+// right-hand side, their forest passes return at once and they add nothing); rec[0]
+// receives the final relative residual and rec[1] the number of corrections applied.
 template <typename T>
 void device_solve(gmrf_t h, double* x, int refine, double tol, double* rec) {
   hipStream_t st = h->stream;
@@ -1270,7 +1272,7 @@ void device_solve(gmrf_t h, double* x, int refine, double tol, double* rec) {
     launch_norm2(st, n, h->d_r.p, h->d_red.p, h->d_norm.p + 1);
     launch_refine_gate(st, h->d_norm.p, tol, gate, nullptr, 0);
     launch_permute_in(st, n, 1, h->d_perm.p, h->d_scale.p, h->d_r.p, n, h->d_xp.p, gate);
-    run_solve<T>(h, 1, true);
+    run_solve<T>(h, 1, true, gate);
     launch_permute_out(st, n, 1, h->d_perm.p, h->d_scale.p, h->d_xp.p, nullptr, 0, x, n, 1);
   }
   launch_resid(st, n, h->d_qrp.p, h->d_qci.p, h->d_qpost.p, h->d_h.p, x, h->d_r.p);

@@ -168,12 +168,15 @@ struct ForestBufs {
   double* U;               // update parts of all fronts
 };
 // one launch over the whole forest (tasks deepest first for the forward, from the roots
-// for the backward); xp holds the right-hand side on entry and the solution on exit
+// for the backward); xp holds the right-hand side on entry and the solution on exit.
+// skip (device, nullable): when skip[0] == 0 the launch does nothing, which leaves a zero
+// right-hand side as its own solution (the gated refinement passes).
 template <typename T> void launch_fwd_forest(hipStream_t st, const DevSym& S, FusedTasks F, ForestBufs G,
-                                             const T* Lp, const T* D, double* xp);
+                                             const T* Lp, const T* D, double* xp, const double* skip = nullptr);
 // nrhs right-hand sides (column r at xp + r * ldx) in one backward pass
 template <typename T> void launch_bwd_forest(hipStream_t st, const DevSym& S, FusedTasks F, ForestBufs G,
-                                             const T* Lp, const T* D, double* xp, int nrhs = 1, int64_t ldx = 0);
+                                             const T* Lp, const T* D, double* xp, int nrhs = 1, int64_t ldx = 0,
+                                             const double* skip = nullptr);
 // xp = gate[0] * S P src (gate nullable = 1)
 void launch_permute_in(hipStream_t st, int64_t n, int nrhs, const int32_t* perm, const double* scale,
                        const double* src, int64_t lds, double* xp, const double* gate = nullptr);

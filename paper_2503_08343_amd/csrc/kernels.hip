@@ -2652,11 +2652,12 @@ __device__ __forceinline__ void fwd_task_wave(const DevSym& S, const FusedTasks&
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_fwd_forest(DevSym S, FusedTasks F, ForestBufs G,
                                                          const T* __restrict__ Lp, const T* __restrict__ D,
-                                                         double* xp) {
+                                                         double* xp, const double* __restrict__ skip) {
   __shared__ int s_task, s_slot;
   __shared__ double red[4][64];
   __shared__ double xs[64];
   __shared__ double vin[64];
+  if (skip && skip[0] == 0.0) return;
   for (;;) {
   if (threadIdx.x == 0) s_task = atomicAdd(F.ticket, 1);
   __syncthreads();
@@ -2803,12 +2804,14 @@ struct LaneFold<NV, 1> {
 template <typename T, int NR>
 __global__ __launch_bounds__(kThreads) void k_bwd_forest(DevSym S, FusedTasks F, ForestBufs G,
                                                          const T* __restrict__ Lp, const T* __restrict__ D,
-                                                         double* xp, int nrhs, int64_t ldx) {
+                                                         double* xp, int nrhs, int64_t ldx,
+                                                         const double* __restrict__ skip) {
   constexpr int NV = 16 * NR;
   __shared__ int s_task, s_slot;
   __shared__ T Ds[kNB * (kNB + 1)];
   __shared__ double rs[NR][64];
   __shared__ double red[NR][4][64];
+  if (skip && skip[0] == 0.0) return;
   for (;;) {
   if (threadIdx.x == 0) s_task = atomicAdd(F.ticket, 1);
   __syncthreads();
@@ -3094,20 +3097,21 @@ template <typename T> void launch_bwd_block(hipStream_t st, const DevSym& S, con
 }
 
 template <typename T> void launch_fwd_forest(hipStream_t st, const DevSym& S, FusedTasks F, ForestBufs G,
-                                             const T* Lp, const T* D, double* xp) {
+                                             const T* Lp, const T* D, double* xp, const double* skip) {
   if (F.count <= 0) return;
   hipLaunchKernelGGL(k_fwd_forest<T>, dim3((unsigned)min(F.count, kForestGrid)), dim3(kThreads), 0, st, S, F, G,
-                     Lp, D, xp);
+                     Lp, D, xp, skip);
 }
 template <typename T> void launch_bwd_forest(hipStream_t st, const DevSym& S, FusedTasks F, ForestBufs G,
-                                             const T* Lp, const T* D, double* xp, int nrhs, int64_t ldx) {
+                                             const T* Lp, const T* D, double* xp, int nrhs, int64_t ldx,
+                                             const double* skip) {
   if (F.count <= 0) return;
   if (nrhs > 1)
     hipLaunchKernelGGL((k_bwd_forest<T, 2>), dim3((unsigned)min(F.count, kForestGrid)), dim3(kThreads), 0, st, S,
-                       F, G, Lp, D, xp, nrhs, ldx);
+                       F, G, Lp, D, xp, nrhs, ldx, skip);
   else
     hipLaunchKernelGGL((k_bwd_forest<T, 1>), dim3((unsigned)min(F.count, kForestGrid)), dim3(kThreads), 0, st, S,
-                       F, G, Lp, D, xp, nrhs, ldx);
+                       F, G, Lp, D, xp, nrhs, ldx, skip);
 }
 void launch_permute_in(hipStream_t st, int64_t n, int nrhs, const int32_t* perm, const double* scale,
                        const double* src, int64_t lds, double* xp, const double* gate) {
@@ -3289,8 +3293,8 @@ template <typename T> void launch_sel_pattern(hipStream_t st, int64_t cnt, const
   template void launch_fwd_outer<T>(hipStream_t, const DevSym&, const LaunchList&, int, const T*, SolveBufs); \
   template void launch_bwd_part<T>(hipStream_t, const DevSym&, const LaunchList&, int, const T*, SolveBufs, double*); \
   template void launch_bwd_block<T>(hipStream_t, const DevSym&, const LaunchList&, const LaunchList&, int, const T*, const int64_t*, SolveBufs, const double*); \
-  template void launch_fwd_forest<T>(hipStream_t, const DevSym&, FusedTasks, ForestBufs, const T*, const T*, double*); \
-  template void launch_bwd_forest<T>(hipStream_t, const DevSym&, FusedTasks, ForestBufs, const T*, const T*, double*, int, int64_t); \
+  template void launch_fwd_forest<T>(hipStream_t, const DevSym&, FusedTasks, ForestBufs, const T*, const T*, double*, const double*); \
+  template void launch_bwd_forest<T>(hipStream_t, const DevSym&, FusedTasks, ForestBufs, const T*, const T*, double*, int, int64_t, const double*); \
   template void launch_sel_gather<T>(hipStream_t, const DevSym&, const LaunchList&, const int32_t*, SelBufs<T>); \
   template void launch_inv256<T>(hipStream_t, const DevSym&, const LaunchList&, const T*, int, const T*, const int64_t*, T*, T*); \
   template void launch_sel_Y2<T>(hipStream_t, const DevSym&, const LaunchList&, int, SelBufs<T>, const int64_t*, const T*); \
