@@ -433,46 +433,71 @@ union __attribute__((aligned(16))) G4Smem {
   float ep[64][kG4 + 1];   // epilogue staging of one 64-column group
 };
 
+typedef float f2v_t __attribute__((ext_vector_type(2)));
+typedef __bf16 bf2_t __attribute__((ext_vector_type(2)));
+// round-to-nearest bf16 of (a, b) as one packed pair, and the two values back as floats
+__device__ __forceinline__ uint32_t pk_bf16(float a, float b) {
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector((f2v_t){a, b}, bf2_t));
+}
+__device__ __forceinline__ float bf16_lo(uint32_t p) { return __uint_as_float(p << 16); }
+__device__ __forceinline__ float bf16_hi(uint32_t p) { return __uint_as_float(p & 0xffff0000u); }
+
+// split of eight values two at a time: each level converts a pair once and subtracts the
+// pair's two rounded values from what the earlier levels left
 __device__ __forceinline__ void split3_bf16(const float (&x)[8], uint4& h, uint4& m, uint4& l) {
-  bf8_t vh, vm, vl;
+  uint32_t vh[4], vm[4], vl[4];
 #pragma unroll
-  for (int q = 0; q < 8; ++q) {
-    const __bf16 a = (__bf16)x[q];
-    const float r1 = x[q] - (float)a;
-    const __bf16 b = (__bf16)r1;
+  for (int q = 0; q < 4; ++q) {
+    const uint32_t a = pk_bf16(x[2 * q], x[2 * q + 1]);
+    const float r0 = x[2 * q] - bf16_lo(a), r1 = x[2 * q + 1] - bf16_hi(a);
+    const uint32_t b = pk_bf16(r0, r1);
     vh[q] = a;
     vm[q] = b;
-    vl[q] = (__bf16)(r1 - (float)b);
+    vl[q] = pk_bf16(r0 - bf16_lo(b), r1 - bf16_hi(b));
   }
-  h = __builtin_bit_cast(uint4, vh);
-  m = __builtin_bit_cast(uint4, vm);
-  l = __builtin_bit_cast(uint4, vl);
+  h = make_uint4(vh[0], vh[1], vh[2], vh[3]);
+  m = make_uint4(vm[0], vm[1], vm[2], vm[3]);
+  l = make_uint4(vl[0], vl[1], vl[2], vl[3]);
 }
 
 // row t & 255 (clamped to M - 1, N - 1: the products of such rows land in output rows /
-// columns the epilogues discard), k = k0 + 8 (t >> 8) .. +7 clamped to K - 1
+// columns the epilogues discard), k = k0 + 8 (t >> 8) .. +7; values at k >= K are zero.
+// FULL: the caller knows that every k of the chunk is below K; the loads are then buffer
+// loads from a per-chunk base, with the row as the lane offset and q lda as scalar offsets
+// (no address arithmetic per load).  Otherwise the loads come from clamped addresses.
+template <bool FULL>
 __device__ __forceinline__ void g4_load(const float* __restrict__ A, int64_t lda, const float* __restrict__ B,
                                         int64_t ldb, int M, int N, int K, int k0, float (&ra)[8], float (&rb)[8]) {
   const int t = threadIdx.x;
-  const float* Am = A + min(t & 255, M - 1);
-  const float* Bn = B + min(t & 255, N - 1);
-  const int kb = k0 + 8 * (t >> 8);
+  const int ra_row = min(t & 255, M - 1), rb_row = min(t & 255, N - 1);
+  const int kb = k0 + 8 * __builtin_amdgcn_readfirstlane(t >> 8);
+  if constexpr (FULL) {
+    const __amdgpu_buffer_rsrc_t sa =
+        __builtin_amdgcn_make_buffer_rsrc((void*)(A + (int64_t)kb * lda), (short)0, -1, 0x00020000);
+    const __amdgpu_buffer_rsrc_t sb =
+        __builtin_amdgcn_make_buffer_rsrc((void*)(B + (int64_t)kb * ldb), (short)0, -1, 0x00020000);
+    const int sla = __builtin_amdgcn_readfirstlane((int)(4 * lda)), slb = __builtin_amdgcn_readfirstlane((int)(4 * ldb));
 #pragma unroll
-  for (int q = 0; q < 8; ++q) {
-    const int64_t k = min(kb + q, K - 1);
-    ra[q] = Am[k * lda];
-    rb[q] = Bn[k * ldb];
+    for (int q = 0; q < 8; ++q) {
+      ra[q] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(sa, 4 * ra_row, q * sla, 0));
+      rb[q] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(sb, 4 * rb_row, q * slb, 0));
+    }
+  } else {
+    const float* Am = A + ra_row;
+    const float* Bn = B + rb_row;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int64_t k = min(kb + q, K - 1);
+      const bool ok = kb + q < K;
+      const float va = Am[k * lda], vb = Bn[k * ldb];
+      ra[q] = ok ? va : 0.f;
+      rb[q] = ok ? vb : 0.f;
+    }
   }
 }
-// zero the k >= K values of chunk k0, split, store into LDS buffer (a, b)
-__device__ __forceinline__ void g4_store(uint4* a, uint4* b, float (&ra)[8], float (&rb)[8], int K, int k0) {
-  const int t = threadIdx.x, kb = k0 + 8 * (t >> 8);
-#pragma unroll
-  for (int q = 0; q < 8; ++q) {
-    const bool ok = kb + q < K;
-    ra[q] = ok ? ra[q] : 0.f;
-    rb[q] = ok ? rb[q] : 0.f;
-  }
+// split, store into LDS buffer (a, b)
+__device__ __forceinline__ void g4_store(uint4* a, uint4* b, float (&ra)[8], float (&rb)[8]) {
+  const int t = threadIdx.x;
   const int u = (t & 255) * kRec4 + (t >> 8);
   uint4 h, m, l;
   split3_bf16(ra, h, m, l);
@@ -497,12 +522,14 @@ __device__ __forceinline__ void gemm_tile4(const float* __restrict__ A, int64_t 
   const int rl = lane & 31, kh = lane >> 5;
   float ra[8], rb[8];
   if (K <= 0) return;
-  g4_load(A, lda, B, ldb, M, N, K, 0, ra, rb);
-  g4_store(S.a[0], S.b[0], ra, rb, K, 0);
-  g4_load(A, lda, B, ldb, M, N, K, kG4K, ra, rb);
+  g4_load<false>(A, lda, B, ldb, M, N, K, 0, ra, rb);
+  g4_store(S.a[0], S.b[0], ra, rb);
+  g4_load<false>(A, lda, B, ldb, M, N, K, kG4K, ra, rb);
   __syncthreads();
   int buf = 0;
-  for (int k0 = 0; k0 < K; k0 += kG4K) {
+  // one chunk: fragments of chunk k0 from LDS, chunk k0 + 16 (all zero beyond K) split into
+  // the idle buffer, chunk k0 + 32 fetched, then the MFMAs of chunk k0
+  auto chunk = [&](int k0, auto full) {
     const uint4* cA = S.a[buf];
     const uint4* cB = S.b[buf];
     uint4 bf[2][3], af[4][3];
@@ -514,9 +541,8 @@ __device__ __forceinline__ void gemm_tile4(const float* __restrict__ A, int64_t 
     for (int i = 0; i < 4; ++i)
 #pragma unroll
       for (int p = 0; p < 3; ++p) af[i][p] = cA[(wm + 32 * i + rl) * kRec4 + 2 * p + kh];
-    // chunk k0 + 16 into the idle buffer (all zero beyond K), then fetch chunk k0 + 32
-    g4_store(S.a[buf ^ 1], S.b[buf ^ 1], ra, rb, K, k0 + kG4K);
-    g4_load(A, lda, B, ldb, M, N, K, k0 + 2 * kG4K, ra, rb);
+    g4_store(S.a[buf ^ 1], S.b[buf ^ 1], ra, rb);
+    g4_load<decltype(full)::value>(A, lda, B, ldb, M, N, K, k0 + 2 * kG4K, ra, rb);
     constexpr int PA[6] = {1, 2, 0, 1, 0, 0}, PB[6] = {1, 0, 2, 0, 1, 0};
 #pragma unroll
     for (int q = 0; q < 6; ++q)
@@ -526,7 +552,12 @@ __device__ __forceinline__ void gemm_tile4(const float* __restrict__ A, int64_t 
         for (int j = 0; j < 2; ++j) acc[i][j] = mfma_bf16(af[i][PA[q]], bf[j][PB[q]], acc[i][j]);
     __syncthreads();
     buf ^= 1;
-  }
+  };
+  // the chunks whose prefetched chunk k0 + 32 lies wholly below K, then the rest
+  const int kfull = (K / kG4K - 2) * kG4K;
+  int k0 = 0;
+  for (; k0 < kfull; k0 += kG4K) chunk(k0, std::true_type{});
+  for (; k0 < K; k0 += kG4K) chunk(k0, std::false_type{});
 }
 
 // columns 64 h .. 64 h + 63 of the tile into sm.ep[column - 64 h][row] (waves w >> 1 == h)
