@@ -9,10 +9,11 @@ refinement in the FP32 mode), one posterior sample and Takahashi selected invers
 value = (F_factor + F_solve (mean) + F_solve/2 (one sample) + F_selinv) / step time,
 with the algorithmic counts of the exact L pattern: F_factor = sum_j c_j^2,
 F_selinv = 2 sum_j c_j^2, F_solve = 4 nnz(L) - 2n.  The step time is the wall time of
-the whole step as the library runs it: the selected inversion on its second stream
-overlaps the log-det, the refined mean and the sample of the same factor.  The phase-sum
-form F / (t_factor + t_solve + t_selinv) is reported beside it from one extra step run
-without the overlap (metric_gflops_phase_sum), with each phase timed alone.  The
+the whole step, its phases one after the other on the context's stream (running the
+selected inversion on the library's second stream beside the solves gains nothing on
+this workload: both fill every CU, and each slows the other by about its own duration).
+The phase-sum form F / (t_factor + t_solve + t_selinv) is reported beside it from one
+extra step with each phase timed alone (metric_gflops_phase_sum).  The
 headline mode is the FP32 factor with FP64 pivots and FP64 refinement; the FP64 mode is
 reported beside it.
 
@@ -43,7 +44,7 @@ HBM_GBS = 8000.0
 # (FETCH_SIZE, WRITE_SIZE) scaled by the same counters over a plain 1 GiB copy; valid only
 # for the kernel build they were taken on (keyed by class and precision: 1 = FP32+refine)
 PMC_TRAFFIC = {
-    ("sel_gemm", 1): {"bytes_per_launch": 3.4291e+09, "kernel": "k_sel_gemm4",
+    ("sel_gemm", 1): {"bytes_per_launch": 3.4287e+09, "kernel": "k_sel_gemm4",
                       "source": "profiles/sel_gemm4_advdiff128x128x64_fp32_hbm_bytes.md"},
 }
 
@@ -68,14 +69,11 @@ def run_mode(binding, ctx, dev, prob, precision, steps, warmup, z_kn, profile):
     def step():
         ctx.update_values(q_data=dev["q_data"], a_data=dev["a_data"], q_eps=dev["q_eps"], y=dev["y"])
         ctx.factor(precision)
-        # the selected inversion runs on the library's second stream, overlapped with
-        # the log-determinant, the refined mean and the samples of the same factor
-        var = ctx.selinv_submit()
         ld = ctx.logdet()
         mu, it, res = ctx.solve(max_refine=30 if precision == binding.GMRF_FP32_REFINE else 0, tol=tol,
                                 raise_not_converged=False)
         x = ctx.sample(z_kn)
-        ctx.selinv_wait()
+        var = ctx.selinv()
         return ld, mu, it, res, x, var
     for _ in range(warmup):
         step()
@@ -103,7 +101,7 @@ def run_mode(binding, ctx, dev, prob, precision, steps, warmup, z_kn, profile):
         ctx.profile(False)
     for k in phases:
         phases[k] /= steps
-    # one step without the overlap: each phase alone, timed with the library's events
+    # one more step with each phase alone, timed with the library's events
     ctx.update_values(q_data=dev["q_data"], a_data=dev["a_data"], q_eps=dev["q_eps"], y=dev["y"])
     ctx.factor(precision)
     ctx.logdet()
@@ -167,15 +165,12 @@ def secondary(binding, which, steps, warmup, autotune=False):
             F = st["flops_factor"] + st["flops_selinv"] + (1 + k) * st["flops_solve"]
 
             def step():
-                # as in the headline step: the selected inversion on the library's second
-                # stream, overlapped with the log-determinants, the refined means and the samples
                 ctx.factor(prec)
-                ctx.selinv_submit()
                 ctx.logdet()
                 ctx.solve(max_refine=30 if prec == binding.GMRF_FP32_REFINE else 0, tol=1e-12,
                           raise_not_converged=False)
                 ctx.sample(z)
-                ctx.selinv_wait()
+                ctx.selinv()
             for _ in range(warmup):
                 step()
             torch.cuda.synchronize()
@@ -228,12 +223,11 @@ def secondary(binding, which, steps, warmup, autotune=False):
 
             def step():
                 ctx.factor(prec)
-                ctx.selinv_submit()
                 ctx.logdet()
                 ctx.solve(max_refine=40 if prec == binding.GMRF_FP32_REFINE else 0, tol=1e-12,
                           raise_not_converged=False)
                 ctx.sample(zk)
-                ctx.selinv_wait()
+                ctx.selinv()
             for _ in range(warmup):
                 step()
             torch.cuda.synchronize()

@@ -405,7 +405,9 @@ __device__ __forceinline__ void zero_acc128(typename V4<T>::type (&acc)[4][4]) {
 // 16 k values (32 bytes each) plus 16 bytes of padding, so a lane's eight k values of one
 // plane are one 128-bit read and the 64 lanes of a read fall in distinct bank groups.
 // Thread t converts row t & 255, k values 8 (t >> 8) .. +7 of both operands (the
-// transpose of the column-major operands happens in registers).  Two LDS buffers; the
+// transpose of the column-major operands happens in registers); the chunks wholly below K
+// run in a loop of their own with buffer loads, so that each of its iterations is one
+// block of loads, split, LDS traffic and MFMAs for the scheduler to interleave.  Two LDS buffers; the
 // registers run one chunk ahead, so that the split of chunk c + 1 into the idle buffer
 // and the loads of chunk c + 2 overlap the MFMAs of chunk c.  One work-group covers a
 // whole 256-wide outer block, so every row panel is read once per K part.
