@@ -730,8 +730,9 @@ gmrf_status build_plan(gmrf_t h) {
       lv.spart2.push_back(B.add(lv.fronts, [&](int32_t s) -> int64_t {
         return oact(s) ? std::max<int64_t>(1, (otail(s) + 511) / 512) * onsub(s) * onsub(s) : 0;
       }, [&](int32_t s) {
+        // the symmetric block's lower half (the kernel computes its lower 64x64 tiles)
         const double r = (double)otail(s), b = (double)okb2(s);
-        return Cost{2.0 * r * b * b, 2.0 * r * b};
+        return Cost{r * b * (b + 1.0), 2.0 * r * b};
       }));
       h->part_max = std::max(h->part_max, lv.spart2.back().total);
       // solves: forward outer block t (left to right), backward outer block from the right

@@ -2259,8 +2259,9 @@ __global__ __launch_bounds__(kThreads) void k_sel_Y2(DevSym S, LaunchList L, int
   const T* XT = D2T + D2off[s] + (int64_t)o.K * kNB2 * kNB2;
   typename V4<T>::type acc[4][4];
   zero_acc128<T>(acc);
-  gemm_tile128<T, false, false>(B.L + S.Loff[s] + row0 + (int64_t)o.k2 * n, n, XT + col0, o.kb2, M, N, o.kb2, acc,
-                                sA, sB);
+  // Linv_KK is lower triangular: the columns from col0 on take only its rows from col0 on
+  gemm_tile128<T, false, false>(B.L + S.Loff[s] + row0 + (int64_t)(o.k2 + col0) * n, n,
+                                XT + col0 + (int64_t)col0 * o.kb2, o.kb2, M, N, o.kb2 - col0, acc, sA, sB);
   T* Y = B.Y + S.Voff[s] * kNB2;
   for_acc128<T>(acc, [&](int r, int c, T v) {
     if (r < M && c < N) Y[(col0 + c) + (int64_t)(row0 - o.rs + r) * kNB2] = v;
@@ -2396,6 +2397,7 @@ __global__ __launch_bounds__(kThreads) void k_sel_part2(DevSym S, LaunchList L, 
   const int nt = o.nsub * o.nsub;
   const int chunk = (int)(loc / nt), rem = (int)(loc % nt);
   const int ti = rem / o.nsub, tj = rem % o.nsub;
+  if (ti < tj) return;   // only the lower tiles of the symmetric block are read
   const int r0 = kChunk * chunk;
   const int kr = max(0, min(kChunk, n - o.rs - r0));
   const int M = min(kNB, o.kb2 - kNB * ti), N = min(kNB, o.kb2 - kNB * tj);
@@ -2429,8 +2431,11 @@ __global__ __launch_bounds__(kThreads) void k_sel_fin2(DevSym S, LaunchList L, L
   const T* X = D2 + D2off[s] + (int64_t)o.K * kNB2 * kNB2;
   typename V4<T>::type acc[2][2];
   zero_acc<T>(acc);
-  gemm_tile<T, true, true>(X + (int64_t)(kNB * ti) * o.kb2, o.kb2, X + (int64_t)(kNB * tj) * o.kb2, o.kb2, M, N,
-                           o.kb2, acc, sA, sB);
+  // (Linv^T Linv)[ti, tj], ti >= tj: the columns of Linv in block ti are zero above row
+  // 64 ti, so the sum starts there
+  const int k0 = kNB * ti;
+  gemm_tile<T, true, true>(X + (int64_t)(kNB * ti) * o.kb2 + k0, o.kb2, X + (int64_t)(kNB * tj) * o.kb2 + k0, o.kb2,
+                           M, N, o.kb2 - k0, acc, sA, sB);
   const int nt = o.nsub * o.nsub;
   const int64_t q0 = Lpart.prefix[fi];
   const int nchunks = (int)((Lpart.prefix[fi + 1] - q0) / nt);
