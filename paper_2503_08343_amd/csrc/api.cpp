@@ -728,7 +728,7 @@ gmrf_status build_plan(gmrf_t h) {
         }, [&](int32_t s) { return std::make_pair((int32_t)gsplit4(s), (int32_t)gbase[s]); }));
       }
       lv.spart2.push_back(B.add(lv.fronts, [&](int32_t s) -> int64_t {
-        return oact(s) ? std::max<int64_t>(1, (otail(s) + 511) / 512) * onsub(s) * onsub(s) : 0;
+        return oact(s) ? std::max<int64_t>(1, (otail(s) + kSelChunk - 1) / kSelChunk) * onsub(s) * onsub(s) : 0;
       }, [&](int32_t s) {
         // the symmetric block's lower half (the kernel computes its lower 64x64 tiles)
         const double r = (double)otail(s), b = (double)okb2(s);

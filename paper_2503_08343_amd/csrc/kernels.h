@@ -77,6 +77,7 @@ void launch_cg_p(hipStream_t st, int64_t n, double* sc, const double* z, double*
 void launch_copy_f64(hipStream_t st, int64_t n, const double* a, double* b);
 // z = r / diag(Q) (qdiag: index of each row's diagonal entry)
 void launch_jacobi(hipStream_t st, int64_t n, const int64_t* qdiag, const double* qv, const double* r, double* z);
+constexpr int kSelChunk = 512;   // rows of R' per split-K partial of the Sigma diagonal blocks
 constexpr int kCgPartials = 3 * 2048;  // partial sums of launch_cg_iteration
 // one Jacobi-preconditioned CG iteration: q = Q p with the partials of p^T q (summed into
 // sc[2]); x, r, z updates with the partials of r^T z (summed into sc[1 - cur]) and r^T r;

@@ -27,7 +27,6 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kP = 80;        // LDS row pitch of the MFMA operand tiles (bank spread)
 constexpr int kTK = 16;       // K chunk of the MFMA tile loop
-constexpr int kChunk = 512;   // rows per split-K partial in the Sigma diagonal blocks
 constexpr int kSub = kNB2 / kNB;
 constexpr int kExtUnroll = 4;  // relative-index batches in flight per thread
 
@@ -2383,7 +2382,7 @@ __global__ __launch_bounds__(kThreads) void k_sel_gemm_reduce(DevSym S, LaunchLi
 }
 
 // split-K partials of X^T Sigma[R', K]: work-group (front, chunk, ti, tj) computes the
-// 64x64 tile (ti, tj) over kChunk rows of R' into part + wg * 64^2; Sigma[R', K] is read
+// 64x64 tile (ti, tj) over kSelChunk rows of R' into part + wg * 64^2; Sigma[R', K] is read
 // through its stored mirror Sigma[K, R'] (rows contiguous)
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_sel_part2(DevSym S, LaunchList L, int step, SelBufs<T> B) {
@@ -2398,8 +2397,8 @@ __global__ __launch_bounds__(kThreads) void k_sel_part2(DevSym S, LaunchList L, 
   const int chunk = (int)(loc / nt), rem = (int)(loc % nt);
   const int ti = rem / o.nsub, tj = rem % o.nsub;
   if (ti < tj) return;   // only the lower tiles of the symmetric block are read
-  const int r0 = kChunk * chunk;
-  const int kr = max(0, min(kChunk, n - o.rs - r0));
+  const int r0 = kSelChunk * chunk;
+  const int kr = max(0, min(kSelChunk, n - o.rs - r0));
   const int M = min(kNB, o.kb2 - kNB * ti), N = min(kNB, o.kb2 - kNB * tj);
   const T* Sf = B.Scur + S.Woff[s];
   const T* Y = B.Y + S.Voff[s] * kNB2;
