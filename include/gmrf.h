@@ -216,15 +216,21 @@ gmrf_status gmrf_solve_rhs(gmrf_t h, const double* rhs, double* x_out);
    none: alpha = 0, the iterate is kept, so the objective never increases) chosen on the
    device.  With use_graph != 0 the iterations after the first
    replay one hipGraph captured by this call (and destroyed before it returns).
+   decrement_tol > 0: stop after the first iteration whose Newton decrement lambda^2 / 2
+   is below decrement_tol or whose line search takes no step (Sec. 5.3: Gauss-Newton until
+   the Newton decrement subceeds a tolerance or a maximum number of steps is reached; the
+   host reads each iteration's record); 0: run all `iters` iterations.
    u (device, n): start on entry, final iterate on exit.  rec_out (host, 6*iters,
    nullable): per iteration objective at the start, step length, Newton decrement
    lambda^2 = -grad^T d, grad^T d, the final relative residual of the linearised solve
-   and the number of corrections applied.  On return the context holds the factor of the
+   and the number of corrections applied; NaN for the iterations the stopping rule
+   skipped.  On return the context holds the factor of the
    Gauss-Newton Laplace approximation at the final iterate and mu_post = u, so
    gmrf_logdet, gmrf_sample and gmrf_selinv describe N(u*, (Q + J*^T Q_eps J*)^-1). */
 gmrf_status gmrf_gn_burgers(gmrf_t h, int64_t nx, int64_t nt, double dt, double nu,
                             const double* mass, const double* stiff3, int iters, int precision,
-                            int refine, double refine_tol, int use_graph, double* u, double* rec_out);
+                            int refine, double refine_tol, double decrement_tol, int use_graph, double* u,
+                            double* rec_out);
 
 /* Gauss-Newton (Sec. 3.3) for observation residuals with a pointwise power nonlinearity,
    e.g. the lumped Galerkin rows of -Laplace u + u^3 = f:
@@ -235,12 +241,13 @@ gmrf_status gmrf_gn_burgers(gmrf_t h, int64_t nx, int64_t nt, double dt, double 
    linearisation J = lin + power * c * u^(power-1) (at the nonlinear unknown) and
    b = (1 - power) c u^power into the assembled A and b, then proceeds exactly as
    gmrf_gn_burgers (H = Q + J^T Q_eps J on the analysed pattern, refined solve, device
-   Armijo line search, hipGraph replay after the first iteration, Laplace approximation
-   at the final iterate); rec_out receives the same 6 values per iteration.  Returns
+   Armijo line search, hipGraph replay after the first iteration, the same stopping rule,
+   Laplace approximation at the final iterate); rec_out receives the same 6 values per
+   iteration.  Returns
    GMRF_ERR_PATTERN if a nonlinear unknown is not a stored column of its row. */
 gmrf_status gmrf_gn_pointwise(gmrf_t h, const double* lin_val, const int32_t* nl_col, const double* nl_coef,
                               int power, int iters, int precision, int refine, double refine_tol,
-                              int use_graph, double* u, double* rec_out);
+                              double decrement_tol, int use_graph, double* u, double* rec_out);
 
 /* Conjugate gradients (Sec. 3.2, the alternative to the factorisation when fill is too
    large): preconditioned CG for Q_post x = rhs on the device, FP64 vectors and fixed-order

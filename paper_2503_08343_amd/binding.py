@@ -117,12 +117,12 @@ def load():
         "gmrf_spmv": ([P, P, P, P], i32),
         "gmrf_misfit": ([P, P, P], i32),
         "gmrf_solve_rhs": ([P, P, P], i32),
-        "gmrf_gn_burgers": ([P, i64, i64, d, d, P, P, ctypes.c_int, ctypes.c_int, ctypes.c_int, d,
+        "gmrf_gn_burgers": ([P, i64, i64, d, d, P, P, ctypes.c_int, ctypes.c_int, ctypes.c_int, d, d,
                              ctypes.c_int, P, P], i32),
         "gmrf_kernel_stats": ([P, P, ctypes.c_int, P], i32),
         "gmrf_logdet_noalloc": ([P, P], i32),
         "gmrf_lml_gradient": ([P, P, ctypes.c_int, P, P, P, ctypes.c_int, d, P, P], i32),
-        "gmrf_gn_pointwise": ([P, P, P, P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, d,
+        "gmrf_gn_pointwise": ([P, P, P, P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, d, d,
                                ctypes.c_int, P, P], i32),
         "gmrf_pcg": ([P, i64, P, P, P, ctypes.c_int, ctypes.c_int, d, P, P], i32),
         "gmrf_sample_cg": ([P, i64, i64, P, P, P, P, P, P, ctypes.c_int, ctypes.c_int, d, P], i32),
@@ -353,26 +353,27 @@ class Context:
         return x
 
     def gn_burgers(self, nx, nt, dt, nu, mass, stiff3, u, iters=10, precision=GMRF_FP64, refine=2,
-                   use_graph=True, refine_tol=0.0):
+                   use_graph=True, refine_tol=0.0, decrement_tol=0.0):
         """Gauss-Newton iterations on the assembled Burgers problem; u (device) is updated in
         place.  Returns the per-iteration records (objective, step, decrement, slope,
-        relative residual of the linearised solve, corrections applied)."""
+        relative residual of the linearised solve, corrections applied; NaN rows for the
+        iterations a decrement_tol > 0 stopping rule skipped)."""
         rec = np.zeros(6 * iters)
         self._check(self.lib.gmrf_gn_burgers(self.h, int(nx), int(nt), float(dt), float(nu), _t_ptr(mass),
                                              _t_ptr(stiff3), int(iters), int(precision), int(refine),
-                                             float(refine_tol), 1 if use_graph else 0, _t_ptr(u),
-                                             _np_ptr(rec)))
+                                             float(refine_tol), float(decrement_tol), 1 if use_graph else 0,
+                                             _t_ptr(u), _np_ptr(rec)))
         return rec.reshape(iters, 6)
 
     def gn_pointwise(self, lin_val, nl_col, nl_coef, power, u, iters=10, precision=GMRF_FP64, refine=2,
-                     use_graph=True, refine_tol=0.0):
+                     use_graph=True, refine_tol=0.0, decrement_tol=0.0):
         """Gauss-Newton for residuals with a pointwise power nonlinearity (gmrf_gn_pointwise);
         u (device) is updated in place; returns the per-iteration records like gn_burgers."""
         rec = np.zeros(6 * iters)
         self._check(self.lib.gmrf_gn_pointwise(self.h, _t_ptr(lin_val), _t_ptr(nl_col), _t_ptr(nl_coef),
                                                int(power), int(iters), int(precision), int(refine),
-                                               float(refine_tol), 1 if use_graph else 0, _t_ptr(u),
-                                               _np_ptr(rec)))
+                                               float(refine_tol), float(decrement_tol), 1 if use_graph else 0,
+                                               _t_ptr(u), _np_ptr(rec)))
         return rec.reshape(iters, 6)
 
     def pcg(self, rhs=None, x0=None, precond=1, maxit=1000, tol=1e-12, raise_not_converged=True):

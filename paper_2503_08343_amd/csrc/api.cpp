@@ -12,6 +12,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <limits>
 #include <string>
 #include <type_traits>
 #include <unordered_map>
@@ -1318,7 +1319,8 @@ gmrf_status gn_body(gmrf_t h, const GNArgs& a) {
 // Gauss-Newton iterations on the device (Sec. 3.3) for either residual model: iteration 0
 // eager, the later ones replaying one hipGraph captured by this call; then the Laplace
 // approximation at the final iterate (relinearised and refactored).
-gmrf_status gn_run(gmrf_t h, const GNArgs& a, int iters, int precision, int use_graph, double* rec_out) {
+gmrf_status gn_run(gmrf_t h, const GNArgs& a, int iters, int precision, int use_graph, double decrement_tol,
+                   double* rec_out) {
   if (hipSetDevice(h->device) != hipSuccess) return fail(h, GMRF_ERR_HIP, "hipSetDevice failed");
   hipStream_t user = h->stream;
   if (!h->gn_stream) HIPCHK(h, hipStreamCreateWithFlags(&h->gn_stream, hipStreamNonBlocking));
@@ -1377,6 +1379,17 @@ gmrf_status gn_run(gmrf_t h, const GNArgs& a, int iters, int precision, int use_
     }
     HIPCHK(h, hipMemcpyAsync(rec.data() + kGNRec * it, h->d_gn_rec.p, kGNRec * sizeof(double),
                              hipMemcpyDeviceToHost, h->stream));
+    if (decrement_tol > 0.0) {
+      // stopping rule: the Newton decrement lambda^2 / 2 = -grad^T d / 2 of this
+      // iteration's direction below decrement_tol, or no step taken (the objective cannot
+      // decrease any more); the records of the iterations not run are NaN
+      HIPCHK(h, hipStreamSynchronize(h->stream));
+      const double* r = rec.data() + kGNRec * it;
+      if ((r[2] >= 0.0 && 0.5 * r[2] < decrement_tol) || r[1] == 0.0) {
+        std::fill(rec.begin() + kGNRec * (it + 1), rec.end(), std::numeric_limits<double>::quiet_NaN());
+        break;
+      }
+    }
   }
   HIPCHK(h, hipEventRecord(h->ev[1], h->stream));
   // Laplace approximation at the final iterate (Sec. 3.3): relinearise and refactor so that
@@ -2035,8 +2048,8 @@ gmrf_status gmrf_solve_rhs(gmrf_t h, const double* rhs, double* x_out) {
 
 gmrf_status gmrf_gn_burgers(gmrf_t h, int64_t nx, int64_t nt, double dt, double nu, const double* mass,
                             const double* stiff3, int iters, int precision, int refine, double refine_tol,
-                            int use_graph, double* u, double* rec_out) {
-  if (!h || !mass || !stiff3 || !u || iters < 1 || refine < 0 || !(refine_tol >= 0.0))
+                            double decrement_tol, int use_graph, double* u, double* rec_out) {
+  if (!h || !mass || !stiff3 || !u || iters < 1 || refine < 0 || !(refine_tol >= 0.0) || !(decrement_tol >= 0.0))
     return fail(h, GMRF_ERR_ARG, "bad argument");
   HIPCHK(h, sel_sync(h));
   if (precision != GMRF_FP64 && precision != GMRF_FP32_REFINE) return fail(h, GMRF_ERR_ARG, "unknown precision");
@@ -2061,13 +2074,14 @@ gmrf_status gmrf_gn_burgers(gmrf_t h, int64_t nx, int64_t nt, double dt, double 
       if (h->aci[e0 + t] != want[t]) return fail(h, GMRF_ERR_PATTERN, "A row " + std::to_string(r) + " has wrong columns");
   }
   GNArgs a{0, nx, nt, dt, nu, mass, stiff3, nullptr, nullptr, nullptr, 0, u, refine, refine_tol};
-  return gn_run(h, a, iters, precision, use_graph, rec_out);
+  return gn_run(h, a, iters, precision, use_graph, decrement_tol, rec_out);
 }
 
 gmrf_status gmrf_gn_pointwise(gmrf_t h, const double* lin_val, const int32_t* nl_col, const double* nl_coef,
-                              int power, int iters, int precision, int refine, double refine_tol, int use_graph,
-                              double* u, double* rec_out) {
+                              int power, int iters, int precision, int refine, double refine_tol,
+                              double decrement_tol, int use_graph, double* u, double* rec_out) {
   if (!h || !lin_val || !nl_col || !nl_coef || !u || iters < 1 || refine < 0 || !(refine_tol >= 0.0) ||
+      !(decrement_tol >= 0.0) ||
       power < 2 || power > 8)
     return fail(h, GMRF_ERR_ARG, "bad argument");
   HIPCHK(h, sel_sync(h));
@@ -2086,7 +2100,7 @@ gmrf_status gmrf_gn_pointwise(gmrf_t h, const double* lin_val, const int32_t* nl
     }
   }
   GNArgs a{1, 0, 0, 0.0, 0.0, nullptr, nullptr, lin_val, nl_col, nl_coef, power, u, refine, refine_tol};
-  return gn_run(h, a, iters, precision, use_graph, rec_out);
+  return gn_run(h, a, iters, precision, use_graph, decrement_tol, rec_out);
 }
 
 gmrf_status gmrf_sample(gmrf_t h, int64_t k, const float* z, double* x_out) {

@@ -62,6 +62,35 @@ def test_cubic_gn_graph_matches_eager(gpu_lib):
     assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
 
 
+@pytest.mark.parametrize("use_graph", [False, True])
+def test_cubic_gn_stops_at_the_decrement_tolerance(gpu_lib, use_graph):
+    """With decrement_tol > 0 the library stops after the first iteration whose Newton
+    decrement lambda^2 / 2 is below it (or that takes no step); the later records are NaN,
+    and the iterate is bitwise that of a run of exactly that many iterations."""
+    import torch
+    p = gi.elliptic_cubic(side=48)
+    tol = 1e-5
+    ctx, lin, col, coef = _dev(gpu_lib, p, 0)
+    u = torch.zeros(p.n, dtype=torch.float64, device="cuda")
+    rec = ctx.gn_pointwise(lin, col, coef, 3, u, iters=10, precision=0, refine=2, use_graph=use_graph,
+                           refine_tol=1e-12, decrement_tol=tol)
+    ran = int(np.sum(~np.isnan(rec[:, 0])))
+    print(f"[cubic gn] stopping rule: {ran} iterations; decrement {rec[:ran, 2]}; alpha {rec[:ran, 1]}", flush=True)
+    assert 1 <= ran < 10
+    assert np.all(np.isnan(rec[ran:]))
+    last = rec[ran - 1]
+    assert (0.0 <= last[2] and 0.5 * last[2] < tol) or last[1] == 0.0
+    for r in rec[:ran - 1]:
+        assert not ((0.0 <= r[2] and 0.5 * r[2] < tol) or r[1] == 0.0)
+    ctx.close()
+    ctx2, lin2, col2, coef2 = _dev(gpu_lib, p, 0)
+    u2 = torch.zeros(p.n, dtype=torch.float64, device="cuda")
+    rec2 = ctx2.gn_pointwise(lin2, col2, coef2, 3, u2, iters=ran, precision=0, refine=2, use_graph=use_graph,
+                             refine_tol=1e-12)
+    ctx2.close()
+    assert np.array_equal(rec2, rec[:ran]) and torch.equal(u2, u)
+
+
 def test_cubic_gn_fp32_and_fp64_reach_the_same_mode(gpu_lib):
     """At 64 x 64 (kappa of the posterior about 2e6, kappa u32 about 0.1) both precisions
     run to the stopping rule and agree to the refinement accuracy."""
