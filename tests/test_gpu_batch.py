@@ -108,3 +108,44 @@ def test_batch_prior_logdet_identity(gpu_lib, batch):
         ref = -2 * mesh.n * math.log(p.meta["tau"]) + 2 * _logabsdet(K) - float(np.sum(np.log(m)))
         assert abs(ld[b] - ref) <= 1e-9 * abs(ref), (b, ld[b], ref)
     ctx.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_batch_equals_each_problem_alone(gpu_lib, precision):
+    """The block-diagonal batch through the library gives each problem's own results, run
+    alone through the library: means, variances and log-dets to 1e-12 relative (bitwise
+    wherever the launch schedules of the two runs coincide)."""
+    p = gi.matern_batch(n_prob=5, side_lo=12, side_hi=40, seed=71)
+    ctx = gpu_lib.posterior_context(p, precision=precision)
+    ld = ctx.logdet()
+    refine = 30 if precision else 0
+    mu = ctx.solve(max_refine=refine, tol=1e-14, raise_not_converged=False)[0].cpu().numpy()
+    var = ctx.selinv().cpu().numpy()
+    ctx.close()
+    same = []
+    for b in range(5):
+        sub = gi.batch_block(p, b)
+        c1 = gpu_lib.posterior_context(sub, precision=precision)
+        ld1 = c1.logdet()[0]
+        mu1 = c1.solve(max_refine=refine, tol=1e-14, raise_not_converged=False)[0].cpu().numpy()
+        var1 = c1.selinv().cpu().numpy()
+        c1.close()
+        lo, hi = p.block_ptr[b], p.block_ptr[b + 1]
+        e_mu = np.max(np.abs(mu[lo:hi] - mu1)) / np.max(np.abs(mu1))
+        e_var = np.max(np.abs(var[lo:hi] - var1) / var1)
+        e_ld = abs(ld[b] - ld1) / abs(ld1)
+        same.append(bool(np.array_equal(mu[lo:hi], mu1) and np.array_equal(var[lo:hi], var1) and ld[b] == ld1))
+        print(f"[batch vs alone] p={precision} block {b} n={hi - lo}: mean {e_mu:.1e} var {e_var:.1e} "
+              f"logdet {e_ld:.1e} bitwise {same[-1]}", flush=True)
+        if precision == 0:
+            assert e_mu <= 1e-12 and e_var <= 1e-12 and e_ld <= 1e-12
+        else:
+            # FP32 factors: the two runs may group a front's products differently
+            # (launch-level tile choices), so each differs from the exact result by its
+            # own c kappa u32 (variances; n kappa u32 absolute for the log-det); the
+            # refined means agree to the refinement tolerance
+            Qp, _ = O.assemble(sub.Q, sub.A, sub.q_eps, sub.y)
+            kappa = O.condition_number(Qp)[0]
+            assert e_mu <= 1e-11
+            assert e_var <= 2 * C_BOUND * kappa * O.U32
+            assert e_ld <= 2 * C_BOUND * (hi - lo) * kappa * O.U32 / abs(ld1)
