@@ -927,34 +927,18 @@ __device__ __forceinline__ void potrf_phase(int jr, int kb, int t, int ti, int t
   const int j = 16 * JB + jr;
   if (j >= kb + 2) return;
   __syncthreads();
-  if (j >= 1 && j - 1 < kb) {
+  // the owners of column j need only their column JB of the previous column's update
+  // before they take the pivot: that part first, then the pivot, then the rest of the
+  // phase's work (the other columns, the inverse), off the chain from barrier to barrier
+  constexpr int B0 = JB < 4 ? JB : 0;
+  const bool upd1 = j >= 1 && j - 1 < kb;
+  double ci[4], cl[4];
+  if (upd1) {
     const double* c1 = colb[(j - 1) & 3];
-    double ci[4], cl[4];
 #pragma unroll
     for (int a = 0; a < 4; ++a) { ci[a] = c1[ti + 16 * a]; cl[a] = c1[tl + 16 * a]; }
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-      for (int b = 0; b < 4; ++b) a_r[a][b] -= ci[a] * cl[b];
-  }
-  if (j >= 2 && j - 2 < kb) {
-    const double* c2 = colb[(j - 2) & 3];
-    const double* r2 = rowb[(j - 2) & 3];
-    double ci[4], rc[4];
-#pragma unroll
-    for (int a = 0; a < 4; ++a) { ci[a] = c2[ti + 16 * a]; rc[a] = r2[tl + 16 * a]; }
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-      for (int b = 0; b < 4; ++b) x_r[a][b] -= ci[a] * rc[b];
-  }
-  if (j >= 1 && j - 1 < kb && ti == ((j - 1) & 15)) {
-    const double rinv = pinv[(j - 1) & 3];
-    if (jr >= 1) {
-      if constexpr (JB < 4) potrf_scale_row<JB>(x_r, rowb[(j - 1) & 3], tl, rinv);
-    } else {
-      if constexpr (JB >= 1) potrf_scale_row<JB - 1>(x_r, rowb[(j - 1) & 3], tl, rinv);
-    }
+    for (int a = 0; a < 4; ++a) a_r[a][B0] -= ci[a] * cl[B0];
   }
   if constexpr (JB < 4) {
     if (j < kb && (t >> 6) == (jr >> 2)) {
@@ -978,6 +962,32 @@ __device__ __forceinline__ void potrf_phase(int jr, int kb, int t, int ti, int t
           a_r[a][JB] = i == j ? ljj : v;
         }
       }
+    }
+  }
+  if (upd1) {
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+        if (b != B0) a_r[a][b] -= ci[a] * cl[b];
+  }
+  if (j >= 2 && j - 2 < kb) {
+    const double* c2 = colb[(j - 2) & 3];
+    const double* r2 = rowb[(j - 2) & 3];
+    double ci[4], rc[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) { ci[a] = c2[ti + 16 * a]; rc[a] = r2[tl + 16 * a]; }
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) x_r[a][b] -= ci[a] * rc[b];
+  }
+  if (j >= 1 && j - 1 < kb && ti == ((j - 1) & 15)) {
+    const double rinv = pinv[(j - 1) & 3];
+    if (jr >= 1) {
+      if constexpr (JB < 4) potrf_scale_row<JB>(x_r, rowb[(j - 1) & 3], tl, rinv);
+    } else {
+      if constexpr (JB >= 1) potrf_scale_row<JB - 1>(x_r, rowb[(j - 1) & 3], tl, rinv);
     }
   }
 }
