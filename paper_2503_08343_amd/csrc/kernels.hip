@@ -1081,8 +1081,11 @@ __device__ __forceinline__ void upd_region(int mode, int step, int n, int p, int
   clo = k0 + kb; chi = oe; klo = k0; khi = k0 + kb;
 }
 
+// At least two work-groups per SIMD set: the FP64 instance otherwise takes 189+ VGPRs and
+// all 128 AGPRs for one wave per SIMD, which leaves the FP64 matrix cores idle behind each
+// chunk's loads (FP64 factor of the 1M-unknown space-time posterior: 931 -> 718 ms).
 template <typename T, int TS>
-__global__ __launch_bounds__(kThreads) void k_update(DevSym S, LaunchList L, int step, int mode,
+__global__ __launch_bounds__(kThreads, 2) void k_update(DevSym S, LaunchList L, int step, int mode,
                                                      NumBufs<T> B) {
   int fi; int64_t loc;
   find_front(L, wg_id(), fi, loc);
@@ -2278,8 +2281,10 @@ __global__ __launch_bounds__(kThreads) void k_sel_Y2(DevSym S, LaunchList L, int
 }
 
 // Sigma[R', K] = -Sigma[R', R'] Y, mirrored into Sigma[K, R']; 128x128 tiles
+// Two waves per SIMD, for the same reason as k_update (FP64 selected inversion of the
+// 1M-unknown space-time posterior: 1585 -> 1197 ms).
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_sel_gemm2(DevSym S, LaunchList L, int step, SelBufs<T> B) {
+__global__ __launch_bounds__(kThreads, 2) void k_sel_gemm2(DevSym S, LaunchList L, int step, SelBufs<T> B) {
   __shared__ __attribute__((aligned(16))) T sA[BigLds<T>::v];
   __shared__ __attribute__((aligned(16))) T sB[BigLds<T>::v];
   int fi; int64_t loc;
