@@ -270,6 +270,39 @@ constexpr int kBP = 144;   // LDS pitch: rows of a K slice start 32 banks apart 
 // per CU; 32 halved the occupancy and ran slower)
 template <typename T> struct BigTK { static constexpr int v = 16; };
 
+// one element of T from a buffer resource: lane byte offset v, scalar byte offset s
+template <typename T>
+__device__ __forceinline__ T buf_load(__amdgpu_buffer_rsrc_t r, int v, int s) {
+  if constexpr (sizeof(T) == 8)
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, v, s, 0));
+  else
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, v, s, 0));
+}
+
+// Whole chunk (every k of it below K) of two rows-contiguous operands: buffer loads from a
+// per-chunk base with the row as the lane offset and the column steps as scalar offsets,
+// the same elements big_load reads.
+template <typename T>
+__device__ __forceinline__ void big_load_full(const T* __restrict__ A, int64_t lda, const T* __restrict__ B,
+                                              int64_t ldb, int M, int N, int k0, T (&ra)[BigTK<T>::v / 2],
+                                              T (&rb)[BigTK<T>::v / 2]) {
+  constexpr int NL = BigTK<T>::v / 2;
+  const int t = threadIdx.x;
+  const int kb = k0 + __builtin_amdgcn_readfirstlane(t >> 7);
+  const __amdgpu_buffer_rsrc_t sa =
+      __builtin_amdgcn_make_buffer_rsrc((void*)(A + (int64_t)kb * lda), (short)0, -1, 0x00020000);
+  const __amdgpu_buffer_rsrc_t sb =
+      __builtin_amdgcn_make_buffer_rsrc((void*)(B + (int64_t)kb * ldb), (short)0, -1, 0x00020000);
+  const int sla = __builtin_amdgcn_readfirstlane((int)(2 * sizeof(T) * lda));
+  const int slb = __builtin_amdgcn_readfirstlane((int)(2 * sizeof(T) * ldb));
+  const int va = (int)sizeof(T) * min(t & 127, M - 1), vb = (int)sizeof(T) * min(t & 127, N - 1);
+#pragma unroll
+  for (int i = 0; i < NL; ++i) {
+    ra[i] = buf_load<T>(sa, va, i * sla);
+    rb[i] = buf_load<T>(sb, vb, i * slb);
+  }
+}
+
 // Same division of work as tile64_load / tile64_store for the 128 x 128 tiles.
 template <typename T, bool A_KC, bool B_KC>
 __device__ __forceinline__ void big_load(const T* __restrict__ A, int64_t lda, const T* __restrict__ B,
@@ -356,9 +389,13 @@ __device__ __forceinline__ void gemm_tile128(const T* __restrict__ A, int64_t ld
   big_store<T, A_KC, B_KC>(sA, sB, ra, rb, M, N, K, 0);
   __syncthreads();
   int buf = 0;
-  for (int k0 = 0; k0 < K; k0 += TK) {
+  // one chunk: fetch chunk k0 + TK, MFMAs of chunk k0 from LDS, store chunk k0 + TK into the
+  // idle buffer.  FULL: chunk k0 + TK lies wholly below K and both operands are
+  // rows-contiguous, so it is fetched by big_load_full in a loop of its own.
+  auto chunk = [&](int k0, auto full) {
     const bool more = k0 + TK < K;
-    if (more) big_load<T, A_KC, B_KC>(A, lda, B, ldb, M, N, K, k0 + TK, ra, rb);
+    if constexpr (decltype(full)::value) big_load_full<T>(A, lda, B, ldb, M, N, k0 + TK, ra, rb);
+    else if (more) big_load<T, A_KC, B_KC>(A, lda, B, ldb, M, N, K, k0 + TK, ra, rb);
     const T* cA = sA + buf * (TK * kBP);
     const T* cB = sB + buf * (TK * kBP);
 #pragma unroll
@@ -377,7 +414,13 @@ __device__ __forceinline__ void gemm_tile128(const T* __restrict__ A, int64_t ld
                                          k0 + TK);
     __syncthreads();
     buf ^= 1;
+  };
+  int k0 = 0;
+  if constexpr (!A_KC && !B_KC) {
+    const int kfull = (K / TK - 1) * TK;   // chunks whose next chunk k0 + TK lies wholly below K
+    for (; k0 < kfull; k0 += TK) chunk(k0, std::true_type{});
   }
+  for (; k0 < K; k0 += TK) chunk(k0, std::false_type{});
 }
 
 template <typename T>
