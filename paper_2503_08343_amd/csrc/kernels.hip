@@ -281,7 +281,8 @@ __device__ __forceinline__ T buf_load(__amdgpu_buffer_rsrc_t r, int v, int s) {
 
 // Whole chunk (every k of it below K) of two rows-contiguous operands: buffer loads from a
 // per-chunk base with the row as the lane offset and the column steps as scalar offsets,
-// the same elements big_load reads.
+// the same elements big_load reads.  M, N >= 1: every caller's tile holds at least one row
+// and one column, so the clamped row offsets are never negative.
 template <typename T>
 __device__ __forceinline__ void big_load_full(const T* __restrict__ A, int64_t lda, const T* __restrict__ B,
                                               int64_t ldb, int M, int N, int k0, T (&ra)[BigTK<T>::v / 2],
