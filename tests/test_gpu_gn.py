@@ -76,7 +76,7 @@ def test_gn_graph_replays_match_eager(gpu_lib, precision):
     rg = ctx_g.gn_burgers(*args, mass, s3, ug, iters=6, precision=precision, refine=2, use_graph=True)
     assert np.array_equal(re, rg)
     assert torch.equal(ue, ug)
-    # eager work between replays, then more replays of the cached graph
+    # eager work between the calls, then a second call that captures and replays its own graph
     torch.cuda.synchronize()
     _ = (ug * 2.0).sum().item()
     re2 = ctx_e.gn_burgers(*args, mass, s3, ue, iters=3, precision=precision, refine=2, use_graph=False)
