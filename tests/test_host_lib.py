@@ -122,3 +122,14 @@ def test_full_size_fill_library_order_vs_oracle_order():
     print(f"[fill] F_fac library order {st_lib['flops_factor']:.6e}, oracle order {st_or['flops_factor']:.6e} "
           f"(ratio {ratio:.4f}); nnz(L) {st_lib['nnz_l']} / {st_or['nnz_l']}")
     assert ratio <= 1.01
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    """without the built library every entry into the binding raises: there is no CPU or
+    PyTorch fallback for any step of the path"""
+    monkeypatch.setattr(B, "_lib", None)
+    monkeypatch.setattr(B, "LIB_PATH", str(tmp_path / "libgmrf.so"))
+    with pytest.raises(RuntimeError, match="no CPU fallback"):
+        B.load()
+    with pytest.raises(RuntimeError, match="missing"):
+        B.Context(0)
