@@ -133,3 +133,22 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
         B.load()
     with pytest.raises(RuntimeError, match="missing"):
         B.Context(0)
+
+
+def test_autotuner_candidates_give_exact_analyses_and_distinct_keys():
+    """every supernode option set the autotuner may pick analyses the pattern exactly (the
+    oracle's column counts under the library's ordering; only the amalgamated storage
+    grows), and the cache key separates patterns, precisions and devices"""
+    from paper_2503_08343_amd import autotune as at
+    p = gi.matern_batch(n_prob=5, side_lo=8, side_hi=20, seed=12)
+    Qp, _ = O.assemble(p.Q, p.A, p.q_eps, p.y)
+    for c in at.CANDIDATES:
+        opts = dict(leaf_size=c[0], relax_small=c[1], relax_mid=c[2], relax_big=c[3])
+        perm, cc, st = B.symbolic_host(Qp.indptr, Qp.indices, p.coords, opts=opts)
+        F = O.cholesky(Qp, perm.astype(np.int64))
+        assert np.array_equal(cc, F.colcounts()), c
+        assert st["nnz_l"] == F.nnz and st["stored_l"] >= st["nnz_l"], c
+    q = gi.matern_batch(n_prob=5, side_lo=8, side_hi=20, seed=13)
+    k = at.pattern_key(p, 1, "gpu")
+    assert k == at.pattern_key(p, 1, "gpu")
+    assert len({k, at.pattern_key(p, 0, "gpu"), at.pattern_key(p, 1, "other"), at.pattern_key(q, 1, "gpu")}) == 4
