@@ -276,8 +276,24 @@ def secondary(binding, which, steps, warmup, autotune=False):
                           "objective": [float(v) for v in rec[:ran, 0]], "step": [float(v) for v in rec[:ran, 1]],
                           "decrement": [float(v) for v in rec[:ran, 2]],
                           "factor_GFLOP/s": round(ran * st["flops_factor"] / wall / 1e9, 1)}
+            # L2 error against the manufactured solution after k iterations, against the time
+            # k iterations take from the same start (they repeat the first k of the run above)
+            u = torch.zeros(p.n, dtype=torch.float64, device="cuda")
+            curve = [[0.0, hh * float(np.linalg.norm(u.cpu().numpy() - m["u_true"]))]]
+            for k in range(1, ran + 1):
+                u.zero_()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                ctx.gn_pointwise(lin, col, coef, 3, u, iters=k, precision=prec,
+                                 refine=30 if prec == binding.GMRF_FP32_REFINE else 2, use_graph=True,
+                                 refine_tol=1e-12)
+                torch.cuda.synchronize()
+                curve.append([round((time.perf_counter() - t0) * 1e3, 2),
+                              hh * float(np.linalg.norm(u.cpu().numpy() - m["u_true"]))])
+            out[mname]["l2_error_vs_ms"] = curve
             ctx.close()
-            log(f"[bench] c6 {mname}: {wall * 1e3:.1f} ms for {ran} iterations (stopping rule), L2 error {l2:.3e}")
+            log(f"[bench] c6 {mname}: {wall * 1e3:.1f} ms for {ran} iterations (stopping rule), L2 error {l2:.3e}; "
+                f"L2 error vs ms {curve}")
         res["c6_elliptic_gn"] = out
     if "c7" in which:
         # Darcy flow with quadratic triangles and Dirichlet constraints (App. B), 300 elements
