@@ -18,6 +18,9 @@ headline mode is the FP32 factor with FP64 pivots and FP64 refinement; the FP64 
 reported beside it.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+Secondary workloads (batch, Gauss-Newton, LML gradient, Matern noise, elliptic GN with its
+L2-error-against-time curve, P2 Darcy, CG path): --configs c2,c2m,c3,c4,c5,c6,c7,c8; their
+results go to the `secondary` object of the same JSON line.
 """
 from __future__ import annotations
 
